@@ -1,0 +1,259 @@
+"""Python access to the CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use this
+package; the product path never imports it.  It marshals numpy arrays into the
+plain C++ reference in oracle.cpp (see oracle.h for the definitions) and
+shares no code with the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class Camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+                ("znear", C.c_float), ("guard", C.c_float)]
+
+
+class Clip(C.Structure):
+    _fields_ = [("n", C.c_float * 3), ("d", C.c_float), ("layer_bits", C.c_uint32)]
+
+
+class View(C.Structure):
+    _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", Clip * 8), ("bg", C.c_float * 3)]
+
+
+def _model_struct(ptr_t):
+    class M(C.Structure):
+        _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("mean", ptr_t), ("scale", ptr_t),
+                    ("quat", ptr_t), ("opacity", ptr_t), ("sh", ptr_t), ("layer", C.POINTER(C.c_uint8))]
+    return M
+
+
+Model32 = _model_struct(C.POINTER(C.c_float))
+Model64 = _model_struct(C.POINTER(C.c_double))
+
+
+class Outputs(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("alpha", C.c_void_p), ("final_T", C.c_void_p),
+                ("last", C.POINTER(C.c_uint32)), ("n_contrib", C.POINTER(C.c_uint32)),
+                ("margin", C.POINTER(C.c_float)), ("rec", C.c_void_p), ("rect", C.POINTER(C.c_int32)),
+                ("n_tiles", C.POINTER(C.c_uint32)), ("clamp", C.POINTER(C.c_uint32)),
+                ("keys_emit", C.POINTER(C.c_uint64)), ("vals_emit", C.POINTER(C.c_uint32)),
+                ("keys", C.POINTER(C.c_uint64)), ("vals", C.POINTER(C.c_uint32)),
+                ("pair_cap", C.c_uint64), ("ranges", C.POINTER(C.c_uint32)), ("counts", C.c_uint64 * 4)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(_LIB_PATH)
+        for name, mtype, rtype in (("oracle_render_f32", Model32, C.c_float), ("oracle_render_f64", Model64, C.c_double)):
+            f = getattr(_lib, name)
+            f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), C.c_int, C.c_int,
+                          C.POINTER(Outputs), C.c_int]
+            f.restype = C.c_int
+        for name, mtype, rtype in (("oracle_backward_f32", Model32, C.c_float), ("oracle_backward_f64", Model64, C.c_double)):
+            f = getattr(_lib, name)
+            P = C.POINTER(rtype)
+            f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), P, P, C.c_uint32,
+                          P, P, P, P, P, P, P, C.c_int]
+            f.restype = C.c_int
+        _lib.oracle_sh_basis_f64.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        _lib.oracle_sh_basis_f32.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def camera_struct(cam):
+    c = Camera()
+    R = np.asarray(cam["R"], np.float32).reshape(9)
+    t = np.asarray(cam["t"], np.float32).reshape(3)
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.t[i] = float(t[i])
+    c.fx, c.fy, c.cx, c.cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
+    c.width, c.height = cam["width"], cam["height"]
+    c.znear, c.guard = cam["znear"], cam["guard"]
+    return c
+
+
+def view_struct(vs):
+    v = View()
+    v.layer_mask = vs["layer_mask"] & 0xFFFFFFFF
+    v.n_clip = len(vs["clips"])
+    for k, (n, d, bits) in enumerate(vs["clips"]):
+        for j in range(3):
+            v.clip[k].n[j] = float(n[j])
+        v.clip[k].d = float(d)
+        v.clip[k].layer_bits = bits & 0xFFFFFFFF
+    for j in range(3):
+        v.bg[j] = float(vs["bg"][j])
+    return v
+
+
+class _ModelArrays:
+    """Keeps the converted arrays alive while the C call runs."""
+
+    def __init__(self, scene, dtype):
+        self.dtype = np.dtype(dtype)
+        ct = C.c_float if self.dtype == np.float32 else C.c_double
+        self.arrs = {k: np.ascontiguousarray(scene[k], dtype=self.dtype)
+                     for k in ("mean", "scale", "quat", "opacity", "sh")}
+        self.layer = np.ascontiguousarray(scene["layer"], dtype=np.uint8)
+        M = Model32 if self.dtype == np.float32 else Model64
+        self.struct = M(int(self.layer.shape[0]), int(scene["sh_degree"]),
+                        *[_ptr(self.arrs[k], ct) for k in ("mean", "scale", "quat", "opacity", "sh")],
+                        _ptr(self.layer, C.c_uint8))
+
+
+def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pairs=False, n_threads=0):
+    """Render views; `scenes` is one scene for every view or a list, one per view.
+
+    Returns a dict of numpy arrays: rgb [V][3][H][W] (list if resolutions
+    differ), alpha, final_T, last, n_contrib, margin, rec [R][10], rect, n_tiles,
+    clamp, ranges, counts (K, E, A, tiles), and with pairs=True keys_emit,
+    vals_emit, keys, vals.
+    """
+    if isinstance(scenes, dict):
+        scenes = [scenes] * len(cams)
+    assert len(scenes) == len(cams) == len(views)
+    dtype = np.dtype(dtype)
+    L = lib()
+    models_keep = {}
+    mstructs = []
+    for s in scenes:
+        key = id(s)
+        if key not in models_keep:
+            models_keep[key] = _ModelArrays(s, dtype)
+        mstructs.append(models_keep[key].struct)
+    V = len(cams)
+    M = Model32 if dtype == np.float32 else Model64
+    marr = (M * max(V, 1))(*mstructs)
+    carr = (Camera * max(V, 1))(*[camera_struct(c) for c in cams])
+    varr = (View * max(V, 1))(*[view_struct(v) for v in views])
+    n_pix = sum(c["width"] * c["height"] for c in cams)
+    n_rec = sum(int(s["mean"].shape[1]) for s in scenes)
+    tiles = sum(((c["width"] + tile - 1) // tile) * ((c["height"] + tile - 1) // tile) for c in cams)
+    res = {
+        "rgb": np.zeros(3 * n_pix, dtype), "alpha": np.zeros(n_pix, dtype), "final_T": np.zeros(n_pix, dtype),
+        "last": np.zeros(n_pix, np.uint32), "n_contrib": np.zeros(n_pix, np.uint32),
+        "margin": np.zeros(n_pix, np.float32), "rec": np.zeros((max(n_rec, 1), 10), dtype),
+        "rect": np.zeros((max(n_rec, 1), 4), np.int32), "n_tiles": np.zeros(max(n_rec, 1), np.uint32),
+        "clamp": np.zeros(max(n_rec, 1), np.uint32), "ranges": np.zeros((max(tiles, 1), 2), np.uint32),
+    }
+    out = Outputs()
+    ct = C.c_float if dtype == np.float32 else C.c_double
+    out.rgb = res["rgb"].ctypes.data
+    out.alpha = res["alpha"].ctypes.data
+    out.final_T = res["final_T"].ctypes.data
+    out.last = _ptr(res["last"], C.c_uint32)
+    out.n_contrib = _ptr(res["n_contrib"], C.c_uint32)
+    out.margin = _ptr(res["margin"], C.c_float)
+    out.rec = res["rec"].ctypes.data
+    out.rect = _ptr(res["rect"], C.c_int32)
+    out.n_tiles = _ptr(res["n_tiles"], C.c_uint32)
+    out.clamp = _ptr(res["clamp"], C.c_uint32)
+    out.ranges = _ptr(res["ranges"], C.c_uint32)
+    fn = L.oracle_render_f32 if dtype == np.float32 else L.oracle_render_f64
+    if pairs:
+        # first call sizes the pair arrays
+        out.pair_cap = 0
+        probe = Outputs()
+        probe.pair_cap = 0
+        rc = fn(V, marr, carr, varr, tile, int(brute_force), C.byref(probe), n_threads)
+        if rc != 0:
+            raise RuntimeError(f"oracle render failed: {rc}")
+        K = int(probe.counts[0])
+        for k, t in (("keys_emit", np.uint64), ("vals_emit", np.uint32), ("keys", np.uint64), ("vals", np.uint32)):
+            res[k] = np.zeros(max(K, 1), t)
+        out.keys_emit = _ptr(res["keys_emit"], C.c_uint64)
+        out.vals_emit = _ptr(res["vals_emit"], C.c_uint32)
+        out.keys = _ptr(res["keys"], C.c_uint64)
+        out.vals = _ptr(res["vals"], C.c_uint32)
+        out.pair_cap = K
+    rc = fn(V, marr, carr, varr, tile, int(brute_force), C.byref(out), n_threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle render failed: {rc}")
+    K, E, A, T = (int(x) for x in out.counts)
+    res["counts"] = {"K": K, "E": E, "A": A, "tiles": T}
+    res["rec"] = res["rec"][:n_rec]
+    res["rect"] = res["rect"][:n_rec]
+    res["n_tiles"] = res["n_tiles"][:n_rec]
+    res["clamp"] = res["clamp"][:n_rec]
+    res["ranges"] = res["ranges"][:tiles]
+    if pairs:
+        for k in ("keys_emit", "vals_emit", "keys", "vals"):
+            res[k] = res[k][:K]
+    # per-view image views
+    same = len({(c["width"], c["height"]) for c in cams}) <= 1
+    if same and V > 0:
+        H, W = cams[0]["height"], cams[0]["width"]
+        res["rgb"] = res["rgb"].reshape(V, 3, H, W)
+        for k in ("alpha", "final_T", "last", "n_contrib", "margin"):
+            res[k] = res[k].reshape(V, H, W)
+    else:
+        rgbs, others = [], {k: [] for k in ("alpha", "final_T", "last", "n_contrib", "margin")}
+        po = 0
+        for c in cams:
+            H, W = c["height"], c["width"]
+            rgbs.append(res["rgb"][3 * po:3 * (po + H * W)].reshape(3, H, W))
+            for k in others:
+                others[k].append(res[k][po:po + H * W].reshape(H, W))
+            po += H * W
+        res["rgb"] = rgbs
+        res.update(others)
+    return res
+
+
+def backward(scene, cams, views, dL_drgb, dL_dalpha, trainable=0xFFFFFFFF, dtype=np.float32, n_threads=0):
+    """Exact gradients of sum(dL_drgb*rgb) + sum(dL_dalpha*alpha) w.r.t. the
+    activated parameters of one scene rendered in every view."""
+    dtype = np.dtype(dtype)
+    L = lib()
+    ma = _ModelArrays(scene, dtype)
+    V = len(cams)
+    carr = (Camera * max(V, 1))(*[camera_struct(c) for c in cams])
+    varr = (View * max(V, 1))(*[view_struct(v) for v in views])
+    n = int(ma.layer.shape[0])
+    nc = (int(scene["sh_degree"]) + 1) ** 2
+    g = {"mean": np.zeros((3, n), dtype), "scale": np.zeros((3, n), dtype), "quat": np.zeros((4, n), dtype),
+         "opacity": np.zeros(n, dtype), "sh": np.zeros((nc, 3, n), dtype), "max_contrib": np.zeros(n, dtype),
+         "activity": np.zeros(n, dtype)}
+    drgb = np.ascontiguousarray(dL_drgb, dtype).reshape(-1)
+    dal = np.ascontiguousarray(dL_dalpha, dtype).reshape(-1)
+    ct = C.c_float if dtype == np.float32 else C.c_double
+    fn = L.oracle_backward_f32 if dtype == np.float32 else L.oracle_backward_f64
+    rc = fn(V, C.byref(ma.struct), carr, varr, _ptr(drgb, ct), _ptr(dal, ct), trainable & 0xFFFFFFFF,
+            _ptr(g["mean"], ct), _ptr(g["scale"], ct), _ptr(g["quat"], ct), _ptr(g["opacity"], ct),
+            _ptr(g["sh"], ct), _ptr(g["max_contrib"], ct), _ptr(g["activity"], ct), n_threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle backward failed: {rc}")
+    return g
+
+
+def sh_basis(d, dtype=np.float64):
+    dtype = np.dtype(dtype)
+    L = lib()
+    d = np.ascontiguousarray(d, dtype)
+    out = np.zeros(16, dtype)
+    if dtype == np.float64:
+        L.oracle_sh_basis_f64(_ptr(d, C.c_double), _ptr(out, C.c_double))
+    else:
+        L.oracle_sh_basis_f32(_ptr(d, C.c_float), _ptr(out, C.c_float))
+    return out
