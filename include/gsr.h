@@ -1,0 +1,230 @@
+/*
+ * gsr.h - C ABI of the layered Gaussian-splat tile rasterizer (HIP, gfx950).
+ *
+ * The library renders scenes of anisotropic 3D Gaussians the way Gaussian
+ * splatting does (the paper's renderer is "analogous to Kerbl et al.",
+ * Sec. 3.3; splats are projected with the EWA approximation of Zwicker et al.
+ * it cites in Sec. 2.2.1), extended with the paper's layers:
+ *   - every Gaussian carries a layer id; a per-view layer-activation mask
+ *     shows or hides whole layers (Sec. 1 and Sec. 3.3: only active layers
+ *     are rendered);
+ *   - per-layer clip planes cut through layers (Sec. 1, Sec. 5.1: the cut
+ *     edge depends on the splat centres, so a plane removes the Gaussians
+ *     of its layers whose centre lies on its negative side);
+ *   - training renders frozen lower layers as background and updates only
+ *     the trainable layers (Sec. 3.2), with alpha in the loss and a random
+ *     background (Sec. 3.2.1), and tracks per-Gaussian activity for
+ *     inactive pruning (Sec. 3.2.2).
+ *
+ * Pipeline per call: project (gates, EWA covariance, SH colour, tile box) ->
+ * exclusive scan of tile counts -> duplicate into (tile << 32 | depth bits,
+ * record) pairs -> stable LSD radix sort -> per-tile ranges -> per-tile
+ * front-to-back blending (alpha = min(0.99, o exp(-q/2)), pairs below 1/255
+ * skipped, stop before T would drop below 1e-4).  The backward replays the
+ * blend back to front and chains to the Gaussian parameters.
+ *
+ * Conventions (also the CPU oracle's): OpenCV camera axes (x right, y down,
+ * z forward), p_cam = R p_world + t; pixel (i, j) is sampled at
+ * (i + 0.5, j + 0.5); 16 x 16 tiles; low-pass 0.3 px^2 on the 2D covariance
+ * diagonal; splat extent = bounding box of {q <= 11.09375}; SH are the real
+ * orthonormal harmonics with the Condon-Shortley phase, colour =
+ * max(0, sum sh*Y(dir) + 0.5) with dir from the eye centre to the Gaussian.
+ *
+ * Memory: every array pointer is a DEVICE pointer unless marked "host".  The
+ * caller owns every allocation; the library allocates nothing.  Gaussian
+ * attributes are structures of arrays (one plane per component, n floats
+ * each, plane-major):
+ *   mean[3][n], scale[3][n] (activated, > 0), quat[4][n] (w, x, y, z; any
+ *   length, normalised inside; zero culls), opacity[n] (activated, in
+ *   (0, 1)), sh[(D+1)^2][3][n] (coefficient, then channel, then Gaussian),
+ *   layer[n] (uint8, < 32).
+ *
+ * Errors: every entry point returns a gsr_status; nothing aborts or throws.
+ * Arguments are validated before any launch.  Launch failures return
+ * GSR_EHIP; faults inside kernels surface at the caller's next
+ * synchronisation.  All work is enqueued on the caller's stream (a
+ * hipStream_t passed as void*, NULL = the null stream).  Calls on distinct
+ * workspaces/states may run concurrently on different streams.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_TILE 16
+#define GSR_MAX_CLIP 8
+#define GSR_RECORD_FLOATS 12
+
+typedef enum {
+  GSR_OK = 0,
+  GSR_EINVAL = -1,    /* bad argument (null pointer, size, degree, ...) */
+  GSR_ENOSPACE = -2,  /* workspace or pair capacity too small; see the entry point */
+  GSR_EHIP = -3,      /* a HIP call failed */
+  GSR_EDEVICE = -4    /* a kernel reported an internal error (see gsr_forward_check) */
+} gsr_status;
+
+/* Pinhole camera (host struct). */
+typedef struct {
+  float R[9];          /* world -> camera rotation, row-major */
+  float t[3];          /* world -> camera translation */
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float znear;         /* Gaussians with camera depth <= znear are culled (0.2 by default) */
+  float guard;         /* the Jacobian is evaluated with the centre's image-plane slope
+                          clamped to guard * max(c, size - c) / f (1.3 by default) */
+} gsr_camera;
+
+/* Clip plane: for layers whose bit is set in layer_bits, a Gaussian whose
+ * centre m has n.m + d < 0 is removed (Sec. 1 and Sec. 5.1 cutting). */
+typedef struct {
+  float n[3];
+  float d;
+  uint32_t layer_bits;
+} gsr_clip_plane;
+
+/* Per-view visibility state (host struct). */
+typedef struct {
+  uint32_t layer_mask;                 /* bit l set: layer l is shown */
+  int32_t n_clip;                      /* 0 .. GSR_MAX_CLIP */
+  gsr_clip_plane clip[GSR_MAX_CLIP];
+  float bg[3];                         /* background colour composited behind the splats */
+} gsr_view_state;
+
+/* Gaussian arrays (device, structure of arrays, see above; host struct). */
+typedef struct {
+  int32_t n;           /* number of Gaussians, >= 0 */
+  int32_t sh_degree;   /* 0 .. 3 */
+  const float *mean, *scale, *quat, *opacity, *sh;
+  const uint8_t* layer;
+} gsr_model;
+
+/* Buffers that carry a forward pass to its backward (device, caller-owned;
+ * host struct).  R = n_views * model.n records, P = pair_capacity,
+ * X = total tiles = n_views * ceil(W/16) * ceil(H/16), Q = n_views * H * W.
+ *   records   float[R][12]  per (view, Gaussian): u, v, conic a, b, c,
+ *                           opacity, r, g, b, depth, clamp bits (as uint32;
+ *                           bit c = colour channel c clamped at 0), tile count
+ *                           (as uint32; 0 = culled).  Record r = v * n + i.
+ *   pair_vals uint32[2][P]  sorted record ids; which half holds the result is
+ *                           recorded on the device in *sort_sel
+ *   sort_sel  uint32[1]
+ *   ranges    uint32[X][2]  [start, end) of each tile's pairs
+ *   final_T   float[Q]      transmittance left behind the last blended splat
+ *   last      uint32[Q]     1 + index of the last blended pair, 0 if none
+ *   counters  uint32[4]     device: pairs K, overflow flag, error flag, spare */
+typedef struct {
+  float* records;
+  uint32_t* pair_vals;
+  uint32_t* sort_sel;
+  uint32_t* ranges;
+  float* final_T;
+  uint32_t* last;
+  uint32_t* counters;
+  uint32_t pair_capacity;
+} gsr_fwd_state;
+
+/* Optional copies of intermediate arrays for inspection (device, may all be
+ * NULL; host struct).  Filled by gsr_rasterize_forward when non-NULL.  The
+ * call then synchronises the stream once. */
+typedef struct {
+  uint32_t* n_tiles;    /* [R] tiles touched by each record */
+  uint32_t* tile_box;   /* [R][4]: x0 | y0 << 16, x1 | y1 << 16, depth bits, n_tiles */
+  uint64_t* keys_emit;  /* [P] keys in emission order (record order, tiles row-major) */
+  uint32_t* vals_emit;  /* [P] */
+  uint64_t* keys_sorted;/* [P] */
+} gsr_debug;
+
+/* Bytes of scratch workspace a forward or backward of n_views views of a
+ * model with n Gaussians at width x height needs, for a pair capacity of
+ * pair_capacity.  Returns 0 on bad arguments. */
+size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t height,
+                          uint32_t pair_capacity);
+
+/* Forward render of n_views views of one model, all at the same resolution
+ * (cams[v].width/height equal).  cams and views are host arrays of n_views.
+ *   rgb   float[V][3][H][W]  colour composited over views[v].bg
+ *   alpha float[V][H][W]     1 - final transmittance
+ * The state is filled for gsr_rasterize_backward.
+ * n_pairs_host: if non-NULL, the call synchronises the stream after the
+ * tile-count scan, stores the exact pair count K there and returns
+ * GSR_ENOSPACE without rendering when K > state->pair_capacity.  If NULL the
+ * call never synchronises; on overflow the pairs beyond the capacity are
+ * dropped, state->counters[1] is set and the image is incomplete - check
+ * with gsr_forward_check after synchronising.
+ * ws: scratch of at least gsr_workspace_size(...) bytes, 256-byte aligned. */
+gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                                 const gsr_view_state* views, gsr_fwd_state* state,
+                                 void* ws, size_t ws_bytes, float* rgb, float* alpha,
+                                 uint32_t* n_pairs_host, const gsr_debug* debug, void* stream);
+
+/* After a non-synchronising forward has completed (caller synchronised):
+ * reads state->counters and returns GSR_OK, GSR_ENOSPACE (pair capacity
+ * exceeded; *n_pairs_host receives the count needed) or GSR_EDEVICE. */
+gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host, void* stream);
+
+/* Gradients of a loss L given dL/d(rgb) float[V][3][H][W] and dL/d(alpha)
+ * float[V][H][W] (either may be NULL = zero), for the forward whose state
+ * is passed (same model, cameras and views).  Gradients are with respect
+ * to the activated parameters and OVERWRITE grads (same layout as the
+ * model arrays): g_mean[3][n], g_scale[3][n], g_quat[4][n], g_opacity[n],
+ * g_sh[(D+1)^2][3][n].  Gaussians whose layer bit is clear in
+ * trainable_layers receive zero (frozen layers, Sec. 3.2).
+ * max_contrib float[n] (optional): max-accumulated with the largest
+ *   alpha * T each Gaussian reached on any pixel (caller zeroes it to start
+ *   an accumulation window).
+ * activity float[n] (optional): accumulated (+=) with
+ *   2 |dL/dmean| + 0.1 |dL/dsh| + 0.1 |dL/dlog scale| (Sec. 3.2.2).
+ * ws: scratch of at least gsr_workspace_size(...) bytes. */
+typedef struct {
+  float *g_mean, *g_scale, *g_quat, *g_opacity, *g_sh;
+} gsr_grads;
+
+gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                                  const gsr_view_state* views, const gsr_fwd_state* state,
+                                  const float* dL_drgb, const float* dL_dalpha,
+                                  uint32_t trainable_layers, void* ws, size_t ws_bytes,
+                                  const gsr_grads* grads, float* max_contrib, float* activity,
+                                  void* stream);
+
+/* One render request of a batch (host struct): one or two views (stereo)
+ * of models[model] sharing one view state, each written to its own
+ * rgb float[3][H][W] and alpha float[H][W] (device).  Views of one request
+ * may differ in resolution. */
+typedef struct {
+  int32_t model;
+  int32_t n_views;          /* 1 or 2 */
+  gsr_camera cam[2];
+  gsr_view_state vs;
+  float* rgb[2];
+  float* alpha[2];
+} gsr_request;
+
+/* Bytes of workspace gsr_render_batch needs for these requests at a total
+ * pair capacity of pair_capacity (0 on bad arguments). */
+size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const gsr_request* reqs,
+                                int32_t n_req, uint32_t pair_capacity);
+
+/* Render a batch of requests over resident models in one pass: one
+ * projection per (model, its views), one sort over a shared tile space, one
+ * persistent blend launch over every tile of every view.  Never
+ * synchronises.  req_status int32[n_req] (device) receives GSR_OK, or
+ * GSR_ENOSPACE for requests whose pairs did not fit into pair_capacity
+ * (their images are not written; pairs are assigned in request order, so
+ * the failing requests are a suffix).  Each request's image is identical to
+ * rendering it alone. */
+gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs,
+                            int32_t n_req, uint32_t pair_capacity, void* ws, size_t ws_bytes,
+                            int32_t* req_status, void* stream);
+
+/* Human-readable name of a status. */
+const char* gsr_status_string(gsr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

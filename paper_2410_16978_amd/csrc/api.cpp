@@ -1,0 +1,412 @@
+// Host side of the C ABI declared in include/gsr.h: argument checks,
+// workspace layout and the launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/gsr.h"
+#include "common.hpp"
+
+using namespace gsr;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+// Lays buffers out in a byte arena; with base == nullptr it only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T> T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Sort control block: digit counts and offsets of every pass, pass tickets,
+// the persistent-blend tile ticket.  Cleared at the start of each call.
+struct SortCtl {
+  uint32_t hist[2 * kMaxSortPasses * 256];
+  uint32_t pass_ctr[kMaxSortPasses];
+  uint32_t tile_ctr;
+  uint32_t pad[7];
+};
+
+struct PipeBufs {
+  ViewD* views = nullptr;
+  uint32_t* req_rec = nullptr;
+  uint32_t* n_tiles = nullptr;
+  uint32_t* offsets = nullptr;
+  uint32_t* partials = nullptr;
+  uint4* tile_box = nullptr;
+  uint64_t* keys_a = nullptr;
+  uint64_t* keys_b = nullptr;
+  SortCtl* ctl = nullptr;
+  SortPlan* plan = nullptr;
+  uint32_t* status = nullptr;
+  float* g2d = nullptr;
+  // batch only (the single-call path keeps these in the caller's state)
+  float* records = nullptr;
+  uint32_t* vals = nullptr;
+  uint32_t* ranges = nullptr;
+  float* final_T = nullptr;
+  uint32_t* last = nullptr;
+  uint32_t* counters = nullptr;
+  uint32_t* sel = nullptr;
+};
+
+size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t n_req, bool batch,
+             size_t X, size_t Q, bool backward) {
+  b.views = c.take<ViewD>(std::max<size_t>(n_views, 1));
+  b.req_rec = c.take<uint32_t>(n_req + 1);
+  b.n_tiles = c.take<uint32_t>(std::max<size_t>(R, 1));
+  b.offsets = c.take<uint32_t>(R + 1);
+  b.partials = c.take<uint32_t>(div_up((uint32_t)R + 1, (uint32_t)kScanTile) + 1);
+  b.tile_box = c.take<uint4>(std::max<size_t>(R, 1));
+  b.keys_a = c.take<uint64_t>(std::max<size_t>(P, 1));
+  b.keys_b = c.take<uint64_t>(std::max<size_t>(P, 1));
+  b.ctl = c.take<SortCtl>(1);
+  b.plan = c.take<SortPlan>(1);
+  b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
+  if (backward) b.g2d = c.take<float>(9 * std::max<size_t>(R, 1));
+  if (batch) {
+    b.records = c.take<float>(kRecordFloats * std::max<size_t>(R, 1));
+    b.vals = c.take<uint32_t>(2 * std::max<size_t>(P, 1));
+    b.ranges = c.take<uint32_t>(2 * std::max<size_t>(X, 1));
+    b.final_T = c.take<float>(std::max<size_t>(Q, 1));
+    b.last = c.take<uint32_t>(std::max<size_t>(Q, 1));
+    b.counters = c.take<uint32_t>(4);
+    b.sel = c.take<uint32_t>(1);
+  }
+  return c.off + kAlign;
+}
+
+bool model_ok(const gsr_model* m) {
+  if (!m || m->n < 0 || m->sh_degree < 0 || m->sh_degree > 3) return false;
+  if (m->n > 0 && (!m->mean || !m->scale || !m->quat || !m->opacity || !m->sh || !m->layer)) return false;
+  return true;
+}
+
+bool camera_ok(const gsr_camera& c) {
+  return c.width > 0 && c.height > 0 && c.width <= 65535 * kTile && c.height <= 65535 * kTile && c.fx > 0.f &&
+         c.fy > 0.f;
+}
+
+bool view_ok(const gsr_view_state& v) { return v.n_clip >= 0 && v.n_clip <= GSR_MAX_CLIP; }
+
+uint32_t tiles_of(const gsr_camera& c) {
+  return div_up((uint32_t)c.width, (uint32_t)kTile) * div_up((uint32_t)c.height, (uint32_t)kTile);
+}
+
+int key_bits_for(uint64_t total_tiles) {
+  int b = 0;
+  while (b < 32 && (1ull << b) < total_tiles) ++b;
+  return 32 + b;
+}
+
+ViewD make_view(const gsr_camera& c, const gsr_view_state& vs) {
+  ViewD v;
+  std::memset(&v, 0, sizeof(v));
+  std::memcpy(v.R, c.R, sizeof(v.R));
+  std::memcpy(v.t, c.t, sizeof(v.t));
+  v.fx = c.fx; v.fy = c.fy; v.cx = c.cx; v.cy = c.cy; v.znear = c.znear; v.guard = c.guard;
+  v.W = c.width; v.H = c.height;
+  v.tiles_x = (int32_t)div_up((uint32_t)c.width, (uint32_t)kTile);
+  v.tiles_y = (int32_t)div_up((uint32_t)c.height, (uint32_t)kTile);
+  v.layer_mask = vs.layer_mask;
+  v.n_clip = vs.n_clip;
+  for (int k = 0; k < vs.n_clip; ++k) {
+    for (int j = 0; j < 3; ++j) v.clip[k].n[j] = vs.clip[k].n[j];
+    v.clip[k].d = vs.clip[k].d;
+    v.clip[k].bits = vs.clip[k].layer_bits;
+  }
+  for (int j = 0; j < 3; ++j) v.bg[j] = vs.bg[j];
+  return v;
+}
+
+ModelD make_model(const gsr_model& m) {
+  ModelD d;
+  d.n = m.n; d.D = m.sh_degree;
+  d.mean = m.mean; d.scale = m.scale; d.quat = m.quat; d.opacity = m.opacity; d.sh = m.sh; d.layer = m.layer;
+  return d;
+}
+
+// Jobs: the views of one model in chunks of kMaxJobViews.
+std::vector<JobD> make_jobs(const ModelD& m, const std::vector<int>& view_ids) {
+  std::vector<JobD> jobs;
+  for (size_t i = 0; i < view_ids.size(); i += kMaxJobViews) {
+    JobD j;
+    std::memset(&j, 0, sizeof(j));
+    j.m = m;
+    j.n_views = (int32_t)std::min<size_t>(kMaxJobViews, view_ids.size() - i);
+    for (int k = 0; k < j.n_views; ++k) j.view[k] = view_ids[i + k];
+    jobs.push_back(j);
+  }
+  return jobs;
+}
+
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    if ((expr) != hipSuccess) return GSR_EHIP; \
+  } while (0)
+
+bool single_view_args_ok(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                         const gsr_view_state* views) {
+  if (!model_ok(model) || n_views <= 0 || !cams || !views) return false;
+  for (int v = 0; v < n_views; ++v) {
+    if (!camera_ok(cams[v]) || !view_ok(views[v])) return false;
+    if (cams[v].width != cams[0].width || cams[v].height != cams[0].height) return false;
+  }
+  if ((uint64_t)model->n * (uint64_t)n_views >= (1ull << 31)) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gsr_status_string(gsr_status s) {
+  switch (s) {
+    case GSR_OK: return "ok";
+    case GSR_EINVAL: return "invalid argument";
+    case GSR_ENOSPACE: return "workspace or pair capacity too small";
+    case GSR_EHIP: return "HIP runtime error";
+    case GSR_EDEVICE: return "device-side error";
+  }
+  return "unknown status";
+}
+
+size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t height, uint32_t pair_capacity) {
+  if (n < 0 || n_views <= 0 || width <= 0 || height <= 0 || pair_capacity >= (1u << 30)) return 0;
+  Carver c(nullptr);
+  PipeBufs b;
+  return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, 0, 0, true);
+}
+
+gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                                 const gsr_view_state* views, gsr_fwd_state* state, void* ws, size_t ws_bytes,
+                                 float* rgb, float* alpha, uint32_t* n_pairs_host, const gsr_debug* debug,
+                                 void* stream) {
+  if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !rgb || !alpha) return GSR_EINVAL;
+  if (!state->records || !state->pair_vals || !state->sort_sel || !state->ranges || !state->final_T ||
+      !state->last || !state->counters || state->pair_capacity >= (1u << 30))
+    return GSR_EINVAL;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int W = cams[0].width, H = cams[0].height;
+  const uint32_t n = (uint32_t)model->n;
+  const uint32_t R = n * (uint32_t)n_views;
+  const uint32_t P = state->pair_capacity;
+  const uint32_t tiles_per_view = tiles_of(cams[0]);
+  const uint64_t X = (uint64_t)tiles_per_view * n_views;
+  if (X >= (1ull << 32)) return GSR_EINVAL;
+  const size_t plane = (size_t)W * H;
+  Carver c(ws);
+  PipeBufs b;
+  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true) > ws_bytes) return GSR_ENOSPACE;
+
+  std::vector<ViewD> hv(n_views);
+  std::vector<int> ids(n_views);
+  for (int v = 0; v < n_views; ++v) {
+    ViewD d = make_view(cams[v], views[v]);
+    d.tile_off = (uint32_t)v * tiles_per_view;
+    d.rec_off = (uint32_t)v * n;
+    d.rgb = rgb + 3 * plane * v;
+    d.alpha = alpha + plane * v;
+    d.final_T = state->final_T + plane * v;
+    d.last = state->last + plane * v;
+    hv[v] = d;
+    ids[v] = v;
+  }
+  HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.ctl), sizeof(SortCtl) / 4, s));
+  HIP_TRY(launch_clear_u32(state->counters, 4, s));
+  HIP_TRY(launch_clear_u32(state->ranges, 2 * X, s));
+  const ModelD md = make_model(*model);
+  for (const JobD& j : make_jobs(md, ids)) HIP_TRY(launch_project(j, b.views, state->records, b.n_tiles, b.tile_box, s));
+  HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, state->counters, P, s));
+  if (n_pairs_host) {
+    uint32_t K = 0;
+    HIP_TRY(hipMemcpyAsync(&K, state->counters + kCntPairs, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_pairs_host = K;
+    if (K > P) return GSR_ENOSPACE;
+  }
+  HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, state->counters, P, b.keys_a, state->pair_vals, s));
+  if (debug && (debug->keys_emit || debug->vals_emit)) {
+    if (debug->keys_emit) HIP_TRY(hipMemcpyAsync(debug->keys_emit, b.keys_a, 8ull * P, hipMemcpyDeviceToDevice, s));
+    if (debug->vals_emit) HIP_TRY(hipMemcpyAsync(debug->vals_emit, state->pair_vals, 4ull * P, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
+                      key_bits_for(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, state->sort_sel,
+                      state->counters + kCntError, s));
+  HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
+  HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals, state->sort_sel, P,
+                           state->ranges, &b.ctl->tile_ctr, nullptr, false, s));
+  if (debug) {
+    if (debug->n_tiles) HIP_TRY(hipMemcpyAsync(debug->n_tiles, b.n_tiles, 4ull * R, hipMemcpyDeviceToDevice, s));
+    if (debug->tile_box) HIP_TRY(hipMemcpyAsync(debug->tile_box, b.tile_box, 16ull * R, hipMemcpyDeviceToDevice, s));
+    if (debug->keys_sorted) {
+      uint32_t sel = 0;
+      HIP_TRY(hipMemcpyAsync(&sel, state->sort_sel, 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipMemcpyAsync(debug->keys_sorted, sel ? b.keys_b : b.keys_a, 8ull * P, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return GSR_OK;
+}
+
+gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host, void* stream) {
+  if (!state || !state->counters) return GSR_EINVAL;
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(cnt, state->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (n_pairs_host) *n_pairs_host = cnt[kCntPairs];
+  if (cnt[kCntError]) return GSR_EDEVICE;
+  if (cnt[kCntOverflow]) return GSR_ENOSPACE;
+  return GSR_OK;
+}
+
+gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                                  const gsr_view_state* views, const gsr_fwd_state* state, const float* dL_drgb,
+                                  const float* dL_dalpha, uint32_t trainable_layers, void* ws, size_t ws_bytes,
+                                  const gsr_grads* grads, float* max_contrib, float* activity, void* stream) {
+  if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !grads) return GSR_EINVAL;
+  if (n_views > kMaxJobViews) return GSR_EINVAL;
+  if (model->n > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_sh))
+    return GSR_EINVAL;
+  if (!state->records || !state->pair_vals || !state->sort_sel || !state->ranges || !state->final_T || !state->last)
+    return GSR_EINVAL;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int W = cams[0].width, H = cams[0].height;
+  const uint32_t n = (uint32_t)model->n;
+  const uint32_t R = n * (uint32_t)n_views;
+  const uint32_t P = state->pair_capacity;
+  const uint32_t tiles_per_view = tiles_of(cams[0]);
+  const uint64_t X = (uint64_t)tiles_per_view * n_views;
+  const size_t plane = (size_t)W * H;
+  Carver c(ws);
+  PipeBufs b;
+  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true) > ws_bytes) return GSR_ENOSPACE;
+  std::vector<ViewD> hv(n_views);
+  std::vector<int> ids(n_views);
+  for (int v = 0; v < n_views; ++v) {
+    ViewD d = make_view(cams[v], views[v]);
+    d.tile_off = (uint32_t)v * tiles_per_view;
+    d.rec_off = (uint32_t)v * n;
+    d.final_T = state->final_T + plane * v;
+    d.last = state->last + plane * v;
+    hv[v] = d;
+    ids[v] = v;
+  }
+  if (n == 0) return GSR_OK;
+  HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.g2d), 9ull * R, s));
+  // max_contrib is indexed by Gaussian: records of view v start at v * n
+  HIP_TRY(launch_blend_bwd(b.views, n_views, (uint32_t)X, state->records, state->pair_vals, state->sort_sel, P,
+                           state->ranges, dL_drgb, dL_dalpha, b.g2d, R, max_contrib, s));
+  const ModelD md = make_model(*model);
+  for (const JobD& j : make_jobs(md, ids))
+    HIP_TRY(launch_project_bwd(j, b.views, state->records, b.g2d, R, trainable_layers, grads->g_mean,
+                               grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_sh, activity, s));
+  return GSR_OK;
+}
+
+// ---------------------------------------------------------------- batch
+namespace {
+
+struct BatchPlan {
+  std::vector<ViewD> views;
+  std::vector<uint32_t> req_rec;
+  uint64_t R = 0, X = 0, Q = 0;
+};
+
+bool plan_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs, int32_t n_req, BatchPlan& bp) {
+  if (!models || n_models <= 0 || !reqs || n_req <= 0) return false;
+  for (int m = 0; m < n_models; ++m)
+    if (!model_ok(&models[m])) return false;
+  bp.req_rec.assign(n_req + 1, 0);
+  for (int q = 0; q < n_req; ++q) {
+    const gsr_request& r = reqs[q];
+    if (r.model < 0 || r.model >= n_models || r.n_views < 1 || r.n_views > 2 || !view_ok(r.vs)) return false;
+    bp.req_rec[q] = (uint32_t)bp.R;
+    for (int e = 0; e < r.n_views; ++e) {
+      if (!camera_ok(r.cam[e]) || !r.rgb[e] || !r.alpha[e]) return false;
+      ViewD d = make_view(r.cam[e], r.vs);
+      d.model = (uint32_t)r.model;
+      d.request = (uint32_t)q;
+      d.rec_off = (uint32_t)bp.R;
+      d.tile_off = (uint32_t)bp.X;
+      d.rgb = r.rgb[e];
+      d.alpha = r.alpha[e];
+      bp.views.push_back(d);
+      bp.R += (uint64_t)models[r.model].n;
+      bp.X += tiles_of(r.cam[e]);
+      bp.Q += (uint64_t)r.cam[e].width * r.cam[e].height;
+    }
+  }
+  bp.req_rec[n_req] = (uint32_t)bp.R;
+  return bp.R < (1ull << 31) && bp.X < (1ull << 31);
+}
+
+}  // namespace
+
+size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const gsr_request* reqs, int32_t n_req,
+                                uint32_t pair_capacity) {
+  BatchPlan bp;
+  if (!plan_batch(models, n_models, reqs, n_req, bp) || pair_capacity >= (1u << 30)) return 0;
+  Carver c(nullptr);
+  PipeBufs b;
+  return carve(c, b, bp.views.size(), bp.R, pair_capacity, n_req, true, bp.X, bp.Q, false);
+}
+
+gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs, int32_t n_req,
+                            uint32_t pair_capacity, void* ws, size_t ws_bytes, int32_t* req_status, void* stream) {
+  BatchPlan bp;
+  if (!plan_batch(models, n_models, reqs, n_req, bp) || !ws || !req_status || pair_capacity >= (1u << 30))
+    return GSR_EINVAL;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t P = pair_capacity;
+  const uint32_t R = (uint32_t)bp.R;
+  const int n_views = (int)bp.views.size();
+  Carver c(ws);
+  PipeBufs b;
+  if (carve(c, b, n_views, R, P, n_req, true, bp.X, bp.Q, false) > ws_bytes) return GSR_ENOSPACE;
+  // per-view transmittance / last index scratch
+  size_t q_off = 0;
+  for (ViewD& d : bp.views) {
+    d.final_T = b.final_T + q_off;
+    d.last = b.last + q_off;
+    q_off += (size_t)d.W * d.H;
+  }
+  HIP_TRY(hipMemcpyAsync(b.views, bp.views.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b.req_rec, bp.req_rec.data(), 4 * (n_req + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.ctl), sizeof(SortCtl) / 4, s));
+  HIP_TRY(launch_clear_u32(b.counters, 4, s));
+  HIP_TRY(launch_clear_u32(b.ranges, 2 * bp.X, s));
+  for (int m = 0; m < n_models; ++m) {
+    std::vector<int> ids;
+    for (int v = 0; v < n_views; ++v)
+      if ((int)bp.views[v].model == m) ids.push_back(v);
+    if (ids.empty()) continue;
+    const ModelD md = make_model(models[m]);
+    for (const JobD& j : make_jobs(md, ids)) HIP_TRY(launch_project(j, b.views, b.records, b.n_tiles, b.tile_box, s));
+  }
+  HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, b.counters, P, s));
+  HIP_TRY(launch_batch_status(b.req_rec, n_req, b.offsets, P, b.counters, req_status, s));
+  HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, b.counters, P, b.keys_a, b.vals, s));
+  HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, key_bits_for(bp.X), b.ctl->hist,
+                      b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
+  HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
+  HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
+                           &b.ctl->tile_ctr, req_status, true, s));
+  return GSR_OK;
+}
+
+}  // extern "C"

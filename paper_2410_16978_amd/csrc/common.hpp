@@ -1,0 +1,122 @@
+// Shared device-side definitions of the HIP rasterizer (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+constexpr int kTile = 16;
+constexpr int kMaxClip = 8;
+constexpr int kRecordFloats = 12;     // 48-byte splat record
+constexpr int kMaxJobViews = 16;      // views projected per attribute read
+constexpr int kMaxSortPasses = 8;     // 64-bit keys, 8-bit digits
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;        // per thread
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Thresholds of the compositing rule.
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTStop = 1e-4f;
+constexpr float kKappa = 0.3f;        // px^2 low-pass on the 2D covariance diagonal
+constexpr float kQMax = 11.09375f;    // extent: box of {q <= kQMax}; > 2 ln 255
+
+// counters[] slots
+constexpr int kCntPairs = 0;
+constexpr int kCntOverflow = 1;
+constexpr int kCntError = 2;
+
+struct ClipD {
+  float n[3];
+  float d;
+  uint32_t bits;
+};
+
+// One rendered view as the kernels see it (device copy).
+struct ViewD {
+  float R[9], t[3];
+  float fx, fy, cx, cy, znear, guard;
+  int32_t W, H, tiles_x, tiles_y;
+  uint32_t tile_off;   // first global tile id of the view
+  uint32_t rec_off;    // first record id of the view
+  uint32_t model;      // index of the model the view renders
+  uint32_t request;    // request index (batch) or 0
+  uint32_t layer_mask;
+  int32_t n_clip;
+  ClipD clip[kMaxClip];
+  float bg[3];
+  float* rgb;          // [3][H][W]
+  float* alpha;        // [H][W]
+  float* final_T;      // [H][W]
+  uint32_t* last;      // [H][W]
+};
+
+struct ModelD {
+  int32_t n, D;
+  const float *mean, *scale, *quat, *opacity, *sh;
+  const uint8_t* layer;
+};
+
+// A model together with the (up to kMaxJobViews) views that render it; the
+// projection reads each Gaussian's attributes once per job.
+struct JobD {
+  ModelD m;
+  int32_t n_views;
+  int32_t view[kMaxJobViews];
+};
+
+// Sort schedule computed on the device from the global digit histogram.
+struct SortPlan {
+  uint32_t skip[kMaxSortPasses];   // every key has the same digit: pass is a no-op
+  uint32_t src[kMaxSortPasses];    // ping-pong buffer the pass reads
+  uint32_t sel;                    // buffer holding the sorted result
+  uint32_t n_passes;
+};
+
+__host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+}  // namespace gsr
+
+// ---------------------------------------------------------------------------
+// Launchers (host side, defined in the .hip files).  All enqueue on `s`.
+namespace gsr {
+
+hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
+hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
+                          uint4* tile_box, hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t* partials, uint32_t n,
+                       uint32_t* counters, uint32_t pair_capacity, hipStream_t s);
+hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
+                            uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
+                            uint64_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
+                       const uint32_t* counters, uint32_t pair_capacity, int key_bits, uint32_t* hist,
+                       uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
+                       uint32_t* error_flag, hipStream_t s);
+hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,
+                         uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles, uint32_t* ranges,
+                         hipStream_t s);
+hipError_t launch_blend_fwd(const ViewD* views_dev, int n_views, uint32_t total_tiles,
+                            const float* records, uint32_t n_rec, const uint32_t* pair_vals,
+                            const uint32_t* sel, uint32_t pair_capacity, const uint32_t* ranges,
+                            uint32_t* tile_ctr, const int32_t* req_status, bool persistent, hipStream_t s);
+hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, uint32_t total_tiles,
+                            const float* records, const uint32_t* pair_vals, const uint32_t* sel,
+                            uint32_t pair_capacity, const uint32_t* ranges, const float* dL_drgb,
+                            const float* dL_dalpha, float* g2d, uint32_t n_rec, float* max_contrib,
+                            hipStream_t s);
+hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
+                              const float* g2d, uint32_t n_rec, uint32_t trainable, float* g_mean,
+                              float* g_scale, float* g_quat, float* g_opacity, float* g_sh,
+                              float* activity, hipStream_t s);
+hipError_t launch_batch_status(const uint32_t* req_rec, int n_req, const uint32_t* offsets,
+                               uint32_t pair_capacity, uint32_t* counters, int32_t* req_status,
+                               hipStream_t s);
+
+size_t sort_status_words(uint32_t pair_capacity);
+
+}  // namespace gsr

@@ -1,0 +1,214 @@
+// Integer stages between projection and blending: exclusive scan of the
+// per-record tile counts, duplication into (tile << 32 | depth bits, record)
+// pairs in emission order, and per-tile [start, end) ranges of the sorted
+// pairs.
+#include "common.hpp"
+
+namespace gsr {
+
+// ---------------------------------------------------------------- scan
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads = 4 waves).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* lds_waves, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(x);
+  if (lane == 63) lds_waves[wave] = inc;
+  __syncthreads();
+  uint32_t wave_off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t c = lds_waves[w];
+    if (w < wave) wave_off += c;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return wave_off + inc - x;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ partials) {
+  __shared__ uint32_t lds[4];
+  const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint32_t i = base + k * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  uint32_t total;
+  block_exclusive_scan(s, lds, &total);
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block partials; total K and the
+// capacity check go to counters.
+__global__ void __launch_bounds__(1024)
+k_scan_top(uint32_t* __restrict__ partials, uint32_t nb, uint32_t* __restrict__ counters,
+           uint32_t pair_capacity) {
+  __shared__ uint32_t lds[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (uint32_t base = 0; base < nb; base += 1024) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t x = i < nb ? partials[i] : 0u;
+    const uint32_t inc = wave_inclusive_scan(x);
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    uint32_t off = carry, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wave) off += lds[w];
+      tot += lds[w];
+    }
+    if (i < nb) partials[i] = off + inc - x;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    counters[kCntPairs] = carry;
+    counters[kCntOverflow] = carry > pair_capacity ? 1u : 0u;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_down(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ partials,
+            uint32_t* __restrict__ out) {
+  __shared__ uint32_t lds[4];
+  // thread t owns kScanItems consecutive items
+  const uint32_t base = blockIdx.x * (uint32_t)kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, lds, &total) + partials[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  // out[n] = total, written by the block that owns the end
+  if (base <= n && n < base + kScanItems) out[n] = run;
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t* partials, uint32_t n,
+                       uint32_t* counters, uint32_t pair_capacity, hipStream_t s) {
+  const uint32_t nb = div_up(n + 1, (uint32_t)kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, partials);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partials, nb, counters, pair_capacity);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, in, n, partials, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- duplicate
+// One thread per record: its tiles row-major at offsets[r] + j.  Pairs at or
+// beyond min(capacity, counters[pairs]) are dropped (the overflow flag or the
+// batch status already records it).
+__global__ void __launch_bounds__(256)
+k_duplicate(const uint32_t* __restrict__ n_tiles, const uint32_t* __restrict__ offsets,
+            const uint4* __restrict__ tile_box, uint32_t n_rec, const uint32_t* __restrict__ counters,
+            uint32_t pair_capacity, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rec) return;
+  pair_capacity = min(pair_capacity, counters[kCntPairs]);
+  const uint32_t cnt = n_tiles[r];
+  if (cnt == 0) return;
+  uint32_t off = offsets[r];
+  if (off >= pair_capacity) return;
+  const uint4 tb = tile_box[r];
+  const uint32_t w = tb.y & 0xFFFFu, h = tb.y >> 16;
+  const uint64_t depth = tb.z;
+  for (uint32_t dy = 0; dy < h; ++dy) {
+    const uint32_t row = tb.x + dy * tb.w;
+    for (uint32_t dx = 0; dx < w; ++dx) {
+      if (off >= pair_capacity) return;
+      keys[off] = ((uint64_t)(row + dx) << 32) | depth;
+      vals[off] = r;
+      ++off;
+    }
+  }
+}
+
+hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
+                            uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
+                            uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  if (n_rec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_duplicate, dim3(div_up(n_rec, 256u)), dim3(256), 0, s, n_tiles, offsets, tile_box,
+                     n_rec, counters, pair_capacity, keys, vals);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- ranges
+__global__ void __launch_bounds__(256)
+k_ranges(const uint64_t* __restrict__ keys_a, const uint64_t* __restrict__ keys_b,
+         const uint32_t* __restrict__ sel, uint32_t* __restrict__ counters, uint32_t pair_capacity,
+         uint32_t total_tiles, uint32_t* __restrict__ ranges) {
+  const uint32_t K = min(counters[kCntPairs], pair_capacity);
+  const uint64_t* keys = (*sel == 0) ? keys_a : keys_b;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+    const uint32_t t = (uint32_t)(keys[k] >> 32);
+    if (t >= total_tiles) {
+      atomicOr(&counters[kCntError], 4u);
+      continue;
+    }
+    if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != t) ranges[2 * t] = k;
+    if (k + 1 == K || (uint32_t)(keys[k + 1] >> 32) != t) ranges[2 * t + 1] = k + 1;
+  }
+}
+
+hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,
+                         uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles, uint32_t* ranges,
+                         hipStream_t s) {
+  if (pair_capacity == 0) return hipSuccess;
+  uint32_t grid = div_up(pair_capacity, 256u);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(256), 0, s, keys_a, keys_b, sel, counters, pair_capacity,
+                     total_tiles, ranges);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batch status
+// Requests own contiguous record ranges [req_rec[q], req_rec[q+1]), so their
+// pairs are contiguous in emission order.  A request whose pairs end beyond
+// the capacity is marked GSR_ENOSPACE (-2) (a suffix of the requests) and the
+// pair count is cut to the end of the last request that fits, so that only
+// whole requests are duplicated, sorted and blended.
+__global__ void k_batch_status(const uint32_t* __restrict__ req_rec, int n_req,
+                               const uint32_t* __restrict__ offsets, uint32_t pair_capacity,
+                               uint32_t* __restrict__ counters, int32_t* __restrict__ req_status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t k_fit = 0;
+  for (int q = 0; q < n_req; ++q) {
+    const uint32_t end = offsets[req_rec[q + 1]];
+    const bool fits = end <= pair_capacity;
+    req_status[q] = fits ? 0 : -2;
+    if (fits) k_fit = end;
+  }
+  counters[kCntPairs] = k_fit;
+  counters[kCntOverflow] = 0;
+}
+
+hipError_t launch_batch_status(const uint32_t* req_rec, int n_req, const uint32_t* offsets,
+                               uint32_t pair_capacity, uint32_t* counters, int32_t* req_status,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(64), 0, s, req_rec, n_req, offsets, pair_capacity,
+                     counters, req_status);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

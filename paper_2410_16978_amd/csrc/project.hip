@@ -1,0 +1,194 @@
+// Projection of Gaussians into splat records (gates, EWA covariance, SH
+// colour, tile box).  Compiled with -ffp-contract=off: every expression is
+// evaluated as written, each + - * / sqrt correctly rounded, so the records,
+// tile boxes and depth keys are reproducible bit for bit.
+#include "common.hpp"
+#include "sh.hpp"
+
+namespace gsr {
+
+__global__ void __launch_bounds__(256) k_clear_u32(uint32_t* __restrict__ p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = n / 256 + 1;
+  const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
+  hipLaunchKernelGGL(k_clear_u32, dim3(grid), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// One thread per Gaussian; the Gaussian's attributes are read once and
+// projected for every view of the job (stereo eyes, training views).  SH
+// coefficients are read only if some view keeps the Gaussian.
+template <int D>
+__global__ void __launch_bounds__(256)
+k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records,
+          uint32_t* __restrict__ n_tiles_out, uint4* __restrict__ tile_box) {
+  constexpr int NC = (D + 1) * (D + 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const ModelD& m = job.m;
+  if (i >= m.n) return;
+  const int n = m.n;
+  const uint32_t layer = m.layer[i];
+  const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
+  const float op = m.opacity[i];
+  float sh[NC * 3];
+  bool sh_loaded = false;
+  float Rq[9];
+  float qn = -1.f;  // < 0: rotation not computed yet
+
+  for (int jv = 0; jv < job.n_views; ++jv) {
+    const ViewD& V = views[job.view[jv]];
+    const uint32_t r = V.rec_off + (uint32_t)i;
+    uint32_t nt = 0;
+    do {
+      // layer activation mask
+      if (layer >= 32u || !((V.layer_mask >> layer) & 1u)) break;
+      // per-layer clip planes through the centre
+      bool clipped = false;
+      for (int k = 0; k < V.n_clip; ++k) {
+        const ClipD& c = V.clip[k];
+        if (!((c.bits >> layer) & 1u)) continue;
+        const float sd = ((c.n[0] * mx + c.n[1] * my) + c.n[2] * mz) + c.d;
+        if (sd < 0.f) { clipped = true; break; }
+      }
+      if (clipped) break;
+      const float* W = V.R;
+      const float tx = ((W[0] * mx + W[1] * my) + W[2] * mz) + V.t[0];
+      const float ty = ((W[3] * mx + W[4] * my) + W[5] * mz) + V.t[1];
+      const float tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + V.t[2];
+      if (!(tz > V.znear)) break;
+      if (op < kAlphaMin) break;
+      if (qn < 0.f) {
+        float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
+        qn = __fsqrt_rn(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+        if (!(qn > 0.f)) { qn = 0.f; break; }
+        qw = __fdiv_rn(qw, qn); qx = __fdiv_rn(qx, qn); qy = __fdiv_rn(qy, qn); qz = __fdiv_rn(qz, qn);
+        Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
+        Rq[1] = 2.f * (qx * qy - qw * qz);
+        Rq[2] = 2.f * (qx * qz + qw * qy);
+        Rq[3] = 2.f * (qx * qy + qw * qz);
+        Rq[4] = 1.f - 2.f * (qx * qx + qz * qz);
+        Rq[5] = 2.f * (qy * qz - qw * qx);
+        Rq[6] = 2.f * (qx * qz - qw * qy);
+        Rq[7] = 2.f * (qy * qz + qw * qx);
+        Rq[8] = 1.f - 2.f * (qx * qx + qy * qy);
+      }
+      if (!(qn > 0.f)) break;
+      // Sigma = M M^T, M = Rq diag(s)
+      const float s0 = m.scale[i], s1 = m.scale[n + i], s2 = m.scale[2 * n + i];
+      float M[9];
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr) {
+        M[3 * rr + 0] = Rq[3 * rr + 0] * s0;
+        M[3 * rr + 1] = Rq[3 * rr + 1] * s1;
+        M[3 * rr + 2] = Rq[3 * rr + 2] * s2;
+      }
+      float S[9];
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+          S[3 * rr + cc] = (M[3 * rr] * M[3 * cc] + M[3 * rr + 1] * M[3 * cc + 1]) + M[3 * rr + 2] * M[3 * cc + 2];
+      // local affine approximation of the perspective map, slope clamped
+      const float lim_x = __fdiv_rn(V.guard * fmaxf(V.cx, (float)V.W - V.cx), V.fx);
+      const float lim_y = __fdiv_rn(V.guard * fmaxf(V.cy, (float)V.H - V.cy), V.fy);
+      const float xr = fminf(fmaxf(__fdiv_rn(tx, tz), -lim_x), lim_x);
+      const float yr = fminf(fmaxf(__fdiv_rn(ty, tz), -lim_y), lim_y);
+      const float xc = xr * tz, yc = yr * tz;
+      const float tz2 = tz * tz;
+      const float J00 = __fdiv_rn(V.fx, tz);
+      const float J02 = __fdiv_rn(-(V.fx * xc), tz2);
+      const float J11 = __fdiv_rn(V.fy, tz);
+      const float J12 = __fdiv_rn(-(V.fy * yc), tz2);
+      float Tm[6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Tm[c] = J00 * W[c] + J02 * W[6 + c];
+        Tm[3 + c] = J11 * W[3 + c] + J12 * W[6 + c];
+      }
+      float U[6];
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          U[3 * rr + c] = (Tm[3 * rr] * S[c] + Tm[3 * rr + 1] * S[3 + c]) + Tm[3 * rr + 2] * S[6 + c];
+      const float s00 = (U[0] * Tm[0] + U[1] * Tm[1]) + U[2] * Tm[2];
+      const float s01 = (U[0] * Tm[3] + U[1] * Tm[4]) + U[2] * Tm[5];
+      const float s11 = (U[3] * Tm[3] + U[4] * Tm[4]) + U[5] * Tm[5];
+      const float a = s00 + kKappa, b = s01, c = s11 + kKappa;
+      const float det = a * c - b * b;
+      if (!(det > 0.f)) break;
+      const float ca = __fdiv_rn(c, det), cb = __fdiv_rn(-b, det), cc = __fdiv_rn(a, det);
+      const float u = __fdiv_rn(V.fx * tx, tz) + V.cx;
+      const float v = __fdiv_rn(V.fy * ty, tz) + V.cy;
+      // tile box of {q <= qmax}: clamp in float, then convert
+      const float hwx = __fsqrt_rn(kQMax * a), hwy = __fsqrt_rn(kQMax * c);
+      const float ftx = (float)V.tiles_x, fty = (float)V.tiles_y;
+      const float inv_tile = 1.0f / (float)kTile;
+      const float fx0 = fminf(fmaxf(floorf((u - hwx) * inv_tile), 0.f), ftx);
+      const float fx1 = fminf(fmaxf(floorf((u + hwx) * inv_tile) + 1.f, 0.f), ftx);
+      const float fy0 = fminf(fmaxf(floorf((v - hwy) * inv_tile), 0.f), fty);
+      const float fy1 = fminf(fmaxf(floorf((v + hwy) * inv_tile) + 1.f, 0.f), fty);
+      const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+      nt = (uint32_t)((x1 - x0) * (y1 - y0));
+      if (nt == 0) break;
+      // view-dependent colour from the eye centre -R^T t
+      const float ccx = -((W[0] * V.t[0] + W[3] * V.t[1]) + W[6] * V.t[2]);
+      const float ccy = -((W[1] * V.t[0] + W[4] * V.t[1]) + W[7] * V.t[2]);
+      const float ccz = -((W[2] * V.t[0] + W[5] * V.t[1]) + W[8] * V.t[2]);
+      const float ddx = mx - ccx, ddy = my - ccy, ddz = mz - ccz;
+      const float dl = __fsqrt_rn((ddx * ddx + ddy * ddy) + ddz * ddz);
+      const float dirx = __fdiv_rn(ddx, dl), diry = __fdiv_rn(ddy, dl), dirz = __fdiv_rn(ddz, dl);
+      float Y[16];
+      sh_basis<D>(dirx, diry, dirz, Y);
+      if (!sh_loaded) {
+#pragma unroll
+        for (int k = 0; k < NC * 3; ++k) sh[k] = m.sh[(size_t)k * n + i];
+        sh_loaded = true;
+      }
+      float rgb[3];
+      uint32_t clamp_bits = 0;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float acc = sh[ch] * Y[0];
+#pragma unroll
+        for (int k = 1; k < NC; ++k) acc = acc + sh[k * 3 + ch] * Y[k];
+        float raw = acc + 0.5f;
+        if (raw < 0.f) { clamp_bits |= 1u << ch; raw = 0.f; }
+        rgb[ch] = raw;
+      }
+      float4* rec = reinterpret_cast<float4*>(records + (size_t)r * kRecordFloats);
+      rec[0] = make_float4(u, v, ca, cb);
+      rec[1] = make_float4(cc, op, rgb[0], rgb[1]);
+      rec[2] = make_float4(rgb[2], tz, __uint_as_float(clamp_bits), __uint_as_float(nt));
+      const uint32_t base_tile = V.tile_off + (uint32_t)y0 * (uint32_t)V.tiles_x + (uint32_t)x0;
+      tile_box[r] = make_uint4(base_tile, (uint32_t)(x1 - x0) | ((uint32_t)(y1 - y0) << 16),
+                               __float_as_uint(tz), (uint32_t)V.tiles_x);
+    } while (false);
+    n_tiles_out[r] = nt;
+    if (nt == 0) {
+      // culled: the record's tile count slot says so (the rest is never read)
+      records[(size_t)r * kRecordFloats + 11] = __uint_as_float(0u);
+    }
+  }
+}
+
+hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
+                          uint4* tile_box, hipStream_t s) {
+  if (job.m.n <= 0 || job.n_views <= 0) return hipSuccess;
+  const dim3 grid(div_up((uint32_t)job.m.n, 256u)), block(256);
+  switch (job.m.D) {
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsr

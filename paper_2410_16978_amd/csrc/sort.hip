@@ -1,0 +1,281 @@
+// Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits,
+// in the single-pass-per-digit style of OneSweep (Adinets and Merrill, the
+// sort the paper's renderer derives from, Sec. 3.3): one read of the keys
+// builds the digit histograms of every pass, then each pass ranks a tile of
+// keys per block and finds the tile's global digit offsets by decoupled
+// look-back over the preceding tiles.
+//
+// Wave64 details: digits are ranked with 8 ballots per round (peer masks),
+// per-wave digit counters live in LDS, the tile is re-ordered by digit in
+// LDS before it is written out, so consecutive lanes write consecutive
+// addresses of a digit run.  Tiles are assigned in the order blocks start
+// (an atomic ticket), so a block only ever waits for blocks that are already
+// running; the wait is additionally bounded and reports an error instead of
+// spinning forever.
+#include "common.hpp"
+
+namespace gsr {
+
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagIncl = 2u << 30;
+constexpr uint32_t kValueMask = (1u << 30) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Lanes of the wave whose valid 8-bit digit equals this lane's.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    peers &= bit ? bal : ~bal;
+  }
+  return peers;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------- histogram
+// Digit histograms of every pass; also clears the look-back words of the
+// tiles the passes will use.
+__global__ void __launch_bounds__(256)
+k_sort_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counters, uint32_t cap,
+            int n_passes, uint32_t* __restrict__ hist, uint32_t* __restrict__ status, uint32_t nb_max) {
+  __shared__ uint32_t lh[kMaxSortPasses * 256];
+  const uint32_t K = min(counters[kCntPairs], cap);
+  for (int i = threadIdx.x; i < n_passes * 256; i += 256) lh[i] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  // whole-wave rounds so that every lane takes part in the ballots
+  const uint32_t rounds = div_up(K, stride);
+  for (uint32_t rd = 0; rd < rounds; ++rd) {
+    const uint32_t i = rd * stride + blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < K;
+    const uint64_t k = valid ? keys[i] : 0ull;
+    for (int p = 0; p < n_passes; ++p) {
+      const uint32_t d = (uint32_t)(k >> (8 * p)) & 255u;
+      const uint64_t peers = match_digit(d, valid);
+      if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&lh[p * 256 + d], (uint32_t)__popcll(peers));
+    }
+    (void)lane;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_passes * 256; i += 256)
+    if (lh[i]) atomicAdd(&hist[i], lh[i]);
+  // clear the look-back words of the active tiles of every pass
+  const uint32_t nb = div_up(K, (uint32_t)kSortTile);
+  const size_t per_pass = (size_t)nb * 256;
+  const size_t total = per_pass * n_passes;
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += stride) {
+    const size_t p = w / per_pass, rem = w - p * per_pass;
+    status[p * (size_t)nb_max * 256 + rem] = 0u;
+  }
+}
+
+// ---------------------------------------------------------------- plan
+// Exclusive digit offsets per pass, passes whose keys all share one digit
+// are skipped, and the ping-pong buffer of every remaining pass.
+__global__ void __launch_bounds__(256)
+k_sort_plan(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ counters, uint32_t cap,
+            int n_passes, uint32_t* __restrict__ digit_off, SortPlan* __restrict__ plan,
+            uint32_t* __restrict__ sel_out) {
+  __shared__ uint32_t lw[4];
+  __shared__ uint32_t trivial[kMaxSortPasses];
+  const uint32_t K = min(counters[kCntPairs], cap);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t < kMaxSortPasses) trivial[t] = 0;
+  __syncthreads();
+  for (int p = 0; p < n_passes; ++p) {
+    const uint32_t c = hist[p * 256 + t];
+    const uint32_t inc = wave_incl_scan(c);
+    if (lane == 63) lw[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < wave; ++w) off += lw[w];
+    digit_off[p * 256 + t] = off + inc - c;
+    if (c == K) trivial[p] = 1;  // every key has digit t (also K == 0 via c == 0 == K)
+    __syncthreads();
+  }
+  if (t == 0) {
+    uint32_t cur = 0;
+    for (int p = 0; p < kMaxSortPasses; ++p) {
+      const bool skip = p >= n_passes || trivial[p] || K == 0;
+      plan->skip[p] = skip ? 1u : 0u;
+      plan->src[p] = cur;
+      if (!skip) cur ^= 1u;
+    }
+    plan->sel = cur;
+    plan->n_passes = (uint32_t)n_passes;
+    *sel_out = cur;
+  }
+}
+
+// ---------------------------------------------------------------- one pass
+__global__ void __launch_bounds__(kSortThreads)
+k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t* __restrict__ vals0,
+            uint32_t* __restrict__ vals1, const uint32_t* __restrict__ counters, uint32_t cap,
+            const SortPlan* __restrict__ plan, const uint32_t* __restrict__ digit_off,
+            uint32_t* __restrict__ status, uint32_t nb_max, uint32_t* __restrict__ pass_ctr,
+            uint32_t* __restrict__ err, int pass) {
+  __shared__ uint32_t s_bid;
+  __shared__ uint32_t wave_cnt[4][256];
+  __shared__ uint32_t s_start[256];
+  __shared__ uint32_t s_global[256];
+  __shared__ uint32_t s_w[4];
+  __shared__ uint64_t s_keys[kSortTile];
+  __shared__ uint32_t s_vals[kSortTile];
+
+  if (plan->skip[pass]) return;
+  const uint32_t K = min(counters[kCntPairs], cap);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t == 0) s_bid = atomicAdd(&pass_ctr[pass], 1u);
+  for (int i = t; i < 4 * 256; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t bid = s_bid;
+  const uint32_t base = bid * (uint32_t)kSortTile;
+  if (base >= K) return;
+  const uint32_t src = plan->src[pass];
+  const uint64_t* kin = src ? keys1 : keys0;
+  const uint32_t* vin = src ? vals1 : vals0;
+  uint64_t* kout = src ? keys0 : keys1;
+  uint32_t* vout = src ? vals0 : vals1;
+  const int shift = 8 * pass;
+
+  uint64_t key[kSortItems];
+  uint32_t val[kSortItems];
+  uint32_t rank[kSortItems];
+  const uint32_t wbase = base + (uint32_t)wave * (kSortItems * 64);
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t idx = wbase + r * 64 + lane;
+    const bool valid = idx < K;
+    key[r] = valid ? kin[idx] : 0ull;
+    val[r] = valid ? vin[idx] : 0u;
+  }
+  // rank within the wave, in input order (round-major, then lane)
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = (wbase + r * 64 + lane) < K;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+    const uint64_t peers = match_digit(d, valid);
+    const uint64_t before = peers & lanemask_lt();
+    uint32_t pre = 0;
+    if (valid) pre = wave_cnt[wave][d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && before == 0) wave_cnt[wave][d] = pre + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    rank[r] = pre + (uint32_t)__popcll(before);
+  }
+  __syncthreads();
+  // thread t owns digit t: per-wave exclusive offsets and the block count
+  const uint32_t c0 = wave_cnt[0][t], c1 = wave_cnt[1][t], c2 = wave_cnt[2][t], c3 = wave_cnt[3][t];
+  const uint32_t cnt = c0 + c1 + c2 + c3;
+  const uint32_t inc = wave_incl_scan(cnt);
+  if (lane == 63) s_w[wave] = inc;
+  // publish this tile's counts before looking back
+  uint32_t* st = status + ((size_t)pass * nb_max) * 256;
+  if (bid == 0) {
+    __hip_atomic_store(&st[t], kFlagIncl | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  {
+    uint32_t off = 0;
+    for (int w = 0; w < wave; ++w) off += s_w[w];
+    s_start[t] = off + inc - cnt;
+    wave_cnt[0][t] = 0;
+    wave_cnt[1][t] = c0;
+    wave_cnt[2][t] = c0 + c1;
+    wave_cnt[3][t] = c0 + c1 + c2;
+  }
+  uint32_t excl = 0;
+  if (bid > 0) {
+    int j = (int)bid - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+      const uint32_t s = __hip_atomic_load(&st[(size_t)j * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t f = s & ~kValueMask;
+      if (f == 0) {
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += s & kValueMask;
+      if (f == kFlagIncl) break;
+      --j;
+    }
+    __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagIncl | (excl + cnt), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  s_global[t] = digit_off[pass * 256 + t] + excl;
+  __syncthreads();
+  // order the tile by digit in LDS (stable), then write digit runs out
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = (wbase + r * 64 + lane) < K;
+    if (valid) {
+      const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+      const uint32_t pos = s_start[d] + wave_cnt[wave][d] + rank[r];
+      s_keys[pos] = key[r];
+      s_vals[pos] = val[r];
+    }
+  }
+  __syncthreads();
+  const uint32_t n_items = min(K - base, (uint32_t)kSortTile);
+  for (uint32_t i = t; i < n_items; i += kSortThreads) {
+    const uint64_t k = s_keys[i];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t dst = s_global[d] + (i - s_start[d]);
+    if (dst < K) {
+      kout[dst] = k;
+      vout[dst] = s_vals[i];
+    } else {
+      atomicOr(err, 2u);  // inconsistent offsets: never write out of range
+    }
+  }
+}
+
+size_t sort_status_words(uint32_t pair_capacity) {
+  return (size_t)kMaxSortPasses * div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile) * 256;
+}
+
+// hist: [kMaxSortPasses][256] counts followed by [kMaxSortPasses][256]
+// offsets; pass_ctr: [kMaxSortPasses]; both zero on entry.
+hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
+                       const uint32_t* counters, uint32_t pair_capacity, int key_bits, uint32_t* hist,
+                       uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
+                       uint32_t* error_flag, hipStream_t s) {
+  const int n_passes = (key_bits + 7) / 8;
+  const uint32_t nb_max = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile);
+  uint32_t* digit_off = hist + kMaxSortPasses * 256;
+  uint32_t hist_blocks = div_up(pair_capacity > 0 ? pair_capacity : 1u, 256u * 16u);
+  if (hist_blocks > 2048) hist_blocks = 2048;
+  hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, s, keys_a, counters, pair_capacity, n_passes,
+                     hist, status, nb_max);
+  hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(256), 0, s, hist, counters, pair_capacity, n_passes, digit_off,
+                     plan, sel_out);
+  for (int p = 0; p < n_passes; ++p)
+    hipLaunchKernelGGL(k_sort_pass, dim3(nb_max), dim3(kSortThreads), 0, s, keys_a, keys_b, vals_a, vals_b,
+                       counters, pair_capacity, plan, digit_off, status, nb_max, pass_ctr, error_flag, p);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -1,0 +1,397 @@
+"""Python binding of the HIP rasterizer's C ABI (include/gsr.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every stage of the rasterizer runs in the library's
+kernels.  There is no fallback: if libgsr.so is missing or fails to load,
+every call raises.
+
+Entry points (same names as the C ABI):
+  rasterize_forward(model, cams, views, ...)   -> rgb, alpha, ForwardState
+  rasterize_backward(model, cams, views, state, dL_drgb, dL_dalpha, ...)
+  render_batch(models, requests, ...)          -> per-request images + status
+  workspace_size(n, n_views, width, height, pair_capacity)
+
+`model` is a dict of CUDA tensors in the structure-of-arrays layout of
+gsr.h: mean [3,n], scale [3,n] (activated), quat [4,n] (w,x,y,z),
+opacity [n] (activated), sh [(D+1)^2,3,n], layer [n] uint8, and an int
+"sh_degree".  Cameras and view states are the dicts of `scenes`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsr.so")
+_lib = None
+
+GSR_OK, GSR_EINVAL, GSR_ENOSPACE, GSR_EHIP, GSR_EDEVICE = 0, -1, -2, -3, -4
+MAX_CLIP = 8
+RECORD_FLOATS = 12
+TILE = 16
+
+
+class GsrError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class Camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+                ("znear", C.c_float), ("guard", C.c_float)]
+
+
+class ClipPlane(C.Structure):
+    _fields_ = [("n", C.c_float * 3), ("d", C.c_float), ("layer_bits", C.c_uint32)]
+
+
+class ViewState(C.Structure):
+    _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", ClipPlane * MAX_CLIP),
+                ("bg", C.c_float * 3)]
+
+
+class Model(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("mean", C.c_void_p), ("scale", C.c_void_p),
+                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p), ("layer", C.c_void_p)]
+
+
+class FwdState(C.Structure):
+    _fields_ = [("records", C.c_void_p), ("pair_vals", C.c_void_p), ("sort_sel", C.c_void_p),
+                ("ranges", C.c_void_p), ("final_T", C.c_void_p), ("last", C.c_void_p),
+                ("counters", C.c_void_p), ("pair_capacity", C.c_uint32)]
+
+
+class Debug(C.Structure):
+    _fields_ = [("n_tiles", C.c_void_p), ("tile_box", C.c_void_p), ("keys_emit", C.c_void_p),
+                ("vals_emit", C.c_void_p), ("keys_sorted", C.c_void_p)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("g_mean", C.c_void_p), ("g_scale", C.c_void_p), ("g_quat", C.c_void_p),
+                ("g_opacity", C.c_void_p), ("g_sh", C.c_void_p)]
+
+
+class Request(C.Structure):
+    _fields_ = [("model", C.c_int32), ("n_views", C.c_int32), ("cam", Camera * 2), ("vs", ViewState),
+                ("rgb", C.c_void_p * 2), ("alpha", C.c_void_p * 2)]
+
+
+def lib():
+    """Load libgsr.so (built by paper_2410_16978_amd/build.py); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP rasterizer library not built: {LIB_PATH} is missing "
+                           "(run paper_2410_16978_amd/build.py)")
+    L = C.CDLL(LIB_PATH)
+    L.gsr_status_string.restype = C.c_char_p
+    L.gsr_status_string.argtypes = [C.c_int]
+    L.gsr_workspace_size.restype = C.c_size_t
+    L.gsr_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32]
+    L.gsr_rasterize_forward.restype = C.c_int
+    L.gsr_rasterize_forward.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Camera), C.POINTER(ViewState),
+                                        C.POINTER(FwdState), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_uint32), C.POINTER(Debug), C.c_void_p]
+    L.gsr_forward_check.restype = C.c_int
+    L.gsr_forward_check.argtypes = [C.POINTER(FwdState), C.POINTER(C.c_uint32), C.c_void_p]
+    L.gsr_rasterize_backward.restype = C.c_int
+    L.gsr_rasterize_backward.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Camera), C.POINTER(ViewState),
+                                         C.POINTER(FwdState), C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                         C.c_size_t, C.POINTER(Grads), C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gsr_batch_workspace_size.restype = C.c_size_t
+    L.gsr_batch_workspace_size.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Request), C.c_int32, C.c_uint32]
+    L.gsr_render_batch.restype = C.c_int
+    L.gsr_render_batch.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Request), C.c_int32, C.c_uint32,
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+    _lib = L
+    return L
+
+
+def status_string(status):
+    return lib().gsr_status_string(int(status)).decode()
+
+
+def _check(status, what):
+    if status != GSR_OK:
+        raise GsrError(status, what)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ---------------------------------------------------------------- marshalling
+def camera_struct(cam):
+    c = Camera()
+    R = np.asarray(cam["R"], np.float32).reshape(9)
+    t = np.asarray(cam["t"], np.float32).reshape(3)
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.t[i] = float(t[i])
+    c.fx, c.fy, c.cx, c.cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.znear, c.guard = cam["znear"], cam["guard"]
+    return c
+
+
+def view_struct(vs):
+    v = ViewState()
+    v.layer_mask = int(vs["layer_mask"]) & 0xFFFFFFFF
+    clips = vs.get("clips", ())
+    if len(clips) > MAX_CLIP:
+        raise ValueError("at most 8 clip planes")
+    v.n_clip = len(clips)
+    for k, (n, d, bits) in enumerate(clips):
+        for j in range(3):
+            v.clip[k].n[j] = float(n[j])
+        v.clip[k].d = float(d)
+        v.clip[k].layer_bits = int(bits) & 0xFFFFFFFF
+    bg = vs.get("bg", (0.0, 0.0, 0.0))
+    for j in range(3):
+        v.bg[j] = float(bg[j])
+    return v
+
+
+_MODEL_KEYS = ("mean", "scale", "quat", "opacity", "sh", "layer")
+
+
+def to_device(scene, device="cuda"):
+    """Scene dict of numpy arrays -> dict of contiguous CUDA tensors."""
+    out = {"sh_degree": int(scene["sh_degree"])}
+    for k in _MODEL_KEYS:
+        a = scene[k]
+        dtype = torch.uint8 if k == "layer" else torch.float32
+        out[k] = torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).contiguous()
+    return out
+
+
+def model_struct(model):
+    n = int(model["layer"].shape[0])
+    D = int(model["sh_degree"])
+    nc = (D + 1) ** 2
+    shapes = {"mean": (3, n), "scale": (3, n), "quat": (4, n), "opacity": (n,), "sh": (nc, 3, n), "layer": (n,)}
+    for k, shp in shapes.items():
+        t = model[k]
+        if not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError(f"model[{k!r}] must be a contiguous CUDA tensor of shape {shp}, got "
+                             f"{tuple(t.shape)} on {t.device}")
+        want = torch.uint8 if k == "layer" else torch.float32
+        if t.dtype != want:
+            raise ValueError(f"model[{k!r}] must be {want}")
+    return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS])
+
+
+# ---------------------------------------------------------------- forward
+@dataclass
+class ForwardState:
+    """Device buffers carrying a forward to its backward (see gsr_fwd_state)."""
+    records: torch.Tensor
+    pair_vals: torch.Tensor
+    sort_sel: torch.Tensor
+    ranges: torch.Tensor
+    final_T: torch.Tensor
+    last: torch.Tensor
+    counters: torch.Tensor
+    capacity: int
+    workspace: torch.Tensor
+    n_views: int
+    width: int
+    height: int
+    n: int
+
+    def struct(self):
+        return FwdState(self.records.data_ptr(), self.pair_vals.data_ptr(), self.sort_sel.data_ptr(),
+                        self.ranges.data_ptr(), self.final_T.data_ptr(), self.last.data_ptr(),
+                        self.counters.data_ptr(), self.capacity)
+
+
+def workspace_size(n, n_views, width, height, pair_capacity):
+    return int(lib().gsr_workspace_size(int(n), int(n_views), int(width), int(height), int(pair_capacity)))
+
+
+def _tiles(w, h):
+    return ((w + TILE - 1) // TILE) * ((h + TILE - 1) // TILE)
+
+
+def make_state(n, n_views, width, height, capacity, device="cuda", old=None):
+    """Allocate (or reuse, when the shapes match) a forward state."""
+    capacity = int(max(capacity, 1))
+    R = n * n_views
+    X = _tiles(width, height) * n_views
+    Q = n_views * width * height
+    if old is not None and old.n == n and old.n_views == n_views and old.width == width and old.height == height \
+            and old.capacity >= capacity:
+        return old
+    ws = workspace_size(n, n_views, width, height, capacity)
+    if ws == 0:
+        raise GsrError(GSR_EINVAL, "workspace_size")
+    kw = dict(device=device)
+    return ForwardState(
+        records=torch.empty(max(R, 1) * RECORD_FLOATS, dtype=torch.float32, **kw),
+        pair_vals=torch.empty(2 * capacity, dtype=torch.int32, **kw),
+        sort_sel=torch.zeros(1, dtype=torch.int32, **kw),
+        ranges=torch.empty(2 * max(X, 1), dtype=torch.int32, **kw),
+        final_T=torch.empty(max(Q, 1), dtype=torch.float32, **kw),
+        last=torch.empty(max(Q, 1), dtype=torch.int32, **kw),
+        counters=torch.zeros(4, dtype=torch.int32, **kw),
+        capacity=capacity, workspace=torch.empty(ws, dtype=torch.uint8, **kw),
+        n_views=n_views, width=width, height=height, n=n)
+
+
+def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, debug=False, stream=None,
+                      out=None):
+    """Render len(cams) views of one model (equal resolution).
+
+    sync=True: the library reads the pair count once; when the pair buffers
+    are too small they are regrown to the exact need and the call repeats.
+    sync=False: no host synchronisation (the caller checks state later with
+    forward_check).  Returns (rgb [V,3,H,W], alpha [V,H,W], state[, debug]).
+    """
+    L = lib()
+    V = len(cams)
+    if V == 0 or len(views) != V:
+        raise ValueError("need one view state per camera")
+    W, H = int(cams[0]["width"]), int(cams[0]["height"])
+    n = int(model["layer"].shape[0])
+    dev = model["mean"].device
+    m = model_struct(model)
+    carr = (Camera * V)(*[camera_struct(c) for c in cams])
+    varr = (ViewState * V)(*[view_struct(v) for v in views])
+    if capacity is None:
+        capacity = state.capacity if state is not None else max(1024, 4 * n * V)
+    st = make_state(n, V, W, H, capacity, dev, state)
+    if out is None:
+        rgb = torch.empty((V, 3, H, W), dtype=torch.float32, device=dev)
+        alpha = torch.empty((V, H, W), dtype=torch.float32, device=dev)
+    else:
+        rgb, alpha = out
+    s = _stream(stream)
+    dbg = None
+    dbg_struct = None
+    for _attempt in range(3):
+        if debug:
+            R = n * V
+            dbg = {"n_tiles": torch.zeros(max(R, 1), dtype=torch.int32, device=dev),
+                   "tile_box": torch.zeros((max(R, 1), 4), dtype=torch.int32, device=dev),
+                   "keys_emit": torch.zeros(st.capacity, dtype=torch.int64, device=dev),
+                   "vals_emit": torch.zeros(st.capacity, dtype=torch.int32, device=dev),
+                   "keys_sorted": torch.zeros(st.capacity, dtype=torch.int64, device=dev)}
+            dbg_struct = Debug(*[dbg[k].data_ptr() for k in ("n_tiles", "tile_box", "keys_emit", "vals_emit",
+                                                             "keys_sorted")])
+        fs = st.struct()
+        npairs = C.c_uint32(0)
+        rc = L.gsr_rasterize_forward(C.byref(m), V, carr, varr, C.byref(fs), _ptr(st.workspace),
+                                     st.workspace.numel(), _ptr(rgb), _ptr(alpha),
+                                     C.byref(npairs) if sync else None,
+                                     C.byref(dbg_struct) if dbg_struct is not None else None, s)
+        if rc == GSR_ENOSPACE and sync:
+            st = make_state(n, V, W, H, int(npairs.value * 1.125) + 1024, dev, None)
+            continue
+        _check(rc, "gsr_rasterize_forward")
+        st.n_pairs = int(npairs.value) if sync else None
+        if debug:
+            return rgb, alpha, st, dbg
+        return rgb, alpha, st
+    raise GsrError(GSR_ENOSPACE, "gsr_rasterize_forward (capacity)")
+
+
+def forward_check(state, stream=None):
+    """After a sync=False forward: returns the pair count, raises on overflow/error."""
+    fs = state.struct()
+    npairs = C.c_uint32(0)
+    rc = lib().gsr_forward_check(C.byref(fs), C.byref(npairs), _stream(stream))
+    if rc == GSR_ENOSPACE:
+        raise GsrError(rc, f"forward needs {npairs.value} pairs, capacity {state.capacity}")
+    _check(rc, "gsr_forward_check")
+    return int(npairs.value)
+
+
+# ---------------------------------------------------------------- backward
+def rasterize_backward(model, cams, views, state, dL_drgb=None, dL_dalpha=None, trainable=0xFFFFFFFF,
+                       max_contrib=None, activity=None, grads=None, stream=None):
+    """Gradients w.r.t. the activated parameters (dict of tensors like model)."""
+    L = lib()
+    V = len(cams)
+    n = int(model["layer"].shape[0])
+    D = int(model["sh_degree"])
+    nc = (D + 1) ** 2
+    dev = model["mean"].device
+    m = model_struct(model)
+    carr = (Camera * V)(*[camera_struct(c) for c in cams])
+    varr = (ViewState * V)(*[view_struct(v) for v in views])
+    if grads is None:
+        grads = {"mean": torch.empty((3, n), dtype=torch.float32, device=dev),
+                 "scale": torch.empty((3, n), dtype=torch.float32, device=dev),
+                 "quat": torch.empty((4, n), dtype=torch.float32, device=dev),
+                 "opacity": torch.empty((n,), dtype=torch.float32, device=dev),
+                 "sh": torch.empty((nc, 3, n), dtype=torch.float32, device=dev)}
+    g = Grads(*[grads[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "sh")])
+    for t in (dL_drgb, dL_dalpha):
+        if t is not None and (not t.is_contiguous() or t.dtype != torch.float32):
+            raise ValueError("upstream gradients must be contiguous float32")
+    fs = state.struct()
+    rc = L.gsr_rasterize_backward(C.byref(m), V, carr, varr, C.byref(fs), _ptr(dL_drgb), _ptr(dL_dalpha),
+                                  int(trainable) & 0xFFFFFFFF, _ptr(state.workspace), state.workspace.numel(),
+                                  C.byref(g), _ptr(max_contrib), _ptr(activity), _stream(stream))
+    _check(rc, "gsr_rasterize_backward")
+    return grads
+
+
+# ---------------------------------------------------------------- batch
+def request_struct(model_index, cams, vs, rgbs, alphas):
+    r = Request()
+    r.model = int(model_index)
+    r.n_views = len(cams)
+    for e, cam in enumerate(cams):
+        r.cam[e] = camera_struct(cam)
+        r.rgb[e] = rgbs[e].data_ptr()
+        r.alpha[e] = alphas[e].data_ptr()
+    r.vs = view_struct(vs)
+    return r
+
+
+def batch_workspace_size(models_struct, reqs_struct, capacity):
+    return int(lib().gsr_batch_workspace_size(models_struct, len(models_struct), reqs_struct, len(reqs_struct),
+                                              int(capacity)))
+
+
+def render_batch(models, requests, capacity, workspace=None, status=None, outputs=None, stream=None):
+    """Render requests [{"model": i, "cams": [cam] or [left, right], "view": vs}]
+    over resident models in one pass.  Returns (outputs, status tensor,
+    workspace); outputs[q] = (rgb list, alpha list).  Never synchronises."""
+    L = lib()
+    dev = models[0]["mean"].device
+    mstructs = (Model * len(models))(*[model_struct(m) for m in models])
+    if outputs is None:
+        outputs = []
+        for rq in requests:
+            rgbs = [torch.empty((3, c["height"], c["width"]), dtype=torch.float32, device=dev) for c in rq["cams"]]
+            alphas = [torch.empty((c["height"], c["width"]), dtype=torch.float32, device=dev) for c in rq["cams"]]
+            outputs.append((rgbs, alphas))
+    rstructs = (Request * len(requests))(*[request_struct(rq["model"], rq["cams"], rq["view"], o[0], o[1])
+                                           for rq, o in zip(requests, outputs)])
+    need = batch_workspace_size(mstructs, rstructs, capacity)
+    if need == 0:
+        raise GsrError(GSR_EINVAL, "gsr_batch_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if status is None or status.numel() < len(requests):
+        status = torch.empty(len(requests), dtype=torch.int32, device=dev)
+    rc = L.gsr_render_batch(mstructs, len(models), rstructs, len(requests), int(capacity), _ptr(workspace),
+                            workspace.numel(), _ptr(status), _stream(stream))
+    _check(rc, "gsr_render_batch")
+    return outputs, status, workspace

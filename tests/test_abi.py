@@ -1,0 +1,83 @@
+"""The C-ABI library loads without a GPU, exports every entry point that
+include/gsr.h declares, and the Python binding's struct layouts match the
+header's (checked against a C program compiled here)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(gsr_[a-z_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("gsr_rasterize_forward", "gsr_rasterize_backward", "gsr_render_batch", "gsr_workspace_size",
+                 "gsr_batch_workspace_size", "gsr_forward_check", "gsr_status_string"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2410_16978_amd import rasterizer
+    L = rasterizer.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_host_only_calls():
+    from paper_2410_16978_amd import rasterizer as rz
+    L = rz.lib()
+    assert rz.status_string(rz.GSR_ENOSPACE).startswith("workspace")
+    assert rz.workspace_size(4096, 1, 128, 128, 10000) > 0
+    assert rz.workspace_size(-1, 1, 128, 128, 10000) == 0
+    assert rz.workspace_size(10, 0, 128, 128, 10000) == 0
+    assert rz.workspace_size(10, 1, 128, 128, 1 << 30) == 0
+    # the forward rejects bad arguments before touching the device
+    m = rz.Model(-1, 0, None, None, None, None, None, None)
+    rc = L.gsr_rasterize_forward(C.byref(m), 1, None, None, None, None, 0, None, None, None, None, None)
+    assert rc == rz.GSR_EINVAL
+
+
+_LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "gsr.h"
+#define P(T) printf(#T " %zu\n", sizeof(T))
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  P(gsr_camera); O(gsr_camera, fx); O(gsr_camera, width); O(gsr_camera, guard);
+  P(gsr_clip_plane); P(gsr_view_state); O(gsr_view_state, clip); O(gsr_view_state, bg);
+  P(gsr_model); O(gsr_model, mean); O(gsr_model, layer);
+  P(gsr_fwd_state); O(gsr_fwd_state, pair_capacity);
+  P(gsr_debug); P(gsr_grads);
+  P(gsr_request); O(gsr_request, cam); O(gsr_request, vs); O(gsr_request, rgb); O(gsr_request, alpha);
+  return 0;
+}
+"""
+
+
+def test_binding_struct_layout_matches_header(tmp_path):
+    from paper_2410_16978_amd import rasterizer as rz
+    src = tmp_path / "layout.c"
+    src.write_text(_LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    py = {"gsr_camera": rz.Camera, "gsr_clip_plane": rz.ClipPlane, "gsr_view_state": rz.ViewState,
+          "gsr_model": rz.Model, "gsr_fwd_state": rz.FwdState, "gsr_debug": rz.Debug, "gsr_grads": rz.Grads,
+          "gsr_request": rz.Request}
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(py[t], f).offset == int(val), key
+        else:
+            assert C.sizeof(py[key]) == int(val), key
