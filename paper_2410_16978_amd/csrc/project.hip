@@ -7,6 +7,29 @@
 
 namespace gsr {
 
+// Correctly rounded square root.  The hardware square root is within one ulp;
+// the exactly rounded residuals x - s' s of its two neighbours s' decide
+// whether the round-to-nearest root is a neighbour.  (x - dn*s <= 0 means
+// sqrt(x) lies below the geometric, hence below the arithmetic, mean of dn
+// and s; a float x cannot fall between dn*s and the squared midpoint, which
+// differ by a quarter of a squared ulp, less than one unit of the exact
+// product.  Symmetrically for the upper neighbour.)  Tiny inputs are scaled
+// by 2^32 so the estimate stays accurate.
+__device__ __forceinline__ float sqrt_rn(float x) {
+  if (!(x > 0.f) || isinf(x)) return __builtin_sqrtf(x);
+  const bool tiny = x < 0x1p-96f;
+  const float xs = tiny ? x * 0x1p+32f : x;
+  float s = __builtin_amdgcn_sqrtf(xs);
+  const float dn = __uint_as_float(__float_as_uint(s) - 1u);
+  const float up = __uint_as_float(__float_as_uint(s) + 1u);
+  if (fmaf(-dn, s, xs) <= 0.f) {
+    s = dn;
+  } else if (fmaf(-up, s, xs) > 0.f) {
+    s = up;
+  }
+  return tiny ? s * 0x1p-16f : s;
+}
+
 __global__ void __launch_bounds__(256) k_clear_u32(uint32_t* __restrict__ p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -65,7 +88,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       if (op < kAlphaMin) break;
       if (qn < 0.f) {
         float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
-        qn = __fsqrt_rn(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+        qn = sqrt_rn(((qw * qw + qx * qx) + qy * qy) + qz * qz);
         if (!(qn > 0.f)) { qn = 0.f; break; }
         qw = __fdiv_rn(qw, qn); qx = __fdiv_rn(qx, qn); qy = __fdiv_rn(qy, qn); qz = __fdiv_rn(qz, qn);
         Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
@@ -127,7 +150,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const float u = __fdiv_rn(V.fx * tx, tz) + V.cx;
       const float v = __fdiv_rn(V.fy * ty, tz) + V.cy;
       // tile box of {q <= qmax}: clamp in float, then convert
-      const float hwx = __fsqrt_rn(kQMax * a), hwy = __fsqrt_rn(kQMax * c);
+      const float hwx = sqrt_rn(kQMax * a), hwy = sqrt_rn(kQMax * c);
       const float ftx = (float)V.tiles_x, fty = (float)V.tiles_y;
       const float inv_tile = 1.0f / (float)kTile;
       const float fx0 = fminf(fmaxf(floorf((u - hwx) * inv_tile), 0.f), ftx);
@@ -142,7 +165,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const float ccy = -((W[1] * V.t[0] + W[4] * V.t[1]) + W[7] * V.t[2]);
       const float ccz = -((W[2] * V.t[0] + W[5] * V.t[1]) + W[8] * V.t[2]);
       const float ddx = mx - ccx, ddy = my - ccy, ddz = mz - ccz;
-      const float dl = __fsqrt_rn((ddx * ddx + ddy * ddy) + ddz * ddz);
+      const float dl = sqrt_rn((ddx * ddx + ddy * ddy) + ddz * ddz);
       const float dirx = __fdiv_rn(ddx, dl), diry = __fdiv_rn(ddy, dl), dirz = __fdiv_rn(ddz, dl);
       float Y[16];
       sh_basis<D>(dirx, diry, dirz, Y);

@@ -37,6 +37,14 @@ def compare_forward(scene, cams, views, orc, check_pairs=True, label=""):
     rec = st.records.view(-1, 12).cpu().numpy()[:R]
     got = rec[valid][:, [0, 1, 2, 3, 4, 5, 9, 6, 7, 8]]  # u v a b c o depth r g b
     want = ref["rec"][valid]
+    diff = got.view(np.int32).astype(np.int64) - want.astype(np.float32).view(np.int32).astype(np.int64)
+    if np.any(diff):
+        names = "u v conic_a conic_b conic_c opacity depth r g b".split()
+        for c in range(10):
+            bad = np.nonzero(diff[:, c])[0]
+            if len(bad):
+                print(f"{label} record field {names[c]}: {len(bad)} differ, max ulps {np.abs(diff[:, c]).max()}, "
+                      f"e.g. gpu {got[bad[0], c]!r} oracle {want[bad[0], c]!r}")
     np.testing.assert_array_equal(got.view(np.uint32), want.astype(np.float32).view(np.uint32),
                                   err_msg=f"{label} records")
     np.testing.assert_array_equal(rec[valid][:, 10].view(np.uint32), ref["clamp"][valid], err_msg=f"{label} clamp")
