@@ -1,0 +1,71 @@
+"""torch.autograd.Function around the HIP rasterizer.
+
+The forward and the backward are the library's kernels (gsr_rasterize_forward
+/ gsr_rasterize_backward); torch only applies the parameter activations
+(exp of the log-scales, sigmoid of the opacity logits) and their chain rule,
+and holds the buffers.  Frozen layers (the paper's consecutive layer
+training, Sec. 3.2) get zero gradient through `trainable_layers`.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import rasterizer as rz
+
+
+class RenderContext:
+    """Reusable buffers of one rendering configuration (pair capacity,
+    workspace, per-Gaussian accumulators for pruning)."""
+
+    def __init__(self, trainable_layers=0xFFFFFFFF, track_activity=False, sync=True):
+        self.state = None
+        self.trainable_layers = int(trainable_layers)
+        self.track_activity = track_activity
+        self.sync = sync
+        self.max_contrib = None
+        self.activity = None
+
+    def reset_accumulators(self, n, device):
+        self.max_contrib = torch.zeros(n, dtype=torch.float32, device=device)
+        self.activity = torch.zeros(n, dtype=torch.float32, device=device)
+
+
+class _RasterizeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx):
+        model = {"mean": mean.contiguous(), "scale": scale.contiguous(), "quat": quat.contiguous(),
+                 "opacity": opacity.contiguous(), "sh": sh.contiguous(), "layer": layer, "sh_degree": sh_degree}
+        rgb, alpha, st = rz.rasterize_forward(model, cams, views, state=rctx.state, sync=rctx.sync)
+        rctx.state = st
+        ctx.model = model
+        ctx.cams, ctx.views, ctx.rctx, ctx.state = cams, views, rctx, st
+        return rgb, alpha
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_alpha):
+        rctx = ctx.rctx
+        mc = act = None
+        if rctx.track_activity:
+            n = ctx.model["mean"].shape[1]
+            if rctx.max_contrib is None or rctx.max_contrib.numel() != n:
+                rctx.reset_accumulators(n, ctx.model["mean"].device)
+            mc, act = rctx.max_contrib, rctx.activity
+        g = rz.rasterize_backward(ctx.model, ctx.cams, ctx.views, ctx.state,
+                                  g_rgb.contiguous() if g_rgb is not None else None,
+                                  g_alpha.contiguous() if g_alpha is not None else None,
+                                  trainable=rctx.trainable_layers, max_contrib=mc, activity=act)
+        return g["mean"], g["scale"], g["quat"], g["opacity"], g["sh"], None, None, None, None, None
+
+
+def rasterize(mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx=None):
+    """Differentiable render of len(cams) equal-size views; activated inputs.
+    Returns rgb [V,3,H,W] and alpha [V,H,W]."""
+    if rctx is None:
+        rctx = RenderContext()
+    return _RasterizeFn.apply(mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx)
+
+
+def render_params(params, layer, sh_degree, cams, views, rctx=None):
+    """Render from raw parameters {mean, log_scale, quat, opacity_logit, sh}."""
+    return rasterize(params["mean"], torch.exp(params["log_scale"]), params["quat"],
+                     torch.sigmoid(params["opacity_logit"]), params["sh"], layer, sh_degree, cams, views, rctx)
