@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Benchmark of the layered Gaussian-splat rasterizer on one MI355X.
+
+Default workload: one training step of 200k Gaussians in 4 nested shell
+layers (50k each), SH degree 3, one 800x800 view: forward render, L1 loss on
+RGB and alpha against a target rendered from a perturbed copy of the scene
+(random background per step, the paper's alpha-channel training), and the
+backward to every Gaussian parameter.  All inputs are synthetic and resident
+in HBM before timing.  Prints ONE JSON line.
+
+Beside the step throughput it reports the forward render rate (Mpix/s) and
+p50/p99 latencies, a live per-stage timing (HIP events recorded by the
+library on the stream it launches on), the roofline of the dominant kernel
+and, on the host, the CPU oracle timed on one full step of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "render Mpix/s + p50/p99 frame latency; fwd+bwd iters/s; vs plain, 1 GPU"
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (packed) peak, published
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
+STAGES = ("project", "scan", "duplicate", "sort", "ranges", "blend", "blend_bwd", "project_bwd")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_training_step_200k.json")
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = max(0, min(len(xs) - 1, int(np.ceil(q / 100.0 * len(xs))) - 1))  # nearest rank
+    return float(xs[k])
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("blend.hip", "sort.hip", "project.hip", "project_bwd.hip", "pairs.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2410_16978_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_work(orc_fwd, scene, n_pix):
+    """Per-launch algorithmic flops/bytes of each stage from the oracle's
+    exact counts on the same scene (units and per-unit costs: the design doc)."""
+    K, E, A = orc_fwd["counts"]["K"], orc_fwd["counts"]["E"], orc_fwd["counts"]["A"]
+    last = orc_fwd["last"].reshape(-1).astype(np.int64)
+    ranges = orc_fwd["ranges"]
+    # evaluated pairs of the backward: per pixel, the tile's pairs up to its last blended one
+    H, W = orc_fwd["last"].shape[-2:]
+    tx = (W + 15) // 16
+    ys, xs = np.divmod(np.arange(H * W), W)
+    tile = (ys // 16) * tx + xs // 16
+    start = ranges[tile, 0].astype(np.int64)
+    Eb = int(np.where(last > 0, last - start, 0).sum())
+    n = scene["mean"].shape[1]
+    nv = int((orc_fwd["n_tiles"] > 0).sum())
+    D = scene["sh_degree"]
+    nc = (D + 1) ** 2
+    tiles = orc_fwd["counts"]["tiles"]
+    return {
+        "K": K, "E": E, "A": A, "Eb": Eb, "visible": nv,
+        "blend": {"flops": 14 * E + 9 * A},
+        "blend_bwd": {"flops": 14 * Eb + 50 * A},
+        # bytes: all Gaussians read mean/opacity/layer/quat/scale (+ SH when visible), records written
+        "project": {"bytes": n * (12 + 4 + 1 + 16 + 12 + 4) + nv * (12 * nc + 48 + 16)},
+        "sort": {"bytes": (8 + 24 * 5) * K},
+        "duplicate": {"bytes": nv * 24 + 12 * K},
+        "ranges": {"bytes": 8 * K + 8 * tiles},
+        "scan": {"bytes": 8 * n},
+        "project_bwd": {"bytes": nv * (36 + 48 + 12 * nc + 40 + 4 * (10 + 3 * nc)) + 4 * n * (11 + 3 * nc)},
+        "pixels": n_pix,
+    }
+
+
+def run_cpu_baseline(workload, threads):
+    """The oracle (as it stands) on one full step of the same workload."""
+    import oracle
+    sc, cams, views = workload.scene, workload.cams, workload.views
+    H, W = cams[0]["height"], cams[0]["width"]
+    rng = np.random.default_rng(7)
+    Gr = (rng.standard_normal((1, 3, H, W)) * 1e-6).astype(np.float32)
+    Ga = (rng.standard_normal((1, H, W)) * 1e-6).astype(np.float32)
+    t0 = time.perf_counter()
+    fwd = oracle.render(sc, cams, views, pairs=False, n_threads=threads)
+    t1 = time.perf_counter()
+    oracle.backward(sc, cams, views, Gr, Ga, n_threads=threads)
+    t2 = time.perf_counter()
+    return fwd, t1 - t0, t2 - t1
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all host cores, at most 16)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_16978_amd import autograd as ag
+    from paper_2410_16978_amd import rasterizer as rz
+    from paper_2410_16978_amd import scenes
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = "cuda"
+    wl = scenes.training_step_200k(seed=0)
+    sc = wl.scene
+    cam = wl.cams[0]
+    H, W = cam["height"], cam["width"]
+    n = sc["mean"].shape[1]
+    D = sc["sh_degree"]
+
+    # ---------------- inputs resident in HBM
+    params = {k: torch.tensor(sc[k], device=dev, requires_grad=True)
+              for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")}
+    layer = torch.tensor(sc["layer"], device=dev)
+    target_model = rz.to_device(wl.extra["target_scene"])
+    t_rgb, t_alpha, _ = rz.rasterize_forward(target_model, wl.cams, [scenes.view_state(0xF, bg=(0, 0, 0))])
+    bg_rng = np.random.default_rng(123)
+    bgs = [tuple(float(x) for x in bg_rng.uniform(0, 1, 3)) for _ in range(args.steps + args.warmup + 1)]
+    bg_t = [torch.tensor(b, device=dev, dtype=torch.float32).view(1, 3, 1, 1) for b in bgs]
+    views_per_step = [[scenes.view_state(0xF, bg=b)] for b in bgs]
+
+    rctx = ag.RenderContext(sync=True)
+
+    def step(i):
+        vs = views_per_step[i]
+        rgb, alpha = ag.render_params(params, layer, D, wl.cams, vs, rctx)
+        target = t_rgb + (1.0 - t_alpha).unsqueeze(1) * bg_t[i]
+        loss = (rgb - target).abs().mean() + (alpha - t_alpha).abs().mean()
+        loss.backward()
+        for p in params.values():
+            p.grad = None
+        return loss
+
+    # first step sizes the pair buffers (one synchronising call), then no host syncs
+    step(0)
+    torch.cuda.synchronize()
+    K0 = rctx.state.n_pairs
+    rctx.state = rz.make_state(n, 1, W, H, int(K0 * 1.25) + 4096, dev)
+    rctx.sync = False
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    # ---------------- timed: K training steps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for i in range(args.steps):
+        step(args.warmup + i)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rz.forward_check(rctx.state)  # pair capacity held for every step
+    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
+    total_ms = evs[0].elapsed_time(evs[-1])
+    ms_per_step = total_ms / args.steps
+
+    # ---------------- forward-only render rate (same scene, no autograd)
+    with torch.no_grad():
+        model = {"mean": params["mean"].detach(), "scale": torch.exp(params["log_scale"]).detach(),
+                 "quat": params["quat"].detach(), "opacity": torch.sigmoid(params["opacity_logit"]).detach(),
+                 "sh": params["sh"].detach(), "layer": layer, "sh_degree": D}
+        fst = rz.make_state(n, 1, W, H, rctx.state.capacity, dev)
+        out = (torch.empty((1, 3, H, W), device=dev), torch.empty((1, H, W), device=dev))
+        for i in range(args.warmup):
+            rz.rasterize_forward(model, wl.cams, views_per_step[i], state=fst, sync=False, out=out)
+        fevs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        fevs[0].record()
+        for i in range(args.steps):
+            rz.rasterize_forward(model, wl.cams, views_per_step[i], state=fst, sync=False, out=out)
+            fevs[i + 1].record()
+        torch.cuda.synchronize()
+        fwd_ms = [fevs[i].elapsed_time(fevs[i + 1]) for i in range(args.steps)]
+        fwd_mean = fevs[0].elapsed_time(fevs[-1]) / args.steps
+
+    # ---------------- per-stage timing over K steps (library-recorded HIP events)
+    timer = rz.Timer()
+    rctx.timer = timer
+    timer.read()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    stages = timer.read()
+    rctx.timer = None
+    stage_ms = {s: (ms / max(c, 1)) for s, (ms, c) in stages.items()}
+
+    result = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms_per_step, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "gaussians": n, "layers": 4, "sh_degree": D, "width": W, "height": H,
+                   "views_per_step": 1, "step": "forward + L1(rgb, alpha) + backward, random background"},
+        "p50_ms": round(percentile(step_ms, 50), 4),
+        "p99_ms": round(percentile(step_ms, 99), 4),
+        "render_mpix_s": round(W * H / (fwd_mean * 1e-3) / 1e6, 2),
+        "render_p50_ms": round(percentile(fwd_ms, 50), 4),
+        "render_p99_ms": round(percentile(fwd_ms, 99), 4),
+        "wall_s": round(wall, 3),
+        "pairs": K0,
+        "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
+    }
+
+    # ---------------- CPU oracle on one step of the same workload
+    threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+    orc_fwd = None
+    if not args.no_cpu_baseline:
+        orc_fwd, t_f, t_b = run_cpu_baseline(wl, threads)
+        result["cpu_baseline"] = {"value": round(1.0 / (t_f + t_b), 4), "unit": "iters/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": "one full step (forward + backward) of the same 200k/800x800 "
+                                            "workload; forward %.2f s, backward %.2f s" % (t_f, t_b)}
+    else:
+        import oracle
+        orc_fwd = oracle.render(wl.scene, wl.cams, wl.views, n_threads=threads)
+
+    # ---------------- roofline of the dominant kernel
+    work = algorithmic_work(orc_fwd, sc, W * H)
+    dom = max(stage_ms, key=lambda s: stage_ms[s])
+    sec = stage_ms[dom] * 1e-3
+    if "flops" in work.get(dom, {}):
+        ach = work[dom]["flops"] / sec / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4)}
+    else:
+        ach = work[dom]["bytes"] / sec / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4)}
+    roof["traffic"] = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel") == dom and tr.get("source_hash") == kernel_source_hash():
+            roof["traffic"] = tr.get("bytes_per_launch")
+    roof["launch_ms"] = round(stage_ms[dom], 4)
+    result["roofline"] = roof
+    result["algorithmic"] = {k: v for k, v in work.items() if k in ("K", "E", "A", "Eb", "visible")}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

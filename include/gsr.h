@@ -133,11 +133,35 @@ typedef struct {
  * call then synchronises the stream once. */
 typedef struct {
   uint32_t* n_tiles;    /* [R] tiles touched by each record */
-  uint32_t* tile_box;   /* [R][4]: x0 | y0 << 16, x1 | y1 << 16, depth bits, n_tiles */
+  uint32_t* tile_box;   /* [R][4]: global id of the box's first tile, width | height << 16
+                           (in tiles), depth bits, tiles per image row */
   uint64_t* keys_emit;  /* [P] keys in emission order (record order, tiles row-major) */
   uint32_t* vals_emit;  /* [P] */
   uint64_t* keys_sorted;/* [P] */
 } gsr_debug;
+
+/* Per-stage timer (host object holding HIP events).  When a timer is passed
+ * to an entry point, the library records an event pair on the caller's
+ * stream around each stage it launches; gsr_timer_read synchronises on the
+ * recorded events, returns the summed milliseconds and launch counts per
+ * stage since the last read, and starts a new accumulation.  Recording adds
+ * two event records per stage and call.  A timer must not be used from two
+ * threads at once. */
+typedef struct gsr_timer gsr_timer;
+enum {
+  GSR_STAGE_PROJECT = 0,
+  GSR_STAGE_SCAN,
+  GSR_STAGE_DUPLICATE,
+  GSR_STAGE_SORT,
+  GSR_STAGE_RANGES,
+  GSR_STAGE_BLEND,
+  GSR_STAGE_BLEND_BWD,
+  GSR_STAGE_PROJECT_BWD,
+  GSR_N_STAGES
+};
+gsr_status gsr_timer_create(gsr_timer** out);
+void gsr_timer_destroy(gsr_timer* t);
+gsr_status gsr_timer_read(gsr_timer* t, float* ms /* [GSR_N_STAGES] */, uint32_t* calls /* [GSR_N_STAGES] */);
 
 /* Bytes of scratch workspace a forward or backward of n_views views of a
  * model with n Gaussians at width x height needs, for a pair capacity of
@@ -156,11 +180,13 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
  * call never synchronises; on overflow the pairs beyond the capacity are
  * dropped, state->counters[1] is set and the image is incomplete - check
  * with gsr_forward_check after synchronising.
- * ws: scratch of at least gsr_workspace_size(...) bytes, 256-byte aligned. */
+ * ws: scratch of at least gsr_workspace_size(...) bytes, 256-byte aligned.
+ * timer: optional (NULL), see gsr_timer. */
 gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
                                  const gsr_view_state* views, gsr_fwd_state* state,
                                  void* ws, size_t ws_bytes, float* rgb, float* alpha,
-                                 uint32_t* n_pairs_host, const gsr_debug* debug, void* stream);
+                                 uint32_t* n_pairs_host, const gsr_debug* debug, gsr_timer* timer,
+                                 void* stream);
 
 /* After a non-synchronising forward has completed (caller synchronised):
  * reads state->counters and returns GSR_OK, GSR_ENOSPACE (pair capacity
@@ -189,7 +215,7 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
                                   const float* dL_drgb, const float* dL_dalpha,
                                   uint32_t trainable_layers, void* ws, size_t ws_bytes,
                                   const gsr_grads* grads, float* max_contrib, float* activity,
-                                  void* stream);
+                                  gsr_timer* timer, void* stream);
 
 /* One render request of a batch (host struct): one or two views (stereo)
  * of models[model] sharing one view state, each written to its own
@@ -219,7 +245,7 @@ size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const
  * rendering it alone. */
 gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs,
                             int32_t n_req, uint32_t pair_capacity, void* ws, size_t ws_bytes,
-                            int32_t* req_status, void* stream);
+                            int32_t* req_status, gsr_timer* timer, void* stream);
 
 /* Human-readable name of a status. */
 const char* gsr_status_string(gsr_status s);

@@ -17,8 +17,9 @@ class RenderContext:
     """Reusable buffers of one rendering configuration (pair capacity,
     workspace, per-Gaussian accumulators for pruning)."""
 
-    def __init__(self, trainable_layers=0xFFFFFFFF, track_activity=False, sync=True):
+    def __init__(self, trainable_layers=0xFFFFFFFF, track_activity=False, sync=True, timer=None):
         self.state = None
+        self.timer = timer
         self.trainable_layers = int(trainable_layers)
         self.track_activity = track_activity
         self.sync = sync
@@ -35,7 +36,7 @@ class _RasterizeFn(torch.autograd.Function):
     def forward(ctx, mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx):
         model = {"mean": mean.contiguous(), "scale": scale.contiguous(), "quat": quat.contiguous(),
                  "opacity": opacity.contiguous(), "sh": sh.contiguous(), "layer": layer, "sh_degree": sh_degree}
-        rgb, alpha, st = rz.rasterize_forward(model, cams, views, state=rctx.state, sync=rctx.sync)
+        rgb, alpha, st = rz.rasterize_forward(model, cams, views, state=rctx.state, sync=rctx.sync, timer=rctx.timer)
         rctx.state = st
         ctx.model = model
         ctx.cams, ctx.views, ctx.rctx, ctx.state = cams, views, rctx, st
@@ -53,7 +54,7 @@ class _RasterizeFn(torch.autograd.Function):
         g = rz.rasterize_backward(ctx.model, ctx.cams, ctx.views, ctx.state,
                                   g_rgb.contiguous() if g_rgb is not None else None,
                                   g_alpha.contiguous() if g_alpha is not None else None,
-                                  trainable=rctx.trainable_layers, max_contrib=mc, activity=act)
+                                  trainable=rctx.trainable_layers, max_contrib=mc, activity=act, timer=rctx.timer)
         return g["mean"], g["scale"], g["quat"], g["opacity"], g["sh"], None, None, None, None, None
 
 

@@ -155,6 +155,48 @@ std::vector<JobD> make_jobs(const ModelD& m, const std::vector<int>& view_ids) {
     if ((expr) != hipSuccess) return GSR_EHIP; \
   } while (0)
 
+}  // namespace
+
+struct gsr_timer {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Mark { int stage; size_t e0, e1; };
+  std::vector<Mark> marks;
+
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+namespace {
+
+// Event pair around one stage when a timer is attached.
+struct StageScope {
+  gsr_timer* t;
+  int stage;
+  hipStream_t s;
+  size_t e0 = 0;
+  bool ok = false;
+  StageScope(gsr_timer* tm, int st, hipStream_t str) : t(tm), stage(st), s(str) {
+    if (!t) return;
+    hipEvent_t e = t->next();
+    if (!e) return;
+    e0 = t->used - 1;
+    ok = hipEventRecord(e, s) == hipSuccess;
+  }
+  ~StageScope() {
+    if (!t || !ok) return;
+    hipEvent_t e = t->next();
+    if (!e) return;
+    if (hipEventRecord(e, s) == hipSuccess) t->marks.push_back({stage, e0, t->used - 1});
+  }
+};
+
 bool single_view_args_ok(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
                          const gsr_view_state* views) {
   if (!model_ok(model) || n_views <= 0 || !cams || !views) return false;
@@ -169,6 +211,42 @@ bool single_view_args_ok(const gsr_model* model, int32_t n_views, const gsr_came
 }  // namespace
 
 extern "C" {
+
+gsr_status gsr_timer_create(gsr_timer** out) {
+  if (!out) return GSR_EINVAL;
+  *out = new gsr_timer();
+  return GSR_OK;
+}
+
+void gsr_timer_destroy(gsr_timer* t) {
+  if (!t) return;
+  for (hipEvent_t e : t->pool) (void)hipEventDestroy(e);
+  delete t;
+}
+
+gsr_status gsr_timer_read(gsr_timer* t, float* ms, uint32_t* calls) {
+  if (!t) return GSR_EINVAL;
+  float acc[GSR_N_STAGES] = {0};
+  uint32_t cnt[GSR_N_STAGES] = {0};
+  gsr_status st = GSR_OK;
+  for (const gsr_timer::Mark& m : t->marks) {
+    float x = 0.f;
+    if (hipEventSynchronize(t->pool[m.e1]) != hipSuccess ||
+        hipEventElapsedTime(&x, t->pool[m.e0], t->pool[m.e1]) != hipSuccess) {
+      st = GSR_EHIP;
+      continue;
+    }
+    acc[m.stage] += x;
+    cnt[m.stage] += 1;
+  }
+  t->marks.clear();
+  t->used = 0;
+  for (int k = 0; k < GSR_N_STAGES; ++k) {
+    if (ms) ms[k] = acc[k];
+    if (calls) calls[k] = cnt[k];
+  }
+  return st;
+}
 
 const char* gsr_status_string(gsr_status s) {
   switch (s) {
@@ -191,7 +269,7 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
 gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
                                  const gsr_view_state* views, gsr_fwd_state* state, void* ws, size_t ws_bytes,
                                  float* rgb, float* alpha, uint32_t* n_pairs_host, const gsr_debug* debug,
-                                 void* stream) {
+                                 gsr_timer* timer, void* stream) {
   if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !rgb || !alpha) return GSR_EINVAL;
   if (!state->records || !state->pair_vals || !state->sort_sel || !state->ranges || !state->final_T ||
       !state->last || !state->counters || state->pair_capacity >= (1u << 30))
@@ -227,8 +305,15 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   HIP_TRY(launch_clear_u32(state->counters, 4, s));
   HIP_TRY(launch_clear_u32(state->ranges, 2 * X, s));
   const ModelD md = make_model(*model);
-  for (const JobD& j : make_jobs(md, ids)) HIP_TRY(launch_project(j, b.views, state->records, b.n_tiles, b.tile_box, s));
-  HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, state->counters, P, s));
+  {
+    StageScope sc(timer, GSR_STAGE_PROJECT, s);
+    for (const JobD& j : make_jobs(md, ids))
+      HIP_TRY(launch_project(j, b.views, state->records, b.n_tiles, b.tile_box, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_SCAN, s);
+    HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, state->counters, P, s));
+  }
   if (n_pairs_host) {
     uint32_t K = 0;
     HIP_TRY(hipMemcpyAsync(&K, state->counters + kCntPairs, 4, hipMemcpyDeviceToHost, s));
@@ -236,17 +321,29 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     *n_pairs_host = K;
     if (K > P) return GSR_ENOSPACE;
   }
-  HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, state->counters, P, b.keys_a, state->pair_vals, s));
+  {
+    StageScope sc(timer, GSR_STAGE_DUPLICATE, s);
+    HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, state->counters, P, b.keys_a, state->pair_vals, s));
+  }
   if (debug && (debug->keys_emit || debug->vals_emit)) {
     if (debug->keys_emit) HIP_TRY(hipMemcpyAsync(debug->keys_emit, b.keys_a, 8ull * P, hipMemcpyDeviceToDevice, s));
     if (debug->vals_emit) HIP_TRY(hipMemcpyAsync(debug->vals_emit, state->pair_vals, 4ull * P, hipMemcpyDeviceToDevice, s));
   }
-  HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
-                      key_bits_for(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, state->sort_sel,
-                      state->counters + kCntError, s));
-  HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
-  HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals, state->sort_sel, P,
-                           state->ranges, &b.ctl->tile_ctr, nullptr, false, s));
+  {
+    StageScope sc(timer, GSR_STAGE_SORT, s);
+    HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
+                        key_bits_for(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, state->sort_sel,
+                        state->counters + kCntError, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_RANGES, s);
+    HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_BLEND, s);
+    HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals, state->sort_sel, P,
+                             state->ranges, &b.ctl->tile_ctr, nullptr, false, s));
+  }
   if (debug) {
     if (debug->n_tiles) HIP_TRY(hipMemcpyAsync(debug->n_tiles, b.n_tiles, 4ull * R, hipMemcpyDeviceToDevice, s));
     if (debug->tile_box) HIP_TRY(hipMemcpyAsync(debug->tile_box, b.tile_box, 16ull * R, hipMemcpyDeviceToDevice, s));
@@ -276,7 +373,8 @@ gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host,
 gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
                                   const gsr_view_state* views, const gsr_fwd_state* state, const float* dL_drgb,
                                   const float* dL_dalpha, uint32_t trainable_layers, void* ws, size_t ws_bytes,
-                                  const gsr_grads* grads, float* max_contrib, float* activity, void* stream) {
+                                  const gsr_grads* grads, float* max_contrib, float* activity, gsr_timer* timer,
+                                  void* stream) {
   if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !grads) return GSR_EINVAL;
   if (n_views > kMaxJobViews) return GSR_EINVAL;
   if (model->n > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_sh))
@@ -309,12 +407,18 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
   HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
   HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.g2d), 9ull * R, s));
   // max_contrib is indexed by Gaussian: records of view v start at v * n
-  HIP_TRY(launch_blend_bwd(b.views, n_views, (uint32_t)X, state->records, state->pair_vals, state->sort_sel, P,
-                           state->ranges, dL_drgb, dL_dalpha, b.g2d, R, max_contrib, s));
+  {
+    StageScope sc(timer, GSR_STAGE_BLEND_BWD, s);
+    HIP_TRY(launch_blend_bwd(b.views, n_views, (uint32_t)X, state->records, state->pair_vals, state->sort_sel, P,
+                             state->ranges, dL_drgb, dL_dalpha, b.g2d, R, max_contrib, s));
+  }
   const ModelD md = make_model(*model);
-  for (const JobD& j : make_jobs(md, ids))
-    HIP_TRY(launch_project_bwd(j, b.views, state->records, b.g2d, R, trainable_layers, grads->g_mean,
-                               grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_sh, activity, s));
+  {
+    StageScope sc(timer, GSR_STAGE_PROJECT_BWD, s);
+    for (const JobD& j : make_jobs(md, ids))
+      HIP_TRY(launch_project_bwd(j, b.views, state->records, b.g2d, R, trainable_layers, grads->g_mean,
+                                 grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_sh, activity, s));
+  }
   return GSR_OK;
 }
 
@@ -367,7 +471,8 @@ size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const
 }
 
 gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs, int32_t n_req,
-                            uint32_t pair_capacity, void* ws, size_t ws_bytes, int32_t* req_status, void* stream) {
+                            uint32_t pair_capacity, void* ws, size_t ws_bytes, int32_t* req_status, gsr_timer* timer,
+                            void* stream) {
   BatchPlan bp;
   if (!plan_batch(models, n_models, reqs, n_req, bp) || !ws || !req_status || pair_capacity >= (1u << 30))
     return GSR_EINVAL;
@@ -390,22 +495,41 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.ctl), sizeof(SortCtl) / 4, s));
   HIP_TRY(launch_clear_u32(b.counters, 4, s));
   HIP_TRY(launch_clear_u32(b.ranges, 2 * bp.X, s));
-  for (int m = 0; m < n_models; ++m) {
-    std::vector<int> ids;
-    for (int v = 0; v < n_views; ++v)
-      if ((int)bp.views[v].model == m) ids.push_back(v);
-    if (ids.empty()) continue;
-    const ModelD md = make_model(models[m]);
-    for (const JobD& j : make_jobs(md, ids)) HIP_TRY(launch_project(j, b.views, b.records, b.n_tiles, b.tile_box, s));
+  {
+    StageScope sc(timer, GSR_STAGE_PROJECT, s);
+    for (int m = 0; m < n_models; ++m) {
+      std::vector<int> ids;
+      for (int v = 0; v < n_views; ++v)
+        if ((int)bp.views[v].model == m) ids.push_back(v);
+      if (ids.empty()) continue;
+      const ModelD md = make_model(models[m]);
+      for (const JobD& j : make_jobs(md, ids))
+        HIP_TRY(launch_project(j, b.views, b.records, b.n_tiles, b.tile_box, s));
+    }
   }
-  HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, b.counters, P, s));
-  HIP_TRY(launch_batch_status(b.req_rec, n_req, b.offsets, P, b.counters, req_status, s));
-  HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, b.counters, P, b.keys_a, b.vals, s));
-  HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, key_bits_for(bp.X), b.ctl->hist,
-                      b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
-  HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
-  HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
-                           &b.ctl->tile_ctr, req_status, true, s));
+  {
+    StageScope sc(timer, GSR_STAGE_SCAN, s);
+    HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, b.counters, P, s));
+    HIP_TRY(launch_batch_status(b.req_rec, n_req, b.offsets, P, b.counters, req_status, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_DUPLICATE, s);
+    HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, b.counters, P, b.keys_a, b.vals, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_SORT, s);
+    HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, key_bits_for(bp.X), b.ctl->hist,
+                        b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_RANGES, s);
+    HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_BLEND, s);
+    HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
+                             &b.ctl->tile_ctr, req_status, true, s));
+  }
   return GSR_OK;
 }
 

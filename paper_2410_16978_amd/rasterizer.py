@@ -98,18 +98,25 @@ def lib():
     L.gsr_rasterize_forward.restype = C.c_int
     L.gsr_rasterize_forward.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Camera), C.POINTER(ViewState),
                                         C.POINTER(FwdState), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
-                                        C.POINTER(C.c_uint32), C.POINTER(Debug), C.c_void_p]
+                                        C.POINTER(C.c_uint32), C.POINTER(Debug), C.c_void_p, C.c_void_p]
     L.gsr_forward_check.restype = C.c_int
     L.gsr_forward_check.argtypes = [C.POINTER(FwdState), C.POINTER(C.c_uint32), C.c_void_p]
     L.gsr_rasterize_backward.restype = C.c_int
     L.gsr_rasterize_backward.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Camera), C.POINTER(ViewState),
                                          C.POINTER(FwdState), C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
-                                         C.c_size_t, C.POINTER(Grads), C.c_void_p, C.c_void_p, C.c_void_p]
+                                         C.c_size_t, C.POINTER(Grads), C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]
     L.gsr_batch_workspace_size.restype = C.c_size_t
     L.gsr_batch_workspace_size.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Request), C.c_int32, C.c_uint32]
     L.gsr_render_batch.restype = C.c_int
     L.gsr_render_batch.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Request), C.c_int32, C.c_uint32,
-                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gsr_timer_create.restype = C.c_int
+    L.gsr_timer_create.argtypes = [C.POINTER(C.c_void_p)]
+    L.gsr_timer_destroy.restype = None
+    L.gsr_timer_destroy.argtypes = [C.c_void_p]
+    L.gsr_timer_read.restype = C.c_int
+    L.gsr_timer_read.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]
     _lib = L
     return L
 
@@ -195,6 +202,41 @@ def model_struct(model):
     return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS])
 
 
+# ---------------------------------------------------------------- timer
+STAGES = ("project", "scan", "duplicate", "sort", "ranges", "blend", "blend_bwd", "project_bwd")
+
+
+class Timer:
+    """Per-stage HIP-event timer of the library (gsr_timer)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().gsr_timer_create(C.byref(h)), "gsr_timer_create")
+        self.handle = h
+
+    def read(self):
+        """{stage: (total ms, launches)} since the last read (synchronises)."""
+        ms = (C.c_float * len(STAGES))()
+        calls = (C.c_uint32 * len(STAGES))()
+        _check(lib().gsr_timer_read(self.handle, ms, calls), "gsr_timer_read")
+        return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
+
+    def close(self):
+        if self.handle:
+            lib().gsr_timer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _timer(t):
+    return t.handle if t is not None else None
+
+
 # ---------------------------------------------------------------- forward
 @dataclass
 class ForwardState:
@@ -253,7 +295,7 @@ def make_state(n, n_views, width, height, capacity, device="cuda", old=None):
 
 
 def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, debug=False, stream=None,
-                      out=None):
+                      out=None, timer=None):
     """Render len(cams) views of one model (equal resolution).
 
     sync=True: the library reads the pair count once; when the pair buffers
@@ -297,7 +339,7 @@ def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, 
         rc = L.gsr_rasterize_forward(C.byref(m), V, carr, varr, C.byref(fs), _ptr(st.workspace),
                                      st.workspace.numel(), _ptr(rgb), _ptr(alpha),
                                      C.byref(npairs) if sync else None,
-                                     C.byref(dbg_struct) if dbg_struct is not None else None, s)
+                                     C.byref(dbg_struct) if dbg_struct is not None else None, _timer(timer), s)
         if rc == GSR_ENOSPACE and sync:
             st = make_state(n, V, W, H, int(npairs.value * 1.125) + 1024, dev, None)
             continue
@@ -322,7 +364,7 @@ def forward_check(state, stream=None):
 
 # ---------------------------------------------------------------- backward
 def rasterize_backward(model, cams, views, state, dL_drgb=None, dL_dalpha=None, trainable=0xFFFFFFFF,
-                       max_contrib=None, activity=None, grads=None, stream=None):
+                       max_contrib=None, activity=None, grads=None, stream=None, timer=None):
     """Gradients w.r.t. the activated parameters (dict of tensors like model)."""
     L = lib()
     V = len(cams)
@@ -346,7 +388,7 @@ def rasterize_backward(model, cams, views, state, dL_drgb=None, dL_dalpha=None, 
     fs = state.struct()
     rc = L.gsr_rasterize_backward(C.byref(m), V, carr, varr, C.byref(fs), _ptr(dL_drgb), _ptr(dL_dalpha),
                                   int(trainable) & 0xFFFFFFFF, _ptr(state.workspace), state.workspace.numel(),
-                                  C.byref(g), _ptr(max_contrib), _ptr(activity), _stream(stream))
+                                  C.byref(g), _ptr(max_contrib), _ptr(activity), _timer(timer), _stream(stream))
     _check(rc, "gsr_rasterize_backward")
     return grads
 
@@ -369,7 +411,7 @@ def batch_workspace_size(models_struct, reqs_struct, capacity):
                                               int(capacity)))
 
 
-def render_batch(models, requests, capacity, workspace=None, status=None, outputs=None, stream=None):
+def render_batch(models, requests, capacity, workspace=None, status=None, outputs=None, stream=None, timer=None):
     """Render requests [{"model": i, "cams": [cam] or [left, right], "view": vs}]
     over resident models in one pass.  Returns (outputs, status tensor,
     workspace); outputs[q] = (rgb list, alpha list).  Never synchronises."""
@@ -392,6 +434,6 @@ def render_batch(models, requests, capacity, workspace=None, status=None, output
     if status is None or status.numel() < len(requests):
         status = torch.empty(len(requests), dtype=torch.int32, device=dev)
     rc = L.gsr_render_batch(mstructs, len(models), rstructs, len(requests), int(capacity), _ptr(workspace),
-                            workspace.numel(), _ptr(status), _stream(stream))
+                            workspace.numel(), _ptr(status), _timer(timer), _stream(stream))
     _check(rc, "gsr_render_batch")
     return outputs, status, workspace

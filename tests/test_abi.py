@@ -41,9 +41,12 @@ def test_host_only_calls():
     assert rz.workspace_size(-1, 1, 128, 128, 10000) == 0
     assert rz.workspace_size(10, 0, 128, 128, 10000) == 0
     assert rz.workspace_size(10, 1, 128, 128, 1 << 30) == 0
+    t = rz.Timer()  # host object; reading an empty timer needs no device
+    assert all(v == (0.0, 0) for v in t.read().values())
+    t.close()
     # the forward rejects bad arguments before touching the device
     m = rz.Model(-1, 0, None, None, None, None, None, None)
-    rc = L.gsr_rasterize_forward(C.byref(m), 1, None, None, None, None, 0, None, None, None, None, None)
+    rc = L.gsr_rasterize_forward(C.byref(m), 1, None, None, None, None, 0, None, None, None, None, None, None)
     assert rc == rz.GSR_EINVAL
 
 
