@@ -1,0 +1,95 @@
+"""GPU tests of gsr_render_batch: a request's image is bit-identical alone, in
+a mixed batch and through the single-call forward, and matches the oracle;
+pair-capacity overflow fails a suffix of requests cleanly."""
+import numpy as np
+import pytest
+
+from paper_2410_16978_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_16978_amd import rasterizer as rz
+    a = scenes.shell_scene(600, 5, 3, seed=1, log_scale_mu=-3.4, log_scale_sigma=0.4, palette=True)
+    b = scenes.shell_scene(300, 5, 1, seed=2, log_scale_mu=-3.0, log_scale_sigma=0.4, palette=True)
+    rng = np.random.default_rng(5)
+    reqs = []
+    for q in range(7):
+        m = int(rng.integers(0, 2))
+        d = scenes.random_direction(rng)
+        kind = q % 3
+        if kind == 0:
+            cams = [scenes.orbit_camera(d, 48, 40)]
+        elif kind == 1:
+            cams = [scenes.orbit_camera(d, 80, 64)]
+        else:
+            cams = scenes.stereo_cameras(d, 56, 72)
+        reqs.append({"model": m, "cams": cams, "view": scenes.random_view_state(rng, 5, bg=tuple(rng.uniform(0, 1, 3)))})
+    models = [rz.to_device(a), rz.to_device(b)]
+    return rz, [a, b], models, reqs
+
+
+def _render(rz, models, reqs, capacity=200_000):
+    import torch
+    outs, status, ws = rz.render_batch(models, reqs, capacity)
+    torch.cuda.synchronize()
+    return [([r.cpu().numpy() for r in o[0]], [a.cpu().numpy() for a in o[1]]) for o in outs], status.cpu().numpy()
+
+
+def test_alone_equals_in_mix(setup):
+    rz, _, models, reqs = setup
+    mixed, st = _render(rz, models, reqs)
+    assert np.all(st == 0)
+    for q, rq in enumerate(reqs):
+        alone, st1 = _render(rz, models, [rq])
+        assert st1[0] == 0
+        for e in range(len(rq["cams"])):
+            np.testing.assert_array_equal(mixed[q][0][e], alone[0][0][e])
+            np.testing.assert_array_equal(mixed[q][1][e], alone[0][1][e])
+
+
+def test_batch_equals_single_forward_and_oracle(setup, orc):
+    rz, scn, models, reqs = setup
+    mixed, st = _render(rz, models, reqs)
+    for q, rq in enumerate(reqs):
+        rgb, alpha, _ = rz.rasterize_forward(models[rq["model"]], rq["cams"], [rq["view"]] * len(rq["cams"]))
+        for e in range(len(rq["cams"])):
+            np.testing.assert_array_equal(mixed[q][0][e], rgb[e].cpu().numpy())
+        ref = orc.render(scn[rq["model"]], rq["cams"], [rq["view"]] * len(rq["cams"]))
+        for e in range(len(rq["cams"])):
+            ok = ref["margin"][e] >= 1
+            err = np.abs(mixed[q][0][e] - ref["rgb"][e]).max(axis=0)[ok].max(initial=0)
+            assert err <= 1e-4, (q, e, err)
+            assert np.abs(mixed[q][1][e] - ref["alpha"][e])[ok].max(initial=0) <= 1e-4
+
+
+def test_capacity_overflow_fails_a_suffix(setup):
+    rz, _, models, reqs = setup
+    import torch
+    # pair counts of each request alone
+    counts = []
+    for rq in reqs:
+        _, _, st = rz.rasterize_forward(models[rq["model"]], rq["cams"], [rq["view"]] * len(rq["cams"]))
+        counts.append(st.n_pairs)
+    cap = sum(counts[:3]) + counts[3] // 2  # the first three fit, the fourth does not
+    outs, status, ws = rz.render_batch(models, reqs, cap)
+    torch.cuda.synchronize()
+    s = status.cpu().numpy()
+    np.testing.assert_array_equal(s, [0, 0, 0, -2, -2, -2, -2])
+    full, _ = _render(rz, models, reqs)
+    for q in range(3):
+        for e in range(len(reqs[q]["cams"])):
+            np.testing.assert_array_equal(outs[q][0][e].cpu().numpy(), full[q][0][e])
+
+
+def test_batch_workspace_and_argument_checks(setup):
+    rz, _, models, reqs = setup
+    bad = dict(reqs[0])
+    bad["model"] = 5
+    with pytest.raises(rz.GsrError):
+        rz.render_batch(models, [bad], 1000)
