@@ -105,28 +105,49 @@ typedef struct {
 
 /* Buffers that carry a forward pass to its backward (device, caller-owned;
  * host struct).  R = n_views * model.n records, P = pair_capacity,
- * X = total tiles = n_views * ceil(W/16) * ceil(H/16), Q = n_views * H * W.
- *   records   float[R][12]  per (view, Gaussian): u, v, conic a, b, c,
- *                           opacity, r, g, b, depth, clamp bits (as uint32;
- *                           bit c = colour channel c clamped at 0), tile count
- *                           (as uint32; 0 = culled).  Record r = v * n + i.
- *   pair_vals uint32[2][P]  sorted record ids; which half holds the result is
- *                           recorded on the device in *sort_sel
- *   sort_sel  uint32[1]
- *   ranges    uint32[X][2]  [start, end) of each tile's pairs
- *   final_T   float[Q]      transmittance left behind the last blended splat
- *   last      uint32[Q]     1 + index of the last blended pair, 0 if none
- *   counters  uint32[4]     device: pairs K, overflow flag, error flag, spare */
+ * X = total tiles = n_views * ceil(W/16) * ceil(H/16), Q = n_views * H * W,
+ * B = batch_capacity >= P / 256 + X (see gsr_batch_capacity).
+ *   records     float[R][12]  per (view, Gaussian): u, v, conic a, b, c,
+ *                             opacity, r, g, b, depth, clamp bits (as uint32;
+ *                             bit c = colour channel c clamped at 0), tile
+ *                             count (as uint32; 0 = culled).  Record
+ *                             r = v * n + i.
+ *   offsets     uint32[R+1]   first pair (emission order) of each record;
+ *                             offsets[R] = pair count
+ *   pair_vals   uint32[2][P]  sorted record ids; which half holds the result
+ *                             is recorded on the device in *sort_sel
+ *   sort_sel    uint32[1]
+ *   pair_pos    uint32[P]     sorted position of each pair in emission order
+ *   ranges      uint32[X][2]  [start, end) of each tile's pairs
+ *   pixel_state float[Q][4]   transmittance left behind the last blended
+ *                             splat, then the composited colour before the
+ *                             background (premultiplied r, g, b)
+ *   last        uint32[Q]     1 + index of the last blended pair, 0 if none
+ *   checkpoints float[B][256][4]  per 256-pair batch of a tile and pixel:
+ *                             transmittance before the batch, then the
+ *                             colour (r, g, b) the batch adds
+ *   batch_map   uint32[X + 1 + B]  first batch of each tile (exclusive
+ *                             scan, X + 1 entries), then the tile of each batch
+ *   counters    uint32[4]     device: pairs K, overflow flag, error flag,
+ *                             batches */
 typedef struct {
   float* records;
+  uint32_t* offsets;
   uint32_t* pair_vals;
   uint32_t* sort_sel;
+  uint32_t* pair_pos;
   uint32_t* ranges;
-  float* final_T;
+  float* pixel_state;
   uint32_t* last;
+  float* checkpoints;
+  uint32_t* batch_map;
   uint32_t* counters;
   uint32_t pair_capacity;
+  uint32_t batch_capacity;
 } gsr_fwd_state;
+
+/* Batch capacity a state needs for a pair capacity and a tile count. */
+uint32_t gsr_batch_capacity(uint32_t pair_capacity, uint32_t total_tiles);
 
 /* Optional copies of intermediate arrays for inspection (device, may all be
  * NULL; host struct).  Filled by gsr_rasterize_forward when non-NULL.  The
@@ -136,7 +157,7 @@ typedef struct {
   uint32_t* tile_box;   /* [R][4]: global id of the box's first tile, width | height << 16
                            (in tiles), depth bits, tiles per image row */
   uint64_t* keys_emit;  /* [P] keys in emission order (record order, tiles row-major) */
-  uint32_t* vals_emit;  /* [P] */
+  uint32_t* vals_emit;  /* [P] record of each pair in emission order */
   uint64_t* keys_sorted;/* [P] */
 } gsr_debug;
 
@@ -205,7 +226,9 @@ gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host,
  *   an accumulation window).
  * activity float[n] (optional): accumulated (+=) with
  *   2 |dL/dmean| + 0.1 |dL/dsh| + 0.1 |dL/dlog scale| (Sec. 3.2.2).
- * ws: scratch of at least gsr_workspace_size(...) bytes. */
+ * ws: scratch of at least gsr_workspace_size(...) bytes.
+ * The backward uses no atomics: per-pair partial gradients are summed in a
+ * fixed order, so repeated calls give bitwise identical results. */
 typedef struct {
   float *g_mean, *g_scale, *g_quat, *g_opacity, *g_sh;
 } gsr_grads;

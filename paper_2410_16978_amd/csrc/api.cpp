@@ -46,15 +46,16 @@ struct PipeBufs {
   uint4* tile_box = nullptr;
   uint64_t* keys_a = nullptr;
   uint64_t* keys_b = nullptr;
+  uint32_t* rec_of = nullptr;
   SortCtl* ctl = nullptr;
   SortPlan* plan = nullptr;
   uint32_t* status = nullptr;
-  float* g2d = nullptr;
+  float* g_pair = nullptr;
   // batch only (the single-call path keeps these in the caller's state)
   float* records = nullptr;
   uint32_t* vals = nullptr;
   uint32_t* ranges = nullptr;
-  float* final_T = nullptr;
+  float* pix = nullptr;
   uint32_t* last = nullptr;
   uint32_t* counters = nullptr;
   uint32_t* sel = nullptr;
@@ -65,20 +66,21 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.views = c.take<ViewD>(std::max<size_t>(n_views, 1));
   b.req_rec = c.take<uint32_t>(n_req + 1);
   b.n_tiles = c.take<uint32_t>(std::max<size_t>(R, 1));
-  b.offsets = c.take<uint32_t>(R + 1);
   b.partials = c.take<uint32_t>(div_up((uint32_t)R + 1, (uint32_t)kScanTile) + 1);
   b.tile_box = c.take<uint4>(std::max<size_t>(R, 1));
   b.keys_a = c.take<uint64_t>(std::max<size_t>(P, 1));
   b.keys_b = c.take<uint64_t>(std::max<size_t>(P, 1));
+  b.rec_of = c.take<uint32_t>(std::max<size_t>(P, 1));
   b.ctl = c.take<SortCtl>(1);
   b.plan = c.take<SortPlan>(1);
   b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
-  if (backward) b.g2d = c.take<float>(9 * std::max<size_t>(R, 1));
+  if (backward) b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
   if (batch) {
+    b.offsets = c.take<uint32_t>(R + 1);
     b.records = c.take<float>(kRecordFloats * std::max<size_t>(R, 1));
     b.vals = c.take<uint32_t>(2 * std::max<size_t>(P, 1));
     b.ranges = c.take<uint32_t>(2 * std::max<size_t>(X, 1));
-    b.final_T = c.take<float>(std::max<size_t>(Q, 1));
+    b.pix = c.take<float>(4 * std::max<size_t>(Q, 1));
     b.last = c.take<uint32_t>(std::max<size_t>(Q, 1));
     b.counters = c.take<uint32_t>(4);
     b.sel = c.take<uint32_t>(1);
@@ -197,6 +199,12 @@ struct StageScope {
   }
 };
 
+bool state_ok(const gsr_fwd_state* st) {
+  return st && st->records && st->offsets && st->pair_vals && st->sort_sel && st->pair_pos && st->ranges &&
+         st->pixel_state && st->last && st->checkpoints && st->batch_map && st->counters &&
+         st->pair_capacity < (1u << 30);
+}
+
 bool single_view_args_ok(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
                          const gsr_view_state* views) {
   if (!model_ok(model) || n_views <= 0 || !cams || !views) return false;
@@ -259,6 +267,10 @@ const char* gsr_status_string(gsr_status s) {
   return "unknown status";
 }
 
+uint32_t gsr_batch_capacity(uint32_t pair_capacity, uint32_t total_tiles) {
+  return pair_capacity / (uint32_t)kBatch + total_tiles + 1;
+}
+
 size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t height, uint32_t pair_capacity) {
   if (n < 0 || n_views <= 0 || width <= 0 || height <= 0 || pair_capacity >= (1u << 30)) return 0;
   Carver c(nullptr);
@@ -271,9 +283,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
                                  float* rgb, float* alpha, uint32_t* n_pairs_host, const gsr_debug* debug,
                                  gsr_timer* timer, void* stream) {
   if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !rgb || !alpha) return GSR_EINVAL;
-  if (!state->records || !state->pair_vals || !state->sort_sel || !state->ranges || !state->final_T ||
-      !state->last || !state->counters || state->pair_capacity >= (1u << 30))
-    return GSR_EINVAL;
+  if (!state_ok(state)) return GSR_EINVAL;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const int W = cams[0].width, H = cams[0].height;
   const uint32_t n = (uint32_t)model->n;
@@ -281,7 +291,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   const uint32_t P = state->pair_capacity;
   const uint32_t tiles_per_view = tiles_of(cams[0]);
   const uint64_t X = (uint64_t)tiles_per_view * n_views;
-  if (X >= (1ull << 32)) return GSR_EINVAL;
+  if (X >= (1ull << 31) || state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
   const size_t plane = (size_t)W * H;
   Carver c(ws);
   PipeBufs b;
@@ -295,7 +305,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     d.rec_off = (uint32_t)v * n;
     d.rgb = rgb + 3 * plane * v;
     d.alpha = alpha + plane * v;
-    d.final_T = state->final_T + plane * v;
+    d.pix = state->pixel_state + 4 * plane * v;
     d.last = state->last + plane * v;
     hv[v] = d;
     ids[v] = v;
@@ -312,7 +322,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   }
   {
     StageScope sc(timer, GSR_STAGE_SCAN, s);
-    HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, state->counters, P, s));
+    HIP_TRY(launch_scan(b.n_tiles, state->offsets, b.partials, R, state->counters, P, s));
   }
   if (n_pairs_host) {
     uint32_t K = 0;
@@ -323,26 +333,34 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   }
   {
     StageScope sc(timer, GSR_STAGE_DUPLICATE, s);
-    HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, state->counters, P, b.keys_a, state->pair_vals, s));
+    HIP_TRY(launch_duplicate(b.n_tiles, state->offsets, b.tile_box, R, state->counters, P, b.keys_a,
+                             state->pair_vals, b.rec_of, s));
   }
   if (debug && (debug->keys_emit || debug->vals_emit)) {
     if (debug->keys_emit) HIP_TRY(hipMemcpyAsync(debug->keys_emit, b.keys_a, 8ull * P, hipMemcpyDeviceToDevice, s));
-    if (debug->vals_emit) HIP_TRY(hipMemcpyAsync(debug->vals_emit, state->pair_vals, 4ull * P, hipMemcpyDeviceToDevice, s));
+    if (debug->vals_emit) HIP_TRY(hipMemcpyAsync(debug->vals_emit, b.rec_of, 4ull * P, hipMemcpyDeviceToDevice, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
                         key_bits_for(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, state->sort_sel,
                         state->counters + kCntError, s));
+    HIP_TRY(launch_finalize_pairs(state->pair_vals, state->pair_vals + P, state->sort_sel, state->counters, P,
+                                  b.rec_of, state->pair_pos, s));
   }
+  uint32_t* batch_off = state->batch_map;
+  uint32_t* batch_tile = state->batch_map + X + 1;
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
     HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
+    HIP_TRY(launch_tile_batches(state->ranges, (uint32_t)X, state->batch_capacity, batch_off, batch_tile,
+                                state->counters, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);
     HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals, state->sort_sel, P,
-                             state->ranges, &b.ctl->tile_ctr, nullptr, false, s));
+                             state->ranges, &b.ctl->tile_ctr, nullptr, reinterpret_cast<float4*>(state->checkpoints),
+                             batch_off, state->batch_capacity, false, s));
   }
   if (debug) {
     if (debug->n_tiles) HIP_TRY(hipMemcpyAsync(debug->n_tiles, b.n_tiles, 4ull * R, hipMemcpyDeviceToDevice, s));
@@ -379,8 +397,7 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
   if (n_views > kMaxJobViews) return GSR_EINVAL;
   if (model->n > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_sh))
     return GSR_EINVAL;
-  if (!state->records || !state->pair_vals || !state->sort_sel || !state->ranges || !state->final_T || !state->last)
-    return GSR_EINVAL;
+  if (!state_ok(state)) return GSR_EINVAL;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const int W = cams[0].width, H = cams[0].height;
   const uint32_t n = (uint32_t)model->n;
@@ -398,26 +415,28 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
     ViewD d = make_view(cams[v], views[v]);
     d.tile_off = (uint32_t)v * tiles_per_view;
     d.rec_off = (uint32_t)v * n;
-    d.final_T = state->final_T + plane * v;
+    d.pix = state->pixel_state + 4 * plane * v;
     d.last = state->last + plane * v;
     hv[v] = d;
     ids[v] = v;
   }
   if (n == 0) return GSR_OK;
+  if (state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
   HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.g2d), 9ull * R, s));
-  // max_contrib is indexed by Gaussian: records of view v start at v * n
   {
     StageScope sc(timer, GSR_STAGE_BLEND_BWD, s);
-    HIP_TRY(launch_blend_bwd(b.views, n_views, (uint32_t)X, state->records, state->pair_vals, state->sort_sel, P,
-                             state->ranges, dL_drgb, dL_dalpha, b.g2d, R, max_contrib, s));
+    HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
+                             state->ranges, reinterpret_cast<const float4*>(state->checkpoints), state->batch_map,
+                             state->batch_map + X + 1, state->batch_capacity, state->counters, dL_drgb, dL_dalpha,
+                             b.g_pair, s));
   }
   const ModelD md = make_model(*model);
   {
     StageScope sc(timer, GSR_STAGE_PROJECT_BWD, s);
     for (const JobD& j : make_jobs(md, ids))
-      HIP_TRY(launch_project_bwd(j, b.views, state->records, b.g2d, R, trainable_layers, grads->g_mean,
-                                 grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_sh, activity, s));
+      HIP_TRY(launch_project_bwd(j, b.views, state->records, state->offsets, state->pair_pos, b.g_pair, P,
+                                 state->counters, trainable_layers, grads->g_mean, grads->g_scale, grads->g_quat,
+                                 grads->g_opacity, grads->g_sh, max_contrib, activity, s));
   }
   return GSR_OK;
 }
@@ -486,7 +505,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   // per-view transmittance / last index scratch
   size_t q_off = 0;
   for (ViewD& d : bp.views) {
-    d.final_T = b.final_T + q_off;
+    d.pix = b.pix + 4 * q_off;
     d.last = b.last + q_off;
     q_off += (size_t)d.W * d.H;
   }
@@ -514,12 +533,13 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   {
     StageScope sc(timer, GSR_STAGE_DUPLICATE, s);
-    HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, b.counters, P, b.keys_a, b.vals, s));
+    HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, b.counters, P, b.keys_a, b.vals, b.rec_of, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, key_bits_for(bp.X), b.ctl->hist,
                         b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
+    HIP_TRY(launch_finalize_pairs(b.vals, b.vals + P, b.sel, b.counters, P, b.rec_of, nullptr, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
@@ -528,7 +548,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);
     HIP_TRY(launch_blend_fwd(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
-                             &b.ctl->tile_ctr, req_status, true, s));
+                             &b.ctl->tile_ctr, req_status, nullptr, nullptr, 0, true, s));
   }
   return GSR_OK;
 }

@@ -14,6 +14,7 @@ constexpr int kMaxSortPasses = 8;     // 64-bit keys, 8-bit digits
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;        // per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kBatch = 256;          // pairs per blend batch (one per thread of a tile block)
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -29,6 +30,7 @@ constexpr float kQMax = 11.09375f;    // extent: box of {q <= kQMax}; > 2 ln 255
 constexpr int kCntPairs = 0;
 constexpr int kCntOverflow = 1;
 constexpr int kCntError = 2;
+constexpr int kCntBatches = 3;
 
 struct ClipD {
   float n[3];
@@ -51,7 +53,7 @@ struct ViewD {
   float bg[3];
   float* rgb;          // [3][H][W]
   float* alpha;        // [H][W]
-  float* final_T;      // [H][W]
+  float* pix;          // [H][W][4]: final transmittance, colour before the background
   uint32_t* last;      // [H][W]
 };
 
@@ -92,7 +94,11 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t* partials, ui
                        uint32_t* counters, uint32_t pair_capacity, hipStream_t s);
 hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
-                            uint64_t* keys, uint32_t* vals, hipStream_t s);
+                            uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s);
+hipError_t launch_finalize_pairs(uint32_t* vals_a, uint32_t* vals_b, const uint32_t* sel, const uint32_t* counters,
+                                 uint32_t pair_capacity, const uint32_t* rec_of, uint32_t* pos, hipStream_t s);
+hipError_t launch_tile_batches(const uint32_t* ranges, uint32_t n_tiles, uint32_t batch_capacity,
+                               uint32_t* batch_off, uint32_t* batch_tile, uint32_t* counters, hipStream_t s);
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                        const uint32_t* counters, uint32_t pair_capacity, int key_bits, uint32_t* hist,
                        uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
@@ -100,19 +106,21 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
 hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,
                          uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles, uint32_t* ranges,
                          hipStream_t s);
-hipError_t launch_blend_fwd(const ViewD* views_dev, int n_views, uint32_t total_tiles,
-                            const float* records, uint32_t n_rec, const uint32_t* pair_vals,
-                            const uint32_t* sel, uint32_t pair_capacity, const uint32_t* ranges,
-                            uint32_t* tile_ctr, const int32_t* req_status, bool persistent, hipStream_t s);
-hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, uint32_t total_tiles,
-                            const float* records, const uint32_t* pair_vals, const uint32_t* sel,
-                            uint32_t pair_capacity, const uint32_t* ranges, const float* dL_drgb,
-                            const float* dL_dalpha, float* g2d, uint32_t n_rec, float* max_contrib,
+hipError_t launch_blend_fwd(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
+                            uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
+                            const uint32_t* ranges, uint32_t* tile_ctr, const int32_t* req_status,
+                            float4* ckpt, const uint32_t* batch_off, uint32_t batch_cap, bool persistent,
                             hipStream_t s);
+hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,
+                            const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
+                            const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
+                            uint32_t batch_cap, const uint32_t* counters, const float* dL_drgb,
+                            const float* dL_dalpha, float* g_pair, hipStream_t s);
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
-                              const float* g2d, uint32_t n_rec, uint32_t trainable, float* g_mean,
-                              float* g_scale, float* g_quat, float* g_opacity, float* g_sh,
-                              float* activity, hipStream_t s);
+                              const uint32_t* offsets, const uint32_t* pos, const float* g_pair,
+                              uint32_t pair_capacity, const uint32_t* counters, uint32_t trainable,
+                              float* g_mean, float* g_scale, float* g_quat, float* g_opacity, float* g_sh,
+                              float* max_contrib, float* activity, hipStream_t s);
 hipError_t launch_batch_status(const uint32_t* req_rec, int n_req, const uint32_t* offsets,
                                uint32_t pair_capacity, uint32_t* counters, int32_t* req_status,
                                hipStream_t s);

@@ -118,11 +118,13 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t* partials, ui
 // ---------------------------------------------------------------- duplicate
 // One thread per record: its tiles row-major at offsets[r] + j.  Pairs at or
 // beyond min(capacity, counters[pairs]) are dropped (the overflow flag or the
-// batch status already records it).
+// batch status already records it).  The sort carries each pair's emission
+// index as its value; rec_of[e] keeps the record of emission index e.
 __global__ void __launch_bounds__(256)
 k_duplicate(const uint32_t* __restrict__ n_tiles, const uint32_t* __restrict__ offsets,
             const uint4* __restrict__ tile_box, uint32_t n_rec, const uint32_t* __restrict__ counters,
-            uint32_t pair_capacity, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+            uint32_t pair_capacity, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+            uint32_t* __restrict__ rec_of) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rec) return;
   pair_capacity = min(pair_capacity, counters[kCntPairs]);
@@ -138,7 +140,8 @@ k_duplicate(const uint32_t* __restrict__ n_tiles, const uint32_t* __restrict__ o
     for (uint32_t dx = 0; dx < w; ++dx) {
       if (off >= pair_capacity) return;
       keys[off] = ((uint64_t)(row + dx) << 32) | depth;
-      vals[off] = r;
+      vals[off] = off;
+      rec_of[off] = r;
       ++off;
     }
   }
@@ -146,10 +149,84 @@ k_duplicate(const uint32_t* __restrict__ n_tiles, const uint32_t* __restrict__ o
 
 hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
-                            uint64_t* keys, uint32_t* vals, hipStream_t s) {
+                            uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s) {
   if (n_rec == 0) return hipSuccess;
   hipLaunchKernelGGL(k_duplicate, dim3(div_up(n_rec, 256u)), dim3(256), 0, s, n_tiles, offsets, tile_box,
-                     n_rec, counters, pair_capacity, keys, vals);
+                     n_rec, counters, pair_capacity, keys, vals, rec_of);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- finalize
+// After the sort: the sorted emission indices become record ids, and
+// pos[e] records where emission index e landed.
+__global__ void __launch_bounds__(256)
+k_finalize_pairs(uint32_t* __restrict__ vals_a, uint32_t* __restrict__ vals_b, const uint32_t* __restrict__ sel,
+                 const uint32_t* __restrict__ counters, uint32_t pair_capacity, const uint32_t* __restrict__ rec_of,
+                 uint32_t* __restrict__ pos) {
+  const uint32_t K = min(counters[kCntPairs], pair_capacity);
+  uint32_t* vals = (*sel == 0) ? vals_a : vals_b;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+    const uint32_t e = vals[k];
+    if (e >= K) continue;  // cannot happen for a consistent sort; never index out of range
+    vals[k] = rec_of[e];
+    if (pos) pos[e] = k;
+  }
+}
+
+hipError_t launch_finalize_pairs(uint32_t* vals_a, uint32_t* vals_b, const uint32_t* sel, const uint32_t* counters,
+                                 uint32_t pair_capacity, const uint32_t* rec_of, uint32_t* pos, hipStream_t s) {
+  if (pair_capacity == 0) return hipSuccess;
+  uint32_t grid = div_up(pair_capacity, 256u);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_finalize_pairs, dim3(grid), dim3(256), 0, s, vals_a, vals_b, sel, counters, pair_capacity,
+                     rec_of, pos);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- tile batches
+// Each tile's pair list is cut into batches of kBatch pairs.  Single block:
+// first batch of every tile (exclusive scan, X + 1 entries), the tile of every
+// batch, and the batch count in counters[kCntBatches].
+__global__ void __launch_bounds__(1024)
+k_tile_batches(const uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t batch_capacity,
+               uint32_t* __restrict__ batch_off, uint32_t* __restrict__ batch_tile, uint32_t* __restrict__ counters) {
+  __shared__ uint32_t lds[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (uint32_t base = 0; base < n_tiles; base += 1024) {
+    const uint32_t t = base + threadIdx.x;
+    const uint32_t nb = t < n_tiles ? div_up(ranges[2 * t + 1] - ranges[2 * t], (uint32_t)kBatch) : 0u;
+    const uint32_t inc = wave_inclusive_scan(nb);
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    uint32_t off = carry, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wave) off += lds[w];
+      tot += lds[w];
+    }
+    const uint32_t first = off + inc - nb;
+    if (t < n_tiles) {
+      batch_off[t] = first;
+      for (uint32_t c = 0; c < nb; ++c)
+        if (first + c < batch_capacity) batch_tile[first + c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    batch_off[n_tiles] = carry;
+    counters[kCntBatches] = min(carry, batch_capacity);
+    if (carry > batch_capacity) atomicOr(&counters[kCntError], 8u);
+  }
+}
+
+hipError_t launch_tile_batches(const uint32_t* ranges, uint32_t n_tiles, uint32_t batch_capacity,
+                               uint32_t* batch_off, uint32_t* batch_tile, uint32_t* counters, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_batches, dim3(1), dim3(1024), 0, s, ranges, n_tiles, batch_capacity, batch_off,
+                     batch_tile, counters);
   return hipGetLastError();
 }
 

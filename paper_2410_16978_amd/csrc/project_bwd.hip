@@ -13,9 +13,11 @@ namespace gsr {
 template <int D>
 __global__ void __launch_bounds__(256)
 k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict__ records,
-              const float* __restrict__ g2d, uint32_t n_rec, uint32_t trainable, float* __restrict__ g_mean,
-              float* __restrict__ g_scale, float* __restrict__ g_quat, float* __restrict__ g_opacity,
-              float* __restrict__ g_sh, float* __restrict__ activity) {
+              const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pos,
+              const float* __restrict__ g_pair, uint32_t cap, const uint32_t* __restrict__ counters,
+              uint32_t trainable, float* __restrict__ g_mean, float* __restrict__ g_scale,
+              float* __restrict__ g_quat, float* __restrict__ g_opacity, float* __restrict__ g_sh,
+              float* __restrict__ max_contrib, float* __restrict__ activity) {
   constexpr int NC = (D + 1) * (D + 1);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const ModelD& m = job.m;
@@ -23,11 +25,36 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
   const int n = m.n;
   const uint32_t layer = m.layer[i];
   const bool train = layer < 32u && ((trainable >> layer) & 1u);
+  const uint32_t K = min(counters[kCntPairs], cap);
+  // screen-space gradient of each record: sum of its pairs' partials, in
+  // emission order (fixed), and the largest alpha * T it reached
+  float wmax = 0.f;
+  auto record_grad = [&](uint32_t r, float* g) {
+    for (int c = 0; c < 9; ++c) g[c] = 0.f;
+    const uint32_t e1 = min(offsets[r + 1], K);
+    for (uint32_t e = offsets[r]; e < e1; ++e) {
+      const uint32_t k = pos[e];
+      if (k >= K) continue;
+      const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)k * 12);
+      const float4 x0 = src[0], x1 = src[1], x2 = src[2];
+      g[0] += x0.x; g[1] += x0.y; g[2] += x0.z; g[3] += x0.w;
+      g[4] += x1.x; g[5] += x1.y; g[6] += x1.z; g[7] += x1.w;
+      g[8] += x2.x;
+      wmax = fmaxf(wmax, x2.y);
+    }
+  };
   float gm[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
   float gsh[NC * 3];
 #pragma unroll
   for (int k = 0; k < NC * 3; ++k) gsh[k] = 0.f;
 
+  if (!train && max_contrib) {
+    float g[9];
+    for (int jv = 0; jv < job.n_views; ++jv) {
+      const uint32_t r = views[job.view[jv]].rec_off + (uint32_t)i;
+      if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) != 0u) record_grad(r, g);
+    }
+  }
   if (train) {
     const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
     const float s[3] = {m.scale[i], m.scale[n + i], m.scale[2 * n + i]};
@@ -66,8 +93,7 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
       if (__float_as_uint(rec[11]) == 0u) continue;  // culled in this view
       const uint32_t clamp_bits = __float_as_uint(rec[10]);
       float g[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) g[c] = g2d[(size_t)c * n_rec + r];
+      record_grad(r, g);
       go += g[5];
       const float* W = V.R;
       const float tx = W[0] * mx + W[1] * my + W[2] * mz + V.t[0];
@@ -244,22 +270,29 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
   g_opacity[i] = go;
 #pragma unroll
   for (int k = 0; k < NC * 3; ++k) g_sh[(size_t)k * n + i] = gsh[k];
+  if (max_contrib) max_contrib[i] = fmaxf(max_contrib[i], wmax);
 }
 
-hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records, const float* g2d,
-                              uint32_t n_rec, uint32_t trainable, float* g_mean, float* g_scale, float* g_quat,
-                              float* g_opacity, float* g_sh, float* activity, hipStream_t s) {
+hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
+                              const uint32_t* offsets, const uint32_t* pos, const float* g_pair,
+                              uint32_t pair_capacity, const uint32_t* counters, uint32_t trainable,
+                              float* g_mean, float* g_scale, float* g_quat, float* g_opacity, float* g_sh,
+                              float* max_contrib, float* activity, hipStream_t s) {
   if (job.m.n <= 0) return hipSuccess;
   const dim3 grid(div_up((uint32_t)job.m.n, 256u)), block(256);
   switch (job.m.D) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, s, job, views_dev, records, g2d, n_rec, trainable,
-                               g_mean, g_scale, g_quat, g_opacity, g_sh, activity); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, s, job, views_dev, records, g2d, n_rec, trainable,
-                               g_mean, g_scale, g_quat, g_opacity, g_sh, activity); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, s, job, views_dev, records, g2d, n_rec, trainable,
-                               g_mean, g_scale, g_quat, g_opacity, g_sh, activity); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, s, job, views_dev, records, g2d, n_rec, trainable,
-                                g_mean, g_scale, g_quat, g_opacity, g_sh, activity); break;
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
+                               pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
+                               max_contrib, activity); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
+                               pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
+                               max_contrib, activity); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
+                               pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
+                               max_contrib, activity); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
+                                pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
+                                max_contrib, activity); break;
   }
   return hipGetLastError();
 }

@@ -62,9 +62,11 @@ class Model(C.Structure):
 
 
 class FwdState(C.Structure):
-    _fields_ = [("records", C.c_void_p), ("pair_vals", C.c_void_p), ("sort_sel", C.c_void_p),
-                ("ranges", C.c_void_p), ("final_T", C.c_void_p), ("last", C.c_void_p),
-                ("counters", C.c_void_p), ("pair_capacity", C.c_uint32)]
+    _fields_ = [("records", C.c_void_p), ("offsets", C.c_void_p), ("pair_vals", C.c_void_p),
+                ("sort_sel", C.c_void_p), ("pair_pos", C.c_void_p), ("ranges", C.c_void_p),
+                ("pixel_state", C.c_void_p), ("last", C.c_void_p), ("checkpoints", C.c_void_p),
+                ("batch_map", C.c_void_p), ("counters", C.c_void_p), ("pair_capacity", C.c_uint32),
+                ("batch_capacity", C.c_uint32)]
 
 
 class Debug(C.Structure):
@@ -93,6 +95,8 @@ def lib():
     L = C.CDLL(LIB_PATH)
     L.gsr_status_string.restype = C.c_char_p
     L.gsr_status_string.argtypes = [C.c_int]
+    L.gsr_batch_capacity.restype = C.c_uint32
+    L.gsr_batch_capacity.argtypes = [C.c_uint32, C.c_uint32]
     L.gsr_workspace_size.restype = C.c_size_t
     L.gsr_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32]
     L.gsr_rasterize_forward.restype = C.c_int
@@ -242,23 +246,34 @@ def _timer(t):
 class ForwardState:
     """Device buffers carrying a forward to its backward (see gsr_fwd_state)."""
     records: torch.Tensor
+    offsets: torch.Tensor
     pair_vals: torch.Tensor
     sort_sel: torch.Tensor
+    pair_pos: torch.Tensor
     ranges: torch.Tensor
-    final_T: torch.Tensor
+    pixel_state: torch.Tensor
     last: torch.Tensor
+    checkpoints: torch.Tensor
+    batch_map: torch.Tensor
     counters: torch.Tensor
     capacity: int
+    batch_capacity: int
     workspace: torch.Tensor
     n_views: int
     width: int
     height: int
     n: int
+    n_pairs: int = None
+
+    @property
+    def final_T(self):
+        return self.pixel_state.view(-1, 4)[:, 0]
 
     def struct(self):
-        return FwdState(self.records.data_ptr(), self.pair_vals.data_ptr(), self.sort_sel.data_ptr(),
-                        self.ranges.data_ptr(), self.final_T.data_ptr(), self.last.data_ptr(),
-                        self.counters.data_ptr(), self.capacity)
+        return FwdState(self.records.data_ptr(), self.offsets.data_ptr(), self.pair_vals.data_ptr(),
+                        self.sort_sel.data_ptr(), self.pair_pos.data_ptr(), self.ranges.data_ptr(),
+                        self.pixel_state.data_ptr(), self.last.data_ptr(), self.checkpoints.data_ptr(),
+                        self.batch_map.data_ptr(), self.counters.data_ptr(), self.capacity, self.batch_capacity)
 
 
 def workspace_size(n, n_views, width, height, pair_capacity):
@@ -281,16 +296,21 @@ def make_state(n, n_views, width, height, capacity, device="cuda", old=None):
     ws = workspace_size(n, n_views, width, height, capacity)
     if ws == 0:
         raise GsrError(GSR_EINVAL, "workspace_size")
+    B = int(lib().gsr_batch_capacity(capacity, X))
     kw = dict(device=device)
     return ForwardState(
         records=torch.empty(max(R, 1) * RECORD_FLOATS, dtype=torch.float32, **kw),
+        offsets=torch.empty(R + 1, dtype=torch.int32, **kw),
         pair_vals=torch.empty(2 * capacity, dtype=torch.int32, **kw),
         sort_sel=torch.zeros(1, dtype=torch.int32, **kw),
+        pair_pos=torch.empty(capacity, dtype=torch.int32, **kw),
         ranges=torch.empty(2 * max(X, 1), dtype=torch.int32, **kw),
-        final_T=torch.empty(max(Q, 1), dtype=torch.float32, **kw),
+        pixel_state=torch.empty(4 * max(Q, 1), dtype=torch.float32, **kw),
         last=torch.empty(max(Q, 1), dtype=torch.int32, **kw),
+        checkpoints=torch.empty(B * 256 * 4, dtype=torch.float32, **kw),
+        batch_map=torch.empty(X + 1 + B, dtype=torch.int32, **kw),
         counters=torch.zeros(4, dtype=torch.int32, **kw),
-        capacity=capacity, workspace=torch.empty(ws, dtype=torch.uint8, **kw),
+        capacity=capacity, batch_capacity=B, workspace=torch.empty(ws, dtype=torch.uint8, **kw),
         n_views=n_views, width=width, height=height, n=n)
 
 

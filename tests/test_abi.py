@@ -41,6 +41,7 @@ def test_host_only_calls():
     assert rz.workspace_size(-1, 1, 128, 128, 10000) == 0
     assert rz.workspace_size(10, 0, 128, 128, 10000) == 0
     assert rz.workspace_size(10, 1, 128, 128, 1 << 30) == 0
+    assert L.gsr_batch_capacity(1000, 64) >= 1000 // 256 + 64
     t = rz.Timer()  # host object; reading an empty timer needs no device
     assert all(v == (0.0, 0) for v in t.read().values())
     t.close()
@@ -60,7 +61,8 @@ int main(void) {
   P(gsr_camera); O(gsr_camera, fx); O(gsr_camera, width); O(gsr_camera, guard);
   P(gsr_clip_plane); P(gsr_view_state); O(gsr_view_state, clip); O(gsr_view_state, bg);
   P(gsr_model); O(gsr_model, mean); O(gsr_model, layer);
-  P(gsr_fwd_state); O(gsr_fwd_state, pair_capacity);
+  P(gsr_fwd_state); O(gsr_fwd_state, pixel_state); O(gsr_fwd_state, pair_capacity);
+  O(gsr_fwd_state, batch_capacity);
   P(gsr_debug); P(gsr_grads);
   P(gsr_request); O(gsr_request, cam); O(gsr_request, vs); O(gsr_request, rgb); O(gsr_request, alpha);
   return 0;

@@ -77,6 +77,14 @@ def test_gradients_match_oracle(orc, D, n_views):
     _assert_close(got["activity"], ref["activity"], "activity", ref32["activity"])
 
 
+def test_backward_is_bitwise_reproducible():
+    sc, cams, vss, Gr, Ga = _case(seed=14, D=3, n_views=2)
+    a = _gpu_grads(sc, cams, vss, Gr, Ga)
+    b = _gpu_grads(sc, cams, vss, Gr, Ga)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
 def test_frozen_layers_exactly_zero(orc):
     sc, cams, vss, Gr, Ga = _case(seed=9)
     got = _gpu_grads(sc, cams, vss, Gr, Ga, trainable=0b100)

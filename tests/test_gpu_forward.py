@@ -93,6 +93,7 @@ def test_stop_rule_on_gpu():
     cam = scenes.make_camera(np.eye(3), [0, 0, 0], 128, 128, fx=110, fy=110, cx=64.5, cy=64.5)
     _, (rgb, alpha, st, dbg) = gpu_forward(sc, [cam], [scenes.view_state()])
     T = st.final_T.cpu().numpy().reshape(128, 128)
+    assert st.last.cpu().numpy().reshape(128, 128)[64, 64] > 0
     assert T[64, 64] == np.float32(2.0 ** -13)
 
 
