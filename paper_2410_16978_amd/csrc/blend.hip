@@ -1,13 +1,12 @@
 // Per-tile front-to-back compositing and its backward.
 //
-// Forward: one 256-thread block (4 waves) per 16 x 16 tile, one pixel per
+// Work unit: a batch of (at most) 256 consecutive depth-sorted pairs of one
+// 16 x 16 tile, processed by a 256-thread block (4 waves), one pixel per
 // thread; each wave covers an 8 x 8 quadrant so that a small splat touches
-// few waves.  The tile's depth-sorted pairs are staged through LDS in batches
-// of 256 records (every lane then reads the same LDS address, a broadcast);
-// the block stops loading once every pixel has reached the transmittance
-// stop.  For each batch the block stores every pixel's transmittance before
-// the batch and the colour the batch adds (a checkpoint), so that the
-// backward can start at any batch.
+// few waves, and a wave skips (uniformly) every pair whose reach box misses
+// its quadrant.  The batch's records are staged through LDS (every lane then
+// reads the same LDS address, a broadcast).  Batches, not tiles, are the
+// unit of parallelism, so a tile with a long list no longer bounds a launch.
 //
 // Per pixel, front to back: alpha = min(0.99, o exp(-q/2)) with
 // q = d^T conic d; pairs with q < 0 (rounding) or alpha < 1/255 are skipped;
@@ -29,9 +28,10 @@
 namespace gsr {
 
 struct BatchLds {
-  float4 a[kBatch];  // u, v, conic a, conic b
-  float4 b[kBatch];  // conic c, opacity, r, g
-  float c[kBatch];   // b
+  float4 a[kBatch];    // u, v, conic a, conic b
+  float4 b[kBatch];    // conic c, opacity, r, g
+  float c[kBatch];     // b
+  float4 box[kBatch];  // x0, x1, y0, y1: pixel centres outside cannot reach alpha >= 1/255
 };
 
 __device__ __forceinline__ int find_view(const ViewD* __restrict__ views, int n_views, uint32_t tile) {
@@ -49,18 +49,59 @@ __device__ __forceinline__ void pixel_of(int tid, int tx, int ty, int& px, int& 
   py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
 }
 
-__device__ __forceinline__ void stage(BatchLds& L, const float* __restrict__ records, uint32_t n_rec,
-                                      const uint32_t* __restrict__ vals, uint32_t k, bool ok, int tid) {
+// One pair's record in registers (loaded a batch ahead of its use).
+struct Staged {
+  float4 a, b;
+  float c;
+};
+
+__device__ __forceinline__ Staged fetch(const float* __restrict__ records, uint32_t n_rec,
+                                        const uint32_t* __restrict__ vals, uint32_t k, bool ok) {
+  Staged st;
+  st.a = make_float4(0.f, 0.f, 0.f, 0.f);
+  st.b = st.a;
+  st.c = 0.f;
   if (ok) {
     uint32_t r = vals[k];
     if (r >= n_rec) r = 0;  // never read out of range (a sort fault shows up as wrong pixels)
     const float4* rec = reinterpret_cast<const float4*>(records + (size_t)r * kRecordFloats);
-    const float4 r0 = rec[0], r1 = rec[1];
-    const float r2 = records[(size_t)r * kRecordFloats + 8];
-    L.a[tid] = r0;
-    L.b[tid] = r1;
-    L.c[tid] = r2;
+    st.a = rec[0];
+    st.b = rec[1];
+    st.c = records[(size_t)r * kRecordFloats + 8];
   }
+  return st;
+}
+
+// Bounding box of the pixel centres where the pair can reach alpha >= 1/255:
+// o exp(-q/2) >= 1/255 needs q <= 2 ln(255 o); the box of that ellipse has
+// half-widths sqrt(q conic^-1_00) and sqrt(q conic^-1_11).  A relative
+// margin of 1e-3 plus 0.01 on q and 0.01 px on the box covers the rounding
+// of q, exp and this computation, so skipping a pair for pixels outside the
+// box never changes a result.
+__device__ __forceinline__ float4 reach_box(const Staged& st) {
+  const float o = st.b.y;
+  const float qo = fminf(kQMax, 2.f * __logf(255.f * o)) * 1.001f + 0.01f;
+  if (!(qo > 0.f)) return make_float4(1e30f, -1e30f, 1e30f, -1e30f);
+  const float ca = st.a.z, cb = st.a.w, cc = st.b.x;
+  const float det = ca * cc - cb * cb;
+  const float hx = sqrtf(qo * cc / det) + 0.01f, hy = sqrtf(qo * ca / det) + 0.01f;
+  return make_float4(st.a.x - hx, st.a.x + hx, st.a.y - hy, st.a.y + hy);
+}
+
+__device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int tid) {
+  if (ok) {
+    L.a[tid] = st.a;
+    L.b[tid] = st.b;
+    L.c[tid] = st.c;
+    L.box[tid] = reach_box(st);
+  }
+}
+
+// True (uniformly over the wave) when the pair's box misses every pixel
+// centre of the wave's 8 x 8 quadrant [qx0, qx1] x [qy0, qy1].
+__device__ __forceinline__ bool misses_quadrant(const float4 bx, float qx0, float qx1, float qy0, float qy1) {
+  const bool miss = (bx.y < qx0) || (bx.x > qx1) || (bx.w < qy0) || (bx.z > qy1);
+  return __builtin_amdgcn_readfirstlane((int)miss) != 0;
 }
 
 // Exponent -q/2 of one pair at a pixel offset (dx, dy) = centre - pixel,
@@ -76,114 +117,206 @@ __device__ __forceinline__ float pair_alpha(const float4 B, float power) {
   return fminf(kAlphaMax, B.y * __expf(power));
 }
 
-__device__ void blend_tile(const ViewD& V, uint32_t tile, const float* __restrict__ records, uint32_t n_rec,
-                           const uint32_t* __restrict__ vals, uint32_t cap, const uint32_t* __restrict__ ranges,
-                           float4* __restrict__ ckpt, BatchLds& L) {
-  const int tid = threadIdx.x;
-  const uint32_t local = tile - V.tile_off;
+// ---------------------------------------------------------------- batch-parallel forward
+// The single-pass forward walks a tile's whole list in one block, so the
+// tile with the longest list bounds the launch.  The batch-parallel forward
+// gives every 256-pair batch its own block in three launches:
+//   products: per batch and pixel, Q = prod (1 - alpha) over the batch's
+//             blended candidates (no stop);
+//   colour:   the transmittance entering batch c is T_c = prod_{c' < c} Q_c'
+//             (in batch order); the pixel is still active iff T_c >= 1e-4.
+//             The batch is walked again with T = T_c * Q_k (Q_k the same
+//             running product), the stop rule applied to T_c * Q_{k+1}; the
+//             batch's colour, its end transmittance and last pair are stored,
+//             and (T_c, colour) is the batch's checkpoint;
+//   finalize: per tile and pixel, the colours of the active batches are
+//             summed in order and the outputs written.
+// Because T_c * Q is monotone in the pair index, "stopped before batch c"
+// and "T_c < 1e-4" coincide exactly; the transmittance products are
+// associated per batch instead of strictly left to right, a rounding-level
+// difference from the single-pass order.
+struct BatchCtx {
+  uint32_t tile, c, start, n;
+  int vi;
+};
+
+__device__ __forceinline__ BatchCtx batch_ctx(const ViewD* __restrict__ views, int n_views, uint32_t bi,
+                                              const uint32_t* __restrict__ ranges,
+                                              const uint32_t* __restrict__ batch_off,
+                                              const uint32_t* __restrict__ batch_tile, uint32_t cap) {
+  BatchCtx b;
+  b.tile = batch_tile[bi];
+  b.c = bi - batch_off[b.tile];
+  const uint32_t t_end = min(ranges[2 * b.tile + 1], cap);
+  b.start = min(ranges[2 * b.tile] + b.c * kBatch, t_end);
+  b.n = min(b.start + kBatch, t_end) - b.start;
+  b.vi = find_view(views, n_views, b.tile);
+  return b;
+}
+
+__global__ void __launch_bounds__(256)
+k_blend_products(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
+                 const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
+                 const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ batch_off,
+                 const uint32_t* __restrict__ batch_tile, const uint32_t* __restrict__ counters,
+                 uint32_t* __restrict__ ticket, float* __restrict__ prod) {
+  __shared__ BatchLds L;
+  __shared__ uint32_t s_bi;
+  const uint32_t n_batches = counters[kCntBatches];
+  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
+  for (;;) {
+  __syncthreads();
+  if (threadIdx.x == 0) s_bi = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const uint32_t bi = s_bi;
+  if (bi >= n_batches) return;
+  const BatchCtx bc = batch_ctx(views, n_views, bi, ranges, batch_off, batch_tile, cap);
+  const ViewD& V = views[bc.vi];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t local = bc.tile - V.tile_off;
+  const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
+  int px, py;
+  pixel_of(tid, tx, ty, px, py);
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const float qx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, qx1 = qx0 + 7.f;
+  const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
+  put(L, fetch(records, n_rec, vals, bc.start + tid, tid < (int)bc.n), tid < (int)bc.n, tid);
+  __syncthreads();
+  float Q = 1.f;
+  for (int j = 0; j < (int)bc.n; ++j) {
+    if (misses_quadrant(L.box[j], qx0, qx1, qy0, qy1)) continue;
+    const float4 A = L.a[j], B = L.b[j];
+    const float power = pair_power(A, B, A.x - fx, A.y - fy);
+    if (power > 0.f) continue;
+    const float alpha = pair_alpha(B, power);
+    if (alpha < kAlphaMin) continue;
+    Q = Q * (1.f - alpha);
+  }
+  prod[(size_t)bi * kBatch + tid] = Q;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_blend_colour(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
+               const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
+               const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ batch_off,
+               const uint32_t* __restrict__ batch_tile, const uint32_t* __restrict__ counters,
+               uint32_t* __restrict__ ticket, const float* __restrict__ prod, float4* __restrict__ ckpt,
+               float* __restrict__ t_end, uint32_t* __restrict__ last_b) {
+  __shared__ BatchLds L;
+  __shared__ uint32_t s_bi;
+  const uint32_t n_batches = counters[kCntBatches];
+  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
+  for (;;) {
+  __syncthreads();
+  if (threadIdx.x == 0) s_bi = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const uint32_t bi = s_bi;
+  if (bi >= n_batches) return;
+  const BatchCtx bc = batch_ctx(views, n_views, bi, ranges, batch_off, batch_tile, cap);
+  const ViewD& V = views[bc.vi];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t local = bc.tile - V.tile_off;
   const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
   int px, py;
   pixel_of(tid, tx, ty, px, py);
   const bool inside = px < V.W && py < V.H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const uint32_t end = min(ranges[2 * tile + 1], cap);
-  const uint32_t start = min(ranges[2 * tile], end);
+  const float qx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, qx1 = qx0 + 7.f;
+  const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
+  // transmittance entering this batch
+  const uint32_t b0 = bi - bc.c;
+  float Tc = 1.f;
+  for (uint32_t cc = 0; cc < bc.c; ++cc) Tc = Tc * prod[(size_t)(b0 + cc) * kBatch + tid];
+  bool done = !inside || !(Tc >= kTStop);
+  put(L, fetch(records, n_rec, vals, bc.start + tid, tid < (int)bc.n), tid < (int)bc.n, tid);
+  __syncthreads();
+  float Q = 1.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
+  uint32_t last = 0;
+  if (!done) {
+    for (int j = 0; j < (int)bc.n; ++j) {
+      if (misses_quadrant(L.box[j], qx0, qx1, qy0, qy1)) continue;
+      const float4 A = L.a[j], B = L.b[j];
+      const float power = pair_power(A, B, A.x - fx, A.y - fy);
+      if (power > 0.f) continue;
+      const float alpha = pair_alpha(B, power);
+      if (alpha < kAlphaMin) continue;
+      const float Qn = Q * (1.f - alpha);
+      if (Tc * Qn < kTStop) break;  // this pair is not blended; the pixel ends here
+      const float w = alpha * (Tc * Q);
+      D0 = fmaf(B.z, w, D0);
+      D1 = fmaf(B.w, w, D1);
+      D2 = fmaf(L.c[j], w, D2);
+      Q = Qn;
+      last = bc.start + (uint32_t)j + 1;
+    }
+  }
+  const size_t o = (size_t)bi * kBatch + tid;
+  ckpt[o] = make_float4(Tc, D0, D1, D2);
+  t_end[o] = Tc * Q;
+  last_b[o] = last;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_blend_final(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
+              const uint32_t* __restrict__ batch_off, uint32_t batch_cap, const float4* __restrict__ ckpt,
+              const float* __restrict__ t_end, const uint32_t* __restrict__ last_b,
+              const int32_t* __restrict__ req_status) {
+  const uint32_t tile = blockIdx.x;
+  if (tile >= total_tiles) return;
+  const ViewD& V = views[find_view(views, n_views, tile)];
+  if (req_status && req_status[V.request] != 0) return;  // a request that did not fit is not written
+  const int tid = threadIdx.x;
+  const uint32_t local = tile - V.tile_off;
+  const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
+  int px, py;
+  pixel_of(tid, tx, ty, px, py);
+  if (!(px < V.W && py < V.H)) return;
+  const uint32_t b0 = batch_off[tile], b1 = min(batch_off[tile + 1], batch_cap);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = 0;
-  bool done = !inside;
-  uint32_t batch = 0;
-  for (uint32_t b = start; b < end; b += kBatch, ++batch) {
-    if (__syncthreads_and(done)) break;
-    const float T0 = T;
-    float D0 = 0.f, D1 = 0.f, D2 = 0.f;  // colour added by this batch
-    const uint32_t k = b + tid;
-    stage(L, records, n_rec, vals, k, k < end, tid);
-    __syncthreads();
-    const int n = (int)min((uint32_t)kBatch, end - b);
-    if (!done) {
-      for (int j = 0; j < n; ++j) {
-        const float4 A = L.a[j], B = L.b[j];
-        const float dx = A.x - fx, dy = A.y - fy;
-        const float power = pair_power(A, B, dx, dy);
-        if (power > 0.f) continue;
-        const float alpha = pair_alpha(B, power);
-        if (alpha < kAlphaMin) continue;
-        const float Tn = T * (1.f - alpha);
-        if (Tn < kTStop) { done = true; break; }
-        const float w = alpha * T;
-        D0 = fmaf(B.z, w, D0);
-        D1 = fmaf(B.w, w, D1);
-        D2 = fmaf(L.c[j], w, D2);
-        T = Tn;
-        last = b + (uint32_t)j + 1;
-      }
-    }
-    if (ckpt) ckpt[(size_t)batch * kBatch + tid] = make_float4(T0, D0, D1, D2);
-    C0 += D0;
-    C1 += D1;
-    C2 += D2;
+  for (uint32_t bi = b0; bi < b1; ++bi) {
+    const size_t o = (size_t)bi * kBatch + tid;
+    const float4 ck = ckpt[o];
+    if (!(ck.x >= kTStop)) break;  // stopped in an earlier batch
+    C0 += ck.y;
+    C1 += ck.z;
+    C2 += ck.w;
+    T = t_end[o];
+    const uint32_t lb = last_b[o];
+    if (lb) last = lb;
   }
-  if (inside) {
-    const size_t pix = (size_t)py * V.W + px;
-    const size_t plane = (size_t)V.W * V.H;
-    V.rgb[pix] = fmaf(T, V.bg[0], C0);
-    V.rgb[plane + pix] = fmaf(T, V.bg[1], C1);
-    V.rgb[2 * plane + pix] = fmaf(T, V.bg[2], C2);
-    V.alpha[pix] = 1.f - T;
-    reinterpret_cast<float4*>(V.pix)[pix] = make_float4(T, C0, C1, C2);
-    V.last[pix] = last;
-  }
+  const size_t pix = (size_t)py * V.W + px;
+  const size_t plane = (size_t)V.W * V.H;
+  V.rgb[pix] = fmaf(T, V.bg[0], C0);
+  V.rgb[plane + pix] = fmaf(T, V.bg[1], C1);
+  V.rgb[2 * plane + pix] = fmaf(T, V.bg[2], C2);
+  V.alpha[pix] = 1.f - T;
+  reinterpret_cast<float4*>(V.pix)[pix] = make_float4(T, C0, C1, C2);
+  V.last[pix] = last;
 }
 
-template <bool PERSISTENT>
-__global__ void __launch_bounds__(256)
-k_blend_fwd(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles, const float* __restrict__ records,
-            uint32_t n_rec, const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
-            const uint32_t* __restrict__ ranges, uint32_t* __restrict__ tile_ctr,
-            const int32_t* __restrict__ req_status, float4* __restrict__ ckpt,
-            const uint32_t* __restrict__ batch_off, uint32_t batch_cap) {
-  __shared__ BatchLds L;
-  __shared__ uint32_t s_tile;
-  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
-  for (;;) {
-    uint32_t tile;
-    if (PERSISTENT) {
-      __syncthreads();
-      if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
-      __syncthreads();
-      tile = s_tile;
-    } else {
-      tile = blockIdx.x;
-    }
-    if (tile >= total_tiles) return;
-    const ViewD& V = views[find_view(views, n_views, tile)];
-    if (!(req_status && req_status[V.request] != 0)) {
-      float4* tck = nullptr;
-      if (ckpt) {
-        const uint32_t b0 = batch_off[tile], b1 = batch_off[tile + 1];
-        if (b1 <= batch_cap && b0 <= b1) tck = ckpt + (size_t)b0 * kBatch;
-      }
-      blend_tile(V, tile, records, n_rec, vals, cap, ranges, tck, L);
-    }
-    if (!PERSISTENT) return;
-  }
-}
-
-hipError_t launch_blend_fwd(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
-                            uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
-                            const uint32_t* ranges, uint32_t* tile_ctr, const int32_t* req_status,
-                            float4* ckpt, const uint32_t* batch_off, uint32_t batch_cap, bool persistent,
-                            hipStream_t s) {
+// tickets: two zeroed counters (products, colour).  The two batch kernels are
+// persistent: a fixed grid of blocks takes batches in index order from a
+// ticket until every batch is done.
+hipError_t launch_blend_fwd_batched(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
+                                    uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
+                                    const uint32_t* ranges, const uint32_t* batch_off, const uint32_t* batch_tile,
+                                    uint32_t batch_cap, const uint32_t* counters, uint32_t* tickets,
+                                    const int32_t* req_status, float* prod, float4* ckpt, float* t_end,
+                                    uint32_t* last_b, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  if (persistent) {
-    const uint32_t grid = min(total_tiles, 256u * 8u);
-    hipLaunchKernelGGL(k_blend_fwd<true>, dim3(grid), dim3(256), 0, s, views_dev, n_views, total_tiles, records,
-                       n_rec, pair_vals, sel, cap, ranges, tile_ctr, req_status, ckpt, batch_off, batch_cap);
-  } else {
-    hipLaunchKernelGGL(k_blend_fwd<false>, dim3(total_tiles), dim3(256), 0, s, views_dev, n_views, total_tiles,
-                       records, n_rec, pair_vals, sel, cap, ranges, tile_ctr, req_status, ckpt, batch_off,
-                       batch_cap);
+  if (batch_cap > 0) {
+    const uint32_t grid = min(batch_cap, kPersistentBlocks);
+    hipLaunchKernelGGL(k_blend_products, dim3(grid), dim3(256), 0, s, views_dev, n_views, records, n_rec,
+                       pair_vals, sel, cap, ranges, batch_off, batch_tile, counters, tickets, prod);
+    hipLaunchKernelGGL(k_blend_colour, dim3(grid), dim3(256), 0, s, views_dev, n_views, records, n_rec,
+                       pair_vals, sel, cap, ranges, batch_off, batch_tile, counters, tickets + 1, prod, ckpt, t_end,
+                       last_b);
   }
+  hipLaunchKernelGGL(k_blend_final, dim3(total_tiles), dim3(256), 0, s, views_dev, n_views, total_tiles, batch_off,
+                     batch_cap, ckpt, t_end, last_b, req_status);
   return hipGetLastError();
 }
 
@@ -226,7 +359,8 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
             const uint32_t* __restrict__ counters, const float* __restrict__ dL_drgb,
             const float* __restrict__ dL_dalpha, float* __restrict__ g_pair) {
   __shared__ BatchLds L;
-  __shared__ float part[4][kGradSlots][kBatch];
+  constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
+  __shared__ float part[4][kGradSlots][kSub];
   const uint32_t bi = blockIdx.x;
   if (bi >= counters[kCntBatches]) return;
   const uint32_t tile = batch_tile[bi];
@@ -281,85 +415,98 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       plast = 0;
     }
   }
-  stage(L, records, n_rec, vals, start + tid, tid < n, tid);
-  for (int i = tid; i < 4 * kGradSlots * kBatch; i += 256) (&part[0][0][0])[i] = 0.f;
+  put(L, fetch(records, n_rec, vals, start + tid, tid < n), tid < n, tid);
+  for (int i = tid; i < 4 * kGradSlots * kSub; i += 256) (&part[0][0][0])[i] = 0.f;
+  const float qx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, qx1 = qx0 + 7.f;
+  const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
   __syncthreads();
 
-  for (int j = n - 1; j >= 0; --j) {
-    const uint32_t kk = start + (uint32_t)j;
-    float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f, w = 0.f;
-    bool contrib = false;
-    if (kk < plast) {
-      const float4 A = L.a[j], B = L.b[j];
-      const float cbl = L.c[j];
-      const float dx = A.x - fx, dy = A.y - fy;
-      const float power = pair_power(A, B, dx, dy);
-      if (power <= 0.f) {
-        const float G = __expf(power);
-        const float oG = B.y * G;
-        const float alpha = fminf(kAlphaMax, oG);
-        if (alpha >= kAlphaMin) {
-          contrib = true;
-          const float inv1m = 1.f / (1.f - alpha);
-          const float Tb = T * inv1m;  // transmittance in front of this pair
-          w = alpha * Tb;
-          const float dalpha = G0 * (B.z * Tb - S0 * inv1m) + G1 * (B.w * Tb - S1 * inv1m) +
-                               G2 * (cbl * Tb - S2 * inv1m) + GA * Tfin * inv1m;
-          S0 = fmaf(B.z, w, S0);
-          S1 = fmaf(B.w, w, S1);
-          S2 = fmaf(cbl, w, S2);
-          T = Tb;
-          gr = G0 * w;
-          gg = G1 * w;
-          gbl = G2 * w;
-          if (!(oG > kAlphaMax)) {
-            go = dalpha * G;
-            const float dq = dalpha * (-0.5f * oG);
-            gu = dq * 2.f * (A.z * dx + A.w * dy);
-            gv = dq * 2.f * (A.w * dx + B.x * dy);
-            ga = dq * dx * dx;
-            gb = dq * 2.f * dx * dy;
-            gc = dq * dy * dy;
+  // back to front in sub-batches of kSub pairs; after each, the four wave
+  // partials of its pairs are summed in a fixed order and written out
+  const int n_sub = (n + kSub - 1) / kSub;
+  for (int sb = n_sub - 1; sb >= 0; --sb) {
+    const int j0 = sb * kSub, j1 = min(n, j0 + kSub);
+    for (int j = j1 - 1; j >= j0; --j) {
+      if (misses_quadrant(L.box[j], qx0, qx1, qy0, qy1)) continue;
+      const uint32_t kk = start + (uint32_t)j;
+      float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f, w = 0.f;
+      bool contrib = false;
+      if (kk < plast) {
+        const float4 A = L.a[j], B = L.b[j];
+        const float cbl = L.c[j];
+        const float dx = A.x - fx, dy = A.y - fy;
+        const float power = pair_power(A, B, dx, dy);
+        if (power <= 0.f) {
+          const float G = __expf(power);
+          const float oG = B.y * G;
+          const float alpha = fminf(kAlphaMax, oG);
+          if (alpha >= kAlphaMin) {
+            contrib = true;
+            const float inv1m = 1.f / (1.f - alpha);
+            const float Tb = T * inv1m;  // transmittance in front of this pair
+            w = alpha * Tb;
+            const float dalpha = G0 * (B.z * Tb - S0 * inv1m) + G1 * (B.w * Tb - S1 * inv1m) +
+                                 G2 * (cbl * Tb - S2 * inv1m) + GA * Tfin * inv1m;
+            S0 = fmaf(B.z, w, S0);
+            S1 = fmaf(B.w, w, S1);
+            S2 = fmaf(cbl, w, S2);
+            T = Tb;
+            gr = G0 * w;
+            gg = G1 * w;
+            gbl = G2 * w;
+            if (!(oG > kAlphaMax)) {
+              go = dalpha * G;
+              const float dq = dalpha * (-0.5f * oG);
+              gu = dq * 2.f * (A.z * dx + A.w * dy);
+              gv = dq * 2.f * (A.w * dx + B.x * dy);
+              ga = dq * dx * dx;
+              gb = dq * 2.f * dx * dy;
+              gc = dq * dy * dy;
+            }
           }
         }
       }
+      if (__ballot(contrib) == 0ull) continue;
+      gu = wave_sum63(gu);
+      gv = wave_sum63(gv);
+      ga = wave_sum63(ga);
+      gb = wave_sum63(gb);
+      gc = wave_sum63(gc);
+      go = wave_sum63(go);
+      gr = wave_sum63(gr);
+      gg = wave_sum63(gg);
+      gbl = wave_sum63(gbl);
+      w = wave_max63(w);
+      if (lane == 63) {
+        const int js = j - j0;
+        part[wave][0][js] = gu;
+        part[wave][1][js] = gv;
+        part[wave][2][js] = ga;
+        part[wave][3][js] = gb;
+        part[wave][4][js] = gc;
+        part[wave][5][js] = go;
+        part[wave][6][js] = gr;
+        part[wave][7][js] = gg;
+        part[wave][8][js] = gbl;
+        part[wave][9][js] = w;
+      }
     }
-    if (__ballot(contrib) == 0ull) continue;
-    gu = wave_sum63(gu);
-    gv = wave_sum63(gv);
-    ga = wave_sum63(ga);
-    gb = wave_sum63(gb);
-    gc = wave_sum63(gc);
-    go = wave_sum63(go);
-    gr = wave_sum63(gr);
-    gg = wave_sum63(gg);
-    gbl = wave_sum63(gbl);
-    w = wave_max63(w);
-    if (lane == 63) {
-      part[wave][0][j] = gu;
-      part[wave][1][j] = gv;
-      part[wave][2][j] = ga;
-      part[wave][3][j] = gb;
-      part[wave][4][j] = gc;
-      part[wave][5][j] = go;
-      part[wave][6][j] = gr;
-      part[wave][7][j] = gg;
-      part[wave][8][j] = gbl;
-      part[wave][9][j] = w;
-    }
-  }
-  __syncthreads();
-  if (tid < n) {
-    float o[12];
+    __syncthreads();
+    if (tid < j1 - j0) {
+      float o[12];
 #pragma unroll
-    for (int s = 0; s < 9; ++s) o[s] = ((part[0][s][tid] + part[1][s][tid]) + part[2][s][tid]) + part[3][s][tid];
-    o[9] = fmaxf(fmaxf(part[0][9][tid], part[1][9][tid]), fmaxf(part[2][9][tid], part[3][9][tid]));
-    o[10] = 0.f;
-    o[11] = 0.f;
-    float4* dst = reinterpret_cast<float4*>(g_pair + (size_t)(start + tid) * 12);
-    dst[0] = make_float4(o[0], o[1], o[2], o[3]);
-    dst[1] = make_float4(o[4], o[5], o[6], o[7]);
-    dst[2] = make_float4(o[8], o[9], o[10], o[11]);
+      for (int q = 0; q < 9; ++q) o[q] = ((part[0][q][tid] + part[1][q][tid]) + part[2][q][tid]) + part[3][q][tid];
+      o[9] = fmaxf(fmaxf(part[0][9][tid], part[1][9][tid]), fmaxf(part[2][9][tid], part[3][9][tid]));
+      o[10] = 0.f;
+      o[11] = 0.f;
+      float4* dst = reinterpret_cast<float4*>(g_pair + (size_t)(start + j0 + tid) * 12);
+      dst[0] = make_float4(o[0], o[1], o[2], o[3]);
+      dst[1] = make_float4(o[4], o[5], o[6], o[7]);
+      dst[2] = make_float4(o[8], o[9], o[10], o[11]);
+    }
+    __syncthreads();
+    for (int i = tid; i < 4 * kGradSlots * kSub; i += 256) (&part[0][0][0])[i] = 0.f;
+    __syncthreads();
   }
 }
 

@@ -228,7 +228,8 @@ class GpuExecutor:
         return time.perf_counter()
 
     def idle(self, hint):
-        time.sleep(min(hint, 2e-3) if hint else 5e-5)
+        # hint: seconds until the next arrival (may already be <= 0), None = poll
+        time.sleep(max(0.0, min(hint, 2e-3)) if hint is not None else 5e-5)
 
     def pairs_estimate(self, r):
         est = 0
