@@ -97,11 +97,34 @@ __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int 
   }
 }
 
-// True (uniformly over the wave) when the pair's box misses every pixel
-// centre of the wave's 8 x 8 quadrant [qx0, qx1] x [qy0, qy1].
-__device__ __forceinline__ bool misses_quadrant(const float4 bx, float qx0, float qx1, float qy0, float qy1) {
-  const bool miss = (bx.y < qx0) || (bx.x > qx1) || (bx.w < qy0) || (bx.z > qy1);
-  return __builtin_amdgcn_readfirstlane((int)miss) != 0;
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// The wave's list of the batch's pairs (ascending, j < n) whose reach box
+// meets a pixel centre of its 8 x 8 quadrant [qx0, qx1] x [qy0, qy1]: each
+// lane tests one pair per round, a ballot compacts the hits.  Returns the
+// (wave-uniform) count.  Pairs not in the list cannot reach alpha >= 1/255 on
+// any of the wave's pixels, so skipping them changes nothing.
+__device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n, float qx0, float qx1, float qy0,
+                                         float qy1) {
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+#pragma unroll
+  for (int r = 0; r < kBatch / 64; ++r) {
+    const int j = r * 64 + lane;
+    bool hit = false;
+    if (j < n) {
+      const float4 bx = L.box[j];
+      hit = !((bx.y < qx0) || (bx.x > qx1) || (bx.w < qy0) || (bx.z > qy1));
+    }
+    const uint64_t m = __ballot(hit);
+    if (hit) list[cnt + __popcll(m & lanes_below())] = (uint8_t)j;
+    cnt += __popcll(m);
+  }
+  __builtin_amdgcn_wave_barrier();
+  return cnt;
 }
 
 // Exponent -q/2 of one pair at a pixel offset (dx, dy) = centre - pixel,
@@ -161,6 +184,7 @@ k_blend_products(const ViewD* __restrict__ views, int n_views, const float* __re
                  const uint32_t* __restrict__ batch_tile, const uint32_t* __restrict__ counters,
                  uint32_t* __restrict__ ticket, float* __restrict__ prod) {
   __shared__ BatchLds L;
+  __shared__ uint8_t lists[4][kBatch];
   __shared__ uint32_t s_bi;
   const uint32_t n_batches = counters[kCntBatches];
   const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
@@ -171,6 +195,8 @@ k_blend_products(const ViewD* __restrict__ views, int n_views, const float* __re
   const uint32_t bi = s_bi;
   if (bi >= n_batches) return;
   const BatchCtx bc = batch_ctx(views, n_views, bi, ranges, batch_off, batch_tile, cap);
+  // the last batch's product is never used (no batch follows it)
+  if (bi + 1 >= batch_off[bc.tile + 1]) continue;
   const ViewD& V = views[bc.vi];
   const int tid = threadIdx.x, wave = tid >> 6;
   const uint32_t local = bc.tile - V.tile_off;
@@ -182,9 +208,11 @@ k_blend_products(const ViewD* __restrict__ views, int n_views, const float* __re
   const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
   put(L, fetch(records, n_rec, vals, bc.start + tid, tid < (int)bc.n), tid < (int)bc.n, tid);
   __syncthreads();
+  uint8_t* list = lists[wave];
+  const int cnt = wave_list(L, list, (int)bc.n, qx0, qx1, qy0, qy1);
   float Q = 1.f;
-  for (int j = 0; j < (int)bc.n; ++j) {
-    if (misses_quadrant(L.box[j], qx0, qx1, qy0, qy1)) continue;
+  for (int t = 0; t < cnt; ++t) {
+    const int j = list[t];
     const float4 A = L.a[j], B = L.b[j];
     const float power = pair_power(A, B, A.x - fx, A.y - fy);
     if (power > 0.f) continue;
@@ -204,6 +232,7 @@ k_blend_colour(const ViewD* __restrict__ views, int n_views, const float* __rest
                uint32_t* __restrict__ ticket, const float* __restrict__ prod, float4* __restrict__ ckpt,
                float* __restrict__ t_end, uint32_t* __restrict__ last_b) {
   __shared__ BatchLds L;
+  __shared__ uint8_t lists[4][kBatch];
   __shared__ uint32_t s_bi;
   const uint32_t n_batches = counters[kCntBatches];
   const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
@@ -229,20 +258,26 @@ k_blend_colour(const ViewD* __restrict__ views, int n_views, const float* __rest
   float Tc = 1.f;
   for (uint32_t cc = 0; cc < bc.c; ++cc) Tc = Tc * prod[(size_t)(b0 + cc) * kBatch + tid];
   bool done = !inside || !(Tc >= kTStop);
-  put(L, fetch(records, n_rec, vals, bc.start + tid, tid < (int)bc.n), tid < (int)bc.n, tid);
-  __syncthreads();
   float Q = 1.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
   uint32_t last = 0;
-  if (!done) {
-    for (int j = 0; j < (int)bc.n; ++j) {
-      if (misses_quadrant(L.box[j], qx0, qx1, qy0, qy1)) continue;
+  // a batch behind the stop of every pixel of the tile adds nothing
+  if (__syncthreads_or(!done)) {
+    put(L, fetch(records, n_rec, vals, bc.start + tid, tid < (int)bc.n), tid < (int)bc.n, tid);
+    __syncthreads();
+    uint8_t* list = lists[wave];
+    const int cnt = __ballot(!done) ? wave_list(L, list, (int)bc.n, qx0, qx1, qy0, qy1) : 0;
+    for (int t = 0; t < cnt && !done; ++t) {
+      const int j = list[t];
       const float4 A = L.a[j], B = L.b[j];
       const float power = pair_power(A, B, A.x - fx, A.y - fy);
       if (power > 0.f) continue;
       const float alpha = pair_alpha(B, power);
       if (alpha < kAlphaMin) continue;
       const float Qn = Q * (1.f - alpha);
-      if (Tc * Qn < kTStop) break;  // this pair is not blended; the pixel ends here
+      if (Tc * Qn < kTStop) {  // this pair is not blended; the pixel ends here
+        done = true;
+        break;
+      }
       const float w = alpha * (Tc * Q);
       D0 = fmaf(B.z, w, D0);
       D1 = fmaf(B.w, w, D1);
@@ -361,6 +396,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   __shared__ BatchLds L;
   constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
   __shared__ float part[4][kGradSlots][kSub];
+  __shared__ uint8_t lists[4][kBatch];
   const uint32_t bi = blockIdx.x;
   if (bi >= counters[kCntBatches]) return;
   const uint32_t tile = batch_tile[bi];
@@ -421,13 +457,25 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
   __syncthreads();
 
+  // the wave's pairs: those reaching its quadrant, in front of its pixels'
+  // last blended pair
+  uint8_t* list = lists[wave];
+  int cnt = 0;
+  {
+    uint32_t wl = plast;  // wave maximum of plast
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wl = max(wl, (uint32_t)__shfl_xor((int)wl, off, 64));
+    const int n_wave = wl > start ? (int)min(wl - start, (uint32_t)n) : 0;
+    if (n_wave > 0) cnt = wave_list(L, list, n_wave, qx0, qx1, qy0, qy1);
+  }
   // back to front in sub-batches of kSub pairs; after each, the four wave
   // partials of its pairs are summed in a fixed order and written out
   const int n_sub = (n + kSub - 1) / kSub;
+  int t = cnt - 1;
   for (int sb = n_sub - 1; sb >= 0; --sb) {
     const int j0 = sb * kSub, j1 = min(n, j0 + kSub);
-    for (int j = j1 - 1; j >= j0; --j) {
-      if (misses_quadrant(L.box[j], qx0, qx1, qy0, qy1)) continue;
+    for (; t >= 0 && (int)list[t] >= j0; --t) {
+      const int j = list[t];
       const uint32_t kk = start + (uint32_t)j;
       float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f, w = 0.f;
       bool contrib = false;
