@@ -49,7 +49,8 @@ class Outputs(C.Structure):
                 ("n_tiles", C.POINTER(C.c_uint32)), ("clamp", C.POINTER(C.c_uint32)),
                 ("keys_emit", C.POINTER(C.c_uint64)), ("vals_emit", C.POINTER(C.c_uint32)),
                 ("keys", C.POINTER(C.c_uint64)), ("vals", C.POINTER(C.c_uint32)),
-                ("pair_cap", C.c_uint64), ("ranges", C.POINTER(C.c_uint32)), ("counts", C.c_uint64 * 4)]
+                ("pair_cap", C.c_uint64), ("ranges", C.POINTER(C.c_uint32)), ("counts", C.c_uint64 * 4),
+                ("near_rec", C.POINTER(C.c_uint8))]
 
 
 def lib():
@@ -68,7 +69,7 @@ def lib():
             f = getattr(_lib, name)
             P = C.POINTER(rtype)
             f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), P, P, C.c_uint32,
-                          P, P, P, P, P, P, P, C.c_int]
+                          P, P, P, P, P, P, P, P, C.c_int]
             f.restype = C.c_int
         _lib.oracle_sh_basis_f64.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib.oracle_sh_basis_f32.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -127,7 +128,8 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
 
     Returns a dict of numpy arrays: rgb [V][3][H][W] (list if resolutions
     differ), alpha, final_T, last, n_contrib, margin, rec [R][10], rect, n_tiles,
-    clamp, ranges, counts (K, E, A, tiles), and with pairs=True keys_emit,
+    clamp, near_rec (records with a threshold decision below margin 1), ranges,
+    counts (K, E, A, tiles), and with pairs=True keys_emit,
     vals_emit, keys, vals.
     """
     if isinstance(scenes, dict):
@@ -156,6 +158,7 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
         "margin": np.zeros(n_pix, np.float32), "rec": np.zeros((max(n_rec, 1), 10), dtype),
         "rect": np.zeros((max(n_rec, 1), 4), np.int32), "n_tiles": np.zeros(max(n_rec, 1), np.uint32),
         "clamp": np.zeros(max(n_rec, 1), np.uint32), "ranges": np.zeros((max(tiles, 1), 2), np.uint32),
+        "near_rec": np.zeros(max(n_rec, 1), np.uint8),
     }
     out = Outputs()
     ct = C.c_float if dtype == np.float32 else C.c_double
@@ -170,6 +173,7 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
     out.n_tiles = _ptr(res["n_tiles"], C.c_uint32)
     out.clamp = _ptr(res["clamp"], C.c_uint32)
     out.ranges = _ptr(res["ranges"], C.c_uint32)
+    out.near_rec = _ptr(res["near_rec"], C.c_uint8)
     fn = L.oracle_render_f32 if dtype == np.float32 else L.oracle_render_f64
     if pairs:
         # first call sizes the pair arrays
@@ -196,6 +200,7 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
     res["rect"] = res["rect"][:n_rec]
     res["n_tiles"] = res["n_tiles"][:n_rec]
     res["clamp"] = res["clamp"][:n_rec]
+    res["near_rec"] = res["near_rec"][:n_rec]
     res["ranges"] = res["ranges"][:tiles]
     if pairs:
         for k in ("keys_emit", "vals_emit", "keys", "vals"):
@@ -221,9 +226,16 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
     return res
 
 
-def backward(scene, cams, views, dL_drgb, dL_dalpha, trainable=0xFFFFFFFF, dtype=np.float32, n_threads=0):
+def backward(scene, cams, views, dL_drgb, dL_dalpha, trainable=0xFFFFFFFF, dtype=np.float32, n_threads=0,
+             bound=False):
     """Exact gradients of sum(dL_drgb*rgb) + sum(dL_dalpha*alpha) w.r.t. the
-    activated parameters of one scene rendered in every view."""
+    activated parameters of one scene rendered in every view.
+
+    bound=True adds g["bound"]: per gradient entry (same keys and shapes), the
+    rounding-error scale sum_slot |d entry / d slot| * sum_pixels |slot term|
+    * (blended pairs of the pixel + 64), so that an evaluation with unit
+    roundoff eps from the same records errs by at most about c * eps * bound
+    for a small constant c."""
     dtype = np.dtype(dtype)
     L = lib()
     ma = _ModelArrays(scene, dtype)
@@ -239,11 +251,16 @@ def backward(scene, cams, views, dL_drgb, dL_dalpha, trainable=0xFFFFFFFF, dtype
     dal = np.ascontiguousarray(dL_dalpha, dtype).reshape(-1)
     ct = C.c_float if dtype == np.float32 else C.c_double
     fn = L.oracle_backward_f32 if dtype == np.float32 else L.oracle_backward_f64
+    packed = np.zeros((11 + 3 * nc) * n, dtype) if bound else None
     rc = fn(V, C.byref(ma.struct), carr, varr, _ptr(drgb, ct), _ptr(dal, ct), trainable & 0xFFFFFFFF,
             _ptr(g["mean"], ct), _ptr(g["scale"], ct), _ptr(g["quat"], ct), _ptr(g["opacity"], ct),
-            _ptr(g["sh"], ct), _ptr(g["max_contrib"], ct), _ptr(g["activity"], ct), n_threads)
+            _ptr(g["sh"], ct), _ptr(g["max_contrib"], ct), _ptr(g["activity"], ct), _ptr(packed, ct), n_threads)
     if rc != 0:
         raise RuntimeError(f"oracle backward failed: {rc}")
+    if bound:
+        g["bound"] = {"mean": packed[:3 * n].reshape(3, n), "scale": packed[3 * n:6 * n].reshape(3, n),
+                      "quat": packed[6 * n:10 * n].reshape(4, n), "opacity": packed[10 * n:11 * n],
+                      "sh": packed[11 * n:].reshape(nc, 3, n)}
     return g
 
 

@@ -361,9 +361,18 @@ template <typename T> struct PixelOut {
 // Front-to-back compositing of one pixel over a depth-ordered list of record
 // ids.  `on_blend(k, rec, alpha, T_before, G, dx, dy, clamped)` is called for
 // every blended pair.
+// near (optional, [records]): set to 1 for each record one of whose decisions
+// here lies below margin 1.
+inline void mark_near(uint8_t* near, uint32_t rec, float m) {
+  if (near && m < 1.0f) {
+#pragma omp atomic write
+    near[rec] = 1;
+  }
+}
+
 template <typename T, typename F>
 PixelOut<T> blend_pixel(const Scene<T>& sc, const uint32_t* list, size_t count, T px, T py,
-                        const float* bg, F&& on_blend) {
+                        const float* bg, F&& on_blend, uint8_t* near = nullptr) {
   PixelOut<T> o;
   T Tc = T(1);
   T C[3] = {T(0), T(0), T(0)};
@@ -376,17 +385,29 @@ PixelOut<T> blend_pixel(const Scene<T>& sc, const uint32_t* list, size_t count, 
     ++o.evaluated;
     {
       const T mag = std::fabs(qa) + std::fabs(qc) + std::fabs(qb);
-      if (mag > T(0)) o.margin = std::min(o.margin, float(std::fabs(q) / mag / T(1e-5)));
+      if (mag > T(0)) {
+        const float m = float(std::fabs(q) / mag / T(1e-5));
+        o.margin = std::min(o.margin, m);
+        mark_near(near, list[k], m);
+      }
     }
     if (power > T(0)) continue;
     const T G = std::exp(power);
     const T oG = p.op * G;
-    o.margin = std::min(o.margin, float(std::fabs(oG - Consts<T>::alpha_min()) / Consts<T>::alpha_min() / T(1e-5)));
+    {
+      const float m = float(std::fabs(oG - Consts<T>::alpha_min()) / Consts<T>::alpha_min() / T(1e-5));
+      o.margin = std::min(o.margin, m);
+      mark_near(near, list[k], m);
+    }
     const bool clamped = oG > Consts<T>::alpha_max();
     const T alpha = clamped ? Consts<T>::alpha_max() : oG;
     if (alpha < Consts<T>::alpha_min()) continue;
     const T Tn = Tc * (T(1) - alpha);
-    o.margin = std::min(o.margin, float(std::fabs(Tn - Consts<T>::t_stop()) / Consts<T>::t_stop() / T(1e-4)));
+    {
+      const float m = float(std::fabs(Tn - Consts<T>::t_stop()) / Consts<T>::t_stop() / T(1e-4));
+      o.margin = std::min(o.margin, m);
+      mark_near(near, list[k], m);
+    }
     if (Tn < Consts<T>::t_stop()) break;  // this Gaussian is not blended
     const T w = alpha * Tc;
     for (int ch = 0; ch < 3; ++ch) C[ch] = C[ch] + p.rgb[ch] * w;
@@ -525,7 +546,7 @@ int render(int n_views, const Model<T>* models, const oc_camera* cams, const oc_
         size_t count, base;
         const uint32_t* list = src.get(v, x, y, &count, &base);
         PixelOut<T> o = blend_pixel(sc, list, count, T(x) + T(0.5), T(y) + T(0.5), sc.views[v].bg,
-                                    [](size_t, uint32_t, T, T, T, T, T, bool) {});
+                                    [](size_t, uint32_t, T, T, T, T, T, bool) {}, out->near_rec);
         E += o.evaluated;
         A += o.n_contrib;
         const uint64_t pix = po + (uint64_t)y * W + x;
@@ -550,112 +571,150 @@ template <typename T> struct G2 {
   T g[9];
 };
 
-template <typename T>
+// Number type of a first-order running error bound (Wilkinson's running error
+// analysis): v is the value, m bounds the accumulated rounding error in units
+// of the unit roundoff.  Each operation adds its own rounding |result| and
+// propagates its operands' bounds.  Inputs that are themselves computed
+// values carry m = |v| (see in<>), exact constants m = 0.
+struct Mag {
+  double v = 0.0, m = 0.0;
+  Mag() = default;
+  Mag(double x) : v(x), m(0.0) {}
+  Mag(double x, double mm) : v(x), m(mm) {}
+  friend Mag operator+(Mag a, Mag b) { const double r = a.v + b.v; return {r, a.m + b.m + std::fabs(r)}; }
+  friend Mag operator-(Mag a, Mag b) { const double r = a.v - b.v; return {r, a.m + b.m + std::fabs(r)}; }
+  friend Mag operator-(Mag a) { return {-a.v, a.m}; }
+  friend Mag operator*(Mag a, Mag b) {
+    const double r = a.v * b.v;
+    return {r, a.m * std::fabs(b.v) + std::fabs(a.v) * b.m + std::fabs(r)};
+  }
+  friend Mag operator/(Mag a, Mag b) {
+    const double r = a.v / b.v;
+    return {r, a.m / std::fabs(b.v) + std::fabs(a.v) * b.m / (b.v * b.v) + std::fabs(r)};
+  }
+  Mag& operator+=(Mag b) { return *this = *this + b; }
+};
+
+// A computed input value in arithmetic N (for Mag: one rounding already in it).
+template <typename N, typename T> inline N in(T x) { return N(x); }
+template <> inline Mag in<Mag, float>(float x) { return Mag(double(x), std::fabs(double(x))); }
+template <> inline Mag in<Mag, double>(double x) { return Mag(x, std::fabs(x)); }
+
+// Chain rule from the 2D gradient g2 of one record to the Gaussian's
+// parameters, accumulated into gm[3], gs[3], gq[4], go, gsh[nc*3].  All
+// arithmetic is done in N (T itself, or Mag for the error bound).
+template <typename T, typename N = T>
 void backward_gaussian(const Model<T>& m, int i, const Cam<T>& cam, const Proj<T>& p,
-                       const SH<T>& sh, const T* g2, T* gm, T* gs, T* gq, T* go, T* gsh) {
+                       const SH<T>& sh, const N* g2, N* gm, N* gs, N* gq, N* go, N* gsh) {
   const int n = m.n;
-  const T* W = cam.R;
+  N W[9];
+  for (int k = 0; k < 9; ++k) W[k] = in<N>(cam.R[k]);
   // --- opacity
   *go += g2[5];
   // --- colour: SH coefficients and the view direction
-  T drgb[3];
-  for (int ch = 0; ch < 3; ++ch) drgb[ch] = ((p.clamp >> ch) & 1u) ? T(0) : g2[6 + ch];
+  N drgb[3];
+  for (int ch = 0; ch < 3; ++ch) drgb[ch] = ((p.clamp >> ch) & 1u) ? N(T(0)) : g2[6 + ch];
   const int nc = (m.D + 1) * (m.D + 1);
-  T ddir[3] = {T(0), T(0), T(0)};
+  N ddir[3] = {N(T(0)), N(T(0)), N(T(0))};
   T Gy[16][3];
   sh.grad(p.dir[0], p.dir[1], p.dir[2], Gy);
   for (int k = 0; k < nc; ++k)
     for (int ch = 0; ch < 3; ++ch) {
-      gsh[k * 3 + ch] += p.Y[k] * drgb[ch];
-      const T c = m.sh[(size_t)(k * 3 + ch) * n + i];
-      for (int j = 0; j < 3; ++j) ddir[j] += c * Gy[k][j] * drgb[ch];
+      gsh[k * 3 + ch] += in<N>(p.Y[k]) * drgb[ch];
+      const N c = in<N>(m.sh[(size_t)(k * 3 + ch) * n + i]);
+      for (int j = 0; j < 3; ++j) ddir[j] += c * in<N>(Gy[k][j]) * drgb[ch];
     }
-  const T dd = p.dir[0] * ddir[0] + p.dir[1] * ddir[1] + p.dir[2] * ddir[2];
-  for (int j = 0; j < 3; ++j) gm[j] += (ddir[j] - p.dir[j] * dd) / p.dlen;
+  const N dir[3] = {in<N>(p.dir[0]), in<N>(p.dir[1]), in<N>(p.dir[2])};
+  const N dd = dir[0] * ddir[0] + dir[1] * ddir[1] + dir[2] * ddir[2];
+  for (int j = 0; j < 3; ++j) gm[j] += (ddir[j] - dir[j] * dd) / in<N>(p.dlen);
   // --- conic -> (a, b, c) of the 2D covariance
-  const T a = p.a, b = p.b, c = p.c, det2 = p.det * p.det;
-  const T dca = g2[2], dcb = g2[3], dcc = g2[4];
-  const T da = dca * (-c * c / det2) + dcb * (b * c / det2) + dcc * (-b * b / det2);
-  const T db = dca * (T(2) * b * c / det2) + dcb * (-(a * c + b * b) / det2) + dcc * (T(2) * a * b / det2);
-  const T dc = dca * (-b * b / det2) + dcb * (a * b / det2) + dcc * (-a * a / det2);
+  const N a = in<N>(p.a), b = in<N>(p.b), c = in<N>(p.c), det2 = in<N>(p.det) * in<N>(p.det);
+  const N dca = g2[2], dcb = g2[3], dcc = g2[4];
+  const N da = dca * (-c * c / det2) + dcb * (b * c / det2) + dcc * (-b * b / det2);
+  const N db = dca * (N(T(2)) * b * c / det2) + dcb * (-(a * c + b * b) / det2) + dcc * (N(T(2)) * a * b / det2);
+  const N dc = dca * (-b * b / det2) + dcb * (a * b / det2) + dcc * (-a * a / det2);
   // --- Sigma' = T Sigma T^T  (entries s00 = a - kappa, s01 = b, s11 = c - kappa)
-  const T* Tm = p.Tm;
-  const T* S = p.S;
-  T ST0[3], ST1[3];
+  N Tm[6], S[9];
+  for (int k = 0; k < 6; ++k) Tm[k] = in<N>(p.Tm[k]);
+  for (int k = 0; k < 9; ++k) S[k] = in<N>(p.S[k]);
+  N ST0[3], ST1[3];
   for (int r = 0; r < 3; ++r) {
     ST0[r] = S[3 * r] * Tm[0] + S[3 * r + 1] * Tm[1] + S[3 * r + 2] * Tm[2];
     ST1[r] = S[3 * r] * Tm[3] + S[3 * r + 1] * Tm[4] + S[3 * r + 2] * Tm[5];
   }
-  T dT0[3], dT1[3], dS[9];
+  N dT0[3], dT1[3], dS[9];
   for (int r = 0; r < 3; ++r) {
-    dT0[r] = T(2) * da * ST0[r] + db * ST1[r];
-    dT1[r] = db * ST0[r] + T(2) * dc * ST1[r];
+    dT0[r] = N(T(2)) * da * ST0[r] + db * ST1[r];
+    dT1[r] = db * ST0[r] + N(T(2)) * dc * ST1[r];
   }
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q)
       dS[3 * r + q] = da * Tm[r] * Tm[q] + db * Tm[r] * Tm[3 + q] + dc * Tm[3 + r] * Tm[3 + q];
   // --- Sigma = M M^T, M = Rq diag(s)
-  T dM[9];
+  N dM[9];
   for (int r = 0; r < 3; ++r)
     for (int k = 0; k < 3; ++k) {
-      T acc = T(0);
-      for (int j = 0; j < 3; ++j) acc += (dS[3 * r + j] + dS[3 * j + r]) * p.M[3 * j + k];
+      N acc = N(T(0));
+      for (int j = 0; j < 3; ++j) acc += (dS[3 * r + j] + dS[3 * j + r]) * in<N>(p.M[3 * j + k]);
       dM[3 * r + k] = acc;
     }
-  const T s[3] = {m.scale[i], m.scale[n + i], m.scale[2 * n + i]};
-  T dR[9];
+  const N s[3] = {in<N>(m.scale[i]), in<N>(m.scale[n + i]), in<N>(m.scale[2 * n + i])};
+  N dR[9];
   for (int r = 0; r < 3; ++r)
     for (int k = 0; k < 3; ++k) {
-      gs[k] += dM[3 * r + k] * p.Rq[3 * r + k];
+      gs[k] += dM[3 * r + k] * in<N>(p.Rq[3 * r + k]);
       dR[3 * r + k] = dM[3 * r + k] * s[k];
     }
   // --- rotation matrix -> unit quaternion -> raw quaternion
-  const T w = p.qh[0], x = p.qh[1], y = p.qh[2], z = p.qh[3];
-  T dq[4];
-  dq[0] = T(2) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-  dq[1] = T(2) * (y * dR[1] + z * dR[2] + y * dR[3] - T(2) * x * dR[4] - w * dR[5] + z * dR[6] +
-                  w * dR[7] - T(2) * x * dR[8]);
-  dq[2] = T(2) * (-T(2) * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
-                  z * dR[7] - T(2) * y * dR[8]);
-  dq[3] = T(2) * (-T(2) * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - T(2) * z * dR[4] +
-                  y * dR[5] + x * dR[6] + y * dR[7]);
-  const T qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  for (int k = 0; k < 4; ++k) gq[k] += (dq[k] - p.qh[k] * qd) / p.qn;
+  const N w = in<N>(p.qh[0]), x = in<N>(p.qh[1]), y = in<N>(p.qh[2]), z = in<N>(p.qh[3]);
+  const N two = N(T(2));
+  N dq[4];
+  dq[0] = two * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  dq[1] = two * (y * dR[1] + z * dR[2] + y * dR[3] - two * x * dR[4] - w * dR[5] + z * dR[6] +
+                 w * dR[7] - two * x * dR[8]);
+  dq[2] = two * (-two * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                 z * dR[7] - two * y * dR[8]);
+  dq[3] = two * (-two * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - two * z * dR[4] +
+                 y * dR[5] + x * dR[6] + y * dR[7]);
+  const N qh[4] = {w, x, y, z};
+  const N qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  for (int k = 0; k < 4; ++k) gq[k] += (dq[k] - qh[k] * qd) / in<N>(p.qn);
   // --- Jacobian and projected centre -> camera-space centre
-  T dJ00 = T(0), dJ02 = T(0), dJ11 = T(0), dJ12 = T(0);
+  N dJ00 = N(T(0)), dJ02 = N(T(0)), dJ11 = N(T(0)), dJ12 = N(T(0));
   for (int r = 0; r < 3; ++r) {
     dJ00 += dT0[r] * W[r];
     dJ02 += dT0[r] * W[6 + r];
     dJ11 += dT1[r] * W[3 + r];
     dJ12 += dT1[r] * W[6 + r];
   }
-  const T tx = p.tx, ty = p.ty, tz = p.tz, tz2 = tz * tz, tz3 = tz2 * tz;
-  T dtx = T(0), dty = T(0), dtz = T(0);
-  dtz += dJ00 * (-cam.fx / tz2) + dJ11 * (-cam.fy / tz2);
+  const N tx = in<N>(p.tx), ty = in<N>(p.ty), tz = in<N>(p.tz), tz2 = tz * tz, tz3 = tz2 * tz;
+  const N fx = in<N>(cam.fx), fy = in<N>(cam.fy);
+  N dtx = N(T(0)), dty = N(T(0)), dtz = N(T(0));
+  dtz += dJ00 * (-fx / tz2) + dJ11 * (-fy / tz2);
   if (!p.x_clamped) {
-    dtx += dJ02 * (-cam.fx / tz2);
-    dtz += dJ02 * (T(2) * cam.fx * tx / tz3);
+    dtx += dJ02 * (-fx / tz2);
+    dtz += dJ02 * (two * fx * tx / tz3);
   } else {
-    dtz += dJ02 * (cam.fx * p.xr / tz2);
+    dtz += dJ02 * (fx * in<N>(p.xr) / tz2);
   }
   if (!p.y_clamped) {
-    dty += dJ12 * (-cam.fy / tz2);
-    dtz += dJ12 * (T(2) * cam.fy * ty / tz3);
+    dty += dJ12 * (-fy / tz2);
+    dtz += dJ12 * (two * fy * ty / tz3);
   } else {
-    dtz += dJ12 * (cam.fy * p.yr / tz2);
+    dtz += dJ12 * (fy * in<N>(p.yr) / tz2);
   }
-  const T du = g2[0], dv = g2[1];
-  dtx += du * cam.fx / tz;
-  dtz += -du * cam.fx * tx / tz2;
-  dty += dv * cam.fy / tz;
-  dtz += -dv * cam.fy * ty / tz2;
+  const N du = g2[0], dv = g2[1];
+  dtx += du * fx / tz;
+  dtz += -du * fx * tx / tz2;
+  dty += dv * fy / tz;
+  dtz += -dv * fy * ty / tz2;
   for (int j = 0; j < 3; ++j) gm[j] += W[j] * dtx + W[3 + j] * dty + W[6 + j] * dtz;
 }
 
 template <typename T>
 int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_view* views,
              const T* dL_drgb, const T* dL_dalpha, uint32_t trainable, T* g_mean, T* g_scale,
-             T* g_quat, T* g_opacity, T* g_sh, T* max_contrib, T* activity, int n_threads) {
+             T* g_quat, T* g_opacity, T* g_sh, T* max_contrib, T* activity, T* bound, int n_threads) {
   if (n_views < 0 || m.n < 0 || m.D < 0 || m.D > 3) return -1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -675,6 +734,14 @@ int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_vie
 #endif
   std::vector<std::vector<G2<T>>> acc(nthr, std::vector<G2<T>>(sc.total_recs, G2<T>{}));
   std::vector<std::vector<T>> mc(nthr, std::vector<T>(sc.total_recs, T(0)));
+  // with `bound`: per record, the sums over pixels of the magnitudes of the
+  // terms of each 2D gradient slot (differences taken as the sum of the
+  // magnitudes of their operands), each weighted by the pixel's number of
+  // blended pairs plus 64: a term's transmittance and colour-behind carry one
+  // rounding per blended pair, its summation a few dozen more.  This is the
+  // scale of the rounding error of a finite-precision evaluation of the same
+  // sums from the same records.
+  std::vector<std::vector<G2<T>>> accb(bound ? nthr : 0, std::vector<G2<T>>(sc.total_recs, G2<T>{}));
   struct Contrib { uint32_t rec; T alpha, Tb, G, dx, dy; bool clamped; };
   for (int v = 0; v < n_views; ++v) {
     const int W = sc.cams[v].W, H = sc.cams[v].H;
@@ -701,18 +768,23 @@ int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_vie
         // suffix colour S_k = sum_{j>k} c_j alpha_j T_j + T_final * bg
         T S[3];
         for (int ch = 0; ch < 3; ++ch) S[ch] = o.T_final * T(sc.views[v].bg[ch]);
+        const T depth_w = T(cl.size() + 64);
         for (size_t kk = cl.size(); kk-- > 0;) {
           const Contrib& e = cl[kk];
           const Proj<T>& p = sc.proj[e.rec];
           G2<T>& g = acc[tid][e.rec];
           const T w = e.alpha * e.Tb;
           T dalpha = GA * o.T_final / (T(1) - e.alpha);
+          T mag = std::fabs(dalpha);
           for (int ch = 0; ch < 3; ++ch) {
             g.g[6 + ch] += Gc[ch] * w;
             dalpha += Gc[ch] * (p.rgb[ch] * e.Tb - S[ch] / (T(1) - e.alpha));
+            mag += std::fabs(Gc[ch]) * (std::fabs(p.rgb[ch] * e.Tb) + std::fabs(S[ch]) / (T(1) - e.alpha));
             S[ch] += p.rgb[ch] * w;
           }
           if (w > mc[tid][e.rec]) mc[tid][e.rec] = w;
+          if (bound)
+            for (int ch = 0; ch < 3; ++ch) accb[tid][e.rec].g[6 + ch] += depth_w * std::fabs(Gc[ch] * w);
           if (e.clamped) continue;
           g.g[5] += dalpha * e.G;
           const T dq = dalpha * (T(-0.5) * p.op * e.G);
@@ -721,22 +793,40 @@ int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_vie
           g.g[2] += dq * e.dx * e.dx;
           g.g[3] += dq * T(2) * e.dx * e.dy;
           g.g[4] += dq * e.dy * e.dy;
+          if (bound) {
+            G2<T>& b = accb[tid][e.rec];
+            const T mw = depth_w * mag;
+            const T mq = mw * (T(0.5) * p.op * e.G);
+            b.g[5] += mw * e.G;
+            b.g[0] += mq * T(2) * (std::fabs(p.ca * e.dx) + std::fabs(p.cb * e.dy));
+            b.g[1] += mq * T(2) * (std::fabs(p.cb * e.dx) + std::fabs(p.cc * e.dy));
+            b.g[2] += mq * e.dx * e.dx;
+            b.g[3] += mq * T(2) * std::fabs(e.dx * e.dy);
+            b.g[4] += mq * e.dy * e.dy;
+          }
         }
       }
     }
   }
   // reduce thread buffers in thread order
   std::vector<G2<T>> g2(sc.total_recs, G2<T>{});
+  std::vector<G2<T>> g2b(bound ? sc.total_recs : 0, G2<T>{});
   std::vector<T> mcr(sc.total_recs, T(0));
   for (int t = 0; t < nthr; ++t)
     for (uint64_t r = 0; r < sc.total_recs; ++r) {
       for (int k = 0; k < 9; ++k) g2[r].g[k] += acc[t][r].g[k];
+      if (bound)
+        for (int k = 0; k < 9; ++k) g2b[r].g[k] += accb[t][r].g[k];
       mcr[r] = std::max(mcr[r], mc[t][r]);
     }
   const int nc = (m.D + 1) * (m.D + 1);
   SH<T> sh;
   std::vector<T> gm(3), gs(3), gq(4), gsh(nc * 3);
+  const int per = 11 + 3 * nc;  // gradient entries per Gaussian
+  std::vector<T> col(per), bsum(per);
+  std::vector<Mag> cm(per);
   for (int i = 0; i < n; ++i) {
+    if (bound) std::fill(bsum.begin(), bsum.end(), T(0));
     T go = T(0);
     std::fill(gm.begin(), gm.end(), T(0));
     std::fill(gs.begin(), gs.end(), T(0));
@@ -750,6 +840,25 @@ int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_vie
       if (!p.valid) continue;
       mcv = std::max(mcv, mcr[r]);
       if (train) backward_gaussian(m, i, sc.cams[v], p, sh, g2[r].g, gm.data(), gs.data(), gq.data(), &go, gsh.data());
+      if (train && bound) {
+        // the chain rule is linear in the 2D gradient: column s of its matrix,
+        // in magnitude, times the slot's term-magnitude sum
+        for (int sl = 0; sl < 9; ++sl) {
+          if (g2b[r].g[sl] == T(0)) continue;
+          T e[9] = {};
+          e[sl] = T(1);
+          std::fill(col.begin(), col.end(), T(0));
+          backward_gaussian(m, i, sc.cams[v], p, sh, e, &col[0], &col[3], &col[6], &col[10], &col[11]);
+          for (int k = 0; k < per; ++k) bsum[k] += std::fabs(col[k]) * g2b[r].g[sl];
+        }
+        // plus the rounding of the chain rule itself (and of the record
+        // quantities it uses), as a running error bound
+        Mag g2m[9];
+        for (int sl = 0; sl < 9; ++sl) g2m[sl] = Mag(double(g2[r].g[sl]));
+        std::fill(cm.begin(), cm.end(), Mag());
+        backward_gaussian<T, Mag>(m, i, sc.cams[v], p, sh, g2m, &cm[0], &cm[3], &cm[6], &cm[10], &cm[11]);
+        for (int k = 0; k < per; ++k) bsum[k] += T(cm[k].m);
+      }
     }
     if (!train) {
       std::fill(gm.begin(), gm.end(), T(0));
@@ -763,6 +872,15 @@ int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_vie
     for (int j = 0; j < 4; ++j) g_quat[(size_t)j * n + i] = gq[j];
     g_opacity[i] = go;
     for (int k = 0; k < nc * 3; ++k) g_sh[(size_t)k * n + i] = gsh[k];
+    if (bound) {
+      // packed like the gradients: mean [3][n], scale [3][n], quat [4][n], opacity [n], sh [nc*3][n]
+      const size_t N = (size_t)n;
+      for (int j = 0; j < 3; ++j) bound[j * N + i] = bsum[j];
+      for (int j = 0; j < 3; ++j) bound[3 * N + j * N + i] = bsum[3 + j];
+      for (int j = 0; j < 4; ++j) bound[6 * N + j * N + i] = bsum[6 + j];
+      bound[10 * N + i] = bsum[10];
+      for (int k = 0; k < nc * 3; ++k) bound[11 * N + k * N + i] = bsum[11 + k];
+    }
     if (max_contrib) max_contrib[i] = mcv;
     if (activity) {
       T pm = T(0), pc = T(0), ps = T(0);
@@ -807,17 +925,17 @@ int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* ca
 int oracle_backward_f32(int n_views, const oc_model32* model, const oc_camera* cams, const oc_view* views,
                         const float* dL_drgb, const float* dL_dalpha, uint32_t trainable, float* g_mean,
                         float* g_scale, float* g_quat, float* g_opacity, float* g_sh, float* max_contrib,
-                        float* activity, int n_threads) {
+                        float* activity, float* bound, int n_threads) {
   return backward<float>(n_views, to_model<float>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
-                         g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads);
+                         g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, bound, n_threads);
 }
 
 int oracle_backward_f64(int n_views, const oc_model64* model, const oc_camera* cams, const oc_view* views,
                         const double* dL_drgb, const double* dL_dalpha, uint32_t trainable, double* g_mean,
                         double* g_scale, double* g_quat, double* g_opacity, double* g_sh,
-                        double* max_contrib, double* activity, int n_threads) {
+                        double* max_contrib, double* activity, double* bound, int n_threads) {
   return backward<double>(n_views, to_model<double>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
-                          g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads);
+                          g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, bound, n_threads);
 }
 
 void oracle_sh_basis_f64(const double* dir, double* out16) {

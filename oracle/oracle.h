@@ -88,6 +88,8 @@ typedef struct {
   uint64_t pair_cap;
   uint32_t* ranges;     /* [total_tiles][2] start, end */
   uint64_t counts[4];   /* out: pairs K, evaluated pairs E, blended pairs A, total tiles */
+  uint8_t* near_rec;    /* [sum n] zeroed by the caller; set to 1 for a record with a threshold decision
+                           below margin 1 at some pixel */
 } oc_outputs;
 
 /* Render n_views views; view v renders models[v] with cams[v] and views[v].
@@ -108,17 +110,24 @@ int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* ca
  * g_mean[3][n], g_scale[3][n], g_quat[4][n], g_opacity[n], g_sh[(D+1)^2][3][n]
  * are overwritten.  max_contrib[n] (optional) receives the largest
  * alpha * T of each Gaussian over all pixels and views; activity[n]
- * (optional) receives 2|g_mean| + 0.1|g_sh| + 0.1|g_log_scale|. */
+ * (optional) receives 2|g_mean| + 0.1|g_sh| + 0.1|g_log_scale|.
+ * bound (optional, [(11 + 3 (D+1)^2) n], packed in the order mean, scale,
+ * quat, opacity, sh of the gradients) receives, per gradient entry, the sum
+ * over the 2D gradient slots of |d entry / d slot| times the sum over pixels
+ * of the magnitudes of the slot's terms, each weighted by the pixel's number
+ * of blended pairs + 64, plus a running error bound of the chain rule from
+ * the 2D gradient to the parameters: the scale of the rounding error of a
+ * finite-precision evaluation from the same records (error <= c eps bound). */
 int oracle_backward_f32(int n_views, const oc_model32* model, const oc_camera* cams,
                         const oc_view* views, const float* dL_drgb, const float* dL_dalpha,
                         uint32_t trainable_layers, float* g_mean, float* g_scale, float* g_quat,
                         float* g_opacity, float* g_sh, float* max_contrib, float* activity,
-                        int n_threads);
+                        float* bound, int n_threads);
 int oracle_backward_f64(int n_views, const oc_model64* model, const oc_camera* cams,
                         const oc_view* views, const double* dL_drgb, const double* dL_dalpha,
                         uint32_t trainable_layers, double* g_mean, double* g_scale, double* g_quat,
                         double* g_opacity, double* g_sh, double* max_contrib, double* activity,
-                        int n_threads);
+                        double* bound, int n_threads);
 
 /* Real spherical-harmonic basis values Y_k(dir) for k < 16 (degree <= 3),
  * float and double, for the orthonormality check. */

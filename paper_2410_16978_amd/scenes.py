@@ -385,3 +385,25 @@ def poisson_trace(rate_hz, duration_s, seed=0, n_models=2, n_layers=5,
         vs = random_view_state(rng, n_layers)
         out.append({"arrival": t, "model": model, "cams": cams, "view": vs})
     return out
+
+
+def serving_models(n_a=500_000, n_b=2_000_000, n_layers=5):
+    """The two resident models of the serving workload (CT-like shells, SH3)."""
+    return [shell_scene(n_a // n_layers, n_layers, 3, seed=1, log_scale_mu=-5.0, log_scale_sigma=0.7, palette=True),
+            shell_scene(n_b // n_layers, n_layers, 3, seed=2, log_scale_mu=-5.0, log_scale_sigma=0.7, palette=True)]
+
+
+def layered_training_4m(n_per_layer=500_000, n_layers=8, width=1024, height=1024, pool=64, views_per_step=8,
+                        seed=0):
+    """8 shells x 500k, SH3 coefficients N(0, 0.1^2), a pool of orbit views
+    of which `views_per_step` are rendered per step; layer n_layers-1
+    trainable, the others frozen; the target is a perturbed copy."""
+    scene = shell_scene(n_per_layer, n_layers, 3, seed, log_scale_mu=-5.0, log_scale_sigma=0.7,
+                        palette=False, opacity="normal")
+    rng = np.random.default_rng(seed + 300)
+    cams = [orbit_camera(random_direction(rng), width, height) for _ in range(pool)]
+    target = perturbed_copy(scene, seed + 1)
+    name = f"layered_training_{n_layers * n_per_layer // 1000}k_{views_per_step}x{width}px"
+    return Workload(name, scene, cams[:views_per_step], [view_state(0xFFFFFFFF)] * views_per_step,
+                    {"target_scene": target, "pool": cams, "trainable_layers": 1 << (n_layers - 1)})
+
