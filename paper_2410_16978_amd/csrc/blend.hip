@@ -20,9 +20,10 @@
 // division by (1 - alpha) (alpha <= 0.99) and accumulating the colour behind
 // each pair from the back, which keeps that colour relatively accurate deep
 // in a pixel's list.  The per-pixel gradients of each pair are summed over
-// the wave with DPP (lane 63 holds the sum), the four wave sums in a fixed
-// order through LDS, and written as the pair's partial gradient: no atomics,
-// bitwise reproducible.
+// the wave - eight of them by a reduce-scatter with the lane-half and row
+// swaps (each step halves the values a lane carries), the ninth and the max
+// with DPP - the four wave sums in a fixed order through LDS, and written as
+// the pair's partial gradient: no atomics, bitwise reproducible.
 #include "common.hpp"
 
 namespace gsr {
@@ -383,6 +384,31 @@ __device__ __forceinline__ float wave_max63(float v) {  // v >= 0
   return v;
 }
 
+// Reduce-scatter of two values over the wave halves: the swap exchanges the
+// upper half of x with the lower half of y, so the sum holds x summed over
+// lanes l and l+32 in the lower half and y (likewise) in the upper half.
+__device__ __forceinline__ float swap32_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// The same over 16-lane rows: rows 1 and 3 of x are exchanged with rows 0
+// and 2 of y; the sum holds x (rows 0 and 2) and y (rows 1 and 3) summed over
+// rows paired within each half.
+__device__ __forceinline__ float swap16_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum over the 16 lanes of each row; every lane of the row ends with it.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp<0x140, 0xF>(v);  // row_mirror
+  return v;
+}
+
 constexpr int kGradSlots = 10;  // u, v, conic a, b, c, opacity, r, g, b, max alpha*T
 
 // g_pair: [P][12] per sorted pair: the 10 slots above, 2 unused.
@@ -515,26 +541,19 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
         }
       }
       if (__ballot(contrib) == 0ull) continue;
-      gu = wave_sum63(gu);
-      gv = wave_sum63(gv);
-      ga = wave_sum63(ga);
-      gb = wave_sum63(gb);
-      gc = wave_sum63(gc);
-      go = wave_sum63(go);
-      gr = wave_sum63(gr);
-      gg = wave_sum63(gg);
+      // eight sums by reduce-scatter: row r of s0 holds slot {u, v, c, o}[r],
+      // row r of s1 slot {a, b, r, g}[r]; the ninth sum and the max by DPP
+      const float s0 = row_sum16(swap16_add(swap32_add(gu, gc), swap32_add(gv, go)));
+      const float s1 = row_sum16(swap16_add(swap32_add(ga, gr), swap32_add(gb, gg)));
       gbl = wave_sum63(gbl);
       w = wave_max63(w);
+      const int js = j - j0;
+      if ((lane & 15) == 0) {
+        const int row = lane >> 4, slot = row + 2 * (row >> 1);  // 0, 1, 4, 5
+        part[wave][slot][js] = s0;
+        part[wave][slot + 2][js] = s1;
+      }
       if (lane == 63) {
-        const int js = j - j0;
-        part[wave][0][js] = gu;
-        part[wave][1][js] = gv;
-        part[wave][2][js] = ga;
-        part[wave][3][js] = gb;
-        part[wave][4][js] = gc;
-        part[wave][5][js] = go;
-        part[wave][6][js] = gr;
-        part[wave][7][js] = gg;
         part[wave][8][js] = gbl;
         part[wave][9][js] = w;
       }
