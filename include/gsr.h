@@ -125,7 +125,9 @@ typedef struct {
  *   last        uint32[Q]     1 + index of the last blended pair, 0 if none
  *   checkpoints float[B][256][4]  per 256-pair batch of a tile and pixel:
  *                             transmittance before the batch, then the
- *                             colour (r, g, b) the batch adds
+ *                             colour (r, g, b) the batch adds; written for
+ *                             the batches up to the one in which the tile's
+ *                             last pixel stops (later ones are never read)
  *   batch_map   uint32[X + 1 + B]  first batch of each tile (exclusive
  *                             scan, X + 1 entries), then the tile of each batch
  *   counters    uint32[4]     device: pairs K, overflow flag, error flag,

@@ -28,13 +28,12 @@ struct Carver {
   }
 };
 
-// Sort control block: digit counts and offsets of every pass, pass tickets,
-// the persistent-blend tile ticket.  Cleared at the start of each call.
+// Sort control block: digit counts and offsets of every pass, pass tickets.
+// Cleared at the start of each call.
 struct SortCtl {
   uint32_t hist[2 * kMaxSortPasses * 256];
   uint32_t pass_ctr[kMaxSortPasses];
-  uint32_t blend_tickets[2];
-  uint32_t pad[6];
+  uint32_t pad[8];
 };
 
 struct PipeBufs {
@@ -51,9 +50,6 @@ struct PipeBufs {
   SortPlan* plan = nullptr;
   uint32_t* status = nullptr;
   float* g_pair = nullptr;
-  float* prod = nullptr;     // [B][256] per-batch transmittance products
-  float* t_end = nullptr;    // [B][256] transmittance at the end of each batch
-  uint32_t* last_b = nullptr;// [B][256] last blended pair in each batch
   // batch only (the single-call path keeps these in the caller's state)
   float* records = nullptr;
   uint32_t* vals = nullptr;
@@ -62,12 +58,10 @@ struct PipeBufs {
   uint32_t* last = nullptr;
   uint32_t* counters = nullptr;
   uint32_t* sel = nullptr;
-  float* ckpt = nullptr;
-  uint32_t* batch_map = nullptr;
 };
 
 size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t n_req, bool batch,
-             size_t X, size_t Q, bool backward, size_t Bcap = 0) {
+             size_t X, size_t Q, bool backward) {
   b.views = c.take<ViewD>(std::max<size_t>(n_views, 1));
   b.req_rec = c.take<uint32_t>(n_req + 1);
   b.n_tiles = c.take<uint32_t>(std::max<size_t>(R, 1));
@@ -80,19 +74,12 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.plan = c.take<SortPlan>(1);
   b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
   if (backward) b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
-  if (Bcap) {
-    b.prod = c.take<float>(Bcap * kBatch);
-    b.t_end = c.take<float>(Bcap * kBatch);
-    b.last_b = c.take<uint32_t>(Bcap * kBatch);
-  }
   if (batch) {
     b.offsets = c.take<uint32_t>(R + 1);
     b.records = c.take<float>(kRecordFloats * std::max<size_t>(R, 1));
     b.vals = c.take<uint32_t>(2 * std::max<size_t>(P, 1));
     b.ranges = c.take<uint32_t>(2 * std::max<size_t>(X, 1));
     b.pix = c.take<float>(4 * std::max<size_t>(Q, 1));
-    b.ckpt = c.take<float>(4 * std::max<size_t>(Bcap, 1) * kBatch);
-    b.batch_map = c.take<uint32_t>(X + 1 + std::max<size_t>(Bcap, 1));
     b.last = c.take<uint32_t>(std::max<size_t>(Q, 1));
     b.counters = c.take<uint32_t>(4);
     b.sel = c.take<uint32_t>(1);
@@ -112,10 +99,6 @@ bool camera_ok(const gsr_camera& c) {
 }
 
 bool view_ok(const gsr_view_state& v) { return v.n_clip >= 0 && v.n_clip <= GSR_MAX_CLIP; }
-
-uint32_t tiles_of_wh(int32_t w, int32_t h) {
-  return div_up((uint32_t)w, (uint32_t)kTile) * div_up((uint32_t)h, (uint32_t)kTile);
-}
 
 uint32_t tiles_of(const gsr_camera& c) {
   return div_up((uint32_t)c.width, (uint32_t)kTile) * div_up((uint32_t)c.height, (uint32_t)kTile);
@@ -291,9 +274,7 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
   if (n < 0 || n_views <= 0 || width <= 0 || height <= 0 || pair_capacity >= (1u << 30)) return 0;
   Carver c(nullptr);
   PipeBufs b;
-  const uint32_t X = tiles_of_wh(width, height) * (uint32_t)n_views;
-  return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, 0, 0, true,
-               gsr_batch_capacity(pair_capacity, X));
+  return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, 0, 0, true);
 }
 
 gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
@@ -313,7 +294,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   const size_t plane = (size_t)W * H;
   Carver c(ws);
   PipeBufs b;
-  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true, gsr_batch_capacity(P, (uint32_t)X)) > ws_bytes)
+  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true) > ws_bytes)
     return GSR_ENOSPACE;
 
   std::vector<ViewD> hv(n_views);
@@ -377,11 +358,9 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   }
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);
-    HIP_TRY(launch_blend_fwd_batched(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals,
-                                     state->sort_sel, P, state->ranges, batch_off, batch_tile,
-                                     gsr_batch_capacity(P, (uint32_t)X), state->counters, b.ctl->blend_tickets,
-                                     nullptr, b.prod, reinterpret_cast<float4*>(state->checkpoints), b.t_end,
-                                     b.last_b, s));
+    HIP_TRY(launch_blend_fwd_tile(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals,
+                                  state->sort_sel, P, state->ranges, batch_off, gsr_batch_capacity(P, (uint32_t)X),
+                                  nullptr, reinterpret_cast<float4*>(state->checkpoints), s));
   }
   if (debug) {
     if (debug->n_tiles) HIP_TRY(hipMemcpyAsync(debug->n_tiles, b.n_tiles, 4ull * R, hipMemcpyDeviceToDevice, s));
@@ -429,7 +408,7 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
   const size_t plane = (size_t)W * H;
   Carver c(ws);
   PipeBufs b;
-  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true, gsr_batch_capacity(P, (uint32_t)X)) > ws_bytes)
+  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true) > ws_bytes)
     return GSR_ENOSPACE;
   std::vector<ViewD> hv(n_views);
   std::vector<int> ids(n_views);
@@ -508,8 +487,7 @@ size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const
   if (!plan_batch(models, n_models, reqs, n_req, bp) || pair_capacity >= (1u << 30)) return 0;
   Carver c(nullptr);
   PipeBufs b;
-  return carve(c, b, bp.views.size(), bp.R, pair_capacity, n_req, true, bp.X, bp.Q, false,
-               gsr_batch_capacity(pair_capacity, (uint32_t)bp.X));
+  return carve(c, b, bp.views.size(), bp.R, pair_capacity, n_req, true, bp.X, bp.Q, false);
 }
 
 gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs, int32_t n_req,
@@ -524,8 +502,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   const int n_views = (int)bp.views.size();
   Carver c(ws);
   PipeBufs b;
-  const uint32_t Bcap = gsr_batch_capacity(P, (uint32_t)bp.X);
-  if (carve(c, b, n_views, R, P, n_req, true, bp.X, bp.Q, false, Bcap) > ws_bytes) return GSR_ENOSPACE;
+  if (carve(c, b, n_views, R, P, n_req, true, bp.X, bp.Q, false) > ws_bytes) return GSR_ENOSPACE;
   // per-view transmittance / last index scratch
   size_t q_off = 0;
   for (ViewD& d : bp.views) {
@@ -568,14 +545,11 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
     HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
-    HIP_TRY(launch_tile_batches(b.ranges, (uint32_t)bp.X, Bcap, b.batch_map, b.batch_map + bp.X + 1, b.counters,
-                                s));
   }
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);
-    HIP_TRY(launch_blend_fwd_batched(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
-                                     b.batch_map, b.batch_map + bp.X + 1, Bcap, b.counters, b.ctl->blend_tickets,
-                                     req_status, b.prod, reinterpret_cast<float4*>(b.ckpt), b.t_end, b.last_b, s));
+    HIP_TRY(launch_blend_fwd_tile(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
+                                  nullptr, 0, req_status, nullptr, s));
   }
   return GSR_OK;
 }

@@ -1,29 +1,29 @@
 // Per-tile front-to-back compositing and its backward.
 //
-// Work unit: a batch of (at most) 256 consecutive depth-sorted pairs of one
-// 16 x 16 tile, processed by a 256-thread block (4 waves), one pixel per
-// thread; each wave covers an 8 x 8 quadrant so that a small splat touches
-// few waves, and a wave skips (uniformly) every pair whose reach box misses
-// its quadrant.  The batch's records are staged through LDS (every lane then
-// reads the same LDS address, a broadcast).  Batches, not tiles, are the
-// unit of parallelism, so a tile with a long list no longer bounds a launch.
-//
 // Per pixel, front to back: alpha = min(0.99, o exp(-q/2)) with
 // q = d^T conic d; pairs with q < 0 (rounding) or alpha < 1/255 are skipped;
 // a pair that would bring T below 1e-4 ends the pixel without being blended.
 //
+// A tile's depth-sorted pairs are handled in batches of (at most) 256: a
+// batch's records are staged through LDS once and every wave builds the
+// compacted list of the batch's pairs whose reach box (where alpha >= 1/255
+// is possible) meets its pixels, and walks only that list.
+//
+// Forward: one block per tile walks its batches in order (below).
+//
 // Backward: one block per (tile, batch) - the heavy tiles' lists are walked
-// by many blocks at once.  Each block starts at the end of its batch: the
-// transmittance there is the next batch's checkpoint (or the final one), the
-// colour behind it is the background term plus the later batches' colours,
-// summed from the back.  It walks the batch back to front, rebuilding T by
-// division by (1 - alpha) (alpha <= 0.99) and accumulating the colour behind
-// each pair from the back, which keeps that colour relatively accurate deep
-// in a pixel's list.  The per-pixel gradients of each pair are summed over
-// the wave - eight of them by a reduce-scatter with the lane-half and row
-// swaps (each step halves the values a lane carries), the ninth and the max
-// with DPP - the four wave sums in a fixed order through LDS, and written as
-// the pair's partial gradient: no atomics, bitwise reproducible.
+// by many blocks at once, one pixel per thread, each wave an 8 x 8 quadrant.
+// Each block starts at the end of its batch: the transmittance there is the
+// next batch's checkpoint (or the final one), the colour behind it is the
+// background term plus the later batches' colours, summed from the back.  It
+// walks the batch back to front, rebuilding T by division by (1 - alpha)
+// (alpha <= 0.99) and accumulating the colour behind each pair from the back,
+// which keeps that colour relatively accurate deep in a pixel's list.  The
+// per-pixel gradients of each pair are summed over the wave - eight of them
+// by a reduce-scatter with the lane-half and row swaps (each step halves the
+// values a lane carries), the ninth and the max with DPP - the four wave sums
+// in a fixed order through LDS, and written as the pair's partial gradient:
+// no atomics, bitwise reproducible.
 #include "common.hpp"
 
 namespace gsr {
@@ -98,6 +98,13 @@ __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int 
   }
 }
 
+// Lane permutation within rows / quads (DPP); lanes a row mask leaves out
+// read 0.
+template <unsigned CTRL, unsigned ROW_MASK>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
 __device__ __forceinline__ uint64_t lanes_below() {
   const int lane = threadIdx.x & 63;
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -141,188 +148,125 @@ __device__ __forceinline__ float pair_alpha(const float4 B, float power) {
   return fminf(kAlphaMax, B.y * __expf(power));
 }
 
-// ---------------------------------------------------------------- batch-parallel forward
-// The single-pass forward walks a tile's whole list in one block, so the
-// tile with the longest list bounds the launch.  The batch-parallel forward
-// gives every 256-pair batch its own block in three launches:
-//   products: per batch and pixel, Q = prod (1 - alpha) over the batch's
-//             blended candidates (no stop);
-//   colour:   the transmittance entering batch c is T_c = prod_{c' < c} Q_c'
-//             (in batch order); the pixel is still active iff T_c >= 1e-4.
-//             The batch is walked again with T = T_c * Q_k (Q_k the same
-//             running product), the stop rule applied to T_c * Q_{k+1}; the
-//             batch's colour, its end transmittance and last pair are stored,
-//             and (T_c, colour) is the batch's checkpoint;
-//   finalize: per tile and pixel, the colours of the active batches are
-//             summed in order and the outputs written.
-// Because T_c * Q is monotone in the pair index, "stopped before batch c"
-// and "T_c < 1e-4" coincide exactly; the transmittance products are
-// associated per batch instead of strictly left to right, a rounding-level
-// difference from the single-pass order.
-struct BatchCtx {
-  uint32_t tile, c, start, n;
-  int vi;
-};
+// ---------------------------------------------------------------- forward
+// One 1024-thread block per tile walks the tile's batches in order.  Each of
+// its 16 waves owns a 4 x 4 pixel sub-tile and gives every pixel a quad of
+// four lanes: a step takes the next four pairs of the wave's list, one per
+// lane of each quad, and advances the pixel's transmittance by the quad's
+// prefix product of (1 - alpha) - four pairs per step of the serial chain
+// instead of one.  The first pair (in list order) that would bring T below
+// 1e-4 ends the pixel and is not blended, as are the pairs after it.  Per
+// batch the records are staged once, a wave with a live pixel builds its list
+// (pairs whose reach box meets the sub-tile), and the block leaves when every
+// pixel has stopped.  Per batch it stores the checkpoint (T entering the
+// batch, colour the batch adds) the backward starts from, at the pixel's
+// index in the backward's 8 x 8-quadrant layout (ckpt may be null: render
+// only, then batch_off is not read).
+constexpr int kQuadPix = 4;  // sub-tile edge
 
-__device__ __forceinline__ BatchCtx batch_ctx(const ViewD* __restrict__ views, int n_views, uint32_t bi,
-                                              const uint32_t* __restrict__ ranges,
-                                              const uint32_t* __restrict__ batch_off,
-                                              const uint32_t* __restrict__ batch_tile, uint32_t cap) {
-  BatchCtx b;
-  b.tile = batch_tile[bi];
-  b.c = bi - batch_off[b.tile];
-  const uint32_t t_end = min(ranges[2 * b.tile + 1], cap);
-  b.start = min(ranges[2 * b.tile] + b.c * kBatch, t_end);
-  b.n = min(b.start + kBatch, t_end) - b.start;
-  b.vi = find_view(views, n_views, b.tile);
-  return b;
+__device__ __forceinline__ float quad_shift1(float x, int slot) {  // x of slot - 1, 1 for slot 0
+  const float y = dpp<0x90, 0xF>(x);                             // quad_perm [0,0,1,2]
+  return slot >= 1 ? y : 1.f;
 }
 
-__global__ void __launch_bounds__(256)
-k_blend_products(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
-                 const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
-                 const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ batch_off,
-                 const uint32_t* __restrict__ batch_tile, const uint32_t* __restrict__ counters,
-                 uint32_t* __restrict__ ticket, float* __restrict__ prod) {
+__device__ __forceinline__ float quad_shift2(float x, int slot) {  // x of slot - 2, 1 for slots 0, 1
+  const float y = dpp<0x40, 0xF>(x);                             // quad_perm [0,0,0,1]
+  return slot >= 2 ? y : 1.f;
+}
+
+__device__ __forceinline__ float quad_sum(float v) {
+  v += dpp<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
+  v += dpp<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
+  return v;
+}
+
+__device__ __forceinline__ uint32_t quad_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+__global__ void __launch_bounds__(1024)
+k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles, const float* __restrict__ records,
+             uint32_t n_rec, const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
+             const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ batch_off, uint32_t batch_cap,
+             const int32_t* __restrict__ req_status, float4* __restrict__ ckpt) {
   __shared__ BatchLds L;
-  __shared__ uint8_t lists[4][kBatch];
-  __shared__ uint32_t s_bi;
-  const uint32_t n_batches = counters[kCntBatches];
-  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
-  for (;;) {
-  __syncthreads();
-  if (threadIdx.x == 0) s_bi = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const uint32_t bi = s_bi;
-  if (bi >= n_batches) return;
-  const BatchCtx bc = batch_ctx(views, n_views, bi, ranges, batch_off, batch_tile, cap);
-  // the last batch's product is never used (no batch follows it)
-  if (bi + 1 >= batch_off[bc.tile + 1]) continue;
-  const ViewD& V = views[bc.vi];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const uint32_t local = bc.tile - V.tile_off;
-  const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
-  int px, py;
-  pixel_of(tid, tx, ty, px, py);
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const float qx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, qx1 = qx0 + 7.f;
-  const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
-  put(L, fetch(records, n_rec, vals, bc.start + tid, tid < (int)bc.n), tid < (int)bc.n, tid);
-  __syncthreads();
-  uint8_t* list = lists[wave];
-  const int cnt = wave_list(L, list, (int)bc.n, qx0, qx1, qy0, qy1);
-  float Q = 1.f;
-  for (int t = 0; t < cnt; ++t) {
-    const int j = list[t];
-    const float4 A = L.a[j], B = L.b[j];
-    const float power = pair_power(A, B, A.x - fx, A.y - fy);
-    if (power > 0.f) continue;
-    const float alpha = pair_alpha(B, power);
-    if (alpha < kAlphaMin) continue;
-    Q = Q * (1.f - alpha);
-  }
-  prod[(size_t)bi * kBatch + tid] = Q;
-  }
-}
-
-__global__ void __launch_bounds__(256)
-k_blend_colour(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
-               const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
-               const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ batch_off,
-               const uint32_t* __restrict__ batch_tile, const uint32_t* __restrict__ counters,
-               uint32_t* __restrict__ ticket, const float* __restrict__ prod, float4* __restrict__ ckpt,
-               float* __restrict__ t_end, uint32_t* __restrict__ last_b) {
-  __shared__ BatchLds L;
-  __shared__ uint8_t lists[4][kBatch];
-  __shared__ uint32_t s_bi;
-  const uint32_t n_batches = counters[kCntBatches];
-  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
-  for (;;) {
-  __syncthreads();
-  if (threadIdx.x == 0) s_bi = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const uint32_t bi = s_bi;
-  if (bi >= n_batches) return;
-  const BatchCtx bc = batch_ctx(views, n_views, bi, ranges, batch_off, batch_tile, cap);
-  const ViewD& V = views[bc.vi];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const uint32_t local = bc.tile - V.tile_off;
-  const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
-  int px, py;
-  pixel_of(tid, tx, ty, px, py);
-  const bool inside = px < V.W && py < V.H;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const float qx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, qx1 = qx0 + 7.f;
-  const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
-  // transmittance entering this batch
-  const uint32_t b0 = bi - bc.c;
-  float Tc = 1.f;
-  for (uint32_t cc = 0; cc < bc.c; ++cc) Tc = Tc * prod[(size_t)(b0 + cc) * kBatch + tid];
-  bool done = !inside || !(Tc >= kTStop);
-  float Q = 1.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
-  uint32_t last = 0;
-  // a batch behind the stop of every pixel of the tile adds nothing
-  if (__syncthreads_or(!done)) {
-    put(L, fetch(records, n_rec, vals, bc.start + tid, tid < (int)bc.n), tid < (int)bc.n, tid);
-    __syncthreads();
-    uint8_t* list = lists[wave];
-    const int cnt = __ballot(!done) ? wave_list(L, list, (int)bc.n, qx0, qx1, qy0, qy1) : 0;
-    for (int t = 0; t < cnt && !done; ++t) {
-      const int j = list[t];
-      const float4 A = L.a[j], B = L.b[j];
-      const float power = pair_power(A, B, A.x - fx, A.y - fy);
-      if (power > 0.f) continue;
-      const float alpha = pair_alpha(B, power);
-      if (alpha < kAlphaMin) continue;
-      const float Qn = Q * (1.f - alpha);
-      if (Tc * Qn < kTStop) {  // this pair is not blended; the pixel ends here
-        done = true;
-        break;
-      }
-      const float w = alpha * (Tc * Q);
-      D0 = fmaf(B.z, w, D0);
-      D1 = fmaf(B.w, w, D1);
-      D2 = fmaf(L.c[j], w, D2);
-      Q = Qn;
-      last = bc.start + (uint32_t)j + 1;
-    }
-  }
-  const size_t o = (size_t)bi * kBatch + tid;
-  ckpt[o] = make_float4(Tc, D0, D1, D2);
-  t_end[o] = Tc * Q;
-  last_b[o] = last;
-  }
-}
-
-__global__ void __launch_bounds__(256)
-k_blend_final(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
-              const uint32_t* __restrict__ batch_off, uint32_t batch_cap, const float4* __restrict__ ckpt,
-              const float* __restrict__ t_end, const uint32_t* __restrict__ last_b,
-              const int32_t* __restrict__ req_status) {
+  __shared__ uint8_t lists[16][kBatch];
   const uint32_t tile = blockIdx.x;
   if (tile >= total_tiles) return;
-  const ViewD& V = views[find_view(views, n_views, tile)];
+  const int vi = find_view(views, n_views, tile);
+  const ViewD& V = views[vi];
   if (req_status && req_status[V.request] != 0) return;  // a request that did not fit is not written
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int slot = lane & 3, p = lane >> 2;
   const uint32_t local = tile - V.tile_off;
   const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
-  int px, py;
-  pixel_of(tid, tx, ty, px, py);
-  if (!(px < V.W && py < V.H)) return;
-  const uint32_t b0 = batch_off[tile], b1 = min(batch_off[tile + 1], batch_cap);
+  const int sx0 = tx * kTile + (wave & 3) * kQuadPix, sy0 = ty * kTile + (wave >> 2) * kQuadPix;
+  const int lx = (wave & 3) * kQuadPix + (p & 3), ly = (wave >> 2) * kQuadPix + (p >> 2);  // in the tile
+  const int px = tx * kTile + lx, py = ty * kTile + ly;
+  const int bidx = ((ly >> 3) * 2 + (lx >> 3)) * 64 + (ly & 7) * 8 + (lx & 7);  // backward's thread of this pixel
+  const bool inside = px < V.W && py < V.H;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const float qx0 = (float)sx0 + 0.5f, qx1 = qx0 + 3.f, qy0 = (float)sy0 + 0.5f, qy1 = qy0 + 3.f;
+  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
+  const uint32_t t_end = min(ranges[2 * tile + 1], cap);
+  const uint32_t t_start = min(ranges[2 * tile], t_end);
+  const uint32_t b0 = ckpt ? batch_off[tile] : 0u;
+  uint8_t* list = lists[wave];
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = 0;
-  for (uint32_t bi = b0; bi < b1; ++bi) {
-    const size_t o = (size_t)bi * kBatch + tid;
-    const float4 ck = ckpt[o];
-    if (!(ck.x >= kTStop)) break;  // stopped in an earlier batch
-    C0 += ck.y;
-    C1 += ck.z;
-    C2 += ck.w;
-    T = t_end[o];
-    const uint32_t lb = last_b[o];
-    if (lb) last = lb;
+  bool done = !inside;
+  for (uint32_t start = t_start, c = 0; start < t_end; start += kBatch, ++c) {
+    if (!__syncthreads_or(!done)) break;  // also orders the previous batch's LDS reads before the refill
+    const int n = (int)min((uint32_t)kBatch, t_end - start);
+    if (tid < kBatch) put(L, fetch(records, n_rec, vals, start + tid, tid < n), tid < n, tid);
+    __syncthreads();
+    const float T0 = T;
+    float D0 = 0.f, D1 = 0.f, D2 = 0.f;
+    uint32_t lst = 0;
+    const int cnt = __ballot(!done) ? wave_list(L, list, n, qx0, qx1, qy0, qy1) : 0;
+    for (int t0 = 0; t0 < cnt; t0 += 4) {
+      const int te = t0 + slot;
+      const bool has = te < cnt;
+      const int j = has ? (int)list[te] : 0;
+      const float4 A = L.a[j], B = L.b[j];
+      const float cb = L.c[j];
+      const float power = pair_power(A, B, A.x - fx, A.y - fy);
+      const float alpha = pair_alpha(B, power);
+      const bool cand = has && !done && power <= 0.f && alpha >= kAlphaMin;
+      const float f = cand ? 1.f - alpha : 1.f;
+      float P = f * quad_shift1(f, slot);
+      P = P * quad_shift2(P, slot);        // prod of f over slots <= slot
+      const float E = quad_shift1(P, slot);  // over slots < slot
+      const float Tn = T * P;
+      const bool stop = cand && Tn < kTStop;
+      const uint32_t sbits = (uint32_t)(__ballot(stop) >> (lane & 60)) & 0xFu;
+      const int first = sbits ? __builtin_ctz(sbits) : 4;  // the quad's first stopping slot
+      const bool blend = cand && slot < first;
+      const float w = blend ? alpha * (T * E) : 0.f;
+      D0 = fmaf(B.z, w, D0);
+      D1 = fmaf(B.w, w, D1);
+      D2 = fmaf(cb, w, D2);
+      lst = blend ? start + (uint32_t)j + 1 : lst;
+      // T after the quad's last blended slot: T * P[first - 1]
+      const float P0 = dpp<0x00, 0xF>(P), P1 = dpp<0x55, 0xF>(P), P2 = dpp<0xAA, 0xF>(P), P3 = dpp<0xFF, 0xF>(P);
+      const float Pe = first == 0 ? 1.f : first == 1 ? P0 : first == 2 ? P1 : first == 3 ? P2 : P3;
+      T = (done || first == 0) ? T : T * Pe;
+      done = done || first < 4;
+      if (__ballot(!done) == 0ull) break;
+    }
+    D0 = quad_sum(D0);
+    D1 = quad_sum(D1);
+    D2 = quad_sum(D2);
+    lst = quad_max_u32(lst);
+    C0 += D0;
+    C1 += D1;
+    C2 += D2;
+    last = lst ? lst : last;
+    if (ckpt && slot == 0 && b0 + c < batch_cap) ckpt[(size_t)(b0 + c) * kBatch + bidx] = make_float4(T0, D0, D1, D2);
   }
+  if (!inside || slot != 0) return;
   const size_t pix = (size_t)py * V.W + px;
   const size_t plane = (size_t)V.W * V.H;
   V.rgb[pix] = fmaf(T, V.bg[0], C0);
@@ -333,36 +277,19 @@ k_blend_final(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles
   V.last[pix] = last;
 }
 
-// tickets: two zeroed counters (products, colour).  The two batch kernels are
-// persistent: a fixed grid of blocks takes batches in index order from a
-// ticket until every batch is done.
-hipError_t launch_blend_fwd_batched(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
-                                    uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
-                                    const uint32_t* ranges, const uint32_t* batch_off, const uint32_t* batch_tile,
-                                    uint32_t batch_cap, const uint32_t* counters, uint32_t* tickets,
-                                    const int32_t* req_status, float* prod, float4* ckpt, float* t_end,
-                                    uint32_t* last_b, hipStream_t s) {
+hipError_t launch_blend_fwd_tile(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
+                                 uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
+                                 const uint32_t* ranges, const uint32_t* batch_off, uint32_t batch_cap,
+                                 const int32_t* req_status, float4* ckpt, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  if (batch_cap > 0) {
-    const uint32_t grid = min(batch_cap, kPersistentBlocks);
-    hipLaunchKernelGGL(k_blend_products, dim3(grid), dim3(256), 0, s, views_dev, n_views, records, n_rec,
-                       pair_vals, sel, cap, ranges, batch_off, batch_tile, counters, tickets, prod);
-    hipLaunchKernelGGL(k_blend_colour, dim3(grid), dim3(256), 0, s, views_dev, n_views, records, n_rec,
-                       pair_vals, sel, cap, ranges, batch_off, batch_tile, counters, tickets + 1, prod, ckpt, t_end,
-                       last_b);
-  }
-  hipLaunchKernelGGL(k_blend_final, dim3(total_tiles), dim3(256), 0, s, views_dev, n_views, total_tiles, batch_off,
-                     batch_cap, ckpt, t_end, last_b, req_status);
+  hipLaunchKernelGGL(k_blend_tile, dim3(total_tiles), dim3(1024), 0, s, views_dev, n_views, total_tiles, records,
+                     n_rec, pair_vals, sel, cap, ranges, batch_off, batch_cap, req_status, ckpt);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- backward
 // Wave64 reductions with DPP: quad swaps, half-row and row mirrors, then the
 // row broadcasts 15 and 31; lane 63 ends with the result.
-template <unsigned CTRL, unsigned ROW_MASK>
-__device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
-}
 
 __device__ __forceinline__ float wave_sum63(float v) {
   v += dpp<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]

@@ -15,7 +15,6 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;        // per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kBatch = 256;          // pairs per blend batch (one per thread of a tile block)
-constexpr uint32_t kPersistentBlocks = 256 * 8;  // resident 256-thread blocks on 256 CUs
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -107,12 +106,10 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
 hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,
                          uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles, uint32_t* ranges,
                          hipStream_t s);
-hipError_t launch_blend_fwd_batched(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
-                                    uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
-                                    const uint32_t* ranges, const uint32_t* batch_off, const uint32_t* batch_tile,
-                                    uint32_t batch_cap, const uint32_t* counters, uint32_t* tickets,
-                                    const int32_t* req_status, float* prod, float4* ckpt, float* t_end,
-                                    uint32_t* last_b, hipStream_t s);
+hipError_t launch_blend_fwd_tile(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
+                                 uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
+                                 const uint32_t* ranges, const uint32_t* batch_off, uint32_t batch_cap,
+                                 const int32_t* req_status, float4* ckpt, hipStream_t s);
 hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
                             const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
