@@ -429,7 +429,7 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
     HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
                              state->ranges, reinterpret_cast<const float4*>(state->checkpoints), state->batch_map,
                              state->batch_map + X + 1, state->batch_capacity, state->counters, dL_drgb, dL_dalpha,
-                             b.g_pair, s));
+                             b.g_pair, max_contrib != nullptr, s));
   }
   const ModelD md = make_model(*model);
   {

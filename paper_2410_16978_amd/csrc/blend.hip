@@ -301,14 +301,22 @@ __device__ __forceinline__ float wave_sum63(float v) {
   return v;
 }
 
-__device__ __forceinline__ float wave_max63(float v) {  // v >= 0
-  v = fmaxf(v, dpp<0xB1, 0xF>(v));
-  v = fmaxf(v, dpp<0x4E, 0xF>(v));
-  v = fmaxf(v, dpp<0x141, 0xF>(v));
-  v = fmaxf(v, dpp<0x140, 0xF>(v));
-  v = fmaxf(v, dpp<0x142, 0xA>(v));
-  v = fmaxf(v, dpp<0x143, 0xC>(v));
-  return v;
+template <unsigned CTRL, unsigned ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// For v >= 0 the float order is the order of the bit patterns: an integer
+// max, which takes its DPP operand directly.
+__device__ __forceinline__ float wave_max63(float v) {
+  uint32_t u = __float_as_uint(v);
+  u = max(u, dpp_u32<0xB1, 0xF>(u));
+  u = max(u, dpp_u32<0x4E, 0xF>(u));
+  u = max(u, dpp_u32<0x141, 0xF>(u));
+  u = max(u, dpp_u32<0x140, 0xF>(u));
+  u = max(u, dpp_u32<0x142, 0xA>(u));
+  u = max(u, dpp_u32<0x143, 0xC>(u));
+  return __uint_as_float(u);
 }
 
 // Reduce-scatter of two values over the wave halves: the swap exchanges the
@@ -345,7 +353,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
             const uint32_t* __restrict__ ranges, const float4* __restrict__ ckpt,
             const uint32_t* __restrict__ batch_off, const uint32_t* __restrict__ batch_tile,
             const uint32_t* __restrict__ counters, const float* __restrict__ dL_drgb,
-            const float* __restrict__ dL_dalpha, float* __restrict__ g_pair) {
+            const float* __restrict__ dL_dalpha, float* __restrict__ g_pair, int want_max) {
   __shared__ BatchLds L;
   constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
   __shared__ float part[4][kGradSlots][kSub];
@@ -430,50 +438,41 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
     for (; t >= 0 && (int)list[t] >= j0; --t) {
       const int j = list[t];
       const uint32_t kk = start + (uint32_t)j;
-      float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f, w = 0.f;
-      bool contrib = false;
-      if (kk < plast) {
-        const float4 A = L.a[j], B = L.b[j];
-        const float cbl = L.c[j];
-        const float dx = A.x - fx, dy = A.y - fy;
-        const float power = pair_power(A, B, dx, dy);
-        if (power <= 0.f) {
-          const float G = __expf(power);
-          const float oG = B.y * G;
-          const float alpha = fminf(kAlphaMax, oG);
-          if (alpha >= kAlphaMin) {
-            contrib = true;
-            const float inv1m = 1.f / (1.f - alpha);
-            const float Tb = T * inv1m;  // transmittance in front of this pair
-            w = alpha * Tb;
-            const float dalpha = G0 * (B.z * Tb - S0 * inv1m) + G1 * (B.w * Tb - S1 * inv1m) +
-                                 G2 * (cbl * Tb - S2 * inv1m) + GA * Tfin * inv1m;
-            S0 = fmaf(B.z, w, S0);
-            S1 = fmaf(B.w, w, S1);
-            S2 = fmaf(cbl, w, S2);
-            T = Tb;
-            gr = G0 * w;
-            gg = G1 * w;
-            gbl = G2 * w;
-            if (!(oG > kAlphaMax)) {
-              go = dalpha * G;
-              const float dq = dalpha * (-0.5f * oG);
-              gu = dq * 2.f * (A.z * dx + A.w * dy);
-              gv = dq * 2.f * (A.w * dx + B.x * dy);
-              ga = dq * dx * dx;
-              gb = dq * 2.f * dx * dy;
-              gc = dq * dy * dy;
-            }
-          }
-        }
-      }
+      // branch-free: every lane evaluates the pair, selects keep what counts
+      const float4 A = L.a[j], B = L.b[j];
+      const float cbl = L.c[j];
+      const float dx = A.x - fx, dy = A.y - fy;
+      const float power = pair_power(A, B, dx, dy);
+      const float G = __expf(power);
+      const float oG = B.y * G;
+      const float alpha = fminf(kAlphaMax, oG);
+      const bool contrib = kk < plast && power <= 0.f && alpha >= kAlphaMin;
+      const bool has_grad = contrib && !(oG > kAlphaMax);  // alpha not clamped: it has a gradient
+      const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);
+      const float Tb = T * inv1m;  // transmittance in front of this pair
+      const float wv = alpha * Tb;
+      const float dalpha = G0 * (B.z * Tb - S0 * inv1m) + G1 * (B.w * Tb - S1 * inv1m) +
+                           G2 * (cbl * Tb - S2 * inv1m) + GA * Tfin * inv1m;
+      const float w = contrib ? wv : 0.f;
+      S0 = fmaf(B.z, w, S0);
+      S1 = fmaf(B.w, w, S1);
+      S2 = fmaf(cbl, w, S2);
+      T = contrib ? Tb : T;
+      float gr = G0 * w, gg = G1 * w, gbl = G2 * w;
+      const float dq = has_grad ? dalpha * (-0.5f * oG) : 0.f;
+      float go = has_grad ? dalpha * G : 0.f;
+      float gu = dq * 2.f * (A.z * dx + A.w * dy);
+      float gv = dq * 2.f * (A.w * dx + B.x * dy);
+      float ga = dq * dx * dx;
+      float gb = dq * 2.f * dx * dy;
+      float gc = dq * dy * dy;
       if (__ballot(contrib) == 0ull) continue;
       // eight sums by reduce-scatter: row r of s0 holds slot {u, v, c, o}[r],
       // row r of s1 slot {a, b, r, g}[r]; the ninth sum and the max by DPP
       const float s0 = row_sum16(swap16_add(swap32_add(gu, gc), swap32_add(gv, go)));
       const float s1 = row_sum16(swap16_add(swap32_add(ga, gr), swap32_add(gb, gg)));
       gbl = wave_sum63(gbl);
-      w = wave_max63(w);
+      const float wmax = want_max ? wave_max63(w) : 0.f;
       const int js = j - j0;
       if ((lane & 15) == 0) {
         const int row = lane >> 4, slot = row + 2 * (row >> 1);  // 0, 1, 4, 5
@@ -482,7 +481,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       }
       if (lane == 63) {
         part[wave][8][js] = gbl;
-        part[wave][9][js] = w;
+        part[wave][9][js] = wmax;
       }
     }
     __syncthreads();
@@ -508,10 +507,11 @@ hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* re
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
                             const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
                             uint32_t batch_cap, const uint32_t* counters, const float* dL_drgb,
-                            const float* dL_dalpha, float* g_pair, hipStream_t s) {
+                            const float* dL_dalpha, float* g_pair, bool want_max, hipStream_t s) {
   if (batch_cap == 0) return hipSuccess;
   hipLaunchKernelGGL(k_blend_bwd, dim3(batch_cap), dim3(256), 0, s, views_dev, n_views, records, n_rec, pair_vals,
-                     sel, cap, ranges, ckpt, batch_off, batch_tile, counters, dL_drgb, dL_dalpha, g_pair);
+                     sel, cap, ranges, ckpt, batch_off, batch_tile, counters, dL_drgb, dL_dalpha, g_pair,
+                     want_max ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -114,7 +114,7 @@ hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* re
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
                             const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
                             uint32_t batch_cap, const uint32_t* counters, const float* dL_drgb,
-                            const float* dL_dalpha, float* g_pair, hipStream_t s);
+                            const float* dL_dalpha, float* g_pair, bool want_max, hipStream_t s);
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
                               const uint32_t* offsets, const uint32_t* pos, const float* g_pair,
                               uint32_t pair_capacity, const uint32_t* counters, uint32_t trainable,
