@@ -117,7 +117,7 @@ typedef struct {
  *   pair_vals   uint32[2][P]  sorted record ids; which half holds the result
  *                             is recorded on the device in *sort_sel
  *   sort_sel    uint32[1]
- *   pair_pos    uint32[P]     sorted position of each pair in emission order
+ *   pair_emit   uint32[P]     emission index of each sorted pair
  *   ranges      uint32[X][2]  [start, end) of each tile's pairs
  *   pixel_state float[Q][4]   transmittance left behind the last blended
  *                             splat, then the composited colour before the
@@ -137,7 +137,7 @@ typedef struct {
   uint32_t* offsets;
   uint32_t* pair_vals;
   uint32_t* sort_sel;
-  uint32_t* pair_pos;
+  uint32_t* pair_emit;
   uint32_t* ranges;
   float* pixel_state;
   uint32_t* last;

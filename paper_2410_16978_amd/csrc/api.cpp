@@ -50,6 +50,7 @@ struct PipeBufs {
   SortPlan* plan = nullptr;
   uint32_t* status = nullptr;
   float* g_pair = nullptr;
+  float* g_col = nullptr;    // [R][3] colour gradient of each record (backward)
   // batch only (the single-call path keeps these in the caller's state)
   float* records = nullptr;
   uint32_t* vals = nullptr;
@@ -73,7 +74,10 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.ctl = c.take<SortCtl>(1);
   b.plan = c.take<SortPlan>(1);
   b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
-  if (backward) b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
+  if (backward) {
+    b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
+    b.g_col = c.take<float>(3 * std::max<size_t>(R, 1));
+  }
   if (batch) {
     b.offsets = c.take<uint32_t>(R + 1);
     b.records = c.take<float>(kRecordFloats * std::max<size_t>(R, 1));
@@ -199,7 +203,7 @@ struct StageScope {
 };
 
 bool state_ok(const gsr_fwd_state* st) {
-  return st && st->records && st->offsets && st->pair_vals && st->sort_sel && st->pair_pos && st->ranges &&
+  return st && st->records && st->offsets && st->pair_vals && st->sort_sel && st->pair_emit && st->ranges &&
          st->pixel_state && st->last && st->checkpoints && st->batch_map && st->counters &&
          st->pair_capacity < (1u << 30);
 }
@@ -346,7 +350,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
                         key_bits_for(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, state->sort_sel,
                         state->counters + kCntError, s));
     HIP_TRY(launch_finalize_pairs(state->pair_vals, state->pair_vals + P, state->sort_sel, state->counters, P,
-                                  b.rec_of, state->pair_pos, s));
+                                  b.rec_of, state->pair_emit, s));
   }
   uint32_t* batch_off = state->batch_map;
   uint32_t* batch_tile = state->batch_map + X + 1;
@@ -429,15 +433,15 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
     HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
                              state->ranges, reinterpret_cast<const float4*>(state->checkpoints), state->batch_map,
                              state->batch_map + X + 1, state->batch_capacity, state->counters, dL_drgb, dL_dalpha,
-                             b.g_pair, max_contrib != nullptr, s));
+                             state->pair_emit, b.g_pair, max_contrib != nullptr, s));
   }
   const ModelD md = make_model(*model);
   {
     StageScope sc(timer, GSR_STAGE_PROJECT_BWD, s);
     for (const JobD& j : make_jobs(md, ids))
-      HIP_TRY(launch_project_bwd(j, b.views, state->records, state->offsets, state->pair_pos, b.g_pair, P,
+      HIP_TRY(launch_project_bwd(j, b.views, state->records, state->offsets, b.g_pair, P,
                                  state->counters, trainable_layers, grads->g_mean, grads->g_scale, grads->g_quat,
-                                 grads->g_opacity, grads->g_sh, max_contrib, activity, s));
+                                 grads->g_opacity, grads->g_sh, b.g_col, max_contrib, activity, s));
   }
   return GSR_OK;
 }

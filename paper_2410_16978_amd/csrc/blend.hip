@@ -346,14 +346,17 @@ __device__ __forceinline__ float row_sum16(float v) {
 
 constexpr int kGradSlots = 10;  // u, v, conic a, b, c, opacity, r, g, b, max alpha*T
 
-// g_pair: [P][12] per sorted pair: the 10 slots above, 2 unused.
+// g_pair: [P][12] per pair, at its emission index (pair_emit of its sorted
+// position), so that a Gaussian's partials are contiguous: the 10 slots
+// above, 2 unused.
 __global__ void __launch_bounds__(256)
 k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
             const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
             const uint32_t* __restrict__ ranges, const float4* __restrict__ ckpt,
             const uint32_t* __restrict__ batch_off, const uint32_t* __restrict__ batch_tile,
             const uint32_t* __restrict__ counters, const float* __restrict__ dL_drgb,
-            const float* __restrict__ dL_dalpha, float* __restrict__ g_pair, int want_max) {
+            const float* __restrict__ dL_dalpha, const uint32_t* __restrict__ pair_emit,
+            float* __restrict__ g_pair, int want_max) {
   __shared__ BatchLds L;
   constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
   __shared__ float part[4][kGradSlots][kSub];
@@ -492,7 +495,9 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       o[9] = fmaxf(fmaxf(part[0][9][tid], part[1][9][tid]), fmaxf(part[2][9][tid], part[3][9][tid]));
       o[10] = 0.f;
       o[11] = 0.f;
-      float4* dst = reinterpret_cast<float4*>(g_pair + (size_t)(start + j0 + tid) * 12);
+      uint32_t e = pair_emit[start + j0 + tid];
+      if (e >= cap) e = 0;  // never write out of range (an inconsistent sort shows up as wrong gradients)
+      float4* dst = reinterpret_cast<float4*>(g_pair + (size_t)e * 12);
       dst[0] = make_float4(o[0], o[1], o[2], o[3]);
       dst[1] = make_float4(o[4], o[5], o[6], o[7]);
       dst[2] = make_float4(o[8], o[9], o[10], o[11]);
@@ -507,10 +512,11 @@ hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* re
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
                             const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
                             uint32_t batch_cap, const uint32_t* counters, const float* dL_drgb,
-                            const float* dL_dalpha, float* g_pair, bool want_max, hipStream_t s) {
+                            const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair, bool want_max,
+                            hipStream_t s) {
   if (batch_cap == 0) return hipSuccess;
   hipLaunchKernelGGL(k_blend_bwd, dim3(batch_cap), dim3(256), 0, s, views_dev, n_views, records, n_rec, pair_vals,
-                     sel, cap, ranges, ckpt, batch_off, batch_tile, counters, dL_drgb, dL_dalpha, g_pair,
+                     sel, cap, ranges, ckpt, batch_off, batch_tile, counters, dL_drgb, dL_dalpha, pair_emit, g_pair,
                      want_max ? 1 : 0);
   return hipGetLastError();
 }

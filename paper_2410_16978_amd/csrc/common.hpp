@@ -96,7 +96,7 @@ hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, co
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
                             uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s);
 hipError_t launch_finalize_pairs(uint32_t* vals_a, uint32_t* vals_b, const uint32_t* sel, const uint32_t* counters,
-                                 uint32_t pair_capacity, const uint32_t* rec_of, uint32_t* pos, hipStream_t s);
+                                 uint32_t pair_capacity, const uint32_t* rec_of, uint32_t* emit, hipStream_t s);
 hipError_t launch_tile_batches(const uint32_t* ranges, uint32_t n_tiles, uint32_t batch_capacity,
                                uint32_t* batch_off, uint32_t* batch_tile, uint32_t* counters, hipStream_t s);
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
@@ -114,12 +114,13 @@ hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* re
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
                             const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
                             uint32_t batch_cap, const uint32_t* counters, const float* dL_drgb,
-                            const float* dL_dalpha, float* g_pair, bool want_max, hipStream_t s);
+                            const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair, bool want_max,
+                            hipStream_t s);
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
-                              const uint32_t* offsets, const uint32_t* pos, const float* g_pair,
-                              uint32_t pair_capacity, const uint32_t* counters, uint32_t trainable,
-                              float* g_mean, float* g_scale, float* g_quat, float* g_opacity, float* g_sh,
-                              float* max_contrib, float* activity, hipStream_t s);
+                              const uint32_t* offsets, const float* g_pair, uint32_t pair_capacity,
+                              const uint32_t* counters, uint32_t trainable, float* g_mean, float* g_scale,
+                              float* g_quat, float* g_opacity, float* g_sh, float* g_col, float* max_contrib,
+                              float* activity, hipStream_t s);
 hipError_t launch_batch_status(const uint32_t* req_rec, int n_req, const uint32_t* offsets,
                                uint32_t pair_capacity, uint32_t* counters, int32_t* req_status,
                                hipStream_t s);

@@ -3,22 +3,42 @@
 // covariance J W Sigma W^T J^T, Sigma = R S S^T R^T, the quaternion
 // normalisation, the perspective map of the centre and the SH colour with its
 // view direction, and summed over the views.  Frozen layers (Sec. 3.2) get
-// zero.  Fused: the activity 2|g_mean| + 0.1|g_sh| + 0.1|g_log s| of
-// Sec. 3.2.2 is added to activity[].
+// zero.  Two kernels, so that neither holds the covariance chain and the SH
+// expansion at once: the geometry kernel (which also sums each record's pair
+// partials and leaves its colour gradient behind), then the SH kernel, which
+// adds the view-direction term to the mean and computes the activity
+// 2|g_mean| + 0.1|g_sh| + 0.1|g_log s| of Sec. 3.2.2 into activity[].
 #include "common.hpp"
 #include "sh.hpp"
 
 namespace gsr {
 
-template <int D>
+// Screen-space gradient of record r: the sum of its pairs' partials (stored
+// at their emission indices, so contiguous per record) in emission order, and
+// the largest alpha * T it reached.
+__device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restrict__ offsets,
+                                            const float* __restrict__ g_pair, uint32_t K, float* g, float& wmax) {
+  for (int c = 0; c < 9; ++c) g[c] = 0.f;
+  const uint32_t e1 = min(offsets[r + 1], K);
+  for (uint32_t e = offsets[r]; e < e1; ++e) {
+    const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)e * 12);
+    const float4 x0 = src[0], x1 = src[1], x2 = src[2];
+    g[0] += x0.x; g[1] += x0.y; g[2] += x0.z; g[3] += x0.w;
+    g[4] += x1.x; g[5] += x1.y; g[6] += x1.z; g[7] += x1.w;
+    g[8] += x2.x;
+    wmax = fmaxf(wmax, x2.y);
+  }
+}
+
+// Geometry: opacity, and the centre / covariance chain to mean, scale and
+// quaternion.  The colour gradient of each visible record (zero on clamped
+// channels) is left in g_col[r][3] for the SH kernel.
 __global__ void __launch_bounds__(256)
-k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict__ records,
-              const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pos,
-              const float* __restrict__ g_pair, uint32_t cap, const uint32_t* __restrict__ counters,
-              uint32_t trainable, float* __restrict__ g_mean, float* __restrict__ g_scale,
-              float* __restrict__ g_quat, float* __restrict__ g_opacity, float* __restrict__ g_sh,
-              float* __restrict__ max_contrib, float* __restrict__ activity) {
-  constexpr int NC = (D + 1) * (D + 1);
+k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __restrict__ records,
+                   const uint32_t* __restrict__ offsets, const float* __restrict__ g_pair, uint32_t cap, const uint32_t* __restrict__ counters,
+                   uint32_t trainable, float* __restrict__ g_mean, float* __restrict__ g_scale,
+                   float* __restrict__ g_quat, float* __restrict__ g_opacity, float* __restrict__ g_col,
+                   float* __restrict__ max_contrib) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const ModelD& m = job.m;
   if (i >= m.n) return;
@@ -26,33 +46,13 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
   const uint32_t layer = m.layer[i];
   const bool train = layer < 32u && ((trainable >> layer) & 1u);
   const uint32_t K = min(counters[kCntPairs], cap);
-  // screen-space gradient of each record: sum of its pairs' partials, in
-  // emission order (fixed), and the largest alpha * T it reached
   float wmax = 0.f;
-  auto record_grad = [&](uint32_t r, float* g) {
-    for (int c = 0; c < 9; ++c) g[c] = 0.f;
-    const uint32_t e1 = min(offsets[r + 1], K);
-    for (uint32_t e = offsets[r]; e < e1; ++e) {
-      const uint32_t k = pos[e];
-      if (k >= K) continue;
-      const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)k * 12);
-      const float4 x0 = src[0], x1 = src[1], x2 = src[2];
-      g[0] += x0.x; g[1] += x0.y; g[2] += x0.z; g[3] += x0.w;
-      g[4] += x1.x; g[5] += x1.y; g[6] += x1.z; g[7] += x1.w;
-      g[8] += x2.x;
-      wmax = fmaxf(wmax, x2.y);
-    }
-  };
   float gm[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
-  float gsh[NC * 3];
-#pragma unroll
-  for (int k = 0; k < NC * 3; ++k) gsh[k] = 0.f;
-
   if (!train && max_contrib) {
     float g[9];
     for (int jv = 0; jv < job.n_views; ++jv) {
       const uint32_t r = views[job.view[jv]].rec_off + (uint32_t)i;
-      if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) != 0u) record_grad(r, g);
+      if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) != 0u) record_grad(r, offsets, g_pair, K, g, wmax);
     }
   }
   if (train) {
@@ -82,10 +82,7 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         S[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
-    float sh[NC * 3];
-    bool sh_loaded = false;
     float dM[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-
     for (int jv = 0; jv < job.n_views; ++jv) {
       const ViewD& V = views[job.view[jv]];
       const uint32_t r = V.rec_off + (uint32_t)i;
@@ -93,53 +90,14 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
       if (__float_as_uint(rec[11]) == 0u) continue;  // culled in this view
       const uint32_t clamp_bits = __float_as_uint(rec[10]);
       float g[9];
-      record_grad(r, g);
+      record_grad(r, offsets, g_pair, K, g, wmax);
       go += g[5];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) g_col[(size_t)r * 3 + ch] = ((clamp_bits >> ch) & 1u) ? 0.f : g[6 + ch];
       const float* W = V.R;
       const float tx = W[0] * mx + W[1] * my + W[2] * mz + V.t[0];
       const float ty = W[3] * mx + W[4] * my + W[5] * mz + V.t[1];
       const float tz = W[6] * mx + W[7] * my + W[8] * mz + V.t[2];
-      // ---- colour
-      if (!sh_loaded) {
-#pragma unroll
-        for (int k = 0; k < NC * 3; ++k) sh[k] = m.sh[(size_t)k * n + i];
-        sh_loaded = true;
-      }
-      const float ccx = -(W[0] * V.t[0] + W[3] * V.t[1] + W[6] * V.t[2]);
-      const float ccy = -(W[1] * V.t[0] + W[4] * V.t[1] + W[7] * V.t[2]);
-      const float ccz = -(W[2] * V.t[0] + W[5] * V.t[1] + W[8] * V.t[2]);
-      const float ddx = mx - ccx, ddy = my - ccy, ddz = mz - ccz;
-      const float dl = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
-      const float idl = 1.f / dl;
-      const float dirx = ddx * idl, diry = ddy * idl, dirz = ddz * idl;
-      float Y[16];
-      sh_basis<D>(dirx, diry, dirz, Y);
-      float drgb[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) drgb[ch] = ((clamp_bits >> ch) & 1u) ? 0.f : g[6 + ch];
-      float ddir[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        float c[16];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          c[k] = sh[k * 3 + ch];
-          gsh[k * 3 + ch] += Y[k] * drgb[ch];
-        }
-        if (D > 0) {
-          float gx, gy, gz;
-          sh_dir_grad<D>(dirx, diry, dirz, c, gx, gy, gz);
-          ddir[0] += gx * drgb[ch];
-          ddir[1] += gy * drgb[ch];
-          ddir[2] += gz * drgb[ch];
-        }
-      }
-      if (D > 0) {
-        const float dd = dirx * ddir[0] + diry * ddir[1] + dirz * ddir[2];
-        gm[0] += (ddir[0] - dirx * dd) * idl;
-        gm[1] += (ddir[1] - diry * dd) * idl;
-        gm[2] += (ddir[2] - dirz * dd) * idl;
-      }
       // ---- conic -> 2D covariance (a, b, c)
       const float lim_x = V.guard * fmaxf(V.cx, (float)V.W - V.cx) / V.fx;
       const float lim_y = V.guard * fmaxf(V.cy, (float)V.H - V.cy) / V.fy;
@@ -247,19 +205,6 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
     gq[1] = (dq[1] - qx * qd) * iq;
     gq[2] = (dq[2] - qy * qd) * iq;
     gq[3] = (dq[3] - qz * qd) * iq;
-    if (activity) {
-      float pm = gm[0] * gm[0] + gm[1] * gm[1] + gm[2] * gm[2];
-      float pc = 0.f;
-#pragma unroll
-      for (int k = 0; k < NC * 3; ++k) pc += gsh[k] * gsh[k];
-      float ps = 0.f;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float gl = gs[k] * s[k];
-        ps += gl * gl;
-      }
-      activity[i] += 2.f * sqrtf(pm) + 0.1f * sqrtf(pc) + 0.1f * sqrtf(ps);
-    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) g_mean[(size_t)k * n + i] = gm[k];
@@ -268,31 +213,111 @@ k_project_bwd(JobD job, const ViewD* __restrict__ views, const float* __restrict
 #pragma unroll
   for (int k = 0; k < 4; ++k) g_quat[(size_t)k * n + i] = gq[k];
   g_opacity[i] = go;
-#pragma unroll
-  for (int k = 0; k < NC * 3; ++k) g_sh[(size_t)k * n + i] = gsh[k];
   if (max_contrib) max_contrib[i] = fmaxf(max_contrib[i], wmax);
 }
 
+// Colour: SH coefficients and, through the view direction, the mean; then
+// the activity, which needs the final gradients.
+template <int D>
+__global__ void __launch_bounds__(256)
+k_project_bwd_sh(JobD job, const ViewD* __restrict__ views, const float* __restrict__ records,
+                 uint32_t trainable, const float* __restrict__ g_col, float* __restrict__ g_mean,
+                 const float* __restrict__ g_scale, float* __restrict__ g_sh, float* __restrict__ activity) {
+  constexpr int NC = (D + 1) * (D + 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const ModelD& m = job.m;
+  if (i >= m.n) return;
+  const int n = m.n;
+  const uint32_t layer = m.layer[i];
+  const bool train = layer < 32u && ((trainable >> layer) & 1u);
+  float gsh[NC * 3];
+#pragma unroll
+  for (int k = 0; k < NC * 3; ++k) gsh[k] = 0.f;
+  if (!train) {
+#pragma unroll
+    for (int k = 0; k < NC * 3; ++k) g_sh[(size_t)k * n + i] = 0.f;
+    return;
+  }
+  const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
+  float gm[3] = {0.f, 0.f, 0.f};
+  for (int jv = 0; jv < job.n_views; ++jv) {
+    const ViewD& V = views[job.view[jv]];
+    const uint32_t r = V.rec_off + (uint32_t)i;
+    if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) == 0u) continue;  // culled in this view
+    const float drgb[3] = {g_col[(size_t)r * 3], g_col[(size_t)r * 3 + 1], g_col[(size_t)r * 3 + 2]};
+    const float* W = V.R;
+    const float ccx = -(W[0] * V.t[0] + W[3] * V.t[1] + W[6] * V.t[2]);
+    const float ccy = -(W[1] * V.t[0] + W[4] * V.t[1] + W[7] * V.t[2]);
+    const float ccz = -(W[2] * V.t[0] + W[5] * V.t[1] + W[8] * V.t[2]);
+    const float ddx = mx - ccx, ddy = my - ccy, ddz = mz - ccz;
+    const float dl = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
+    const float idl = 1.f / dl;
+    const float dirx = ddx * idl, diry = ddy * idl, dirz = ddz * idl;
+    float Y[16];
+    sh_basis<D>(dirx, diry, dirz, Y);
+    // d rgb / d dir = sum_k (sum_ch drgb_ch sh_k,ch) grad Y_k: one gradient of
+    // the SH expansion with the drgb-weighted coefficients
+    float e[16];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      e[k] = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        e[k] += m.sh[(size_t)(k * 3 + ch) * n + i] * drgb[ch];
+        gsh[k * 3 + ch] += Y[k] * drgb[ch];
+      }
+    }
+    if (D > 0) {
+      float ddir[3];
+      sh_dir_grad<D>(dirx, diry, dirz, e, ddir[0], ddir[1], ddir[2]);
+      const float dd = dirx * ddir[0] + diry * ddir[1] + dirz * ddir[2];
+      gm[0] += (ddir[0] - dirx * dd) * idl;
+      gm[1] += (ddir[1] - diry * dd) * idl;
+      gm[2] += (ddir[2] - dirz * dd) * idl;
+    }
+  }
+  float pm = 0.f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float v = g_mean[(size_t)k * n + i] + gm[k];
+    g_mean[(size_t)k * n + i] = v;
+    pm += v * v;
+  }
+  float pc = 0.f;
+#pragma unroll
+  for (int k = 0; k < NC * 3; ++k) {
+    g_sh[(size_t)k * n + i] = gsh[k];
+    pc += gsh[k] * gsh[k];
+  }
+  if (activity) {
+    float ps = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float gl = g_scale[(size_t)k * n + i] * m.scale[(size_t)k * n + i];
+      ps += gl * gl;
+    }
+    activity[i] += 2.f * sqrtf(pm) + 0.1f * sqrtf(pc) + 0.1f * sqrtf(ps);
+  }
+}
+
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
-                              const uint32_t* offsets, const uint32_t* pos, const float* g_pair,
-                              uint32_t pair_capacity, const uint32_t* counters, uint32_t trainable,
-                              float* g_mean, float* g_scale, float* g_quat, float* g_opacity, float* g_sh,
-                              float* max_contrib, float* activity, hipStream_t s) {
+                              const uint32_t* offsets, const float* g_pair, uint32_t pair_capacity,
+                              const uint32_t* counters, uint32_t trainable, float* g_mean, float* g_scale,
+                              float* g_quat, float* g_opacity, float* g_sh, float* g_col, float* max_contrib,
+                              float* activity, hipStream_t s) {
   if (job.m.n <= 0) return hipSuccess;
   const dim3 grid(div_up((uint32_t)job.m.n, 256u)), block(256);
+  hipLaunchKernelGGL(k_project_bwd_geom, grid, block, 0, s, job, views_dev, records, offsets, g_pair,
+                     pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_col, max_contrib);
   switch (job.m.D) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
-                               pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
-                               max_contrib, activity); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
-                               pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
-                               max_contrib, activity); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
-                               pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
-                               max_contrib, activity); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, s, job, views_dev, records, offsets, pos, g_pair,
-                                pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_sh,
-                                max_contrib, activity); break;
+    case 0: hipLaunchKernelGGL(k_project_bwd_sh<0>, grid, block, 0, s, job, views_dev, records, trainable, g_col,
+                               g_mean, g_scale, g_sh, activity); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd_sh<1>, grid, block, 0, s, job, views_dev, records, trainable, g_col,
+                               g_mean, g_scale, g_sh, activity); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd_sh<2>, grid, block, 0, s, job, views_dev, records, trainable, g_col,
+                               g_mean, g_scale, g_sh, activity); break;
+    default: hipLaunchKernelGGL(k_project_bwd_sh<3>, grid, block, 0, s, job, views_dev, records, trainable, g_col,
+                                g_mean, g_scale, g_sh, activity); break;
   }
   return hipGetLastError();
 }

@@ -63,7 +63,7 @@ class Model(C.Structure):
 
 class FwdState(C.Structure):
     _fields_ = [("records", C.c_void_p), ("offsets", C.c_void_p), ("pair_vals", C.c_void_p),
-                ("sort_sel", C.c_void_p), ("pair_pos", C.c_void_p), ("ranges", C.c_void_p),
+                ("sort_sel", C.c_void_p), ("pair_emit", C.c_void_p), ("ranges", C.c_void_p),
                 ("pixel_state", C.c_void_p), ("last", C.c_void_p), ("checkpoints", C.c_void_p),
                 ("batch_map", C.c_void_p), ("counters", C.c_void_p), ("pair_capacity", C.c_uint32),
                 ("batch_capacity", C.c_uint32)]
@@ -249,7 +249,7 @@ class ForwardState:
     offsets: torch.Tensor
     pair_vals: torch.Tensor
     sort_sel: torch.Tensor
-    pair_pos: torch.Tensor
+    pair_emit: torch.Tensor
     ranges: torch.Tensor
     pixel_state: torch.Tensor
     last: torch.Tensor
@@ -271,7 +271,7 @@ class ForwardState:
 
     def struct(self):
         return FwdState(self.records.data_ptr(), self.offsets.data_ptr(), self.pair_vals.data_ptr(),
-                        self.sort_sel.data_ptr(), self.pair_pos.data_ptr(), self.ranges.data_ptr(),
+                        self.sort_sel.data_ptr(), self.pair_emit.data_ptr(), self.ranges.data_ptr(),
                         self.pixel_state.data_ptr(), self.last.data_ptr(), self.checkpoints.data_ptr(),
                         self.batch_map.data_ptr(), self.counters.data_ptr(), self.capacity, self.batch_capacity)
 
@@ -303,7 +303,7 @@ def make_state(n, n_views, width, height, capacity, device="cuda", old=None):
         offsets=torch.empty(R + 1, dtype=torch.int32, **kw),
         pair_vals=torch.empty(2 * capacity, dtype=torch.int32, **kw),
         sort_sel=torch.zeros(1, dtype=torch.int32, **kw),
-        pair_pos=torch.empty(capacity, dtype=torch.int32, **kw),
+        pair_emit=torch.empty(capacity, dtype=torch.int32, **kw),
         ranges=torch.empty(2 * max(X, 1), dtype=torch.int32, **kw),
         pixel_state=torch.empty(4 * max(Q, 1), dtype=torch.float32, **kw),
         last=torch.empty(max(Q, 1), dtype=torch.int32, **kw),
