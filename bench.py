@@ -10,9 +10,11 @@ in HBM before timing.  Prints ONE JSON line.
 
 Beside the step throughput it reports the forward render rate (Mpix/s) and
 p50/p99 latencies, a live per-stage timing (HIP events recorded by the
-library on the stream it launches on), the roofline of the dominant kernel
-and, on the host, the CPU oracle timed on one full step of the same
-workload.
+library on the stream it launches on), the roofline of the dominant kernel,
+a layered stereo render (1M Gaussians, two 1832x1920 eyes) and a serving
+trace (two resident models, Poisson requests), each against the plain
+one-request-per-launch path, and, on the host, the CPU oracle timed on one
+full step of the same workload.
 """
 from __future__ import annotations
 
@@ -100,6 +102,94 @@ def run_cpu_baseline(workload, threads):
     return fwd, t1 - t0, t2 - t1
 
 
+def bench_stereo(rz, scenes, torch, frames, warmup):
+    """Layered stereo frames: 1M Gaussians in 5 CT-like shells, SH3, two eyes
+    of 1832x1920, a random 5-bit layer mask and 1-3 clip planes per frame.
+    Both eyes in one launch chain vs the plain path (one launch chain per
+    eye).  Inputs resident in HBM; frame latency from HIP events."""
+    wl = scenes.layered_stereo()
+    model = rz.to_device(wl.scene)
+    cams = wl.cams
+    W, H = cams[0]["width"], cams[0]["height"]
+    rng = np.random.default_rng(1)
+    vstates = [scenes.random_view_state(rng, 5) for _ in range(frames + warmup)]
+    full = scenes.view_state(0x1F)
+    # pair buffers sized for every layer drawn (masks and clips only remove pairs)
+    _, _, st2 = rz.rasterize_forward(model, cams, [full, full])
+    _, _, st1 = rz.rasterize_forward(model, cams[:1], [full])
+    _, _, st1b = rz.rasterize_forward(model, cams[1:], [full])
+    n = int(model["layer"].shape[0])
+    st2 = rz.make_state(n, 2, W, H, int(st2.n_pairs * 1.02) + 4096)
+    st1 = rz.make_state(n, 1, W, H, int(max(st1.n_pairs, st1b.n_pairs) * 1.02) + 4096)
+    out2 = (torch.empty((2, 3, H, W), device="cuda"), torch.empty((2, H, W), device="cuda"))
+    outs = [(torch.empty((1, 3, H, W), device="cuda"), torch.empty((1, H, W), device="cuda")) for _ in range(2)]
+
+    def batched(vs):
+        rz.rasterize_forward(model, cams, [vs, vs], state=st2, sync=False, out=out2)
+
+    def plain(vs):
+        for e in range(2):
+            rz.rasterize_forward(model, cams[e:e + 1], [vs], state=st1, sync=False, out=outs[e])
+
+    res = {}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        for i in range(warmup):
+            fn(vstates[i])
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(frames):
+            fn(vstates[warmup + i])
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(frames)]
+        mean = ev[0].elapsed_time(ev[-1]) / frames
+        res[name] = {"mpix_s": round(2 * W * H / (mean * 1e-3) / 1e6, 1), "ms_per_frame": round(mean, 4),
+                     "p50_ms": round(percentile(ms, 50), 4), "p99_ms": round(percentile(ms, 99), 4)}
+    rz.forward_check(st2)
+    rz.forward_check(st1)
+    return {"workload": wl.name, "frames": frames, "pairs": st2.capacity, **res,
+            "speedup_vs_plain": round(res["plain"]["ms_per_frame"] / res["batched"]["ms_per_frame"], 3)}
+
+
+def bench_serving(rz, scenes, torch, seconds, rate):
+    """Serving: resident models of 500k and 2M Gaussians (5 layers, SH3);
+    open-loop Poisson requests (resolution 512^2, 1024^2 or stereo
+    1832x1920, random layer mask and clip planes).  Continuous batching
+    (arrival-order admission into batched launches on two streams) vs the
+    plain path (one request per launch, one stream) on the same trace, then
+    the same requests all at once (saturation throughput)."""
+    from paper_2410_16978_amd.serve import GpuExecutor, Scheduler, requests_from_trace
+    models = [rz.to_device(m) for m in scenes.serving_models()]
+    trace = scenes.poisson_trace(rate, seconds, seed=0)
+    ex0 = GpuExecutor(models, slots=2)
+    ex0.calibrate(requests_from_trace(trace))
+    table = ex0.pair_table
+    budget = 16 << 30
+    res = {"models": [500_000, 2_000_000], "rate_hz": rate, "trace_s": seconds, "requests": len(trace)}
+    for mode in ("open_loop", "saturation"):
+        for name, batched in (("batched", True), ("plain", False)):
+            reqs = requests_from_trace(trace)
+            if mode == "saturation":
+                for r in reqs:
+                    r.arrival = 0.0
+            ex = GpuExecutor(models, slots=2 if batched else 1, pair_table=table)
+            Scheduler(ex, budget, max_batch=16, batched=batched).run(reqs[:8])  # warm the workspaces
+            reqs = requests_from_trace(trace)
+            if mode == "saturation":
+                for r in reqs:
+                    r.arrival = 0.0
+            torch.cuda.synchronize()
+            stats = Scheduler(ex, budget, max_batch=16, batched=batched).run(reqs)
+            torch.cuda.synchronize()
+            sm = stats.summary()
+            res.setdefault(mode, {})[name] = {k: sm[k] for k in ("p50_ms", "p99_ms", "frames_per_s", "mpix_per_s",
+                                                                  "launches", "reruns")}
+            if any(r.status != 0 for r in reqs):
+                res.setdefault(mode, {})[name]["failed"] = sum(r.status != 0 for r in reqs)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +197,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all host cores, at most 16)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the layered-stereo and serving measurements (profiling runs)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving trace")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -243,6 +336,12 @@ def main():
         "pairs": K0,
         "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
     }
+
+    # ---------------- layered stereo render and serving, each vs the plain path
+    if not args.no_extra:
+        result["stereo_render"] = bench_stereo(rz, scenes, torch, frames=max(10, min(args.steps, 50)),
+                                               warmup=max(2, min(args.warmup, 5)))
+        result["serving"] = bench_serving(rz, scenes, torch, args.serve_seconds, 200.0)
 
     # ---------------- CPU oracle on one step of the same workload
     threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
