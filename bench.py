@@ -242,7 +242,6 @@ def main():
     t_rgb, t_alpha, _ = rz.rasterize_forward(target_model, wl.cams, [scenes.view_state(0xF, bg=(0, 0, 0))])
     bg_rng = np.random.default_rng(123)
     bgs = [tuple(float(x) for x in bg_rng.uniform(0, 1, 3)) for _ in range(args.steps + args.warmup + 1)]
-    bg_t = [torch.tensor(b, device=dev, dtype=torch.float32).view(1, 3, 1, 1) for b in bgs]
     views_per_step = [[scenes.view_state(0xF, bg=b)] for b in bgs]
 
     rctx = ag.RenderContext(sync=True)
@@ -250,8 +249,7 @@ def main():
     def step(i):
         vs = views_per_step[i]
         rgb, alpha = ag.render_params(params, layer, D, wl.cams, vs, rctx)
-        target = t_rgb + (1.0 - t_alpha).unsqueeze(1) * bg_t[i]
-        loss = (rgb - target).abs().mean() + (alpha - t_alpha).abs().mean()
+        loss = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, [bgs[i]])  # fused L1 on RGB and alpha
         loss.backward()
         for p in params.values():
             p.grad = None

@@ -262,7 +262,7 @@ size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const
 
 /* Render a batch of requests over resident models in one pass: one
  * projection per (model, its views), one sort over a shared tile space, one
- * persistent blend launch over every tile of every view.  Never
+ * blend launch over every tile of every view.  Never
  * synchronises.  req_status int32[n_req] (device) receives GSR_OK, or
  * GSR_ENOSPACE for requests whose pairs did not fit into pair_capacity
  * (their images are not written; pairs are assigned in request order, so
@@ -271,6 +271,28 @@ size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const
 gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs,
                             int32_t n_req, uint32_t pair_capacity, void* ws, size_t ws_bytes,
                             int32_t* req_status, gsr_timer* timer, void* stream);
+
+/* L1 loss of alpha-channel training (Sec. 3.2.1) and its gradient.  Per
+ * view v the target colour is the target's premultiplied colour composited
+ * over the view's background bg_v: target = target_rgb + (1 - target_alpha)
+ * bg_v, and L = mean |rgb - target| + mean |alpha - target_alpha| (means over
+ * the n_views x 3 x H x W colour and n_views x H x W alpha values).
+ *   rgb, target_rgb     float[n_views][3][H][W]
+ *   alpha, target_alpha float[n_views][H][W]
+ *   bg_host             host float[n_views][3]; n_views <= 16
+ *   loss                float[1] (NULL: loss not computed)
+ *   g_loss              float[1] incoming gradient of L (NULL: 1)
+ *   dL_drgb, dL_dalpha  overwritten with sign(d) g / N (both NULL: no
+ *                       gradient); d the difference, N the value count
+ *   ws                  gsr_l1_loss_workspace_size bytes; its first 256 bytes
+ *                       must be zero before the first call on it (every
+ *                       call leaves them zero); one call at a time per ws.
+ * The loss is reduced in a fixed order (bitwise reproducible). */
+size_t gsr_l1_loss_workspace_size(int32_t n_views, int32_t width, int32_t height);
+gsr_status gsr_l1_alpha_loss(int32_t n_views, int32_t width, int32_t height, const float* rgb, const float* alpha,
+                             const float* target_rgb, const float* target_alpha, const float* bg_host, void* ws,
+                             size_t ws_bytes, float* loss, const float* g_loss, float* dL_drgb, float* dL_dalpha,
+                             void* stream);
 
 /* Human-readable name of a status. */
 const char* gsr_status_string(gsr_status s);

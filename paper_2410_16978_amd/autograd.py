@@ -70,3 +70,28 @@ def render_params(params, layer, sh_degree, cams, views, rctx=None):
     """Render from raw parameters {mean, log_scale, quat, opacity_logit, sh}."""
     return rasterize(params["mean"], torch.exp(params["log_scale"]), params["quat"],
                      torch.sigmoid(params["opacity_logit"]), params["sh"], layer, sh_degree, cams, views, rctx)
+
+
+class _L1AlphaLossFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rgb, alpha, target_rgb, target_alpha, bgs):
+        loss, _, _ = rz.l1_alpha_loss(rgb, alpha, target_rgb, target_alpha, bgs)
+        ctx.save_for_backward(rgb, alpha, target_rgb, target_alpha)
+        ctx.bgs = bgs
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        rgb, alpha, target_rgb, target_alpha = ctx.saved_tensors
+        _, g_rgb, g_a = rz.l1_alpha_loss(rgb, alpha, target_rgb, target_alpha, ctx.bgs, loss=False, grads=True,
+                                         g_loss=g.reshape(1).contiguous())
+        return g_rgb, g_a, None, None, None
+
+
+def l1_alpha_loss(rgb, alpha, target_rgb, target_alpha, bgs):
+    """mean|rgb - (target_rgb + (1 - target_alpha) bg)| + mean|alpha - target_alpha|
+    (alpha-channel training with a random background, Sec. 3.2.1) on the
+    library's fused kernels; differentiable in rgb and alpha."""
+    return _L1AlphaLossFn.apply(rgb.contiguous(), alpha.contiguous(), target_rgb.contiguous(),
+                                target_alpha.contiguous(), bgs)
+

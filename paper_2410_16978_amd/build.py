@@ -24,6 +24,7 @@ SOURCES = {
     "sort.hip": [],
     "blend.hip": ["-ffp-contract=off"],
     "project_bwd.hip": [],
+    "loss.hip": [],
     "api.cpp": ["-x", "hip"],
 }
 

@@ -1,0 +1,122 @@
+// L1 loss of the alpha-channel training (Sec. 3.2.1) and its gradient.
+//
+// Per view v with background colour bg_v, the target colour is the target's
+// premultiplied colour composited over that background,
+//   target = t_rgb + (1 - t_alpha) bg_v,
+// and L = mean |rgb - target| + mean |alpha - t_alpha| (the means over all
+// V x 3 x H x W colour values and V x H x W alpha values).  The loss is
+// reduced per block and the block sums are added in block order by the last
+// block to finish (deterministic); the gradient is sign(d) g / N per value,
+// g the incoming gradient of L.
+#include "common.hpp"
+
+namespace gsr {
+
+struct LossBg {
+  float bg[kMaxJobViews][3];
+};
+
+__device__ __forceinline__ float l1_block_sum(float v, float* lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w];
+  return s;  // valid in thread 0
+}
+
+__global__ void __launch_bounds__(256)
+k_l1_loss(int n_views, int hw, const float* __restrict__ rgb, const float* __restrict__ alpha,
+          const float* __restrict__ t_rgb, const float* __restrict__ t_alpha, LossBg bg,
+          float* __restrict__ partials, uint32_t* __restrict__ ctl, float* __restrict__ loss) {
+  __shared__ float lds[8];
+  __shared__ bool last;
+  const uint32_t total = (uint32_t)n_views * (uint32_t)hw;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  float sc = 0.f, sa = 0.f;
+  if (i < total) {
+    const uint32_t v = i / (uint32_t)hw, q = i - v * (uint32_t)hw;
+    const size_t b3 = (size_t)v * 3 * hw + q;
+    const float ta = t_alpha[i];
+    const float om = 1.f - ta;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float target = t_rgb[b3 + (size_t)ch * hw] + om * bg.bg[v][ch];
+      sc += fabsf(rgb[b3 + (size_t)ch * hw] - target);
+    }
+    sa = fabsf(alpha[i] - ta);
+  }
+  const float bc = l1_block_sum(sc, lds);
+  __syncthreads();
+  const float ba = l1_block_sum(sa, lds);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = bc;
+    partials[2 * blockIdx.x + 1] = ba;
+    __threadfence();
+    last = atomicAdd(ctl, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // the last block adds the block sums: thread t the blocks t, t + 256, ...
+  // in order, then the threads in a fixed order
+  float c = 0.f, a = 0.f;
+  for (uint32_t b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+    c += __hip_atomic_load(&partials[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a += __hip_atomic_load(&partials[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const float tc = l1_block_sum(c, lds);
+  __syncthreads();
+  const float ta2 = l1_block_sum(a, lds);
+  if (threadIdx.x == 0) {
+    loss[0] = tc / (float)(3 * (size_t)total) + ta2 / (float)total;
+    *ctl = 0u;  // ready for the next call
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_l1_loss_grad(int n_views, int hw, const float* __restrict__ rgb, const float* __restrict__ alpha,
+               const float* __restrict__ t_rgb, const float* __restrict__ t_alpha, LossBg bg,
+               const float* __restrict__ g_loss, float* __restrict__ dL_drgb, float* __restrict__ dL_dalpha) {
+  const uint32_t total = (uint32_t)n_views * (uint32_t)hw;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const float g = g_loss ? g_loss[0] : 1.f;
+  const float kc = g / (float)(3 * (size_t)total), ka = g / (float)total;
+  const uint32_t v = i / (uint32_t)hw, q = i - v * (uint32_t)hw;
+  const size_t b3 = (size_t)v * 3 * hw + q;
+  const float ta = t_alpha[i];
+  const float om = 1.f - ta;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const size_t o = b3 + (size_t)ch * hw;
+    const float d = rgb[o] - (t_rgb[o] + om * bg.bg[v][ch]);
+    dL_drgb[o] = d > 0.f ? kc : (d < 0.f ? -kc : 0.f);
+  }
+  const float d = alpha[i] - ta;
+  dL_dalpha[i] = d > 0.f ? ka : (d < 0.f ? -ka : 0.f);
+}
+
+uint32_t l1_loss_blocks(int n_views, int hw) { return div_up((uint32_t)n_views * (uint32_t)hw, 256u); }
+
+hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
+                          const float* t_alpha, const float* bg_host, float* partials, uint32_t* ctl, float* loss,
+                          const float* g_loss, float* dL_drgb, float* dL_dalpha, hipStream_t s) {
+  LossBg bg;
+  for (int v = 0; v < kMaxJobViews; ++v)
+    for (int ch = 0; ch < 3; ++ch) bg.bg[v][ch] = v < n_views ? bg_host[3 * v + ch] : 0.f;
+  const uint32_t grid = l1_loss_blocks(n_views, hw);
+  if (grid == 0) return hipSuccess;
+  if (loss)
+    hipLaunchKernelGGL(k_l1_loss, dim3(grid), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
+                       partials, ctl, loss);
+  if (dL_drgb && dL_dalpha)
+    hipLaunchKernelGGL(k_l1_loss_grad, dim3(grid), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
+                       g_loss, dL_drgb, dL_dalpha);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -115,6 +115,11 @@ def lib():
     L.gsr_render_batch.restype = C.c_int
     L.gsr_render_batch.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Request), C.c_int32, C.c_uint32,
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gsr_l1_loss_workspace_size.restype = C.c_size_t
+    L.gsr_l1_loss_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    L.gsr_l1_alpha_loss.restype = C.c_int
+    L.gsr_l1_alpha_loss.argtypes = [C.c_int32, C.c_int32, C.c_int32] + [C.c_void_p] * 4 + [
+        C.POINTER(C.c_float), C.c_void_p, C.c_size_t] + [C.c_void_p] * 4 + [C.c_void_p]
     L.gsr_timer_create.restype = C.c_int
     L.gsr_timer_create.argtypes = [C.POINTER(C.c_void_p)]
     L.gsr_timer_destroy.restype = None
@@ -457,3 +462,45 @@ def render_batch(models, requests, capacity, workspace=None, status=None, output
                             workspace.numel(), _ptr(status), _timer(timer), _stream(stream))
     _check(rc, "gsr_render_batch")
     return outputs, status, workspace
+
+
+# ---------------------------------------------------------------- loss
+_loss_ws = {}
+
+
+def _loss_workspace(V, W, H, device, stream):
+    """Workspace of the fused loss per (device, stream, shape); zeroed once (every call leaves its counter zero)."""
+    key = (str(device), int(stream.value or 0), V, W, H)
+    ws = _loss_ws.get(key)
+    if ws is None:
+        n = int(lib().gsr_l1_loss_workspace_size(V, W, H))
+        if n == 0:
+            raise ValueError("bad loss shape (n_views must be 1..16)")
+        ws = torch.zeros(n, dtype=torch.uint8, device=device)
+        _loss_ws[key] = ws
+    return ws
+
+
+def l1_alpha_loss(rgb, alpha, target_rgb, target_alpha, bgs, loss=True, grads=False, g_loss=None, stream=None):
+    """L1 loss of alpha-channel training (Sec. 3.2.1) on the library's fused
+    kernels: target colour = target_rgb + (1 - target_alpha) * bg per view,
+    L = mean|rgb - target| + mean|alpha - target_alpha|.  rgb [V,3,H,W],
+    alpha [V,H,W]; bgs: V background colours.  Returns (loss [1] or None,
+    dL_drgb or None, dL_dalpha or None); g_loss: incoming gradient [1]
+    (None = 1)."""
+    V, _, H, W = rgb.shape
+    for t, shp in ((rgb, (V, 3, H, W)), (target_rgb, (V, 3, H, W)), (alpha, (V, H, W)), (target_alpha, (V, H, W))):
+        if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("l1_alpha_loss: contiguous float32 rgb [V,3,H,W] and alpha [V,H,W] expected")
+    bg = np.ascontiguousarray(np.asarray(bgs, np.float32).reshape(V, 3))
+    s = _stream(stream)
+    ws = _loss_workspace(V, W, H, rgb.device, s)
+    out = torch.empty(1, dtype=torch.float32, device=rgb.device) if loss else None
+    g_rgb = torch.empty_like(rgb) if grads else None
+    g_a = torch.empty_like(alpha) if grads else None
+    rc = lib().gsr_l1_alpha_loss(V, W, H, _ptr(rgb), _ptr(alpha), _ptr(target_rgb), _ptr(target_alpha),
+                                 bg.ctypes.data_as(C.POINTER(C.c_float)), _ptr(ws), ws.numel(), _ptr(out),
+                                 _ptr(g_loss), _ptr(g_rgb), _ptr(g_a), s)
+    _check(rc, "gsr_l1_alpha_loss")
+    return out, g_rgb, g_a
+

@@ -111,12 +111,10 @@ class LayeredTrainer:
         bg = self.rng.uniform(0.0, 1.0, 3)
         cams = [self.cams[i] for i in idx]
         views = [{"layer_mask": 0xFFFFFFFF, "clips": [], "bg": tuple(bg)}] * len(cams)
-        t_rgb = self.targets[0][idx]
-        t_alpha = self.targets[1][idx]
-        bg_t = torch.tensor(bg, device=self.device, dtype=torch.float32).view(1, 3, 1, 1)
+        t_rgb = self.targets[0][idx].contiguous()
+        t_alpha = self.targets[1][idx].contiguous()
         rgb, alpha = ag.render_params(self.params, self.layer, self.sh_degree, cams, views, self.rctx)
-        target = t_rgb + (1.0 - t_alpha).unsqueeze(1) * bg_t
-        loss = (rgb - target).abs().mean() + (alpha - t_alpha).abs().mean()
+        loss = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, [bg] * len(cams))
         self.opt.zero_grad(set_to_none=True)
         loss.backward()
         self.opt.step()

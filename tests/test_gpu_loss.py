@@ -1,0 +1,47 @@
+"""GPU: the fused L1 loss of alpha-channel training (Sec. 3.2.1) equals the
+same loss written with plain torch ops - the loss to float32 summation
+order, the gradients to one rounding of g / N (same sign pattern, zero on
+exact ties) - for one and several views and with an incoming gradient other
+than 1."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("V,H,W", [(1, 800, 800), (3, 57, 93)])
+def test_fused_l1_alpha_loss_matches_torch(V, H, W):
+    import torch
+    from paper_2410_16978_amd import autograd as ag
+    g = torch.Generator(device="cpu").manual_seed(V * 1000 + H)
+    rgb = torch.rand((V, 3, H, W), generator=g).cuda().requires_grad_(True)
+    alpha = torch.rand((V, H, W), generator=g).cuda().requires_grad_(True)
+    t_rgb = (torch.rand((V, 3, H, W), generator=g) * 0.8).cuda()
+    t_alpha = torch.rand((V, H, W), generator=g).cuda()
+    rgb.data[0, 0, 0, :5] = (t_rgb[0, 0, 0, :5] + (1 - t_alpha[0, 0, :5]) * 0.25)  # exact ties: zero gradient
+    bgs = [tuple(float(x) for x in np.random.default_rng(v).uniform(0, 1, 3)) for v in range(V)]
+    bg_t = torch.tensor(bgs, device="cuda", dtype=torch.float32).view(V, 3, 1, 1)
+    bgs[0] = (0.25, bgs[0][1], bgs[0][2])
+    bg_t[0, 0] = 0.25
+    ref = (rgb - (t_rgb + (1.0 - t_alpha).unsqueeze(1) * bg_t)).abs().mean() + (alpha - t_alpha).abs().mean()
+    ref.backward(torch.tensor(2.5, device="cuda"))
+    g_rgb_ref, g_a_ref = rgb.grad.clone(), alpha.grad.clone()
+    rgb.grad = alpha.grad = None
+    loss = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, bgs)
+    loss.backward(torch.tensor(2.5, device="cuda"))
+    torch.cuda.synchronize()
+    assert float(loss) == pytest.approx(float(ref), rel=2e-6)
+    for got, want in ((rgb.grad, g_rgb_ref), (alpha.grad, g_a_ref)):
+        assert torch.equal(torch.sign(got), torch.sign(want))
+        torch.testing.assert_close(got, want, rtol=1.2e-7, atol=0.0)
+    assert int((rgb.grad[0, 0, 0, :5] == 0).sum()) == 5
+    # the reduction is reproducible
+    loss2 = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, bgs)
+    assert float(loss2) == float(loss)
