@@ -49,33 +49,27 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 }
 
 // ---------------------------------------------------------------- histogram
-// Digit histograms of every pass; also clears the look-back words of the
+// Digit histograms of every pass (per-wave LDS counters, merged per block
+// and added to the global counts); also clears the look-back words of the
 // tiles the passes will use.
 __global__ void __launch_bounds__(256)
 k_sort_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counters, uint32_t cap,
             int n_passes, uint32_t* __restrict__ hist, uint32_t* __restrict__ status, uint32_t nb_max) {
-  __shared__ uint32_t lh[kMaxSortPasses * 256];
+  __shared__ uint32_t lh[4][kMaxSortPasses * 256];
   const uint32_t K = min(counters[kCntPairs], cap);
-  for (int i = threadIdx.x; i < n_passes * 256; i += 256) lh[i] = 0;
+  const int wave = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < 4 * kMaxSortPasses * 256; i += 256) (&lh[0][0])[i] = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
   const uint32_t stride = gridDim.x * blockDim.x;
-  // whole-wave rounds so that every lane takes part in the ballots
-  const uint32_t rounds = div_up(K, stride);
-  for (uint32_t rd = 0; rd < rounds; ++rd) {
-    const uint32_t i = rd * stride + blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < K;
-    const uint64_t k = valid ? keys[i] : 0ull;
-    for (int p = 0; p < n_passes; ++p) {
-      const uint32_t d = (uint32_t)(k >> (8 * p)) & 255u;
-      const uint64_t peers = match_digit(d, valid);
-      if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&lh[p * 256 + d], (uint32_t)__popcll(peers));
-    }
-    (void)lane;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += stride) {
+    const uint64_t k = keys[i];
+    for (int p = 0; p < n_passes; ++p) atomicAdd(&lh[wave][p * 256 + ((uint32_t)(k >> (8 * p)) & 255u)], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n_passes * 256; i += 256)
-    if (lh[i]) atomicAdd(&hist[i], lh[i]);
+  for (int i = threadIdx.x; i < n_passes * 256; i += 256) {
+    const uint32_t c = lh[0][i] + lh[1][i] + lh[2][i] + lh[3][i];
+    if (c) atomicAdd(&hist[i], c);
+  }
   // clear the look-back words of the active tiles of every pass
   const uint32_t nb = div_up(K, (uint32_t)kSortTile);
   const size_t per_pass = (size_t)nb * 256;
@@ -267,7 +261,7 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
   const uint32_t nb_max = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile);
   uint32_t* digit_off = hist + kMaxSortPasses * 256;
   uint32_t hist_blocks = div_up(pair_capacity > 0 ? pair_capacity : 1u, 256u * 16u);
-  if (hist_blocks > 2048) hist_blocks = 2048;
+  if (hist_blocks > 128) hist_blocks = 128;  // fewer blocks: fewer global count additions
   hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, s, keys_a, counters, pair_capacity, n_passes,
                      hist, status, nb_max);
   hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(256), 0, s, hist, counters, pair_capacity, n_passes, digit_off,
