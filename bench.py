@@ -190,6 +190,84 @@ def bench_serving(rz, scenes, torch, seconds, rate):
     return res
 
 
+def bench_layered_training(args, torch, rz, ag, scenes):
+    """Layered training at scale: 4M Gaussians in 8 shells (SH3), 8 views of
+    1024^2 per fwd+bwd launch drawn from a pool of 64, layer 7 trainable and
+    layers 0-6 frozen (Sec. 3.2), Adam, inactive pruning every 100 steps
+    (Sec. 3.2.2) - iters/s and the pruned fraction per criterion; and the
+    plain path (8 sequential single-view launches per step) for the same
+    steps."""
+    from paper_2410_16978_amd.train import LayeredTrainer, PruneConfig
+    wl = scenes.layered_training_4m()
+    pool = wl.extra["pool"]
+    tgt = rz.to_device(wl.extra["target_scene"])
+    W, H = pool[0]["width"], pool[0]["height"]
+    t_rgb = torch.empty((len(pool), 3, H, W), device="cuda")
+    t_alpha = torch.empty((len(pool), H, W), device="cuda")
+    for i in range(0, len(pool), 8):
+        r, a, _ = rz.rasterize_forward(tgt, pool[i:i + 8], [scenes.view_state(bg=(0, 0, 0))] * len(pool[i:i + 8]))
+        t_rgb[i:i + 8], t_alpha[i:i + 8] = r, a
+    del tgt
+    trainable = wl.extra["trainable_layers"]
+    # the activity threshold's magnitude is tied to the paper's loss scaling (here every trainable Gaussian
+    # falls below T0 = 0.015): its decisions are counted, the pruning uses the max-contribution criterion
+    tr = LayeredTrainer(wl.scene, pool, (t_rgb, t_alpha), trainable_layers=trainable, views_per_step=8,
+                        prune=PruneConfig(interval=100, use_activity=False), seed=0)
+    n0 = tr.n
+    n_trainable0 = int(((trainable >> tr.layer.to(torch.int64)) & 1).sum())
+    for _ in range(args.warmup):  # sizes the pair buffers (synchronising forwards)
+        tr.step()
+    cap = tr.rctx.state.capacity
+    tr.rctx.state = rz.make_state(tr.n, 8, W, H, int(cap * 1.3) + 4096)
+    tr.rctx.sync = False
+    steps = args.train_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prunes = []
+    for _ in range(steps):
+        out = tr.step()
+        if "prune" in out:
+            prunes.append(out["prune"])
+            tr.rctx.state = rz.make_state(tr.n, 8, W, H, int(cap * 1.3) + 4096)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rz.forward_check(tr.rctx.state)
+    # plain: the same training, one view per launch (8 launches per step)
+    plain_steps = max(5, min(steps // 10, 20))
+    params = {k: v.detach().clone().requires_grad_(True) for k, v in tr.params.items()}
+    opt = torch.optim.Adam([params[k] for k in params], lr=1e-4, eps=1e-15)
+    ctxs = [ag.RenderContext(trainable_layers=trainable) for _ in range(8)]
+    rng = np.random.default_rng(1)
+    for it in range(plain_steps + 2):
+        if it == 2:
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+        idx = rng.choice(len(pool), 8, replace=False)
+        bg = tuple(float(x) for x in rng.uniform(0, 1, 3))
+        opt.zero_grad(set_to_none=True)
+        for v, i in enumerate(idx):
+            rgb, alpha = ag.render_params(params, tr.layer, tr.sh_degree, [pool[i]], [scenes.view_state(bg=bg)],
+                                          ctxs[v])
+            (ag.l1_alpha_loss(rgb, alpha, t_rgb[i:i + 1], t_alpha[i:i + 1], [bg]) / 8.0).backward()
+        opt.step()
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - tp) / plain_steps
+    pr = {"activity_rule_would_prune": [p["activity"] for p in prunes],
+          "max_contrib": sum(p["max_contrib"] for p in prunes), "pruned": sum(p["pruned"] for p in prunes)}
+    return {"metric": "layered training iters/s (8 views of 1024^2 per step), 1 GPU", "value": round(steps / dt, 3),
+            "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "ms_per_step": round(dt / steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "gaussians": n0, "layers": 8, "sh_degree": 3, "views_per_step": 8,
+                       "width": W, "height": H, "trainable_layers": trainable, "prune_interval": 100,
+                       "step": "forward + L1(rgb, alpha) + backward + Adam, random background"},
+            "plain_ms_per_step": round(dt_plain * 1e3, 3),
+            "speedup_vs_plain": round(dt_plain / (dt / steps), 3),
+            "prunes": len(prunes), "pruned": pr,
+            "pruned_fraction_of_trainable": round(pr["pruned"] / max(n_trainable0, 1), 4),
+            "gaussians_after": tr.n}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +278,11 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the layered-stereo and serving measurements (profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving trace")
+    ap.add_argument("--workload", default="training_step_200k",
+                    choices=["training_step_200k", "layered_training_4m"],
+                    help="training_step_200k (default): the 200k/800x800 step; layered_training_4m: 4M Gaussians, "
+                         "8 views of 1024^2 per step, pruning every 100 steps")
+    ap.add_argument("--train-steps", type=int, default=200, help="steps of the layered_training_4m workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -226,6 +309,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+        return
+    if args.workload == "layered_training_4m":
+        print(json.dumps(bench_layered_training(args, torch, rz, ag, scenes)), flush=True)
         return
     wl = scenes.training_step_200k(seed=0)
     sc = wl.scene

@@ -38,6 +38,7 @@ class PruneConfig:
     decay: float = 0.975
     use_max_contrib: bool = True
     min_contrib: float = 1.0 / 255.0
+    use_activity: bool = True  # False: count the activity rule's decisions but prune by max_contrib only
 
 
 class PruneState:
@@ -64,7 +65,7 @@ class PruneState:
         inactive = trainable & (avg <= self.T)
         invisible = trainable & (max_contrib < self.cfg.min_contrib) if self.cfg.use_max_contrib else \
             torch.zeros_like(inactive)
-        keep = ~(inactive | invisible)
+        keep = ~((inactive if self.cfg.use_activity else torch.zeros_like(inactive)) | invisible)
         counts = {"activity": int(inactive.sum()), "max_contrib": int(invisible.sum()),
                   "both": int((inactive & invisible).sum()), "pruned": int((~keep).sum()), "threshold": self.T}
         self.T *= self.cfg.decay
