@@ -284,9 +284,8 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
  *   g_loss              float[1] incoming gradient of L (NULL: 1)
  *   dL_drgb, dL_dalpha  overwritten with sign(d) g / N (both NULL: no
  *                       gradient); d the difference, N the value count
- *   ws                  gsr_l1_loss_workspace_size bytes; its first 256 bytes
- *                       must be zero before the first call on it (every
- *                       call leaves them zero); one call at a time per ws.
+ *   ws                  gsr_l1_loss_workspace_size bytes (block partial
+ *                       sums); one call at a time per ws.
  * The loss is reduced in a fixed order (bitwise reproducible). */
 size_t gsr_l1_loss_workspace_size(int32_t n_views, int32_t width, int32_t height);
 gsr_status gsr_l1_alpha_loss(int32_t n_views, int32_t width, int32_t height, const float* rgb, const float* alpha,

@@ -562,7 +562,7 @@ size_t gsr_l1_loss_workspace_size(int32_t n_views, int32_t width, int32_t height
   if (n_views <= 0 || n_views > kMaxJobViews || width <= 0 || height <= 0) return 0;
   const uint64_t hw = (uint64_t)width * (uint64_t)height;
   if (hw * (uint64_t)n_views >= (1ull << 31)) return 0;
-  return 256 + 8 * (size_t)l1_loss_blocks(n_views, (int)hw);
+  return 8 * (size_t)std::min<uint32_t>(l1_loss_blocks(n_views, (int)hw), 1024u);
 }
 
 gsr_status gsr_l1_alpha_loss(int32_t n_views, int32_t width, int32_t height, const float* rgb, const float* alpha,
@@ -573,10 +573,8 @@ gsr_status gsr_l1_alpha_loss(int32_t n_views, int32_t width, int32_t height, con
   if (need == 0 || !rgb || !alpha || !target_rgb || !target_alpha || !bg_host || !ws) return GSR_EINVAL;
   if ((dL_drgb == nullptr) != (dL_dalpha == nullptr)) return GSR_EINVAL;
   if (ws_bytes < need) return GSR_ENOSPACE;
-  char* base = static_cast<char*>(ws);
   HIP_TRY(launch_l1_loss(n_views, width * height, rgb, alpha, target_rgb, target_alpha, bg_host,
-                         reinterpret_cast<float*>(base + 256), reinterpret_cast<uint32_t*>(base), loss, g_loss,
-                         dL_drgb, dL_dalpha, static_cast<hipStream_t>(stream)));
+                         static_cast<float*>(ws), loss, g_loss, dL_drgb, dL_dalpha, static_cast<hipStream_t>(stream)));
   return GSR_OK;
 }
 

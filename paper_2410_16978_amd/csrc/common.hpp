@@ -112,7 +112,7 @@ hipError_t launch_blend_fwd_tile(const ViewD* views_dev, int n_views, uint32_t t
                                  const int32_t* req_status, float4* ckpt, hipStream_t s);
 uint32_t l1_loss_blocks(int n_views, int hw);
 hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
-                          const float* t_alpha, const float* bg_host, float* partials, uint32_t* ctl, float* loss,
+                          const float* t_alpha, const float* bg_host, float* partials, float* loss,
                           const float* g_loss, float* dL_drgb, float* dL_dalpha, hipStream_t s);
 hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,

@@ -5,9 +5,9 @@
 //   target = t_rgb + (1 - t_alpha) bg_v,
 // and L = mean |rgb - target| + mean |alpha - t_alpha| (the means over all
 // V x 3 x H x W colour values and V x H x W alpha values).  The loss is
-// reduced per block and the block sums are added in block order by the last
-// block to finish (deterministic); the gradient is sign(d) g / N per value,
-// g the incoming gradient of L.
+// reduced per block (grid-stride) and the block sums are added in a fixed
+// order by one block (deterministic); the gradient is sign(d) g / N per
+// value, g the incoming gradient of L.
 #include "common.hpp"
 
 namespace gsr {
@@ -28,16 +28,16 @@ __device__ __forceinline__ float l1_block_sum(float v, float* lds) {
   return s;  // valid in thread 0
 }
 
+constexpr uint32_t kLossBlocks = 1024;  // partial sums (grid-stride)
+
 __global__ void __launch_bounds__(256)
 k_l1_loss(int n_views, int hw, const float* __restrict__ rgb, const float* __restrict__ alpha,
           const float* __restrict__ t_rgb, const float* __restrict__ t_alpha, LossBg bg,
-          float* __restrict__ partials, uint32_t* __restrict__ ctl, float* __restrict__ loss) {
+          float* __restrict__ partials) {
   __shared__ float lds[8];
-  __shared__ bool last;
   const uint32_t total = (uint32_t)n_views * (uint32_t)hw;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   float sc = 0.f, sa = 0.f;
-  if (i < total) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     const uint32_t v = i / (uint32_t)hw, q = i - v * (uint32_t)hw;
     const size_t b3 = (size_t)v * 3 * hw + q;
     const float ta = t_alpha[i];
@@ -47,7 +47,7 @@ k_l1_loss(int n_views, int hw, const float* __restrict__ rgb, const float* __res
       const float target = t_rgb[b3 + (size_t)ch * hw] + om * bg.bg[v][ch];
       sc += fabsf(rgb[b3 + (size_t)ch * hw] - target);
     }
-    sa = fabsf(alpha[i] - ta);
+    sa += fabsf(alpha[i] - ta);
   }
   const float bc = l1_block_sum(sc, lds);
   __syncthreads();
@@ -55,26 +55,22 @@ k_l1_loss(int n_views, int hw, const float* __restrict__ rgb, const float* __res
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = bc;
     partials[2 * blockIdx.x + 1] = ba;
-    __threadfence();
-    last = atomicAdd(ctl, 1u) == gridDim.x - 1;
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // the last block adds the block sums: thread t the blocks t, t + 256, ...
-  // in order, then the threads in a fixed order
+}
+
+// One block: the partial sums in a fixed order.
+__global__ void __launch_bounds__(256)
+k_l1_loss_final(uint32_t n_part, uint32_t total, const float* __restrict__ partials, float* __restrict__ loss) {
+  __shared__ float lds[8];
   float c = 0.f, a = 0.f;
-  for (uint32_t b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-    c += __hip_atomic_load(&partials[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a += __hip_atomic_load(&partials[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t b = threadIdx.x; b < n_part; b += blockDim.x) {
+    c += partials[2 * b];
+    a += partials[2 * b + 1];
   }
   const float tc = l1_block_sum(c, lds);
   __syncthreads();
-  const float ta2 = l1_block_sum(a, lds);
-  if (threadIdx.x == 0) {
-    loss[0] = tc / (float)(3 * (size_t)total) + ta2 / (float)total;
-    *ctl = 0u;  // ready for the next call
-  }
+  const float ta = l1_block_sum(a, lds);
+  if (threadIdx.x == 0) loss[0] = tc / (float)(3 * (size_t)total) + ta / (float)total;
 }
 
 __global__ void __launch_bounds__(256)
@@ -103,18 +99,22 @@ k_l1_loss_grad(int n_views, int hw, const float* __restrict__ rgb, const float* 
 uint32_t l1_loss_blocks(int n_views, int hw) { return div_up((uint32_t)n_views * (uint32_t)hw, 256u); }
 
 hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
-                          const float* t_alpha, const float* bg_host, float* partials, uint32_t* ctl, float* loss,
+                          const float* t_alpha, const float* bg_host, float* partials, float* loss,
                           const float* g_loss, float* dL_drgb, float* dL_dalpha, hipStream_t s) {
   LossBg bg;
   for (int v = 0; v < kMaxJobViews; ++v)
     for (int ch = 0; ch < 3; ++ch) bg.bg[v][ch] = v < n_views ? bg_host[3 * v + ch] : 0.f;
-  const uint32_t grid = l1_loss_blocks(n_views, hw);
-  if (grid == 0) return hipSuccess;
-  if (loss)
-    hipLaunchKernelGGL(k_l1_loss, dim3(grid), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
-                       partials, ctl, loss);
+  const uint32_t blocks = l1_loss_blocks(n_views, hw);
+  if (blocks == 0) return hipSuccess;
+  if (loss) {
+    const uint32_t n_part = min(blocks, kLossBlocks);
+    hipLaunchKernelGGL(k_l1_loss, dim3(n_part), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
+                       partials);
+    hipLaunchKernelGGL(k_l1_loss_final, dim3(1), dim3(256), 0, s, n_part, (uint32_t)n_views * (uint32_t)hw,
+                       partials, loss);
+  }
   if (dL_drgb && dL_dalpha)
-    hipLaunchKernelGGL(k_l1_loss_grad, dim3(grid), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
+    hipLaunchKernelGGL(k_l1_loss_grad, dim3(blocks), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
                        g_loss, dL_drgb, dL_dalpha);
   return hipGetLastError();
 }

@@ -469,14 +469,14 @@ _loss_ws = {}
 
 
 def _loss_workspace(V, W, H, device, stream):
-    """Workspace of the fused loss per (device, stream, shape); zeroed once (every call leaves its counter zero)."""
+    """Workspace of the fused loss (block partial sums) per (device, stream, shape)."""
     key = (str(device), int(stream.value or 0), V, W, H)
     ws = _loss_ws.get(key)
     if ws is None:
         n = int(lib().gsr_l1_loss_workspace_size(V, W, H))
         if n == 0:
             raise ValueError("bad loss shape (n_views must be 1..16)")
-        ws = torch.zeros(n, dtype=torch.uint8, device=device)
+        ws = torch.empty(n, dtype=torch.uint8, device=device)
         _loss_ws[key] = ws
     return ws
 
