@@ -11,8 +11,9 @@ constexpr int kMaxClip = 8;
 constexpr int kRecordFloats = 12;     // 48-byte splat record
 constexpr int kMaxJobViews = 16;      // views projected per attribute read
 constexpr int kMaxSortPasses = 8;     // 64-bit keys, 8-bit digits
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;        // per thread
+constexpr int kSortThreads = 512;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortItems = 8;         // per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kBatch = 256;          // pairs per blend batch (one per thread of a tile block)
 constexpr int kScanThreads = 256;

@@ -126,7 +126,7 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
             uint32_t* __restrict__ status, uint32_t nb_max, uint32_t* __restrict__ pass_ctr,
             uint32_t* __restrict__ err, int pass) {
   __shared__ uint32_t s_bid;
-  __shared__ uint32_t wave_cnt[4][256];
+  __shared__ uint32_t wave_cnt[kSortWaves][256];
   __shared__ uint32_t s_start[256];
   __shared__ uint32_t s_global[256];
   __shared__ uint32_t s_w[4];
@@ -137,7 +137,7 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
   const uint32_t K = min(counters[kCntPairs], cap);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t == 0) s_bid = atomicAdd(&pass_ctr[pass], 1u);
-  for (int i = t; i < 4 * 256; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
+  for (int i = t; i < kSortWaves * 256; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
   __syncthreads();
   const uint32_t bid = s_bid;
   const uint32_t base = bid * (uint32_t)kSortTile;
@@ -175,51 +175,60 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
     rank[r] = pre + (uint32_t)__popcll(before);
   }
   __syncthreads();
-  // thread t owns digit t: per-wave exclusive offsets and the block count
-  const uint32_t c0 = wave_cnt[0][t], c1 = wave_cnt[1][t], c2 = wave_cnt[2][t], c3 = wave_cnt[3][t];
-  const uint32_t cnt = c0 + c1 + c2 + c3;
-  const uint32_t inc = wave_incl_scan(cnt);
-  if (lane == 63) s_w[wave] = inc;
-  // publish this tile's counts before looking back
+  // thread t < 256 owns digit t: per-wave exclusive offsets and the block count
+  uint32_t cw[kSortWaves];
+  uint32_t cnt = 0, inc = 0;
   uint32_t* st = status + ((size_t)pass * nb_max) * 256;
-  if (bid == 0) {
-    __hip_atomic_store(&st[t], kFlagIncl | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t < 256) {
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      cw[w] = wave_cnt[w][t];
+      cnt += cw[w];
+    }
+    inc = wave_incl_scan(cnt);
+    if (lane == 63) s_w[wave] = inc;
+    // publish this tile's counts before looking back
+    if (bid == 0) {
+      __hip_atomic_store(&st[t], kFlagIncl | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
   __syncthreads();
-  {
+  uint32_t excl = 0;
+  if (t < 256) {
     uint32_t off = 0;
     for (int w = 0; w < wave; ++w) off += s_w[w];
     s_start[t] = off + inc - cnt;
-    wave_cnt[0][t] = 0;
-    wave_cnt[1][t] = c0;
-    wave_cnt[2][t] = c0 + c1;
-    wave_cnt[3][t] = c0 + c1 + c2;
-  }
-  uint32_t excl = 0;
-  if (bid > 0) {
-    int j = (int)bid - 1;
-    uint32_t spins = 0;
-    while (j >= 0) {
-      const uint32_t s = __hip_atomic_load(&st[(size_t)j * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t f = s & ~kValueMask;
-      if (f == 0) {
-        if (++spins > kSpinLimit) {
-          atomicOr(err, 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      excl += s & kValueMask;
-      if (f == kFlagIncl) break;
-      --j;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      wave_cnt[w][t] = run;
+      run += cw[w];
     }
-    __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagIncl | (excl + cnt), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    if (bid > 0) {
+      int j = (int)bid - 1;
+      uint32_t spins = 0;
+      while (j >= 0) {
+        const uint32_t sv = __hip_atomic_load(&st[(size_t)j * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t f = sv & ~kValueMask;
+        if (f == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += sv & kValueMask;
+        if (f == kFlagIncl) break;
+        --j;
+      }
+      __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagIncl | (excl + cnt), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_global[t] = digit_off[pass * 256 + t] + excl;
   }
-  s_global[t] = digit_off[pass * 256 + t] + excl;
   __syncthreads();
   // order the tile by digit in LDS (stable), then write digit runs out
 #pragma unroll
