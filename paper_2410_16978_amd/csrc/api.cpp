@@ -33,7 +33,8 @@ struct Carver {
 struct SortCtl {
   uint32_t hist[2 * kMaxSortPasses * 256];
   uint32_t pass_ctr[kMaxSortPasses];
-  uint32_t pad[8];
+  uint32_t scan_ticket;
+  uint32_t pad[7];
 };
 
 struct PipeBufs {
@@ -41,7 +42,7 @@ struct PipeBufs {
   uint32_t* req_rec = nullptr;
   uint32_t* n_tiles = nullptr;
   uint32_t* offsets = nullptr;
-  uint32_t* partials = nullptr;
+  uint64_t* scan_status = nullptr;  // look-back words of the offsets scan
   uint4* tile_box = nullptr;
   uint64_t* keys_a = nullptr;
   uint64_t* keys_b = nullptr;
@@ -66,7 +67,7 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.views = c.take<ViewD>(std::max<size_t>(n_views, 1));
   b.req_rec = c.take<uint32_t>(n_req + 1);
   b.n_tiles = c.take<uint32_t>(std::max<size_t>(R, 1));
-  b.partials = c.take<uint32_t>(div_up((uint32_t)R + 1, (uint32_t)kScanTile) + 1);
+  b.scan_status = c.take<uint64_t>(scan_tiles((uint32_t)R));
   b.tile_box = c.take<uint4>(std::max<size_t>(R, 1));
   b.keys_a = c.take<uint64_t>(std::max<size_t>(P, 1));
   b.keys_b = c.take<uint64_t>(std::max<size_t>(P, 1));
@@ -89,6 +90,24 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
     b.sel = c.take<uint32_t>(1);
   }
   return c.off + kAlign;
+}
+
+// One launch zeroes everything a call expects to start at zero: the sort
+// control block (digit counts, tickets), the pair counters, the tile ranges
+// and the scan's look-back words.
+hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, uint32_t* ranges, size_t X, size_t R,
+                           hipStream_t s) {
+  ClearSet cs{};
+  cs.p[0] = reinterpret_cast<uint32_t*>(b.ctl);
+  cs.n[0] = sizeof(SortCtl) / 4;
+  cs.p[1] = counters;
+  cs.n[1] = 4;
+  cs.p[2] = ranges;
+  cs.n[2] = 2 * X;
+  cs.p[3] = reinterpret_cast<uint32_t*>(b.scan_status);
+  cs.n[3] = 2 * (size_t)scan_tiles((uint32_t)R);
+  cs.n_ranges = 4;
+  return launch_clear_multi(cs, s);
 }
 
 bool model_ok(const gsr_model* m) {
@@ -315,9 +334,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     ids[v] = v;
   }
   HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.ctl), sizeof(SortCtl) / 4, s));
-  HIP_TRY(launch_clear_u32(state->counters, 4, s));
-  HIP_TRY(launch_clear_u32(state->ranges, 2 * X, s));
+  HIP_TRY(clear_workspace(b, state->counters, state->ranges, X, R, s));
   const ModelD md = make_model(*model);
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
@@ -326,7 +343,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   }
   {
     StageScope sc(timer, GSR_STAGE_SCAN, s);
-    HIP_TRY(launch_scan(b.n_tiles, state->offsets, b.partials, R, state->counters, P, s));
+    HIP_TRY(launch_scan(b.n_tiles, state->offsets, b.scan_status, &b.ctl->scan_ticket, R, state->counters, P, s));
   }
   if (n_pairs_host) {
     uint32_t K = 0;
@@ -516,9 +533,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   HIP_TRY(hipMemcpyAsync(b.views, bp.views.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(b.req_rec, bp.req_rec.data(), 4 * (n_req + 1), hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_clear_u32(reinterpret_cast<uint32_t*>(b.ctl), sizeof(SortCtl) / 4, s));
-  HIP_TRY(launch_clear_u32(b.counters, 4, s));
-  HIP_TRY(launch_clear_u32(b.ranges, 2 * bp.X, s));
+  HIP_TRY(clear_workspace(b, b.counters, b.ranges, bp.X, R, s));
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
     for (int m = 0; m < n_models; ++m) {
@@ -533,7 +548,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   {
     StageScope sc(timer, GSR_STAGE_SCAN, s);
-    HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.partials, R, b.counters, P, s));
+    HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.scan_status, &b.ctl->scan_ticket, R, b.counters, P, s));
     HIP_TRY(launch_batch_status(b.req_rec, n_req, b.offsets, P, b.counters, req_status, s));
   }
   {

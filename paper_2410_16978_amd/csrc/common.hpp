@@ -88,10 +88,17 @@ __host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a +
 // Launchers (host side, defined in the .hip files).  All enqueue on `s`.
 namespace gsr {
 
+struct ClearSet {
+  uint32_t* p[4];
+  size_t n[4];
+  int n_ranges;
+};
+hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s);
 hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
                           uint4* tile_box, hipStream_t s);
-hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t* partials, uint32_t n,
+uint32_t scan_tiles(uint32_t n);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint32_t* ticket, uint32_t n,
                        uint32_t* counters, uint32_t pair_capacity, hipStream_t s);
 hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,

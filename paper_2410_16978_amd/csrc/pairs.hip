@@ -35,83 +35,131 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* l
   return wave_off + inc - x;
 }
 
-__global__ void __launch_bounds__(kScanThreads)
-k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ partials) {
-  __shared__ uint32_t lds[4];
-  const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint32_t i = base + k * kScanThreads + threadIdx.x;
-    if (i < n) s += in[i];
-  }
-  uint32_t total;
-  block_exclusive_scan(s, lds, &total);
-  if (threadIdx.x == 0) partials[blockIdx.x] = total;
-}
+// Single pass with decoupled look-back: blocks take their tile index from a
+// ticket (so a block only waits for blocks already running), publish the
+// tile's total, and the first wave looks back over 64 predecessors at a time
+// for the nearest inclusive prefix.  Status words: flag in the top 2 bits,
+// 62-bit value.  The last tile writes the total K and the capacity check to
+// counters.
+constexpr uint64_t kScanAgg = 1ull << 62;
+constexpr uint64_t kScanIncl = 2ull << 62;
+constexpr uint64_t kScanValue = (1ull << 62) - 1;
+constexpr uint32_t kScanSpinLimit = 1u << 22;
 
-// Single block: exclusive scan of the block partials; total K and the
-// capacity check go to counters.
-__global__ void __launch_bounds__(1024)
-k_scan_top(uint32_t* __restrict__ partials, uint32_t nb, uint32_t* __restrict__ counters,
-           uint32_t pair_capacity) {
-  __shared__ uint32_t lds[16];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
+__global__ void __launch_bounds__(kScanThreads)
+k_scan(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out, uint64_t* __restrict__ status,
+       uint32_t* __restrict__ ticket, uint32_t* __restrict__ counters, uint32_t pair_capacity) {
+  __shared__ uint32_t lds[4];
+  __shared__ uint32_t s_bid;
+  __shared__ uint64_t s_excl;
+  if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (uint32_t base = 0; base < nb; base += 1024) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t x = i < nb ? partials[i] : 0u;
-    const uint32_t inc = wave_inclusive_scan(x);
-    if (lane == 63) lds[wave] = inc;
-    __syncthreads();
-    uint32_t off = carry, tot = 0;
-    for (int w = 0; w < 16; ++w) {
-      if (w < wave) off += lds[w];
-      tot += lds[w];
-    }
-    if (i < nb) partials[i] = off + inc - x;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    counters[kCntPairs] = carry;
-    counters[kCntOverflow] = carry > pair_capacity ? 1u : 0u;
-  }
-}
-
-__global__ void __launch_bounds__(kScanThreads)
-k_scan_down(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ partials,
-            uint32_t* __restrict__ out) {
-  __shared__ uint32_t lds[4];
+  const uint32_t bid = s_bid;
+  const uint32_t nb = gridDim.x;
   // thread t owns kScanItems consecutive items
-  const uint32_t base = blockIdx.x * (uint32_t)kScanTile + threadIdx.x * kScanItems;
+  const uint32_t base = bid * (uint32_t)kScanTile + threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
-  uint32_t s = 0;
+  if (base + kScanItems <= n) {
+    const uint4* in4 = reinterpret_cast<const uint4*>(in + base);  // 64-byte aligned run
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < n) ? in[base + k] : 0u;
-    s += v[k];
+    for (int k = 0; k < kScanItems / 4; ++k) {
+      const uint4 q = in4[k];
+      v[4 * k] = q.x;
+      v[4 * k + 1] = q.y;
+      v[4 * k + 2] = q.z;
+      v[4 * k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? in[base + k] : 0u;
   }
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) sum += v[k];
   uint32_t total;
-  uint32_t run = block_exclusive_scan(s, lds, &total) + partials[blockIdx.x];
+  const uint32_t local = block_exclusive_scan(sum, lds, &total);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(&status[bid], (bid == 0 ? kScanIncl : kScanAgg) | total, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    if (bid > 0) {
+      int j = (int)bid - 1;  // window [j - 63, j]
+      uint32_t spins = 0;
+      for (;;) {
+        const int idx = j - lane;
+        const uint64_t sv =
+            idx >= 0 ? __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanIncl;
+        const uint64_t flag = sv & ~kScanValue;
+        const uint64_t ready = __ballot(flag != 0);
+        const uint64_t incl = __ballot(flag == kScanIncl);
+        // lanes up to the first inclusive one, all ready: sum them
+        const int first_incl = incl ? __builtin_ctzll(incl) : 64;
+        const uint64_t need = first_incl < 63 ? ((2ull << first_incl) - 1) : ~0ull;
+        if ((ready & need) != need) {
+          if (++spins > kScanSpinLimit) {
+            if (lane == 0) atomicOr(&counters[kCntError], 16u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        uint64_t x = (lane <= first_incl && idx >= 0) ? (sv & kScanValue) : 0ull;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        excl += x;
+        if (first_incl < 64) break;
+        j -= 64;
+      }
+      if (lane == 0)
+        __hip_atomic_store(&status[bid], kScanIncl | ((excl + total) & kScanValue), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) {
+      s_excl = excl;
+      if (bid == nb - 1) {
+        const uint64_t K = excl + total;
+        counters[kCntPairs] = K > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)K;
+        counters[kCntOverflow] = K > pair_capacity ? 1u : 0u;
+      }
+    }
   }
-  // out[n] = total, written by the block that owns the end
+  __syncthreads();
+  uint32_t run = (uint32_t)s_excl + local;
+  if (base + kScanItems <= n && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+    uint4* out4 = reinterpret_cast<uint4*>(out + base);
+#pragma unroll
+    for (int k = 0; k < kScanItems / 4; ++k) {
+      uint4 q;
+      q.x = run;
+      run += v[4 * k];
+      q.y = run;
+      run += v[4 * k + 1];
+      q.z = run;
+      run += v[4 * k + 2];
+      q.w = run;
+      run += v[4 * k + 3];
+      out4[k] = q;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+  }
+  // out[n] = total, written by the thread that owns the end
   if (base <= n && n < base + kScanItems) out[n] = run;
 }
 
-hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t* partials, uint32_t n,
+uint32_t scan_tiles(uint32_t n) { return div_up(n + 1, (uint32_t)kScanTile); }
+
+// status: scan_tiles(n) zeroed words; ticket: a zeroed counter.
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint32_t* ticket, uint32_t n,
                        uint32_t* counters, uint32_t pair_capacity, hipStream_t s) {
-  const uint32_t nb = div_up(n + 1, (uint32_t)kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, partials);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partials, nb, counters, pair_capacity);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, in, n, partials, out);
+  hipLaunchKernelGGL(k_scan, dim3(scan_tiles(n)), dim3(kScanThreads), 0, s, in, n, out, status, ticket, counters,
+                     pair_capacity);
   return hipGetLastError();
 }
 

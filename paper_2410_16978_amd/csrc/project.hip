@@ -44,6 +44,28 @@ hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Several ranges in one launch (the per-call control words).
+__global__ void __launch_bounds__(256) k_clear_multi(ClearSet cs) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (r >= cs.n_ranges) break;
+    for (; i < cs.n[r]; i += stride) cs.p[r][i] = 0u;
+    i -= cs.n[r];  // continue the grid-stride walk into the next range
+  }
+}
+
+hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s) {
+  size_t total = 0;
+  for (int r = 0; r < cs.n_ranges; ++r) total += cs.n[r];
+  if (total == 0) return hipSuccess;
+  const size_t blocks = total / 256 + 1;
+  const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
+  hipLaunchKernelGGL(k_clear_multi, dim3(grid), dim3(256), 0, s, cs);
+  return hipGetLastError();
+}
+
 // One thread per Gaussian; the Gaussian's attributes are read once and
 // projected for every view of the job (stereo eyes, training views).  SH
 // coefficients are read only if some view keeps the Gaussian.
