@@ -127,10 +127,13 @@ uint32_t tiles_of(const gsr_camera& c) {
   return div_up((uint32_t)c.width, (uint32_t)kTile) * div_up((uint32_t)c.height, (uint32_t)kTile);
 }
 
-int key_bits_for(uint64_t total_tiles) {
+// The global radix passes cover only the tile bits of the keys (bits 32
+// up); the depth bits are sorted per tile segment.
+constexpr int kDepthPasses = 4;
+int tile_pass_end(uint64_t total_tiles) {
   int b = 0;
   while (b < 32 && (1ull << b) < total_tiles) ++b;
-  return 32 + b;
+  return kDepthPasses + (b + 7) / 8;
 }
 
 ViewD make_view(const gsr_camera& c, const gsr_view_state& vs) {
@@ -364,16 +367,17 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
-                        key_bits_for(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, state->sort_sel,
-                        state->counters + kCntError, s));
-    HIP_TRY(launch_finalize_pairs(state->pair_vals, state->pair_vals + P, state->sort_sel, state->counters, P,
-                                  b.rec_of, state->pair_emit, s));
+                        kDepthPasses, tile_pass_end(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan,
+                        state->sort_sel, state->counters + kCntError, s));
+    HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
+    HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->sort_sel,
+                                 state->ranges, (uint32_t)X, b.rec_of, state->counters, P, state->pair_emit,
+                                 debug ? debug->keys_sorted : nullptr, state->counters + kCntError, s));
   }
   uint32_t* batch_off = state->batch_map;
   uint32_t* batch_tile = state->batch_map + X + 1;
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
-    HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
     HIP_TRY(launch_tile_batches(state->ranges, (uint32_t)X, state->batch_capacity, batch_off, batch_tile,
                                 state->counters, s));
   }
@@ -386,12 +390,6 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   if (debug) {
     if (debug->n_tiles) HIP_TRY(hipMemcpyAsync(debug->n_tiles, b.n_tiles, 4ull * R, hipMemcpyDeviceToDevice, s));
     if (debug->tile_box) HIP_TRY(hipMemcpyAsync(debug->tile_box, b.tile_box, 16ull * R, hipMemcpyDeviceToDevice, s));
-    if (debug->keys_sorted) {
-      uint32_t sel = 0;
-      HIP_TRY(hipMemcpyAsync(&sel, state->sort_sel, 4, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      HIP_TRY(hipMemcpyAsync(debug->keys_sorted, sel ? b.keys_b : b.keys_a, 8ull * P, hipMemcpyDeviceToDevice, s));
-    }
     HIP_TRY(hipStreamSynchronize(s));
   }
   return GSR_OK;
@@ -557,13 +555,11 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
-    HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, key_bits_for(bp.X), b.ctl->hist,
-                        b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
-    HIP_TRY(launch_finalize_pairs(b.vals, b.vals + P, b.sel, b.counters, P, b.rec_of, nullptr, s));
-  }
-  {
-    StageScope sc(timer, GSR_STAGE_RANGES, s);
+    HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, kDepthPasses, tile_pass_end(bp.X),
+                        b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
     HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
+    HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, b.vals, b.vals + P, b.sel, b.ranges, (uint32_t)bp.X, b.rec_of,
+                                 b.counters, P, nullptr, nullptr, b.counters + kCntError, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);

@@ -103,14 +103,16 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint
 hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
                             uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s);
-hipError_t launch_finalize_pairs(uint32_t* vals_a, uint32_t* vals_b, const uint32_t* sel, const uint32_t* counters,
-                                 uint32_t pair_capacity, const uint32_t* rec_of, uint32_t* emit, hipStream_t s);
 hipError_t launch_tile_batches(const uint32_t* ranges, uint32_t n_tiles, uint32_t batch_capacity,
                                uint32_t* batch_off, uint32_t* batch_tile, uint32_t* counters, hipStream_t s);
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
-                       const uint32_t* counters, uint32_t pair_capacity, int key_bits, uint32_t* hist,
-                       uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
+                       const uint32_t* counters, uint32_t pair_capacity, int pass_begin, int pass_end,
+                       uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
                        uint32_t* error_flag, hipStream_t s);
+hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
+                                const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
+                                const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,
+                                uint32_t* emit, uint64_t* keys_out, uint32_t* error_flag, hipStream_t s);
 hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,
                          uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles, uint32_t* ranges,
                          hipStream_t s);

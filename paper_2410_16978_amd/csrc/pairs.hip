@@ -204,33 +204,6 @@ hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, co
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- finalize
-// After the sort: the sorted emission indices become record ids, and
-// emit[k] keeps the emission index of sorted pair k.
-__global__ void __launch_bounds__(256)
-k_finalize_pairs(uint32_t* __restrict__ vals_a, uint32_t* __restrict__ vals_b, const uint32_t* __restrict__ sel,
-                 const uint32_t* __restrict__ counters, uint32_t pair_capacity, const uint32_t* __restrict__ rec_of,
-                 uint32_t* __restrict__ emit) {
-  const uint32_t K = min(counters[kCntPairs], pair_capacity);
-  uint32_t* vals = (*sel == 0) ? vals_a : vals_b;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
-    const uint32_t e = vals[k];
-    if (e >= K) continue;  // cannot happen for a consistent sort; never index out of range
-    vals[k] = rec_of[e];
-    if (emit) emit[k] = e;
-  }
-}
-
-hipError_t launch_finalize_pairs(uint32_t* vals_a, uint32_t* vals_b, const uint32_t* sel, const uint32_t* counters,
-                                 uint32_t pair_capacity, const uint32_t* rec_of, uint32_t* emit, hipStream_t s) {
-  if (pair_capacity == 0) return hipSuccess;
-  uint32_t grid = div_up(pair_capacity, 256u);
-  if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(k_finalize_pairs, dim3(grid), dim3(256), 0, s, vals_a, vals_b, sel, counters, pair_capacity,
-                     rec_of, emit);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------- tile batches
 // Each tile's pair list is cut into batches of kBatch pairs.  Single block:
 // first batch of every tile (exclusive scan, X + 1 entries), the tile of every

@@ -6,7 +6,7 @@ import pytest
 
 from paper_2410_16978_amd import scenes
 from tests.gpu_helpers import compare_forward, gpu_forward
-from tests.helpers import make_scene, small_layered_scene
+from tests.helpers import axis_camera, make_scene, small_layered_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +62,26 @@ def test_sh2_large_splats_many_tiles(orc):
     cam = scenes.orbit_camera([0.0, 0.2, -1.0], 150, 130)
     scenes.enforce_distinct_depths(sc, [cam])
     print("large splats:", compare_forward(sc, [cam], [scenes.view_state()], orc, label="large"))
+
+
+def test_crowded_tiles_and_depth_ties(orc):
+    """40k small splats over 9 tiles of a 128x96 image: per-tile segments of
+    about 1k to 22k pairs, so both the in-LDS and the chunked per-tile depth
+    sort run; a third of the splats share one of 9 exact depths, so equal
+    keys must keep emission order."""
+    rng = np.random.default_rng(11)
+    n = 40000
+    z = rng.uniform(1.5, 6.0, n)
+    tied = rng.random(n) < 0.33
+    z[tied] = 1.5 + 0.5 * rng.integers(0, 9, tied.sum())
+    xy = rng.uniform(-0.12, 0.12, (n, 2)) * z[:, None]
+    means = np.column_stack([xy, z])
+    sc = make_scene(means, np.exp(rng.normal(-5.5, 0.3, (n, 3))), quats=rng.standard_normal((n, 4)),
+                    opacity=rng.uniform(0.01, 0.3, n), rgb=rng.uniform(0, 1, (n, 3)))
+    cam = axis_camera(128, 96, f=110.0, cx=70.0, cy=52.0)
+    st = compare_forward(sc, [cam], [scenes.view_state()], orc, label="crowded")
+    print("crowded tiles:", st)
+    assert st["K"] > 3 * 8192
 
 
 def test_tiny_and_odd_images(orc):
