@@ -101,6 +101,12 @@ typedef struct {
   int32_t sh_degree;   /* 0 .. 3 */
   const float *mean, *scale, *quat, *opacity, *sh;
   const uint8_t* layer;
+  int32_t raw;         /* 0: scale and opacity hold activated values.  1: they hold the
+                          training parameters of Sec. 3.2, log-scales and opacity logits;
+                          the kernels apply exp and the logistic function themselves and
+                          the backward's g_scale / g_opacity are with respect to these raw
+                          values. */
+  int32_t reserved;    /* must be 0 */
 } gsr_model;
 
 /* Buffers that carry a forward pass to its backward (device, caller-owned;
@@ -128,10 +134,12 @@ typedef struct {
  *                             colour (r, g, b) the batch adds; written for
  *                             the batches up to the one in which the tile's
  *                             last pixel stops (later ones are never read)
- *   batch_map   uint32[X + 1 + B]  first batch of each tile (exclusive
- *                             scan, X + 1 entries), then the tile of each batch
+ *   batch_map   uint32[X + 1 + B]  X + 1 unused words, then for each
+ *                             checkpoint batch index 1 + its tile (0: none);
+ *                             tile t's batches have the indices
+ *                             floor(ranges[t][0] / 256) + t + c
  *   counters    uint32[4]     device: pairs K, overflow flag, error flag,
- *                             batches */
+ *                             reserved */
 typedef struct {
   float* records;
   uint32_t* offsets;
@@ -192,6 +200,13 @@ gsr_status gsr_timer_read(gsr_timer* t, float* ms /* [GSR_N_STAGES] */, uint32_t
 size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t height,
                           uint32_t pair_capacity);
 
+/* The activated scale float[3][n] and opacity float[n] of a model exactly as
+ * the kernels compute them: for model->raw = 1, exp of the log-scales and
+ * the logistic function of the logits (Sec. 3.2 parameters); for raw = 0 a
+ * copy.  Outputs are device arrays the caller owns.  Returns GSR_EINVAL on
+ * bad arguments; asynchronous on stream. */
+gsr_status gsr_activate(const gsr_model* model, float* scale_out, float* opacity_out, void* stream);
+
 /* Forward render of n_views views of one model, all at the same resolution
  * (cams[v].width/height equal).  cams and views are host arrays of n_views.
  *   rgb   float[V][3][H][W]  colour composited over views[v].bg
@@ -219,7 +234,8 @@ gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host,
 /* Gradients of a loss L given dL/d(rgb) float[V][3][H][W] and dL/d(alpha)
  * float[V][H][W] (either may be NULL = zero), for the forward whose state
  * is passed (same model, cameras and views).  Gradients are with respect
- * to the activated parameters and OVERWRITE grads (same layout as the
+ * to the activated parameters (to the raw ones if model->raw) and
+ * OVERWRITE grads (same layout as the
  * model arrays): g_mean[3][n], g_scale[3][n], g_quat[4][n], g_opacity[n],
  * g_sh[(D+1)^2][3][n].  Gaussians whose layer bit is clear in
  * trainable_layers receive zero (frozen layers, Sec. 3.2).

@@ -1,9 +1,9 @@
 """torch.autograd.Function around the HIP rasterizer.
 
 The forward and the backward are the library's kernels (gsr_rasterize_forward
-/ gsr_rasterize_backward); torch only applies the parameter activations
-(exp of the log-scales, sigmoid of the opacity logits) and their chain rule,
-and holds the buffers.  Frozen layers (the paper's consecutive layer
+/ gsr_rasterize_backward); for the raw training parameters the kernels also
+apply the activations (exp of the log-scales, logistic function of the
+opacity logits) and their chain rule.  torch holds the buffers.  Frozen layers (the paper's consecutive layer
 training, Sec. 3.2) get zero gradient through `trainable_layers`.
 """
 from __future__ import annotations
@@ -33,9 +33,10 @@ class RenderContext:
 
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx):
+    def forward(ctx, mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx, raw):
         model = {"mean": mean.contiguous(), "scale": scale.contiguous(), "quat": quat.contiguous(),
-                 "opacity": opacity.contiguous(), "sh": sh.contiguous(), "layer": layer, "sh_degree": sh_degree}
+                 "opacity": opacity.contiguous(), "sh": sh.contiguous(), "layer": layer, "sh_degree": sh_degree,
+                 "raw": raw}
         rgb, alpha, st = rz.rasterize_forward(model, cams, views, state=rctx.state, sync=rctx.sync, timer=rctx.timer)
         rctx.state = st
         ctx.model = model
@@ -55,7 +56,7 @@ class _RasterizeFn(torch.autograd.Function):
                                   g_rgb.contiguous() if g_rgb is not None else None,
                                   g_alpha.contiguous() if g_alpha is not None else None,
                                   trainable=rctx.trainable_layers, max_contrib=mc, activity=act, timer=rctx.timer)
-        return g["mean"], g["scale"], g["quat"], g["opacity"], g["sh"], None, None, None, None, None
+        return g["mean"], g["scale"], g["quat"], g["opacity"], g["sh"], None, None, None, None, None, None
 
 
 def rasterize(mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx=None):
@@ -63,13 +64,17 @@ def rasterize(mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rct
     Returns rgb [V,3,H,W] and alpha [V,H,W]."""
     if rctx is None:
         rctx = RenderContext()
-    return _RasterizeFn.apply(mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx)
+    return _RasterizeFn.apply(mean, scale, quat, opacity, sh, layer, sh_degree, cams, views, rctx, False)
 
 
 def render_params(params, layer, sh_degree, cams, views, rctx=None):
-    """Render from raw parameters {mean, log_scale, quat, opacity_logit, sh}."""
-    return rasterize(params["mean"], torch.exp(params["log_scale"]), params["quat"],
-                     torch.sigmoid(params["opacity_logit"]), params["sh"], layer, sh_degree, cams, views, rctx)
+    """Render from raw parameters {mean, log_scale, quat, opacity_logit, sh};
+    the kernels apply the activations, and the gradients are with respect to
+    the raw parameters."""
+    if rctx is None:
+        rctx = RenderContext()
+    return _RasterizeFn.apply(params["mean"], params["log_scale"], params["quat"], params["opacity_logit"],
+                              params["sh"], layer, sh_degree, cams, views, rctx, True)
 
 
 class _L1AlphaLossFn(torch.autograd.Function):

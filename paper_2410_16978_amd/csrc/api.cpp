@@ -93,10 +93,10 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
 }
 
 // One launch zeroes everything a call expects to start at zero: the sort
-// control block (digit counts, tickets), the pair counters, the tile ranges
-// and the scan's look-back words.
+// control block (digit counts, tickets), the pair counters, the tile ranges,
+// the scan's look-back words and (forward) the batch-to-tile map.
 hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, uint32_t* ranges, size_t X, size_t R,
-                           hipStream_t s) {
+                           hipStream_t s, uint32_t* batch_tile = nullptr, size_t n_batches = 0) {
   ClearSet cs{};
   cs.p[0] = reinterpret_cast<uint32_t*>(b.ctl);
   cs.n[0] = sizeof(SortCtl) / 4;
@@ -107,11 +107,17 @@ hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, uint32_t* rang
   cs.p[3] = reinterpret_cast<uint32_t*>(b.scan_status);
   cs.n[3] = 2 * (size_t)scan_tiles((uint32_t)R);
   cs.n_ranges = 4;
+  if (batch_tile && n_batches) {
+    cs.p[4] = batch_tile;
+    cs.n[4] = n_batches;
+    cs.n_ranges = 5;
+  }
   return launch_clear_multi(cs, s);
 }
 
 bool model_ok(const gsr_model* m) {
   if (!m || m->n < 0 || m->sh_degree < 0 || m->sh_degree > 3) return false;
+  if ((m->raw != 0 && m->raw != 1) || m->reserved != 0) return false;
   if (m->n > 0 && (!m->mean || !m->scale || !m->quat || !m->opacity || !m->sh || !m->layer)) return false;
   return true;
 }
@@ -160,6 +166,7 @@ ModelD make_model(const gsr_model& m) {
   ModelD d;
   d.n = m.n; d.D = m.sh_degree;
   d.mean = m.mean; d.scale = m.scale; d.quat = m.quat; d.opacity = m.opacity; d.sh = m.sh; d.layer = m.layer;
+  d.raw = m.raw;
   return d;
 }
 
@@ -300,7 +307,8 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
   if (n < 0 || n_views <= 0 || width <= 0 || height <= 0 || pair_capacity >= (1u << 30)) return 0;
   Carver c(nullptr);
   PipeBufs b;
-  return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, 0, 0, true);
+  const size_t X = (size_t)n_views * (size_t)((width + kTile - 1) / kTile) * (size_t)((height + kTile - 1) / kTile);
+  return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, X, 0, true);
 }
 
 gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
@@ -320,7 +328,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   const size_t plane = (size_t)W * H;
   Carver c(ws);
   PipeBufs b;
-  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true) > ws_bytes)
+  if (carve(c, b, n_views, R, P, 0, false, X, 0, true) > ws_bytes)
     return GSR_ENOSPACE;
 
   std::vector<ViewD> hv(n_views);
@@ -337,7 +345,8 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     ids[v] = v;
   }
   HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
-  HIP_TRY(clear_workspace(b, state->counters, state->ranges, X, R, s));
+  HIP_TRY(clear_workspace(b, state->counters, state->ranges, X, R, s, state->batch_map + X + 1,
+                          state->batch_capacity));
   const ModelD md = make_model(*model);
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
@@ -369,22 +378,22 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
                         kDepthPasses, tile_pass_end(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan,
                         state->sort_sel, state->counters + kCntError, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_RANGES, s);
     HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->sort_sel,
                                  state->ranges, (uint32_t)X, b.rec_of, state->counters, P, state->pair_emit,
                                  debug ? debug->keys_sorted : nullptr, state->counters + kCntError, s));
   }
-  uint32_t* batch_off = state->batch_map;
   uint32_t* batch_tile = state->batch_map + X + 1;
-  {
-    StageScope sc(timer, GSR_STAGE_RANGES, s);
-    HIP_TRY(launch_tile_batches(state->ranges, (uint32_t)X, state->batch_capacity, batch_off, batch_tile,
-                                state->counters, s));
-  }
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);
     HIP_TRY(launch_blend_fwd_tile(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals,
-                                  state->sort_sel, P, state->ranges, batch_off, gsr_batch_capacity(P, (uint32_t)X),
+                                  state->sort_sel, P, state->ranges, batch_tile, state->batch_capacity,
                                   nullptr, reinterpret_cast<float4*>(state->checkpoints), s));
   }
   if (debug) {
@@ -427,7 +436,7 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
   const size_t plane = (size_t)W * H;
   Carver c(ws);
   PipeBufs b;
-  if (carve(c, b, n_views, R, P, 0, false, 0, 0, true) > ws_bytes)
+  if (carve(c, b, n_views, R, P, 0, false, X, 0, true) > ws_bytes)
     return GSR_ENOSPACE;
   std::vector<ViewD> hv(n_views);
   std::vector<int> ids(n_views);
@@ -446,8 +455,8 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
   {
     StageScope sc(timer, GSR_STAGE_BLEND_BWD, s);
     HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
-                             state->ranges, reinterpret_cast<const float4*>(state->checkpoints), state->batch_map,
-                             state->batch_map + X + 1, state->batch_capacity, state->counters, dL_drgb, dL_dalpha,
+                             state->ranges, reinterpret_cast<const float4*>(state->checkpoints),
+                             state->batch_map + X + 1, state->batch_capacity, dL_drgb, dL_dalpha,
                              state->pair_emit, b.g_pair, max_contrib != nullptr, s));
   }
   const ModelD md = make_model(*model);
@@ -557,7 +566,13 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
     StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, kDepthPasses, tile_pass_end(bp.X),
                         b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_RANGES, s);
     HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
+  }
+  {
+    StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, b.vals, b.vals + P, b.sel, b.ranges, (uint32_t)bp.X, b.rec_of,
                                  b.counters, P, nullptr, nullptr, b.counters + kCntError, s));
   }
@@ -566,6 +581,12 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
     HIP_TRY(launch_blend_fwd_tile(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
                                   nullptr, 0, req_status, nullptr, s));
   }
+  return GSR_OK;
+}
+
+gsr_status gsr_activate(const gsr_model* model, float* scale_out, float* opacity_out, void* stream) {
+  if (!model_ok(model) || (model->n > 0 && (!scale_out || !opacity_out))) return GSR_EINVAL;
+  HIP_TRY(launch_activate(make_model(*model), scale_out, opacity_out, static_cast<hipStream_t>(stream)));
   return GSR_OK;
 }
 

@@ -6,8 +6,9 @@
 //
 // A tile's depth-sorted pairs are handled in batches of (at most) 256: a
 // batch's records are staged through LDS once and every wave builds the
-// compacted list of the batch's pairs whose reach box (where alpha >= 1/255
-// is possible) meets its pixels, and walks only that list.
+// compacted list of the batch's pairs whose ellipse of possible
+// alpha >= 1/255 (reach box first, then the conic's minimum over the wave's
+// pixel rectangle) meets its pixels, and walks only that list.
 //
 // Forward: one block per tile walks its batches in order (below).
 //
@@ -33,6 +34,7 @@ struct BatchLds {
   float4 b[kBatch];    // conic c, opacity, r, g
   float c[kBatch];     // b
   float4 box[kBatch];  // x0, x1, y0, y1: pixel centres outside cannot reach alpha >= 1/255
+  float4 ell[kBatch];  // q cut-off with margin, -b/c, -b/a (the conic's minimum over a rectangle)
 };
 
 __device__ __forceinline__ int find_view(const ViewD* __restrict__ views, int n_views, uint32_t tile) {
@@ -89,13 +91,44 @@ __device__ __forceinline__ float4 reach_box(const Staged& st) {
   return make_float4(st.a.x - hx, st.a.x + hx, st.a.y - hy, st.a.y + hy);
 }
 
+// The same cut-off for the exact test of wave_list, with wider margins: a
+// relative 1e-2 and 0.05 on q.
+__device__ __forceinline__ float4 reach_conic(const Staged& st) {
+  const float o = st.b.y;
+  const float qo = fminf(kQMax, 2.f * __logf(255.f * o)) * 1.01f + 0.05f;
+  return make_float4(qo, -st.a.w / st.b.x, -st.a.w / st.a.z, 0.f);
+}
+
 __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int tid) {
   if (ok) {
     L.a[tid] = st.a;
     L.b[tid] = st.b;
     L.c[tid] = st.c;
     L.box[tid] = reach_box(st);
+    L.ell[tid] = reach_conic(st);
   }
+}
+
+// q = a dx^2 + 2 b dx dy + c dy^2 at an offset, lowered by a bound on its
+// rounding (a few ulps of the summed term magnitudes).
+__device__ __forceinline__ float conic_low(float a, float b, float c, float dx, float dy) {
+  const float t1 = a * dx * dx, t2 = c * dy * dy, t3 = 2.f * b * dx * dy;
+  return (t1 + t2 + t3) - 4e-6f * (t1 + t2 + fabsf(t3));
+}
+
+// Whether the pair's ellipse {q <= cut-off} meets the rectangle of pixel
+// centres [x0, x1] x [y0, y1]: q is convex, so if the centre lies outside
+// the rectangle its minimum there is on an edge, where it is the clamped
+// one-dimensional minimum.  Anything not finite keeps the pair.
+__device__ __forceinline__ bool conic_meets(const float4 A, float c, const float4 E, float x0, float x1, float y0,
+                                            float y1) {
+  const float mx = A.x, my = A.y, a = A.z, b = A.w;
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
+  float m = conic_low(a, b, c, x0 - mx, fminf(fmaxf(E.y * (x0 - mx), y0 - my), y1 - my));
+  m = fminf(m, conic_low(a, b, c, x1 - mx, fminf(fmaxf(E.y * (x1 - mx), y0 - my), y1 - my)));
+  m = fminf(m, conic_low(a, b, c, fminf(fmaxf(E.z * (y0 - my), x0 - mx), x1 - mx), y0 - my));
+  m = fminf(m, conic_low(a, b, c, fminf(fmaxf(E.z * (y1 - my), x0 - mx), x1 - mx), y1 - my));
+  return !(m > E.x);
 }
 
 // Lane permutation within rows / quads (DPP); lanes a row mask leaves out
@@ -110,11 +143,12 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// The wave's list of the batch's pairs (ascending, j < n) whose reach box
-// meets a pixel centre of its 8 x 8 quadrant [qx0, qx1] x [qy0, qy1]: each
-// lane tests one pair per round, a ballot compacts the hits.  Returns the
-// (wave-uniform) count.  Pairs not in the list cannot reach alpha >= 1/255 on
-// any of the wave's pixels, so skipping them changes nothing.
+// The wave's list of the batch's pairs (ascending, j < n) that can reach a
+// pixel centre of its rectangle [qx0, qx1] x [qy0, qy1]: the reach box
+// first, then the ellipse itself; each lane tests one pair per round, a
+// ballot compacts the hits.  Returns the (wave-uniform) count.  Pairs not in
+// the list cannot reach alpha >= 1/255 on any of the wave's pixels, so
+// skipping them changes nothing.
 __device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n, float qx0, float qx1, float qy0,
                                          float qy1) {
   const int lane = threadIdx.x & 63;
@@ -126,6 +160,7 @@ __device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n
     if (j < n) {
       const float4 bx = L.box[j];
       hit = !((bx.y < qx0) || (bx.x > qx1) || (bx.w < qy0) || (bx.z > qy1));
+      if (hit) hit = conic_meets(L.a[j], L.b[j].x, L.ell[j], qx0, qx1, qy0, qy1);
     }
     const uint64_t m = __ballot(hit);
     if (hit) list[cnt + __popcll(m & lanes_below())] = (uint8_t)j;
@@ -161,8 +196,17 @@ __device__ __forceinline__ float pair_alpha(const float4 B, float power) {
 // pixel has stopped.  Per batch it stores the checkpoint (T entering the
 // batch, colour the batch adds) the backward starts from, at the pixel's
 // index in the backward's 8 x 8-quadrant layout (ckpt may be null: render
-// only, then batch_off is not read).
+// only, then batch_tile is not written).  Tile t's batches have the indices
+// first_batch(t) + c, c = 0, 1, ...: distinct over the tiles and below
+// P / 256 + X + 1 for any pair count P.
 constexpr int kQuadPix = 4;  // sub-tile edge
+
+// Checkpoint batch index of a tile's first batch: floor(start / 256) + t.
+// Since floor((s + n) / 256) + 1 >= floor(s / 256) + ceil(n / 256), tile t + 1
+// starts after tile t's last batch.
+__device__ __forceinline__ uint32_t first_batch(uint32_t tile, uint32_t tile_start) {
+  return tile_start / (uint32_t)kBatch + tile;
+}
 
 __device__ __forceinline__ float quad_shift1(float x, int slot) {  // x of slot - 1, 1 for slot 0
   const float y = dpp<0x90, 0xF>(x);                             // quad_perm [0,0,1,2]
@@ -189,7 +233,7 @@ __device__ __forceinline__ uint32_t quad_max_u32(uint32_t v) {
 __global__ void __launch_bounds__(1024)
 k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles, const float* __restrict__ records,
              uint32_t n_rec, const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
-             const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ batch_off, uint32_t batch_cap,
+             const uint32_t* __restrict__ ranges, uint32_t* __restrict__ batch_tile, uint32_t batch_cap,
              const int32_t* __restrict__ req_status, float4* __restrict__ ckpt) {
   __shared__ BatchLds L;
   __shared__ uint8_t lists[16][kBatch];
@@ -212,7 +256,12 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
   const uint32_t t_end = min(ranges[2 * tile + 1], cap);
   const uint32_t t_start = min(ranges[2 * tile], t_end);
-  const uint32_t b0 = ckpt ? batch_off[tile] : 0u;
+  const uint32_t b0 = first_batch(tile, t_start);
+  if (ckpt) {  // the backward's map from batch index to tile (1 + tile; 0 = no batch)
+    const uint32_t nb = (t_end - t_start + (uint32_t)kBatch - 1) / (uint32_t)kBatch;
+    for (uint32_t c = tid; c < nb; c += 1024)
+      if (b0 + c < batch_cap) batch_tile[b0 + c] = tile + 1u;
+  }
   uint8_t* list = lists[wave];
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = 0;
@@ -279,11 +328,11 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
 
 hipError_t launch_blend_fwd_tile(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
                                  uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
-                                 const uint32_t* ranges, const uint32_t* batch_off, uint32_t batch_cap,
+                                 const uint32_t* ranges, uint32_t* batch_tile, uint32_t batch_cap,
                                  const int32_t* req_status, float4* ckpt, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_blend_tile, dim3(total_tiles), dim3(1024), 0, s, views_dev, n_views, total_tiles, records,
-                     n_rec, pair_vals, sel, cap, ranges, batch_off, batch_cap, req_status, ckpt);
+                     n_rec, pair_vals, sel, cap, ranges, batch_tile, batch_cap, req_status, ckpt);
   return hipGetLastError();
 }
 
@@ -353,8 +402,7 @@ __global__ void __launch_bounds__(256)
 k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
             const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
             const uint32_t* __restrict__ ranges, const float4* __restrict__ ckpt,
-            const uint32_t* __restrict__ batch_off, const uint32_t* __restrict__ batch_tile,
-            const uint32_t* __restrict__ counters, const float* __restrict__ dL_drgb,
+            const uint32_t* __restrict__ batch_tile, const float* __restrict__ dL_drgb,
             const float* __restrict__ dL_dalpha, const uint32_t* __restrict__ pair_emit,
             float* __restrict__ g_pair, int want_max) {
   __shared__ BatchLds L;
@@ -362,9 +410,10 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   __shared__ float part[4][kGradSlots][kSub];
   __shared__ uint8_t lists[4][kBatch];
   const uint32_t bi = blockIdx.x;
-  if (bi >= counters[kCntBatches]) return;
-  const uint32_t tile = batch_tile[bi];
-  const uint32_t c = bi - batch_off[tile];
+  const uint32_t tile_p1 = batch_tile[bi];
+  if (tile_p1 == 0) return;  // no tile's batch
+  const uint32_t tile = tile_p1 - 1u;
+  const uint32_t c = bi - first_batch(tile, ranges[2 * tile]);
   const int vi = find_view(views, n_views, tile);
   const ViewD& V = views[vi];
   const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
@@ -510,13 +559,13 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
 
 hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
-                            const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
-                            uint32_t batch_cap, const uint32_t* counters, const float* dL_drgb,
+                            const float4* ckpt, const uint32_t* batch_tile, uint32_t batch_cap,
+                            const float* dL_drgb,
                             const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair, bool want_max,
                             hipStream_t s) {
   if (batch_cap == 0) return hipSuccess;
   hipLaunchKernelGGL(k_blend_bwd, dim3(batch_cap), dim3(256), 0, s, views_dev, n_views, records, n_rec, pair_vals,
-                     sel, cap, ranges, ckpt, batch_off, batch_tile, counters, dL_drgb, dL_dalpha, pair_emit, g_pair,
+                     sel, cap, ranges, ckpt, batch_tile, dL_drgb, dL_dalpha, pair_emit, g_pair,
                      want_max ? 1 : 0);
   return hipGetLastError();
 }

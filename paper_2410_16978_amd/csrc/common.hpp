@@ -16,6 +16,7 @@ constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortItems = 8;         // per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kBatch = 256;          // pairs per blend batch (one per thread of a tile block)
+constexpr uint32_t kSegWaveMax = 512;  // tiles with more pairs are depth-sorted by a whole block
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -31,7 +32,7 @@ constexpr float kQMax = 11.09375f;    // extent: box of {q <= kQMax}; > 2 ln 255
 constexpr int kCntPairs = 0;
 constexpr int kCntOverflow = 1;
 constexpr int kCntError = 2;
-constexpr int kCntBatches = 3;
+constexpr int kCntReserved = 3;
 
 struct ClipD {
   float n[3];
@@ -62,7 +63,13 @@ struct ModelD {
   int32_t n, D;
   const float *mean, *scale, *quat, *opacity, *sh;
   const uint8_t* layer;
+  int32_t raw;  // scale / opacity hold log-scales / logits
 };
+
+// Parameter activations of raw models: scale = exp(log-scale), opacity =
+// logistic(logit) (Sec. 3.2 training parameters).
+__device__ __forceinline__ float act_scale(float v, int32_t raw) { return raw ? expf(v) : v; }
+__device__ __forceinline__ float act_opacity(float v, int32_t raw) { return raw ? 1.0f / (1.0f + expf(-v)) : v; }
 
 // A model together with the (up to kMaxJobViews) views that render it; the
 // projection reads each Gaussian's attributes once per job.
@@ -82,6 +89,31 @@ struct SortPlan {
 
 __host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
+// Wave64 inclusive scans with DPP: Hillis-Steele within each 16-lane row
+// (row_shr 1, 2, 4, 8), then row_bcast:15 and row_bcast:31 carry row totals
+// into the rows above.  Lanes whose DPP source is outside the row, or whose
+// row is masked off, receive the identity.
+__device__ __forceinline__ uint32_t wave_scan_add(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);
+  return x;
+}
+
+// Bitwise OR over the wave, returned to every lane.
+__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 }  // namespace gsr
 
 // ---------------------------------------------------------------------------
@@ -89,11 +121,12 @@ __host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a +
 namespace gsr {
 
 struct ClearSet {
-  uint32_t* p[4];
-  size_t n[4];
+  uint32_t* p[6];
+  size_t n[6];
   int n_ranges;
 };
 hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s);
+hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out, hipStream_t s);
 hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
                           uint4* tile_box, hipStream_t s);
@@ -103,8 +136,6 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint
 hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
                             uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s);
-hipError_t launch_tile_batches(const uint32_t* ranges, uint32_t n_tiles, uint32_t batch_capacity,
-                               uint32_t* batch_off, uint32_t* batch_tile, uint32_t* counters, hipStream_t s);
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                        const uint32_t* counters, uint32_t pair_capacity, int pass_begin, int pass_end,
                        uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
@@ -118,7 +149,7 @@ hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const u
                          hipStream_t s);
 hipError_t launch_blend_fwd_tile(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
                                  uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
-                                 const uint32_t* ranges, const uint32_t* batch_off, uint32_t batch_cap,
+                                 const uint32_t* ranges, uint32_t* batch_tile, uint32_t batch_cap,
                                  const int32_t* req_status, float4* ckpt, hipStream_t s);
 uint32_t l1_loss_blocks(int n_views, int hw);
 hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
@@ -126,10 +157,9 @@ hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* al
                           const float* g_loss, float* dL_drgb, float* dL_dalpha, hipStream_t s);
 hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
-                            const float4* ckpt, const uint32_t* batch_off, const uint32_t* batch_tile,
-                            uint32_t batch_cap, const uint32_t* counters, const float* dL_drgb,
-                            const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair, bool want_max,
-                            hipStream_t s);
+                            const float4* ckpt, const uint32_t* batch_tile, uint32_t batch_cap,
+                            const float* dL_drgb, const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair,
+                            bool want_max, hipStream_t s);
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
                               const uint32_t* offsets, const float* g_pair, uint32_t pair_capacity,
                               const uint32_t* counters, uint32_t trainable, float* g_mean, float* g_scale,

@@ -7,15 +7,7 @@
 namespace gsr {
 
 // ---------------------------------------------------------------- scan
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  return x;
-}
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) { return wave_scan_add(x); }
 
 // Block-wide exclusive scan of one value per thread (256 threads = 4 waves).
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* lds_waves, uint32_t* total) {
@@ -201,53 +193,6 @@ hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, co
   if (n_rec == 0) return hipSuccess;
   hipLaunchKernelGGL(k_duplicate, dim3(div_up(n_rec, 256u)), dim3(256), 0, s, n_tiles, offsets, tile_box,
                      n_rec, counters, pair_capacity, keys, vals, rec_of);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- tile batches
-// Each tile's pair list is cut into batches of kBatch pairs.  Single block:
-// first batch of every tile (exclusive scan, X + 1 entries), the tile of every
-// batch, and the batch count in counters[kCntBatches].
-__global__ void __launch_bounds__(1024)
-k_tile_batches(const uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t batch_capacity,
-               uint32_t* __restrict__ batch_off, uint32_t* __restrict__ batch_tile, uint32_t* __restrict__ counters) {
-  __shared__ uint32_t lds[16];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (uint32_t base = 0; base < n_tiles; base += 1024) {
-    const uint32_t t = base + threadIdx.x;
-    const uint32_t nb = t < n_tiles ? div_up(ranges[2 * t + 1] - ranges[2 * t], (uint32_t)kBatch) : 0u;
-    const uint32_t inc = wave_inclusive_scan(nb);
-    if (lane == 63) lds[wave] = inc;
-    __syncthreads();
-    uint32_t off = carry, tot = 0;
-    for (int w = 0; w < 16; ++w) {
-      if (w < wave) off += lds[w];
-      tot += lds[w];
-    }
-    const uint32_t first = off + inc - nb;
-    if (t < n_tiles) {
-      batch_off[t] = first;
-      for (uint32_t c = 0; c < nb; ++c)
-        if (first + c < batch_capacity) batch_tile[first + c] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) carry += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    batch_off[n_tiles] = carry;
-    counters[kCntBatches] = min(carry, batch_capacity);
-    if (carry > batch_capacity) atomicOr(&counters[kCntError], 8u);
-  }
-}
-
-hipError_t launch_tile_batches(const uint32_t* ranges, uint32_t n_tiles, uint32_t batch_capacity,
-                               uint32_t* batch_off, uint32_t* batch_tile, uint32_t* counters, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_batches, dim3(1), dim3(1024), 0, s, ranges, n_tiles, batch_capacity, batch_off,
-                     batch_tile, counters);
   return hipGetLastError();
 }
 

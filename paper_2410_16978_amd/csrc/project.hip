@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(256) k_clear_multi(ClearSet cs) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < 6; ++r) {
     if (r >= cs.n_ranges) break;
     for (; i < cs.n[r]; i += stride) cs.p[r][i] = 0u;
     i -= cs.n[r];  // continue the grid-stride walk into the next range
@@ -63,6 +63,22 @@ hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s) {
   const size_t blocks = total / 256 + 1;
   const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
   hipLaunchKernelGGL(k_clear_multi, dim3(grid), dim3(256), 0, s, cs);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_activate(ModelD m, float* __restrict__ scale_out,
+                                                  float* __restrict__ opacity_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.n) return;
+  const int n = m.n;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) scale_out[(size_t)k * n + i] = act_scale(m.scale[(size_t)k * n + i], m.raw);
+  opacity_out[i] = act_opacity(m.opacity[i], m.raw);
+}
+
+hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out, hipStream_t s) {
+  if (m.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_activate, dim3(div_up((uint32_t)m.n, 256u)), dim3(256), 0, s, m, scale_out, opacity_out);
   return hipGetLastError();
 }
 
@@ -80,7 +96,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
   const int n = m.n;
   const uint32_t layer = m.layer[i];
   const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
-  const float op = m.opacity[i];
+  const float op = act_opacity(m.opacity[i], m.raw);
   float sh[NC * 3];
   bool sh_loaded = false;
   float Rq[9];
@@ -125,7 +141,8 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       }
       if (!(qn > 0.f)) break;
       // Sigma = M M^T, M = Rq diag(s)
-      const float s0 = m.scale[i], s1 = m.scale[n + i], s2 = m.scale[2 * n + i];
+      const float s0 = act_scale(m.scale[i], m.raw), s1 = act_scale(m.scale[n + i], m.raw),
+                  s2 = act_scale(m.scale[2 * n + i], m.raw);
       float M[9];
 #pragma unroll
       for (int rr = 0; rr < 3; ++rr) {

@@ -57,7 +57,8 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
   }
   if (train) {
     const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
-    const float s[3] = {m.scale[i], m.scale[n + i], m.scale[2 * n + i]};
+    const float s[3] = {act_scale(m.scale[i], m.raw), act_scale(m.scale[n + i], m.raw),
+                        act_scale(m.scale[2 * n + i], m.raw)};
     float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
     const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
     const float iq = qn > 0.f ? 1.f / qn : 0.f;
@@ -205,6 +206,12 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
     gq[1] = (dq[1] - qx * qd) * iq;
     gq[2] = (dq[2] - qy * qd) * iq;
     gq[3] = (dq[3] - qz * qd) * iq;
+    if (m.raw) {  // chain rule of the activations: d exp = exp, d logistic = o (1 - o)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gs[k] *= s[k];
+      const float o = act_opacity(m.opacity[i], 1);
+      go *= o * (1.0f - o);
+    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) g_mean[(size_t)k * n + i] = gm[k];
@@ -293,7 +300,7 @@ k_project_bwd_sh(JobD job, const ViewD* __restrict__ views, const float* __restr
     float ps = 0.f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float gl = g_scale[(size_t)k * n + i] * m.scale[(size_t)k * n + i];
+      const float gl = m.raw ? g_scale[(size_t)k * n + i] : g_scale[(size_t)k * n + i] * m.scale[(size_t)k * n + i];
       ps += gl * gl;
     }
     activity[i] += 2.f * sqrtf(pm) + 0.1f * sqrtf(pc) + 0.1f * sqrtf(ps);

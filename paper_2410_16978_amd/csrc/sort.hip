@@ -22,6 +22,8 @@
 // error instead of spinning forever.
 #include "common.hpp"
 
+#include <algorithm>
+
 namespace gsr {
 
 constexpr uint32_t kFlagAgg = 1u << 30;
@@ -34,27 +36,24 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Lanes of the wave whose valid 8-bit digit equals this lane's.
+// Lanes of the wave whose valid 8-bit digit equals this lane's.  Per bit b:
+// s = all ones if this lane's bit is set, and the lanes that agree with it
+// are ~(ballot ^ s); each half of the 64-lane mask is narrowed with one
+// three-input bit operation (truth table 0x82: acc & ~(bal ^ s)).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
-  uint64_t peers = __ballot(valid);
+  const uint64_t vb = __ballot(valid);
+  uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bal = __ballot(bit);
-    peers &= bit ? bal : ~bal;
+    const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)d, (unsigned)b, 1u);
+    const uint64_t bal = __ballot(s != 0u);
+    lo = __builtin_amdgcn_bitop3_b32((uint32_t)bal, s, lo, 0x82);
+    hi = __builtin_amdgcn_bitop3_b32((uint32_t)(bal >> 32), s, hi, 0x82);
   }
-  return peers;
+  return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  return x;
-}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) { return wave_scan_add(x); }
 
 // ---------------------------------------------------------------- histogram
 // Digit histograms of every pass (per-wave LDS counters, merged per block
@@ -294,32 +293,57 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
 }
 
 // ---------------------------------------------------------------- per-tile depth sort
-constexpr int kSegThreads = 1024;
-constexpr int kSegWaves = kSegThreads / 64;
-constexpr int kSegItems = 8;                       // per thread and chunk
-constexpr int kSegCap = kSegThreads * kSegItems;   // segments up to this size stay in LDS
+constexpr int kSegItems = 8;  // keys per thread and chunk
 
+// A sorting group is either one wave (THREADS == 64, one of several
+// independent groups of a block) or the whole block.
+template <int THREADS>
+__device__ __forceinline__ void seg_sync() {
+  if constexpr (THREADS == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+template <int THREADS>
+__device__ __forceinline__ int seg_tid() {
+  return THREADS == 64 ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
+}
+
+// Sorting groups: one wave for segments up to 512 pairs (most tiles), a
+// 1024-thread block above that; segments beyond 8192 pairs are sorted chunk
+// by chunk through global memory.
+template <int THREADS, bool CHUNKED>
 struct SegLds {
-  uint32_t key[kSegCap];              // depth bits of the chunk, in digit order after a pass
-  uint32_t val[kSegCap];              // emission indices
-  uint16_t wave_cnt[kSegWaves][256];  // per-wave digit counts, then per-wave digit offsets
+  static constexpr int kWaves = THREADS / 64;
+  static constexpr int kCap = THREADS * kSegItems;
+  uint32_t key[kCap];                 // depth bits, in digit order after a pass
+  uint32_t val[kCap];                 // emission indices
+  uint32_t rec[kCap];                 // record ids
+  uint16_t wave_cnt[2][kWaves][256];  // per-wave digit counts, then offsets; alternate buffers by pass
   uint32_t start[256];                // first chunk position of every digit
-  uint32_t run[256];                  // segment position of the next key of every digit
-  uint32_t base[4][256];              // segment histograms, then exclusive offsets (large segments)
-  uint32_t wsum[kSegWaves];
-  uint32_t red[2][kSegWaves];
+  uint32_t wsum[kWaves];
+  uint32_t run[CHUNKED ? 256 : 1];      // segment position of the next key of every digit
+  uint32_t base[CHUNKED ? 4 : 1][CHUNKED ? 256 : 1];  // segment histograms, then exclusive offsets
 };
 
 // Chunk positions of this thread's items when the chunk is stably ordered by
 // the digit at `shift`.  Items: thread (wave, lane) holds chunk entries
-// wave * I * 64 + r * 64 + lane, r < I, valid below n.  Leaves the chunk's
-// digit starts in L.start and, for thread t < 256, returns the count of
-// digit t.
-__device__ __forceinline__ uint32_t seg_rank(SegLds& L, const uint32_t (&key)[kSegItems], int I, uint32_t n,
-                                             int shift, uint32_t (&pos)[kSegItems]) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int i = t; i < kSegWaves * 256; i += kSegThreads) (&L.wave_cnt[0][0])[i] = 0;
-  __syncthreads();
+// wave * I * 64 + r * 64 + lane, r < I, valid below n.  Counts in
+// L.wave_cnt[buf], which must be zero on entry; clears the other buffer for
+// the next call.  Leaves the chunk's digit starts in L.start; with 256
+// threads or more, thread t < 256 gets the count of digit t back.
+template <int THREADS, bool CHUNKED>
+__device__ __forceinline__ uint32_t seg_rank(SegLds<THREADS, CHUNKED>& L, const uint32_t (&key)[kSegItems], int I,
+                                             uint32_t n, int shift, int buf, uint32_t (&pos)[kSegItems]) {
+  constexpr int W = THREADS / 64;
+  constexpr int DPT = THREADS >= 256 ? 1 : 256 / THREADS;  // digits owned per thread
+  constexpr int OWNERS = 256 / DPT;
+  const int t = seg_tid<THREADS>(), lane = t & 63, wave = t >> 6;
+  uint16_t(&cnt_w)[W][256] = L.wave_cnt[buf];
+  for (int i = t; i < W * 256; i += THREADS) (&L.wave_cnt[buf ^ 1][0][0])[i] = 0;
   uint32_t rank[kSegItems];
 #pragma unroll
   for (int r = 0; r < kSegItems; ++r) {
@@ -330,127 +354,150 @@ __device__ __forceinline__ uint32_t seg_rank(SegLds& L, const uint32_t (&key)[kS
     const uint64_t peers = match_digit(d, valid);
     const uint64_t before = peers & lanemask_lt();
     uint32_t pre = 0;
-    if (valid) pre = L.wave_cnt[wave][d];
+    if (valid) pre = cnt_w[wave][d];
     __builtin_amdgcn_wave_barrier();
-    if (valid && before == 0) L.wave_cnt[wave][d] = (uint16_t)(pre + (uint32_t)__popcll(peers));
+    if (valid && before == 0) cnt_w[wave][d] = (uint16_t)(pre + (uint32_t)__popcll(peers));
     __builtin_amdgcn_wave_barrier();
     rank[r] = pre + (uint32_t)__popcll(before);
   }
-  __syncthreads();
-  uint32_t cnt = 0, inc = 0;
-  if (t < 256) {
-    uint32_t cw[kSegWaves];
+  seg_sync<THREADS>();
+  // owner threads: digits [t * DPT, t * DPT + DPT), block order digit-major
+  uint32_t dcnt[DPT];
+  uint32_t own = 0, inc = 0;
+  if (t < OWNERS) {
 #pragma unroll
-    for (int w = 0; w < kSegWaves; ++w) {
-      cw[w] = L.wave_cnt[w][t];
-      cnt += cw[w];
+    for (int j = 0; j < DPT; ++j) {
+      const int d = t * DPT + j;
+      uint32_t run = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint32_t c = cnt_w[w][d];
+        cnt_w[w][d] = (uint16_t)run;
+        run += c;
+      }
+      dcnt[j] = run;
+      own += run;
     }
-    inc = wave_incl_scan(cnt);
-    if (lane == 63) L.wsum[wave] = inc;
-    uint32_t run = 0;
+    inc = wave_incl_scan(own);
+    if (OWNERS > 64 && lane == 63) L.wsum[wave] = inc;
+  }
+  if (OWNERS > 64) seg_sync<THREADS>();
+  if (t < OWNERS) {
+    uint32_t off = inc - own;
+    if (OWNERS > 64)
+      for (int w = 0; w < wave; ++w) off += L.wsum[w];
 #pragma unroll
-    for (int w = 0; w < kSegWaves; ++w) {
-      L.wave_cnt[w][t] = (uint16_t)run;
-      run += cw[w];
+    for (int j = 0; j < DPT; ++j) {
+      L.start[t * DPT + j] = off;
+      off += dcnt[j];
     }
   }
-  __syncthreads();
-  if (t < 256) {
-    uint32_t off = 0;
-    for (int w = 0; w < wave; ++w) off += L.wsum[w];
-    L.start[t] = off + inc - cnt;
-  }
-  __syncthreads();
+  seg_sync<THREADS>();
 #pragma unroll
   for (int r = 0; r < kSegItems; ++r) {
     if (r >= I) break;
     const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
     const uint32_t d = (key[r] >> shift) & 255u;
-    pos[r] = idx < n ? L.start[d] + L.wave_cnt[wave][d] + rank[r] : 0u;
+    pos[r] = idx < n ? L.start[d] + cnt_w[wave][d] + rank[r] : 0u;
   }
-  return cnt;
+  return (DPT == 1 && t < OWNERS) ? dcnt[0] : 0u;
 }
 
-// Bitwise OR and AND of every thread's value over the block.
-__device__ __forceinline__ uint32_t seg_varying_bits(SegLds& L, uint32_t lor, uint32_t land) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    lor |= __shfl_xor(lor, off, 64);
-    land &= __shfl_xor(land, off, 64);
-  }
-  if (lane == 0) {
-    L.red[0][wave] = lor;
-    L.red[1][wave] = land;
-  }
+// OR of every thread's value over the block (the bits in which some key
+// differs from the reference key).
+template <int THREADS, bool CHUNKED>
+__device__ __forceinline__ uint32_t seg_block_or(SegLds<THREADS, CHUNKED>& L, uint32_t x) {
+  constexpr int W = THREADS / 64;
+  const int t = seg_tid<THREADS>(), wave = t >> 6;
+  x = wave_or(x);
+  if (W == 1) return x;
+  if ((t & 63) == 0) L.wsum[wave] = x;
   __syncthreads();
-  uint32_t o = 0, a = ~0u;
+  uint32_t o = 0;
 #pragma unroll
-  for (int w = 0; w < kSegWaves; ++w) {
-    o |= L.red[0][w];
-    a &= L.red[1][w];
-  }
-  return o ^ a;
+  for (int w = 0; w < W; ++w) o |= L.wsum[w];
+  __syncthreads();  // wsum is reused by the passes
+  return o;
 }
 
-// One block per screen tile; the tile's pairs [ranges[2t], ranges[2t+1])
-// are already grouped by tile in emission order.  Sorts them by depth bits
-// (stable) and writes vals[k] = record id, emit[k] = emission index (if
-// emit), keys_out[k] = full key (if keys_out).  The keys buffer of the
-// other ping-pong side is scratch for segments larger than kSegCap.
-__global__ void __launch_bounds__(kSegThreads)
-k_sort_segments(uint64_t* __restrict__ keys_a, uint64_t* __restrict__ keys_b, uint32_t* __restrict__ vals_a,
-                uint32_t* __restrict__ vals_b, const uint32_t* __restrict__ sel, const uint32_t* __restrict__ ranges,
-                const uint32_t* __restrict__ rec_of, const uint32_t* __restrict__ counters, uint32_t cap,
-                uint32_t* __restrict__ emit, uint64_t* __restrict__ keys_out, uint32_t* __restrict__ err) {
-  __shared__ SegLds L;
-  const uint32_t tile = blockIdx.x;
-  const uint32_t s0 = ranges[2 * tile], s1 = ranges[2 * tile + 1];
-  if (s1 <= s0) return;
-  const uint32_t K = min(counters[kCntPairs], cap);
-  if (s1 > K) {
-    if (threadIdx.x == 0) atomicOr(err, 32u);
-    return;
-  }
-  const uint32_t n = s1 - s0;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const bool side = *sel != 0;
-  uint64_t* kin = side ? keys_b : keys_a;
-  uint64_t* kother = side ? keys_a : keys_b;
-  uint32_t* vals = side ? vals_b : vals_a;
+struct SegArgs {
+  uint64_t* keys_a;
+  uint64_t* keys_b;
+  uint32_t* vals_a;
+  uint32_t* vals_b;
+  const uint32_t* sel;
+  const uint32_t* ranges;
+  const uint32_t* rec_of;
+  const uint32_t* counters;
+  uint32_t cap;
+  uint32_t* emit;       // nullable
+  uint64_t* keys_out;   // nullable
+  uint32_t* err;
+  uint32_t n_tiles;
+};
+
+// Sorts one screen tile's segment [s0, s0 + n) (already grouped by tile, in
+// emission order) by depth bits, stably, and writes vals[k] = record id,
+// emit[k] = emission index (if emit), keys_out[k] = full key (if keys_out).
+// The keys buffer of the other ping-pong side is scratch for chunked
+// segments.
+template <int THREADS, bool CHUNKED>
+__device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint32_t tile, uint32_t s0, uint32_t n,
+                             uint32_t K) {
+  constexpr int kCap = SegLds<THREADS, CHUNKED>::kCap;
+  constexpr int W = THREADS / 64;
+  const int t = seg_tid<THREADS>(), lane = t & 63, wave = t >> 6;
+  const bool side = *a.sel != 0;
+  uint64_t* kin = side ? a.keys_b : a.keys_a;
+  uint64_t* kother = side ? a.keys_a : a.keys_b;
+  uint32_t* vals = side ? a.vals_b : a.vals_a;
+  uint32_t* err = a.err;
   // final write of sorted position o (segment-relative)
-  auto put = [&](uint32_t o, uint32_t depth, uint32_t e) {
-    if (o >= n || e >= K) {
+  auto put = [&](uint32_t o, uint32_t depth, uint32_t e, uint32_t rec) {
+    if (o >= n) {
       atomicOr(err, 32u);
       return;
     }
-    vals[s0 + o] = rec_of[e];
-    if (emit) emit[s0 + o] = e;
-    if (keys_out) keys_out[s0 + o] = ((uint64_t)tile << 32) | depth;
+    vals[s0 + o] = rec;
+    if (a.emit) a.emit[s0 + o] = e;
+    if (a.keys_out) a.keys_out[s0 + o] = ((uint64_t)tile << 32) | depth;
   };
+  auto record_of = [&](uint32_t e) -> uint32_t {
+    if (e < K) return a.rec_of[e];
+    atomicOr(err, 32u);
+    return 0u;
+  };
+  for (int i = t; i < W * 256; i += THREADS) (&L.wave_cnt[0][0][0])[i] = 0;
+  const uint32_t ref = (uint32_t)kin[s0];  // depth bits that differ from this one need passes
 
-  uint32_t key[kSegItems], val[kSegItems], pos[kSegItems];
-  if (n <= (uint32_t)kSegCap) {
-    const int I = (int)div_up(n, (uint32_t)kSegThreads);
-    uint32_t lor = 0, land = ~0u;
+  uint32_t key[kSegItems], val[kSegItems], rec[kSegItems], pos[kSegItems];
+  if (n <= (uint32_t)kCap) {
+    const int I = (int)div_up(n, (uint32_t)THREADS);
+    uint32_t diff = 0;
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
       key[r] = 0;
       val[r] = 0;
+      rec[r] = 0;
       if (r >= I) break;
       const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
       if (idx < n) {
         key[r] = (uint32_t)kin[s0 + idx];
         val[r] = vals[s0 + idx];
-        lor |= key[r];
-        land &= key[r];
+        diff |= key[r] ^ ref;
       }
     }
-    const uint32_t vary = seg_varying_bits(L, lor, land);
-    bool moved = false;
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+      if (r >= I) break;
+      const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+      if (idx < n) rec[r] = record_of(val[r]);  // gathered while the passes run
+    }
+    const uint32_t vary = seg_block_or(L, diff);
+    int buf = 0;
     for (int p = 0; p < 4; ++p) {
       if (((vary >> (8 * p)) & 255u) == 0) continue;
-      if (moved) {
+      if (buf) {
 #pragma unroll
         for (int r = 0; r < kSegItems; ++r) {
           if (r >= I) break;
@@ -458,10 +505,11 @@ k_sort_segments(uint64_t* __restrict__ keys_a, uint64_t* __restrict__ keys_b, ui
           if (idx < n) {
             key[r] = L.key[idx];
             val[r] = L.val[idx];
+            rec[r] = L.rec[idx];
           }
         }
       }
-      seg_rank(L, key, I, n, 8 * p, pos);
+      seg_rank(L, key, I, n, 8 * p, buf & 1, pos);
 #pragma unroll
       for (int r = 0; r < kSegItems; ++r) {
         if (r >= I) break;
@@ -469,127 +517,249 @@ k_sort_segments(uint64_t* __restrict__ keys_a, uint64_t* __restrict__ keys_b, ui
         if (idx < n) {
           L.key[pos[r]] = key[r];
           L.val[pos[r]] = val[r];
+          L.rec[pos[r]] = rec[r];
         }
       }
-      __syncthreads();
-      moved = true;
+      seg_sync<THREADS>();
+      ++buf;
     }
-    if (!moved) {
+    if (buf == 0) {
 #pragma unroll
       for (int r = 0; r < kSegItems; ++r) {
         if (r >= I) break;
         const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-        if (idx < n) put(idx, key[r], val[r]);
+        if (idx < n) put(idx, key[r], val[r], rec[r]);
       }
     } else {
-      for (uint32_t i = t; i < n; i += kSegThreads) put(i, L.key[i], L.val[i]);
+      for (uint32_t i = t; i < n; i += THREADS) put(i, L.key[i], L.val[i], L.rec[i]);
     }
     return;
   }
-
-  // Large segment: pack (depth, emission index) into the scratch side while
-  // taking the segment's digit histograms, then run the passes chunk by
-  // chunk, ping-ponging between the two key buffers; the last pass writes
-  // the results.
-  for (int i = t; i < 4 * 256; i += kSegThreads) (&L.base[0][0])[i] = 0;
-  __syncthreads();
-  uint32_t lor = 0, land = ~0u;
-  for (uint32_t b0 = 0; b0 < n; b0 += kSegThreads) {
-    const uint32_t i = b0 + t;
-    const bool valid = i < n;
-    uint32_t k = 0;
-    if (valid) {
-      k = (uint32_t)kin[s0 + i];
-      kother[s0 + i] = ((uint64_t)k << 32) | vals[s0 + i];
-      lor |= k;
-      land &= k;
-    }
+  if constexpr (CHUNKED) {
+    static_assert(THREADS >= 256, "chunked passes keep one digit per owner thread");
+    // Large segment: pack (depth, emission index) into the scratch side while
+    // taking the segment's digit histograms, then run the passes chunk by
+    // chunk, ping-ponging between the two key buffers; the last pass writes
+    // the results.
+    for (int i = t; i < 4 * 256; i += THREADS) (&L.base[0][0])[i] = 0;
+    seg_sync<THREADS>();
+    uint32_t diff = 0;
+    for (uint32_t b0 = 0; b0 < n; b0 += THREADS) {
+      const uint32_t i = b0 + t;
+      const bool valid = i < n;
+      uint32_t k = 0;
+      if (valid) {
+        k = (uint32_t)kin[s0 + i];
+        kother[s0 + i] = ((uint64_t)k << 32) | vals[s0 + i];
+        diff |= k ^ ref;
+      }
 #pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const uint32_t d = (k >> (8 * p)) & 255u;
+        const uint64_t peers = match_digit(d, valid);
+        if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&L.base[p][d], (uint32_t)__popcll(peers));
+      }
+    }
+    const uint32_t vary = seg_block_or(L, diff);  // (its barrier also publishes L.base)
+    int last_pass = -1;
+    for (int p = 0; p < 4; ++p)
+      if ((vary >> (8 * p)) & 255u) last_pass = p;
+    // exclusive digit offsets per pass
     for (int p = 0; p < 4; ++p) {
-      const uint32_t d = (k >> (8 * p)) & 255u;
-      const uint64_t peers = match_digit(d, valid);
-      if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&L.base[p][d], (uint32_t)__popcll(peers));
+      uint32_t c = 0, inc = 0;
+      if (t < 256) {
+        c = L.base[p][t];
+        inc = wave_incl_scan(c);
+        if (lane == 63) L.wsum[wave] = inc;
+      }
+      seg_sync<THREADS>();
+      if (t < 256) {
+        uint32_t off = 0;
+        for (int w = 0; w < wave; ++w) off += L.wsum[w];
+        L.base[p][t] = off + inc - c;
+      }
+      seg_sync<THREADS>();
     }
+    if (last_pass < 0) {
+      for (uint32_t i = t; i < n; i += THREADS) {
+        const uint64_t v = kother[s0 + i];
+        put(i, (uint32_t)(v >> 32), (uint32_t)v, record_of((uint32_t)v));
+      }
+      return;
+    }
+    uint64_t* src = kother;
+    uint64_t* dst = kin;
+    int buf = 0;
+    for (int p = 0; p <= last_pass; ++p) {
+      if (((vary >> (8 * p)) & 255u) == 0) continue;
+      const int shift = 8 * p;
+      if (t < 256) L.run[t] = L.base[p][t];
+      for (uint32_t cb = 0; cb < n; cb += kCap) {
+        const uint32_t nc = min((uint32_t)kCap, n - cb);
+        const int I = (int)div_up(nc, (uint32_t)THREADS);
+#pragma unroll
+        for (int r = 0; r < kSegItems; ++r) {
+          key[r] = 0;
+          val[r] = 0;
+          if (r >= I) break;
+          const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+          if (idx < nc) {
+            const uint64_t v = src[s0 + cb + idx];
+            key[r] = (uint32_t)(v >> 32);
+            val[r] = (uint32_t)v;
+          }
+        }
+        const uint32_t cnt = seg_rank(L, key, I, nc, shift, buf & 1, pos);
+        ++buf;
+#pragma unroll
+        for (int r = 0; r < kSegItems; ++r) {
+          if (r >= I) break;
+          const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+          if (idx < nc) {
+            L.key[pos[r]] = key[r];
+            L.val[pos[r]] = val[r];
+          }
+        }
+        seg_sync<THREADS>();
+        for (uint32_t i = t; i < nc; i += THREADS) {
+          const uint32_t k = L.key[i];
+          const uint32_t d = (k >> shift) & 255u;
+          const uint32_t o = L.run[d] + (i - L.start[d]);
+          if (p == last_pass) {
+            put(o, k, L.val[i], record_of(L.val[i]));
+          } else if (o < n) {
+            dst[s0 + o] = ((uint64_t)k << 32) | L.val[i];
+          } else {
+            atomicOr(err, 32u);
+          }
+        }
+        seg_sync<THREADS>();
+        if (t < 256) L.run[t] += cnt;
+        seg_sync<THREADS>();
+      }
+      uint64_t* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+  } else {
+    if (t == 0) atomicOr(err, 32u);  // a segment beyond this class's bound: never dropped silently
   }
-  const uint32_t vary = seg_varying_bits(L, lor, land);  // (its barrier also publishes L.base)
-  int last_pass = -1;
-  for (int p = 0; p < 4; ++p)
-    if ((vary >> (8 * p)) & 255u) last_pass = p;
-  // exclusive digit offsets per pass
-  for (int p = 0; p < 4; ++p) {
-    uint32_t c = 0, inc = 0;
-    if (t < 256) {
-      c = L.base[p][t];
-      inc = wave_incl_scan(c);
-      if (lane == 63) L.wsum[wave] = inc;
-    }
-    __syncthreads();
-    if (t < 256) {
-      uint32_t off = 0;
-      for (int w = 0; w < wave; ++w) off += L.wsum[w];
-      L.base[p][t] = off + inc - c;
-    }
-    __syncthreads();
-  }
-  if (last_pass < 0) {
-    for (uint32_t i = t; i < n; i += kSegThreads) {
-      const uint64_t v = kother[s0 + i];
-      put(i, (uint32_t)(v >> 32), (uint32_t)v);
-    }
+}
+
+static_assert(kSegWaveMax == 64 * kSegItems, "a wave sorts kSegItems keys per lane");
+
+constexpr uint32_t kSegHugeMin = 4096;  // block tiles above this size are scheduled first
+constexpr uint32_t kSegWorkCap = 1024;  // block tiles collected per scan and tier
+constexpr int kSegWaveBlock = 256;       // wave-kernel block: 4 waves, one tile each
+
+// One screen tile with at most kSegWaveMax pairs per wave.
+__global__ void __launch_bounds__(kSegWaveBlock) k_sort_segments_wave(SegArgs a) {
+  __shared__ SegLds<64, false> L[kSegWaveBlock / 64];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t tile = blockIdx.x * (kSegWaveBlock / 64) + wave;
+  if (tile >= a.n_tiles) return;
+  const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
+  if (s1 <= s0 || s1 - s0 > kSegWaveMax) return;
+  const uint32_t K = min(a.counters[kCntPairs], a.cap);
+  if (s1 > K) {
+    if (lane == 0) atomicOr(a.err, 32u);
     return;
   }
-  uint64_t* src = kother;
-  uint64_t* dst = kin;
-  for (int p = 0; p <= last_pass; ++p) {
-    if (((vary >> (8 * p)) & 255u) == 0) continue;
-    const int shift = 8 * p;
-    if (t < 256) L.run[t] = L.base[p][t];
-    for (uint32_t cb = 0; cb < n; cb += kSegCap) {
-      const uint32_t nc = min((uint32_t)kSegCap, n - cb);
-      const int I = (int)div_up(nc, (uint32_t)kSegThreads);
-#pragma unroll
-      for (int r = 0; r < kSegItems; ++r) {
-        key[r] = 0;
-        val[r] = 0;
-        if (r >= I) break;
-        const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-        if (idx < nc) {
-          const uint64_t v = src[s0 + cb + idx];
-          key[r] = (uint32_t)(v >> 32);
-          val[r] = (uint32_t)v;
-        }
+  sort_segment(L[wave], a, tile, s0, s1 - s0, K);
+}
+
+// A fixed grid of G blocks of 1024 threads for the tiles with more than
+// kSegWaveMax pairs.  Every block scans the tile ranges and numbers those
+// tiles in two tiers (above kSegHugeMin first, dealt from block 0 up; the
+// rest dealt from block G - 1 down), then sorts its share, huge tiles first.
+__global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
+  __shared__ SegLds<1024, true> L;
+  __shared__ uint32_t work[2 * kSegWorkCap];
+  __shared__ uint32_t wcnt[16][2];
+  __shared__ uint32_t n_work, more;
+  const uint32_t K = min(a.counters[kCntPairs], a.cap);
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t me = blockIdx.x, G = gridDim.x;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (uint32_t round = 0;; ++round) {
+    if (threadIdx.x == 0) {
+      n_work = 0;
+      more = 0;
+    }
+    __syncthreads();
+    uint32_t run0 = 0, run1 = 0;
+    for (uint32_t base = 0; base < a.n_tiles; base += 1024) {
+      const uint32_t tile = base + threadIdx.x;
+      uint32_t n = 0;
+      if (tile < a.n_tiles) {
+        const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
+        n = s1 > s0 ? s1 - s0 : 0u;
       }
-      const uint32_t cnt = seg_rank(L, key, I, nc, shift, pos);
-#pragma unroll
-      for (int r = 0; r < kSegItems; ++r) {
-        if (r >= I) break;
-        const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-        if (idx < nc) {
-          L.key[pos[r]] = key[r];
-          L.val[pos[r]] = val[r];
-        }
-      }
-      __syncthreads();
-      for (uint32_t i = t; i < nc; i += kSegThreads) {
-        const uint32_t k = L.key[i];
-        const uint32_t d = (k >> shift) & 255u;
-        const uint32_t o = L.run[d] + (i - L.start[d]);
-        if (p == last_pass) {
-          put(o, k, L.val[i]);
-        } else if (o < n) {
-          dst[s0 + o] = ((uint64_t)k << 32) | L.val[i];
-        } else {
-          atomicOr(err, 32u);
-        }
+      const bool t0 = n > kSegHugeMin, t1 = n > kSegWaveMax && !t0;
+      const uint64_t m0 = __ballot(t0), m1 = __ballot(t1);
+      if (lane == 0) {
+        wcnt[wave][0] = (uint32_t)__popcll(m0);
+        wcnt[wave][1] = (uint32_t)__popcll(m1);
       }
       __syncthreads();
-      if (t < 256) L.run[t] += cnt;
+      uint32_t pre0 = run0, pre1 = run1, tot0 = 0, tot1 = 0;
+#pragma unroll
+      for (uint32_t w = 0; w < 16; ++w) {
+        const uint32_t c0 = wcnt[w][0], c1 = wcnt[w][1];
+        if (w < wave) {
+          pre0 += c0;
+          pre1 += c1;
+        }
+        tot0 += c0;
+        tot1 += c1;
+      }
+      if (t0 || t1) {
+        const uint32_t g = t0 ? pre0 + (uint32_t)__popcll(m0 & lt) : pre1 + (uint32_t)__popcll(m1 & lt);
+        const uint32_t owner = t0 ? g % G : G - 1u - g % G;
+        const uint32_t k = g / G;
+        if (owner == me) {
+          if (k >= round * kSegWorkCap && k < (round + 1) * kSegWorkCap) {
+            const uint32_t slot = atomicAdd(&n_work, 1u);
+            work[slot] = tile | (t1 ? 0x80000000u : 0u);
+          } else if (k >= (round + 1) * kSegWorkCap) {
+            more = 1;
+          }
+        }
+      }
+      run0 += tot0;
+      run1 += tot1;
       __syncthreads();
     }
-    uint64_t* tmp = src;
-    src = dst;
-    dst = tmp;
+    const uint32_t nw = n_work;
+    for (uint32_t tier = 0; tier < 2; ++tier) {
+      for (uint32_t j = 0; j < nw; ++j) {
+        const uint32_t e = work[j];
+        if ((e >> 31) != tier) continue;
+        const uint32_t tile = e & 0x7FFFFFFFu;
+        const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
+        if (s1 > K) {
+          if (threadIdx.x == 0) atomicOr(a.err, 32u);
+          continue;
+        }
+        sort_segment(L, a, tile, s0, s1 - s0, K);
+        __syncthreads();  // LDS is reused by the next tile
+      }
+    }
+    if (!more) break;
+    __syncthreads();
   }
+}
+
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cus[dev] = c;
+  }
+  return cus[dev];
 }
 
 // After the tile passes: per-tile depth sort, record ids and emission
@@ -599,8 +769,12 @@ hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* va
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,
                                 uint32_t* emit, uint64_t* keys_out, uint32_t* error_flag, hipStream_t s) {
   if (total_tiles == 0 || pair_capacity == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sort_segments, dim3(total_tiles), dim3(kSegThreads), 0, s, keys_a, keys_b, vals_a, vals_b,
-                     sel, ranges, rec_of, counters, pair_capacity, emit, keys_out, error_flag);
+  SegArgs a{keys_a, keys_b, vals_a, vals_b, sel, ranges, rec_of, counters, pair_capacity, emit, keys_out,
+            error_flag, total_tiles};
+  const uint32_t G = std::min<uint32_t>(total_tiles, (uint32_t)std::max(1, device_cus()));
+  hipLaunchKernelGGL(k_sort_segments_block, dim3(G), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_sort_segments_wave, dim3(div_up(total_tiles, (uint32_t)(kSegWaveBlock / 64))),
+                     dim3(kSegWaveBlock), 0, s, a);
   return hipGetLastError();
 }
 

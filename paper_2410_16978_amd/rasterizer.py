@@ -58,7 +58,8 @@ class ViewState(C.Structure):
 
 class Model(C.Structure):
     _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("mean", C.c_void_p), ("scale", C.c_void_p),
-                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p), ("layer", C.c_void_p)]
+                ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p), ("layer", C.c_void_p),
+                ("raw", C.c_int32), ("reserved", C.c_int32)]
 
 
 class FwdState(C.Structure):
@@ -120,6 +121,8 @@ def lib():
     L.gsr_l1_alpha_loss.restype = C.c_int
     L.gsr_l1_alpha_loss.argtypes = [C.c_int32, C.c_int32, C.c_int32] + [C.c_void_p] * 4 + [
         C.POINTER(C.c_float), C.c_void_p, C.c_size_t] + [C.c_void_p] * 4 + [C.c_void_p]
+    L.gsr_activate.restype = C.c_int
+    L.gsr_activate.argtypes = [C.POINTER(Model), C.c_void_p, C.c_void_p, C.c_void_p]
     L.gsr_timer_create.restype = C.c_int
     L.gsr_timer_create.argtypes = [C.POINTER(C.c_void_p)]
     L.gsr_timer_destroy.restype = None
@@ -208,7 +211,19 @@ def model_struct(model):
         want = torch.uint8 if k == "layer" else torch.float32
         if t.dtype != want:
             raise ValueError(f"model[{k!r}] must be {want}")
-    return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS])
+    return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS], 1 if model.get("raw", False) else 0, 0)
+
+
+def activate(model, stream=None):
+    """(scale [3,n], opacity [n]) as the kernels compute them from `model`
+    (exp / logistic of the raw parameters if model["raw"], else copies)."""
+    m = model_struct(model)
+    n = int(model["layer"].shape[0])
+    dev = model["mean"].device
+    scale = torch.empty((3, n), dtype=torch.float32, device=dev)
+    opacity = torch.empty((n,), dtype=torch.float32, device=dev)
+    _check(lib().gsr_activate(C.byref(m), _ptr(scale), _ptr(opacity), _stream(stream)), "gsr_activate")
+    return scale, opacity
 
 
 # ---------------------------------------------------------------- timer

@@ -131,9 +131,11 @@ def test_gradient_central_differences_on_gpu():
 
 
 def test_autograd_function_chain_rule(orc):
-    """render_params: torch chains exp/sigmoid on top of the kernel gradient."""
+    """render_params: the kernels apply exp / logistic to the raw parameters
+    and chain their gradients."""
     import torch
     from paper_2410_16978_amd import autograd as ag
+    from paper_2410_16978_amd import rasterizer as rz
     sc, cams, vss, Gr, Ga = _case(seed=12, D=1)
     dev = "cuda"
     params = {k: torch.tensor(sc[k], device=dev, requires_grad=True)
@@ -144,10 +146,14 @@ def test_autograd_function_chain_rule(orc):
     loss = (rgb * torch.tensor(Gr, device=dev)).sum() + (alpha * torch.tensor(Ga, device=dev)).sum()
     loss.backward()
     torch.cuda.synchronize()
-    # the oracle takes the activations exactly as torch computed them
+    # the oracle takes the activations exactly as the kernels computed them
     act = dict(sc)
-    act["scale"] = torch.exp(params["log_scale"]).detach().cpu().numpy()
-    act["opacity"] = torch.sigmoid(params["opacity_logit"]).detach().cpu().numpy()
+    sc_t, op_t = rz.activate({"mean": params["mean"].detach(), "scale": params["log_scale"].detach(),
+                              "quat": params["quat"].detach(), "opacity": params["opacity_logit"].detach(),
+                              "sh": params["sh"].detach(), "layer": layer, "sh_degree": sc["sh_degree"],
+                              "raw": True})
+    act["scale"] = sc_t.cpu().numpy()
+    act["opacity"] = op_t.cpu().numpy()
     ref32, ref64, ex = _refs(orc, act, cams, vss, Gr, Ga, last=rctx.state.last.cpu().numpy().view(np.uint32),
                              final_T=rctx.state.final_T.cpu().numpy())
     o = act["opacity"].astype(np.float64)

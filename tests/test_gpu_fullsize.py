@@ -43,8 +43,8 @@ def test_training_step_200k_forward(c2, orc):
 
 
 def _raw_to_scene64(raw, layer, D):
-    """Activated float64 scene from raw parameters (as the autograd wrapper
-    applies them: exp of log-scales, sigmoid of logits)."""
+    """Activated float64 scene from raw parameters (exp of log-scales,
+    logistic function of logits)."""
     return {"mean": raw["mean"], "scale": np.exp(raw["log_scale"]), "quat": raw["quat"],
             "opacity": 1.0 / (1.0 + np.exp(-raw["opacity_logit"])), "sh": raw["sh"], "layer": layer,
             "sh_degree": D}
@@ -83,10 +83,14 @@ def c2_grads(c2, orc):
     torch.cuda.synchronize()
     rz.forward_check(rctx.state)
     got = {k: params[k].grad.cpu().numpy() for k in KEYS}
-    # the oracle takes the activations exactly as torch computed them
+    # the oracle takes the activations exactly as the kernels computed them
     act = dict(sc)
-    act["scale"] = torch.exp(params["log_scale"]).detach().cpu().numpy()
-    act["opacity"] = torch.sigmoid(params["opacity_logit"]).detach().cpu().numpy()
+    sc_t, op_t = rz.activate({"mean": params["mean"].detach(), "scale": params["log_scale"].detach(),
+                              "quat": params["quat"].detach(), "opacity": params["opacity_logit"].detach(),
+                              "sh": params["sh"].detach(), "layer": layer, "sh_degree": sc["sh_degree"],
+                              "raw": True})
+    act["scale"] = sc_t.cpu().numpy()
+    act["opacity"] = op_t.cpu().numpy()
     ref32 = orc.backward(act, cams, vss, Gr, Ga, bound=True)
     ref = orc.backward(to64(act), cams, vss, Gr.astype(np.float64), Ga.astype(np.float64), dtype=np.float64)
     o = act["opacity"].astype(np.float64)
