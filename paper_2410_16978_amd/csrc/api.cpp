@@ -31,7 +31,7 @@ struct Carver {
 // Sort control block: digit counts and offsets of every pass, pass tickets.
 // Cleared at the start of each call.
 struct SortCtl {
-  uint32_t hist[2 * kMaxSortPasses * 256];
+  uint32_t hist[kMaxSortPasses * 256];
   uint32_t pass_ctr[kMaxSortPasses];
   uint32_t scan_ticket;
   uint32_t pad[7];
@@ -48,7 +48,6 @@ struct PipeBufs {
   uint64_t* keys_b = nullptr;
   uint32_t* rec_of = nullptr;
   SortCtl* ctl = nullptr;
-  SortPlan* plan = nullptr;
   uint32_t* status = nullptr;
   float* g_pair = nullptr;
   float* g_col = nullptr;    // [R][3] colour gradient of each record (backward)
@@ -73,7 +72,6 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.keys_b = c.take<uint64_t>(std::max<size_t>(P, 1));
   b.rec_of = c.take<uint32_t>(std::max<size_t>(P, 1));
   b.ctl = c.take<SortCtl>(1);
-  b.plan = c.take<SortPlan>(1);
   b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
   if (backward) {
     b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
@@ -94,9 +92,35 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
 
 // One launch zeroes everything a call expects to start at zero: the sort
 // control block (digit counts, tickets), the pair counters, the tile ranges,
-// the scan's look-back words and (forward) the batch-to-tile map.
+// the scan's and the radix passes' look-back words, the sorted-buffer
+// selector and (forward) the batch-to-tile map.
+// The global radix passes cover only the tile bits of the keys (bits 32
+// up); the depth bits are sorted per tile segment.
+constexpr int kDepthPasses = 4;
+int tile_pass_end(uint64_t total_tiles) {
+  int b = 0;
+  while (b < 32 && (1ull << b) < total_tiles) ++b;
+  return kDepthPasses + (b + 7) / 8;
+}
+
+// The views array goes to the device in the arguments of the clear launch
+// when it is small enough (one launch, no copy), else by a copy.
+hipError_t upload_views(ViewD* dst, const ViewD* src, int n_views, WordUpload& up, hipStream_t s) {
+  const size_t bytes = sizeof(ViewD) * (size_t)n_views;
+  up.dst = nullptr;
+  up.n = 0;
+  if (bytes <= sizeof(up.w)) {
+    up.dst = reinterpret_cast<uint32_t*>(dst);
+    up.n = (uint32_t)(bytes / 4);
+    std::memcpy(up.w, src, bytes);
+    return hipSuccess;
+  }
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+}
+
 hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, uint32_t* ranges, size_t X, size_t R,
-                           hipStream_t s, uint32_t* batch_tile = nullptr, size_t n_batches = 0) {
+                           uint32_t P, uint32_t* sel, hipStream_t s, const WordUpload* up,
+                           uint32_t* batch_tile = nullptr, size_t n_batches = 0) {
   ClearSet cs{};
   cs.p[0] = reinterpret_cast<uint32_t*>(b.ctl);
   cs.n[0] = sizeof(SortCtl) / 4;
@@ -106,13 +130,20 @@ hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, uint32_t* rang
   cs.n[2] = 2 * X;
   cs.p[3] = reinterpret_cast<uint32_t*>(b.scan_status);
   cs.n[3] = 2 * (size_t)scan_tiles((uint32_t)R);
-  cs.n_ranges = 4;
+  // look-back words of the tile passes, and the sorted-buffer selector
+  const size_t stride = sort_status_stride(P);
+  const int pb = kDepthPasses, pe = tile_pass_end(X);
+  cs.p[4] = b.status + (size_t)pb * stride;
+  cs.n[4] = (size_t)(pe - pb) * stride;
+  cs.p[5] = sel;
+  cs.n[5] = 1;
+  cs.n_ranges = 6;
   if (batch_tile && n_batches) {
-    cs.p[4] = batch_tile;
-    cs.n[4] = n_batches;
-    cs.n_ranges = 5;
+    cs.p[6] = batch_tile;
+    cs.n[6] = n_batches;
+    cs.n_ranges = 7;
   }
-  return launch_clear_multi(cs, s);
+  return launch_clear_multi(cs, s, up);
 }
 
 bool model_ok(const gsr_model* m) {
@@ -131,15 +162,6 @@ bool view_ok(const gsr_view_state& v) { return v.n_clip >= 0 && v.n_clip <= GSR_
 
 uint32_t tiles_of(const gsr_camera& c) {
   return div_up((uint32_t)c.width, (uint32_t)kTile) * div_up((uint32_t)c.height, (uint32_t)kTile);
-}
-
-// The global radix passes cover only the tile bits of the keys (bits 32
-// up); the depth bits are sorted per tile segment.
-constexpr int kDepthPasses = 4;
-int tile_pass_end(uint64_t total_tiles) {
-  int b = 0;
-  while (b < 32 && (1ull << b) < total_tiles) ++b;
-  return kDepthPasses + (b + 7) / 8;
 }
 
 ViewD make_view(const gsr_camera& c, const gsr_view_state& vs) {
@@ -344,9 +366,10 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     hv[v] = d;
     ids[v] = v;
   }
-  HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
-  HIP_TRY(clear_workspace(b, state->counters, state->ranges, X, R, s, state->batch_map + X + 1,
-                          state->batch_capacity));
+  WordUpload up;
+  HIP_TRY(upload_views(b.views, hv.data(), n_views, up, s));
+  HIP_TRY(clear_workspace(b, state->counters, state->ranges, X, R, P, state->sort_sel, s, &up,
+                          state->batch_map + X + 1, state->batch_capacity));
   const ModelD md = make_model(*model);
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
@@ -376,7 +399,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
-                        kDepthPasses, tile_pass_end(X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan,
+                        kDepthPasses, tile_pass_end(X), b.ctl->hist, b.status, b.ctl->pass_ctr,
                         state->sort_sel, state->counters + kCntError, s));
   }
   {
@@ -451,7 +474,11 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
   }
   if (n == 0) return GSR_OK;
   if (state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
-  HIP_TRY(hipMemcpyAsync(b.views, hv.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
+  {
+    WordUpload up;
+    HIP_TRY(upload_views(b.views, hv.data(), n_views, up, s));
+    if (up.n) HIP_TRY(launch_clear_multi(ClearSet{}, s, &up));
+  }
   {
     StageScope sc(timer, GSR_STAGE_BLEND_BWD, s);
     HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
@@ -538,9 +565,10 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
     d.last = b.last + q_off;
     q_off += (size_t)d.W * d.H;
   }
-  HIP_TRY(hipMemcpyAsync(b.views, bp.views.data(), sizeof(ViewD) * n_views, hipMemcpyHostToDevice, s));
+  WordUpload up;
+  HIP_TRY(upload_views(b.views, bp.views.data(), n_views, up, s));
   HIP_TRY(hipMemcpyAsync(b.req_rec, bp.req_rec.data(), 4 * (n_req + 1), hipMemcpyHostToDevice, s));
-  HIP_TRY(clear_workspace(b, b.counters, b.ranges, bp.X, R, s));
+  HIP_TRY(clear_workspace(b, b.counters, b.ranges, bp.X, R, P, b.sel, s, &up));
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
     for (int m = 0; m < n_models; ++m) {
@@ -565,7 +593,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, kDepthPasses, tile_pass_end(bp.X),
-                        b.ctl->hist, b.status, b.ctl->pass_ctr, b.plan, b.sel, b.counters + kCntError, s));
+                        b.ctl->hist, b.status, b.ctl->pass_ctr, b.sel, b.counters + kCntError, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);

@@ -79,13 +79,6 @@ struct JobD {
   int32_t view[kMaxJobViews];
 };
 
-// Sort schedule computed on the device from the global digit histogram.
-struct SortPlan {
-  uint32_t skip[kMaxSortPasses];   // every key has the same digit: pass is a no-op
-  uint32_t src[kMaxSortPasses];    // ping-pong buffer the pass reads
-  uint32_t sel;                    // buffer holding the sorted result
-  uint32_t n_passes;
-};
 
 __host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
@@ -121,11 +114,19 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
 namespace gsr {
 
 struct ClearSet {
-  uint32_t* p[6];
-  size_t n[6];
+  uint32_t* p[8];
+  size_t n[8];
   int n_ranges;
 };
-hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s);
+// Small host data (view descriptions) carried in the kernel arguments of
+// the clear launch instead of a host-to-device copy.
+constexpr int kUploadWords = 4 * (int)(sizeof(ViewD) / 4);
+struct WordUpload {
+  uint32_t* dst;
+  uint32_t n;
+  uint32_t w[kUploadWords];
+};
+hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s, const WordUpload* up = nullptr);
 hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out, hipStream_t s);
 hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
@@ -138,8 +139,9 @@ hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, co
                             uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s);
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                        const uint32_t* counters, uint32_t pair_capacity, int pass_begin, int pass_end,
-                       uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
+                       uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, uint32_t* sel_out,
                        uint32_t* error_flag, hipStream_t s);
+size_t sort_status_stride(uint32_t pair_capacity);
 hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,

@@ -3,6 +3,8 @@
 // evaluated as written, each + - * / sqrt correctly rounded, so the records,
 // tile boxes and depth keys are reproducible bit for bit.
 #include "common.hpp"
+
+#include <cstddef>
 #include "sh.hpp"
 
 namespace gsr {
@@ -44,25 +46,38 @@ hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Several ranges in one launch (the per-call control words).
-__global__ void __launch_bounds__(256) k_clear_multi(ClearSet cs) {
+// Several ranges in one launch (the per-call control words), and an
+// optional upload of words carried in the arguments (block 0).  The upload's
+// words are read from the argument segment, where it follows the ClearSet.
+static_assert(sizeof(ClearSet) % alignof(WordUpload) == 0, "WordUpload follows ClearSet unpadded");
+__global__ void __launch_bounds__(256) k_clear_multi(ClearSet cs, WordUpload up) {
+  if (blockIdx.x == 0 && up.n) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(
+        (const char*)__builtin_amdgcn_kernarg_segment_ptr() + sizeof(ClearSet) +
+        offsetof(WordUpload, w));
+    for (uint32_t k = threadIdx.x; k < up.n; k += 256) up.dst[k] = src[k];
+  }
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
 #pragma unroll
-  for (int r = 0; r < 6; ++r) {
+  for (int r = 0; r < 8; ++r) {
     if (r >= cs.n_ranges) break;
     for (; i < cs.n[r]; i += stride) cs.p[r][i] = 0u;
     i -= cs.n[r];  // continue the grid-stride walk into the next range
   }
 }
 
-hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s) {
+hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s, const WordUpload* up) {
   size_t total = 0;
   for (int r = 0; r < cs.n_ranges; ++r) total += cs.n[r];
-  if (total == 0) return hipSuccess;
+  WordUpload u;
+  u.dst = nullptr;
+  u.n = 0;
+  if (up) u = *up;
+  if (total == 0 && u.n == 0) return hipSuccess;
   const size_t blocks = total / 256 + 1;
   const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
-  hipLaunchKernelGGL(k_clear_multi, dim3(grid), dim3(256), 0, s, cs);
+  hipLaunchKernelGGL(k_clear_multi, dim3(grid), dim3(256), 0, s, cs, u);
   return hipGetLastError();
 }
 

@@ -3,9 +3,9 @@
 // 1. The tile digits: stable LSD radix passes over the whole pair array,
 //    8-bit digits, in the single-pass-per-digit style of OneSweep (Adinets
 //    and Merrill, the sort the paper's renderer derives from, Sec. 3.3): one
-//    read of the keys builds the digit histograms of every pass, then each
-//    pass ranks a tile of keys per block and finds the tile's global digit
-//    offsets by decoupled look-back over the preceding tiles.
+//    read of the keys counts the digits of every pass, then each pass ranks
+//    a tile of keys per block and finds the tile's global digit offsets by
+//    decoupled look-back over the preceding tiles.
 // 2. The depth digits, per screen tile: one block per screen tile sorts its
 //    segment by the 32 depth bits with block-local LSD passes (in LDS when
 //    the segment fits, else chunk by chunk through global memory), stable,
@@ -56,74 +56,34 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) { return wave_scan_add(x); }
 
 // ---------------------------------------------------------------- histogram
-// Digit histograms of every pass (per-wave LDS counters, merged per block
-// and added to the global counts); also clears the look-back words of the
-// tiles the passes will use.
-__global__ void __launch_bounds__(256)
+// Digit counts of the passes [pass_begin, pass_end) from one read of the
+// keys: a few large blocks (so that each global count takes few additions),
+// per-wave LDS counts merged per block.
+constexpr int kHistThreads = 1024;
+constexpr int kHistWaves = kHistThreads / 64;
+constexpr int kHistMaxPasses = 4;  // tile bytes
+
+__global__ void __launch_bounds__(kHistThreads)
 k_sort_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counters, uint32_t cap,
-            int pass_begin, int pass_end, uint32_t* __restrict__ hist, uint32_t* __restrict__ status,
-            uint32_t nb_max) {
-  __shared__ uint32_t lh[4][kMaxSortPasses * 256];
+            int pass_begin, int pass_end, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[kHistWaves][kHistMaxPasses * 256];
   const uint32_t K = min(counters[kCntPairs], cap);
   const int wave = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < 4 * kMaxSortPasses * 256; i += 256) (&lh[0][0])[i] = 0;
+  const int np = pass_end - pass_begin;
+  for (int i = threadIdx.x; i < kHistWaves * kHistMaxPasses * 256; i += kHistThreads) (&lh[0][0])[i] = 0;
   __syncthreads();
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += stride) {
     const uint64_t k = keys[i];
-    for (int p = pass_begin; p < pass_end; ++p)
-      atomicAdd(&lh[wave][p * 256 + ((uint32_t)(k >> (8 * p)) & 255u)], 1u);
+    for (int q = 0; q < np; ++q)
+      atomicAdd(&lh[wave][q * 256 + ((uint32_t)(k >> (8 * (pass_begin + q))) & 255u)], 1u);
   }
   __syncthreads();
-  for (int i = pass_begin * 256 + threadIdx.x; i < pass_end * 256; i += 256) {
-    const uint32_t c = lh[0][i] + lh[1][i] + lh[2][i] + lh[3][i];
-    if (c) atomicAdd(&hist[i], c);
-  }
-  // clear the look-back words of the active tiles of every pass
-  const uint32_t nb = div_up(K, (uint32_t)kSortTile);
-  const size_t per_pass = (size_t)nb * 256;
-  const size_t total = per_pass * (size_t)(pass_end - pass_begin);
-  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += stride) {
-    const size_t p = pass_begin + w / per_pass, rem = w % per_pass;
-    status[p * (size_t)nb_max * 256 + rem] = 0u;
-  }
-}
-
-// ---------------------------------------------------------------- plan
-// Exclusive digit offsets per pass, passes whose keys all share one digit
-// are skipped, and the ping-pong buffer of every remaining pass.
-__global__ void __launch_bounds__(256)
-k_sort_plan(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ counters, uint32_t cap,
-            int pass_begin, int pass_end, uint32_t* __restrict__ digit_off, SortPlan* __restrict__ plan,
-            uint32_t* __restrict__ sel_out) {
-  __shared__ uint32_t lw[4];
-  __shared__ uint32_t trivial[kMaxSortPasses];
-  const uint32_t K = min(counters[kCntPairs], cap);
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  if (t < kMaxSortPasses) trivial[t] = 0;
-  __syncthreads();
-  for (int p = pass_begin; p < pass_end; ++p) {
-    const uint32_t c = hist[p * 256 + t];
-    const uint32_t inc = wave_incl_scan(c);
-    if (lane == 63) lw[wave] = inc;
-    __syncthreads();
-    uint32_t off = 0;
-    for (int w = 0; w < wave; ++w) off += lw[w];
-    digit_off[p * 256 + t] = off + inc - c;
-    if (c == K) trivial[p] = 1;  // every key has digit t (also K == 0 via c == 0 == K)
-    __syncthreads();
-  }
-  if (t == 0) {
-    uint32_t cur = 0;
-    for (int p = 0; p < kMaxSortPasses; ++p) {
-      const bool skip = p < pass_begin || p >= pass_end || trivial[p] || K == 0;
-      plan->skip[p] = skip ? 1u : 0u;
-      plan->src[p] = cur;
-      if (!skip) cur ^= 1u;
-    }
-    plan->sel = cur;
-    plan->n_passes = (uint32_t)(pass_end - pass_begin);
-    *sel_out = cur;
+  for (int i = threadIdx.x; i < np * 256; i += kHistThreads) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kHistWaves; ++w) c += lh[w][i];
+    if (c) atomicAdd(&hist[pass_begin * 256 + i], c);
   }
 }
 
@@ -131,7 +91,7 @@ k_sort_plan(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ coun
 __global__ void __launch_bounds__(kSortThreads)
 k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t* __restrict__ vals0,
             uint32_t* __restrict__ vals1, const uint32_t* __restrict__ counters, uint32_t cap,
-            const SortPlan* __restrict__ plan, const uint32_t* __restrict__ digit_off,
+            const uint32_t* __restrict__ hist, int pass_begin, int pass_end, uint32_t* __restrict__ sel_out,
             uint32_t* __restrict__ status, uint32_t nb_max, uint32_t* __restrict__ pass_ctr,
             uint32_t* __restrict__ err, int pass) {
   __shared__ uint32_t s_bid;
@@ -141,17 +101,43 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
   __shared__ uint32_t s_w[4];
   __shared__ uint64_t s_keys[kSortTile];
   __shared__ uint32_t s_vals[kSortTile];
+  __shared__ uint32_t s_triv;
+  __shared__ uint32_t s_hw[4];
 
-  if (plan->skip[pass]) return;
   const uint32_t K = min(counters[kCntPairs], cap);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // Plan, from the digit counts of all passes (complete before the first
+  // pass): a pass is a no-op when one digit holds every key; the buffers
+  // alternate over the passes that move keys.  Thread t < 256 also takes
+  // the exclusive global offset of digit t for this pass.
+  if (t == 0) s_triv = 0;
+  __syncthreads();
+  uint32_t hc = 0, hinc = 0;
+  if (t < 256) {
+    for (int p = pass_begin; p < pass_end; ++p)
+      if (hist[p * 256 + t] == K) atomicOr(&s_triv, 1u << p);
+    hc = hist[pass * 256 + t];
+    hinc = wave_incl_scan(hc);
+    if (lane == 63) s_hw[wave] = hinc;
+  }
+  if (t == 0) s_bid = 0xFFFFFFFFu;
+  __syncthreads();
+  const uint32_t triv = s_triv;
+  uint32_t moved_before = 0, moved_all = 0;
+  for (int p = pass_begin; p < pass_end; ++p) {
+    const uint32_t mv = ((triv >> p) & 1u) ? 0u : 1u;
+    moved_all += mv;
+    if (p < pass) moved_before += mv;
+  }
+  if (pass == pass_end - 1 && blockIdx.x == 0 && t == 0) *sel_out = moved_all & 1u;
+  if ((triv >> pass) & 1u) return;
   if (t == 0) s_bid = atomicAdd(&pass_ctr[pass], 1u);
   for (int i = t; i < kSortWaves * 256; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
   __syncthreads();
   const uint32_t bid = s_bid;
   const uint32_t base = bid * (uint32_t)kSortTile;
   if (base >= K) return;
-  const uint32_t src = plan->src[pass];
+  const uint32_t src = moved_before & 1u;
   const uint64_t* kin = src ? keys1 : keys0;
   const uint32_t* vin = src ? vals1 : vals0;
   uint64_t* kout = src ? keys0 : keys1;
@@ -236,7 +222,9 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
       __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagIncl | (excl + cnt), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_global[t] = digit_off[pass * 256 + t] + excl;
+    uint32_t doff = hinc - hc;
+    for (int w = 0; w < wave; ++w) doff += s_hw[w];
+    s_global[t] = doff + excl;
   }
   __syncthreads();
   // order the tile by digit in LDS (stable), then write digit runs out
@@ -270,26 +258,35 @@ size_t sort_status_words(uint32_t pair_capacity) {
 }
 
 // Radix passes [pass_begin, pass_end) (bits 8 * pass_begin up) of the
-// pair keys.  hist: [kMaxSortPasses][256] counts followed by
-// [kMaxSortPasses][256] offsets; pass_ctr: [kMaxSortPasses]; both zero on
-// entry.
+// pair keys in keys_a / vals_a.  On entry hist [kMaxSortPasses][256],
+// pass_ctr [kMaxSortPasses] and the passes' look-back words in status are
+// zero; the digit counts go to hist.
+// *sel_out receives the buffer holding the result (0: a, 1: b); with no
+// pass it is left as it is.
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                        const uint32_t* counters, uint32_t pair_capacity, int pass_begin, int pass_end,
-                       uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, SortPlan* plan, uint32_t* sel_out,
+                       uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, uint32_t* sel_out,
                        uint32_t* error_flag, hipStream_t s) {
   if (pass_begin < 0 || pass_end > kMaxSortPasses || pass_begin > pass_end) return hipErrorInvalidValue;
+  if (pass_end - pass_begin > kHistMaxPasses) return hipErrorInvalidValue;
   const uint32_t nb_max = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile);
-  uint32_t* digit_off = hist + kMaxSortPasses * 256;
-  uint32_t hist_blocks = div_up(pair_capacity > 0 ? pair_capacity : 1u, 256u * 16u);
-  if (hist_blocks > 128) hist_blocks = 128;  // fewer blocks: fewer global count additions
-  hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, s, keys_a, counters, pair_capacity, pass_begin,
-                     pass_end, hist, status, nb_max);
-  hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(256), 0, s, hist, counters, pair_capacity, pass_begin, pass_end,
-                     digit_off, plan, sel_out);
+  if (pass_end > pass_begin) {
+    // about 16 keys per thread, at most 64 blocks
+    uint32_t hb = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kHistThreads * 16u);
+    if (hb > 64) hb = 64;
+    hipLaunchKernelGGL(k_sort_hist, dim3(hb), dim3(kHistThreads), 0, s, keys_a, counters, pair_capacity,
+                       pass_begin, pass_end, hist);
+  }
   for (int p = pass_begin; p < pass_end; ++p)
     hipLaunchKernelGGL(k_sort_pass, dim3(nb_max), dim3(kSortThreads), 0, s, keys_a, keys_b, vals_a, vals_b,
-                       counters, pair_capacity, plan, digit_off, status, nb_max, pass_ctr, error_flag, p);
+                       counters, pair_capacity, hist, pass_begin, pass_end, sel_out, status, nb_max, pass_ctr,
+                       error_flag, p);
   return hipGetLastError();
+}
+
+// Look-back words of pass p: status + p * sort_status_stride(P), that many.
+size_t sort_status_stride(uint32_t pair_capacity) {
+  return (size_t)div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile) * 256;
 }
 
 // ---------------------------------------------------------------- per-tile depth sort
@@ -649,7 +646,6 @@ __device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint
 static_assert(kSegWaveMax == 64 * kSegItems, "a wave sorts kSegItems keys per lane");
 
 constexpr uint32_t kSegHugeMin = 4096;  // block tiles above this size are scheduled first
-constexpr uint32_t kSegWorkCap = 1024;  // block tiles collected per scan and tier
 constexpr int kSegWaveBlock = 256;       // wave-kernel block: 4 waves, one tile each
 
 // One screen tile with at most kSegWaveMax pairs per wave.
@@ -669,67 +665,27 @@ __global__ void __launch_bounds__(kSegWaveBlock) k_sort_segments_wave(SegArgs a)
 }
 
 // A fixed grid of G blocks of 1024 threads for the tiles with more than
-// kSegWaveMax pairs.  Every block scans the tile ranges and numbers those
-// tiles in two tiers (above kSegHugeMin first, dealt from block 0 up; the
-// rest dealt from block G - 1 down), then sorts its share, huge tiles first.
+// kSegWaveMax pairs.  Block b owns the tiles t = b (mod G), so neighbouring
+// (similarly loaded) tiles go to different blocks; it collects its large
+// tiles 1024 candidates at a time and sorts those above kSegHugeMin first.
 __global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
   __shared__ SegLds<1024, true> L;
-  __shared__ uint32_t work[2 * kSegWorkCap];
-  __shared__ uint32_t wcnt[16][2];
-  __shared__ uint32_t n_work, more;
+  __shared__ uint32_t work[1024];
+  __shared__ uint32_t n_work;
   const uint32_t K = min(a.counters[kCntPairs], a.cap);
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  const uint32_t me = blockIdx.x, G = gridDim.x;
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  for (uint32_t round = 0;; ++round) {
-    if (threadIdx.x == 0) {
-      n_work = 0;
-      more = 0;
+  const uint32_t G = gridDim.x;
+  const uint64_t span = (uint64_t)1024 * G;
+  for (uint64_t base = 0; base < a.n_tiles; base += span) {
+    if (threadIdx.x == 0) n_work = 0;
+    __syncthreads();
+    const uint64_t tile64 = base + (uint64_t)threadIdx.x * G + blockIdx.x;
+    if (tile64 < a.n_tiles) {
+      const uint32_t tile = (uint32_t)tile64;
+      const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
+      const uint32_t n = s1 > s0 ? s1 - s0 : 0u;
+      if (n > kSegWaveMax) work[atomicAdd(&n_work, 1u)] = tile | (n > kSegHugeMin ? 0u : 0x80000000u);
     }
     __syncthreads();
-    uint32_t run0 = 0, run1 = 0;
-    for (uint32_t base = 0; base < a.n_tiles; base += 1024) {
-      const uint32_t tile = base + threadIdx.x;
-      uint32_t n = 0;
-      if (tile < a.n_tiles) {
-        const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
-        n = s1 > s0 ? s1 - s0 : 0u;
-      }
-      const bool t0 = n > kSegHugeMin, t1 = n > kSegWaveMax && !t0;
-      const uint64_t m0 = __ballot(t0), m1 = __ballot(t1);
-      if (lane == 0) {
-        wcnt[wave][0] = (uint32_t)__popcll(m0);
-        wcnt[wave][1] = (uint32_t)__popcll(m1);
-      }
-      __syncthreads();
-      uint32_t pre0 = run0, pre1 = run1, tot0 = 0, tot1 = 0;
-#pragma unroll
-      for (uint32_t w = 0; w < 16; ++w) {
-        const uint32_t c0 = wcnt[w][0], c1 = wcnt[w][1];
-        if (w < wave) {
-          pre0 += c0;
-          pre1 += c1;
-        }
-        tot0 += c0;
-        tot1 += c1;
-      }
-      if (t0 || t1) {
-        const uint32_t g = t0 ? pre0 + (uint32_t)__popcll(m0 & lt) : pre1 + (uint32_t)__popcll(m1 & lt);
-        const uint32_t owner = t0 ? g % G : G - 1u - g % G;
-        const uint32_t k = g / G;
-        if (owner == me) {
-          if (k >= round * kSegWorkCap && k < (round + 1) * kSegWorkCap) {
-            const uint32_t slot = atomicAdd(&n_work, 1u);
-            work[slot] = tile | (t1 ? 0x80000000u : 0u);
-          } else if (k >= (round + 1) * kSegWorkCap) {
-            more = 1;
-          }
-        }
-      }
-      run0 += tot0;
-      run1 += tot1;
-      __syncthreads();
-    }
     const uint32_t nw = n_work;
     for (uint32_t tier = 0; tier < 2; ++tier) {
       for (uint32_t j = 0; j < nw; ++j) {
@@ -745,8 +701,6 @@ __global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
         __syncthreads();  // LDS is reused by the next tile
       }
     }
-    if (!more) break;
-    __syncthreads();
   }
 }
 
