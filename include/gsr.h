@@ -131,8 +131,10 @@ typedef struct {
  *   last        uint32[Q]     1 + index of the last blended pair, 0 if none
  *   checkpoints float[B][256][4]  per 256-pair batch of a tile and pixel:
  *                             transmittance before the batch, then the
- *                             colour (r, g, b) the batch adds; written for
- *                             the batches up to the one in which the tile's
+ *                             colour (r, g, b) behind the batch (the later
+ *                             batches' colours plus the background times
+ *                             the final transmittance); written for the
+ *                             batches up to the one in which the tile's
  *                             last pixel stops (later ones are never read)
  *   batch_map   uint32[X + 1 + B]  X + 1 unused words, then for each
  *                             checkpoint batch index 1 + its tile (0: none);

@@ -194,8 +194,8 @@ __device__ __forceinline__ float pair_alpha(const float4 B, float power) {
 // batch the records are staged once, a wave with a live pixel builds its list
 // (pairs whose reach box meets the sub-tile), and the block leaves when every
 // pixel has stopped.  Per batch it stores the checkpoint (T entering the
-// batch, colour the batch adds) the backward starts from, at the pixel's
-// index in the backward's 8 x 8-quadrant layout (ckpt may be null: render
+// batch, then colour behind the batch) the backward starts from, at the
+// pixel's index in the backward's 8 x 8-quadrant layout (ckpt may be null: render
 // only, then batch_tile is not written).  Tile t's batches have the indices
 // first_batch(t) + c, c = 0, 1, ...: distinct over the tiles and below
 // P / 256 + X + 1 for any pair count P.
@@ -266,6 +266,7 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = 0;
   bool done = !inside;
+  uint32_t n_ck = 0;  // batches processed (checkpoints written)
   for (uint32_t start = t_start, c = 0; start < t_end; start += kBatch, ++c) {
     if (!__syncthreads_or(!done)) break;  // also orders the previous batch's LDS reads before the refill
     const int n = (int)min((uint32_t)kBatch, t_end - start);
@@ -314,6 +315,22 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
     C2 += D2;
     last = lst ? lst : last;
     if (ckpt && slot == 0 && b0 + c < batch_cap) ckpt[(size_t)(b0 + c) * kBatch + bidx] = make_float4(T0, D0, D1, D2);
+    n_ck = c + 1;
+  }
+  if (ckpt && slot == 0) {
+    // replace each batch's colour by the colour behind the batch: the
+    // background under the final transmittance plus the later batches,
+    // summed from the back (a batch after the pixel stopped adds 0)
+    float a0 = T * V.bg[0], a1 = T * V.bg[1], a2 = T * V.bg[2];
+    for (int cc = (int)n_ck - 1; cc >= 0; --cc) {
+      if (b0 + (uint32_t)cc >= batch_cap) continue;
+      float4* q = ckpt + (size_t)(b0 + (uint32_t)cc) * kBatch + bidx;
+      const float4 d = *q;
+      *q = make_float4(d.x, a0, a1, a2);
+      a0 += d.y;
+      a1 += d.z;
+      a2 += d.w;
+    }
   }
   if (!inside || slot != 0) return;
   const size_t pix = (size_t)py * V.W + px;
@@ -445,15 +462,10 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       const float4* tck = ckpt + (size_t)(bi - c) * kBatch + tid;
       // transmittance at the end of this batch, colour behind it
       T = (c_last == c) ? Tfin : tck[(size_t)(c + 1) * kBatch].x;
-      S0 = Tfin * V.bg[0];
-      S1 = Tfin * V.bg[1];
-      S2 = Tfin * V.bg[2];
-      for (uint32_t cc = c_last; cc > c; --cc) {
-        const float4 d = tck[(size_t)cc * kBatch];
-        S0 += d.y;
-        S1 += d.z;
-        S2 += d.w;
-      }
+      const float4 sb = tck[(size_t)c * kBatch];
+      S0 = sb.y;
+      S1 = sb.z;
+      S2 = sb.w;
       if (dL_drgb) {
         G0 = dL_drgb[3 * vpix + pix];
         G1 = dL_drgb[3 * vpix + plane + pix];
