@@ -7,8 +7,8 @@
 // A tile's depth-sorted pairs are handled in batches of (at most) 256: a
 // batch's records are staged through LDS once and every wave builds the
 // compacted list of the batch's pairs whose ellipse of possible
-// alpha >= 1/255 (reach box first, then the conic's minimum over the wave's
-// pixel rectangle) meets its pixels, and walks only that list.
+// alpha >= 1/255 (the conic's minimum over the wave's pixel rectangle) meets
+// its pixels, and walks only that list.
 //
 // Forward: one block per tile walks its batches in order (below).
 //
@@ -33,7 +33,6 @@ struct BatchLds {
   float4 a[kBatch];    // u, v, conic a, conic b
   float4 b[kBatch];    // conic c, opacity, r, g
   float c[kBatch];     // b
-  float4 box[kBatch];  // x0, x1, y0, y1: pixel centres outside cannot reach alpha >= 1/255
   float4 ell[kBatch];  // q cut-off with margin, -b/c, -b/a (the conic's minimum over a rectangle)
 };
 
@@ -75,24 +74,11 @@ __device__ __forceinline__ Staged fetch(const float* __restrict__ records, uint3
   return st;
 }
 
-// Bounding box of the pixel centres where the pair can reach alpha >= 1/255:
-// o exp(-q/2) >= 1/255 needs q <= 2 ln(255 o); the box of that ellipse has
-// half-widths sqrt(q conic^-1_00) and sqrt(q conic^-1_11).  A relative
-// margin of 1e-3 plus 0.01 on q and 0.01 px on the box covers the rounding
-// of q, exp and this computation, so skipping a pair for pixels outside the
-// box never changes a result.
-__device__ __forceinline__ float4 reach_box(const Staged& st) {
-  const float o = st.b.y;
-  const float qo = fminf(kQMax, 2.f * __logf(255.f * o)) * 1.001f + 0.01f;
-  if (!(qo > 0.f)) return make_float4(1e30f, -1e30f, 1e30f, -1e30f);
-  const float ca = st.a.z, cb = st.a.w, cc = st.b.x;
-  const float det = ca * cc - cb * cb;
-  const float hx = sqrtf(qo * cc / det) + 0.01f, hy = sqrtf(qo * ca / det) + 0.01f;
-  return make_float4(st.a.x - hx, st.a.x + hx, st.a.y - hy, st.a.y + hy);
-}
-
-// The same cut-off for the exact test of wave_list, with wider margins: a
-// relative 1e-2 and 0.05 on q.
+// Cut-off of the pair's reach: o exp(-q/2) >= 1/255 needs q <= 2 ln(255 o).
+// A relative margin of 1e-2 plus 0.05 on q covers the rounding of q, exp
+// and this computation, so skipping a pair for pixel centres where its q
+// exceeds the cut-off never changes a result.  The cut-off is negative
+// (nothing reachable) when 255 o < 1.
 __device__ __forceinline__ float4 reach_conic(const Staged& st) {
   const float o = st.b.y;
   const float qo = fminf(kQMax, 2.f * __logf(255.f * o)) * 1.01f + 0.05f;
@@ -104,7 +90,6 @@ __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int 
     L.a[tid] = st.a;
     L.b[tid] = st.b;
     L.c[tid] = st.c;
-    L.box[tid] = reach_box(st);
     L.ell[tid] = reach_conic(st);
   }
 }
@@ -144,8 +129,8 @@ __device__ __forceinline__ uint64_t lanes_below() {
 }
 
 // The wave's list of the batch's pairs (ascending, j < n) that can reach a
-// pixel centre of its rectangle [qx0, qx1] x [qy0, qy1]: the reach box
-// first, then the ellipse itself; each lane tests one pair per round, a
+// pixel centre of its rectangle [qx0, qx1] x [qy0, qy1] (the ellipse of the
+// cut-off meets the rectangle); each lane tests one pair per round, a
 // ballot compacts the hits.  Returns the (wave-uniform) count.  Pairs not in
 // the list cannot reach alpha >= 1/255 on any of the wave's pixels, so
 // skipping them changes nothing.
@@ -158,9 +143,8 @@ __device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n
     const int j = r * 64 + lane;
     bool hit = false;
     if (j < n) {
-      const float4 bx = L.box[j];
-      hit = !((bx.y < qx0) || (bx.x > qx1) || (bx.w < qy0) || (bx.z > qy1));
-      if (hit) hit = conic_meets(L.a[j], L.b[j].x, L.ell[j], qx0, qx1, qy0, qy1);
+      const float4 E = L.ell[j];
+      hit = E.x > 0.05f && conic_meets(L.a[j], L.b[j].x, E, qx0, qx1, qy0, qy1);
     }
     const uint64_t m = __ballot(hit);
     if (hit) list[cnt + __popcll(m & lanes_below())] = (uint8_t)j;
@@ -192,7 +176,7 @@ __device__ __forceinline__ float pair_alpha(const float4 B, float power) {
 // instead of one.  The first pair (in list order) that would bring T below
 // 1e-4 ends the pixel and is not blended, as are the pairs after it.  Per
 // batch the records are staged once, a wave with a live pixel builds its list
-// (pairs whose reach box meets the sub-tile), and the block leaves when every
+// (pairs whose ellipse meets the sub-tile), and the block leaves when every
 // pixel has stopped.  Per batch it stores the checkpoint (T entering the
 // batch, then colour behind the batch) the backward starts from, at the
 // pixel's index in the backward's 8 x 8-quadrant layout (ckpt may be null: render
