@@ -156,33 +156,64 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint
 }
 
 // ---------------------------------------------------------------- duplicate
-// One thread per record: its tiles row-major at offsets[r] + j.  Pairs at or
-// beyond min(capacity, counters[pairs]) are dropped (the overflow flag or the
-// batch status already records it).  The sort carries each pair's emission
-// index as its value; rec_of[e] keeps the record of emission index e.
+// Each wave takes 64 consecutive records, whose pairs form one contiguous
+// emission range (offsets is their exclusive scan), and writes that range
+// with its lanes striding over the pairs: lane i writes pair base + i,
+// finding the record that owns it by a binary search over the wave's
+// offsets.  A record's tiles are row-major in its box.  Writes are
+// coalesced and a large splat's pairs spread over the wave instead of one
+// lane.  Pairs at or beyond min(capacity, counters[pairs]) are dropped (the
+// overflow flag or the batch status already records it).  The sort carries
+// each pair's emission index as its value; rec_of[e] keeps the record of
+// emission index e.
 __global__ void __launch_bounds__(256)
 k_duplicate(const uint32_t* __restrict__ n_tiles, const uint32_t* __restrict__ offsets,
             const uint4* __restrict__ tile_box, uint32_t n_rec, const uint32_t* __restrict__ counters,
             uint32_t pair_capacity, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
             uint32_t* __restrict__ rec_of) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rec) return;
-  pair_capacity = min(pair_capacity, counters[kCntPairs]);
-  const uint32_t cnt = n_tiles[r];
-  if (cnt == 0) return;
-  uint32_t off = offsets[r];
-  if (off >= pair_capacity) return;
-  const uint4 tb = tile_box[r];
-  const uint32_t w = tb.y & 0xFFFFu, h = tb.y >> 16;
-  const uint64_t depth = tb.z;
-  for (uint32_t dy = 0; dy < h; ++dy) {
-    const uint32_t row = tb.x + dy * tb.w;
-    for (uint32_t dx = 0; dx < w; ++dx) {
-      if (off >= pair_capacity) return;
-      keys[off] = ((uint64_t)(row + dx) << 32) | depth;
-      vals[off] = off;
-      rec_of[off] = r;
-      ++off;
+  const int lane = threadIdx.x & 63;
+  const uint32_t lim = min(pair_capacity, counters[kCntPairs]);
+  const bool valid = r < n_rec;
+  const uint32_t cnt = valid ? n_tiles[r] : 0u;
+  const uint32_t off = valid ? offsets[r] : 0xFFFFFFFFu;  // invalid lanes never own a pair
+  uint4 tb = make_uint4(0u, 0u, 0u, 0u);
+  if (cnt) tb = tile_box[r];
+  uint32_t end = valid ? off + cnt : 0u;
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, s, 64));
+  const uint32_t w0 = (uint32_t)__shfl((int)off, 0, 64);
+  const uint32_t w1 = min(end, lim);
+  const uint32_t r0 = r - (uint32_t)lane;
+  for (uint32_t base = w0; base < w1; base += 64) {
+    const uint32_t e = base + (uint32_t)lane;
+    // last lane whose offset is <= e (zero-count records share the next offset)
+    int lo = 0;
+#pragma unroll
+    for (int st = 32; st > 0; st >>= 1) {
+      const uint32_t o = (uint32_t)__shfl((int)off, lo + st, 64);
+      if (o <= e) lo += st;
+    }
+    const uint32_t o = (uint32_t)__shfl((int)off, lo, 64);
+    const uint32_t bx = (uint32_t)__shfl((int)tb.x, lo, 64);
+    const uint32_t by = (uint32_t)__shfl((int)tb.y, lo, 64);
+    const uint32_t bz = (uint32_t)__shfl((int)tb.z, lo, 64);
+    const uint32_t bw = (uint32_t)__shfl((int)tb.w, lo, 64);
+    if (e < w1) {
+      const uint32_t j = e - o;
+      const uint32_t w = max(by & 0xFFFFu, 1u);
+      uint32_t dy;
+      if (j < (1u << 24)) {  // float quotient, corrected to floor(j / w)
+        dy = (uint32_t)((float)j / (float)w);
+        if (dy * w > j) --dy;
+        if ((dy + 1) * w <= j) ++dy;
+      } else {
+        dy = j / w;
+      }
+      const uint32_t tile = bx + dy * bw + (j - dy * w);
+      keys[e] = ((uint64_t)tile << 32) | bz;
+      vals[e] = e;
+      rec_of[e] = r0 + (uint32_t)lo;
     }
   }
 }
