@@ -396,7 +396,8 @@ def main():
     torch.cuda.synchronize()
     stages = timer.read()
     rctx.timer = None
-    stage_ms = {s: (ms / max(c, 1)) for s, (ms, c) in stages.items()}
+    # per step: a stage may be timed in several pieces per call (the sort is split by the ranges)
+    stage_ms = {s: ms / args.steps for s, (ms, c) in stages.items()}
 
     result = {
         "metric": METRIC,

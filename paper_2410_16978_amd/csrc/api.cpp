@@ -34,6 +34,7 @@ struct SortCtl {
   uint32_t hist[kMaxSortPasses * 256];
   uint32_t pass_ctr[kMaxSortPasses];
   uint32_t scan_ticket;
+  uint32_t tile_class[kTileClasses];  // tiles per size class (forward order)
   uint32_t pad[7];
 };
 
@@ -49,6 +50,7 @@ struct PipeBufs {
   uint32_t* rec_of = nullptr;
   SortCtl* ctl = nullptr;
   uint32_t* status = nullptr;
+  uint32_t* class_list = nullptr;  // [kTileClasses][X] tiles by size class
   float* g_pair = nullptr;
   float* g_col = nullptr;    // [R][3] colour gradient of each record (backward)
   // batch only (the single-call path keeps these in the caller's state)
@@ -73,6 +75,7 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.rec_of = c.take<uint32_t>(std::max<size_t>(P, 1));
   b.ctl = c.take<SortCtl>(1);
   b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
+  b.class_list = c.take<uint32_t>(kTileClasses * std::max<size_t>(X, 1));
   if (backward) {
     b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
     b.g_col = c.take<float>(3 * std::max<size_t>(R, 1));
@@ -405,6 +408,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
     HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
+    HIP_TRY(launch_tile_order(state->ranges, (uint32_t)X, b.ctl->tile_class, b.class_list, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
@@ -417,7 +421,8 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     StageScope sc(timer, GSR_STAGE_BLEND, s);
     HIP_TRY(launch_blend_fwd_tile(b.views, n_views, (uint32_t)X, state->records, R, state->pair_vals,
                                   state->sort_sel, P, state->ranges, batch_tile, state->batch_capacity,
-                                  nullptr, reinterpret_cast<float4*>(state->checkpoints), s));
+                                  nullptr, reinterpret_cast<float4*>(state->checkpoints), b.ctl->tile_class,
+                                  b.class_list, s));
   }
   if (debug) {
     if (debug->n_tiles) HIP_TRY(hipMemcpyAsync(debug->n_tiles, b.n_tiles, 4ull * R, hipMemcpyDeviceToDevice, s));
@@ -598,6 +603,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
     HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
+    HIP_TRY(launch_tile_order(b.ranges, (uint32_t)bp.X, b.ctl->tile_class, b.class_list, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
@@ -607,7 +613,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);
     HIP_TRY(launch_blend_fwd_tile(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
-                                  nullptr, 0, req_status, nullptr, s));
+                                  nullptr, 0, req_status, nullptr, b.ctl->tile_class, b.class_list, s));
   }
   return GSR_OK;
 }

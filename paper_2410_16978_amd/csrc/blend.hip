@@ -218,10 +218,27 @@ __global__ void __launch_bounds__(1024)
 k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles, const float* __restrict__ records,
              uint32_t n_rec, const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
              const uint32_t* __restrict__ ranges, uint32_t* __restrict__ batch_tile, uint32_t batch_cap,
-             const int32_t* __restrict__ req_status, float4* __restrict__ ckpt) {
+             const int32_t* __restrict__ req_status, float4* __restrict__ ckpt,
+             const uint32_t* __restrict__ class_count, const uint32_t* __restrict__ class_list) {
   __shared__ BatchLds L;
   __shared__ uint8_t lists[16][kBatch];
-  const uint32_t tile = blockIdx.x;
+  // block b takes the b-th tile of the largest-first order (if given): the
+  // class counts are read at once, the first wave finds b's class by a scan
+  __shared__ uint32_t s_tile;
+  uint32_t tile = blockIdx.x;
+  if (class_count) {
+    if (threadIdx.x < 64) {
+      const uint32_t k = threadIdx.x;
+      const uint32_t cnt = k < kTileClasses ? min(class_count[k], total_tiles) : 0u;
+      const uint32_t inc = wave_scan_add(cnt);
+      const uint32_t b = blockIdx.x;
+      const bool here = k < kTileClasses && b >= inc - cnt && b < inc;
+      if (here) s_tile = class_list[(size_t)k * total_tiles + (b - (inc - cnt))];
+      if (__ballot(here) == 0ull && threadIdx.x == 0) s_tile = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    tile = s_tile;
+  }
   if (tile >= total_tiles) return;
   const int vi = find_view(views, n_views, tile);
   const ViewD& V = views[vi];
@@ -330,10 +347,12 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
 hipError_t launch_blend_fwd_tile(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
                                  uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
                                  const uint32_t* ranges, uint32_t* batch_tile, uint32_t batch_cap,
-                                 const int32_t* req_status, float4* ckpt, hipStream_t s) {
+                                 const int32_t* req_status, float4* ckpt, const uint32_t* class_count,
+                                 const uint32_t* class_list, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_blend_tile, dim3(total_tiles), dim3(1024), 0, s, views_dev, n_views, total_tiles, records,
-                     n_rec, pair_vals, sel, cap, ranges, batch_tile, batch_cap, req_status, ckpt);
+                     n_rec, pair_vals, sel, cap, ranges, batch_tile, batch_cap, req_status, ckpt, class_count,
+                     class_list);
   return hipGetLastError();
 }
 

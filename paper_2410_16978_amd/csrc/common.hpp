@@ -16,6 +16,7 @@ constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortItems = 8;         // per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kBatch = 256;          // pairs per blend batch (one per thread of a tile block)
+constexpr uint32_t kTileClasses = 34;  // tile size classes of the forward's largest-first order
 constexpr uint32_t kSegWaveMax = 512;  // tiles with more pairs are depth-sorted by a whole block
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -146,13 +147,16 @@ hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* va
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,
                                 uint32_t* emit, uint64_t* keys_out, uint32_t* error_flag, hipStream_t s);
+hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* class_count,
+                             uint32_t* class_list, hipStream_t s);
 hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,
                          uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles, uint32_t* ranges,
                          hipStream_t s);
 hipError_t launch_blend_fwd_tile(const ViewD* views_dev, int n_views, uint32_t total_tiles, const float* records,
                                  uint32_t n_rec, const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap,
                                  const uint32_t* ranges, uint32_t* batch_tile, uint32_t batch_cap,
-                                 const int32_t* req_status, float4* ckpt, hipStream_t s);
+                                 const int32_t* req_status, float4* ckpt, const uint32_t* class_count,
+                                 const uint32_t* class_list, hipStream_t s);
 uint32_t l1_loss_blocks(int n_views, int hw);
 hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
                           const float* t_alpha, const float* bg_host, float* partials, float* loss,

@@ -256,6 +256,65 @@ hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const u
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- tile order
+// Tiles grouped by pair count into kTileClasses classes (largest first,
+// empty tiles last), so that the forward blend starts its longest tiles
+// first.  One block per 1024
+// tiles: class counts per block (ballots), one addition per class and
+// block reserves the block's slots in the class list.  The order within a
+// class depends on the order the blocks run, which changes no result.
+__device__ __forceinline__ uint32_t tile_class(uint32_t n) {
+  // half-octave classes, largest first: class 0 holds n >= 2^16, class
+  // kTileClasses - 2 holds n = 1, the last class the empty tiles
+  if (n == 0) return kTileClasses - 1;
+  const uint32_t lg = 31u - (uint32_t)__clz(n);
+  const uint32_t h = 2u * lg + ((lg > 0 && ((n >> (lg - 1)) & 1u)) ? 1u : 0u);  // floor(2 log2 n)
+  return h >= 32u ? 0u : 32u - h;
+}
+
+__global__ void __launch_bounds__(1024)
+k_tile_order(const uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ class_count,
+             uint32_t* __restrict__ class_list) {
+  __shared__ uint32_t wc[16][kTileClasses];
+  __shared__ uint32_t base[kTileClasses];
+  const uint32_t t = blockIdx.x * 1024u + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t n = 0;
+  if (t < n_tiles) {
+    const uint32_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
+    n = s1 > s0 ? s1 - s0 : 0u;
+  }
+  const uint32_t c = t < n_tiles ? tile_class(n) : kTileClasses;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t rank = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kTileClasses; ++k) {
+    const uint64_t m = __ballot(c == k);
+    if (c == k) rank = (uint32_t)__popcll(m & below);
+    if (lane == 0) wc[wave][k] = (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < kTileClasses) {
+    uint32_t tot = 0;
+    for (int w = 0; w < 16; ++w) tot += wc[w][threadIdx.x];
+    base[threadIdx.x] = tot ? atomicAdd(&class_count[threadIdx.x], tot) : 0u;
+  }
+  __syncthreads();
+  if (c < kTileClasses) {
+    uint32_t pos = base[c] + rank;
+    for (int w = 0; w < wave; ++w) pos += wc[w][c];
+    if (pos < n_tiles) class_list[(size_t)c * n_tiles + pos] = t;
+  }
+}
+
+hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* class_count,
+                             uint32_t* class_list, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_order, dim3(div_up(n_tiles, 1024u)), dim3(1024), 0, s, ranges, n_tiles, class_count,
+                     class_list);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- batch status
 // Requests own contiguous record ranges [req_rec[q], req_rec[q+1]), so their
 // pairs are contiguous in emission order.  A request whose pairs end beyond
