@@ -146,7 +146,8 @@ size_t sort_status_stride(uint32_t pair_capacity);
 hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,
-                                uint32_t* emit, uint64_t* keys_out, uint32_t* error_flag, hipStream_t s);
+                                uint32_t* emit, uint64_t* keys_out, const uint32_t* class_count,
+                                const uint32_t* class_list, uint32_t* error_flag, hipStream_t s);
 hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* class_count,
                              uint32_t* class_list, hipStream_t s);
 hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,

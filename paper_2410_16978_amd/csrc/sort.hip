@@ -431,6 +431,8 @@ struct SegArgs {
   uint64_t* keys_out;   // nullable
   uint32_t* err;
   uint32_t n_tiles;
+  const uint32_t* class_count;  // tiles per size class, largest first (k_tile_order)
+  const uint32_t* class_list;   // [kTileClasses][n_tiles]
 };
 
 // Sorts one screen tile's segment [s0, s0 + n) (already grouped by tile, in
@@ -645,7 +647,6 @@ __device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint
 
 static_assert(kSegWaveMax == 64 * kSegItems, "a wave sorts kSegItems keys per lane");
 
-constexpr uint32_t kSegHugeMin = 4096;  // block tiles above this size are scheduled first
 constexpr int kSegWaveBlock = 256;       // wave-kernel block: 4 waves, one tile each
 
 // One screen tile with at most kSegWaveMax pairs per wave.
@@ -665,42 +666,41 @@ __global__ void __launch_bounds__(kSegWaveBlock) k_sort_segments_wave(SegArgs a)
 }
 
 // A fixed grid of G blocks of 1024 threads for the tiles with more than
-// kSegWaveMax pairs.  Block b owns the tiles t = b (mod G), so neighbouring
-// (similarly loaded) tiles go to different blocks; it collects its large
-// tiles 1024 candidates at a time and sorts those above kSegHugeMin first.
+// kSegWaveMax pairs, dealt out largest first: block b sorts the tiles b,
+// b + G, b + 2G, ... of the size classes in descending order (the classes
+// of k_tile_order; the ones that can hold more than kSegWaveMax pairs).
+constexpr uint32_t kSegBlockClasses = 15;  // floor(2 log2 n) >= 18, i.e. n >= 512
+static_assert(kSegWaveMax == 512 && kSegBlockClasses < kTileClasses, "size classes of k_tile_order");
+
 __global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
   __shared__ SegLds<1024, true> L;
-  __shared__ uint32_t work[1024];
-  __shared__ uint32_t n_work;
+  __shared__ uint32_t s_end[kSegBlockClasses];  // inclusive prefix of the class counts
   const uint32_t K = min(a.counters[kCntPairs], a.cap);
-  const uint32_t G = gridDim.x;
-  const uint64_t span = (uint64_t)1024 * G;
-  for (uint64_t base = 0; base < a.n_tiles; base += span) {
-    if (threadIdx.x == 0) n_work = 0;
-    __syncthreads();
-    const uint64_t tile64 = base + (uint64_t)threadIdx.x * G + blockIdx.x;
-    if (tile64 < a.n_tiles) {
-      const uint32_t tile = (uint32_t)tile64;
-      const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
-      const uint32_t n = s1 > s0 ? s1 - s0 : 0u;
-      if (n > kSegWaveMax) work[atomicAdd(&n_work, 1u)] = tile | (n > kSegHugeMin ? 0u : 0x80000000u);
+  if (threadIdx.x < 64) {
+    const uint32_t k = threadIdx.x;
+    const uint32_t cnt = k < kSegBlockClasses ? min(a.class_count[k], a.n_tiles) : 0u;
+    const uint32_t inc = wave_scan_add(cnt);
+    if (k < kSegBlockClasses) s_end[k] = inc;
+  }
+  __syncthreads();
+  const uint32_t total = s_end[kSegBlockClasses - 1];
+  uint32_t k = 0;
+  for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+    while (i >= s_end[k]) ++k;  // i only grows
+    const uint32_t first = k ? s_end[k - 1] : 0u;
+    const uint32_t tile = a.class_list[(size_t)k * a.n_tiles + (i - first)];
+    if (tile >= a.n_tiles) {
+      if (threadIdx.x == 0) atomicOr(a.err, 32u);
+      continue;
     }
-    __syncthreads();
-    const uint32_t nw = n_work;
-    for (uint32_t tier = 0; tier < 2; ++tier) {
-      for (uint32_t j = 0; j < nw; ++j) {
-        const uint32_t e = work[j];
-        if ((e >> 31) != tier) continue;
-        const uint32_t tile = e & 0x7FFFFFFFu;
-        const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
-        if (s1 > K) {
-          if (threadIdx.x == 0) atomicOr(a.err, 32u);
-          continue;
-        }
-        sort_segment(L, a, tile, s0, s1 - s0, K);
-        __syncthreads();  // LDS is reused by the next tile
-      }
+    const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
+    if (s1 <= s0 || s1 - s0 <= kSegWaveMax) continue;  // the wave kernel's
+    if (s1 > K) {
+      if (threadIdx.x == 0) atomicOr(a.err, 32u);
+      continue;
     }
+    sort_segment(L, a, tile, s0, s1 - s0, K);
+    __syncthreads();  // LDS is reused by the next tile
   }
 }
 
@@ -721,10 +721,11 @@ int device_cus() {
 hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,
-                                uint32_t* emit, uint64_t* keys_out, uint32_t* error_flag, hipStream_t s) {
+                                uint32_t* emit, uint64_t* keys_out, const uint32_t* class_count,
+                                const uint32_t* class_list, uint32_t* error_flag, hipStream_t s) {
   if (total_tiles == 0 || pair_capacity == 0) return hipSuccess;
   SegArgs a{keys_a, keys_b, vals_a, vals_b, sel, ranges, rec_of, counters, pair_capacity, emit, keys_out,
-            error_flag, total_tiles};
+            error_flag, total_tiles, class_count, class_list};
   const uint32_t G = std::min<uint32_t>(total_tiles, (uint32_t)std::max(1, device_cus()));
   hipLaunchKernelGGL(k_sort_segments_block, dim3(G), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_sort_segments_wave, dim3(div_up(total_tiles, (uint32_t)(kSegWaveBlock / 64))),
