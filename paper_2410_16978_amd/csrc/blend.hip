@@ -413,11 +413,19 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
-constexpr int kGradSlots = 10;  // u, v, conic a, b, c, opacity, r, g, b, max alpha*T
+// Per pair, the wave sums of: h dx, h dy, h dx^2, h dx dy, h dy^2, h, and the
+// three colour weights G_ch w, plus the wave maximum of w = alpha T.  Here
+// h = dL/dalpha * o * G and (dx, dy) = mean - pixel centre.  With the conic
+// (a, b, c) the screen-space gradients are linear in these sums:
+//   dL/du = -(a Shx + b Shy), dL/dv = -(b Shx + c Shy),
+//   dL/da = -Shxx / 2, dL/db = -Shxy, dL/dc = -Shyy / 2, dL/do = Sh / o,
+// so the per-pixel work needs no conic products and the conic is applied
+// once per pair after the sums.
+constexpr int kGradSlots = 10;
 
 // g_pair: [P][12] per pair, at its emission index (pair_emit of its sorted
-// position), so that a Gaussian's partials are contiguous: the 10 slots
-// above, 2 unused.
+// position), so that a Gaussian's partials are contiguous: u, v, conic a,
+// b, c, opacity, r, g, b, max alpha*T, 2 unused.
 __global__ void __launch_bounds__(256)
 k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
             const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
@@ -453,7 +461,9 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   const size_t pix = inside ? (size_t)py * V.W + px : 0;
   const size_t vpix = (size_t)vi * plane;  // views of one call share a resolution
   uint32_t plast = 0;
-  float T = 1.f, Tfin = 1.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GA = 0.f;
+  // P = sum_ch G_ch S_ch - GA Tfin, with S the colour behind the current pair:
+  // dL/dalpha = Tb (G . c) - P / (1 - alpha), and P grows by w (G . c) per pair
+  float T = 1.f, Tfin = 1.f, P = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GA = 0.f;
   if (inside) {
     plast = V.last[pix];
     if (plast > start) {
@@ -466,15 +476,13 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       // transmittance at the end of this batch, colour behind it
       T = (c_last == c) ? Tfin : tck[(size_t)(c + 1) * kBatch].x;
       const float4 sb = tck[(size_t)c * kBatch];
-      S0 = sb.y;
-      S1 = sb.z;
-      S2 = sb.w;
       if (dL_drgb) {
         G0 = dL_drgb[3 * vpix + pix];
         G1 = dL_drgb[3 * vpix + plane + pix];
         G2 = dL_drgb[3 * vpix + 2 * plane + pix];
       }
       if (dL_dalpha) GA = dL_dalpha[vpix + pix];
+      P = fmaf(G2, sb.w, fmaf(G1, sb.z, fmaf(G0, sb.y, -GA * Tfin)));
     } else {
       plast = 0;
     }
@@ -518,26 +526,20 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);
       const float Tb = T * inv1m;  // transmittance in front of this pair
       const float wv = alpha * Tb;
-      const float dalpha = G0 * (B.z * Tb - S0 * inv1m) + G1 * (B.w * Tb - S1 * inv1m) +
-                           G2 * (cbl * Tb - S2 * inv1m) + GA * Tfin * inv1m;
+      const float gcol = fmaf(G2, cbl, fmaf(G1, B.w, G0 * B.z));  // G . c
+      const float dalpha = fmaf(-inv1m, P, Tb * gcol);
       const float w = contrib ? wv : 0.f;
-      S0 = fmaf(B.z, w, S0);
-      S1 = fmaf(B.w, w, S1);
-      S2 = fmaf(cbl, w, S2);
+      P = fmaf(w, gcol, P);
       T = contrib ? Tb : T;
       float gr = G0 * w, gg = G1 * w, gbl = G2 * w;
-      const float dq = has_grad ? dalpha * (-0.5f * oG) : 0.f;
-      float go = has_grad ? dalpha * G : 0.f;
-      float gu = dq * 2.f * (A.z * dx + A.w * dy);
-      float gv = dq * 2.f * (A.w * dx + B.x * dy);
-      float ga = dq * dx * dx;
-      float gb = dq * 2.f * dx * dy;
-      float gc = dq * dy * dy;
+      const float h = has_grad ? dalpha * oG : 0.f;
+      const float hx = h * dx, hy = h * dy;
+      const float hxx = hx * dx, hxy = hx * dy, hyy = hy * dy;
       if (__ballot(contrib) == 0ull) continue;
-      // eight sums by reduce-scatter: row r of s0 holds slot {u, v, c, o}[r],
-      // row r of s1 slot {a, b, r, g}[r]; the ninth sum and the max by DPP
-      const float s0 = row_sum16(swap16_add(swap32_add(gu, gc), swap32_add(gv, go)));
-      const float s1 = row_sum16(swap16_add(swap32_add(ga, gr), swap32_add(gb, gg)));
+      // eight sums by reduce-scatter: row r of s0 holds slot {0, 1, 4, 5}[r],
+      // row r of s1 slot {2, 3, 6, 7}[r]; the ninth sum and the max by DPP
+      const float s0 = row_sum16(swap16_add(swap32_add(hx, hyy), swap32_add(hy, h)));
+      const float s1 = row_sum16(swap16_add(swap32_add(hxx, gr), swap32_add(hxy, gg)));
       gbl = wave_sum63(gbl);
       const float wmax = want_max ? wave_max63(w) : 0.f;
       const int js = j - j0;
@@ -553,9 +555,19 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
     }
     __syncthreads();
     if (tid < j1 - j0) {
-      float o[12];
+      float m[9], o[12];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) o[q] = ((part[0][q][tid] + part[1][q][tid]) + part[2][q][tid]) + part[3][q][tid];
+      for (int q = 0; q < 9; ++q) m[q] = ((part[0][q][tid] + part[1][q][tid]) + part[2][q][tid]) + part[3][q][tid];
+      const float4 A = L.a[j0 + tid], B = L.b[j0 + tid];
+      o[0] = -fmaf(A.z, m[0], A.w * m[1]);
+      o[1] = -fmaf(A.w, m[0], B.x * m[1]);
+      o[2] = -0.5f * m[2];
+      o[3] = -m[3];
+      o[4] = -0.5f * m[4];
+      o[5] = B.y > 0.f ? m[5] / B.y : 0.f;
+      o[6] = m[6];
+      o[7] = m[7];
+      o[8] = m[8];
       o[9] = fmaxf(fmaxf(part[0][9][tid], part[1][9][tid]), fmaxf(part[2][9][tid], part[3][9][tid]));
       o[10] = 0.f;
       o[11] = 0.f;
