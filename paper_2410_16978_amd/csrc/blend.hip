@@ -507,50 +507,86 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   // back to front in sub-batches of kSub pairs; after each, the four wave
   // partials of its pairs are summed in a fixed order and written out
   const int n_sub = (n + kSub - 1) / kSub;
+  // where the 18-value reduce-scatter leaves each sum: rows 0-1 hold the back
+  // pair of a step, rows 2-3 the front one; lane bits 3, 2 and the row's
+  // parity pick one of the first eight sums, lane bit 1 the ninth
+  const int row = lane >> 4;
+  const int q_lane = (lane & 2) ? 8 : 2 * (((lane >> 2) & 1) * 2 + ((lane >> 3) & 1)) + (row & 1);
+  const bool writer = !(lane & 1) && (!(lane & 2) || ((lane & 12) == 0 && !(row & 1)));
+  float* part_lane = &part[wave][q_lane][0];
+  // one pair for this pixel: updates T and P (back to front) and returns the
+  // nine per-pixel terms; inactive pairs give zeros
+  auto eval = [&](int j, bool valid, float (&v)[9], float& w) -> bool {
+    const uint32_t kk = start + (uint32_t)j;
+    // branch-free: every lane evaluates the pair, selects keep what counts
+    const float4 A = L.a[j], B = L.b[j];
+    const float cbl = L.c[j];
+    const float dx = A.x - fx, dy = A.y - fy;
+    const float power = pair_power(A, B, dx, dy);
+    const float G = __expf(power);
+    const float oG = B.y * G;
+    const float alpha = fminf(kAlphaMax, oG);
+    const bool contrib = valid && kk < plast && power <= 0.f && alpha >= kAlphaMin;
+    const bool has_grad = contrib && !(oG > kAlphaMax);  // alpha not clamped: it has a gradient
+    const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);
+    const float Tb = T * inv1m;  // transmittance in front of this pair
+    const float wv = alpha * Tb;
+    const float gcol = fmaf(G2, cbl, fmaf(G1, B.w, G0 * B.z));  // G . c
+    const float dalpha = fmaf(-inv1m, P, Tb * gcol);
+    w = contrib ? wv : 0.f;
+    P = fmaf(w, gcol, P);
+    T = contrib ? Tb : T;
+    const float h = has_grad ? dalpha * oG : 0.f;
+    const float hx = h * dx, hy = h * dy;
+    v[0] = hx;
+    v[1] = hy;
+    v[2] = hx * dx;
+    v[3] = hx * dy;
+    v[4] = hy * dy;
+    v[5] = h;
+    v[6] = G0 * w;
+    v[7] = G1 * w;
+    v[8] = G2 * w;
+    return contrib;
+  };
   int t = cnt - 1;
   for (int sb = n_sub - 1; sb >= 0; --sb) {
     const int j0 = sb * kSub, j1 = min(n, j0 + kSub);
-    for (; t >= 0 && (int)list[t] >= j0; --t) {
-      const int j = list[t];
-      const uint32_t kk = start + (uint32_t)j;
-      // branch-free: every lane evaluates the pair, selects keep what counts
-      const float4 A = L.a[j], B = L.b[j];
-      const float cbl = L.c[j];
-      const float dx = A.x - fx, dy = A.y - fy;
-      const float power = pair_power(A, B, dx, dy);
-      const float G = __expf(power);
-      const float oG = B.y * G;
-      const float alpha = fminf(kAlphaMax, oG);
-      const bool contrib = kk < plast && power <= 0.f && alpha >= kAlphaMin;
-      const bool has_grad = contrib && !(oG > kAlphaMax);  // alpha not clamped: it has a gradient
-      const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);
-      const float Tb = T * inv1m;  // transmittance in front of this pair
-      const float wv = alpha * Tb;
-      const float gcol = fmaf(G2, cbl, fmaf(G1, B.w, G0 * B.z));  // G . c
-      const float dalpha = fmaf(-inv1m, P, Tb * gcol);
-      const float w = contrib ? wv : 0.f;
-      P = fmaf(w, gcol, P);
-      T = contrib ? Tb : T;
-      float gr = G0 * w, gg = G1 * w, gbl = G2 * w;
-      const float h = has_grad ? dalpha * oG : 0.f;
-      const float hx = h * dx, hy = h * dy;
-      const float hxx = hx * dx, hxy = hx * dy, hyy = hy * dy;
-      if (__ballot(contrib) == 0ull) continue;
-      // eight sums by reduce-scatter: row r of s0 holds slot {0, 1, 4, 5}[r],
-      // row r of s1 slot {2, 3, 6, 7}[r]; the ninth sum and the max by DPP
-      const float s0 = row_sum16(swap16_add(swap32_add(hx, hyy), swap32_add(hy, h)));
-      const float s1 = row_sum16(swap16_add(swap32_add(hxx, gr), swap32_add(hxy, gg)));
-      gbl = wave_sum63(gbl);
-      const float wmax = want_max ? wave_max63(w) : 0.f;
-      const int js = j - j0;
-      if ((lane & 15) == 0) {
-        const int row = lane >> 4, slot = row + 2 * (row >> 1);  // 0, 1, 4, 5
-        part[wave][slot][js] = s0;
-        part[wave][slot + 2][js] = s1;
-      }
+    // two pairs per step (the second, in front, may be absent)
+    while (t >= 0) {
+      const int ja = list[t];
+      if (ja < j0) break;
+      const int jn = t > 0 ? (int)list[t - 1] : -1;
+      const bool hb = jn >= j0;
+      const int jb = hb ? jn : ja;
+      t -= hb ? 2 : 1;
+      float va[9], vb[9], wa, wb;
+      const bool ca = eval(ja, true, va, wa);
+      const bool cb = eval(jb, hb, vb, wb);
+      if (__ballot(ca || cb) == 0ull) continue;
+      // reduce-scatter: halves (back | front pair), then row pairs, then
+      // within rows by mirror exchanges that keep one operand per lane half
+      float X[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) X[q] = swap32_add(va[q], vb[q]);
+      const float Y0 = swap16_add(X[0], X[1]), Y1 = swap16_add(X[2], X[3]);
+      const float Y2 = swap16_add(X[4], X[5]), Y3 = swap16_add(X[6], X[7]);
+      const float Y4 = swap16_add(X[8], X[8]);
+      const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+      const float Z0 = (b3 ? Y1 : Y0) + dpp<0x140, 0xF>(b3 ? Y0 : Y1);  // row_mirror
+      const float Z1 = (b3 ? Y3 : Y2) + dpp<0x140, 0xF>(b3 ? Y2 : Y3);
+      const float Z2 = Y4 + dpp<0x140, 0xF>(Y4);
+      const float W0 = (b2 ? Z1 : Z0) + dpp<0x141, 0xF>(b2 ? Z0 : Z1);  // row_half_mirror
+      const float W1 = Z2 + dpp<0x141, 0xF>(Z2);
+      float R = (b1 ? W1 : W0) + dpp<0x4E, 0xF>(b1 ? W0 : W1);  // quad_perm [2,3,0,1]
+      R += dpp<0xB1, 0xF>(R);                                     // quad_perm [1,0,3,2]
+      const float mxa = want_max ? wave_max63(wa) : 0.f;
+      const float mxb = want_max ? wave_max63(wb) : 0.f;
+      const bool front = row >= 2;
+      if (writer && (!front || hb)) part_lane[(front ? jb : ja) - j0] = R;
       if (lane == 63) {
-        part[wave][8][js] = gbl;
-        part[wave][9][js] = wmax;
+        part[wave][9][ja - j0] = mxa;
+        if (hb) part[wave][9][jb - j0] = mxb;
       }
     }
     __syncthreads();
