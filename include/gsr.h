@@ -137,7 +137,10 @@ typedef struct {
  *                             batches up to the one in which the tile's
  *                             last pixel stops (later ones are never read)
  *   batch_map   uint32[X + 1 + B]  X + 1 unused words, then for each
- *                             checkpoint batch index 1 + its tile (0: none);
+ *                             checkpoint batch index a word whose low 24
+ *                             bits hold 1 + its tile (0: none) and whose top
+ *                             byte holds the batch's work class (the
+ *                             backward runs the heavier batches first);
  *                             tile t's batches have the indices
  *                             floor(ranges[t][0] / 256) + t + c
  *   counters    uint32[4]     device: pairs K, overflow flag, error flag,
@@ -221,7 +224,8 @@ gsr_status gsr_activate(const gsr_model* model, float* scale_out, float* opacity
  * dropped, state->counters[1] is set and the image is incomplete - check
  * with gsr_forward_check after synchronising.
  * ws: scratch of at least gsr_workspace_size(...) bytes, 256-byte aligned.
- * timer: optional (NULL), see gsr_timer. */
+ * timer: optional (NULL), see gsr_timer.  GSR_EINVAL when the total tile
+ * count X is 2^24 - 1 or more (the batch map holds tiles in 24 bits). */
 gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
                                  const gsr_view_state* views, gsr_fwd_state* state,
                                  void* ws, size_t ws_bytes, float* rgb, float* alpha,

@@ -53,6 +53,8 @@ struct PipeBufs {
   uint32_t* class_list = nullptr;  // [kTileClasses][X] tiles by size class
   float* g_pair = nullptr;
   float* g_col = nullptr;    // [R][3] colour gradient of each record (backward)
+  uint32_t* order_cnt = nullptr;   // [kBatchClasses] batches per work class (backward)
+  uint32_t* order_list = nullptr;  // [kBatchClasses][batch capacity] batch indices by class (backward)
   // batch only (the single-call path keeps these in the caller's state)
   float* records = nullptr;
   uint32_t* vals = nullptr;
@@ -79,6 +81,8 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   if (backward) {
     b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
     b.g_col = c.take<float>(3 * std::max<size_t>(R, 1));
+    b.order_cnt = c.take<uint32_t>(kBatchClasses);
+    b.order_list = c.take<uint32_t>(kBatchClasses * (P / kBatch + X + 1));
   }
   if (batch) {
     b.offsets = c.take<uint32_t>(R + 1);
@@ -349,7 +353,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   const uint32_t P = state->pair_capacity;
   const uint32_t tiles_per_view = tiles_of(cams[0]);
   const uint64_t X = (uint64_t)tiles_per_view * n_views;
-  if (X >= (1ull << 31) || state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
+  if (X >= kBatchTileMask || state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
   const size_t plane = (size_t)W * H;
   Carver c(ws);
   PipeBufs b;
@@ -479,18 +483,26 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
     ids[v] = v;
   }
   if (n == 0) return GSR_OK;
-  if (state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
+  if (X >= kBatchTileMask || state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
+  // batch indices are below P / 256 + X + 1 (the order list's row length)
+  const uint32_t n_batches = std::min(state->batch_capacity, gsr_batch_capacity(P, (uint32_t)X));
   {
     WordUpload up;
     HIP_TRY(upload_views(b.views, hv.data(), n_views, up, s));
-    if (up.n) HIP_TRY(launch_clear_multi(ClearSet{}, s, &up));
+    ClearSet cs{};
+    cs.p[0] = b.order_cnt;
+    cs.n[0] = kBatchClasses;
+    cs.n_ranges = 1;
+    HIP_TRY(launch_clear_multi(cs, s, up.n ? &up : nullptr));
   }
   {
     StageScope sc(timer, GSR_STAGE_BLEND_BWD, s);
+    const uint32_t* batch_tile = state->batch_map + X + 1;
+    HIP_TRY(launch_batch_order(batch_tile, n_batches, b.order_cnt, b.order_list, s));
     HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
-                             state->ranges, reinterpret_cast<const float4*>(state->checkpoints),
-                             state->batch_map + X + 1, state->batch_capacity, dL_drgb, dL_dalpha,
-                             state->pair_emit, b.g_pair, max_contrib != nullptr, s));
+                             state->ranges, reinterpret_cast<const float4*>(state->checkpoints), batch_tile,
+                             n_batches, b.order_cnt, b.order_list, dL_drgb, dL_dalpha, state->pair_emit, b.g_pair,
+                             max_contrib != nullptr, s));
   }
   const ModelD md = make_model(*model);
   {

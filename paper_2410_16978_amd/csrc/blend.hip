@@ -182,7 +182,10 @@ __device__ __forceinline__ float pair_alpha(const float4 B, float power) {
 // pixel's index in the backward's 8 x 8-quadrant layout (ckpt may be null: render
 // only, then batch_tile is not written).  Tile t's batches have the indices
 // first_batch(t) + c, c = 0, 1, ...: distinct over the tiles and below
-// P / 256 + X + 1 for any pair count P.
+// P / 256 + X + 1 for any pair count P.  Each batch's word in batch_tile holds
+// 1 + tile and, in the top byte, a work class for the backward's order: from
+// the longest list any wave stepped through in the batch (16 classes of 16
+// entries, heaviest first), the last class for batches never reached.
 constexpr int kQuadPix = 4;  // sub-tile edge
 
 // Checkpoint batch index of a tile's first batch: floor(start / 256) + t.
@@ -190,6 +193,11 @@ constexpr int kQuadPix = 4;  // sub-tile edge
 // starts after tile t's last batch.
 __device__ __forceinline__ uint32_t first_batch(uint32_t tile, uint32_t tile_start) {
   return tile_start / (uint32_t)kBatch + tile;
+}
+
+__device__ __forceinline__ uint32_t batch_word(uint32_t tile, uint32_t est) {
+  const uint32_t cls = est == 0 ? kBatchClasses - 1 : (kBatch - min(est, (uint32_t)kBatch)) >> 4;
+  return (tile + 1u) | (cls << 24);
 }
 
 __device__ __forceinline__ float quad_shift1(float x, int slot) {  // x of slot - 1, 1 for slot 0
@@ -258,11 +266,8 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   const uint32_t t_end = min(ranges[2 * tile + 1], cap);
   const uint32_t t_start = min(ranges[2 * tile], t_end);
   const uint32_t b0 = first_batch(tile, t_start);
-  if (ckpt) {  // the backward's map from batch index to tile (1 + tile; 0 = no batch)
-    const uint32_t nb = (t_end - t_start + (uint32_t)kBatch - 1) / (uint32_t)kBatch;
-    for (uint32_t c = tid; c < nb; c += 1024)
-      if (b0 + c < batch_cap) batch_tile[b0 + c] = tile + 1u;
-  }
+  __shared__ uint32_t s_est;  // longest list stepped through in the current batch
+  if (tid == 0) s_est = 0;
   uint8_t* list = lists[wave];
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = 0;
@@ -270,6 +275,10 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   uint32_t n_ck = 0;  // batches processed (checkpoints written)
   for (uint32_t start = t_start, c = 0; start < t_end; start += kBatch, ++c) {
     if (!__syncthreads_or(!done)) break;  // also orders the previous batch's LDS reads before the refill
+    if (ckpt && tid == 0 && c > 0) {
+      if (b0 + c - 1 < batch_cap) batch_tile[b0 + c - 1] = batch_word(tile, s_est);
+      s_est = 0;
+    }
     const int n = (int)min((uint32_t)kBatch, t_end - start);
     if (tid < kBatch) put(L, fetch(records, n_rec, vals, start + tid, tid < n), tid < n, tid);
     __syncthreads();
@@ -277,6 +286,7 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
     float D0 = 0.f, D1 = 0.f, D2 = 0.f;
     uint32_t lst = 0;
     const int cnt = __ballot(!done) ? wave_list(L, list, n, qx0, qx1, qy0, qy1) : 0;
+    int stepped = cnt;
     for (int t0 = 0; t0 < cnt; t0 += 4) {
       const int te = t0 + slot;
       const bool has = te < cnt;
@@ -305,8 +315,12 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       const float Pe = first == 0 ? 1.f : first == 1 ? P0 : first == 2 ? P1 : first == 3 ? P2 : P3;
       T = (done || first == 0) ? T : T * Pe;
       done = done || first < 4;
-      if (__ballot(!done) == 0ull) break;
+      if (__ballot(!done) == 0ull) {
+        stepped = min(cnt, t0 + 4);
+        break;
+      }
     }
+    if (ckpt && lane == 0 && stepped > 0) atomicMax(&s_est, (uint32_t)stepped);
     D0 = quad_sum(D0);
     D1 = quad_sum(D1);
     D2 = quad_sum(D2);
@@ -317,6 +331,14 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
     last = lst ? lst : last;
     if (ckpt && slot == 0 && b0 + c < batch_cap) ckpt[(size_t)(b0 + c) * kBatch + bidx] = make_float4(T0, D0, D1, D2);
     n_ck = c + 1;
+  }
+  if (ckpt) {
+    // the last batch reached, then the ones never reached
+    __syncthreads();
+    if (tid == 0 && n_ck > 0 && b0 + n_ck - 1 < batch_cap) batch_tile[b0 + n_ck - 1] = batch_word(tile, s_est);
+    const uint32_t nb = (t_end - t_start + (uint32_t)kBatch - 1) / (uint32_t)kBatch;
+    for (uint32_t c = n_ck + tid; c < nb; c += 1024)
+      if (b0 + c < batch_cap) batch_tile[b0 + c] = batch_word(tile, 0);
   }
   if (ckpt && slot == 0) {
     // replace each batch's colour by the colour behind the batch: the
@@ -426,19 +448,74 @@ constexpr int kGradSlots = 10;
 // g_pair: [P][12] per pair, at its emission index (pair_emit of its sorted
 // position), so that a Gaussian's partials are contiguous: u, v, conic a,
 // b, c, opacity, r, g, b, max alpha*T, 2 unused.
+// The backward's block order: batches by work class, heaviest first, so that
+// the longest blocks start early instead of ending the launch.  Each block
+// buckets 4096 batch words; per class one atomic reserves its range of the
+// class's list (order_list[k][n_batches]); the order inside a class is
+// arbitrary (each batch's results do not depend on it).
+constexpr uint32_t kOrderItems = 4;
+
+__global__ void __launch_bounds__(1024)
+k_batch_order(const uint32_t* __restrict__ batch_tile, uint32_t n, uint32_t* __restrict__ order_cnt,
+              uint32_t* __restrict__ order_list) {
+  __shared__ uint32_t s_cnt[kBatchClasses], s_base[kBatchClasses];
+  const uint32_t tid = threadIdx.x;
+  if (tid < kBatchClasses) s_cnt[tid] = 0;
+  __syncthreads();
+  const uint32_t i0 = blockIdx.x * (1024u * kOrderItems) + tid;
+  uint32_t cls[kOrderItems], rank[kOrderItems];
+#pragma unroll
+  for (uint32_t r = 0; r < kOrderItems; ++r) {
+    const uint32_t i = i0 + r * 1024u;
+    const uint32_t word = i < n ? batch_tile[i] : 0u;
+    cls[r] = (word & kBatchTileMask) ? min(word >> 24, kBatchClasses - 1) : kBatchClasses;
+    if (cls[r] < kBatchClasses) rank[r] = atomicAdd(&s_cnt[cls[r]], 1u);
+  }
+  __syncthreads();
+  if (tid < kBatchClasses) s_base[tid] = s_cnt[tid] ? atomicAdd(&order_cnt[tid], s_cnt[tid]) : 0u;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r = 0; r < kOrderItems; ++r)
+    if (cls[r] < kBatchClasses) order_list[(size_t)cls[r] * n + s_base[cls[r]] + rank[r]] = i0 + r * 1024u;
+}
+
+hipError_t launch_batch_order(const uint32_t* batch_tile, uint32_t n_batches, uint32_t* order_cnt,
+                              uint32_t* order_list, hipStream_t s) {
+  if (n_batches == 0) return hipSuccess;
+  const uint32_t per = 1024u * kOrderItems;
+  hipLaunchKernelGGL(k_batch_order, dim3((n_batches + per - 1) / per), dim3(1024), 0, s, batch_tile, n_batches,
+                     order_cnt, order_list);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256)
 k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restrict__ records, uint32_t n_rec,
             const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
             const uint32_t* __restrict__ ranges, const float4* __restrict__ ckpt,
-            const uint32_t* __restrict__ batch_tile, const float* __restrict__ dL_drgb,
+            const uint32_t* __restrict__ batch_tile, uint32_t n_batches, const uint32_t* __restrict__ order_cnt,
+            const uint32_t* __restrict__ order_list, const float* __restrict__ dL_drgb,
             const float* __restrict__ dL_dalpha, const uint32_t* __restrict__ pair_emit,
             float* __restrict__ g_pair, int want_max) {
   __shared__ BatchLds L;
   constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
   __shared__ float part[4][kGradSlots][kSub];
   __shared__ uint8_t lists[4][kBatch];
-  const uint32_t bi = blockIdx.x;
-  const uint32_t tile_p1 = batch_tile[bi];
+  // block b takes the b-th batch of the heaviest-first order: the first wave
+  // scans the class counts and finds b's class
+  __shared__ uint32_t s_bi;
+  if (threadIdx.x < 64) {
+    const uint32_t k = threadIdx.x;
+    const uint32_t cnt = k < kBatchClasses ? min(order_cnt[k], n_batches) : 0u;
+    const uint32_t inc = wave_scan_add(cnt);
+    const uint32_t b = blockIdx.x;
+    const bool here = k < kBatchClasses && b >= inc - cnt && b < inc;
+    if (here) s_bi = order_list[(size_t)k * n_batches + (b - (inc - cnt))];
+    if (__ballot(here) == 0ull && threadIdx.x == 0) s_bi = 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  const uint32_t bi = s_bi;
+  if (bi >= n_batches) return;
+  const uint32_t tile_p1 = batch_tile[bi] & kBatchTileMask;
   if (tile_p1 == 0) return;  // no tile's batch
   const uint32_t tile = tile_p1 - 1u;
   const uint32_t c = bi - first_batch(tile, ranges[2 * tile]);
@@ -622,14 +699,14 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
 
 hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
-                            const float4* ckpt, const uint32_t* batch_tile, uint32_t batch_cap,
-                            const float* dL_drgb,
+                            const float4* ckpt, const uint32_t* batch_tile, uint32_t n_batches,
+                            const uint32_t* order_cnt, const uint32_t* order_list, const float* dL_drgb,
                             const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair, bool want_max,
                             hipStream_t s) {
-  if (batch_cap == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_blend_bwd, dim3(batch_cap), dim3(256), 0, s, views_dev, n_views, records, n_rec, pair_vals,
-                     sel, cap, ranges, ckpt, batch_tile, dL_drgb, dL_dalpha, pair_emit, g_pair,
-                     want_max ? 1 : 0);
+  if (n_batches == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_blend_bwd, dim3(n_batches), dim3(256), 0, s, views_dev, n_views, records, n_rec, pair_vals,
+                     sel, cap, ranges, ckpt, batch_tile, n_batches, order_cnt, order_list, dL_drgb, dL_dalpha,
+                     pair_emit, g_pair, want_max ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -17,6 +17,11 @@ constexpr int kSortItems = 8;         // per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kBatch = 256;          // pairs per blend batch (one per thread of a tile block)
 constexpr uint32_t kTileClasses = 34;  // tile size classes of the forward's largest-first order
+// Work classes of the backward's batches (heaviest first; the last class holds
+// the batches the forward never reached), kept in the top byte of the
+// batch-to-tile words; the low 24 bits hold 1 + tile.
+constexpr uint32_t kBatchClasses = 17;
+constexpr uint32_t kBatchTileMask = 0xFFFFFFu;
 constexpr uint32_t kSegWaveMax = 512;  // tiles with more pairs are depth-sorted by a whole block
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -162,9 +167,12 @@ uint32_t l1_loss_blocks(int n_views, int hw);
 hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
                           const float* t_alpha, const float* bg_host, float* partials, float* loss,
                           const float* g_loss, float* dL_drgb, float* dL_dalpha, hipStream_t s);
+hipError_t launch_batch_order(const uint32_t* batch_tile, uint32_t n_batches, uint32_t* order_cnt,
+                              uint32_t* order_list, hipStream_t s);
 hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
-                            const float4* ckpt, const uint32_t* batch_tile, uint32_t batch_cap,
+                            const float4* ckpt, const uint32_t* batch_tile, uint32_t n_batches,
+                            const uint32_t* order_cnt, const uint32_t* order_list,
                             const float* dL_drgb, const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair,
                             bool want_max, hipStream_t s);
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
