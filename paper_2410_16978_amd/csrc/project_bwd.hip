@@ -20,13 +20,25 @@ __device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restri
                                             const float* __restrict__ g_pair, uint32_t K, float* g, float& wmax) {
   for (int c = 0; c < 9; ++c) g[c] = 0.f;
   const uint32_t e1 = min(offsets[r + 1], K);
-  for (uint32_t e = offsets[r]; e < e1; ++e) {
-    const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)e * 12);
-    const float4 x0 = src[0], x1 = src[1], x2 = src[2];
+  auto add = [&](const float4 x0, const float4 x1, const float4 x2) {
     g[0] += x0.x; g[1] += x0.y; g[2] += x0.z; g[3] += x0.w;
     g[4] += x1.x; g[5] += x1.y; g[6] += x1.z; g[7] += x1.w;
     g[8] += x2.x;
     wmax = fmaxf(wmax, x2.y);
+  };
+  uint32_t e = offsets[r];
+  // four pairs' loads in flight per step (same summation order)
+  for (; e + 4 <= e1; e += 4) {
+    const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)e * 12);
+    float4 x[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) add(x[3 * k], x[3 * k + 1], x[3 * k + 2]);
+  }
+  for (; e < e1; ++e) {
+    const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)e * 12);
+    add(src[0], src[1], src[2]);
   }
 }
 
