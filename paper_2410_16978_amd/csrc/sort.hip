@@ -112,6 +112,9 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
   // the exclusive global offset of digit t for this pass.
   if (t == 0) s_triv = 0;
   __syncthreads();
+  // the block's ticket is drawn while the counts load (a no-op pass leaves
+  // its tickets unused)
+  if (t == 511 % kSortThreads) s_bid = atomicAdd(&pass_ctr[pass], 1u);
   uint32_t hc = 0, hinc = 0;
   if (t < 256) {
     for (int p = pass_begin; p < pass_end; ++p)
@@ -120,7 +123,6 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
     hinc = wave_incl_scan(hc);
     if (lane == 63) s_hw[wave] = hinc;
   }
-  if (t == 0) s_bid = 0xFFFFFFFFu;
   __syncthreads();
   const uint32_t triv = s_triv;
   uint32_t moved_before = 0, moved_all = 0;
@@ -131,7 +133,6 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
   }
   if (pass == pass_end - 1 && blockIdx.x == 0 && t == 0) *sel_out = moved_all & 1u;
   if ((triv >> pass) & 1u) return;
-  if (t == 0) s_bid = atomicAdd(&pass_ctr[pass], 1u);
   for (int i = t; i < kSortWaves * 256; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
   __syncthreads();
   const uint32_t bid = s_bid;
@@ -202,22 +203,38 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
       run += cw[w];
     }
     if (bid > 0) {
+      // look back four predecessors per step (block 0 is always inclusive,
+      // so the walk ends at j >= 0)
+      constexpr int kWin = 4;
       int j = (int)bid - 1;
       uint32_t spins = 0;
       while (j >= 0) {
-        const uint32_t sv = __hip_atomic_load(&st[(size_t)j * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t f = sv & ~kValueMask;
-        if (f == 0) {
+        uint32_t sv[kWin];
+#pragma unroll
+        for (int k = 0; k < kWin; ++k)
+          sv[k] = j - k >= 0 ? __hip_atomic_load(&st[(size_t)(j - k) * 256 + t], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : 0u;
+        int used = 0;
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) {
+          if (found || used < k) break;
+          const uint32_t f = sv[k] & ~kValueMask;
+          if (f == 0) break;
+          excl += sv[k] & kValueMask;
+          used = k + 1;
+          found = f == kFlagIncl;
+        }
+        if (found) break;
+        j -= used;
+        if (used == 0) {
           if (++spins > kSpinLimit) {
             atomicOr(err, 1u);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        excl += sv & kValueMask;
-        if (f == kFlagIncl) break;
-        --j;
       }
       __hip_atomic_store(&st[(size_t)bid * 256 + t], kFlagIncl | (excl + cnt), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
