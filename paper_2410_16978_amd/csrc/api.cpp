@@ -35,7 +35,8 @@ struct SortCtl {
   uint32_t pass_ctr[kMaxSortPasses];
   uint32_t scan_ticket;
   uint32_t tile_class[kTileClasses];  // tiles per size class (forward order)
-  uint32_t pad[7];
+  uint32_t seg_ticket;                // next large tile of the block depth sort
+  uint32_t pad[6];
 };
 
 struct PipeBufs {
@@ -419,7 +420,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->sort_sel,
                                  state->ranges, (uint32_t)X, b.rec_of, state->counters, P, state->pair_emit,
                                  debug ? debug->keys_sorted : nullptr, b.ctl->tile_class, b.class_list,
-                                 state->counters + kCntError, s));
+                                 &b.ctl->seg_ticket, state->counters + kCntError, s));
   }
   uint32_t* batch_tile = state->batch_map + X + 1;
   {
@@ -622,7 +623,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
     StageScope sc(timer, GSR_STAGE_SORT, s);
     HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, b.vals, b.vals + P, b.sel, b.ranges, (uint32_t)bp.X, b.rec_of,
                                  b.counters, P, nullptr, nullptr, b.ctl->tile_class, b.class_list,
-                                 b.counters + kCntError, s));
+                                 &b.ctl->seg_ticket, b.counters + kCntError, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);

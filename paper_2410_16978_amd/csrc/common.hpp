@@ -152,7 +152,8 @@ hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* va
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,
                                 uint32_t* emit, uint64_t* keys_out, const uint32_t* class_count,
-                                const uint32_t* class_list, uint32_t* error_flag, hipStream_t s);
+                                const uint32_t* class_list, uint32_t* seg_ticket, uint32_t* error_flag,
+                                hipStream_t s);
 hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* class_count,
                              uint32_t* class_list, hipStream_t s);
 hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const uint32_t* sel,

@@ -450,6 +450,7 @@ struct SegArgs {
   uint32_t n_tiles;
   const uint32_t* class_count;  // tiles per size class, largest first (k_tile_order)
   const uint32_t* class_list;   // [kTileClasses][n_tiles]
+  uint32_t* ticket;             // zero on entry: large tiles handed out after the first G
 };
 
 // Sorts one screen tile's segment [s0, s0 + n) (already grouped by tile, in
@@ -701,23 +702,31 @@ __global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
   }
   __syncthreads();
   const uint32_t total = s_end[kSegBlockClasses - 1];
+  // block b starts with item b; later items go to whichever block is free
+  // first, so a block holding one of the largest tiles takes no second one
+  __shared__ uint32_t s_next;
   uint32_t k = 0;
-  for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
-    while (i >= s_end[k]) ++k;  // i only grows
+  for (uint32_t i = blockIdx.x; i < total;) {
+    while (i >= s_end[k]) ++k;  // a block's items only grow
     const uint32_t first = k ? s_end[k - 1] : 0u;
     const uint32_t tile = a.class_list[(size_t)k * a.n_tiles + (i - first)];
-    if (tile >= a.n_tiles) {
-      if (threadIdx.x == 0) atomicOr(a.err, 32u);
-      continue;
+    uint32_t s0 = 0, s1 = 0;
+    if (tile < a.n_tiles) {
+      s0 = a.ranges[2 * tile];
+      s1 = a.ranges[2 * tile + 1];
+    } else if (threadIdx.x == 0) {
+      atomicOr(a.err, 32u);
     }
-    const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
-    if (s1 <= s0 || s1 - s0 <= kSegWaveMax) continue;  // the wave kernel's
-    if (s1 > K) {
-      if (threadIdx.x == 0) atomicOr(a.err, 32u);
-      continue;
+    if (s1 > s0 && s1 - s0 > kSegWaveMax) {  // smaller segments are the wave kernel's
+      if (s1 <= K)
+        sort_segment(L, a, tile, s0, s1 - s0, K);
+      else if (threadIdx.x == 0)
+        atomicOr(a.err, 32u);
     }
-    sort_segment(L, a, tile, s0, s1 - s0, K);
+    if (threadIdx.x == 0) s_next = gridDim.x + atomicAdd(a.ticket, 1u);
     __syncthreads();  // LDS is reused by the next tile
+    i = s_next;
+    __syncthreads();
   }
 }
 
@@ -739,10 +748,11 @@ hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* va
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,
                                 uint32_t* emit, uint64_t* keys_out, const uint32_t* class_count,
-                                const uint32_t* class_list, uint32_t* error_flag, hipStream_t s) {
+                                const uint32_t* class_list, uint32_t* seg_ticket, uint32_t* error_flag,
+                                hipStream_t s) {
   if (total_tiles == 0 || pair_capacity == 0) return hipSuccess;
   SegArgs a{keys_a, keys_b, vals_a, vals_b, sel, ranges, rec_of, counters, pair_capacity, emit, keys_out,
-            error_flag, total_tiles, class_count, class_list};
+            error_flag, total_tiles, class_count, class_list, seg_ticket};
   const uint32_t G = std::min<uint32_t>(total_tiles, (uint32_t)std::max(1, device_cus()));
   hipLaunchKernelGGL(k_sort_segments_block, dim3(G), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_sort_segments_wave, dim3(div_up(total_tiles, (uint32_t)(kSegWaveBlock / 64))),
