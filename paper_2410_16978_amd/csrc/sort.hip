@@ -490,26 +490,23 @@ __device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint
   uint32_t key[kSegItems], val[kSegItems], rec[kSegItems], pos[kSegItems];
   if (n <= (uint32_t)kCap) {
     const int I = (int)div_up(n, (uint32_t)THREADS);
-    uint32_t diff = 0;
+    // branch-free loads (indices clamped into the segment) so that all of
+    // them are in flight at once
+    uint32_t diff = 0, bad = 0;
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
-      key[r] = 0;
-      val[r] = 0;
-      rec[r] = 0;
-      if (r >= I) break;
-      const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-      if (idx < n) {
-        key[r] = (uint32_t)kin[s0 + idx];
-        val[r] = vals[s0 + idx];
-        diff |= key[r] ^ ref;
-      }
+      // items past the segment (or r >= I) reload its last entry: one cached line
+      const uint32_t ic = min((uint32_t)(wave * I + r) * 64u + lane, n - 1u);
+      key[r] = (uint32_t)kin[s0 + ic];
+      val[r] = vals[s0 + ic];
     }
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
-      if (r >= I) break;
-      const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-      if (idx < n) rec[r] = record_of(val[r]);  // gathered while the passes run
+      bad |= val[r] >= K ? 1u : 0u;
+      rec[r] = a.rec_of[min(val[r], K - 1u)];  // gathered while the passes run
+      diff |= key[r] ^ ref;                    // duplicates of real keys add nothing
     }
+    if (bad) atomicOr(err, 32u);
     const uint32_t vary = seg_block_or(L, diff);
     int buf = 0;
     for (int p = 0; p < 4; ++p) {
