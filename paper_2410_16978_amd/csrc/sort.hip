@@ -453,11 +453,240 @@ struct SegArgs {
   uint32_t* ticket;             // zero on entry: large tiles handed out after the first G
 };
 
-// Sorts one screen tile's segment [s0, s0 + n) (already grouped by tile, in
-// emission order) by depth bits, stably, and writes vals[k] = record id,
-// emit[k] = emission index (if emit), keys_out[k] = full key (if keys_out).
-// The keys buffer of the other ping-pong side is scratch for chunked
-// segments.
+// Digit of DBITS bits: the lanes holding the same digit (and valid).
+template <int DBITS>
+__device__ __forceinline__ uint64_t match_digit_bits(uint32_t d, bool valid) {
+  const uint64_t vb = __ballot(valid);
+  uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
+#pragma unroll
+  for (int b = 0; b < DBITS; ++b) {
+    const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)d, (unsigned)b, 1u);
+    const uint64_t bal = __ballot(s != 0u);
+    lo = __builtin_amdgcn_bitop3_b32((uint32_t)bal, s, lo, 0x82);
+    hi = __builtin_amdgcn_bitop3_b32((uint32_t)(bal >> 32), s, hi, 0x82);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Segments that fit in LDS are sorted on packed items: (depth bits minus the
+// segment's smallest) << 16 | index in the segment, with digits of DBITS
+// bits; only as many passes as the depth range needs (a range below
+// 2^(3 DBITS) takes three).  The emission index and record id stay in LDS by
+// segment index and are looked up once at the end.
+template <int THREADS, int DBITS>
+struct SegLdsP {
+  static constexpr int kWaves = THREADS / 64;
+  static constexpr int kCap = THREADS * kSegItems;
+  static constexpr int kDigits = 1 << DBITS;
+  uint64_t item[kCap];
+  uint32_t val[kCap];
+  uint32_t rec[kCap];
+  uint16_t cnt[kWaves][kDigits];  // per-wave digit counts, then offsets
+  uint32_t start[kDigits];        // first position of every digit
+  uint32_t wsum[kWaves];
+  uint32_t red[2][kWaves];
+};
+
+// Positions of this thread's items (entries wave * I * 64 + r * 64 + lane,
+// r < I, valid below n) when the segment is stably ordered by the digit at
+// `shift`.  L.cnt must be zero on entry; it holds offsets on return.
+template <int THREADS, int DBITS>
+__device__ __forceinline__ void seg_rank_p(SegLdsP<THREADS, DBITS>& L, const uint64_t (&item)[kSegItems], int I,
+                                           uint32_t n, int shift, uint32_t (&pos)[kSegItems]) {
+  constexpr int D = 1 << DBITS;
+  constexpr int DPT = D >= THREADS ? D / THREADS : 1;  // digits per owner thread
+  constexpr int OWNERS = D / DPT;
+  constexpr int W = THREADS / 64;
+  const int t = seg_tid<THREADS>(), lane = t & 63, wave = t >> 6;
+  uint32_t rank[kSegItems];
+#pragma unroll
+  for (int r = 0; r < kSegItems; ++r) {
+    if (r >= I) break;
+    const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+    const bool valid = idx < n;
+    const uint32_t d = (uint32_t)(item[r] >> shift) & (uint32_t)(D - 1);
+    const uint64_t peers = match_digit_bits<DBITS>(d, valid);
+    const uint64_t before = peers & lanemask_lt();
+    uint32_t pre = 0;
+    if (valid) pre = L.cnt[wave][d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && before == 0) L.cnt[wave][d] = (uint16_t)(pre + (uint32_t)__popcll(peers));
+    __builtin_amdgcn_wave_barrier();
+    rank[r] = pre + (uint32_t)__popcll(before);
+  }
+  seg_sync<THREADS>();
+  uint32_t dcnt[DPT];
+  uint32_t own = 0, inc = 0;
+  if (t < OWNERS) {
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = t * DPT + j;
+      uint32_t run = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint32_t c = L.cnt[w][d];
+        L.cnt[w][d] = (uint16_t)run;
+        run += c;
+      }
+      dcnt[j] = run;
+      own += run;
+    }
+    inc = wave_incl_scan(own);
+    if (OWNERS > 64 && lane == 63) L.wsum[wave] = inc;
+  }
+  if (OWNERS > 64) seg_sync<THREADS>();
+  if (t < OWNERS) {
+    uint32_t off = inc - own;
+    if (OWNERS > 64)
+      for (int w = 0; w < wave; ++w) off += L.wsum[w];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      L.start[t * DPT + j] = off;
+      off += dcnt[j];
+    }
+  }
+  seg_sync<THREADS>();
+#pragma unroll
+  for (int r = 0; r < kSegItems; ++r) {
+    if (r >= I) break;
+    const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+    const uint32_t d = (uint32_t)(item[r] >> shift) & (uint32_t)(D - 1);
+    pos[r] = idx < n ? L.start[d] + L.cnt[wave][d] + rank[r] : 0u;
+  }
+}
+
+template <int THREADS, int DBITS>
+__device__ __forceinline__ void seg_clear_counts(SegLdsP<THREADS, DBITS>& L) {
+  constexpr int kWords = THREADS / 64 * (1 << DBITS) / 2;
+  uint32_t* c = reinterpret_cast<uint32_t*>(&L.cnt[0][0]);
+  for (int i = seg_tid<THREADS>(); i < kWords; i += THREADS) c[i] = 0;
+}
+
+// Block-wide min and max of the thread values.
+template <int THREADS, int DBITS>
+__device__ __forceinline__ void seg_min_max(SegLdsP<THREADS, DBITS>& L, uint32_t& lo, uint32_t& hi) {
+  constexpr int W = THREADS / 64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+  }
+  if constexpr (W > 1) {
+    const int t = seg_tid<THREADS>(), wave = t >> 6;
+    if ((t & 63) == 0) {
+      L.red[0][wave] = lo;
+      L.red[1][wave] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      lo = min(lo, L.red[0][w]);
+      hi = max(hi, L.red[1][w]);
+    }
+  }
+}
+
+// Sorts segment [s0, s0 + n), n <= kCap, stably by depth bits and writes
+// vals[k] = record id, emit[k] = emission index (if emit), keys_out[k] =
+// full key (if keys_out).
+template <int THREADS, int DBITS>
+__device__ void sort_segment_lds(SegLdsP<THREADS, DBITS>& L, const SegArgs& a, uint32_t tile, uint32_t s0,
+                                 uint32_t n, uint32_t K) {
+  constexpr int kCap = SegLdsP<THREADS, DBITS>::kCap;
+  static_assert(kCap <= 65536, "segment index is packed in 16 bits");
+  const int t = seg_tid<THREADS>(), lane = t & 63, wave = t >> 6;
+  const bool side = *a.sel != 0;
+  const uint64_t* kin = side ? a.keys_b : a.keys_a;
+  uint32_t* vals = side ? a.vals_b : a.vals_a;
+  const int I = (int)div_up(n, (uint32_t)THREADS);
+  // branch-free loads (indices clamped into the segment) so that all of
+  // them are in flight at once; items past the segment (or r >= I) reload
+  // its last entry, a real key, which changes neither the minimum nor the
+  // maximum
+  uint32_t key[kSegItems], val[kSegItems], rec[kSegItems];
+#pragma unroll
+  for (int r = 0; r < kSegItems; ++r) {
+    const uint32_t ic = min((uint32_t)(wave * I + r) * 64u + lane, n - 1u);
+    key[r] = (uint32_t)kin[s0 + ic];
+    val[r] = vals[s0 + ic];
+  }
+  uint32_t bad = 0, lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+  for (int r = 0; r < kSegItems; ++r) {
+    bad |= val[r] >= K ? 1u : 0u;
+    rec[r] = a.rec_of[min(val[r], K - 1u)];
+    lo = min(lo, key[r]);
+    hi = max(hi, key[r]);
+  }
+  if (bad) atomicOr(a.err, 32u);
+  seg_clear_counts(L);
+  seg_min_max(L, lo, hi);  // (with several waves its barrier also publishes the cleared counts)
+  if constexpr (THREADS == 64) seg_sync<THREADS>();
+  const uint32_t range = hi - lo;
+  const int bits = range ? 32 - __builtin_clz(range) : 0;
+  const int passes = (bits + DBITS - 1) / DBITS;
+  auto put = [&](uint32_t o, uint32_t depth, uint32_t e, uint32_t rc) {
+    if (o >= n) {
+      atomicOr(a.err, 32u);
+      return;
+    }
+    vals[s0 + o] = rc;
+    if (a.emit) a.emit[s0 + o] = e;
+    if (a.keys_out) a.keys_out[s0 + o] = ((uint64_t)tile << 32) | depth;
+  };
+  if (passes == 0) {  // one depth: the emission order stands
+    seg_sync<THREADS>();  // every lane has read its input before any output overwrites vals
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+      if (r >= I) break;
+      const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+      if (idx < n) put(idx, key[r], val[r], rec[r]);
+    }
+    return;
+  }
+  uint64_t item[kSegItems];
+  uint32_t pos[kSegItems];
+#pragma unroll
+  for (int r = 0; r < kSegItems; ++r) {
+    const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+    item[r] = ((uint64_t)(key[r] - lo) << 16) | (idx & 0xFFFFu);
+    if (r < I && idx < n) {
+      L.val[idx] = val[r];
+      L.rec[idx] = rec[r];
+    }
+  }
+  for (int p = 0; p < passes; ++p) {
+    if (p > 0) {
+#pragma unroll
+      for (int r = 0; r < kSegItems; ++r) {
+        if (r >= I) break;
+        const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+        if (idx < n) item[r] = L.item[idx];
+      }
+    }
+    seg_rank_p(L, item, I, n, 16 + DBITS * p, pos);
+    seg_sync<THREADS>();  // all positions taken: the counts can be cleared, items moved
+    if (p + 1 < passes) seg_clear_counts(L);
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+      if (r >= I) break;
+      const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+      if (idx < n) L.item[pos[r]] = item[r];
+    }
+    seg_sync<THREADS>();
+  }
+  for (uint32_t i = t; i < n; i += THREADS) {
+    const uint64_t x = L.item[i];
+    const uint32_t idx = (uint32_t)x & 0xFFFFu;
+    put(i, (uint32_t)(x >> 16) + lo, L.val[idx], L.rec[idx]);
+  }
+}
+
+// Sorts a segment too large for LDS (n > kCap; already grouped by tile, in
+// emission order) by depth bits, stably, chunk by chunk through global
+// memory, and writes vals[k] = record id, emit[k] = emission index (if emit),
+// keys_out[k] = full key (if keys_out).  The keys buffer of the other
+// ping-pong side is scratch.
 template <int THREADS, bool CHUNKED>
 __device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint32_t tile, uint32_t s0, uint32_t n,
                              uint32_t K) {
@@ -487,68 +716,7 @@ __device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint
   for (int i = t; i < W * 256; i += THREADS) (&L.wave_cnt[0][0][0])[i] = 0;
   const uint32_t ref = (uint32_t)kin[s0];  // depth bits that differ from this one need passes
 
-  uint32_t key[kSegItems], val[kSegItems], rec[kSegItems], pos[kSegItems];
-  if (n <= (uint32_t)kCap) {
-    const int I = (int)div_up(n, (uint32_t)THREADS);
-    // branch-free loads (indices clamped into the segment) so that all of
-    // them are in flight at once
-    uint32_t diff = 0, bad = 0;
-#pragma unroll
-    for (int r = 0; r < kSegItems; ++r) {
-      // items past the segment (or r >= I) reload its last entry: one cached line
-      const uint32_t ic = min((uint32_t)(wave * I + r) * 64u + lane, n - 1u);
-      key[r] = (uint32_t)kin[s0 + ic];
-      val[r] = vals[s0 + ic];
-    }
-#pragma unroll
-    for (int r = 0; r < kSegItems; ++r) {
-      bad |= val[r] >= K ? 1u : 0u;
-      rec[r] = a.rec_of[min(val[r], K - 1u)];  // gathered while the passes run
-      diff |= key[r] ^ ref;                    // duplicates of real keys add nothing
-    }
-    if (bad) atomicOr(err, 32u);
-    const uint32_t vary = seg_block_or(L, diff);
-    int buf = 0;
-    for (int p = 0; p < 4; ++p) {
-      if (((vary >> (8 * p)) & 255u) == 0) continue;
-      if (buf) {
-#pragma unroll
-        for (int r = 0; r < kSegItems; ++r) {
-          if (r >= I) break;
-          const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-          if (idx < n) {
-            key[r] = L.key[idx];
-            val[r] = L.val[idx];
-            rec[r] = L.rec[idx];
-          }
-        }
-      }
-      seg_rank(L, key, I, n, 8 * p, buf & 1, pos);
-#pragma unroll
-      for (int r = 0; r < kSegItems; ++r) {
-        if (r >= I) break;
-        const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-        if (idx < n) {
-          L.key[pos[r]] = key[r];
-          L.val[pos[r]] = val[r];
-          L.rec[pos[r]] = rec[r];
-        }
-      }
-      seg_sync<THREADS>();
-      ++buf;
-    }
-    if (buf == 0) {
-#pragma unroll
-      for (int r = 0; r < kSegItems; ++r) {
-        if (r >= I) break;
-        const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-        if (idx < n) put(idx, key[r], val[r], rec[r]);
-      }
-    } else {
-      for (uint32_t i = t; i < n; i += THREADS) put(i, L.key[i], L.val[i], L.rec[i]);
-    }
-    return;
-  }
+  uint32_t key[kSegItems], val[kSegItems], pos[kSegItems];
   if constexpr (CHUNKED) {
     static_assert(THREADS >= 256, "chunked passes keep one digit per owner thread");
     // Large segment: pack (depth, emission index) into the scratch side while
@@ -665,8 +833,11 @@ static_assert(kSegWaveMax == 64 * kSegItems, "a wave sorts kSegItems keys per la
 constexpr int kSegWaveBlock = 256;       // wave-kernel block: 4 waves, one tile each
 
 // One screen tile with at most kSegWaveMax pairs per wave.
+constexpr int kSegWaveDigitBits = 8;
+constexpr int kSegBlockDigitBits = 9;
+
 __global__ void __launch_bounds__(kSegWaveBlock) k_sort_segments_wave(SegArgs a) {
-  __shared__ SegLds<64, false> L[kSegWaveBlock / 64];
+  __shared__ SegLdsP<64, kSegWaveDigitBits> L[kSegWaveBlock / 64];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t tile = blockIdx.x * (kSegWaveBlock / 64) + wave;
   if (tile >= a.n_tiles) return;
@@ -677,7 +848,7 @@ __global__ void __launch_bounds__(kSegWaveBlock) k_sort_segments_wave(SegArgs a)
     if (lane == 0) atomicOr(a.err, 32u);
     return;
   }
-  sort_segment(L[wave], a, tile, s0, s1 - s0, K);
+  sort_segment_lds(L[wave], a, tile, s0, s1 - s0, K);
 }
 
 // A fixed grid of G blocks of 1024 threads for the tiles with more than
@@ -688,7 +859,11 @@ constexpr uint32_t kSegBlockClasses = 15;  // floor(2 log2 n) >= 18, i.e. n >= 5
 static_assert(kSegWaveMax == 512 && kSegBlockClasses < kTileClasses, "size classes of k_tile_order");
 
 __global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
-  __shared__ SegLds<1024, true> L;
+  // packed items for segments that fit in LDS, chunks through global memory above
+  __shared__ union {
+    SegLdsP<1024, kSegBlockDigitBits> packed;
+    SegLds<1024, true> chunked;
+  } L;
   __shared__ uint32_t s_end[kSegBlockClasses];  // inclusive prefix of the class counts
   const uint32_t K = min(a.counters[kCntPairs], a.cap);
   if (threadIdx.x < 64) {
@@ -715,10 +890,13 @@ __global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
       atomicOr(a.err, 32u);
     }
     if (s1 > s0 && s1 - s0 > kSegWaveMax) {  // smaller segments are the wave kernel's
-      if (s1 <= K)
-        sort_segment(L, a, tile, s0, s1 - s0, K);
-      else if (threadIdx.x == 0)
-        atomicOr(a.err, 32u);
+      if (s1 > K) {
+        if (threadIdx.x == 0) atomicOr(a.err, 32u);
+      } else if (s1 - s0 <= (uint32_t)SegLdsP<1024, kSegBlockDigitBits>::kCap) {
+        sort_segment_lds(L.packed, a, tile, s0, s1 - s0, K);
+      } else {
+        sort_segment(L.chunked, a, tile, s0, s1 - s0, K);
+      }
     }
     if (threadIdx.x == 0) s_next = gridDim.x + atomicAdd(a.ticket, 1u);
     __syncthreads();  // LDS is reused by the next tile
