@@ -29,9 +29,16 @@
 
 namespace gsr {
 
+// The conic is staged pre-multiplied by kPowScale = -log2(e) / 2 (and b
+// doubled): the exponent of G = exp(-q / 2) = 2^(kPowScale q) is then one
+// fused chain of the staged coefficients, the same in the forward and the
+// backward.
+constexpr float kPowScale = -0.72134752044448170368f;
+constexpr float kPowScaleInv = -1.38629436111989061883f;  // 1 / kPowScale = -2 ln 2
+
 struct BatchLds {
-  float4 a[kBatch];    // u, v, conic a, conic b
-  float4 b[kBatch];    // conic c, opacity, r, g
+  float4 a[kBatch];    // u, v, conic a * kPowScale, 2 b * kPowScale
+  float4 b[kBatch];    // conic c * kPowScale, opacity, r, g
   float c[kBatch];     // b
   float4 ell[kBatch];  // q cut-off with margin, -b/c, -b/a (the conic's minimum over a rectangle)
 };
@@ -87,8 +94,8 @@ __device__ __forceinline__ float4 reach_conic(const Staged& st) {
 
 __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int tid) {
   if (ok) {
-    L.a[tid] = st.a;
-    L.b[tid] = st.b;
+    L.a[tid] = make_float4(st.a.x, st.a.y, st.a.z * kPowScale, (2.f * st.a.w) * kPowScale);
+    L.b[tid] = make_float4(st.b.x * kPowScale, st.b.y, st.b.z, st.b.w);
     L.c[tid] = st.c;
     L.ell[tid] = reach_conic(st);
   }
@@ -144,7 +151,10 @@ __device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n
     bool hit = false;
     if (j < n) {
       const float4 E = L.ell[j];
-      hit = E.x > 0.05f && conic_meets(L.a[j], L.b[j].x, E, qx0, qx1, qy0, qy1);
+      const float4 A = L.a[j];
+      // the staged conic scaled back (within a few ulps; the test's margins cover it)
+      hit = E.x > 0.05f && conic_meets(make_float4(A.x, A.y, A.z * kPowScaleInv, 0.5f * A.w * kPowScaleInv),
+                                       L.b[j].x * kPowScaleInv, E, qx0, qx1, qy0, qy1);
     }
     const uint64_t m = __ballot(hit);
     if (hit) list[cnt + __popcll(m & lanes_below())] = (uint8_t)j;
@@ -154,18 +164,24 @@ __device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n
   return cnt;
 }
 
-// Exponent -q/2 of one pair at a pixel offset (dx, dy) = centre - pixel,
-// q = a dx^2 + 2 b dx dy + c dy^2.  This file is compiled without implicit
-// FMA contraction, so the forward and the backward evaluate this (and alpha)
-// with the same instructions and take the same skip decisions.
+// Base-2 exponent kPowScale q of one pair at a pixel offset (dx, dy) =
+// centre - pixel, q = a dx^2 + 2 b dx dy + c dy^2, from the staged
+// coefficients; G = 2^power.  This file is compiled without implicit FMA
+// contraction, so the forward and the backward evaluate this (and alpha)
+// with the same instructions and take the same skip decisions.  power <= 0
+// is q >= 0.
 __device__ __forceinline__ float pair_power(const float4 A, const float4 B, float dx, float dy) {
-  const float q = fmaf(A.z * dx, dx, fmaf(B.x * dy, dy, (2.f * A.w) * (dx * dy)));
-  return -0.5f * q;
+  return fmaf(A.z * dx, dx, fmaf(B.x * dy, dy, A.w * (dx * dy)));
 }
 
+__device__ __forceinline__ float pair_gauss(float power) { return __builtin_amdgcn_exp2f(power); }
+
 __device__ __forceinline__ float pair_alpha(const float4 B, float power) {
-  return fminf(kAlphaMax, B.y * __expf(power));
+  return fminf(kAlphaMax, B.y * pair_gauss(power));
 }
+
+// Wave ballot of a condition (no round trip of the flag through a VGPR).
+__device__ __forceinline__ uint64_t ballot(bool x) { return __builtin_amdgcn_ballot_w64(x); }
 
 // ---------------------------------------------------------------- forward
 // One 1024-thread block per tile walks the tile's batches in order.  Each of
@@ -302,7 +318,7 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       const float E = quad_shift1(P, slot);  // over slots < slot
       const float Tn = T * P;
       const bool stop = cand && Tn < kTStop;
-      const uint32_t sbits = (uint32_t)(__ballot(stop) >> (lane & 60)) & 0xFu;
+      const uint32_t sbits = (uint32_t)(ballot(stop) >> (lane & 60)) & 0xFu;
       const int first = sbits ? __builtin_ctz(sbits) : 4;  // the quad's first stopping slot
       const bool blend = cand && slot < first;
       const float w = blend ? alpha * (T * E) : 0.f;
@@ -310,12 +326,15 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       D1 = fmaf(B.w, w, D1);
       D2 = fmaf(cb, w, D2);
       lst = blend ? start + (uint32_t)j + 1 : lst;
-      // T after the quad's last blended slot: T * P[first - 1]
-      const float P0 = dpp<0x00, 0xF>(P), P1 = dpp<0x55, 0xF>(P), P2 = dpp<0xAA, 0xF>(P), P3 = dpp<0xFF, 0xF>(P);
-      const float Pe = first == 0 ? 1.f : first == 1 ? P0 : first == 2 ? P1 : first == 3 ? P2 : P3;
-      T = (done || first == 0) ? T : T * Pe;
+      // T after the quad's last blended slot: T times the quad's product of
+      // (1 - alpha) over its blended slots (1 elsewhere; a quad that blends
+      // nothing multiplies T by exactly 1)
+      float g = blend ? f : 1.f;
+      g *= dpp<0xB1, 0xF>(g);  // quad_perm [1,0,3,2]
+      g *= dpp<0x4E, 0xF>(g);  // quad_perm [2,3,0,1]
+      T *= g;
       done = done || first < 4;
-      if (__ballot(!done) == 0ull) {
+      if (ballot(!done) == 0ull) {
         stepped = min(cnt, t0 + 4);
         break;
       }
@@ -600,7 +619,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
     const float cbl = L.c[j];
     const float dx = A.x - fx, dy = A.y - fy;
     const float power = pair_power(A, B, dx, dy);
-    const float G = __expf(power);
+    const float G = pair_gauss(power);
     const float oG = B.y * G;
     const float alpha = fminf(kAlphaMax, oG);
     const bool contrib = valid && kk < plast && power <= 0.f && alpha >= kAlphaMin;
@@ -640,7 +659,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       float va[9], vb[9], wa, wb;
       const bool ca = eval(ja, true, va, wa);
       const bool cb = eval(jb, hb, vb, wb);
-      if (__ballot(ca || cb) == 0ull) continue;
+      if (ballot(ca || cb) == 0ull) continue;
       // reduce-scatter: halves (back | front pair), then row pairs, then
       // within rows by mirror exchanges that keep one operand per lane half
       float X[9];
@@ -671,7 +690,9 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       float m[9], o[12];
 #pragma unroll
       for (int q = 0; q < 9; ++q) m[q] = ((part[0][q][tid] + part[1][q][tid]) + part[2][q][tid]) + part[3][q][tid];
-      const float4 A = L.a[j0 + tid], B = L.b[j0 + tid];
+      // the conic unscaled, from the record
+      const Staged st = fetch(records, n_rec, vals, start + j0 + tid, true);
+      const float4 A = st.a, B = st.b;
       o[0] = -fmaf(A.z, m[0], A.w * m[1]);
       o[1] = -fmaf(A.w, m[0], B.x * m[1]);
       o[2] = -0.5f * m[2];
