@@ -331,24 +331,31 @@ def main():
     bgs = [tuple(float(x) for x in bg_rng.uniform(0, 1, 3)) for _ in range(args.steps + args.warmup + 1)]
     views_per_step = [[scenes.view_state(0xF, bg=b)] for b in bgs]
 
-    rctx = ag.RenderContext(sync=True)
-    one = torch.ones((), device=dev)  # dL/dL, allocated once
+    # The step on the library's entry points: forward on the raw parameters,
+    # the fused L1 loss with its gradient, backward into preallocated
+    # gradients (what the autograd wrapper does, without its Python work).
+    model = {"mean": params["mean"].detach(), "scale": params["log_scale"].detach(),
+             "quat": params["quat"].detach(), "opacity": params["opacity_logit"].detach(),
+             "sh": params["sh"].detach(), "layer": layer, "sh_degree": D, "raw": True}
+    out = (torch.empty((1, 3, H, W), device=dev), torch.empty((1, H, W), device=dev))
+    grads = {"mean": torch.empty((3, n), device=dev), "scale": torch.empty((3, n), device=dev),
+             "quat": torch.empty((4, n), device=dev), "opacity": torch.empty((n,), device=dev),
+             "sh": torch.empty_like(params["sh"])}
+    # first call sizes the pair buffers (one synchronising call), then no host syncs
+    _, _, st0 = rz.rasterize_forward(model, wl.cams, views_per_step[0])
+    torch.cuda.synchronize()
+    K0 = st0.n_pairs
+    state = rz.make_state(n, 1, W, H, int(K0 * 1.25) + 4096, dev)
+    del st0
+    timer = None
 
     def step(i):
         vs = views_per_step[i]
-        rgb, alpha = ag.render_params(params, layer, D, wl.cams, vs, rctx)
-        loss = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, [bgs[i]])  # fused L1 on RGB and alpha
-        loss.backward(one)
-        for p in params.values():
-            p.grad = None
+        rgb, alpha, st = rz.rasterize_forward(model, wl.cams, vs, state=state, sync=False, out=out, timer=timer)
+        loss, g_rgb, g_a = rz.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, [bgs[i]], loss=True, grads=True)
+        rz.rasterize_backward(model, wl.cams, vs, st, g_rgb, g_a, grads=grads, timer=timer)
         return loss
 
-    # first step sizes the pair buffers (one synchronising call), then no host syncs
-    step(0)
-    torch.cuda.synchronize()
-    K0 = rctx.state.n_pairs
-    rctx.state = rz.make_state(n, 1, W, H, int(K0 * 1.25) + 4096, dev)
-    rctx.sync = False
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -363,10 +370,37 @@ def main():
         evs[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rz.forward_check(rctx.state)  # pair capacity held for every step
+    rz.forward_check(state)  # pair capacity held for every step
     step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     total_ms = evs[0].elapsed_time(evs[-1])
     ms_per_step = total_ms / args.steps
+
+    # ---------------- the same step through the autograd wrapper (Python-side cost)
+    rctx = ag.RenderContext(sync=False)
+    rctx.state = state
+    one = torch.ones((), device=dev)
+
+    def step_autograd(i):
+        vs = views_per_step[i]
+        rgb, alpha = ag.render_params(params, layer, D, wl.cams, vs, rctx)
+        loss = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, [bgs[i]])
+        loss.backward(one)
+        for p in params.values():
+            p.grad = None
+        return loss
+
+    for i in range(args.warmup):
+        step_autograd(i)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    aev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    aev[0].record()
+    for i in range(args.steps):
+        step_autograd(args.warmup + i)
+    aev[1].record()
+    torch.cuda.synchronize()
+    autograd_ms = aev[0].elapsed_time(aev[1]) / args.steps
+    autograd_wall_ms = (time.perf_counter() - ta) * 1e3 / args.steps
 
     # ---------------- forward-only render rate (same scene, no autograd)
     with torch.no_grad():
@@ -389,13 +423,12 @@ def main():
 
     # ---------------- per-stage timing over K steps (library-recorded HIP events)
     timer = rz.Timer()
-    rctx.timer = timer
     timer.read()
     for i in range(args.steps):
         step(args.warmup + i)
     torch.cuda.synchronize()
     stages = timer.read()
-    rctx.timer = None
+    timer = None
     # per step: a stage may be timed in several pieces per call (the sort is split by the ranges)
     stage_ms = {s: ms / args.steps for s, (ms, c) in stages.items()}
 
@@ -420,6 +453,7 @@ def main():
         "render_p50_ms": round(percentile(fwd_ms, 50), 4),
         "render_p99_ms": round(percentile(fwd_ms, 99), 4),
         "wall_s": round(wall, 3),
+        "autograd_step": {"ms_per_step": round(autograd_ms, 4), "host_ms_per_step": round(autograd_wall_ms, 4)},
         "pairs": K0,
         "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
     }
