@@ -73,7 +73,18 @@ k_sort_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ coun
   for (int i = threadIdx.x; i < kHistWaves * kHistMaxPasses * 256; i += kHistThreads) (&lh[0][0])[i] = 0;
   __syncthreads();
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += stride) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  // four keys in flight per step
+  for (; i + 3 * stride < K; i += 4 * stride) {
+    uint64_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k[u] = keys[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      for (int q = 0; q < np; ++q)
+        atomicAdd(&lh[wave][q * 256 + ((uint32_t)(k[u] >> (8 * (pass_begin + q))) & 255u)], 1u);
+  }
+  for (; i < K; i += stride) {
     const uint64_t k = keys[i];
     for (int q = 0; q < np; ++q)
       atomicAdd(&lh[wave][q * 256 + ((uint32_t)(k >> (8 * (pass_begin + q))) & 255u)], 1u);
@@ -117,9 +128,15 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
   if (t == 511 % kSortThreads) s_bid = atomicAdd(&pass_ctr[pass], 1u);
   uint32_t hc = 0, hinc = 0;
   if (t < 256) {
-    for (int p = pass_begin; p < pass_end; ++p)
-      if (hist[p * 256 + t] == K) atomicOr(&s_triv, 1u << p);
-    hc = hist[pass * 256 + t];
+    // every pass's count of digit t at once (at most kHistMaxPasses passes)
+    uint32_t hv[kHistMaxPasses];
+#pragma unroll
+    for (int q = 0; q < kHistMaxPasses; ++q) hv[q] = hist[min(pass_begin + q, pass_end - 1) * 256 + t];
+#pragma unroll
+    for (int q = 0; q < kHistMaxPasses; ++q) {
+      if (pass_begin + q < pass_end && hv[q] == K) atomicOr(&s_triv, 1u << (pass_begin + q));
+      if (pass_begin + q == pass) hc = hv[q];
+    }
     hinc = wave_incl_scan(hc);
     if (lane == 63) s_hw[wave] = hinc;
   }
