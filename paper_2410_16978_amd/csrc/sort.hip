@@ -847,76 +847,87 @@ __device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint
 
 static_assert(kSegWaveMax == 64 * kSegItems, "a wave sorts kSegItems keys per lane");
 
-constexpr int kSegWaveBlock = 256;       // wave-kernel block: 4 waves, one tile each
-
-// One screen tile with at most kSegWaveMax pairs per wave.
+// Segments up to kSegWaveMax pairs are sorted by one wave each (8-bit
+// digits), larger ones by the whole block (9-bit digits: three passes for a
+// depth range below 2^27).
 constexpr int kSegWaveDigitBits = 8;
 constexpr int kSegBlockDigitBits = 9;
-
-__global__ void __launch_bounds__(kSegWaveBlock) k_sort_segments_wave(SegArgs a) {
-  __shared__ SegLdsP<64, kSegWaveDigitBits> L[kSegWaveBlock / 64];
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  const uint32_t tile = blockIdx.x * (kSegWaveBlock / 64) + wave;
-  if (tile >= a.n_tiles) return;
-  const uint32_t s0 = a.ranges[2 * tile], s1 = a.ranges[2 * tile + 1];
-  if (s1 <= s0 || s1 - s0 > kSegWaveMax) return;
-  const uint32_t K = min(a.counters[kCntPairs], a.cap);
-  if (s1 > K) {
-    if (lane == 0) atomicOr(a.err, 32u);
-    return;
-  }
-  sort_segment_lds(L[wave], a, tile, s0, s1 - s0, K);
-}
-
-// A fixed grid of G blocks of 1024 threads for the tiles with more than
-// kSegWaveMax pairs, dealt out largest first: block b sorts the tiles b,
-// b + G, b + 2G, ... of the size classes in descending order (the classes
-// of k_tile_order; the ones that can hold more than kSegWaveMax pairs).
-constexpr uint32_t kSegBlockClasses = 15;  // floor(2 log2 n) >= 18, i.e. n >= 512
+constexpr int kSegSmallWaves = 16;           // small tiles per block item, one per wave
+constexpr uint32_t kSegBlockClasses = 15;  // classes with floor(2 log2 n) >= 18, i.e. n >= 512
+constexpr uint32_t kSegHeavyClasses = 11;  // n >= 2048: a block takes about as long as a wave on ~500 pairs
 static_assert(kSegWaveMax == 512 && kSegBlockClasses < kTileClasses, "size classes of k_tile_order");
 
-__global__ void __launch_bounds__(1024) k_sort_segments_block(SegArgs a) {
-  // packed items for segments that fit in LDS, chunks through global memory above
+// One launch of G blocks of 1024 threads for every tile (the size classes of
+// k_tile_order, largest first).  Items, in about descending cost: the tiles
+// of at least 2048 pairs, one per block; then the tiles of at most
+// kSegWaveMax pairs in groups of kSegSmallWaves, one per wave (a wave sorts
+// ~500 pairs in about the time a block needs for ~2000); then the remaining
+// tiles above kSegWaveMax.  Block b starts with item b; later items go to
+// whichever block is free first, so a block holding one of the largest tiles
+// takes nothing else.
+__global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
   __shared__ union {
-    SegLdsP<1024, kSegBlockDigitBits> packed;
-    SegLds<1024, true> chunked;
+    SegLdsP<1024, kSegBlockDigitBits> packed;  // a large tile that fits in LDS
+    SegLds<1024, true> chunked;                 // larger: chunks through global memory
+    SegLdsP<64, kSegWaveDigitBits> small[kSegSmallWaves];
   } L;
-  __shared__ uint32_t s_end[kSegBlockClasses];  // inclusive prefix of the class counts
+  __shared__ uint32_t s_end[kTileClasses];  // inclusive prefix of the class counts (empty tiles left out)
+  __shared__ uint32_t s_next;
   const uint32_t K = min(a.counters[kCntPairs], a.cap);
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   if (threadIdx.x < 64) {
     const uint32_t k = threadIdx.x;
-    const uint32_t cnt = k < kSegBlockClasses ? min(a.class_count[k], a.n_tiles) : 0u;
+    const uint32_t cnt = k + 1 < kTileClasses ? min(a.class_count[k], a.n_tiles) : 0u;
     const uint32_t inc = wave_scan_add(cnt);
-    if (k < kSegBlockClasses) s_end[k] = inc;
+    if (k < kTileClasses) s_end[k] = inc;
   }
   __syncthreads();
-  const uint32_t total = s_end[kSegBlockClasses - 1];
-  // block b starts with item b; later items go to whichever block is free
-  // first, so a block holding one of the largest tiles takes no second one
-  __shared__ uint32_t s_next;
-  uint32_t k = 0;
-  for (uint32_t i = blockIdx.x; i < total;) {
-    while (i >= s_end[k]) ++k;  // a block's items only grow
-    const uint32_t first = k ? s_end[k - 1] : 0u;
-    const uint32_t tile = a.class_list[(size_t)k * a.n_tiles + (i - first)];
-    uint32_t s0 = 0, s1 = 0;
+  const uint32_t n_heavy = s_end[kSegHeavyClasses - 1];
+  const uint32_t n_big = s_end[kSegBlockClasses - 1];
+  const uint32_t n_all = s_end[kTileClasses - 1];
+  const uint32_t n_groups = div_up(n_all - n_big, (uint32_t)kSegSmallWaves);
+  const uint32_t total = n_big + n_groups;
+  // the idx-th tile of the class order (idx < n_all) and its segment
+  auto segment = [&](uint32_t idx, uint32_t& tile, uint32_t& s0, uint32_t& s1) {
+    uint32_t lo = 0, hi = kTileClasses - 1;  // first class with s_end > idx
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_end[mid] > idx) hi = mid; else lo = mid + 1;
+    }
+    tile = a.class_list[(size_t)lo * a.n_tiles + (idx - (lo ? s_end[lo - 1] : 0u))];
+    s0 = s1 = 0;
     if (tile < a.n_tiles) {
       s0 = a.ranges[2 * tile];
       s1 = a.ranges[2 * tile + 1];
-    } else if (threadIdx.x == 0) {
-      atomicOr(a.err, 32u);
     }
-    if (s1 > s0 && s1 - s0 > kSegWaveMax) {  // smaller segments are the wave kernel's
-      if (s1 > K) {
+    return tile < a.n_tiles && s1 <= K && s0 <= s1;
+  };
+  for (uint32_t i = blockIdx.x; i < total;) {
+    uint32_t tile, s0, s1;
+    const bool group = i >= n_heavy && i < n_heavy + n_groups;
+    if (!group) {
+      const bool ok = segment(i < n_heavy ? i : i - n_groups, tile, s0, s1);
+      if (!ok) {
         if (threadIdx.x == 0) atomicOr(a.err, 32u);
-      } else if (s1 - s0 <= (uint32_t)SegLdsP<1024, kSegBlockDigitBits>::kCap) {
-        sort_segment_lds(L.packed, a, tile, s0, s1 - s0, K);
-      } else {
-        sort_segment(L.chunked, a, tile, s0, s1 - s0, K);
+      } else if (s1 > s0) {
+        if (s1 - s0 <= (uint32_t)SegLdsP<1024, kSegBlockDigitBits>::kCap)
+          sort_segment_lds(L.packed, a, tile, s0, s1 - s0, K);
+        else
+          sort_segment(L.chunked, a, tile, s0, s1 - s0, K);
+      }
+    } else {
+      const uint32_t idx = n_big + (i - n_heavy) * kSegSmallWaves + wave;
+      if (idx < n_all) {
+        const bool ok = segment(idx, tile, s0, s1) && s1 - s0 <= kSegWaveMax;
+        if (!ok) {
+          if (lane == 0) atomicOr(a.err, 32u);
+        } else if (s1 > s0) {
+          sort_segment_lds(L.small[wave], a, tile, s0, s1 - s0, K);
+        }
       }
     }
     if (threadIdx.x == 0) s_next = gridDim.x + atomicAdd(a.ticket, 1u);
-    __syncthreads();  // LDS is reused by the next tile
+    __syncthreads();  // LDS is reused by the next item
     i = s_next;
     __syncthreads();
   }
@@ -946,9 +957,7 @@ hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* va
   SegArgs a{keys_a, keys_b, vals_a, vals_b, sel, ranges, rec_of, counters, pair_capacity, emit, keys_out,
             error_flag, total_tiles, class_count, class_list, seg_ticket};
   const uint32_t G = std::min<uint32_t>(total_tiles, (uint32_t)std::max(1, device_cus()));
-  hipLaunchKernelGGL(k_sort_segments_block, dim3(G), dim3(1024), 0, s, a);
-  hipLaunchKernelGGL(k_sort_segments_wave, dim3(div_up(total_tiles, (uint32_t)(kSegWaveBlock / 64))),
-                     dim3(kSegWaveBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sort_segments, dim3(G), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
