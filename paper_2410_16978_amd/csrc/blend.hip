@@ -583,7 +583,13 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       plast = 0;
     }
   }
-  put(L, fetch(records, n_rec, vals, start + tid, tid < n), tid < n, tid);
+  // thread t stages pair t and later combines its sums (sub-batch t / kSub
+  // runs on wave t / kSub), so the pair's exact conic, opacity and emission
+  // index stay in its registers
+  const Staged mine = fetch(records, n_rec, vals, start + tid, tid < n);
+  put(L, mine, tid < n, tid);
+  uint32_t my_emit = tid < n ? pair_emit[start + tid] : 0u;
+  if (my_emit >= cap) my_emit = 0;  // never write out of range (an inconsistent sort shows up as wrong gradients)
   for (int i = tid; i < 4 * kGradSlots * kSub; i += 256) (&part[0][0][0])[i] = 0.f;
   const float qx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, qx1 = qx0 + 7.f;
   const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
@@ -686,13 +692,12 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       }
     }
     __syncthreads();
-    if (tid < j1 - j0) {
+    if (tid >= j0 && tid < j1) {
+      const int js = tid - j0;
       float m[9], o[12];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) m[q] = ((part[0][q][tid] + part[1][q][tid]) + part[2][q][tid]) + part[3][q][tid];
-      // the conic unscaled, from the record
-      const Staged st = fetch(records, n_rec, vals, start + j0 + tid, true);
-      const float4 A = st.a, B = st.b;
+      for (int q = 0; q < 9; ++q) m[q] = ((part[0][q][js] + part[1][q][js]) + part[2][q][js]) + part[3][q][js];
+      const float4 A = mine.a, B = mine.b;  // the conic unscaled
       o[0] = -fmaf(A.z, m[0], A.w * m[1]);
       o[1] = -fmaf(A.w, m[0], B.x * m[1]);
       o[2] = -0.5f * m[2];
@@ -702,12 +707,10 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       o[6] = m[6];
       o[7] = m[7];
       o[8] = m[8];
-      o[9] = fmaxf(fmaxf(part[0][9][tid], part[1][9][tid]), fmaxf(part[2][9][tid], part[3][9][tid]));
+      o[9] = fmaxf(fmaxf(part[0][9][js], part[1][9][js]), fmaxf(part[2][9][js], part[3][9][js]));
       o[10] = 0.f;
       o[11] = 0.f;
-      uint32_t e = pair_emit[start + j0 + tid];
-      if (e >= cap) e = 0;  // never write out of range (an inconsistent sort shows up as wrong gradients)
-      float4* dst = reinterpret_cast<float4*>(g_pair + (size_t)e * 12);
+      float4* dst = reinterpret_cast<float4*>(g_pair + (size_t)my_emit * 12);
       dst[0] = make_float4(o[0], o[1], o[2], o[3]);
       dst[1] = make_float4(o[4], o[5], o[6], o[7]);
       dst[2] = make_float4(o[8], o[9], o[10], o[11]);
