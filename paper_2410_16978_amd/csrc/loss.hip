@@ -30,12 +30,18 @@ __device__ __forceinline__ float l1_block_sum(float v, float* lds) {
 
 constexpr uint32_t kLossBlocks = 1024;  // partial sums (grid-stride)
 
+// Block partial sums of the loss; with dL_drgb / dL_dalpha (both or
+// neither) also the gradient, in the same pass (it does not depend on L).
 __global__ void __launch_bounds__(256)
 k_l1_loss(int n_views, int hw, const float* __restrict__ rgb, const float* __restrict__ alpha,
           const float* __restrict__ t_rgb, const float* __restrict__ t_alpha, LossBg bg,
-          float* __restrict__ partials) {
+          float* __restrict__ partials, const float* __restrict__ g_loss, float* __restrict__ dL_drgb,
+          float* __restrict__ dL_dalpha) {
   __shared__ float lds[8];
   const uint32_t total = (uint32_t)n_views * (uint32_t)hw;
+  const bool grad = dL_drgb != nullptr;
+  const float g = grad && g_loss ? g_loss[0] : 1.f;
+  const float kc = g / (float)(3 * (size_t)total), ka = g / (float)total;
   float sc = 0.f, sa = 0.f;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     const uint32_t v = i / (uint32_t)hw, q = i - v * (uint32_t)hw;
@@ -45,9 +51,13 @@ k_l1_loss(int n_views, int hw, const float* __restrict__ rgb, const float* __res
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       const float target = t_rgb[b3 + (size_t)ch * hw] + om * bg.bg[v][ch];
-      sc += fabsf(rgb[b3 + (size_t)ch * hw] - target);
+      const float d = rgb[b3 + (size_t)ch * hw] - target;
+      sc += fabsf(d);
+      if (grad) dL_drgb[b3 + (size_t)ch * hw] = d > 0.f ? kc : (d < 0.f ? -kc : 0.f);
     }
-    sa += fabsf(alpha[i] - ta);
+    const float d = alpha[i] - ta;
+    sa += fabsf(d);
+    if (grad) dL_dalpha[i] = d > 0.f ? ka : (d < 0.f ? -ka : 0.f);
   }
   const float bc = l1_block_sum(sc, lds);
   __syncthreads();
@@ -106,14 +116,14 @@ hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* al
     for (int ch = 0; ch < 3; ++ch) bg.bg[v][ch] = v < n_views ? bg_host[3 * v + ch] : 0.f;
   const uint32_t blocks = l1_loss_blocks(n_views, hw);
   if (blocks == 0) return hipSuccess;
-  if (loss) {
+  const bool grads = dL_drgb && dL_dalpha;
+  if (loss) {  // with the gradient in the same pass when both are asked for
     const uint32_t n_part = min(blocks, kLossBlocks);
     hipLaunchKernelGGL(k_l1_loss, dim3(n_part), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
-                       partials);
+                       partials, g_loss, grads ? dL_drgb : nullptr, grads ? dL_dalpha : nullptr);
     hipLaunchKernelGGL(k_l1_loss_final, dim3(1), dim3(256), 0, s, n_part, (uint32_t)n_views * (uint32_t)hw,
                        partials, loss);
-  }
-  if (dL_drgb && dL_dalpha)
+  } else if (grads)
     hipLaunchKernelGGL(k_l1_loss_grad, dim3(blocks), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
                        g_loss, dL_drgb, dL_dalpha);
   return hipGetLastError();

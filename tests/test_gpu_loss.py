@@ -45,3 +45,25 @@ def test_fused_l1_alpha_loss_matches_torch(V, H, W):
     # the reduction is reproducible
     loss2 = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, bgs)
     assert float(loss2) == float(loss)
+
+
+@pytest.mark.parametrize("V,H,W", [(1, 800, 800), (2, 33, 71)])
+def test_loss_and_gradient_in_one_pass_equal_separate_calls(V, H, W):
+    """Asking for the loss and its gradient in one call (one pass over the
+    images) gives the loss bit for bit and the same gradients as the two
+    separate calls."""
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    g = torch.Generator(device="cpu").manual_seed(7 * V + W)
+    rgb = torch.rand((V, 3, H, W), generator=g).cuda()
+    alpha = torch.rand((V, H, W), generator=g).cuda()
+    t_rgb = (torch.rand((V, 3, H, W), generator=g) * 0.8).cuda()
+    t_alpha = torch.rand((V, H, W), generator=g).cuda()
+    bgs = [tuple(float(x) for x in np.random.default_rng(10 + v).uniform(0, 1, 3)) for v in range(V)]
+    gl = torch.tensor([2.5], device="cuda")
+    loss_a, _, _ = rz.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, bgs, loss=True, grads=False)
+    _, gr_a, ga_a = rz.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, bgs, loss=False, grads=True, g_loss=gl)
+    loss_b, gr_b, ga_b = rz.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, bgs, loss=True, grads=True, g_loss=gl)
+    torch.cuda.synchronize()
+    assert float(loss_a) == float(loss_b)
+    assert torch.equal(gr_a, gr_b) and torch.equal(ga_a, ga_b)
