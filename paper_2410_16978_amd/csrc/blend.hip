@@ -216,13 +216,19 @@ __device__ __forceinline__ uint32_t batch_word(uint32_t tile, uint32_t est) {
   return (tile + 1u) | (cls << 24);
 }
 
+// Full-mask lane permutation: every lane has a source, so no old value.
+template <unsigned CTRL>
+__device__ __forceinline__ float qperm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
 __device__ __forceinline__ float quad_shift1(float x, int slot) {  // x of slot - 1, 1 for slot 0
-  const float y = dpp<0x90, 0xF>(x);                             // quad_perm [0,0,1,2]
+  const float y = qperm<0x90>(x);                                // quad_perm [0,0,1,2]
   return slot >= 1 ? y : 1.f;
 }
 
 __device__ __forceinline__ float quad_shift2(float x, int slot) {  // x of slot - 2, 1 for slots 0, 1
-  const float y = dpp<0x40, 0xF>(x);                             // quad_perm [0,0,0,1]
+  const float y = qperm<0x40>(x);                                // quad_perm [0,0,0,1]
   return slot >= 2 ? y : 1.f;
 }
 
@@ -681,7 +687,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       const float W0 = (b2 ? Z1 : Z0) + dpp<0x141, 0xF>(b2 ? Z0 : Z1);  // row_half_mirror
       const float W1 = Z2 + dpp<0x141, 0xF>(Z2);
       float R = (b1 ? W1 : W0) + dpp<0x4E, 0xF>(b1 ? W0 : W1);  // quad_perm [2,3,0,1]
-      R += dpp<0xB1, 0xF>(R);                                     // quad_perm [1,0,3,2]
+      R += qperm<0xB1>(R);                                        // quad_perm [1,0,3,2]
       const float mxa = want_max ? wave_max63(wa) : 0.f;
       const float mxb = want_max ? wave_max63(wb) : 0.f;
       const bool front = row >= 2;
