@@ -54,6 +54,7 @@ struct PipeBufs {
   uint32_t* class_list = nullptr;  // [kTileClasses][X] tiles by size class
   float* g_pair = nullptr;
   float* g_col = nullptr;    // [R][3] colour gradient of each record (backward)
+  uint32_t* alive = nullptr;       // [P] bytes (as words): 1 where a pair's partials were written (backward)
   uint32_t* order_cnt = nullptr;   // [kBatchClasses] batches per work class (backward)
   uint32_t* order_list = nullptr;  // [kBatchClasses][batch capacity] batch indices by class (backward)
   // batch only (the single-call path keeps these in the caller's state)
@@ -80,8 +81,9 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
   b.class_list = c.take<uint32_t>(kTileClasses * std::max<size_t>(X, 1));
   if (backward) {
-    b.g_pair = c.take<float>(12 * std::max<size_t>(P, 1));
+    b.g_pair = c.take<float>(12 * (std::max<size_t>(P, 1) + 1));  // + one zero entry, index P
     b.g_col = c.take<float>(3 * std::max<size_t>(R, 1));
+    b.alive = c.take<uint32_t>(std::max<size_t>(P, 1) / 4 + 1);
     b.order_cnt = c.take<uint32_t>(kBatchClasses);
     b.order_list = c.take<uint32_t>(kBatchClasses * (P / kBatch + X + 1));
   }
@@ -493,7 +495,11 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
     ClearSet cs{};
     cs.p[0] = b.order_cnt;
     cs.n[0] = kBatchClasses;
-    cs.n_ranges = 1;
+    cs.p[1] = b.alive;
+    cs.n[1] = (size_t)P / 4 + 1;
+    cs.p[2] = reinterpret_cast<uint32_t*>(b.g_pair + 12 * (size_t)P);  // the zero entry
+    cs.n[2] = 12;
+    cs.n_ranges = 3;
     HIP_TRY(launch_clear_multi(cs, s, up.n ? &up : nullptr));
   }
   {
@@ -503,13 +509,14 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
     HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
                              state->ranges, reinterpret_cast<const float4*>(state->checkpoints), batch_tile,
                              n_batches, b.order_cnt, b.order_list, dL_drgb, dL_dalpha, state->pair_emit, b.g_pair,
-                             max_contrib != nullptr, s));
+                             reinterpret_cast<uint8_t*>(b.alive), max_contrib != nullptr, s));
   }
   const ModelD md = make_model(*model);
   {
     StageScope sc(timer, GSR_STAGE_PROJECT_BWD, s);
     for (const JobD& j : make_jobs(md, ids))
-      HIP_TRY(launch_project_bwd(j, b.views, state->records, state->offsets, b.g_pair, P,
+      HIP_TRY(launch_project_bwd(j, b.views, state->records, state->offsets, b.g_pair,
+                                 reinterpret_cast<const uint8_t*>(b.alive), P,
                                  state->counters, trainable_layers, grads->g_mean, grads->g_scale, grads->g_quat,
                                  grads->g_opacity, grads->g_sh, b.g_col, max_contrib, activity, s));
   }

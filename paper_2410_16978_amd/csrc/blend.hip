@@ -472,7 +472,9 @@ constexpr int kGradSlots = 10;
 
 // g_pair: [P][12] per pair, at its emission index (pair_emit of its sorted
 // position), so that a Gaussian's partials are contiguous: u, v, conic a,
-// b, c, opacity, r, g, b, max alpha*T, 2 unused.
+// b, c, opacity, r, g, b, max alpha*T, 2 unused; alive[e] = 1 marks the
+// entries written (pairs of batches the forward never evaluated at a live
+// pixel are zero and skipped).
 // The backward's block order: batches by work class, heaviest first, so that
 // the longest blocks start early instead of ending the launch.  Each block
 // buckets 4096 batch words; per class one atomic reserves its range of the
@@ -520,7 +522,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
             const uint32_t* __restrict__ batch_tile, uint32_t n_batches, const uint32_t* __restrict__ order_cnt,
             const uint32_t* __restrict__ order_list, const float* __restrict__ dL_drgb,
             const float* __restrict__ dL_dalpha, const uint32_t* __restrict__ pair_emit,
-            float* __restrict__ g_pair, int want_max) {
+            float* __restrict__ g_pair, uint8_t* __restrict__ alive, int want_max) {
   __shared__ BatchLds L;
   constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
   __shared__ float part[4][kGradSlots][kSub];
@@ -540,18 +542,23 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   __syncthreads();
   const uint32_t bi = s_bi;
   if (bi >= n_batches) return;
-  const uint32_t tile_p1 = batch_tile[bi] & kBatchTileMask;
+  const uint32_t word = batch_tile[bi];
+  const uint32_t tile_p1 = word & kBatchTileMask;
   if (tile_p1 == 0) return;  // no tile's batch
   const uint32_t tile = tile_p1 - 1u;
   const uint32_t c = bi - first_batch(tile, ranges[2 * tile]);
-  const int vi = find_view(views, n_views, tile);
-  const ViewD& V = views[vi];
-  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t t_end = min(ranges[2 * tile + 1], cap);
   const uint32_t start = min(ranges[2 * tile] + c * kBatch, t_end);
   const uint32_t end = min(start + kBatch, t_end);
   const int n = (int)(end - start);
+  // The forward evaluated none of this batch's pairs at a live pixel (its
+  // pixels had stopped, or no pair's ellipse reaches one): every partial is
+  // zero, and none is written (their alive flags stay 0).
+  if ((word >> 24) == kBatchClasses - 1) return;
+  const int vi = find_view(views, n_views, tile);
+  const ViewD& V = views[vi];
+  const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
 
   const uint32_t local = tile - V.tile_off;
   const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
@@ -720,6 +727,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       dst[0] = make_float4(o[0], o[1], o[2], o[3]);
       dst[1] = make_float4(o[4], o[5], o[6], o[7]);
       dst[2] = make_float4(o[8], o[9], o[10], o[11]);
+      alive[my_emit] = 1;
     }
     __syncthreads();
     for (int i = tid; i < 4 * kGradSlots * kSub; i += 256) (&part[0][0][0])[i] = 0.f;
@@ -731,12 +739,12 @@ hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* re
                             const uint32_t* pair_vals, const uint32_t* sel, uint32_t cap, const uint32_t* ranges,
                             const float4* ckpt, const uint32_t* batch_tile, uint32_t n_batches,
                             const uint32_t* order_cnt, const uint32_t* order_list, const float* dL_drgb,
-                            const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair, bool want_max,
-                            hipStream_t s) {
+                            const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair, uint8_t* alive,
+                            bool want_max, hipStream_t s) {
   if (n_batches == 0) return hipSuccess;
   hipLaunchKernelGGL(k_blend_bwd, dim3(n_batches), dim3(256), 0, s, views_dev, n_views, records, n_rec, pair_vals,
                      sel, cap, ranges, ckpt, batch_tile, n_batches, order_cnt, order_list, dL_drgb, dL_dalpha,
-                     pair_emit, g_pair, want_max ? 1 : 0);
+                     pair_emit, g_pair, alive, want_max ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -175,9 +175,10 @@ hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* re
                             const float4* ckpt, const uint32_t* batch_tile, uint32_t n_batches,
                             const uint32_t* order_cnt, const uint32_t* order_list,
                             const float* dL_drgb, const float* dL_dalpha, const uint32_t* pair_emit, float* g_pair,
-                            bool want_max, hipStream_t s);
+                            uint8_t* alive, bool want_max, hipStream_t s);
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
-                              const uint32_t* offsets, const float* g_pair, uint32_t pair_capacity,
+                              const uint32_t* offsets, const float* g_pair, const uint8_t* alive,
+                              uint32_t pair_capacity,
                               const uint32_t* counters, uint32_t trainable, float* g_mean, float* g_scale,
                               float* g_quat, float* g_opacity, float* g_sh, float* g_col, float* max_contrib,
                               float* activity, hipStream_t s);

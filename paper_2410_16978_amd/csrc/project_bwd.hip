@@ -15,30 +15,41 @@ namespace gsr {
 
 // Screen-space gradient of record r: the sum of its pairs' partials (stored
 // at their emission indices, so contiguous per record) in emission order, and
-// the largest alpha * T it reached.
+// the largest alpha * T it reached.  Only pairs with alive[e] set have
+// partials (the others are exactly zero and were never written); their
+// loads are redirected to the zero entry at index `zero`, so the loads stay
+// branch-free and adding its +0 leaves every sum bit for bit unchanged (a
+// sum that starts at +0 never holds -0).
 __device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restrict__ offsets,
-                                            const float* __restrict__ g_pair, uint32_t K, float* g, float& wmax) {
+                                            const float* __restrict__ g_pair, const uint8_t* __restrict__ alive,
+                                            uint32_t zero, uint32_t K, float* g, float& wmax) {
   for (int c = 0; c < 9; ++c) g[c] = 0.f;
-  const uint32_t e1 = min(offsets[r + 1], K);
-  auto add = [&](const float4 x0, const float4 x1, const float4 x2) {
-    g[0] += x0.x; g[1] += x0.y; g[2] += x0.z; g[3] += x0.w;
-    g[4] += x1.x; g[5] += x1.y; g[6] += x1.z; g[7] += x1.w;
-    g[8] += x2.x;
-    wmax = fmaxf(wmax, x2.y);
-  };
-  uint32_t e = offsets[r];
-  // four pairs' loads in flight per step (same summation order)
-  for (; e + 4 <= e1; e += 4) {
-    const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)e * 12);
+  const uint32_t e0 = offsets[r], e1 = min(offsets[r + 1], K);
+  // four pairs per step: their flags, then their loads, in flight at once
+  for (uint32_t e = e0; e < e1; e += 4) {
+    uint32_t idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t q = e + (uint32_t)u;
+      const bool live = alive[min(q, e1 - 1u)] != 0;
+      idx[u] = q < e1 && live ? q : zero;
+    }
     float4 x[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) x[k] = src[k];
+    for (int u = 0; u < 4; ++u) {
+      const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)idx[u] * 12);
+      x[3 * u] = src[0];
+      x[3 * u + 1] = src[1];
+      x[3 * u + 2] = src[2];
+    }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) add(x[3 * k], x[3 * k + 1], x[3 * k + 2]);
-  }
-  for (; e < e1; ++e) {
-    const float4* src = reinterpret_cast<const float4*>(g_pair + (size_t)e * 12);
-    add(src[0], src[1], src[2]);
+    for (int u = 0; u < 4; ++u) {
+      const float4 x0 = x[3 * u], x1 = x[3 * u + 1], x2 = x[3 * u + 2];
+      g[0] += x0.x; g[1] += x0.y; g[2] += x0.z; g[3] += x0.w;
+      g[4] += x1.x; g[5] += x1.y; g[6] += x1.z; g[7] += x1.w;
+      g[8] += x2.x;
+      wmax = fmaxf(wmax, x2.y);
+    }
   }
 }
 
@@ -47,7 +58,8 @@ __device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restri
 // channels) is left in g_col[r][3] for the SH kernel.
 __global__ void __launch_bounds__(256)
 k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __restrict__ records,
-                   const uint32_t* __restrict__ offsets, const float* __restrict__ g_pair, uint32_t cap, const uint32_t* __restrict__ counters,
+                   const uint32_t* __restrict__ offsets, const float* __restrict__ g_pair,
+                   const uint8_t* __restrict__ alive, uint32_t cap, const uint32_t* __restrict__ counters,
                    uint32_t trainable, float* __restrict__ g_mean, float* __restrict__ g_scale,
                    float* __restrict__ g_quat, float* __restrict__ g_opacity, float* __restrict__ g_col,
                    float* __restrict__ max_contrib) {
@@ -64,7 +76,7 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
     float g[9];
     for (int jv = 0; jv < job.n_views; ++jv) {
       const uint32_t r = views[job.view[jv]].rec_off + (uint32_t)i;
-      if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) != 0u) record_grad(r, offsets, g_pair, K, g, wmax);
+      if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) != 0u) record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
     }
   }
   if (train) {
@@ -103,7 +115,7 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
       if (__float_as_uint(rec[11]) == 0u) continue;  // culled in this view
       const uint32_t clamp_bits = __float_as_uint(rec[10]);
       float g[9];
-      record_grad(r, offsets, g_pair, K, g, wmax);
+      record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
       go += g[5];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) g_col[(size_t)r * 3 + ch] = ((clamp_bits >> ch) & 1u) ? 0.f : g[6 + ch];
@@ -320,13 +332,14 @@ k_project_bwd_sh(JobD job, const ViewD* __restrict__ views, const float* __restr
 }
 
 hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const float* records,
-                              const uint32_t* offsets, const float* g_pair, uint32_t pair_capacity,
+                              const uint32_t* offsets, const float* g_pair, const uint8_t* alive,
+                              uint32_t pair_capacity,
                               const uint32_t* counters, uint32_t trainable, float* g_mean, float* g_scale,
                               float* g_quat, float* g_opacity, float* g_sh, float* g_col, float* max_contrib,
                               float* activity, hipStream_t s) {
   if (job.m.n <= 0) return hipSuccess;
   const dim3 grid(div_up((uint32_t)job.m.n, 256u)), block(256);
-  hipLaunchKernelGGL(k_project_bwd_geom, grid, block, 0, s, job, views_dev, records, offsets, g_pair,
+  hipLaunchKernelGGL(k_project_bwd_geom, grid, block, 0, s, job, views_dev, records, offsets, g_pair, alive,
                      pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_col, max_contrib);
   switch (job.m.D) {
     case 0: hipLaunchKernelGGL(k_project_bwd_sh<0>, grid, block, 0, s, job, views_dev, records, trainable, g_col,
