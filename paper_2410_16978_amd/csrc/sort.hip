@@ -98,6 +98,8 @@ k_sort_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ coun
   }
 }
 
+int device_cus();
+
 // ---------------------------------------------------------------- one pass
 __global__ void __launch_bounds__(kSortThreads)
 k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t* __restrict__ vals0,
@@ -305,9 +307,11 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
   if (pass_end - pass_begin > kHistMaxPasses) return hipErrorInvalidValue;
   const uint32_t nb_max = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile);
   if (pass_end > pass_begin) {
-    // about 16 keys per thread, at most 64 blocks
+    // about 16 keys per thread; at most 64 blocks (few global additions per
+    // count) unless the pairs need more, then up to one block per compute unit
     uint32_t hb = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kHistThreads * 16u);
-    if (hb > 64) hb = 64;
+    const uint32_t hb_max = hb > 256 ? (uint32_t)std::max(64, device_cus()) : 64u;
+    if (hb > hb_max) hb = hb_max;
     hipLaunchKernelGGL(k_sort_hist, dim3(hb), dim3(kHistThreads), 0, s, keys_a, counters, pair_capacity,
                        pass_begin, pass_end, hist);
   }
@@ -341,114 +345,6 @@ __device__ __forceinline__ void seg_sync() {
 template <int THREADS>
 __device__ __forceinline__ int seg_tid() {
   return THREADS == 64 ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
-}
-
-// Sorting groups: one wave for segments up to 512 pairs (most tiles), a
-// 1024-thread block above that; segments beyond 8192 pairs are sorted chunk
-// by chunk through global memory.
-template <int THREADS, bool CHUNKED>
-struct SegLds {
-  static constexpr int kWaves = THREADS / 64;
-  static constexpr int kCap = THREADS * kSegItems;
-  uint32_t key[kCap];                 // depth bits, in digit order after a pass
-  uint32_t val[kCap];                 // emission indices
-  uint32_t rec[kCap];                 // record ids
-  uint16_t wave_cnt[2][kWaves][256];  // per-wave digit counts, then offsets; alternate buffers by pass
-  uint32_t start[256];                // first chunk position of every digit
-  uint32_t wsum[kWaves];
-  uint32_t run[CHUNKED ? 256 : 1];      // segment position of the next key of every digit
-  uint32_t base[CHUNKED ? 4 : 1][CHUNKED ? 256 : 1];  // segment histograms, then exclusive offsets
-};
-
-// Chunk positions of this thread's items when the chunk is stably ordered by
-// the digit at `shift`.  Items: thread (wave, lane) holds chunk entries
-// wave * I * 64 + r * 64 + lane, r < I, valid below n.  Counts in
-// L.wave_cnt[buf], which must be zero on entry; clears the other buffer for
-// the next call.  Leaves the chunk's digit starts in L.start; with 256
-// threads or more, thread t < 256 gets the count of digit t back.
-template <int THREADS, bool CHUNKED>
-__device__ __forceinline__ uint32_t seg_rank(SegLds<THREADS, CHUNKED>& L, const uint32_t (&key)[kSegItems], int I,
-                                             uint32_t n, int shift, int buf, uint32_t (&pos)[kSegItems]) {
-  constexpr int W = THREADS / 64;
-  constexpr int DPT = THREADS >= 256 ? 1 : 256 / THREADS;  // digits owned per thread
-  constexpr int OWNERS = 256 / DPT;
-  const int t = seg_tid<THREADS>(), lane = t & 63, wave = t >> 6;
-  uint16_t(&cnt_w)[W][256] = L.wave_cnt[buf];
-  for (int i = t; i < W * 256; i += THREADS) (&L.wave_cnt[buf ^ 1][0][0])[i] = 0;
-  uint32_t rank[kSegItems];
-#pragma unroll
-  for (int r = 0; r < kSegItems; ++r) {
-    if (r >= I) break;
-    const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-    const bool valid = idx < n;
-    const uint32_t d = (key[r] >> shift) & 255u;
-    const uint64_t peers = match_digit(d, valid);
-    const uint64_t before = peers & lanemask_lt();
-    uint32_t pre = 0;
-    if (valid) pre = cnt_w[wave][d];
-    __builtin_amdgcn_wave_barrier();
-    if (valid && before == 0) cnt_w[wave][d] = (uint16_t)(pre + (uint32_t)__popcll(peers));
-    __builtin_amdgcn_wave_barrier();
-    rank[r] = pre + (uint32_t)__popcll(before);
-  }
-  seg_sync<THREADS>();
-  // owner threads: digits [t * DPT, t * DPT + DPT), block order digit-major
-  uint32_t dcnt[DPT];
-  uint32_t own = 0, inc = 0;
-  if (t < OWNERS) {
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) {
-      const int d = t * DPT + j;
-      uint32_t run = 0;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const uint32_t c = cnt_w[w][d];
-        cnt_w[w][d] = (uint16_t)run;
-        run += c;
-      }
-      dcnt[j] = run;
-      own += run;
-    }
-    inc = wave_incl_scan(own);
-    if (OWNERS > 64 && lane == 63) L.wsum[wave] = inc;
-  }
-  if (OWNERS > 64) seg_sync<THREADS>();
-  if (t < OWNERS) {
-    uint32_t off = inc - own;
-    if (OWNERS > 64)
-      for (int w = 0; w < wave; ++w) off += L.wsum[w];
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) {
-      L.start[t * DPT + j] = off;
-      off += dcnt[j];
-    }
-  }
-  seg_sync<THREADS>();
-#pragma unroll
-  for (int r = 0; r < kSegItems; ++r) {
-    if (r >= I) break;
-    const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-    const uint32_t d = (key[r] >> shift) & 255u;
-    pos[r] = idx < n ? L.start[d] + cnt_w[wave][d] + rank[r] : 0u;
-  }
-  return (DPT == 1 && t < OWNERS) ? dcnt[0] : 0u;
-}
-
-// OR of every thread's value over the block (the bits in which some key
-// differs from the reference key).
-template <int THREADS, bool CHUNKED>
-__device__ __forceinline__ uint32_t seg_block_or(SegLds<THREADS, CHUNKED>& L, uint32_t x) {
-  constexpr int W = THREADS / 64;
-  const int t = seg_tid<THREADS>(), wave = t >> 6;
-  x = wave_or(x);
-  if (W == 1) return x;
-  if ((t & 63) == 0) L.wsum[wave] = x;
-  __syncthreads();
-  uint32_t o = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) o |= L.wsum[w];
-  __syncthreads();  // wsum is reused by the passes
-  return o;
 }
 
 struct SegArgs {
@@ -490,26 +386,33 @@ __device__ __forceinline__ uint64_t match_digit_bits(uint32_t d, bool valid) {
 // bits; only as many passes as the depth range needs (a range below
 // 2^(3 DBITS) takes three).  The emission index and record id stay in LDS by
 // segment index and are looked up once at the end.
-template <int THREADS, int DBITS>
+// BIG: the layout of the chunked sort of segments above kCap pairs (below),
+// where items carry the emission index and the segment's digit offsets and
+// running positions are kept instead.
+template <int THREADS, int DBITS, bool BIG = false>
 struct SegLdsP {
   static constexpr int kWaves = THREADS / 64;
   static constexpr int kCap = THREADS * kSegItems;
   static constexpr int kDigits = 1 << DBITS;
   uint64_t item[kCap];
-  uint32_t val[kCap];
-  uint32_t rec[kCap];
+  uint32_t val[BIG ? 1 : kCap];
+  uint32_t rec[BIG ? 1 : kCap];
   uint16_t cnt[kWaves][kDigits];  // per-wave digit counts, then offsets
   uint32_t start[kDigits];        // first position of every digit
   uint32_t wsum[kWaves];
   uint32_t red[2][kWaves];
+  uint32_t run[BIG ? kDigits : 1];                  // segment position of every digit's next item
+  uint32_t base[BIG ? 4 : 1][BIG ? kDigits : 1];  // segment digit counts, then offsets, per pass
 };
 
 // Positions of this thread's items (entries wave * I * 64 + r * 64 + lane,
 // r < I, valid below n) when the segment is stably ordered by the digit at
-// `shift`.  L.cnt must be zero on entry; it holds offsets on return.
-template <int THREADS, int DBITS>
-__device__ __forceinline__ void seg_rank_p(SegLdsP<THREADS, DBITS>& L, const uint64_t (&item)[kSegItems], int I,
-                                           uint32_t n, int shift, uint32_t (&pos)[kSegItems]) {
+// `shift`.  L.cnt must be zero on entry; it holds offsets on return.  With
+// one digit per owner thread (THREADS >= 2^DBITS), thread t < 2^DBITS gets
+// the count of digit t back.
+template <int THREADS, int DBITS, bool BIG>
+__device__ __forceinline__ uint32_t seg_rank_p(SegLdsP<THREADS, DBITS, BIG>& L, const uint64_t (&item)[kSegItems],
+                                               int I, uint32_t n, int shift, uint32_t (&pos)[kSegItems]) {
   constexpr int D = 1 << DBITS;
   constexpr int DPT = D >= THREADS ? D / THREADS : 1;  // digits per owner thread
   constexpr int OWNERS = D / DPT;
@@ -570,18 +473,19 @@ __device__ __forceinline__ void seg_rank_p(SegLdsP<THREADS, DBITS>& L, const uin
     const uint32_t d = (uint32_t)(item[r] >> shift) & (uint32_t)(D - 1);
     pos[r] = idx < n ? L.start[d] + L.cnt[wave][d] + rank[r] : 0u;
   }
+  return (DPT == 1 && t < OWNERS) ? dcnt[0] : 0u;  // with one digit per owner: its count
 }
 
-template <int THREADS, int DBITS>
-__device__ __forceinline__ void seg_clear_counts(SegLdsP<THREADS, DBITS>& L) {
+template <int THREADS, int DBITS, bool BIG>
+__device__ __forceinline__ void seg_clear_counts(SegLdsP<THREADS, DBITS, BIG>& L) {
   constexpr int kWords = THREADS / 64 * (1 << DBITS) / 2;
   uint32_t* c = reinterpret_cast<uint32_t*>(&L.cnt[0][0]);
   for (int i = seg_tid<THREADS>(); i < kWords; i += THREADS) c[i] = 0;
 }
 
 // Block-wide min and max of the thread values.
-template <int THREADS, int DBITS>
-__device__ __forceinline__ void seg_min_max(SegLdsP<THREADS, DBITS>& L, uint32_t& lo, uint32_t& hi) {
+template <int THREADS, int DBITS, bool BIG>
+__device__ __forceinline__ void seg_min_max(SegLdsP<THREADS, DBITS, BIG>& L, uint32_t& lo, uint32_t& hi) {
   constexpr int W = THREADS / 64;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -607,7 +511,7 @@ __device__ __forceinline__ void seg_min_max(SegLdsP<THREADS, DBITS>& L, uint32_t
 // vals[k] = record id, emit[k] = emission index (if emit), keys_out[k] =
 // full key (if keys_out).
 template <int THREADS, int DBITS>
-__device__ void sort_segment_lds(SegLdsP<THREADS, DBITS>& L, const SegArgs& a, uint32_t tile, uint32_t s0,
+__device__ void sort_segment_lds(SegLdsP<THREADS, DBITS, false>& L, const SegArgs& a, uint32_t tile, uint32_t s0,
                                  uint32_t n, uint32_t K) {
   constexpr int kCap = SegLdsP<THREADS, DBITS>::kCap;
   static_assert(kCap <= 65536, "segment index is packed in 16 bits");
@@ -699,149 +603,165 @@ __device__ void sort_segment_lds(SegLdsP<THREADS, DBITS>& L, const SegArgs& a, u
   }
 }
 
-// Sorts a segment too large for LDS (n > kCap; already grouped by tile, in
-// emission order) by depth bits, stably, chunk by chunk through global
-// memory, and writes vals[k] = record id, emit[k] = emission index (if emit),
-// keys_out[k] = full key (if keys_out).  The keys buffer of the other
-// ping-pong side is scratch.
-template <int THREADS, bool CHUNKED>
-__device__ void sort_segment(SegLds<THREADS, CHUNKED>& L, const SegArgs& a, uint32_t tile, uint32_t s0, uint32_t n,
-                             uint32_t K) {
-  constexpr int kCap = SegLds<THREADS, CHUNKED>::kCap;
-  constexpr int W = THREADS / 64;
-  const int t = seg_tid<THREADS>(), lane = t & 63, wave = t >> 6;
+// Segments above kCap pairs (many in the 4M and stereo workloads): LSD
+// passes through global memory, one chunk of kCap items at a time, on
+// packed items ((depth - segment minimum) << 32 | emission index) with
+// 9-bit digits and only as many passes as the depth range needs.  One read
+// finds the depth range, a second packs the items into the other key buffer
+// and counts the digits of every pass; each pass then ranks a chunk in LDS
+// (stable), and places each digit's items after those of the earlier chunks
+// (running positions from the segment's digit offsets), ping-ponging between
+// the two key buffers.  The last pass writes the results.
+using SegLdsBig = SegLdsP<1024, 9, true>;
+
+__device__ void sort_segment_big(SegLdsBig& L, const SegArgs& a, uint32_t tile, uint32_t s0, uint32_t n,
+                                 uint32_t K) {
+  constexpr int T = 1024, DB = 9, D = 1 << DB, kCap = SegLdsBig::kCap;
+  const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool side = *a.sel != 0;
   uint64_t* kin = side ? a.keys_b : a.keys_a;
   uint64_t* kother = side ? a.keys_a : a.keys_b;
   uint32_t* vals = side ? a.vals_b : a.vals_a;
-  uint32_t* err = a.err;
-  // final write of sorted position o (segment-relative)
-  auto put = [&](uint32_t o, uint32_t depth, uint32_t e, uint32_t rec) {
+  auto put = [&](uint32_t o, uint32_t depth, uint32_t e, uint32_t rc) {
     if (o >= n) {
-      atomicOr(err, 32u);
+      atomicOr(a.err, 32u);
       return;
     }
-    vals[s0 + o] = rec;
+    vals[s0 + o] = rc;
     if (a.emit) a.emit[s0 + o] = e;
     if (a.keys_out) a.keys_out[s0 + o] = ((uint64_t)tile << 32) | depth;
   };
-  auto record_of = [&](uint32_t e) -> uint32_t {
-    if (e < K) return a.rec_of[e];
-    atomicOr(err, 32u);
-    return 0u;
-  };
-  for (int i = t; i < W * 256; i += THREADS) (&L.wave_cnt[0][0][0])[i] = 0;
-  const uint32_t ref = (uint32_t)kin[s0];  // depth bits that differ from this one need passes
-
-  uint32_t key[kSegItems], val[kSegItems], pos[kSegItems];
-  if constexpr (CHUNKED) {
-    static_assert(THREADS >= 256, "chunked passes keep one digit per owner thread");
-    // Large segment: pack (depth, emission index) into the scratch side while
-    // taking the segment's digit histograms, then run the passes chunk by
-    // chunk, ping-ponging between the two key buffers; the last pass writes
-    // the results.
-    for (int i = t; i < 4 * 256; i += THREADS) (&L.base[0][0])[i] = 0;
-    seg_sync<THREADS>();
-    uint32_t diff = 0;
-    for (uint32_t b0 = 0; b0 < n; b0 += THREADS) {
-      const uint32_t i = b0 + t;
-      const bool valid = i < n;
-      uint32_t k = 0;
-      if (valid) {
-        k = (uint32_t)kin[s0 + i];
-        kother[s0 + i] = ((uint64_t)k << 32) | vals[s0 + i];
-        diff |= k ^ ref;
-      }
+  constexpr uint32_t kRound = (uint32_t)T * kSegItems;
+  // depth range (branch-free rounds of kSegItems keys per thread)
+  uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+  for (uint32_t b0 = 0; b0 < n; b0 += kRound) {
+    uint32_t k[kSegItems];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const uint32_t d = (k >> (8 * p)) & 255u;
-        const uint64_t peers = match_digit(d, valid);
+    for (int r = 0; r < kSegItems; ++r) k[r] = (uint32_t)kin[s0 + min(b0 + (uint32_t)(r * T + t), n - 1u)];
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+      lo = min(lo, k[r]);
+      hi = max(hi, k[r]);
+    }
+  }
+  seg_min_max(L, lo, hi);
+  const uint32_t range = hi - lo;
+  const int bits = range ? 32 - __builtin_clz(range) : 0;
+  const int passes = (bits + DB - 1) / DB;
+  for (int i = t; i < 4 * D; i += T) (&L.base[0][0])[i] = 0u;
+  seg_clear_counts(L);
+  __syncthreads();
+  // pack, and count the digits of every pass
+  for (uint32_t b0 = 0; b0 < n; b0 += kRound) {
+    uint32_t k[kSegItems], v[kSegItems];
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+      const uint32_t ic = min(b0 + (uint32_t)(r * T + t), n - 1u);
+      k[r] = (uint32_t)kin[s0 + ic] - lo;
+      v[r] = vals[s0 + ic];
+    }
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+      const uint32_t i = b0 + (uint32_t)(r * T + t);
+      const bool valid = i < n;
+      if (valid) kother[s0 + i] = ((uint64_t)k[r] << 32) | v[r];
+      for (int p = 0; p < passes; ++p) {
+        const uint32_t d = (k[r] >> (DB * p)) & (uint32_t)(D - 1);
+        const uint64_t peers = match_digit_bits<DB>(d, valid);
         if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&L.base[p][d], (uint32_t)__popcll(peers));
       }
     }
-    const uint32_t vary = seg_block_or(L, diff);  // (its barrier also publishes L.base)
-    int last_pass = -1;
-    for (int p = 0; p < 4; ++p)
-      if ((vary >> (8 * p)) & 255u) last_pass = p;
-    // exclusive digit offsets per pass
-    for (int p = 0; p < 4; ++p) {
-      uint32_t c = 0, inc = 0;
-      if (t < 256) {
-        c = L.base[p][t];
-        inc = wave_incl_scan(c);
-        if (lane == 63) L.wsum[wave] = inc;
-      }
-      seg_sync<THREADS>();
-      if (t < 256) {
-        uint32_t off = 0;
-        for (int w = 0; w < wave; ++w) off += L.wsum[w];
-        L.base[p][t] = off + inc - c;
-      }
-      seg_sync<THREADS>();
+  }
+  __syncthreads();
+  // exclusive digit offsets per pass (owner thread t < D holds digit t)
+  for (int p = 0; p < passes; ++p) {
+    uint32_t c = 0, inc = 0;
+    if (t < D) {
+      c = L.base[p][t];
+      inc = wave_incl_scan(c);
+      if (lane == 63) L.wsum[wave] = inc;
     }
-    if (last_pass < 0) {
-      for (uint32_t i = t; i < n; i += THREADS) {
-        const uint64_t v = kother[s0 + i];
-        put(i, (uint32_t)(v >> 32), (uint32_t)v, record_of((uint32_t)v));
-      }
-      return;
+    __syncthreads();
+    if (t < D) {
+      uint32_t off = inc - c;
+      for (int w = 0; w < wave; ++w) off += L.wsum[w];
+      L.base[p][t] = off;
     }
-    uint64_t* src = kother;
-    uint64_t* dst = kin;
-    int buf = 0;
-    for (int p = 0; p <= last_pass; ++p) {
-      if (((vary >> (8 * p)) & 255u) == 0) continue;
-      const int shift = 8 * p;
-      if (t < 256) L.run[t] = L.base[p][t];
-      for (uint32_t cb = 0; cb < n; cb += kCap) {
-        const uint32_t nc = min((uint32_t)kCap, n - cb);
-        const int I = (int)div_up(nc, (uint32_t)THREADS);
+    __syncthreads();
+  }
+  auto record_of = [&](uint32_t e) -> uint32_t { return a.rec_of[min(e, K - 1u)]; };
+  if (passes == 0) {  // one depth: the emission order stands
+    for (uint32_t b0 = 0; b0 < n; b0 += 4u * T) {
+      uint64_t x[4];
+      uint32_t rc[4];
 #pragma unroll
-        for (int r = 0; r < kSegItems; ++r) {
-          key[r] = 0;
-          val[r] = 0;
-          if (r >= I) break;
-          const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-          if (idx < nc) {
-            const uint64_t v = src[s0 + cb + idx];
-            key[r] = (uint32_t)(v >> 32);
-            val[r] = (uint32_t)v;
-          }
-        }
-        const uint32_t cnt = seg_rank(L, key, I, nc, shift, buf & 1, pos);
-        ++buf;
+      for (int r = 0; r < 4; ++r) x[r] = kother[s0 + min(b0 + (uint32_t)(r * T + t), n - 1u)];
 #pragma unroll
-        for (int r = 0; r < kSegItems; ++r) {
-          if (r >= I) break;
-          const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
-          if (idx < nc) {
-            L.key[pos[r]] = key[r];
-            L.val[pos[r]] = val[r];
-          }
+      for (int r = 0; r < 4; ++r) rc[r] = record_of((uint32_t)x[r]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = b0 + (uint32_t)(r * T + t);
+        if (i < n) put(i, (uint32_t)(x[r] >> 32) + lo, (uint32_t)x[r], rc[r]);
+      }
+    }
+    return;
+  }
+  uint64_t* src = kother;
+  uint64_t* dst = kin;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 32 + DB * p;
+    const bool last = p + 1 == passes;
+    if (t < D) L.run[t] = L.base[p][t];
+    for (uint32_t cb = 0; cb < n; cb += kCap) {
+      const uint32_t nc = min((uint32_t)kCap, n - cb);
+      const int I = (int)div_up(nc, (uint32_t)T);
+      uint64_t it[kSegItems];
+      uint32_t pos[kSegItems];
+#pragma unroll
+      for (int r = 0; r < kSegItems; ++r) it[r] = src[s0 + cb + min((uint32_t)(wave * I + r) * 64u + lane, nc - 1u)];
+      const uint32_t dc = seg_rank_p(L, it, I, nc, shift, pos);  // (its barriers also publish L.run)
+      __syncthreads();  // all positions taken: the counts can be cleared, items moved
+      seg_clear_counts(L);
+#pragma unroll
+      for (int r = 0; r < kSegItems; ++r) {
+        if (r >= I) break;
+        const uint32_t idx = (uint32_t)(wave * I + r) * 64u + lane;
+        if (idx < nc) L.item[pos[r]] = it[r];
+      }
+      __syncthreads();
+      // each digit's run of the chunk goes after the earlier chunks' items of
+      // that digit (four items per thread at a time, their gathers in flight)
+      for (int h = 0; h < kSegItems; h += 4) {
+        uint64_t x[4];
+        uint32_t rc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = L.item[min((uint32_t)((h + r) * T + t), nc - 1u)];
+        if (last) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) rc[r] = record_of((uint32_t)x[r]);
         }
-        seg_sync<THREADS>();
-        for (uint32_t i = t; i < nc; i += THREADS) {
-          const uint32_t k = L.key[i];
-          const uint32_t d = (k >> shift) & 255u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t i = (uint32_t)((h + r) * T + t);
+          if (i >= nc) break;
+          const uint32_t d = (uint32_t)(x[r] >> shift) & (uint32_t)(D - 1);
           const uint32_t o = L.run[d] + (i - L.start[d]);
-          if (p == last_pass) {
-            put(o, k, L.val[i], record_of(L.val[i]));
+          if (last) {
+            put(o, (uint32_t)(x[r] >> 32) + lo, (uint32_t)x[r], rc[r]);
           } else if (o < n) {
-            dst[s0 + o] = ((uint64_t)k << 32) | L.val[i];
+            dst[s0 + o] = x[r];
           } else {
-            atomicOr(err, 32u);
+            atomicOr(a.err, 32u);
           }
         }
-        seg_sync<THREADS>();
-        if (t < 256) L.run[t] += cnt;
-        seg_sync<THREADS>();
       }
-      uint64_t* tmp = src;
-      src = dst;
-      dst = tmp;
+      __syncthreads();
+      if (t < D) L.run[t] += dc;
+      __syncthreads();
     }
-  } else {
-    if (t == 0) atomicOr(err, 32u);  // a segment beyond this class's bound: never dropped silently
+    uint64_t* tmp = src;
+    src = dst;
+    dst = tmp;
   }
 }
 
@@ -868,7 +788,7 @@ static_assert(kSegWaveMax == 512 && kSegBlockClasses < kTileClasses, "size class
 __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
   __shared__ union {
     SegLdsP<1024, kSegBlockDigitBits> packed;  // a large tile that fits in LDS
-    SegLds<1024, true> chunked;                 // larger: chunks through global memory
+    SegLdsBig chunked;                          // larger: chunks through global memory
     SegLdsP<64, kSegWaveDigitBits> small[kSegSmallWaves];
   } L;
   __shared__ uint32_t s_end[kTileClasses];  // inclusive prefix of the class counts (empty tiles left out)
@@ -913,7 +833,7 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
         if (s1 - s0 <= (uint32_t)SegLdsP<1024, kSegBlockDigitBits>::kCap)
           sort_segment_lds(L.packed, a, tile, s0, s1 - s0, K);
         else
-          sort_segment(L.chunked, a, tile, s0, s1 - s0, K);
+          sort_segment_big(L.chunked, a, tile, s0, s1 - s0, K);
       }
     } else {
       const uint32_t idx = n_big + (i - n_heavy) * kSegSmallWaves + wave;
