@@ -275,6 +275,7 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   if (req_status && req_status[V.request] != 0) return;  // a request that did not fit is not written
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int slot = lane & 3, p = lane >> 2;
+  const uint32_t upto_slot = (2u << slot) - 1u;  // stop bits of the slots up to this one
   const uint32_t local = tile - V.tile_off;
   const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
   const int sx0 = tx * kTile + (wave & 3) * kQuadPix, sy0 = ty * kTile + (wave >> 2) * kQuadPix;
@@ -324,9 +325,9 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       const float E = quad_shift1(P, slot);  // over slots < slot
       const float Tn = T * P;
       const bool stop = cand && Tn < kTStop;
-      const uint32_t sbits = (uint32_t)(ballot(stop) >> (lane & 60)) & 0xFu;
-      const int first = sbits ? __builtin_ctz(sbits) : 4;  // the quad's first stopping slot
-      const bool blend = cand && slot < first;
+      // the quad's stop bits: a slot blends if no slot up to it stops
+      const uint32_t sbits = (uint32_t)(ballot(stop) >> (lane & 60));
+      const bool blend = cand && (sbits & upto_slot) == 0u;
       const float w = blend ? alpha * (T * E) : 0.f;
       D0 = fmaf(B.z, w, D0);
       D1 = fmaf(B.w, w, D1);
@@ -339,7 +340,7 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       g *= dpp<0xB1, 0xF>(g);  // quad_perm [1,0,3,2]
       g *= dpp<0x4E, 0xF>(g);  // quad_perm [2,3,0,1]
       T *= g;
-      done = done || first < 4;
+      done = done || (sbits & 0xFu) != 0u;
       if (ballot(!done) == 0ull) {
         stepped = min(cnt, t0 + 4);
         break;
