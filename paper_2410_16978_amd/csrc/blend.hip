@@ -64,14 +64,13 @@ struct Staged {
   float c;
 };
 
-__device__ __forceinline__ Staged fetch(const float* __restrict__ records, uint32_t n_rec,
-                                        const uint32_t* __restrict__ vals, uint32_t k, bool ok) {
+__device__ __forceinline__ Staged fetch_record(const float* __restrict__ records, uint32_t n_rec, uint32_t r,
+                                               bool ok) {
   Staged st;
   st.a = make_float4(0.f, 0.f, 0.f, 0.f);
   st.b = st.a;
   st.c = 0.f;
   if (ok) {
-    uint32_t r = vals[k];
     if (r >= n_rec) r = 0;  // never read out of range (a sort fault shows up as wrong pixels)
     const float4* rec = reinterpret_cast<const float4*>(records + (size_t)r * kRecordFloats);
     st.a = rec[0];
@@ -79,6 +78,11 @@ __device__ __forceinline__ Staged fetch(const float* __restrict__ records, uint3
     st.c = records[(size_t)r * kRecordFloats + 8];
   }
   return st;
+}
+
+__device__ __forceinline__ Staged fetch(const float* __restrict__ records, uint32_t n_rec,
+                                        const uint32_t* __restrict__ vals, uint32_t k, bool ok) {
+  return fetch_record(records, n_rec, ok ? vals[k] : 0u, ok);
 }
 
 // Cut-off of the pair's reach: o exp(-q/2) >= 1/255 needs q <= 2 ln(255 o).
@@ -296,6 +300,9 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   uint32_t last = 0;
   bool done = !inside;
   uint32_t n_ck = 0;  // batches processed (checkpoints written)
+  // record id of this thread's pair of the next batch, loaded a batch ahead
+  // (one of the two dependent loads of the staging off the serial path)
+  uint32_t rid = tid < kBatch && t_start + (uint32_t)tid < t_end ? vals[t_start + tid] : 0u;
   for (uint32_t start = t_start, c = 0; start < t_end; start += kBatch, ++c) {
     if (!__syncthreads_or(!done)) break;  // also orders the previous batch's LDS reads before the refill
     if (ckpt && tid == 0 && c > 0) {
@@ -303,8 +310,12 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       s_est = 0;
     }
     const int n = (int)min((uint32_t)kBatch, t_end - start);
-    if (tid < kBatch) put(L, fetch(records, n_rec, vals, start + tid, tid < n), tid < n, tid);
+    if (tid < kBatch) put(L, fetch_record(records, n_rec, rid, tid < n), tid < n, tid);
     __syncthreads();
+    {
+      const uint32_t k = start + kBatch + (uint32_t)tid;
+      rid = tid < kBatch && k < t_end ? vals[k] : 0u;
+    }
     const float T0 = T;
     float D0 = 0.f, D1 = 0.f, D2 = 0.f;
     uint32_t lst = 0;
