@@ -37,6 +37,7 @@ struct SortCtl {
   uint32_t tile_class[kTileClasses];  // tiles per size class (forward order)
   uint32_t seg_ticket;                // next large tile of the block depth sort
   uint32_t pad[6];
+  uint32_t hist12[4096];              // tile counts of the one-pass tile grouping
 };
 
 struct PipeBufs {
@@ -78,7 +79,8 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
   b.keys_b = c.take<uint64_t>(std::max<size_t>(P, 1));
   b.rec_of = c.take<uint32_t>(std::max<size_t>(P, 1));
   b.ctl = c.take<SortCtl>(1);
-  b.status = c.take<uint32_t>(sort_status_words((uint32_t)P));
+  b.status = c.take<uint32_t>(std::max(sort_status_words((uint32_t)P),
+                                        tile_sort12(X, (uint32_t)P) ? tile_sort12_status_words((uint32_t)P) : 0));
   b.class_list = c.take<uint32_t>(kTileClasses * std::max<size_t>(X, 1));
   if (backward) {
     b.g_pair = c.take<float>(12 * (std::max<size_t>(P, 1) + 1));  // + one zero entry, index P
@@ -141,10 +143,15 @@ hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, uint32_t* rang
   cs.p[3] = reinterpret_cast<uint32_t*>(b.scan_status);
   cs.n[3] = 2 * (size_t)scan_tiles((uint32_t)R);
   // look-back words of the tile passes, and the sorted-buffer selector
-  const size_t stride = sort_status_stride(P);
-  const int pb = kDepthPasses, pe = tile_pass_end(X);
-  cs.p[4] = b.status + (size_t)pb * stride;
-  cs.n[4] = (size_t)(pe - pb) * stride;
+  if (tile_sort12(X, P)) {  // block counts: written before they are read, no clearing
+    cs.p[4] = nullptr;
+    cs.n[4] = 0;
+  } else {
+    const size_t stride = sort_status_stride(P);
+    const int pb = kDepthPasses, pe = tile_pass_end(X);
+    cs.p[4] = b.status + (size_t)pb * stride;
+    cs.n[4] = (size_t)(pe - pb) * stride;
+  }
   cs.p[5] = sel;
   cs.n[5] = 1;
   cs.n_ranges = 6;
@@ -408,9 +415,13 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
-    HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
-                        kDepthPasses, tile_pass_end(X), b.ctl->hist, b.status, b.ctl->pass_ctr,
-                        state->sort_sel, state->counters + kCntError, s));
+    if (tile_sort12(X, P))
+      HIP_TRY(launch_tile_sort12(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
+                                 b.ctl->hist12, b.status, state->sort_sel, state->counters + kCntError, s));
+    else
+      HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
+                          kDepthPasses, tile_pass_end(X), b.ctl->hist, b.status, b.ctl->pass_ctr,
+                          state->sort_sel, state->counters + kCntError, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
@@ -618,8 +629,13 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
-    HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, kDepthPasses, tile_pass_end(bp.X),
-                        b.ctl->hist, b.status, b.ctl->pass_ctr, b.sel, b.counters + kCntError, s));
+    if (tile_sort12(bp.X, P))
+      HIP_TRY(launch_tile_sort12(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, b.ctl->hist12, b.status,
+                                 b.sel, b.counters + kCntError, s));
+    else
+      HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, kDepthPasses,
+                          tile_pass_end(bp.X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.sel,
+                          b.counters + kCntError, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);

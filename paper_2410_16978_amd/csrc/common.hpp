@@ -148,6 +148,12 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
                        uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, uint32_t* sel_out,
                        uint32_t* error_flag, hipStream_t s);
 size_t sort_status_stride(uint32_t pair_capacity);
+constexpr uint32_t kT12MaxPairs = 1u << 24;  // the one-pass tile grouping's look-back words: 4 B per pair
+bool tile_sort12(uint64_t total_tiles, uint32_t pair_capacity);
+size_t tile_sort12_status_words(uint32_t pair_capacity);
+hipError_t launch_tile_sort12(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
+                              const uint32_t* counters, uint32_t pair_capacity, uint32_t* totals,
+                              uint32_t* block_counts, uint32_t* sel_out, uint32_t* error_flag, hipStream_t s);
 hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,

@@ -53,6 +53,21 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Digit of DBITS bits: the lanes holding the same digit (and valid).
+template <int DBITS>
+__device__ __forceinline__ uint64_t match_digit_bits(uint32_t d, bool valid) {
+  const uint64_t vb = __ballot(valid);
+  uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
+#pragma unroll
+  for (int b = 0; b < DBITS; ++b) {
+    const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)d, (unsigned)b, 1u);
+    const uint64_t bal = __ballot(s != 0u);
+    lo = __builtin_amdgcn_bitop3_b32((uint32_t)bal, s, lo, 0x82);
+    hi = __builtin_amdgcn_bitop3_b32((uint32_t)(bal >> 32), s, hi, 0x82);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) { return wave_scan_add(x); }
 
 // ---------------------------------------------------------------- histogram
@@ -289,6 +304,212 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
   }
 }
 
+// ---------------------------------------------------------------- 12-bit tile pass
+// With at most 4096 tiles the whole tile id is one 12-bit digit: the pairs
+// are grouped by tile (stably) in one counting pass instead of two 8-bit
+// passes, reduce-then-scan: each block of 4096 keys counts its tiles, a scan
+// turns the counts into per-block offsets (and the tile totals), and the
+// pass ranks and scatters each block's keys with its offsets known - no
+// chain of look-backs between blocks.
+constexpr int kT12Threads = 512;
+constexpr int kT12Waves = kT12Threads / 64;
+constexpr int kT12Items = 8;
+constexpr int kT12Tile = kT12Threads * kT12Items;  // keys per block
+constexpr int kT12Digits = 4096;
+constexpr int kT12Own = kT12Digits / kT12Threads;  // digits per thread
+static_assert(kT12Own == 8, "eight digits per owner thread");
+
+// Block b's tile counts into counts[b][4096].
+__global__ void __launch_bounds__(kT12Threads)
+k_tile_count12(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counters, uint32_t cap,
+               uint32_t* __restrict__ counts) {
+  __shared__ uint32_t lh[kT12Digits];
+  for (int i = threadIdx.x; i < kT12Digits; i += kT12Threads) lh[i] = 0;
+  __syncthreads();
+  const uint32_t K = min(counters[kCntPairs], cap);
+  const uint32_t base = blockIdx.x * (uint32_t)kT12Tile;
+  uint32_t d[kT12Items];
+#pragma unroll
+  for (int r = 0; r < kT12Items; ++r) {
+    const uint32_t i = base + (uint32_t)(r * kT12Threads) + threadIdx.x;
+    d[r] = i < K ? (uint32_t)(keys[i] >> 32) & (uint32_t)(kT12Digits - 1) : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int r = 0; r < kT12Items; ++r)
+    if (d[r] != 0xFFFFFFFFu) atomicAdd(&lh[d[r]], 1u);
+  __syncthreads();
+  uint4* out = reinterpret_cast<uint4*>(counts + (size_t)blockIdx.x * kT12Digits);
+  for (int i = threadIdx.x; i < kT12Digits / 4; i += kT12Threads)
+    out[i] = make_uint4(lh[4 * i], lh[4 * i + 1], lh[4 * i + 2], lh[4 * i + 3]);
+}
+
+// Per tile (one thread each): counts[b][d] becomes the count of tile d in
+// blocks before b; totals[d] the tile's count.  Loads in flight 16 blocks
+// at a time.
+__global__ void __launch_bounds__(256)
+k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, uint32_t* __restrict__ totals) {
+  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= (uint32_t)kT12Digits) return;
+  uint32_t run = 0;
+  uint32_t b = 0;
+  for (; b + 16 <= n_blocks; b += 16) {
+    uint32_t c[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) c[u] = counts[(size_t)(b + u) * kT12Digits + d];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      counts[(size_t)(b + u) * kT12Digits + d] = run;
+      run += c[u];
+    }
+  }
+  for (; b < n_blocks; ++b) {
+    const uint32_t c = counts[(size_t)b * kT12Digits + d];
+    counts[(size_t)b * kT12Digits + d] = run;
+    run += c;
+  }
+  totals[d] = run;
+}
+
+__global__ void __launch_bounds__(kT12Threads)
+k_tile_pass12(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
+              uint32_t* __restrict__ vout, const uint32_t* __restrict__ counters, uint32_t cap,
+              const uint32_t* __restrict__ totals, const uint32_t* __restrict__ block_off,
+              uint32_t* __restrict__ sel_out, uint32_t* __restrict__ err) {
+  __shared__ uint16_t wave_cnt[kT12Waves][kT12Digits];  // per-wave digit counts, then offsets
+  __shared__ uint64_t s_keys[kT12Tile];
+  __shared__ uint32_t s_vals[kT12Tile];
+  __shared__ uint16_t s_start[kT12Digits];  // block-local start of every digit
+  __shared__ uint32_t s_global[kT12Digits];
+  __shared__ uint32_t s_w[kT12Waves], s_h[kT12Waves];
+  const uint32_t K = min(counters[kCntPairs], cap);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t bid = blockIdx.x;
+  if (bid == 0 && t == 0) *sel_out = 1u;  // the result is in the second buffers
+  const uint32_t base = bid * (uint32_t)kT12Tile;
+  if (base >= K) return;
+  {
+    uint32_t* c = reinterpret_cast<uint32_t*>(&wave_cnt[0][0]);
+    for (int i = t; i < kT12Waves * kT12Digits / 2; i += kT12Threads) c[i] = 0u;
+  }
+  uint64_t key[kT12Items];
+  uint32_t val[kT12Items], rank[kT12Items];
+  const uint32_t wbase = base + (uint32_t)wave * (kT12Items * 64);
+#pragma unroll
+  for (int r = 0; r < kT12Items; ++r) {
+    const uint32_t idx = wbase + r * 64 + lane;
+    const bool valid = idx < K;
+    key[r] = valid ? kin[idx] : 0ull;
+    val[r] = valid ? vin[idx] : 0u;
+  }
+  // the tile totals and this block's offsets of the thread's eight digits
+  uint32_t hg[kT12Own], bo[kT12Own];
+#pragma unroll
+  for (int j = 0; j < kT12Own; ++j) {
+    hg[j] = totals[kT12Own * t + j];
+    bo[j] = block_off[(size_t)bid * kT12Digits + kT12Own * t + j];
+  }
+  __syncthreads();
+  // rank within the wave, in input order (round-major, then lane)
+#pragma unroll
+  for (int r = 0; r < kT12Items; ++r) {
+    const bool valid = (wbase + r * 64 + lane) < K;
+    const uint32_t d = (uint32_t)(key[r] >> 32) & (uint32_t)(kT12Digits - 1);
+    const uint64_t peers = match_digit_bits<12>(d, valid);
+    const uint64_t before = peers & lanemask_lt();
+    uint32_t pre = 0;
+    if (valid) pre = wave_cnt[wave][d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && before == 0) wave_cnt[wave][d] = (uint16_t)(pre + (uint32_t)__popcll(peers));
+    __builtin_amdgcn_wave_barrier();
+    rank[r] = pre + (uint32_t)__popcll(before);
+  }
+  __syncthreads();
+  // owner thread t: digits 8t .. 8t + 7 - per-wave offsets and block counts
+  uint32_t cnt[kT12Own];
+  uint32_t own = 0, hown = 0;
+#pragma unroll
+  for (int j = 0; j < kT12Own; ++j) {
+    const int d = kT12Own * t + j;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kT12Waves; ++w) {
+      const uint32_t c = wave_cnt[w][d];
+      wave_cnt[w][d] = (uint16_t)run;
+      run += c;
+    }
+    cnt[j] = run;
+    own += run;
+    hown += hg[j];
+  }
+  const uint32_t inc = wave_incl_scan(own), hinc = wave_incl_scan(hown);
+  if (lane == 63) {
+    s_w[wave] = inc;
+    s_h[wave] = hinc;
+  }
+  __syncthreads();
+  uint32_t off = inc - own, hoff = hinc - hown;
+  for (int w = 0; w < wave; ++w) {
+    off += s_w[w];
+    hoff += s_h[w];
+  }
+#pragma unroll
+  for (int j = 0; j < kT12Own; ++j) {
+    const int d = kT12Own * t + j;
+    s_start[d] = (uint16_t)off;
+    s_global[d] = hoff + bo[j];
+    off += cnt[j];
+    hoff += hg[j];
+  }
+  __syncthreads();
+  // order the block's keys by digit in LDS (stable), then write digit runs out
+#pragma unroll
+  for (int r = 0; r < kT12Items; ++r) {
+    const bool valid = (wbase + r * 64 + lane) < K;
+    if (valid) {
+      const uint32_t d = (uint32_t)(key[r] >> 32) & (uint32_t)(kT12Digits - 1);
+      const uint32_t pos = s_start[d] + wave_cnt[wave][d] + rank[r];
+      s_keys[pos] = key[r];
+      s_vals[pos] = val[r];
+    }
+  }
+  __syncthreads();
+  const uint32_t n_items = min(K - base, (uint32_t)kT12Tile);
+  for (uint32_t i = t; i < n_items; i += kT12Threads) {
+    const uint64_t k = s_keys[i];
+    const uint32_t d = (uint32_t)(k >> 32) & (uint32_t)(kT12Digits - 1);
+    const uint32_t dst = s_global[d] + (i - s_start[d]);
+    if (dst < K) {
+      kout[dst] = k;
+      vout[dst] = s_vals[i];
+    } else {
+      atomicOr(err, 2u);  // inconsistent offsets: never write out of range
+    }
+  }
+}
+
+bool tile_sort12(uint64_t total_tiles, uint32_t pair_capacity) {
+  return total_tiles <= (uint64_t)kT12Digits && pair_capacity <= kT12MaxPairs;
+}
+
+size_t tile_sort12_status_words(uint32_t pair_capacity) {
+  return (size_t)div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kT12Tile) * kT12Digits;
+}
+
+// The tile grouping in one pass (tile_sort12 true): keys_a / vals_a into
+// keys_b / vals_b, *sel_out = 1.  block_counts holds
+// tile_sort12_status_words words, totals 4096 (neither needs clearing).
+hipError_t launch_tile_sort12(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
+                              const uint32_t* counters, uint32_t pair_capacity, uint32_t* totals,
+                              uint32_t* block_counts, uint32_t* sel_out, uint32_t* error_flag, hipStream_t s) {
+  const uint32_t nb = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kT12Tile);
+  hipLaunchKernelGGL(k_tile_count12, dim3(nb), dim3(kT12Threads), 0, s, keys_a, counters, pair_capacity,
+                     block_counts);
+  hipLaunchKernelGGL(k_tile_scan12, dim3(kT12Digits / 256), dim3(256), 0, s, block_counts, nb, totals);
+  hipLaunchKernelGGL(k_tile_pass12, dim3(nb), dim3(kT12Threads), 0, s, keys_a, keys_b, vals_a, vals_b, counters,
+                     pair_capacity, totals, block_counts, sel_out, error_flag);
+  return hipGetLastError();
+}
+
 size_t sort_status_words(uint32_t pair_capacity) {
   return (size_t)kMaxSortPasses * div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile) * 256;
 }
@@ -365,21 +586,6 @@ struct SegArgs {
   const uint32_t* class_list;   // [kTileClasses][n_tiles]
   uint32_t* ticket;             // zero on entry: large tiles handed out after the first G
 };
-
-// Digit of DBITS bits: the lanes holding the same digit (and valid).
-template <int DBITS>
-__device__ __forceinline__ uint64_t match_digit_bits(uint32_t d, bool valid) {
-  const uint64_t vb = __ballot(valid);
-  uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
-#pragma unroll
-  for (int b = 0; b < DBITS; ++b) {
-    const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)d, (unsigned)b, 1u);
-    const uint64_t bal = __ballot(s != 0u);
-    lo = __builtin_amdgcn_bitop3_b32((uint32_t)bal, s, lo, 0x82);
-    hi = __builtin_amdgcn_bitop3_b32((uint32_t)(bal >> 32), s, hi, 0x82);
-  }
-  return ((uint64_t)hi << 32) | lo;
-}
 
 // Segments that fit in LDS are sorted on packed items: (depth bits minus the
 // segment's smallest) << 16 | index in the segment, with digits of DBITS
