@@ -417,7 +417,8 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     StageScope sc(timer, GSR_STAGE_SORT, s);
     if (tile_sort12(X, P))
       HIP_TRY(launch_tile_sort12(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
-                                 b.ctl->hist12, b.status, state->sort_sel, state->counters + kCntError, s));
+                                 (uint32_t)X, b.ctl->hist12, b.status, state->ranges, b.ctl->tile_class,
+                                 b.class_list, state->sort_sel, state->counters + kCntError, s));
     else
       HIP_TRY(launch_sort(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->counters, P,
                           kDepthPasses, tile_pass_end(X), b.ctl->hist, b.status, b.ctl->pass_ctr,
@@ -425,8 +426,10 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   }
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
-    HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
-    HIP_TRY(launch_tile_order(state->ranges, (uint32_t)X, b.ctl->tile_class, b.class_list, s));
+    if (!tile_sort12(X, P)) {  // (the one-pass grouping writes the ranges and classes itself)
+      HIP_TRY(launch_ranges(b.keys_a, b.keys_b, state->sort_sel, state->counters, P, (uint32_t)X, state->ranges, s));
+      HIP_TRY(launch_tile_order(state->ranges, (uint32_t)X, b.ctl->tile_class, b.class_list, s));
+    }
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
@@ -630,8 +633,9 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
     if (tile_sort12(bp.X, P))
-      HIP_TRY(launch_tile_sort12(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, b.ctl->hist12, b.status,
-                                 b.sel, b.counters + kCntError, s));
+      HIP_TRY(launch_tile_sort12(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, (uint32_t)bp.X,
+                                 b.ctl->hist12, b.status, b.ranges, b.ctl->tile_class, b.class_list, b.sel,
+                                 b.counters + kCntError, s));
     else
       HIP_TRY(launch_sort(b.keys_a, b.keys_b, b.vals, b.vals + P, b.counters, P, kDepthPasses,
                           tile_pass_end(bp.X), b.ctl->hist, b.status, b.ctl->pass_ctr, b.sel,
@@ -639,8 +643,10 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   {
     StageScope sc(timer, GSR_STAGE_RANGES, s);
-    HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
-    HIP_TRY(launch_tile_order(b.ranges, (uint32_t)bp.X, b.ctl->tile_class, b.class_list, s));
+    if (!tile_sort12(bp.X, P)) {  // (the one-pass grouping writes the ranges and classes itself)
+      HIP_TRY(launch_ranges(b.keys_a, b.keys_b, b.sel, b.counters, P, (uint32_t)bp.X, b.ranges, s));
+      HIP_TRY(launch_tile_order(b.ranges, (uint32_t)bp.X, b.ctl->tile_class, b.class_list, s));
+    }
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);

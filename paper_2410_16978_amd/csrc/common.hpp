@@ -92,6 +92,16 @@ __host__ __device__ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a +
 // (row_shr 1, 2, 4, 8), then row_bcast:15 and row_bcast:31 carry row totals
 // into the rows above.  Lanes whose DPP source is outside the row, or whose
 // row is masked off, receive the identity.
+// Size class of a tile with n pairs (the forward's largest-first order).
+__device__ __forceinline__ uint32_t tile_class(uint32_t n) {
+  // half-octave classes, largest first: class 0 holds n >= 2^16, class
+  // kTileClasses - 2 holds n = 1, the last class the empty tiles
+  if (n == 0) return kTileClasses - 1;
+  const uint32_t lg = 31u - (uint32_t)__clz(n);
+  const uint32_t h = 2u * lg + ((lg > 0 && ((n >> (lg - 1)) & 1u)) ? 1u : 0u);  // floor(2 log2 n)
+  return h >= 32u ? 0u : 32u - h;
+}
+
 __device__ __forceinline__ uint32_t wave_scan_add(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);
@@ -152,8 +162,9 @@ constexpr uint32_t kT12MaxPairs = 1u << 24;  // the one-pass tile grouping's loo
 bool tile_sort12(uint64_t total_tiles, uint32_t pair_capacity);
 size_t tile_sort12_status_words(uint32_t pair_capacity);
 hipError_t launch_tile_sort12(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
-                              const uint32_t* counters, uint32_t pair_capacity, uint32_t* totals,
-                              uint32_t* block_counts, uint32_t* sel_out, uint32_t* error_flag, hipStream_t s);
+                              const uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles,
+                              uint32_t* totals, uint32_t* block_counts, uint32_t* ranges, uint32_t* class_count,
+                              uint32_t* class_list, uint32_t* sel_out, uint32_t* error_flag, hipStream_t s);
 hipError_t launch_sort_segments(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                                 const uint32_t* sel, const uint32_t* ranges, uint32_t total_tiles,
                                 const uint32_t* rec_of, const uint32_t* counters, uint32_t pair_capacity,

@@ -263,14 +263,6 @@ hipError_t launch_ranges(const uint64_t* keys_a, const uint64_t* keys_b, const u
 // tiles: class counts per block (ballots), one addition per class and
 // block reserves the block's slots in the class list.  The order within a
 // class depends on the order the blocks run, which changes no result.
-__device__ __forceinline__ uint32_t tile_class(uint32_t n) {
-  // half-octave classes, largest first: class 0 holds n >= 2^16, class
-  // kTileClasses - 2 holds n = 1, the last class the empty tiles
-  if (n == 0) return kTileClasses - 1;
-  const uint32_t lg = 31u - (uint32_t)__clz(n);
-  const uint32_t h = 2u * lg + ((lg > 0 && ((n >> (lg - 1)) & 1u)) ? 1u : 0u);  // floor(2 log2 n)
-  return h >= 32u ? 0u : 32u - h;
-}
 
 __global__ void __launch_bounds__(1024)
 k_tile_order(const uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ class_count,

@@ -345,11 +345,15 @@ k_tile_count12(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ c
 
 // Per tile (one thread each): counts[b][d] becomes the count of tile d in
 // blocks before b; totals[d] the tile's count.  Loads in flight 16 blocks
-// at a time.
+// at a time.  Then the tile's size class (the forward's largest-first order,
+// as k_tile_order files it): ballot ranks per class, one addition per class
+// and block reserves the block's slots.
 __global__ void __launch_bounds__(256)
-k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, uint32_t* __restrict__ totals) {
-  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= (uint32_t)kT12Digits) return;
+k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, uint32_t* __restrict__ totals, uint32_t n_tiles,
+              uint32_t* __restrict__ class_count, uint32_t* __restrict__ class_list, uint32_t* __restrict__ err) {
+  __shared__ uint32_t wc[4][kTileClasses];
+  __shared__ uint32_t cbase[kTileClasses];
+  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;  // < kT12Digits: the grid is exact
   uint32_t run = 0;
   uint32_t b = 0;
   for (; b + 16 <= n_blocks; b += 16) {
@@ -368,13 +372,34 @@ k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, uint32_t* __rest
     run += c;
   }
   totals[d] = run;
+  if (d >= n_tiles && run) atomicOr(err, 4u);  // a key beyond the tiles
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t c = d < n_tiles ? tile_class(run) : kTileClasses;
+  uint32_t rank = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kTileClasses; ++k) {
+    const uint64_t m = __ballot(c == k);
+    if (c == k) rank = (uint32_t)__popcll(m & lanemask_lt());
+    if (lane == 0) wc[wave][k] = (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < kTileClasses) {
+    const uint32_t tot = wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] + wc[3][threadIdx.x];
+    cbase[threadIdx.x] = tot ? atomicAdd(&class_count[threadIdx.x], tot) : 0u;
+  }
+  __syncthreads();
+  if (c < kTileClasses) {
+    uint32_t pos = cbase[c] + rank;
+    for (int w = 0; w < wave; ++w) pos += wc[w][c];
+    if (pos < n_tiles) class_list[(size_t)c * n_tiles + pos] = d;
+  }
 }
 
 __global__ void __launch_bounds__(kT12Threads)
 k_tile_pass12(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
               uint32_t* __restrict__ vout, const uint32_t* __restrict__ counters, uint32_t cap,
-              const uint32_t* __restrict__ totals, const uint32_t* __restrict__ block_off,
-              uint32_t* __restrict__ sel_out, uint32_t* __restrict__ err) {
+              const uint32_t* __restrict__ totals, const uint32_t* __restrict__ block_off, uint32_t n_tiles,
+              uint32_t* __restrict__ ranges, uint32_t* __restrict__ sel_out, uint32_t* __restrict__ err) {
   __shared__ uint16_t wave_cnt[kT12Waves][kT12Digits];  // per-wave digit counts, then offsets
   __shared__ uint64_t s_keys[kT12Tile];
   __shared__ uint32_t s_vals[kT12Tile];
@@ -457,6 +482,10 @@ k_tile_pass12(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, con
     const int d = kT12Own * t + j;
     s_start[d] = (uint16_t)off;
     s_global[d] = hoff + bo[j];
+    if (bid == 0 && (uint32_t)d < n_tiles && hg[j]) {  // the tiles' ranges, from their totals (empty: 0, 0)
+      ranges[2 * d] = hoff;
+      ranges[2 * d + 1] = hoff + hg[j];
+    }
     off += cnt[j];
     hoff += hg[j];
   }
@@ -496,17 +525,22 @@ size_t tile_sort12_status_words(uint32_t pair_capacity) {
 }
 
 // The tile grouping in one pass (tile_sort12 true): keys_a / vals_a into
-// keys_b / vals_b, *sel_out = 1.  block_counts holds
-// tile_sort12_status_words words, totals 4096 (neither needs clearing).
+// keys_b / vals_b, *sel_out = 1, the tiles' ranges and their size classes
+// (class_count zero on entry; replaces k_ranges and k_tile_order).
+// block_counts holds tile_sort12_status_words words, totals 4096 (neither
+// needs clearing).
 hipError_t launch_tile_sort12(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
-                              const uint32_t* counters, uint32_t pair_capacity, uint32_t* totals,
-                              uint32_t* block_counts, uint32_t* sel_out, uint32_t* error_flag, hipStream_t s) {
+                              const uint32_t* counters, uint32_t pair_capacity, uint32_t total_tiles,
+                              uint32_t* totals, uint32_t* block_counts, uint32_t* ranges, uint32_t* class_count,
+                              uint32_t* class_list, uint32_t* sel_out, uint32_t* error_flag, hipStream_t s) {
+  if (total_tiles > (uint32_t)kT12Digits) return hipErrorInvalidValue;
   const uint32_t nb = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kT12Tile);
   hipLaunchKernelGGL(k_tile_count12, dim3(nb), dim3(kT12Threads), 0, s, keys_a, counters, pair_capacity,
                      block_counts);
-  hipLaunchKernelGGL(k_tile_scan12, dim3(kT12Digits / 256), dim3(256), 0, s, block_counts, nb, totals);
+  hipLaunchKernelGGL(k_tile_scan12, dim3(kT12Digits / 256), dim3(256), 0, s, block_counts, nb, totals, total_tiles,
+                     class_count, class_list, error_flag);
   hipLaunchKernelGGL(k_tile_pass12, dim3(nb), dim3(kT12Threads), 0, s, keys_a, keys_b, vals_a, vals_b, counters,
-                     pair_capacity, totals, block_counts, sel_out, error_flag);
+                     pair_capacity, totals, block_counts, total_tiles, ranges, sel_out, error_flag);
   return hipGetLastError();
 }
 
