@@ -343,52 +343,78 @@ k_tile_count12(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ c
     out[i] = make_uint4(lh[4 * i], lh[4 * i + 1], lh[4 * i + 2], lh[4 * i + 3]);
 }
 
-// Per tile (one thread each): counts[b][d] becomes the count of tile d in
-// blocks before b; totals[d] the tile's count.  Loads in flight 16 blocks
-// at a time.  Then the tile's size class (the forward's largest-first order,
-// as k_tile_order files it): ballot ranks per class, one addition per class
-// and block reserves the block's slots.
-__global__ void __launch_bounds__(256)
-k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, uint32_t* __restrict__ totals, uint32_t n_tiles,
-              uint32_t* __restrict__ class_count, uint32_t* __restrict__ class_list, uint32_t* __restrict__ err) {
-  __shared__ uint32_t wc[4][kTileClasses];
+// counts[b][d] becomes the count of tile d in blocks before b, totals[d] the
+// tile's count.  A block takes 128 tiles; eight threads per tile split the
+// blocks holding pairs between them (sum, combine in LDS, then write the
+// running offsets), loads in flight 8 at a time.  Then each tile's size
+// class (the forward's largest-first order, as k_tile_order files it):
+// ballot ranks per class, one addition per class and block reserves the
+// block's slots.
+constexpr int kT12ScanTiles = 128;
+constexpr int kT12ScanSegs = 8;
+
+__global__ void __launch_bounds__(kT12ScanTiles * kT12ScanSegs)
+k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, const uint32_t* __restrict__ counters,
+              uint32_t cap, uint32_t* __restrict__ totals, uint32_t n_tiles, uint32_t* __restrict__ class_count,
+              uint32_t* __restrict__ class_list, uint32_t* __restrict__ err) {
+  __shared__ uint32_t seg_sum[kT12ScanSegs][kT12ScanTiles];
+  __shared__ uint32_t wc[kT12ScanTiles / 64][kTileClasses];
   __shared__ uint32_t cbase[kTileClasses];
-  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;  // < kT12Digits: the grid is exact
-  uint32_t run = 0;
-  uint32_t b = 0;
-  for (; b + 16 <= n_blocks; b += 16) {
-    uint32_t c[16];
+  const int seg = threadIdx.x / kT12ScanTiles, dl = threadIdx.x % kT12ScanTiles;
+  const uint32_t d = blockIdx.x * kT12ScanTiles + dl;  // < kT12Digits: the grid is exact
+  const uint32_t K = min(counters[kCntPairs], cap);
+  const uint32_t nb = min(n_blocks, div_up(K, (uint32_t)kT12Tile));  // the blocks holding pairs
+  const uint32_t per = div_up(nb, (uint32_t)kT12ScanSegs);
+  const uint32_t b0 = min(nb, seg * per), b1 = min(nb, b0 + per);
+  uint32_t sum = 0;
+  for (uint32_t b = b0; b < b1; b += 8) {
+    uint32_t c[8];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) c[u] = counts[(size_t)(b + u) * kT12Digits + d];
+    for (int u = 0; u < 8; ++u) c[u] = b + u < b1 ? counts[(size_t)(b + u) * kT12Digits + d] : 0u;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      counts[(size_t)(b + u) * kT12Digits + d] = run;
+    for (int u = 0; u < 8; ++u) sum += c[u];
+  }
+  seg_sum[seg][dl] = sum;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < kT12ScanSegs; ++q) {
+    const uint32_t v = seg_sum[q][dl];
+    run += q < seg ? v : 0u;
+    total += v;
+  }
+  for (uint32_t b = b0; b < b1; b += 8) {
+    uint32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = b + u < b1 ? counts[(size_t)(b + u) * kT12Digits + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (b + u < b1) counts[(size_t)(b + u) * kT12Digits + d] = run;
       run += c[u];
     }
   }
-  for (; b < n_blocks; ++b) {
-    const uint32_t c = counts[(size_t)b * kT12Digits + d];
-    counts[(size_t)b * kT12Digits + d] = run;
-    run += c;
-  }
-  totals[d] = run;
-  if (d >= n_tiles && run) atomicOr(err, 4u);  // a key beyond the tiles
+  // segment 0's threads (waves 0 and 1) hold the tile totals
+  const bool head = seg == 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t c = d < n_tiles ? tile_class(run) : kTileClasses;
-  uint32_t rank = 0;
+  uint32_t c = kTileClasses, rank = 0;
+  if (head) {
+    totals[d] = total;
+    if (d >= n_tiles && total) atomicOr(err, 4u);  // a key beyond the tiles
+    c = d < n_tiles ? tile_class(total) : kTileClasses;
 #pragma unroll
-  for (uint32_t k = 0; k < kTileClasses; ++k) {
-    const uint64_t m = __ballot(c == k);
-    if (c == k) rank = (uint32_t)__popcll(m & lanemask_lt());
-    if (lane == 0) wc[wave][k] = (uint32_t)__popcll(m);
+    for (uint32_t k = 0; k < kTileClasses; ++k) {
+      const uint64_t m = __ballot(c == k);
+      if (c == k) rank = (uint32_t)__popcll(m & lanemask_lt());
+      if (lane == 0) wc[wave][k] = (uint32_t)__popcll(m);
+    }
   }
   __syncthreads();
   if (threadIdx.x < kTileClasses) {
-    const uint32_t tot = wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] + wc[3][threadIdx.x];
+    const uint32_t tot = wc[0][threadIdx.x] + wc[1][threadIdx.x];
     cbase[threadIdx.x] = tot ? atomicAdd(&class_count[threadIdx.x], tot) : 0u;
   }
   __syncthreads();
-  if (c < kTileClasses) {
+  if (head && c < kTileClasses) {
     uint32_t pos = cbase[c] + rank;
     for (int w = 0; w < wave; ++w) pos += wc[w][c];
     if (pos < n_tiles) class_list[(size_t)c * n_tiles + pos] = d;
@@ -537,8 +563,9 @@ hipError_t launch_tile_sort12(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals
   const uint32_t nb = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kT12Tile);
   hipLaunchKernelGGL(k_tile_count12, dim3(nb), dim3(kT12Threads), 0, s, keys_a, counters, pair_capacity,
                      block_counts);
-  hipLaunchKernelGGL(k_tile_scan12, dim3(kT12Digits / 256), dim3(256), 0, s, block_counts, nb, totals, total_tiles,
-                     class_count, class_list, error_flag);
+  hipLaunchKernelGGL(k_tile_scan12, dim3(kT12Digits / kT12ScanTiles), dim3(kT12ScanTiles * kT12ScanSegs), 0, s,
+                     block_counts, nb, counters, pair_capacity, totals, total_tiles, class_count, class_list,
+                     error_flag);
   hipLaunchKernelGGL(k_tile_pass12, dim3(nb), dim3(kT12Threads), 0, s, keys_a, keys_b, vals_a, vals_b, counters,
                      pair_capacity, totals, block_counts, total_tiles, ranges, sel_out, error_flag);
   return hipGetLastError();
