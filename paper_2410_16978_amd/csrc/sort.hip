@@ -625,8 +625,8 @@ __device__ __forceinline__ void seg_sync() {
   }
 }
 template <int THREADS>
-__device__ __forceinline__ int seg_tid() {
-  return THREADS == 64 ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
+__device__ __forceinline__ int seg_tid() {  // index within the sorting group
+  return (int)(threadIdx.x % (unsigned)THREADS);
 }
 
 struct SegArgs {
@@ -776,10 +776,13 @@ __device__ __forceinline__ void seg_min_max(SegLdsP<THREADS, DBITS, BIG>& L, uin
 
 // Sorts segment [s0, s0 + n), n <= kCap, stably by depth bits and writes
 // vals[k] = record id, emit[k] = emission index (if emit), keys_out[k] =
-// full key (if keys_out).
+// full key (if keys_out).  Groups that share the block's barriers (halves
+// of a block) run in lockstep: pass_max (zero on entry, shared) makes them
+// take the same number of passes (extra passes on a zero digit move
+// nothing), and a group with n = 0 only takes part in the barriers.
 template <int THREADS, int DBITS>
 __device__ void sort_segment_lds(SegLdsP<THREADS, DBITS, false>& L, const SegArgs& a, uint32_t tile, uint32_t s0,
-                                 uint32_t n, uint32_t K) {
+                                 uint32_t n, uint32_t K, uint32_t* pass_max = nullptr) {
   constexpr int kCap = SegLdsP<THREADS, DBITS>::kCap;
   static_assert(kCap <= 65536, "segment index is packed in 16 bits");
   const int t = seg_tid<THREADS>(), lane = t & 63, wave = t >> 6;
@@ -792,27 +795,37 @@ __device__ void sort_segment_lds(SegLdsP<THREADS, DBITS, false>& L, const SegArg
   // its last entry, a real key, which changes neither the minimum nor the
   // maximum
   uint32_t key[kSegItems], val[kSegItems], rec[kSegItems];
-#pragma unroll
-  for (int r = 0; r < kSegItems; ++r) {
-    const uint32_t ic = min((uint32_t)(wave * I + r) * 64u + lane, n - 1u);
-    key[r] = (uint32_t)kin[s0 + ic];
-    val[r] = vals[s0 + ic];
-  }
   uint32_t bad = 0, lo = 0xFFFFFFFFu, hi = 0u;
+  if (n > 0) {  // (uniform in the group)
 #pragma unroll
-  for (int r = 0; r < kSegItems; ++r) {
-    bad |= val[r] >= K ? 1u : 0u;
-    rec[r] = a.rec_of[min(val[r], K - 1u)];
-    lo = min(lo, key[r]);
-    hi = max(hi, key[r]);
+    for (int r = 0; r < kSegItems; ++r) {
+      const uint32_t ic = min((uint32_t)(wave * I + r) * 64u + lane, n - 1u);
+      key[r] = (uint32_t)kin[s0 + ic];
+      val[r] = vals[s0 + ic];
+    }
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+      bad |= val[r] >= K ? 1u : 0u;
+      rec[r] = a.rec_of[min(val[r], K - 1u)];
+      lo = min(lo, key[r]);
+      hi = max(hi, key[r]);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) key[r] = val[r] = rec[r] = 0u;
   }
   if (bad) atomicOr(a.err, 32u);
   seg_clear_counts(L);
   seg_min_max(L, lo, hi);  // (with several waves its barrier also publishes the cleared counts)
   if constexpr (THREADS == 64) seg_sync<THREADS>();
-  const uint32_t range = hi - lo;
+  const uint32_t range = n > 0 ? hi - lo : 0u;
   const int bits = range ? 32 - __builtin_clz(range) : 0;
-  const int passes = (bits + DBITS - 1) / DBITS;
+  int passes = (bits + DBITS - 1) / DBITS;
+  if (pass_max) {  // groups in lockstep: the most passes any of them needs
+    if (t == 0) atomicMax(pass_max, (uint32_t)passes);
+    __syncthreads();
+    passes = (int)*pass_max;
+  }
   auto put = [&](uint32_t o, uint32_t depth, uint32_t e, uint32_t rc) {
     if (o >= n) {
       atomicOr(a.err, 32u);
@@ -1041,25 +1054,27 @@ constexpr int kSegWaveDigitBits = 8;
 constexpr int kSegBlockDigitBits = 9;
 constexpr int kSegSmallWaves = 16;           // small tiles per block item, one per wave
 constexpr uint32_t kSegBlockClasses = 15;  // classes with floor(2 log2 n) >= 18, i.e. n >= 512
-constexpr uint32_t kSegHeavyClasses = 11;  // n >= 2048: a block takes about as long as a wave on ~500 pairs
+constexpr uint32_t kSegSingleClasses = 9;  // n >= 4096: a whole block; below, two tiles per block (halves)
+constexpr int kSegHalfThreads = 512;
 static_assert(kSegWaveMax == 512 && kSegBlockClasses < kTileClasses, "size classes of k_tile_order");
 
 // One launch of G blocks of 1024 threads for every tile (the size classes of
 // k_tile_order, largest first).  Items, in about descending cost: the tiles
-// of at least 2048 pairs, one per block; then the tiles of at most
-// kSegWaveMax pairs in groups of kSegSmallWaves, one per wave (a wave sorts
-// ~500 pairs in about the time a block needs for ~2000); then the remaining
-// tiles above kSegWaveMax.  Block b starts with item b; later items go to
-// whichever block is free first, so a block holding one of the largest tiles
-// takes nothing else.
+// of at least 4096 pairs, one per block; the tiles of at most kSegWaveMax
+// pairs in groups of kSegSmallWaves, one per wave (a wave on ~500 pairs
+// takes about as long as a block on a large tile); then the tiles in
+// between two per block, one per 512-thread half, the halves in lockstep.
+// Block b starts with item b; later items go to whichever block is free
+// first, so a block holding one of the largest tiles takes nothing else.
 __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
   __shared__ union {
     SegLdsP<1024, kSegBlockDigitBits> packed;  // a large tile that fits in LDS
     SegLdsBig chunked;                          // larger: chunks through global memory
     SegLdsP<64, kSegWaveDigitBits> small[kSegSmallWaves];
+    SegLdsP<kSegHalfThreads, kSegBlockDigitBits> half[2];
   } L;
   __shared__ uint32_t s_end[kTileClasses];  // inclusive prefix of the class counts (empty tiles left out)
-  __shared__ uint32_t s_next;
+  __shared__ uint32_t s_next, s_passes;
   const uint32_t K = min(a.counters[kCntPairs], a.cap);
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   if (threadIdx.x < 64) {
@@ -1069,11 +1084,12 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
     if (k < kTileClasses) s_end[k] = inc;
   }
   __syncthreads();
-  const uint32_t n_heavy = s_end[kSegHeavyClasses - 1];
+  const uint32_t n_single = s_end[kSegSingleClasses - 1];
   const uint32_t n_big = s_end[kSegBlockClasses - 1];
   const uint32_t n_all = s_end[kTileClasses - 1];
   const uint32_t n_groups = div_up(n_all - n_big, (uint32_t)kSegSmallWaves);
-  const uint32_t total = n_big + n_groups;
+  const uint32_t n_pairs = div_up(n_big - n_single, 2u);
+  const uint32_t total = n_single + n_groups + n_pairs;
   // the idx-th tile of the class order (idx < n_all) and its segment
   auto segment = [&](uint32_t idx, uint32_t& tile, uint32_t& s0, uint32_t& s1) {
     uint32_t lo = 0, hi = kTileClasses - 1;  // first class with s_end > idx
@@ -1090,10 +1106,9 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
     return tile < a.n_tiles && s1 <= K && s0 <= s1;
   };
   for (uint32_t i = blockIdx.x; i < total;) {
-    uint32_t tile, s0, s1;
-    const bool group = i >= n_heavy && i < n_heavy + n_groups;
-    if (!group) {
-      const bool ok = segment(i < n_heavy ? i : i - n_groups, tile, s0, s1);
+    uint32_t tile = 0, s0 = 0, s1 = 0;
+    if (i < n_single) {
+      const bool ok = segment(i, tile, s0, s1);
       if (!ok) {
         if (threadIdx.x == 0) atomicOr(a.err, 32u);
       } else if (s1 > s0) {
@@ -1102,8 +1117,8 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
         else
           sort_segment_big(L.chunked, a, tile, s0, s1 - s0, K);
       }
-    } else {
-      const uint32_t idx = n_big + (i - n_heavy) * kSegSmallWaves + wave;
+    } else if (i < n_single + n_groups) {
+      const uint32_t idx = n_big + (i - n_single) * kSegSmallWaves + wave;
       if (idx < n_all) {
         const bool ok = segment(idx, tile, s0, s1) && s1 - s0 <= kSegWaveMax;
         if (!ok) {
@@ -1112,6 +1127,22 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
           sort_segment_lds(L.small[wave], a, tile, s0, s1 - s0, K);
         }
       }
+    } else {
+      // two tiles, one per half; a half without a (valid) tile only keeps step
+      const uint32_t h = threadIdx.x / kSegHalfThreads;
+      const uint32_t idx = n_single + 2 * (i - n_single - n_groups) + h;
+      uint32_t n = 0;
+      if (idx < n_big) {
+        const bool ok = segment(idx, tile, s0, s1) &&
+                        s1 - s0 <= (uint32_t)SegLdsP<kSegHalfThreads, kSegBlockDigitBits>::kCap;
+        if (!ok) {
+          if (threadIdx.x % kSegHalfThreads == 0) atomicOr(a.err, 32u);
+        } else {
+          n = s1 - s0;
+        }
+      }
+      if (threadIdx.x == 0) s_passes = 0;  // (published by the first barrier inside)
+      sort_segment_lds(L.half[h], a, tile, s0, n, K, &s_passes);
     }
     if (threadIdx.x == 0) s_next = gridDim.x + atomicAdd(a.ticket, 1u);
     __syncthreads();  // LDS is reused by the next item
