@@ -84,6 +84,19 @@ def test_crowded_tiles_and_depth_ties(orc):
     assert st["K"] > 3 * 8192
 
 
+def test_tile_grouping_at_the_4096_tile_boundary(orc):
+    """A view of exactly 4096 tiles (1024 x 1024: the one-pass 12-bit tile
+    grouping) and one of 4160 tiles (1040 x 1024: the 8-bit tile passes)
+    both give the oracle's sorted keys, tile ranges and images."""
+    sc = small_layered_scene(seed=5, n_per_layer=1500, n_layers=2, sh_degree=1, log_scale_mu=-3.0)
+    for W, H in ((1024, 1024), (1040, 1024)):
+        cam = scenes.orbit_camera([0.1, 0.3, -1.0], W, H)
+        scenes.enforce_distinct_depths(sc, [cam])
+        st = compare_forward(sc, [cam], [scenes.view_state()], orc, label=f"{W}x{H}")
+        print(f"{W}x{H}:", st)
+        assert st["K"] > 1000
+
+
 def test_raw_parameters_match_activated():
     """A model given as log-scales and logits (raw = 1) renders bit-for-bit
     like the same model given the activated values gsr_activate returns, and
