@@ -158,7 +158,8 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
                        uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, uint32_t* sel_out,
                        uint32_t* error_flag, hipStream_t s);
 size_t sort_status_stride(uint32_t pair_capacity);
-constexpr uint32_t kT12MaxPairs = 1u << 24;  // the one-pass tile grouping's look-back words: 4 B per pair
+constexpr uint32_t kXcds = 8;  // accelerator dies per MI355X, each with its own L2
+constexpr uint32_t kT12MaxPairs = 1u << 24;  // the one-pass tile grouping keeps per-block tile counts: 4 B per pair slot
 bool tile_sort12(uint64_t total_tiles, uint32_t pair_capacity);
 size_t tile_sort12_status_words(uint32_t pair_capacity);
 hipError_t launch_tile_sort12(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,

@@ -434,10 +434,17 @@ k_tile_pass12(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, con
   __shared__ uint32_t s_w[kT12Waves], s_h[kT12Waves];
   const uint32_t K = min(counters[kCntPairs], cap);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const uint32_t bid = blockIdx.x;
-  if (bid == 0 && t == 0) *sel_out = 1u;  // the result is in the second buffers
+  if (blockIdx.x == 0 && t == 0) *sel_out = 1u;  // the result is in the second buffers
+  // Workgroups go to the XCDs in turn (w -> XCD w % 8), and every tile's run
+  // takes a few keys from each block, so with blocks in input order an
+  // output cache line would be written in part by up to eight L2s.  Each XCD
+  // takes consecutive blocks of the ones holding pairs instead: a tile's run
+  // is then split between at most eight L2s in eight pieces.
+  const uint32_t n_act = div_up(K, (uint32_t)kT12Tile);
+  if (blockIdx.x >= n_act) return;
+  const uint32_t xcd = blockIdx.x % kXcds, q = n_act / kXcds, rem = n_act % kXcds;
+  const uint32_t bid = xcd * q + min(xcd, rem) + blockIdx.x / kXcds;  // a permutation of [0, n_act)
   const uint32_t base = bid * (uint32_t)kT12Tile;
-  if (base >= K) return;
   {
     uint32_t* c = reinterpret_cast<uint32_t*>(&wave_cnt[0][0]);
     for (int i = t; i < kT12Waves * kT12Digits / 2; i += kT12Threads) c[i] = 0u;
