@@ -631,9 +631,18 @@ __device__ __forceinline__ void seg_sync() {
     __syncthreads();
   }
 }
+// The thread index, read afresh at each use: a volatile move cannot be
+// hoisted, so the index arithmetic of every sorting path stays inside the
+// work item that needs it instead of being kept live (and spilled) across
+// the whole hand-out loop.
+__device__ __forceinline__ uint32_t seg_thread() {
+  uint32_t r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"((uint32_t)threadIdx.x));
+  return r;
+}
 template <int THREADS>
 __device__ __forceinline__ int seg_tid() {  // index within the sorting group
-  return (int)(threadIdx.x % (unsigned)THREADS);
+  return (int)(seg_thread() % (unsigned)THREADS);
 }
 
 struct SegArgs {
@@ -904,7 +913,7 @@ using SegLdsBig = SegLdsP<1024, 9, true>;
 __device__ void sort_segment_big(SegLdsBig& L, const SegArgs& a, uint32_t tile, uint32_t s0, uint32_t n,
                                  uint32_t K) {
   constexpr int T = 1024, DB = 9, D = 1 << DB, kCap = SegLdsBig::kCap;
-  const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = (int)seg_thread(), lane = t & 63, wave = t >> 6;
   const bool side = *a.sel != 0;
   uint64_t* kin = side ? a.keys_b : a.keys_a;
   uint64_t* kother = side ? a.keys_a : a.keys_b;
@@ -1083,7 +1092,6 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
   __shared__ uint32_t s_end[kTileClasses];  // inclusive prefix of the class counts (empty tiles left out)
   __shared__ uint32_t s_next, s_passes;
   const uint32_t K = min(a.counters[kCntPairs], a.cap);
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   if (threadIdx.x < 64) {
     const uint32_t k = threadIdx.x;
     const uint32_t cnt = k + 1 < kTileClasses ? min(a.class_count[k], a.n_tiles) : 0u;
@@ -1125,6 +1133,7 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
           sort_segment_big(L.chunked, a, tile, s0, s1 - s0, K);
       }
     } else if (i < n_single + n_groups) {
+      const uint32_t wave = seg_thread() >> 6, lane = seg_thread() & 63u;
       const uint32_t idx = n_big + (i - n_single) * kSegSmallWaves + wave;
       if (idx < n_all) {
         const bool ok = segment(idx, tile, s0, s1) && s1 - s0 <= kSegWaveMax;
@@ -1136,7 +1145,7 @@ __global__ void __launch_bounds__(1024) k_sort_segments(SegArgs a) {
       }
     } else {
       // two tiles, one per half; a half without a (valid) tile only keeps step
-      const uint32_t h = threadIdx.x / kSegHalfThreads;
+      const uint32_t h = seg_thread() / kSegHalfThreads;
       const uint32_t idx = n_single + 2 * (i - n_single - n_groups) + h;
       uint32_t n = 0;
       if (idx < n_big) {
