@@ -344,21 +344,25 @@ k_tile_count12(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ c
 }
 
 // counts[b][d] becomes the count of tile d in blocks before b, totals[d] the
-// tile's count.  A block takes 128 tiles; eight threads per tile split the
+// tile's count.  A block takes 64 tiles; sixteen threads per tile split the
 // blocks holding pairs between them (sum, combine in LDS, then write the
-// running offsets), loads in flight 8 at a time.  Then each tile's size
+// running offsets), loads in flight 16 at a time (one round for up to 256
+// blocks, i.e. 1M pairs).  Then each tile's size
 // class (the forward's largest-first order, as k_tile_order files it):
 // ballot ranks per class, one addition per class and block reserves the
 // block's slots.
-constexpr int kT12ScanTiles = 128;
-constexpr int kT12ScanSegs = 8;
+constexpr int kT12ScanTiles = 64;
+constexpr int kT12ScanSegs = 16;
+constexpr int kT12ScanBatch = 16;
+constexpr int kT12ScanHeadWaves = kT12ScanTiles / 64;  // waves of segment 0, which hold the totals
+static_assert(kT12ScanTiles % 64 == 0 && kT12ScanTiles * kT12ScanSegs <= 1024, "scan block shape");
 
 __global__ void __launch_bounds__(kT12ScanTiles * kT12ScanSegs)
 k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, const uint32_t* __restrict__ counters,
               uint32_t cap, uint32_t* __restrict__ totals, uint32_t n_tiles, uint32_t* __restrict__ class_count,
               uint32_t* __restrict__ class_list, uint32_t* __restrict__ err) {
   __shared__ uint32_t seg_sum[kT12ScanSegs][kT12ScanTiles];
-  __shared__ uint32_t wc[kT12ScanTiles / 64][kTileClasses];
+  __shared__ uint32_t wc[kT12ScanHeadWaves][kTileClasses];
   __shared__ uint32_t cbase[kTileClasses];
   const int seg = threadIdx.x / kT12ScanTiles, dl = threadIdx.x % kT12ScanTiles;
   const uint32_t d = blockIdx.x * kT12ScanTiles + dl;  // < kT12Digits: the grid is exact
@@ -367,12 +371,12 @@ k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, const uint32_t* 
   const uint32_t per = div_up(nb, (uint32_t)kT12ScanSegs);
   const uint32_t b0 = min(nb, seg * per), b1 = min(nb, b0 + per);
   uint32_t sum = 0;
-  for (uint32_t b = b0; b < b1; b += 8) {
-    uint32_t c[8];
+  for (uint32_t b = b0; b < b1; b += kT12ScanBatch) {
+    uint32_t c[kT12ScanBatch];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = b + u < b1 ? counts[(size_t)(b + u) * kT12Digits + d] : 0u;
+    for (int u = 0; u < kT12ScanBatch; ++u) c[u] = b + u < b1 ? counts[(size_t)(b + u) * kT12Digits + d] : 0u;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) sum += c[u];
+    for (int u = 0; u < kT12ScanBatch; ++u) sum += c[u];
   }
   seg_sum[seg][dl] = sum;
   __syncthreads();
@@ -383,17 +387,17 @@ k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, const uint32_t* 
     run += q < seg ? v : 0u;
     total += v;
   }
-  for (uint32_t b = b0; b < b1; b += 8) {
-    uint32_t c[8];
+  for (uint32_t b = b0; b < b1; b += kT12ScanBatch) {
+    uint32_t c[kT12ScanBatch];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = b + u < b1 ? counts[(size_t)(b + u) * kT12Digits + d] : 0u;
+    for (int u = 0; u < kT12ScanBatch; ++u) c[u] = b + u < b1 ? counts[(size_t)(b + u) * kT12Digits + d] : 0u;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kT12ScanBatch; ++u) {
       if (b + u < b1) counts[(size_t)(b + u) * kT12Digits + d] = run;
       run += c[u];
     }
   }
-  // segment 0's threads (waves 0 and 1) hold the tile totals
+  // segment 0's threads (the first kT12ScanHeadWaves waves) hold the tile totals
   const bool head = seg == 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t c = kTileClasses, rank = 0;
@@ -410,7 +414,9 @@ k_tile_scan12(uint32_t* __restrict__ counts, uint32_t n_blocks, const uint32_t* 
   }
   __syncthreads();
   if (threadIdx.x < kTileClasses) {
-    const uint32_t tot = wc[0][threadIdx.x] + wc[1][threadIdx.x];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kT12ScanHeadWaves; ++w) tot += wc[w][threadIdx.x];
     cbase[threadIdx.x] = tot ? atomicAdd(&class_count[threadIdx.x], tot) : 0u;
   }
   __syncthreads();
