@@ -77,7 +77,10 @@ def algorithmic_work(orc_fwd, scene, n_pix):
         "blend_bwd": {"flops": 14 * Eb + 50 * A},
         # bytes: all Gaussians read mean/opacity/layer/quat/scale (+ SH when visible), records written
         "project": {"bytes": n * (12 + 4 + 1 + 16 + 12 + 4) + nv * (12 * nc + 48 + 16)},
-        "sort": {"bytes": (8 + 24 * 5) * K},
+        # one-pass tile grouping (at most 4096 tiles: counts, keys and values in
+        # and out, 4 B block counts per (block of 4096 pairs, tile) written, read
+        # twice, written once) + per-tile depth sort (8 + 4 B in, 4 B record id, 8 B out)
+        "sort": {"bytes": (8 + 24 + 24) * K + 16 * 4096 * ((K + 4095) // 4096)},
         "duplicate": {"bytes": nv * 24 + 12 * K},
         "ranges": {"bytes": 8 * K + 8 * tiles},
         "scan": {"bytes": 8 * n},
