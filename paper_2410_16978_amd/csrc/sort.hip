@@ -494,12 +494,14 @@ k_tile_pass12(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, con
 #pragma unroll
   for (int j = 0; j < kT12Own; ++j) {
     const int d = kT12Own * t + j;
+    uint32_t c[kT12Waves];  // all waves' counts first, so the reads are in flight together
+#pragma unroll
+    for (int w = 0; w < kT12Waves; ++w) c[w] = wave_cnt[w][d];
     uint32_t run = 0;
 #pragma unroll
     for (int w = 0; w < kT12Waves; ++w) {
-      const uint32_t c = wave_cnt[w][d];
       wave_cnt[w][d] = (uint16_t)run;
-      run += c;
+      run += c[w];
     }
     cnt[j] = run;
     own += run;
@@ -730,12 +732,14 @@ __device__ __forceinline__ uint32_t seg_rank_p(SegLdsP<THREADS, DBITS, BIG>& L, 
 #pragma unroll
     for (int j = 0; j < DPT; ++j) {
       const int d = t * DPT + j;
+      uint32_t c[W];  // all waves' counts first, so the reads are in flight together
+#pragma unroll
+      for (int w = 0; w < W; ++w) c[w] = L.cnt[w][d];
       uint32_t run = 0;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        const uint32_t c = L.cnt[w][d];
         L.cnt[w][d] = (uint16_t)run;
-        run += c;
+        run += c[w];
       }
       dcnt[j] = run;
       own += run;
