@@ -55,7 +55,9 @@ def kernel_source_hash():
 
 def algorithmic_work(orc_fwd, scene, n_pix):
     """Per-launch algorithmic flops/bytes of each stage from the oracle's
-    exact counts on the same scene (units and per-unit costs: the design doc)."""
+    exact counts on the same scene: K pairs, E evaluated (pixel, pair) tests,
+    A blended pairs, Eb tests of the backward (per pixel, its tile's pairs up
+    to its last blended one); flops count an FMA as 2 and exp as 1."""
     K, E, A = orc_fwd["counts"]["K"], orc_fwd["counts"]["E"], orc_fwd["counts"]["A"]
     last = orc_fwd["last"].reshape(-1).astype(np.int64)
     ranges = orc_fwd["ranges"]
