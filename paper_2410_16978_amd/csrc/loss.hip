@@ -68,6 +68,53 @@ k_l1_loss(int n_views, int hw, const float* __restrict__ rgb, const float* __res
   }
 }
 
+// The same with four consecutive pixels per thread and step (hw a multiple
+// of 4 and every array 16-byte aligned): eight 16-byte loads in flight per
+// step instead of one pixel's eight 4-byte loads.
+__global__ void __launch_bounds__(256)
+k_l1_loss4(int n_views, int hw, const float4* __restrict__ rgb, const float4* __restrict__ alpha,
+           const float4* __restrict__ t_rgb, const float4* __restrict__ t_alpha, LossBg bg,
+           float* __restrict__ partials, const float* __restrict__ g_loss, float4* __restrict__ dL_drgb,
+           float4* __restrict__ dL_dalpha) {
+  __shared__ float lds[8];
+  const uint32_t total = (uint32_t)n_views * (uint32_t)hw;
+  const uint32_t hw4 = (uint32_t)hw / 4u, total4 = total / 4u;
+  const bool grad = dL_drgb != nullptr;
+  const float g = grad && g_loss ? g_loss[0] : 1.f;
+  const float kc = g / (float)(3 * (size_t)total), ka = g / (float)total;
+  float sc = 0.f, sa = 0.f;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total4; i += gridDim.x * blockDim.x) {
+    const uint32_t v = i / hw4, q = i - v * hw4;
+    const size_t b3 = (size_t)v * 3 * hw4 + q;
+    const float4 ta = t_alpha[i], al = alpha[i];
+    float4 tc[3], c[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      tc[ch] = t_rgb[b3 + (size_t)ch * hw4];
+      c[ch] = rgb[b3 + (size_t)ch * hw4];
+    }
+    auto sgn = [](float d, float k) { return d > 0.f ? k : (d < 0.f ? -k : 0.f); };
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float bgc = bg.bg[v][ch];
+      const float dx = c[ch].x - (tc[ch].x + (1.f - ta.x) * bgc), dy = c[ch].y - (tc[ch].y + (1.f - ta.y) * bgc);
+      const float dz = c[ch].z - (tc[ch].z + (1.f - ta.z) * bgc), dw = c[ch].w - (tc[ch].w + (1.f - ta.w) * bgc);
+      sc += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
+      if (grad) dL_drgb[b3 + (size_t)ch * hw4] = make_float4(sgn(dx, kc), sgn(dy, kc), sgn(dz, kc), sgn(dw, kc));
+    }
+    const float dx = al.x - ta.x, dy = al.y - ta.y, dz = al.z - ta.z, dw = al.w - ta.w;
+    sa += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
+    if (grad) dL_dalpha[i] = make_float4(sgn(dx, ka), sgn(dy, ka), sgn(dz, ka), sgn(dw, ka));
+  }
+  const float bc = l1_block_sum(sc, lds);
+  __syncthreads();
+  const float ba = l1_block_sum(sa, lds);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = bc;
+    partials[2 * blockIdx.x + 1] = ba;
+  }
+}
+
 // One block: the partial sums in a fixed order.
 __global__ void __launch_bounds__(256)
 k_l1_loss_final(uint32_t n_part, uint32_t total, const float* __restrict__ partials, float* __restrict__ loss) {
@@ -117,7 +164,19 @@ hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* al
   const uint32_t blocks = l1_loss_blocks(n_views, hw);
   if (blocks == 0) return hipSuccess;
   const bool grads = dL_drgb && dL_dalpha;
-  if (loss) {  // with the gradient in the same pass when both are asked for
+  auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+  const uint32_t blocks4 = min(div_up((uint32_t)n_views * (uint32_t)hw / 4u, 256u), kLossBlocks);
+  const bool vec = hw % 4 == 0 && a16(rgb) && a16(alpha) && a16(t_rgb) && a16(t_alpha) &&
+                   (!grads || (a16(dL_drgb) && a16(dL_dalpha)));
+  if (loss && vec) {
+    hipLaunchKernelGGL(k_l1_loss4, dim3(blocks4), dim3(256), 0, s, n_views, hw,
+                       reinterpret_cast<const float4*>(rgb), reinterpret_cast<const float4*>(alpha),
+                       reinterpret_cast<const float4*>(t_rgb), reinterpret_cast<const float4*>(t_alpha), bg, partials,
+                       g_loss, grads ? reinterpret_cast<float4*>(dL_drgb) : nullptr,
+                       grads ? reinterpret_cast<float4*>(dL_dalpha) : nullptr);
+    hipLaunchKernelGGL(k_l1_loss_final, dim3(1), dim3(256), 0, s, blocks4, (uint32_t)n_views * (uint32_t)hw,
+                       partials, loss);
+  } else if (loss) {  // with the gradient in the same pass when both are asked for
     const uint32_t n_part = min(blocks, kLossBlocks);
     hipLaunchKernelGGL(k_l1_loss, dim3(n_part), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
                        partials, g_loss, grads ? dL_drgb : nullptr, grads ? dL_dalpha : nullptr);
