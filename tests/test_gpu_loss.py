@@ -67,3 +67,33 @@ def test_loss_and_gradient_in_one_pass_equal_separate_calls(V, H, W):
     torch.cuda.synchronize()
     assert float(loss_a) == float(loss_b)
     assert torch.equal(gr_a, gr_b) and torch.equal(ga_a, ga_b)
+
+
+def test_misaligned_images_take_the_per_pixel_pass_with_equal_results():
+    """Images whose pixel count is a multiple of 4 but whose data do not start
+    on a 16-byte boundary take the one-pixel-per-step pass instead of the
+    four-pixel one: the same gradients bit for bit and the same loss to
+    float32 summation order."""
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    V, H, W = 2, 64, 48
+    g = torch.Generator(device="cpu").manual_seed(11)
+    rgb = torch.rand((V, 3, H, W), generator=g).cuda()
+    alpha = torch.rand((V, H, W), generator=g).cuda()
+    t_rgb = (torch.rand((V, 3, H, W), generator=g) * 0.8).cuda()
+    t_alpha = torch.rand((V, H, W), generator=g).cuda()
+    bgs = [(0.1, 0.5, 0.9), (0.7, 0.2, 0.4)]
+    gl = torch.tensor([2.5], device="cuda")
+
+    def off(x):  # the same values, one float past a 16-byte boundary
+        buf = torch.empty(x.numel() + 1, device="cuda")
+        buf[1:] = x.reshape(-1)
+        return buf[1:].view(x.shape)
+
+    m = [off(x) for x in (rgb, alpha, t_rgb, t_alpha)]
+    assert all(x.data_ptr() % 16 == 4 and x.is_contiguous() for x in m)
+    loss_a, gr_a, ga_a = rz.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, bgs, loss=True, grads=True, g_loss=gl)
+    loss_m, gr_m, ga_m = rz.l1_alpha_loss(*m, bgs, loss=True, grads=True, g_loss=gl)
+    torch.cuda.synchronize()
+    assert float(loss_m) == pytest.approx(float(loss_a), rel=2e-6)
+    assert torch.equal(gr_a, gr_m) and torch.equal(ga_a, ga_m)
