@@ -8,7 +8,7 @@
  *   - every Gaussian carries a layer id; a per-view layer-activation mask
  *     shows or hides whole layers (Sec. 1 and Sec. 3.3: only active layers
  *     are rendered);
- *   - per-layer clip planes cut through layers (Sec. 1, Sec. 5.1: the cut
+ *   - per-layer clip planes cut through layers (Sec. 1, Sec. 5: the cut
  *     edge depends on the splat centres, so a plane removes the Gaussians
  *     of its layers whose centre lies on its negative side);
  *   - training renders frozen lower layers as background and updates only
@@ -80,7 +80,7 @@ typedef struct {
 } gsr_camera;
 
 /* Clip plane: for layers whose bit is set in layer_bits, a Gaussian whose
- * centre m has n.m + d < 0 is removed (Sec. 1 and Sec. 5.1 cutting). */
+ * centre m has n.m + d < 0 is removed (Sec. 1 and Sec. 5 cutting). */
 typedef struct {
   float n[3];
   float d;

@@ -65,11 +65,13 @@ def lib():
             f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), C.c_int, C.c_int,
                           C.POINTER(Outputs), C.c_int]
             f.restype = C.c_int
-        for name, mtype, rtype in (("oracle_backward_f32", Model32, C.c_float), ("oracle_backward_f64", Model64, C.c_double)):
+        for name, mtype, in_t, out_t in (("oracle_backward_f32", Model32, C.c_float, C.c_float),
+                                         ("oracle_backward_f64", Model64, C.c_double, C.c_double),
+                                         ("oracle_backward_exact", Model32, C.c_float, C.c_double)):
             f = getattr(_lib, name)
-            P = C.POINTER(rtype)
-            f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), P, P, C.c_uint32,
-                          P, P, P, P, P, P, P, P, C.c_int]
+            Pi, Po = C.POINTER(in_t), C.POINTER(out_t)
+            f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), Pi, Pi, C.c_uint32,
+                          Po, Po, Po, Po, Po, Po, Po] + ([Po, C.c_int] if name.endswith("exact") else []) + [C.c_int]
             f.restype = C.c_int
         _lib.oracle_sh_basis_f64.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib.oracle_sh_basis_f32.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -227,40 +229,50 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
 
 
 def backward(scene, cams, views, dL_drgb, dL_dalpha, trainable=0xFFFFFFFF, dtype=np.float32, n_threads=0,
-             bound=False):
+             cond=False):
     """Exact gradients of sum(dL_drgb*rgb) + sum(dL_dalpha*alpha) w.r.t. the
     activated parameters of one scene rendered in every view.
 
-    bound=True adds g["bound"]: per gradient entry (same keys and shapes), the
-    rounding-error scale sum_slot |d entry / d slot| * sum_pixels |slot term|
-    * (blended pairs of the pixel + 64), so that an evaluation with unit
-    roundoff eps from the same records errs by at most about c * eps * bound
-    for a small constant c."""
-    dtype = np.dtype(dtype)
+    dtype float32 / float64: forward and gradient in that precision.
+    dtype "exact": the float32 forward's decisions (records, pair lists,
+    skips, clamps, stops) with the gradient evaluated in float64 from the
+    float32 records; inputs are taken as float32, results are float64.
+    dtype "exact_fwd_values": as "exact", but each blended pair's pixel
+    offset, G, alpha and transmittance are the float32 forward's own values.
+    cond=True (exact dtypes): g["cond"] holds each entry's condition (the
+    magnitude sum of its per-pixel contributions, see oracle.h), keyed and
+    shaped like the gradients."""
+    fwd_values = isinstance(dtype, str) and dtype == "exact_fwd_values"
+    exact = isinstance(dtype, str) and dtype in ("exact", "exact_fwd_values")
+    in_dt = np.dtype(np.float32) if exact else np.dtype(dtype)
+    out_dt = np.dtype(np.float64) if exact else in_dt
     L = lib()
-    ma = _ModelArrays(scene, dtype)
+    ma = _ModelArrays(scene, in_dt)
     V = len(cams)
     carr = (Camera * max(V, 1))(*[camera_struct(c) for c in cams])
     varr = (View * max(V, 1))(*[view_struct(v) for v in views])
     n = int(ma.layer.shape[0])
     nc = (int(scene["sh_degree"]) + 1) ** 2
-    g = {"mean": np.zeros((3, n), dtype), "scale": np.zeros((3, n), dtype), "quat": np.zeros((4, n), dtype),
-         "opacity": np.zeros(n, dtype), "sh": np.zeros((nc, 3, n), dtype), "max_contrib": np.zeros(n, dtype),
-         "activity": np.zeros(n, dtype)}
-    drgb = np.ascontiguousarray(dL_drgb, dtype).reshape(-1)
-    dal = np.ascontiguousarray(dL_dalpha, dtype).reshape(-1)
-    ct = C.c_float if dtype == np.float32 else C.c_double
-    fn = L.oracle_backward_f32 if dtype == np.float32 else L.oracle_backward_f64
-    packed = np.zeros((11 + 3 * nc) * n, dtype) if bound else None
-    rc = fn(V, C.byref(ma.struct), carr, varr, _ptr(drgb, ct), _ptr(dal, ct), trainable & 0xFFFFFFFF,
-            _ptr(g["mean"], ct), _ptr(g["scale"], ct), _ptr(g["quat"], ct), _ptr(g["opacity"], ct),
-            _ptr(g["sh"], ct), _ptr(g["max_contrib"], ct), _ptr(g["activity"], ct), _ptr(packed, ct), n_threads)
+    g = {"mean": np.zeros((3, n), out_dt), "scale": np.zeros((3, n), out_dt), "quat": np.zeros((4, n), out_dt),
+         "opacity": np.zeros(n, out_dt), "sh": np.zeros((nc, 3, n), out_dt), "max_contrib": np.zeros(n, out_dt),
+         "activity": np.zeros(n, out_dt)}
+    drgb = np.ascontiguousarray(dL_drgb, in_dt).reshape(-1)
+    dal = np.ascontiguousarray(dL_dalpha, in_dt).reshape(-1)
+    ci = C.c_float if in_dt == np.float32 else C.c_double
+    co = C.c_float if out_dt == np.float32 else C.c_double
+    fn = L.oracle_backward_exact if exact else (L.oracle_backward_f32 if in_dt == np.float32
+                                                 else L.oracle_backward_f64)
+    packed = np.zeros((11 + 3 * nc) * n, np.float64) if (cond and exact) else None
+    extra = (_ptr(packed, C.c_double), int(fwd_values)) if exact else ()
+    rc = fn(V, C.byref(ma.struct), carr, varr, _ptr(drgb, ci), _ptr(dal, ci), trainable & 0xFFFFFFFF,
+            _ptr(g["mean"], co), _ptr(g["scale"], co), _ptr(g["quat"], co), _ptr(g["opacity"], co),
+            _ptr(g["sh"], co), _ptr(g["max_contrib"], co), _ptr(g["activity"], co), *extra, n_threads)
     if rc != 0:
         raise RuntimeError(f"oracle backward failed: {rc}")
-    if bound:
-        g["bound"] = {"mean": packed[:3 * n].reshape(3, n), "scale": packed[3 * n:6 * n].reshape(3, n),
-                      "quat": packed[6 * n:10 * n].reshape(4, n), "opacity": packed[10 * n:11 * n],
-                      "sh": packed[11 * n:].reshape(nc, 3, n)}
+    if packed is not None:
+        g["cond"] = {"mean": packed[:3 * n].reshape(3, n), "scale": packed[3 * n:6 * n].reshape(3, n),
+                     "quat": packed[6 * n:10 * n].reshape(4, n), "opacity": packed[10 * n:11 * n],
+                     "sh": packed[11 * n:].reshape(nc, 3, n)}
     return g
 
 

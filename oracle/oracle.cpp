@@ -11,7 +11,7 @@
 // What is computed (readings of the paper where it is silent are stated in the
 // design notes and in oracle.h):
 //  * per (view, Gaussian): the paper's layer visibility and cutting (Sec. 1,
-//    Sec. 3.3 "only active layers", Sec. 5.1 cutting depends on the splat
+//    Sec. 3.3 "only active layers", Sec. 5: the cut edge depends on the splat
 //    centres) as a layer-mask bit test and centre-versus-plane tests; the
 //    EWA projection of the 3D covariance, Sigma' = J W Sigma W^T J^T
 //    (Zwicker et al., the splatting the paper names in Sec. 2.2.1); a
@@ -571,104 +571,72 @@ template <typename T> struct G2 {
   T g[9];
 };
 
-// Number type of a first-order running error bound (Wilkinson's running error
-// analysis): v is the value, m bounds the accumulated rounding error in units
-// of the unit roundoff.  Each operation adds its own rounding |result| and
-// propagates its operands' bounds.  Inputs that are themselves computed
-// values carry m = |v| (see in<>), exact constants m = 0.
-struct Mag {
-  double v = 0.0, m = 0.0;
-  Mag() = default;
-  Mag(double x) : v(x), m(0.0) {}
-  Mag(double x, double mm) : v(x), m(mm) {}
-  friend Mag operator+(Mag a, Mag b) { const double r = a.v + b.v; return {r, a.m + b.m + std::fabs(r)}; }
-  friend Mag operator-(Mag a, Mag b) { const double r = a.v - b.v; return {r, a.m + b.m + std::fabs(r)}; }
-  friend Mag operator-(Mag a) { return {-a.v, a.m}; }
-  friend Mag operator*(Mag a, Mag b) {
-    const double r = a.v * b.v;
-    return {r, a.m * std::fabs(b.v) + std::fabs(a.v) * b.m + std::fabs(r)};
-  }
-  friend Mag operator/(Mag a, Mag b) {
-    const double r = a.v / b.v;
-    return {r, a.m / std::fabs(b.v) + std::fabs(a.v) * b.m / (b.v * b.v) + std::fabs(r)};
-  }
-  Mag& operator+=(Mag b) { return *this = *this + b; }
-};
-
-// A computed input value in arithmetic N (for Mag: one rounding already in it).
-template <typename N, typename T> inline N in(T x) { return N(x); }
-template <> inline Mag in<Mag, float>(float x) { return Mag(double(x), std::fabs(double(x))); }
-template <> inline Mag in<Mag, double>(double x) { return Mag(x, std::fabs(x)); }
-
 // Chain rule from the 2D gradient g2 of one record to the Gaussian's
-// parameters, accumulated into gm[3], gs[3], gq[4], go, gsh[nc*3].  All
-// arithmetic is done in N (T itself, or Mag for the error bound).
-template <typename T, typename N = T>
-void backward_gaussian(const Model<T>& m, int i, const Cam<T>& cam, const Proj<T>& p,
-                       const SH<T>& sh, const N* g2, N* gm, N* gs, N* gq, N* go, N* gsh) {
+// parameters, accumulated into gm[3], gs[3], gq[4], go, gsh[nc*3].
+template <typename T>
+void backward_gaussian(const Model<T>& m, int i, const Cam<T>& cam, const Proj<T>& p, const SH<T>& sh,
+                       const T* g2, T* gm, T* gs, T* gq, T* go, T* gsh) {
   const int n = m.n;
-  N W[9];
-  for (int k = 0; k < 9; ++k) W[k] = in<N>(cam.R[k]);
+  const T* W = cam.R;
   // --- opacity
   *go += g2[5];
   // --- colour: SH coefficients and the view direction
-  N drgb[3];
-  for (int ch = 0; ch < 3; ++ch) drgb[ch] = ((p.clamp >> ch) & 1u) ? N(T(0)) : g2[6 + ch];
+  T drgb[3];
+  for (int ch = 0; ch < 3; ++ch) drgb[ch] = ((p.clamp >> ch) & 1u) ? T(0) : g2[6 + ch];
   const int nc = (m.D + 1) * (m.D + 1);
-  N ddir[3] = {N(T(0)), N(T(0)), N(T(0))};
+  T ddir[3] = {T(0), T(0), T(0)};
   T Gy[16][3];
   sh.grad(p.dir[0], p.dir[1], p.dir[2], Gy);
   for (int k = 0; k < nc; ++k)
     for (int ch = 0; ch < 3; ++ch) {
-      gsh[k * 3 + ch] += in<N>(p.Y[k]) * drgb[ch];
-      const N c = in<N>(m.sh[(size_t)(k * 3 + ch) * n + i]);
-      for (int j = 0; j < 3; ++j) ddir[j] += c * in<N>(Gy[k][j]) * drgb[ch];
+      gsh[k * 3 + ch] += p.Y[k] * drgb[ch];
+      const T c = m.sh[(size_t)(k * 3 + ch) * n + i];
+      for (int j = 0; j < 3; ++j) ddir[j] += c * Gy[k][j] * drgb[ch];
     }
-  const N dir[3] = {in<N>(p.dir[0]), in<N>(p.dir[1]), in<N>(p.dir[2])};
-  const N dd = dir[0] * ddir[0] + dir[1] * ddir[1] + dir[2] * ddir[2];
-  for (int j = 0; j < 3; ++j) gm[j] += (ddir[j] - dir[j] * dd) / in<N>(p.dlen);
+  const T* dir = p.dir;
+  const T dd = dir[0] * ddir[0] + dir[1] * ddir[1] + dir[2] * ddir[2];
+  for (int j = 0; j < 3; ++j) gm[j] += (ddir[j] - dir[j] * dd) / p.dlen;
   // --- conic -> (a, b, c) of the 2D covariance
-  const N a = in<N>(p.a), b = in<N>(p.b), c = in<N>(p.c), det2 = in<N>(p.det) * in<N>(p.det);
-  const N dca = g2[2], dcb = g2[3], dcc = g2[4];
-  const N da = dca * (-c * c / det2) + dcb * (b * c / det2) + dcc * (-b * b / det2);
-  const N db = dca * (N(T(2)) * b * c / det2) + dcb * (-(a * c + b * b) / det2) + dcc * (N(T(2)) * a * b / det2);
-  const N dc = dca * (-b * b / det2) + dcb * (a * b / det2) + dcc * (-a * a / det2);
+  const T a = p.a, b = p.b, c = p.c, det2 = p.det * p.det;
+  const T dca = g2[2], dcb = g2[3], dcc = g2[4];
+  const T da = dca * (-c * c / det2) + dcb * (b * c / det2) + dcc * (-b * b / det2);
+  const T db = dca * (T(2) * b * c / det2) + dcb * (-(a * c + b * b) / det2) + dcc * (T(2) * a * b / det2);
+  const T dc = dca * (-b * b / det2) + dcb * (a * b / det2) + dcc * (-a * a / det2);
   // --- Sigma' = T Sigma T^T  (entries s00 = a - kappa, s01 = b, s11 = c - kappa)
-  N Tm[6], S[9];
-  for (int k = 0; k < 6; ++k) Tm[k] = in<N>(p.Tm[k]);
-  for (int k = 0; k < 9; ++k) S[k] = in<N>(p.S[k]);
-  N ST0[3], ST1[3];
+  const T* Tm = p.Tm;
+  const T* S = p.S;
+  T ST0[3], ST1[3];
   for (int r = 0; r < 3; ++r) {
     ST0[r] = S[3 * r] * Tm[0] + S[3 * r + 1] * Tm[1] + S[3 * r + 2] * Tm[2];
     ST1[r] = S[3 * r] * Tm[3] + S[3 * r + 1] * Tm[4] + S[3 * r + 2] * Tm[5];
   }
-  N dT0[3], dT1[3], dS[9];
+  T dT0[3], dT1[3], dS[9];
   for (int r = 0; r < 3; ++r) {
-    dT0[r] = N(T(2)) * da * ST0[r] + db * ST1[r];
-    dT1[r] = db * ST0[r] + N(T(2)) * dc * ST1[r];
+    dT0[r] = T(2) * da * ST0[r] + db * ST1[r];
+    dT1[r] = db * ST0[r] + T(2) * dc * ST1[r];
   }
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q)
       dS[3 * r + q] = da * Tm[r] * Tm[q] + db * Tm[r] * Tm[3 + q] + dc * Tm[3 + r] * Tm[3 + q];
   // --- Sigma = M M^T, M = Rq diag(s)
-  N dM[9];
+  T dM[9];
   for (int r = 0; r < 3; ++r)
     for (int k = 0; k < 3; ++k) {
-      N acc = N(T(0));
-      for (int j = 0; j < 3; ++j) acc += (dS[3 * r + j] + dS[3 * j + r]) * in<N>(p.M[3 * j + k]);
+      T acc = T(0);
+      for (int j = 0; j < 3; ++j) acc += (dS[3 * r + j] + dS[3 * j + r]) * p.M[3 * j + k];
       dM[3 * r + k] = acc;
     }
-  const N s[3] = {in<N>(m.scale[i]), in<N>(m.scale[n + i]), in<N>(m.scale[2 * n + i])};
-  N dR[9];
+  const T s[3] = {m.scale[i], m.scale[n + i], m.scale[2 * n + i]};
+  T dR[9];
   for (int r = 0; r < 3; ++r)
     for (int k = 0; k < 3; ++k) {
-      gs[k] += dM[3 * r + k] * in<N>(p.Rq[3 * r + k]);
+      gs[k] += dM[3 * r + k] * p.Rq[3 * r + k];
       dR[3 * r + k] = dM[3 * r + k] * s[k];
     }
   // --- rotation matrix -> unit quaternion -> raw quaternion
-  const N w = in<N>(p.qh[0]), x = in<N>(p.qh[1]), y = in<N>(p.qh[2]), z = in<N>(p.qh[3]);
-  const N two = N(T(2));
-  N dq[4];
+  const T w = p.qh[0], x = p.qh[1], y = p.qh[2], z = p.qh[3];
+  const T two = T(2);
+  T dq[4];
   dq[0] = two * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
   dq[1] = two * (y * dR[1] + z * dR[2] + y * dR[3] - two * x * dR[4] - w * dR[5] + z * dR[6] +
                  w * dR[7] - two * x * dR[8]);
@@ -676,34 +644,33 @@ void backward_gaussian(const Model<T>& m, int i, const Cam<T>& cam, const Proj<T
                  z * dR[7] - two * y * dR[8]);
   dq[3] = two * (-two * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - two * z * dR[4] +
                  y * dR[5] + x * dR[6] + y * dR[7]);
-  const N qh[4] = {w, x, y, z};
-  const N qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  for (int k = 0; k < 4; ++k) gq[k] += (dq[k] - qh[k] * qd) / in<N>(p.qn);
+  const T qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  for (int k = 0; k < 4; ++k) gq[k] += (dq[k] - p.qh[k] * qd) / p.qn;
   // --- Jacobian and projected centre -> camera-space centre
-  N dJ00 = N(T(0)), dJ02 = N(T(0)), dJ11 = N(T(0)), dJ12 = N(T(0));
+  T dJ00 = T(0), dJ02 = T(0), dJ11 = T(0), dJ12 = T(0);
   for (int r = 0; r < 3; ++r) {
     dJ00 += dT0[r] * W[r];
     dJ02 += dT0[r] * W[6 + r];
     dJ11 += dT1[r] * W[3 + r];
     dJ12 += dT1[r] * W[6 + r];
   }
-  const N tx = in<N>(p.tx), ty = in<N>(p.ty), tz = in<N>(p.tz), tz2 = tz * tz, tz3 = tz2 * tz;
-  const N fx = in<N>(cam.fx), fy = in<N>(cam.fy);
-  N dtx = N(T(0)), dty = N(T(0)), dtz = N(T(0));
+  const T tx = p.tx, ty = p.ty, tz = p.tz, tz2 = tz * tz, tz3 = tz2 * tz;
+  const T fx = cam.fx, fy = cam.fy;
+  T dtx = T(0), dty = T(0), dtz = T(0);
   dtz += dJ00 * (-fx / tz2) + dJ11 * (-fy / tz2);
   if (!p.x_clamped) {
     dtx += dJ02 * (-fx / tz2);
     dtz += dJ02 * (two * fx * tx / tz3);
   } else {
-    dtz += dJ02 * (fx * in<N>(p.xr) / tz2);
+    dtz += dJ02 * (fx * p.xr / tz2);
   }
   if (!p.y_clamped) {
     dty += dJ12 * (-fy / tz2);
     dtz += dJ12 * (two * fy * ty / tz3);
   } else {
-    dtz += dJ12 * (fy * in<N>(p.yr) / tz2);
+    dtz += dJ12 * (fy * p.yr / tz2);
   }
-  const N du = g2[0], dv = g2[1];
+  const T du = g2[0], dv = g2[1];
   dtx += du * fx / tz;
   dtz += -du * fx * tx / tz2;
   dty += dv * fy / tz;
@@ -711,38 +678,94 @@ void backward_gaussian(const Model<T>& m, int i, const Cam<T>& cam, const Proj<T
   for (int j = 0; j < 3; ++j) gm[j] += W[j] * dtx + W[3 + j] * dty + W[6 + j] * dtz;
 }
 
-template <typename T>
-int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_view* views,
-             const T* dL_drgb, const T* dL_dalpha, uint32_t trainable, T* g_mean, T* g_scale,
-             T* g_quat, T* g_opacity, T* g_sh, T* max_contrib, T* activity, T* bound, int n_threads) {
+// A projection's values in another floating-point type (each rounded or
+// widened once).
+template <typename TG, typename TF> Proj<TG> convert(const Proj<TF>& p) {
+  Proj<TG> q;
+  q.valid = p.valid;
+  q.tx = TG(p.tx); q.ty = TG(p.ty); q.tz = TG(p.tz); q.xr = TG(p.xr); q.yr = TG(p.yr);
+  q.x_clamped = p.x_clamped; q.y_clamped = p.y_clamped;
+  q.qn = TG(p.qn);
+  for (int k = 0; k < 4; ++k) q.qh[k] = TG(p.qh[k]);
+  for (int k = 0; k < 9; ++k) { q.Rq[k] = TG(p.Rq[k]); q.M[k] = TG(p.M[k]); q.S[k] = TG(p.S[k]); }
+  q.J00 = TG(p.J00); q.J02 = TG(p.J02); q.J11 = TG(p.J11); q.J12 = TG(p.J12);
+  for (int k = 0; k < 6; ++k) q.Tm[k] = TG(p.Tm[k]);
+  q.a = TG(p.a); q.b = TG(p.b); q.c = TG(p.c); q.det = TG(p.det);
+  q.u = TG(p.u); q.v = TG(p.v); q.ca = TG(p.ca); q.cb = TG(p.cb); q.cc = TG(p.cc); q.op = TG(p.op);
+  for (int k = 0; k < 3; ++k) q.rgb[k] = TG(p.rgb[k]);
+  q.clamp = p.clamp;
+  for (int k = 0; k < 4; ++k) q.rect[k] = p.rect[k];
+  q.ntiles = p.ntiles;
+  for (int k = 0; k < 3; ++k) q.dir[k] = TG(p.dir[k]);
+  q.dlen = TG(p.dlen);
+  for (int k = 0; k < 16; ++k) q.Y[k] = TG(p.Y[k]);
+  return q;
+}
+
+// The model's parameter arrays in another floating-point type.
+template <typename TG, typename TF> struct ModelCopy {
+  std::vector<TG> mean, scale, quat, opacity, sh;
+  Model<TG> m;
+  explicit ModelCopy(const Model<TF>& s) {
+    const size_t n = (size_t)s.n, nc = (size_t)(s.D + 1) * (s.D + 1);
+    mean.assign(s.mean, s.mean + 3 * n);
+    scale.assign(s.scale, s.scale + 3 * n);
+    quat.assign(s.quat, s.quat + 4 * n);
+    opacity.assign(s.opacity, s.opacity + n);
+    sh.assign(s.sh, s.sh + 3 * nc * n);
+    m.n = s.n; m.D = s.D;
+    m.mean = mean.data(); m.scale = scale.data(); m.quat = quat.data(); m.opacity = opacity.data();
+    m.sh = sh.data(); m.layer = s.layer;
+  }
+};
+
+// Exact gradient of L = sum(dL_drgb * rgb) + sum(dL_dalpha * alpha) (B1-B10
+// of the design notes).  The forward - projection, pair lists and every
+// per-pixel decision (skip below 1/255, the 0.99 clamp, the 1e-4 stop) - is
+// the TF forward above; every quantity of the gradient (alpha, G and T of the
+// blended pairs, the colour behind each of them, the per-record 2D gradients
+// and the chain rule) is evaluated in TG from the TF records.  TF = TG is the
+// plain float or double backward; TF = float, TG = double is the float32
+// forward's gradient evaluated without float32 rounding.  With fwd_values
+// the blended pairs' offsets (dx, dy), G, alpha and transmittances are the
+// TF forward's own values instead (only the arithmetic after them is in TG).
+// cond (optional, [(11 + 3 (D+1)^2) n], packed mean, scale, quat, opacity,
+// sh like the gradients): per entry, the sum over the 2D slots of
+// |d entry / d slot| times the sum over pixels of the magnitude of the
+// slot's per-pixel terms, each taken with the magnitudes of its operands
+// (dL/dalpha as sum_ch |G_ch| (|c_ch| T + |S_ch| / (1 - alpha)) +
+// |G_A| T_final / (1 - alpha)) and weighted by the pixel's number of blended
+// pairs + 16.  A float32 evaluation's per-pixel terms carry about one
+// rounding per pair of the product behind T (and the colour behind) plus a
+// few of their own, so cond is the scale of the error that float32 leaves
+// on that entry: it errs by a small multiple of 2^-24 cond.
+template <typename TF, typename TG>
+int backward(int n_views, const Model<TF>& m, const oc_camera* cams, const oc_view* views, const TF* dL_drgb,
+             const TF* dL_dalpha, uint32_t trainable, TG* g_mean, TG* g_scale, TG* g_quat, TG* g_opacity,
+             TG* g_sh, TG* max_contrib, TG* activity, int n_threads, bool fwd_values = false,
+             TG* cond = nullptr) {
   if (n_views < 0 || m.n < 0 || m.D < 0 || m.D > 3) return -1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
   (void)n_threads;
 #endif
-  std::vector<Model<T>> models(n_views, m);
-  Scene<T> sc;
+  std::vector<Model<TF>> models(n_views, m);
+  Scene<TF> sc;
   build_scene(sc, n_views, models.data(), cams, views, 16);
-  Sorted<T> so = sort_pairs(sc);
-  ListSource<T> src(sc, &so, false);
+  Sorted<TF> so = sort_pairs(sc);
+  ListSource<TF> src(sc, &so, false);
   const int n = m.n;
   // per-record 2D gradients and max contribution, accumulated per thread
   int nthr = 1;
 #ifdef _OPENMP
   nthr = omp_get_max_threads();
 #endif
-  std::vector<std::vector<G2<T>>> acc(nthr, std::vector<G2<T>>(sc.total_recs, G2<T>{}));
-  std::vector<std::vector<T>> mc(nthr, std::vector<T>(sc.total_recs, T(0)));
-  // with `bound`: per record, the sums over pixels of the magnitudes of the
-  // terms of each 2D gradient slot (differences taken as the sum of the
-  // magnitudes of their operands), each weighted by the pixel's number of
-  // blended pairs plus 64: a term's transmittance and colour-behind carry one
-  // rounding per blended pair, its summation a few dozen more.  This is the
-  // scale of the rounding error of a finite-precision evaluation of the same
-  // sums from the same records.
-  std::vector<std::vector<G2<T>>> accb(bound ? nthr : 0, std::vector<G2<T>>(sc.total_recs, G2<T>{}));
-  struct Contrib { uint32_t rec; T alpha, Tb, G, dx, dy; bool clamped; };
+  std::vector<std::vector<G2<TG>>> acc(nthr, std::vector<G2<TG>>(sc.total_recs, G2<TG>{}));
+  std::vector<std::vector<TG>> mc(nthr, std::vector<TG>(sc.total_recs, TG(0)));
+  std::vector<std::vector<G2<TG>>> accm(cond ? nthr : 0, std::vector<G2<TG>>(sc.total_recs, G2<TG>{}));
+  struct Blended { uint32_t rec; TF alpha, Tb, G, dx, dy; bool clamped; };
+  struct Contrib { uint32_t rec; TG alpha, Tb, G, dx, dy; bool clamped; };
   for (int v = 0; v < n_views; ++v) {
     const int W = sc.cams[v].W, H = sc.cams[v].H;
     const uint64_t po = sc.info[v].pix_off;
@@ -752,145 +775,172 @@ int backward(int n_views, const Model<T>& m, const oc_camera* cams, const oc_vie
 #ifdef _OPENMP
       tid = omp_get_thread_num();
 #endif
+      std::vector<Blended> bl;
       std::vector<Contrib> cl;
       for (int x = 0; x < W; ++x) {
         size_t count, base;
         const uint32_t* list = src.get(v, x, y, &count, &base);
+        bl.clear();
+        const PixelOut<TF> fo =
+            blend_pixel(sc, list, count, TF(x) + TF(0.5), TF(y) + TF(0.5), sc.views[v].bg,
+                        [&](size_t, uint32_t rec, TF alpha, TF Tb, TF G, TF dx, TF dy, bool clamped) {
+                          bl.push_back({rec, alpha, Tb, G, dx, dy, clamped});
+                        });
+        // the blended pairs' alpha, G and transmittance in front, in TG
         cl.clear();
-        PixelOut<T> o = blend_pixel(sc, list, count, T(x) + T(0.5), T(y) + T(0.5), sc.views[v].bg,
-                                    [&](size_t, uint32_t rec, T alpha, T Tb, T G, T dx, T dy, bool clamped) {
-                                      cl.push_back({rec, alpha, Tb, G, dx, dy, clamped});
-                                    });
-        const uint64_t pix = po + (uint64_t)y * W + x;
-        T Gc[3];
-        for (int ch = 0; ch < 3; ++ch) Gc[ch] = dL_drgb[3 * po + (uint64_t)ch * W * H + (uint64_t)y * W + x];
-        const T GA = dL_dalpha[pix];
+        const TG pxg = TG(x) + TG(0.5), pyg = TG(y) + TG(0.5);
+        TG Tc = TG(1);
+        for (const Blended& e : bl) {
+          if (fwd_values) {
+            cl.push_back({e.rec, TG(e.alpha), TG(e.Tb), TG(e.G), TG(e.dx), TG(e.dy), e.clamped});
+            continue;
+          }
+          const Proj<TF>& p = sc.proj[e.rec];
+          const TG dx = TG(p.u) - pxg, dy = TG(p.v) - pyg;
+          const TG q = (TG(p.ca) * dx * dx + TG(p.cc) * dy * dy) + TG(2) * TG(p.cb) * dx * dy;
+          const TG G = std::exp(TG(-0.5) * q);
+          const TG alpha = e.clamped ? Consts<TG>::alpha_max() : TG(p.op) * G;
+          cl.push_back({e.rec, alpha, Tc, G, dx, dy, e.clamped});
+          Tc = Tc * (TG(1) - alpha);
+        }
+        const TG T_final = fwd_values ? TG(fo.T_final) : Tc;
+        TG Gc[3];
+        for (int ch = 0; ch < 3; ++ch) Gc[ch] = TG(dL_drgb[3 * po + (uint64_t)ch * W * H + (uint64_t)y * W + x]);
+        const TG GA = TG(dL_dalpha[po + (uint64_t)y * W + x]);
         // suffix colour S_k = sum_{j>k} c_j alpha_j T_j + T_final * bg
-        T S[3];
-        for (int ch = 0; ch < 3; ++ch) S[ch] = o.T_final * T(sc.views[v].bg[ch]);
-        const T depth_w = T(cl.size() + 64);
+        TG S[3];
+        for (int ch = 0; ch < 3; ++ch) S[ch] = T_final * TG(sc.views[v].bg[ch]);
         for (size_t kk = cl.size(); kk-- > 0;) {
           const Contrib& e = cl[kk];
-          const Proj<T>& p = sc.proj[e.rec];
-          G2<T>& g = acc[tid][e.rec];
-          const T w = e.alpha * e.Tb;
-          T dalpha = GA * o.T_final / (T(1) - e.alpha);
-          T mag = std::fabs(dalpha);
+          const Proj<TF>& p = sc.proj[e.rec];
+          G2<TG>& g = acc[tid][e.rec];
+          const TG w = e.alpha * e.Tb;
+          TG dalpha = GA * T_final / (TG(1) - e.alpha);
+          TG dmag = std::fabs(dalpha);
           for (int ch = 0; ch < 3; ++ch) {
+            const TG c = TG(p.rgb[ch]);
             g.g[6 + ch] += Gc[ch] * w;
-            dalpha += Gc[ch] * (p.rgb[ch] * e.Tb - S[ch] / (T(1) - e.alpha));
-            mag += std::fabs(Gc[ch]) * (std::fabs(p.rgb[ch] * e.Tb) + std::fabs(S[ch]) / (T(1) - e.alpha));
-            S[ch] += p.rgb[ch] * w;
+            dalpha += Gc[ch] * (c * e.Tb - S[ch] / (TG(1) - e.alpha));
+            dmag += std::fabs(Gc[ch]) * (std::fabs(c) * e.Tb + std::fabs(S[ch]) / (TG(1) - e.alpha));
+            S[ch] += c * w;
           }
           if (w > mc[tid][e.rec]) mc[tid][e.rec] = w;
-          if (bound)
-            for (int ch = 0; ch < 3; ++ch) accb[tid][e.rec].g[6 + ch] += depth_w * std::fabs(Gc[ch] * w);
+          const TG depth_w = TG(cl.size() + 16);
+          if (cond)
+            for (int ch = 0; ch < 3; ++ch) accm[tid][e.rec].g[6 + ch] += depth_w * std::fabs(Gc[ch] * w);
           if (e.clamped) continue;
+          const TG op = TG(p.op), ca = TG(p.ca), cb = TG(p.cb), cc = TG(p.cc);
           g.g[5] += dalpha * e.G;
-          const T dq = dalpha * (T(-0.5) * p.op * e.G);
-          g.g[0] += dq * T(2) * (p.ca * e.dx + p.cb * e.dy);
-          g.g[1] += dq * T(2) * (p.cb * e.dx + p.cc * e.dy);
+          const TG dq = dalpha * (TG(-0.5) * op * e.G);
+          g.g[0] += dq * TG(2) * (ca * e.dx + cb * e.dy);
+          g.g[1] += dq * TG(2) * (cb * e.dx + cc * e.dy);
           g.g[2] += dq * e.dx * e.dx;
-          g.g[3] += dq * T(2) * e.dx * e.dy;
+          g.g[3] += dq * TG(2) * e.dx * e.dy;
           g.g[4] += dq * e.dy * e.dy;
-          if (bound) {
-            G2<T>& b = accb[tid][e.rec];
-            const T mw = depth_w * mag;
-            const T mq = mw * (T(0.5) * p.op * e.G);
-            b.g[5] += mw * e.G;
-            b.g[0] += mq * T(2) * (std::fabs(p.ca * e.dx) + std::fabs(p.cb * e.dy));
-            b.g[1] += mq * T(2) * (std::fabs(p.cb * e.dx) + std::fabs(p.cc * e.dy));
-            b.g[2] += mq * e.dx * e.dx;
-            b.g[3] += mq * T(2) * std::fabs(e.dx * e.dy);
-            b.g[4] += mq * e.dy * e.dy;
+          if (cond) {
+            G2<TG>& a = accm[tid][e.rec];
+            const TG mw = depth_w * dmag;
+            const TG mq = mw * (TG(0.5) * op * e.G);
+            a.g[5] += mw * e.G;
+            a.g[0] += mq * TG(2) * (std::fabs(ca * e.dx) + std::fabs(cb * e.dy));
+            a.g[1] += mq * TG(2) * (std::fabs(cb * e.dx) + std::fabs(cc * e.dy));
+            a.g[2] += mq * e.dx * e.dx;
+            a.g[3] += mq * TG(2) * std::fabs(e.dx * e.dy);
+            a.g[4] += mq * e.dy * e.dy;
           }
         }
       }
     }
   }
   // reduce thread buffers in thread order
-  std::vector<G2<T>> g2(sc.total_recs, G2<T>{});
-  std::vector<G2<T>> g2b(bound ? sc.total_recs : 0, G2<T>{});
-  std::vector<T> mcr(sc.total_recs, T(0));
+  std::vector<G2<TG>> g2(sc.total_recs, G2<TG>{});
+  std::vector<G2<TG>> g2m(cond ? sc.total_recs : 0, G2<TG>{});
+  std::vector<TG> mcr(sc.total_recs, TG(0));
   for (int t = 0; t < nthr; ++t)
     for (uint64_t r = 0; r < sc.total_recs; ++r) {
       for (int k = 0; k < 9; ++k) g2[r].g[k] += acc[t][r].g[k];
-      if (bound)
-        for (int k = 0; k < 9; ++k) g2b[r].g[k] += accb[t][r].g[k];
+      if (cond)
+        for (int k = 0; k < 9; ++k) g2m[r].g[k] += accm[t][r].g[k];
       mcr[r] = std::max(mcr[r], mc[t][r]);
     }
   const int nc = (m.D + 1) * (m.D + 1);
-  SH<T> sh;
-  std::vector<T> gm(3), gs(3), gq(4), gsh(nc * 3);
+  SH<TG> sh;
+  const ModelCopy<TG, TF> mg(m);
+  std::vector<Cam<TG>> cams_g;
+  for (int v = 0; v < n_views; ++v) cams_g.emplace_back(cams[v]);
+  int i_cur = 0;
+  // The chain rule differentiates the projection at the parameters: its
+  // intermediate values are recomputed in TG from them (for TF = TG they
+  // equal the forward's), with the forward's decisions - the guard-band
+  // clamp of the Jacobian and the colour clamp bits - kept.
+  auto chain_proj = [&](int v, const Proj<TF>& pf) {
+    Proj<TG> pg = project_one(mg.m, i_cur, cams_g[v], sc.views[v], 16, sh);
+    if (!pg.valid) return convert<TG>(pf);
+    pg.x_clamped = pf.x_clamped;
+    pg.y_clamped = pf.y_clamped;
+    if (pf.x_clamped) pg.xr = TG(pf.xr);
+    if (pf.y_clamped) pg.yr = TG(pf.yr);
+    pg.clamp = pf.clamp;
+    return pg;
+  };
+  std::vector<TG> gm(3), gs(3), gq(4), gsh(nc * 3);
   const int per = 11 + 3 * nc;  // gradient entries per Gaussian
-  std::vector<T> col(per), bsum(per);
-  std::vector<Mag> cm(per);
+  std::vector<TG> col(per), csum(per);
   for (int i = 0; i < n; ++i) {
-    if (bound) std::fill(bsum.begin(), bsum.end(), T(0));
-    T go = T(0);
-    std::fill(gm.begin(), gm.end(), T(0));
-    std::fill(gs.begin(), gs.end(), T(0));
-    std::fill(gq.begin(), gq.end(), T(0));
-    std::fill(gsh.begin(), gsh.end(), T(0));
-    T mcv = T(0);
+    i_cur = i;
+    if (cond) std::fill(csum.begin(), csum.end(), TG(0));
+    TG go = TG(0);
+    std::fill(gm.begin(), gm.end(), TG(0));
+    std::fill(gs.begin(), gs.end(), TG(0));
+    std::fill(gq.begin(), gq.end(), TG(0));
+    std::fill(gsh.begin(), gsh.end(), TG(0));
+    TG mcv = TG(0);
     const bool train = m.layer[i] < 32 && ((trainable >> m.layer[i]) & 1u);
     for (int v = 0; v < n_views; ++v) {
       const uint64_t r = sc.info[v].rec_off + i;
-      const Proj<T>& p = sc.proj[r];
-      if (!p.valid) continue;
+      if (!sc.proj[r].valid) continue;
       mcv = std::max(mcv, mcr[r]);
-      if (train) backward_gaussian(m, i, sc.cams[v], p, sh, g2[r].g, gm.data(), gs.data(), gq.data(), &go, gsh.data());
-      if (train && bound) {
-        // the chain rule is linear in the 2D gradient: column s of its matrix,
-        // in magnitude, times the slot's term-magnitude sum
+      const Proj<TG> pg = train ? chain_proj(v, sc.proj[r]) : Proj<TG>();
+      if (train)
+        backward_gaussian(mg.m, i, cams_g[v], pg, sh, g2[r].g, gm.data(), gs.data(), gq.data(), &go, gsh.data());
+      if (train && cond)
+        // the chain rule is linear in the 2D gradient: column `sl` of its
+        // matrix, in magnitude, times the slot's magnitude sum
         for (int sl = 0; sl < 9; ++sl) {
-          if (g2b[r].g[sl] == T(0)) continue;
-          T e[9] = {};
-          e[sl] = T(1);
-          std::fill(col.begin(), col.end(), T(0));
-          backward_gaussian(m, i, sc.cams[v], p, sh, e, &col[0], &col[3], &col[6], &col[10], &col[11]);
-          for (int k = 0; k < per; ++k) bsum[k] += std::fabs(col[k]) * g2b[r].g[sl];
+          if (g2m[r].g[sl] == TG(0)) continue;
+          TG e[9] = {};
+          e[sl] = TG(1);
+          std::fill(col.begin(), col.end(), TG(0));
+          backward_gaussian(mg.m, i, cams_g[v], pg, sh, e, &col[0], &col[3], &col[6], &col[10], &col[11]);
+          for (int k = 0; k < per; ++k) csum[k] += std::fabs(col[k]) * g2m[r].g[sl];
         }
-        // plus the rounding of the chain rule itself (and of the record
-        // quantities it uses), as a running error bound
-        Mag g2m[9];
-        for (int sl = 0; sl < 9; ++sl) g2m[sl] = Mag(double(g2[r].g[sl]));
-        std::fill(cm.begin(), cm.end(), Mag());
-        backward_gaussian<T, Mag>(m, i, sc.cams[v], p, sh, g2m, &cm[0], &cm[3], &cm[6], &cm[10], &cm[11]);
-        for (int k = 0; k < per; ++k) bsum[k] += T(cm[k].m);
-      }
     }
     if (!train) {
-      std::fill(gm.begin(), gm.end(), T(0));
-      std::fill(gs.begin(), gs.end(), T(0));
-      std::fill(gq.begin(), gq.end(), T(0));
-      std::fill(gsh.begin(), gsh.end(), T(0));
-      go = T(0);
+      std::fill(gm.begin(), gm.end(), TG(0));
+      std::fill(gs.begin(), gs.end(), TG(0));
+      std::fill(gq.begin(), gq.end(), TG(0));
+      std::fill(gsh.begin(), gsh.end(), TG(0));
+      go = TG(0);
     }
     for (int j = 0; j < 3; ++j) g_mean[(size_t)j * n + i] = gm[j];
     for (int j = 0; j < 3; ++j) g_scale[(size_t)j * n + i] = gs[j];
     for (int j = 0; j < 4; ++j) g_quat[(size_t)j * n + i] = gq[j];
     g_opacity[i] = go;
     for (int k = 0; k < nc * 3; ++k) g_sh[(size_t)k * n + i] = gsh[k];
-    if (bound) {
-      // packed like the gradients: mean [3][n], scale [3][n], quat [4][n], opacity [n], sh [nc*3][n]
+    if (cond) {
       const size_t N = (size_t)n;
-      for (int j = 0; j < 3; ++j) bound[j * N + i] = bsum[j];
-      for (int j = 0; j < 3; ++j) bound[3 * N + j * N + i] = bsum[3 + j];
-      for (int j = 0; j < 4; ++j) bound[6 * N + j * N + i] = bsum[6 + j];
-      bound[10 * N + i] = bsum[10];
-      for (int k = 0; k < nc * 3; ++k) bound[11 * N + k * N + i] = bsum[11 + k];
+      for (int k = 0; k < per; ++k) cond[(size_t)k * N + i] = csum[k];
     }
     if (max_contrib) max_contrib[i] = mcv;
     if (activity) {
-      T pm = T(0), pc = T(0), ps = T(0);
+      TG pm = TG(0), pc = TG(0), ps = TG(0);
       for (int j = 0; j < 3; ++j) pm += gm[j] * gm[j];
       for (int k = 0; k < nc * 3; ++k) pc += gsh[k] * gsh[k];
       for (int j = 0; j < 3; ++j) {
-        const T gl = gs[j] * m.scale[(size_t)j * n + i];  // d/d log s = s * d/ds
+        const TG gl = gs[j] * mg.m.scale[(size_t)j * n + i];  // d/d log s = s * d/ds
         ps += gl * gl;
       }
-      activity[i] = T(2) * std::sqrt(pm) + T(0.1) * std::sqrt(pc) + T(0.1) * std::sqrt(ps);
+      activity[i] = TG(2) * std::sqrt(pm) + TG(0.1) * std::sqrt(pc) + TG(0.1) * std::sqrt(ps);
     }
   }
   return 0;
@@ -925,17 +975,27 @@ int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* ca
 int oracle_backward_f32(int n_views, const oc_model32* model, const oc_camera* cams, const oc_view* views,
                         const float* dL_drgb, const float* dL_dalpha, uint32_t trainable, float* g_mean,
                         float* g_scale, float* g_quat, float* g_opacity, float* g_sh, float* max_contrib,
-                        float* activity, float* bound, int n_threads) {
-  return backward<float>(n_views, to_model<float>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
-                         g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, bound, n_threads);
+                        float* activity, int n_threads) {
+  return backward<float, float>(n_views, to_model<float>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
+                                g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads);
 }
 
 int oracle_backward_f64(int n_views, const oc_model64* model, const oc_camera* cams, const oc_view* views,
                         const double* dL_drgb, const double* dL_dalpha, uint32_t trainable, double* g_mean,
                         double* g_scale, double* g_quat, double* g_opacity, double* g_sh,
-                        double* max_contrib, double* activity, double* bound, int n_threads) {
-  return backward<double>(n_views, to_model<double>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
-                          g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, bound, n_threads);
+                        double* max_contrib, double* activity, int n_threads) {
+  return backward<double, double>(n_views, to_model<double>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
+                                  g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads);
+}
+
+int oracle_backward_exact(int n_views, const oc_model32* model, const oc_camera* cams, const oc_view* views,
+                          const float* dL_drgb, const float* dL_dalpha, uint32_t trainable, double* g_mean,
+                          double* g_scale, double* g_quat, double* g_opacity, double* g_sh,
+                          double* max_contrib, double* activity, double* cond, int fwd_values,
+                          int n_threads) {
+  return backward<float, double>(n_views, to_model<float>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
+                                 g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads,
+                                 fwd_values != 0, cond);
 }
 
 void oracle_sh_basis_f64(const double* dir, double* out16) {

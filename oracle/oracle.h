@@ -8,7 +8,7 @@
  * Plain, slow, obviously correct reference of what the rasterizer computes:
  * EWA splat projection (Zwicker et al., cited in Sec. 2.2.1), view-dependent
  * spherical-harmonic colour, the paper's per-layer visibility and cutting
- * (Sec. 1, Sec. 3.3, Sec. 5.1), tile/depth keys, a stable sort, per-pixel
+ * (Sec. 1, Sec. 3.3, Sec. 5), tile/depth keys, a stable sort, per-pixel
  * front-to-back alpha compositing and its exact gradient.  Every function is
  * instantiated in float (parity) and double (finite differences).
  *
@@ -109,25 +109,41 @@ int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* ca
  * whose layer bit is clear in trainable_layers get zero gradient.
  * g_mean[3][n], g_scale[3][n], g_quat[4][n], g_opacity[n], g_sh[(D+1)^2][3][n]
  * are overwritten.  max_contrib[n] (optional) receives the largest
- * alpha * T of each Gaussian over all pixels and views; activity[n]
+ * alpha * T of each Gaussian over all pixels and views (alpha the Gaussian's
+ * opacity at the pixel, T the transmittance in front of it); activity[n]
  * (optional) receives 2|g_mean| + 0.1|g_sh| + 0.1|g_log_scale|.
- * bound (optional, [(11 + 3 (D+1)^2) n], packed in the order mean, scale,
- * quat, opacity, sh of the gradients) receives, per gradient entry, the sum
- * over the 2D gradient slots of |d entry / d slot| times the sum over pixels
- * of the magnitudes of the slot's terms, each weighted by the pixel's number
- * of blended pairs + 64, plus a running error bound of the chain rule from
- * the 2D gradient to the parameters: the scale of the rounding error of a
- * finite-precision evaluation from the same records (error <= c eps bound). */
+ * _f32 / _f64: forward and gradient in that precision.  _exact: the float32
+ * forward (records, pair lists and every per-pixel decision exactly as
+ * oracle_render_f32 takes them) with every quantity of the gradient
+ * evaluated in double from the float32 records - the gradient of the
+ * float32 forward without the float32 rounding of the backward itself.
+ * fwd_values != 0 (_exact only): the blended pairs' pixel offsets, G, alpha
+ * and transmittances are the float32 forward's own values, and only the
+ * arithmetic after them is in double; the difference to fwd_values = 0 is
+ * what the float32 rounding of those per-pixel values does to each entry.
+ * cond (_exact only, optional, [(11 + 3 (D+1)^2) n] packed mean[3][n],
+ * scale[3][n], quat[4][n], opacity[n], sh[(D+1)^2*3][n]): per entry, the
+ * sum over its 2D screen-space slots (u, v, conic a, b, c, opacity, r, g,
+ * b) of |d entry / d slot| times the sum over pixels of the magnitudes of
+ * the slot's per-pixel terms (dL/dalpha taken as the sum of the magnitudes
+ * of its operands), each weighted by its pixel's number of blended pairs
+ * + 16: the scale of the error that float32 per-pixel arithmetic (whose
+ * transmittance carries one rounding per pair) leaves on the entry. */
 int oracle_backward_f32(int n_views, const oc_model32* model, const oc_camera* cams,
                         const oc_view* views, const float* dL_drgb, const float* dL_dalpha,
                         uint32_t trainable_layers, float* g_mean, float* g_scale, float* g_quat,
                         float* g_opacity, float* g_sh, float* max_contrib, float* activity,
-                        float* bound, int n_threads);
+                        int n_threads);
 int oracle_backward_f64(int n_views, const oc_model64* model, const oc_camera* cams,
                         const oc_view* views, const double* dL_drgb, const double* dL_dalpha,
                         uint32_t trainable_layers, double* g_mean, double* g_scale, double* g_quat,
                         double* g_opacity, double* g_sh, double* max_contrib, double* activity,
-                        double* bound, int n_threads);
+                        int n_threads);
+int oracle_backward_exact(int n_views, const oc_model32* model, const oc_camera* cams,
+                          const oc_view* views, const float* dL_drgb, const float* dL_dalpha,
+                          uint32_t trainable_layers, double* g_mean, double* g_scale, double* g_quat,
+                          double* g_opacity, double* g_sh, double* max_contrib, double* activity,
+                          double* cond, int fwd_values, int n_threads);
 
 /* Real spherical-harmonic basis values Y_k(dir) for k < 16 (degree <= 3),
  * float and double, for the orthonormality check. */

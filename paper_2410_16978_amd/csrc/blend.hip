@@ -18,8 +18,9 @@
 // next batch's checkpoint (or the final one), the colour behind it is the
 // background term plus the later batches' colours, summed from the back.  It
 // walks the batch back to front, rebuilding T by division by (1 - alpha)
-// (alpha <= 0.99) and accumulating the colour behind each pair from the back,
-// which keeps that colour relatively accurate deep in a pixel's list.  The
+// (alpha <= 0.99) and carrying the upstream-weighted colour behind each pair
+// normalised by the transmittance behind it (a running convex combination),
+// which keeps it relatively accurate deep in a pixel's list.  The
 // per-pixel gradients of each pair are summed over the wave - eight of them
 // by a reduce-scatter with the lane-half and row swaps (each step halves the
 // values a lane carries), the ninth and the max with DPP - the four wave sums
@@ -29,16 +30,18 @@
 
 namespace gsr {
 
-// The conic is staged pre-multiplied by kPowScale = -log2(e) / 2 (and b
-// doubled): the exponent of G = exp(-q / 2) = 2^(kPowScale q) is then one
-// fused chain of the staged coefficients, the same in the forward and the
-// backward.
+// G = exp(-q / 2) = 2^(kPowScale q): the kernels evaluate q from the record's
+// conic (b staged doubled, which is exact) and scale it once.  Staging the
+// conic pre-multiplied by kPowScale would save that multiply but round each
+// coefficient once per splat: the same relative error at every pixel of the
+// splat, which the gradient sums over its pixels would then add up
+// coherently (thin splats, whose q is a small difference of large terms,
+// lose several digits that way).
 constexpr float kPowScale = -0.72134752044448170368f;
-constexpr float kPowScaleInv = -1.38629436111989061883f;  // 1 / kPowScale = -2 ln 2
 
 struct BatchLds {
-  float4 a[kBatch];    // u, v, conic a * kPowScale, 2 b * kPowScale
-  float4 b[kBatch];    // conic c * kPowScale, opacity, r, g
+  float4 a[kBatch];    // u, v, conic a, 2 b
+  float4 b[kBatch];    // conic c, opacity, r, g
   float c[kBatch];     // b
   float4 ell[kBatch];  // q cut-off with margin, -b/c, -b/a (the conic's minimum over a rectangle)
 };
@@ -98,8 +101,8 @@ __device__ __forceinline__ float4 reach_conic(const Staged& st) {
 
 __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int tid) {
   if (ok) {
-    L.a[tid] = make_float4(st.a.x, st.a.y, st.a.z * kPowScale, (2.f * st.a.w) * kPowScale);
-    L.b[tid] = make_float4(st.b.x * kPowScale, st.b.y, st.b.z, st.b.w);
+    L.a[tid] = make_float4(st.a.x, st.a.y, st.a.z, 2.f * st.a.w);
+    L.b[tid] = st.b;
     L.c[tid] = st.c;
     L.ell[tid] = reach_conic(st);
   }
@@ -156,9 +159,7 @@ __device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n
     if (j < n) {
       const float4 E = L.ell[j];
       const float4 A = L.a[j];
-      // the staged conic scaled back (within a few ulps; the test's margins cover it)
-      hit = E.x > 0.05f && conic_meets(make_float4(A.x, A.y, A.z * kPowScaleInv, 0.5f * A.w * kPowScaleInv),
-                                       L.b[j].x * kPowScaleInv, E, qx0, qx1, qy0, qy1);
+      hit = E.x > 0.05f && conic_meets(make_float4(A.x, A.y, A.z, 0.5f * A.w), L.b[j].x, E, qx0, qx1, qy0, qy1);
     }
     const uint64_t m = __ballot(hit);
     if (hit) list[cnt + __popcll(m & lanes_below())] = (uint8_t)j;
@@ -169,13 +170,12 @@ __device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n
 }
 
 // Base-2 exponent kPowScale q of one pair at a pixel offset (dx, dy) =
-// centre - pixel, q = a dx^2 + 2 b dx dy + c dy^2, from the staged
-// coefficients; G = 2^power.  This file is compiled without implicit FMA
-// contraction, so the forward and the backward evaluate this (and alpha)
-// with the same instructions and take the same skip decisions.  power <= 0
-// is q >= 0.
+// centre - pixel, q = a dx^2 + 2 b dx dy + c dy^2 from the staged conic;
+// G = 2^power.  This file is compiled without implicit FMA contraction, so
+// the forward and the backward evaluate this (and alpha) with the same
+// instructions and take the same skip decisions.  power <= 0 is q >= 0.
 __device__ __forceinline__ float pair_power(const float4 A, const float4 B, float dx, float dy) {
-  return fmaf(A.z * dx, dx, fmaf(B.x * dy, dy, A.w * (dx * dy)));
+  return kPowScale * fmaf(A.z * dx, dx, fmaf(B.x * dy, dy, A.w * (dx * dy)));
 }
 
 __device__ __forceinline__ float pair_gauss(float power) { return __builtin_amdgcn_exp2f(power); }
@@ -582,9 +582,18 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   const size_t pix = inside ? (size_t)py * V.W + px : 0;
   const size_t vpix = (size_t)vi * plane;  // views of one call share a resolution
   uint32_t plast = 0;
-  // P = sum_ch G_ch S_ch - GA Tfin, with S the colour behind the current pair:
-  // dL/dalpha = Tb (G . c) - P / (1 - alpha), and P grows by w (G . c) per pair
-  float T = 1.f, Tfin = 1.f, P = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GA = 0.f;
+  // With S the colour behind the current pair and T the transmittance behind
+  // it, dL/dalpha = Tb (G . c) - P / (1 - alpha) where P = sum_ch G_ch S_ch -
+  // GA Tfin.  The kernel carries Q = P / T instead: then dL/dalpha =
+  // Tb (G . c - Q) and, per blended pair, Q <- Q + alpha (G . c - Q), a convex
+  // combination of the pairs' G . c behind (and G . bg - GA), so Q keeps a
+  // relative error of a few roundings however deep the pixel, and only the
+  // factor Tb carries the transmittance rebuilt by division.  That division
+  // runs in double: in float each of up to 256 steps back from the batch end
+  // would add a rounding, several times the error a float forward leaves in
+  // T, which near-cancelling per-pixel terms turn into gradient error.
+  double T = 1.0;
+  float Tfin = 1.f, Q = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GA = 0.f;
   if (inside) {
     plast = V.last[pix];
     if (plast > start) {
@@ -603,7 +612,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
         G2 = dL_drgb[3 * vpix + 2 * plane + pix];
       }
       if (dL_dalpha) GA = dL_dalpha[vpix + pix];
-      P = fmaf(G2, sb.w, fmaf(G1, sb.z, fmaf(G0, sb.y, -GA * Tfin)));
+      Q = __fdiv_rn(fmaf(G2, sb.w, fmaf(G1, sb.z, fmaf(G0, sb.y, -GA * Tfin))), (float)T);
     } else {
       plast = 0;
     }
@@ -641,7 +650,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   const int q_lane = (lane & 2) ? 8 : 2 * (((lane >> 2) & 1) * 2 + ((lane >> 3) & 1)) + (row & 1);
   const bool writer = !(lane & 1) && (!(lane & 2) || ((lane & 12) == 0 && !(row & 1)));
   float* part_lane = &part[wave][q_lane][0];
-  // one pair for this pixel: updates T and P (back to front) and returns the
+  // one pair for this pixel: updates T and Q (back to front) and returns the
   // nine per-pixel terms; inactive pairs give zeros
   auto eval = [&](int j, bool valid, float (&v)[9], float& w) -> bool {
     const uint32_t kk = start + (uint32_t)j;
@@ -655,14 +664,20 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
     const float alpha = fminf(kAlphaMax, oG);
     const bool contrib = valid && kk < plast && power <= 0.f && alpha >= kAlphaMin;
     const bool has_grad = contrib && !(oG > kAlphaMax);  // alpha not clamped: it has a gradient
-    const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);
-    const float Tb = T * inv1m;  // transmittance in front of this pair
+    // transmittance in front of this pair: T / (1 - alpha), alpha <= 0.99,
+    // the reciprocal refined by one Newton step (a few units of 2^-53)
+    const double om = 1.0 - (double)alpha;
+    double inv1m = __builtin_amdgcn_rcp(om);
+    inv1m = fma(inv1m, fma(-om, inv1m, 1.0), inv1m);
+    const double Tbd = T * inv1m;
+    const float Tb = (float)Tbd;
     const float wv = alpha * Tb;
     const float gcol = fmaf(G2, cbl, fmaf(G1, B.w, G0 * B.z));  // G . c
-    const float dalpha = fmaf(-inv1m, P, Tb * gcol);
+    const float dq = gcol - Q;
+    const float dalpha = Tb * dq;
     w = contrib ? wv : 0.f;
-    P = fmaf(w, gcol, P);
-    T = contrib ? Tb : T;
+    Q = fmaf(contrib ? alpha : 0.f, dq, Q);
+    T = contrib ? Tbd : T;
     const float h = has_grad ? dalpha * oG : 0.f;
     const float hx = h * dx, hy = h * dy;
     v[0] = hx;

@@ -14,16 +14,16 @@
 namespace gsr {
 
 // Screen-space gradient of record r: the sum of its pairs' partials (stored
-// at their emission indices, so contiguous per record) in emission order, and
-// the largest alpha * T it reached.  Only pairs with alive[e] set have
-// partials (the others are exactly zero and were never written); their
-// loads are redirected to the zero entry at index `zero`, so the loads stay
-// branch-free and adding its +0 leaves every sum bit for bit unchanged (a
-// sum that starts at +0 never holds -0).
+// at their emission indices, so contiguous per record) in emission order,
+// accumulated in double, and the largest alpha * T it reached.  Only pairs
+// with alive[e] set have partials (the others are exactly zero and were never
+// written); their loads are redirected to the zero entry at index `zero`, so
+// the loads stay branch-free and adding its +0 leaves every sum bit for bit
+// unchanged (a sum that starts at +0 never holds -0).
 __device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restrict__ offsets,
                                             const float* __restrict__ g_pair, const uint8_t* __restrict__ alive,
-                                            uint32_t zero, uint32_t K, float* g, float& wmax) {
-  for (int c = 0; c < 9; ++c) g[c] = 0.f;
+                                            uint32_t zero, uint32_t K, double* g, float& wmax) {
+  for (int c = 0; c < 9; ++c) g[c] = 0.0;
   const uint32_t e0 = offsets[r], e1 = min(offsets[r + 1], K);
   // four pairs per step: their flags, then their loads, in flight at once
   for (uint32_t e = e0; e < e1; e += 4) {
@@ -54,8 +54,13 @@ __device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restri
 }
 
 // Geometry: opacity, and the centre / covariance chain to mean, scale and
-// quaternion.  The colour gradient of each visible record (zero on clamped
-// channels) is left in g_col[r][3] for the SH kernel.
+// quaternion, in double: the chain rule takes differences of products of
+// the covariance terms (a nearly isotropic splat's rotation gradient is a
+// small difference of large ones), which float32 would leave with a relative
+// error far above the per-pixel terms' own.  The kernel is bound by the
+// loads of the pair partials, so the double arithmetic costs no time.  The
+// colour gradient of each visible record (zero on clamped channels) is left
+// in g_col[r][3] for the SH kernel.
 __global__ void __launch_bounds__(256)
 k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __restrict__ records,
                    const uint32_t* __restrict__ offsets, const float* __restrict__ g_pair,
@@ -71,33 +76,33 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
   const bool train = layer < 32u && ((trainable >> layer) & 1u);
   const uint32_t K = min(counters[kCntPairs], cap);
   float wmax = 0.f;
-  float gm[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
+  double gm[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0}, go = 0.0;
   if (!train && max_contrib) {
-    float g[9];
+    double g[9];
     for (int jv = 0; jv < job.n_views; ++jv) {
       const uint32_t r = views[job.view[jv]].rec_off + (uint32_t)i;
       if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) != 0u) record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
     }
   }
   if (train) {
-    const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
-    const float s[3] = {act_scale(m.scale[i], m.raw), act_scale(m.scale[n + i], m.raw),
-                        act_scale(m.scale[2 * n + i], m.raw)};
-    float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
-    const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-    const float iq = qn > 0.f ? 1.f / qn : 0.f;
+    const double mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
+    const double s[3] = {act_scale(m.scale[i], m.raw), act_scale(m.scale[n + i], m.raw),
+                         act_scale(m.scale[2 * n + i], m.raw)};
+    double qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double iq = qn > 0.0 ? 1.0 / qn : 0.0;
     qw *= iq; qx *= iq; qy *= iq; qz *= iq;
-    float Rq[9];
-    Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
-    Rq[1] = 2.f * (qx * qy - qw * qz);
-    Rq[2] = 2.f * (qx * qz + qw * qy);
-    Rq[3] = 2.f * (qx * qy + qw * qz);
-    Rq[4] = 1.f - 2.f * (qx * qx + qz * qz);
-    Rq[5] = 2.f * (qy * qz - qw * qx);
-    Rq[6] = 2.f * (qx * qz - qw * qy);
-    Rq[7] = 2.f * (qy * qz + qw * qx);
-    Rq[8] = 1.f - 2.f * (qx * qx + qy * qy);
-    float M[9], S[9];
+    double Rq[9];
+    Rq[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+    Rq[1] = 2.0 * (qx * qy - qw * qz);
+    Rq[2] = 2.0 * (qx * qz + qw * qy);
+    Rq[3] = 2.0 * (qx * qy + qw * qz);
+    Rq[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
+    Rq[5] = 2.0 * (qy * qz - qw * qx);
+    Rq[6] = 2.0 * (qx * qz - qw * qy);
+    Rq[7] = 2.0 * (qy * qz + qw * qx);
+    Rq[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+    double M[9], S[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -107,62 +112,81 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         S[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
-    float dM[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    double dM[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int jv = 0; jv < job.n_views; ++jv) {
       const ViewD& V = views[job.view[jv]];
       const uint32_t r = V.rec_off + (uint32_t)i;
       const float* rec = records + (size_t)r * kRecordFloats;
       if (__float_as_uint(rec[11]) == 0u) continue;  // culled in this view
       const uint32_t clamp_bits = __float_as_uint(rec[10]);
-      float g[9];
+      double g[9];
       record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
       go += g[5];
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) g_col[(size_t)r * 3 + ch] = ((clamp_bits >> ch) & 1u) ? 0.f : g[6 + ch];
-      const float* W = V.R;
-      const float tx = W[0] * mx + W[1] * my + W[2] * mz + V.t[0];
-      const float ty = W[3] * mx + W[4] * my + W[5] * mz + V.t[1];
-      const float tz = W[6] * mx + W[7] * my + W[8] * mz + V.t[2];
-      // ---- conic -> 2D covariance (a, b, c)
-      const float lim_x = V.guard * fmaxf(V.cx, (float)V.W - V.cx) / V.fx;
-      const float lim_y = V.guard * fmaxf(V.cy, (float)V.H - V.cy) / V.fy;
-      const float xr0 = tx / tz, yr0 = ty / tz;
-      const bool xcl = (xr0 < -lim_x) || (xr0 > lim_x);
-      const bool ycl = (yr0 < -lim_y) || (yr0 > lim_y);
-      const float xr = fminf(fmaxf(xr0, -lim_x), lim_x), yr = fminf(fmaxf(yr0, -lim_y), lim_y);
-      const float itz = 1.f / tz, itz2 = itz * itz, itz3 = itz2 * itz;
-      const float J00 = V.fx * itz, J02 = -V.fx * xr * itz;
-      const float J11 = V.fy * itz, J12 = -V.fy * yr * itz;
-      float Tm[6];
+      for (int ch = 0; ch < 3; ++ch) g_col[(size_t)r * 3 + ch] = ((clamp_bits >> ch) & 1u) ? 0.f : (float)g[6 + ch];
+      double W[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) W[k] = V.R[k];
+      const double fx = V.fx, fy = V.fy;
+      const double tx = W[0] * mx + W[1] * my + W[2] * mz + (double)V.t[0];
+      const double ty = W[3] * mx + W[4] * my + W[5] * mz + (double)V.t[1];
+      const double tz = W[6] * mx + W[7] * my + W[8] * mz + (double)V.t[2];
+      // ---- guard band: the clamp decision and the clamped slope exactly as
+      // the projection took them (float, same operation order)
+      bool xcl, ycl;
+      float xr_f, yr_f;
+      {
+        const float* Wf = V.R;
+        const float fmx = m.mean[i], fmy = m.mean[n + i], fmz = m.mean[2 * n + i];
+        const float ftx = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(Wf[0], fmx), __fmul_rn(Wf[1], fmy)),
+                                              __fmul_rn(Wf[2], fmz)), V.t[0]);
+        const float fty = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(Wf[3], fmx), __fmul_rn(Wf[4], fmy)),
+                                              __fmul_rn(Wf[5], fmz)), V.t[1]);
+        const float ftz = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(Wf[6], fmx), __fmul_rn(Wf[7], fmy)),
+                                              __fmul_rn(Wf[8], fmz)), V.t[2]);
+        const float lim_x = __fdiv_rn(__fmul_rn(V.guard, fmaxf(V.cx, __fsub_rn((float)V.W, V.cx))), V.fx);
+        const float lim_y = __fdiv_rn(__fmul_rn(V.guard, fmaxf(V.cy, __fsub_rn((float)V.H, V.cy))), V.fy);
+        const float x0 = __fdiv_rn(ftx, ftz), y0 = __fdiv_rn(fty, ftz);
+        xcl = (x0 < -lim_x) || (x0 > lim_x);
+        ycl = (y0 < -lim_y) || (y0 > lim_y);
+        xr_f = fminf(fmaxf(x0, -lim_x), lim_x);
+        yr_f = fminf(fmaxf(y0, -lim_y), lim_y);
+      }
+      const double xr = xcl ? (double)xr_f : tx / tz;
+      const double yr = ycl ? (double)yr_f : ty / tz;
+      const double itz = 1.0 / tz, itz2 = itz * itz, itz3 = itz2 * itz;
+      const double J00 = fx * itz, J02 = -fx * xr * itz;
+      const double J11 = fy * itz, J12 = -fy * yr * itz;
+      double Tm[6];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         Tm[c] = J00 * W[c] + J02 * W[6 + c];
         Tm[3 + c] = J11 * W[3 + c] + J12 * W[6 + c];
       }
-      float ST0[3], ST1[3];
+      double ST0[3], ST1[3];
 #pragma unroll
       for (int r2 = 0; r2 < 3; ++r2) {
         ST0[r2] = S[3 * r2] * Tm[0] + S[3 * r2 + 1] * Tm[1] + S[3 * r2 + 2] * Tm[2];
         ST1[r2] = S[3 * r2] * Tm[3] + S[3 * r2 + 1] * Tm[4] + S[3 * r2 + 2] * Tm[5];
       }
-      const float a = Tm[0] * ST0[0] + Tm[1] * ST0[1] + Tm[2] * ST0[2] + kKappa;
-      const float b = Tm[0] * ST1[0] + Tm[1] * ST1[1] + Tm[2] * ST1[2];
-      const float c = Tm[3] * ST1[0] + Tm[4] * ST1[1] + Tm[5] * ST1[2] + kKappa;
-      const float det = a * c - b * b;
-      const float id2 = 1.f / (det * det);
-      const float dca = g[2], dcb = g[3], dcc = g[4];
-      const float da = (-c * c * dca + b * c * dcb - b * b * dcc) * id2;
-      const float db = (2.f * b * c * dca - (a * c + b * b) * dcb + 2.f * a * b * dcc) * id2;
-      const float dc = (-b * b * dca + a * b * dcb - a * a * dcc) * id2;
+      const double a = Tm[0] * ST0[0] + Tm[1] * ST0[1] + Tm[2] * ST0[2] + (double)kKappa;
+      const double b = Tm[0] * ST1[0] + Tm[1] * ST1[1] + Tm[2] * ST1[2];
+      const double c = Tm[3] * ST1[0] + Tm[4] * ST1[1] + Tm[5] * ST1[2] + (double)kKappa;
+      const double det = a * c - b * b;
+      const double id2 = 1.0 / (det * det);
+      const double dca = g[2], dcb = g[3], dcc = g[4];
+      const double da = (-c * c * dca + b * c * dcb - b * b * dcc) * id2;
+      const double db = (2.0 * b * c * dca - (a * c + b * b) * dcb + 2.0 * a * b * dcc) * id2;
+      const double dc = (-b * b * dca + a * b * dcb - a * a * dcc) * id2;
       // ---- Sigma' = T Sigma T^T
-      float dT0[3], dT1[3];
+      double dT0[3], dT1[3];
 #pragma unroll
       for (int r2 = 0; r2 < 3; ++r2) {
-        dT0[r2] = 2.f * da * ST0[r2] + db * ST1[r2];
-        dT1[r2] = db * ST0[r2] + 2.f * dc * ST1[r2];
+        dT0[r2] = 2.0 * da * ST0[r2] + db * ST1[r2];
+        dT1[r2] = db * ST0[r2] + 2.0 * dc * ST1[r2];
       }
       // dSigma (symmetrised) and dM = (dS + dS^T) M
-      float dS[9];
+      double dS[9];
 #pragma unroll
       for (int r2 = 0; r2 < 3; ++r2)
 #pragma unroll
@@ -172,13 +196,13 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
       for (int r2 = 0; r2 < 3; ++r2)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          float acc = 0.f;
+          double acc = 0.0;
 #pragma unroll
           for (int j = 0; j < 3; ++j) acc += (dS[3 * r2 + j] + dS[3 * j + r2]) * M[3 * j + k];
           dM[3 * r2 + k] += acc;
         }
       // ---- Jacobian and projected centre -> camera-space centre
-      float dJ00 = 0.f, dJ02 = 0.f, dJ11 = 0.f, dJ12 = 0.f;
+      double dJ00 = 0.0, dJ02 = 0.0, dJ11 = 0.0, dJ12 = 0.0;
 #pragma unroll
       for (int r2 = 0; r2 < 3; ++r2) {
         dJ00 += dT0[r2] * W[r2];
@@ -186,30 +210,30 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
         dJ11 += dT1[r2] * W[3 + r2];
         dJ12 += dT1[r2] * W[6 + r2];
       }
-      float dtx = 0.f, dty = 0.f, dtz = 0.f;
-      dtz += -(dJ00 * V.fx + dJ11 * V.fy) * itz2;
+      double dtx = 0.0, dty = 0.0, dtz = 0.0;
+      dtz += -(dJ00 * fx + dJ11 * fy) * itz2;
       if (!xcl) {
-        dtx += -dJ02 * V.fx * itz2;
-        dtz += 2.f * dJ02 * V.fx * tx * itz3;
+        dtx += -dJ02 * fx * itz2;
+        dtz += 2.0 * dJ02 * fx * tx * itz3;
       } else {
-        dtz += dJ02 * V.fx * xr * itz2;
+        dtz += dJ02 * fx * xr * itz2;
       }
       if (!ycl) {
-        dty += -dJ12 * V.fy * itz2;
-        dtz += 2.f * dJ12 * V.fy * ty * itz3;
+        dty += -dJ12 * fy * itz2;
+        dtz += 2.0 * dJ12 * fy * ty * itz3;
       } else {
-        dtz += dJ12 * V.fy * yr * itz2;
+        dtz += dJ12 * fy * yr * itz2;
       }
-      dtx += g[0] * V.fx * itz;
-      dtz += -g[0] * V.fx * tx * itz2;
-      dty += g[1] * V.fy * itz;
-      dtz += -g[1] * V.fy * ty * itz2;
+      dtx += g[0] * fx * itz;
+      dtz += -g[0] * fx * tx * itz2;
+      dty += g[1] * fy * itz;
+      dtz += -g[1] * fy * ty * itz2;
       gm[0] += W[0] * dtx + W[3] * dty + W[6] * dtz;
       gm[1] += W[1] * dtx + W[4] * dty + W[7] * dtz;
       gm[2] += W[2] * dtx + W[5] * dty + W[8] * dtz;
     }
     // ---- M = Rq diag(s) -> scale, rotation -> quaternion
-    float dR[9];
+    double dR[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -217,15 +241,15 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
         gs[k] += dM[3 * r + k] * Rq[3 * r + k];
         dR[3 * r + k] = dM[3 * r + k] * s[k];
       }
-    float dq[4];
-    dq[0] = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-    dq[1] = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - qw * dR[5] + qz * dR[6] +
-                   qw * dR[7] - 2.f * qx * dR[8]);
-    dq[2] = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
-                   qz * dR[7] - 2.f * qy * dR[8]);
-    dq[3] = 2.f * (-2.f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.f * qz * dR[4] +
+    double dq[4];
+    dq[0] = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+    dq[1] = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] +
+                   qw * dR[7] - 2.0 * qx * dR[8]);
+    dq[2] = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
+                   qz * dR[7] - 2.0 * qy * dR[8]);
+    dq[3] = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
                    qy * dR[5] + qx * dR[6] + qy * dR[7]);
-    const float qd = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+    const double qd = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
     gq[0] = (dq[0] - qw * qd) * iq;
     gq[1] = (dq[1] - qx * qd) * iq;
     gq[2] = (dq[2] - qy * qd) * iq;
@@ -233,17 +257,17 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
     if (m.raw) {  // chain rule of the activations: d exp = exp, d logistic = o (1 - o)
 #pragma unroll
       for (int k = 0; k < 3; ++k) gs[k] *= s[k];
-      const float o = act_opacity(m.opacity[i], 1);
-      go *= o * (1.0f - o);
+      const double o = act_opacity(m.opacity[i], 1);
+      go *= o * (1.0 - o);
     }
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) g_mean[(size_t)k * n + i] = gm[k];
+  for (int k = 0; k < 3; ++k) g_mean[(size_t)k * n + i] = (float)gm[k];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) g_scale[(size_t)k * n + i] = gs[k];
+  for (int k = 0; k < 3; ++k) g_scale[(size_t)k * n + i] = (float)gs[k];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) g_quat[(size_t)k * n + i] = gq[k];
-  g_opacity[i] = go;
+  for (int k = 0; k < 4; ++k) g_quat[(size_t)k * n + i] = (float)gq[k];
+  g_opacity[i] = (float)go;
   if (max_contrib) max_contrib[i] = fmaxf(max_contrib[i], wmax);
 }
 
@@ -270,7 +294,7 @@ k_project_bwd_sh(JobD job, const ViewD* __restrict__ views, const float* __restr
     return;
   }
   const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
-  float gm[3] = {0.f, 0.f, 0.f};
+  double gm[3] = {0.0, 0.0, 0.0};
   for (int jv = 0; jv < job.n_views; ++jv) {
     const ViewD& V = views[job.view[jv]];
     const uint32_t r = V.rec_off + (uint32_t)i;
@@ -287,30 +311,36 @@ k_project_bwd_sh(JobD job, const ViewD* __restrict__ views, const float* __restr
     float Y[16];
     sh_basis<D>(dirx, diry, dirz, Y);
     // d rgb / d dir = sum_k (sum_ch drgb_ch sh_k,ch) grad Y_k: one gradient of
-    // the SH expansion with the drgb-weighted coefficients
-    float e[16];
+    // the SH expansion with the drgb-weighted coefficients (below)
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      e[k] = 0.f;
+    for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        e[k] += m.sh[(size_t)(k * 3 + ch) * n + i] * drgb[ch];
-        gsh[k * 3 + ch] += Y[k] * drgb[ch];
-      }
-    }
+      for (int ch = 0; ch < 3; ++ch) gsh[k * 3 + ch] += Y[k] * drgb[ch];
     if (D > 0) {
-      float ddir[3];
-      sh_dir_grad<D>(dirx, diry, dirz, e, ddir[0], ddir[1], ddir[2]);
-      const float dd = dirx * ddir[0] + diry * ddir[1] + dirz * ddir[2];
-      gm[0] += (ddir[0] - dirx * dd) * idl;
-      gm[1] += (ddir[1] - diry * dd) * idl;
-      gm[2] += (ddir[2] - dirz * dd) * idl;
+      // the tangential part of the direction gradient, in double (a
+      // difference of nearly parallel vectors when the gradient points along
+      // the view direction)
+      double ed[16];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        ed[k] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) ed[k] += (double)m.sh[(size_t)(k * 3 + ch) * n + i] * (double)drgb[ch];
+      }
+      const double dl64 = sqrt((double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz);
+      const double ux = ddx / dl64, uy = ddy / dl64, uz = ddz / dl64;
+      double ddir[3];
+      sh_dir_grad<D>(ux, uy, uz, ed, ddir[0], ddir[1], ddir[2]);
+      const double dd = ux * ddir[0] + uy * ddir[1] + uz * ddir[2];
+      gm[0] += (ddir[0] - ux * dd) / dl64;
+      gm[1] += (ddir[1] - uy * dd) / dl64;
+      gm[2] += (ddir[2] - uz * dd) / dl64;
     }
   }
   float pm = 0.f;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float v = g_mean[(size_t)k * n + i] + gm[k];
+    const float v = (float)((double)g_mean[(size_t)k * n + i] + gm[k]);
     g_mean[(size_t)k * n + i] = v;
     pm += v * v;
   }

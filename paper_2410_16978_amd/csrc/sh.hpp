@@ -44,51 +44,50 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
   }
 }
 
-// d/d(x, y, z) of sum_k c_k Y_k for one colour channel's coefficients c.
-template <int D>
-__device__ __forceinline__ void sh_dir_grad(float x, float y, float z, const float* c, float& gx,
-                                            float& gy, float& gz) {
-  gx = 0.f;
-  gy = 0.f;
-  gz = 0.f;
+// d/d(x, y, z) of sum_k c_k Y_k for the coefficients c (float or double).
+template <int D, typename T>
+__device__ __forceinline__ void sh_dir_grad(T x, T y, T z, const T* c, T& gx, T& gy, T& gz) {
+  gx = T(0);
+  gy = T(0);
+  gz = T(0);
   if (D >= 1) {
-    gy += -kShC1 * c[1];
-    gz += kShC1 * c[2];
-    gx += -kShC1 * c[3];
+    gy += -T(kShC1) * c[1];
+    gz += T(kShC1) * c[2];
+    gx += -T(kShC1) * c[3];
   }
   if (D >= 2) {
-    gx += kShC2a * y * c[4];
-    gy += kShC2a * x * c[4];
-    gy += -kShC2a * z * c[5];
-    gz += -kShC2a * y * c[5];
-    gx += -2.f * kShC2b * x * c[6];
-    gy += -2.f * kShC2b * y * c[6];
-    gz += 4.f * kShC2b * z * c[6];
-    gx += -kShC2a * z * c[7];
-    gz += -kShC2a * x * c[7];
-    gx += 2.f * kShC2c * x * c[8];
-    gy += -2.f * kShC2c * y * c[8];
+    gx += T(kShC2a) * y * c[4];
+    gy += T(kShC2a) * x * c[4];
+    gy += -T(kShC2a) * z * c[5];
+    gz += -T(kShC2a) * y * c[5];
+    gx += -T(2) * T(kShC2b) * x * c[6];
+    gy += -T(2) * T(kShC2b) * y * c[6];
+    gz += T(4) * T(kShC2b) * z * c[6];
+    gx += -T(kShC2a) * z * c[7];
+    gz += -T(kShC2a) * x * c[7];
+    gx += T(2) * T(kShC2c) * x * c[8];
+    gy += -T(2) * T(kShC2c) * y * c[8];
     if (D >= 3) {
-      const float xx = x * x, yy = y * y, zz = z * z;
-      gx += -6.f * kShC3a * x * y * c[9];
-      gy += -kShC3a * (3.f * xx - 3.f * yy) * c[9];
-      gx += kShC3b * y * z * c[10];
-      gy += kShC3b * x * z * c[10];
-      gz += kShC3b * x * y * c[10];
-      gx += 2.f * kShC3c * x * y * c[11];
-      gy += -kShC3c * (4.f * zz - xx - 3.f * yy) * c[11];
-      gz += -8.f * kShC3c * y * z * c[11];
-      gx += -6.f * kShC3d * x * z * c[12];
-      gy += -6.f * kShC3d * y * z * c[12];
-      gz += kShC3d * (6.f * zz - 3.f * xx - 3.f * yy) * c[12];
-      gx += -kShC3c * (4.f * zz - 3.f * xx - yy) * c[13];
-      gy += 2.f * kShC3c * x * y * c[13];
-      gz += -8.f * kShC3c * x * z * c[13];
-      gx += 2.f * kShC3e * x * z * c[14];
-      gy += -2.f * kShC3e * y * z * c[14];
-      gz += kShC3e * (xx - yy) * c[14];
-      gx += -kShC3a * (3.f * xx - 3.f * yy) * c[15];
-      gy += 6.f * kShC3a * x * y * c[15];
+      const T xx = x * x, yy = y * y, zz = z * z;
+      gx += -T(6) * T(kShC3a) * x * y * c[9];
+      gy += -T(kShC3a) * (T(3) * xx - T(3) * yy) * c[9];
+      gx += T(kShC3b) * y * z * c[10];
+      gy += T(kShC3b) * x * z * c[10];
+      gz += T(kShC3b) * x * y * c[10];
+      gx += T(2) * T(kShC3c) * x * y * c[11];
+      gy += -T(kShC3c) * (T(4) * zz - xx - T(3) * yy) * c[11];
+      gz += -T(8) * T(kShC3c) * y * z * c[11];
+      gx += -T(6) * T(kShC3d) * x * z * c[12];
+      gy += -T(6) * T(kShC3d) * y * z * c[12];
+      gz += T(kShC3d) * (T(6) * zz - T(3) * xx - T(3) * yy) * c[12];
+      gx += -T(kShC3c) * (T(4) * zz - T(3) * xx - yy) * c[13];
+      gy += T(2) * T(kShC3c) * x * y * c[13];
+      gz += -T(8) * T(kShC3c) * x * z * c[13];
+      gx += T(2) * T(kShC3e) * x * z * c[14];
+      gy += -T(2) * T(kShC3e) * y * z * c[14];
+      gz += T(kShC3e) * (xx - yy) * c[14];
+      gx += -T(kShC3a) * (T(3) * xx - T(3) * yy) * c[15];
+      gy += T(6) * T(kShC3a) * x * y * c[15];
     }
   }
 }

@@ -99,55 +99,102 @@ def assert_images(rgb, alpha, ref, label="", last=None):
             "max_err_all": max(float(err_rgb.max()), float(err_a.max()))}
 
 
-ROUNDING_C = 1.0  # multiple of eps32 * (the oracle's first-order rounding-error bound) allowed per entry
+SENS_K = 4.0  # multiple of an entry's float32 sensitivity allowed beyond the plain bar
+EXTRA_FLOOR_FRACTION = 1e-5  # plain-bar misses allowed beyond the float32 oracle's own count
+U32 = 2.0 ** -24  # unit roundoff of float32
 
 
-def assert_grad_close(got, ref32, name, bound, exempt=None, ref64=None):
-    """Gradient parity bar.
+def grad_refs(orc, scene, cams, views, Gr, Ga, trainable=0xFFFFFFFF):
+    """Reference gradient, per-entry float32 sensitivity and the float32
+    oracle's gradient.
 
-    Per entry, against the float32 oracle (the method's precision, same
-    records bit for bit): |got - ref32| <= max(1e-3 * max(|ref32|,
-    1e-3 * RMS(ref32)), eps32 * bound), where `bound` is the oracle's
-    first-order rounding-error bound of that entry (depth-weighted magnitudes
-    of the per-pixel terms of each 2D gradient slot through |d entry / d slot|,
-    plus a running error bound of the chain rule): an entry that is a small
-    difference of large terms cannot be reproduced to 1e-3 by any float32
-    evaluation in a different order.  In aggregate, against the float64 oracle:
-    ||got - ref64|| <= 1.5 ||ref32 - ref64|| + 1e-4 ||ref64||.  `exempt`
-    (bool [n], last axis) excludes Gaussians on pixels where a threshold
-    decision went the other way."""
+    ref: the float32 forward's gradient evaluated in float64 (oracle dtype
+    "exact": the same records, pair lists and per-pixel decisions as the
+    GPU's float32 forward; the chain rule differentiates the projection at
+    the parameters in float64).
+    sens: the larger of (a) how far the same float64 arithmetic lands when
+    fed with the float32 forward's own per-pixel offsets, G, alpha and
+    transmittances ("exact_fwd_values") and (b) 2^-24 times the entry's
+    condition (oracle "cond": the depth-weighted magnitude sum of its
+    per-pixel terms; float32 per-pixel arithmetic errs by a small multiple of
+    it).  Both are large only where an entry is a near-cancellation of
+    per-pixel terms.
+    g32: the float32 oracle (its count of plain-bar misses is the yardstick
+    of what a float32 evaluation achieves).  Also returns the exact
+    max_contrib and activity."""
+    ex = orc.backward(scene, cams, views, Gr, Ga, trainable=trainable, dtype="exact", cond=True)
+    fv = orc.backward(scene, cams, views, Gr, Ga, trainable=trainable, dtype="exact_fwd_values")
+    g32 = orc.backward(scene, cams, views, Gr, Ga, trainable=trainable, dtype=np.float32)
+    keys = ("mean", "scale", "quat", "opacity", "sh")
+    sens = {k: np.maximum(np.abs(ex[k] - fv[k]), U32 * ex["cond"][k]) for k in keys}
+    # activity = 2 |g_mean| + 0.1 |g_sh| + 0.1 |g_log s|: its sensitivity from
+    # the parts' (triangle inequality), plus the float32 forward values' own
+    n = ex["opacity"].shape[-1]
+    s = np.asarray(scene["scale"], np.float64)
+    sens["activity"] = np.maximum(
+        np.abs(ex["activity"] - fv["activity"]),
+        2.0 * np.linalg.norm(sens["mean"].reshape(-1, n), axis=0)
+        + 0.1 * np.linalg.norm(sens["sh"].reshape(-1, n), axis=0)
+        + 0.1 * np.linalg.norm((sens["scale"] * s).reshape(-1, n), axis=0))
+    ref = {k: ex[k] for k in keys + ("activity", "max_contrib")}
+    return ref, sens, {k: g32[k].astype(np.float64) for k in keys + ("activity",)}
+
+
+def assert_grad_close(got, ref, sens, name, exempt=None, ref32=None):
+    """Gradient parity bar, per entry against the exact reference (grad_refs):
+
+        |got - ref| <= 1e-3 * max(|ref|, 1e-3 * RMS(ref)) + SENS_K * sens.
+
+    The first term is the plain relative bar; the second admits entries that
+    float32 arithmetic cannot pin to it (near-cancellations: the float32
+    oracle misses the plain bar on about 1e-4 of the entries of the
+    200k-Gaussian step).  The entries that miss the plain bar are counted,
+    printed and limited to the float32 oracle's own count (ref32, same
+    entries) plus EXTRA_FLOOR_FRACTION of the entries (without ref32: that
+    fraction alone).  `exempt` (bool [n], last axis) excludes Gaussians on
+    pixels where a threshold decision went the other way (flip_exempt).
+    Returns the number of plain-bar misses."""
     got = np.asarray(got, np.float64)
-    ref32 = np.asarray(ref32, np.float64)
-    bound = np.asarray(bound, np.float64)
+    ref = np.asarray(ref, np.float64)
+    sens = np.asarray(sens, np.float64)
+    keep = np.arange(got.shape[-1])
     if exempt is not None:
-        got, ref32, bound = got[..., ~exempt], ref32[..., ~exempt], bound[..., ~exempt]
-        ref64 = None if ref64 is None else np.asarray(ref64)[..., ~exempt]
-    rms = float(np.sqrt(np.mean(ref32 ** 2))) if ref32.size else 0.0
-    scale = np.maximum(np.abs(ref32), 1e-3 * rms)
-    err = np.abs(got - ref32)
-    tol = np.maximum(GRAD_RTOL * scale, ROUNDING_C * float(np.finfo(np.float32).eps) * bound)
+        got, ref, sens = got[..., ~exempt], ref[..., ~exempt], sens[..., ~exempt]
+        keep = keep[~exempt]
+        ref32 = None if ref32 is None else np.asarray(ref32, np.float64)[..., ~exempt]
+    rms = float(np.sqrt(np.mean(ref ** 2))) if ref.size else 0.0
+    plain = GRAD_RTOL * np.maximum(np.abs(ref), 1e-3 * rms)
+    err = np.abs(got - ref)
+    tol = plain + SENS_K * sens
     bad = err > tol
+    misses = int((err > plain).sum())
+    misses32 = int((np.abs(np.asarray(ref32) - ref) > plain).sum()) if ref32 is not None else 0
     if bad.any():
         for w in np.argsort(-(err - tol).ravel())[:5]:
             ix = np.unravel_index(w, err.shape)
-            print(f"{name}{ix}: got {float(got[ix])!r} ref32 {float(ref32[ix])!r} tol {float(tol[ix])!r}")
+            print(f"{name}[{', '.join(str(int(v)) for v in ix[:-1] + (keep[ix[-1]],))}]: got {float(got[ix])!r} "
+                  f"ref {float(ref[ix])!r} plain {float(plain[ix])!r} sens {float(sens[ix])!r}")
+    worst = float(np.max(err / np.maximum(plain, 1e-300))) if err.size else 0.0
+    print(f"{name}: {err.size} entries, worst err / plain bar {worst:.3f}, {misses} beyond the plain bar "
+          f"(float32 oracle: {misses32 if ref32 is not None else '-'})", flush=True)
     assert not bad.any(), (f"{name}: {int(bad.sum())}/{bad.size} outside the bar; worst err/tol "
                            f"{float(np.max(err / tol))}")
-    if ref64 is not None:
-        ref64 = np.asarray(ref64, np.float64)
-        d_got = float(np.linalg.norm(got - ref64))
-        d_32 = float(np.linalg.norm(ref32 - ref64))
-        nrm = float(np.linalg.norm(ref64))
-        assert d_got <= 1.5 * d_32 + 1e-4 * nrm, (f"{name}: aggregate error {d_got / max(nrm, 1e-300)} vs the "
-                                                  f"float32 oracle's {d_32 / max(nrm, 1e-300)}")
+    cap = misses32 + EXTRA_FLOOR_FRACTION * err.size
+    assert misses <= cap, f"{name}: {misses} of {err.size} entries beyond the plain bar (cap {cap:.1f})"
+    return misses
 
 
-def activity_bound(bound, scale):
-    """Rounding-error scale of the activity 2|g_mean| + 0.1|g_sh| + 0.1|g_log_scale|."""
-    n = bound["opacity"].shape[-1]
-    return (2.0 * np.linalg.norm(bound["mean"].reshape(-1, n), axis=0)
-            + 0.1 * np.linalg.norm(bound["sh"].reshape(-1, n), axis=0)
-            + 0.1 * np.linalg.norm((bound["scale"] * scale).reshape(-1, n), axis=0))
+def checked_exempt(orc, scene, cams, views, rgb, alpha, last, final_T, label="", cap=0.01):
+    """Forward parity first (images and last index on the unflagged pixels,
+    see assert_images), then the flip exemption, capped at max(2, cap * n)
+    Gaussians."""
+    ref_fwd = orc.render(scene, cams, views, pairs=True)
+    assert_images(rgb, alpha, ref_fwd, label, last=np.asarray(last).reshape(ref_fwd["last"].shape))
+    n = scene["mean"].shape[1]
+    ex = flip_exempt(ref_fwd, n, last, final_T)
+    print(f"{label} exempt Gaussians: {int(ex.sum())} of {n}", flush=True)
+    assert ex.sum() <= max(2, cap * n), f"{label} {int(ex.sum())} exempt Gaussians"
+    return ex
 
 
 def flip_exempt(ref_fwd, n, last_gpu=None, T_gpu=None):
