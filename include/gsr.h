@@ -232,6 +232,27 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
                                  uint32_t* n_pairs_host, const gsr_debug* debug, gsr_timer* timer,
                                  void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * forward of gsr_rasterize_forward (same arguments and results, no debug
+ * copies, no timer) without a workspace argument.  Its scratch is a device
+ * array of GSR_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held
+ * until the process ends; its address is looked up on the first call on a
+ * device (the device current at the call, which must own `stream`).  The
+ * call allocates nothing.  Returns GSR_ENOSPACE, before any launch, when
+ * the forward's scratch for these sizes (records n * n_views, the state's
+ * pair capacity, the tiles of the views) exceeds that size: about 28 MB
+ * for 200k Gaussians at 800 x 800 with 1M pair slots.  Every call on a GPU
+ * shares its array, so calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller; each call clears
+ * what it needs zeroed itself (with a kernel, no memset node).  The state
+ * it fills is the same as gsr_rasterize_forward's: gsr_rasterize_backward
+ * takes it with its own workspace. */
+#define GSR_NOALLOC_SCRATCH_BYTES (64u << 20)
+gsr_status gsr_rasterize_forward_noalloc(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                                         const gsr_view_state* views, gsr_fwd_state* state, float* rgb,
+                                         float* alpha, uint32_t* n_pairs_host, void* stream);
+
 /* After a non-synchronising forward has completed (caller synchronised):
  * reads state->counters and returns GSR_OK, GSR_ENOSPACE (pair capacity
  * exceeded; *n_pairs_host receives the count needed) or GSR_EDEVICE. */

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/gsr.h"
@@ -350,10 +351,17 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
   return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, X, 0, true);
 }
 
-gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
-                                 const gsr_view_state* views, gsr_fwd_state* state, void* ws, size_t ws_bytes,
-                                 float* rgb, float* alpha, uint32_t* n_pairs_host, const gsr_debug* debug,
-                                 gsr_timer* timer, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The forward of gsr_rasterize_forward on a given scratch workspace; the
+// layout is the forward's and the backward's (backward_layout, what
+// gsr_workspace_size measures) or the forward's alone.
+gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                        const gsr_view_state* views, gsr_fwd_state* state, void* ws, size_t ws_bytes, float* rgb,
+                        float* alpha, uint32_t* n_pairs_host, const gsr_debug* debug, gsr_timer* timer,
+                        void* stream, bool backward_layout) {
   if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !rgb || !alpha) return GSR_EINVAL;
   if (!state_ok(state)) return GSR_EINVAL;
   const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -367,7 +375,7 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
   const size_t plane = (size_t)W * H;
   Carver c(ws);
   PipeBufs b;
-  if (carve(c, b, n_views, R, P, 0, false, X, 0, true) > ws_bytes)
+  if (carve(c, b, n_views, R, P, 0, false, X, 0, backward_layout) > ws_bytes)
     return GSR_ENOSPACE;
 
   std::vector<ViewD> hv(n_views);
@@ -452,6 +460,71 @@ gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const 
     HIP_TRY(hipStreamSynchronize(s));
   }
   return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                                 const gsr_view_state* views, gsr_fwd_state* state, void* ws, size_t ws_bytes,
+                                 float* rgb, float* alpha, uint32_t* n_pairs_host, const gsr_debug* debug,
+                                 gsr_timer* timer, void* stream) {
+  return forward_impl(model, n_views, cams, views, state, ws, ws_bytes, rgb, alpha, n_pairs_host, debug, timer,
+                      stream, true);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- no allocation
+// The scratch of gsr_rasterize_forward_noalloc: a file-scope device array
+// (one copy per GPU, held until the process ends).  Host code never uses the
+// array's name as an address (on the host it is a stand-in symbol): each
+// device's address comes from hipGetSymbolAddress, taken once per device
+// with that device current and kept here.
+namespace {
+
+constexpr size_t kNoallocScratchBytes = (size_t)GSR_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+gsr_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GSR_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return GSR_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GSR_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_rasterize_forward_noalloc(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
+                                         const gsr_view_state* views, gsr_fwd_state* state, float* rgb,
+                                         float* alpha, uint32_t* n_pairs_host, void* stream) {
+  if (!single_view_args_ok(model, n_views, cams, views) || !state || !rgb || !alpha || !state_ok(state))
+    return GSR_EINVAL;
+  const uint64_t X = (uint64_t)tiles_of(cams[0]) * (uint64_t)n_views;
+  Carver c(nullptr);
+  PipeBufs b;
+  const size_t need = carve(c, b, (size_t)n_views, (size_t)model->n * (size_t)n_views, state->pair_capacity, 0,
+                            false, X, 0, false);
+  if (need > kNoallocScratchBytes) return GSR_ENOSPACE;
+  void* ws = nullptr;
+  const gsr_status st = scratch_of_current_device(&ws);
+  if (st != GSR_OK) return st;
+  return forward_impl(model, n_views, cams, views, state, ws, kNoallocScratchBytes, rgb, alpha, n_pairs_host,
+                      nullptr, nullptr, stream, false);
 }
 
 gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host, void* stream) {

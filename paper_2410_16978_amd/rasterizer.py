@@ -104,6 +104,10 @@ def lib():
     L.gsr_rasterize_forward.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Camera), C.POINTER(ViewState),
                                         C.POINTER(FwdState), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_uint32), C.POINTER(Debug), C.c_void_p, C.c_void_p]
+    L.gsr_rasterize_forward_noalloc.restype = C.c_int
+    L.gsr_rasterize_forward_noalloc.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Camera), C.POINTER(ViewState),
+                                                C.POINTER(FwdState), C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32),
+                                                C.c_void_p]
     L.gsr_forward_check.restype = C.c_int
     L.gsr_forward_check.argtypes = [C.POINTER(FwdState), C.POINTER(C.c_uint32), C.c_void_p]
     L.gsr_rasterize_backward.restype = C.c_int
@@ -389,6 +393,33 @@ def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, 
             return rgb, alpha, st, dbg
         return rgb, alpha, st
     raise GsrError(GSR_ENOSPACE, "gsr_rasterize_forward (capacity)")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # GSR_NOALLOC_SCRATCH_BYTES
+
+
+def rasterize_forward_noalloc(model, cams, views, state, out, n_pairs=False, stream=None):
+    """gsr_rasterize_forward_noalloc: the forward on the library's own scratch
+    (no workspace, no device allocation in the call).  `state` (a
+    ForwardState, make_state) and `out` = (rgb [V,3,H,W], alpha [V,H,W]) are
+    the caller's; nothing is allocated or regrown here.  n_pairs=True
+    synchronises once and returns the pair count (the call returns ENOSPACE,
+    raised as GsrError, when it exceeds the state's capacity).  Returns
+    (rgb, alpha, state)."""
+    V = len(cams)
+    if V == 0 or len(views) != V:
+        raise ValueError("need one view state per camera")
+    m = model_struct(model)
+    carr = (Camera * V)(*[camera_struct(c) for c in cams])
+    varr = (ViewState * V)(*[view_struct(v) for v in views])
+    rgb, alpha = out
+    fs = state.struct()
+    npairs = C.c_uint32(0)
+    rc = lib().gsr_rasterize_forward_noalloc(C.byref(m), V, carr, varr, C.byref(fs), _ptr(rgb), _ptr(alpha),
+                                             C.byref(npairs) if n_pairs else None, _stream(stream))
+    _check(rc, "gsr_rasterize_forward_noalloc")
+    state.n_pairs = int(npairs.value) if n_pairs else None
+    return rgb, alpha, state
 
 
 def forward_check(state, stream=None):

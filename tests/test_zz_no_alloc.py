@@ -1,0 +1,98 @@
+"""gsr_rasterize_forward_noalloc (the forward on the library's own device
+scratch, for callers that cannot allocate) against gsr_rasterize_forward
+through the C ABI: two calls in a row, the second on a smaller input, each
+bit-identical to the workspace entry point (same kernels in the same order);
+a size beyond the scratch is refused before any launch; the state it fills
+drives the backward exactly like the other forward's."""
+import numpy as np
+import pytest
+
+from paper_2410_16978_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _scene(n_per_layer, W, H, seed):
+    sc = scenes.shell_scene(n_per_layer, 4, 3, seed=seed, log_scale_mu=-4.5, log_scale_sigma=0.6, palette=True)
+    cams = scenes.stereo_cameras([0.3, 0.2, -1.0], W, H)
+    vs = scenes.view_state(0b1011, clips=[([0.2, 0.1, 1.0], 0.1, 0b10)], bg=(0.1, 0.2, 0.3))
+    return sc, cams, [vs, vs]
+
+
+def _both(sc, cams, vss):
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    model = rz.to_device(sc)
+    rgb_w, alpha_w, st_w = rz.rasterize_forward(model, cams, vss)  # sizes the pair buffers (one sync)
+    V, W, H, n = len(cams), cams[0]["width"], cams[0]["height"], sc["mean"].shape[1]
+    st_n = rz.make_state(n, V, W, H, st_w.capacity)
+    out = (torch.full((V, 3, H, W), float("nan"), device="cuda"), torch.full((V, H, W), float("nan"), device="cuda"))
+    rgb_n, alpha_n, st_n = rz.rasterize_forward_noalloc(model, cams, vss, st_n, out, n_pairs=True)
+    torch.cuda.synchronize()
+    assert rz.forward_check(st_n) == st_w.n_pairs == st_n.n_pairs
+    return model, (rgb_w, alpha_w, st_w), (rgb_n, alpha_n, st_n)
+
+
+def _assert_same(a, b, K):
+    rgb_w, alpha_w, st_w = a
+    rgb_n, alpha_n, st_n = b
+    np.testing.assert_array_equal(rgb_n.cpu().numpy(), rgb_w.cpu().numpy())
+    np.testing.assert_array_equal(alpha_n.cpu().numpy(), alpha_w.cpu().numpy())
+    np.testing.assert_array_equal(st_n.last.cpu().numpy(), st_w.last.cpu().numpy())
+    np.testing.assert_array_equal(st_n.pixel_state.cpu().numpy(), st_w.pixel_state.cpu().numpy())
+    np.testing.assert_array_equal(st_n.ranges.cpu().numpy(), st_w.ranges.cpu().numpy())
+    sel_w, sel_n = int(st_w.sort_sel.item()), int(st_n.sort_sel.item())
+    vw = st_w.pair_vals.cpu().numpy()[sel_w * st_w.capacity: sel_w * st_w.capacity + K]
+    vn = st_n.pair_vals.cpu().numpy()[sel_n * st_n.capacity: sel_n * st_n.capacity + K]
+    np.testing.assert_array_equal(vn, vw)
+    np.testing.assert_array_equal(st_n.pair_emit.cpu().numpy()[:K], st_w.pair_emit.cpu().numpy()[:K])
+
+
+def test_noalloc_forward_equals_workspace_forward_twice(orc):
+    """A stereo pair of 200k-Gaussian views at 640 x 480, then a smaller
+    input (16k Gaussians at 96 x 72) on the same scratch: both equal the
+    workspace entry point bit for bit; the first also against the oracle."""
+    from tests.gpu_helpers import assert_images
+    sc, cams, vss = _scene(50_000, 640, 480, seed=3)
+    _, a, b = _both(sc, cams, vss)
+    _assert_same(a, b, a[2].n_pairs)
+    ref = orc.render(sc, cams, vss)
+    st = assert_images(b[0], b[1], ref, "noalloc 200k", last=b[2].last.cpu().numpy().reshape(ref["last"].shape))
+    print("noalloc 200k stereo:", st, flush=True)
+    sc2, cams2, vss2 = _scene(4_000, 96, 72, seed=4)
+    _, a2, b2 = _both(sc2, cams2, vss2)
+    _assert_same(a2, b2, a2[2].n_pairs)
+
+
+def test_noalloc_state_drives_the_backward():
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    sc, cams, vss = _scene(2_000, 80, 64, seed=5)
+    model, a, b = _both(sc, cams, vss)
+    rng = np.random.default_rng(5)
+    Gr = torch.tensor(rng.standard_normal((2, 3, 64, 80)).astype(np.float32), device="cuda")
+    Ga = torch.tensor(rng.standard_normal((2, 64, 80)).astype(np.float32), device="cuda")
+    gw = rz.rasterize_backward(model, cams, vss, a[2], Gr, Ga)
+    gn = rz.rasterize_backward(model, cams, vss, b[2], Gr, Ga)
+    torch.cuda.synchronize()
+    for k in gw:
+        np.testing.assert_array_equal(gn[k].cpu().numpy(), gw[k].cpu().numpy())
+
+
+def test_noalloc_refuses_sizes_beyond_its_scratch():
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    sc, cams, vss = _scene(500, 64, 48, seed=6)
+    model = rz.to_device(sc)
+    st = rz.make_state(sc["mean"].shape[1], 2, 64, 48, 8_000_000)  # 8M pair slots: 128 MB of keys alone
+    out = (torch.empty((2, 3, 48, 64), device="cuda"), torch.empty((2, 48, 64), device="cuda"))
+    with pytest.raises(rz.GsrError) as e:
+        rz.rasterize_forward_noalloc(model, cams, vss, st, out)
+    assert e.value.status == rz.GSR_ENOSPACE
