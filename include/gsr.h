@@ -144,7 +144,12 @@ typedef struct {
  *                             tile t's batches have the indices
  *                             floor(ranges[t][0] / 256) + t + c
  *   counters    uint32[4]     device: pairs K, overflow flag, error flag,
- *                             reserved */
+ *                             reserved.  Zeroed by the caller when the state
+ *                             is created.  The overflow and error words are
+ *                             sticky: any call on the state may set them and
+ *                             only gsr_forward_check clears them (after
+ *                             reporting them), so one check after a loop of
+ *                             non-synchronising calls sees every call. */
 typedef struct {
   float* records;
   uint32_t* offsets;
@@ -219,10 +224,12 @@ gsr_status gsr_activate(const gsr_model* model, float* scale_out, float* opacity
  * The state is filled for gsr_rasterize_backward.
  * n_pairs_host: if non-NULL, the call synchronises the stream after the
  * tile-count scan, stores the exact pair count K there and returns
- * GSR_ENOSPACE without rendering when K > state->pair_capacity.  If NULL the
- * call never synchronises; on overflow the pairs beyond the capacity are
- * dropped, state->counters[1] is set and the image is incomplete - check
- * with gsr_forward_check after synchronising.
+ * GSR_ENOSPACE without rendering when K > state->pair_capacity, or
+ * GSR_EDEVICE without rendering when the state's error word is set (by this
+ * call's scan or an earlier unchecked call; gsr_forward_check clears it).
+ * If NULL the call never synchronises; on overflow the pairs beyond the
+ * capacity are dropped, state->counters[1] is set and the image is
+ * incomplete - check with gsr_forward_check after synchronising.
  * ws: scratch of at least gsr_workspace_size(...) bytes, 256-byte aligned.
  * timer: optional (NULL), see gsr_timer.  GSR_EINVAL when the total tile
  * count X is 2^24 - 1 or more (the batch map holds tiles in 24 bits). */
@@ -253,9 +260,12 @@ gsr_status gsr_rasterize_forward_noalloc(const gsr_model* model, int32_t n_views
                                          const gsr_view_state* views, gsr_fwd_state* state, float* rgb,
                                          float* alpha, uint32_t* n_pairs_host, void* stream);
 
-/* After a non-synchronising forward has completed (caller synchronised):
- * reads state->counters and returns GSR_OK, GSR_ENOSPACE (pair capacity
- * exceeded; *n_pairs_host receives the count needed) or GSR_EDEVICE. */
+/* After non-synchronising forwards have completed (caller synchronised):
+ * reads state->counters and returns GSR_OK, GSR_ENOSPACE (the pair capacity
+ * was exceeded by some call since the last check; *n_pairs_host receives
+ * the last call's count) or GSR_EDEVICE (a kernel reported an internal
+ * error: a bounded wait gave up, or offsets and keys were inconsistent),
+ * then clears the overflow and error words.  Synchronises the stream. */
 gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host, void* stream);
 
 /* Gradients of a loss L given dL/d(rgb) float[V][3][H][W] and dL/d(alpha)
@@ -309,8 +319,9 @@ size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const
  * synchronises.  req_status int32[n_req] (device) receives GSR_OK, or
  * GSR_ENOSPACE for requests whose pairs did not fit into pair_capacity
  * (their images are not written; pairs are assigned in request order, so
- * the failing requests are a suffix).  Each request's image is identical to
- * rendering it alone. */
+ * the failing requests are a suffix), or GSR_EDEVICE for every request when
+ * a kernel of the call reported an internal error.  Each request's image is
+ * identical to rendering it alone. */
 gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs,
                             int32_t n_req, uint32_t pair_capacity, void* ws, size_t ws_bytes,
                             int32_t* req_status, gsr_timer* timer, void* stream);

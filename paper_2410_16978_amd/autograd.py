@@ -41,11 +41,17 @@ class _RasterizeFn(torch.autograd.Function):
         rctx.state = st
         ctx.model = model
         ctx.cams, ctx.views, ctx.rctx, ctx.state = cams, views, rctx, st
+        ctx.generation = st.generation
         return rgb, alpha
 
     @staticmethod
     def backward(ctx, g_rgb, g_alpha):
         rctx = ctx.rctx
+        if ctx.state.generation != ctx.generation:
+            # the context's buffers (records, sorted pairs, checkpoints) now
+            # hold a later forward's: this graph's backward would be wrong
+            raise RuntimeError("render state overwritten by a later forward on the same RenderContext before "
+                               "this backward; use one RenderContext per forward awaiting its backward")
         mc = act = None
         if rctx.track_activity:
             n = ctx.model["mean"].shape[1]

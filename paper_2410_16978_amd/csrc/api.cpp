@@ -104,9 +104,12 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
 }
 
 // One launch zeroes everything a call expects to start at zero: the sort
-// control block (digit counts, tickets), the pair counters, the tile ranges,
-// the scan's and the radix passes' look-back words, the sorted-buffer
-// selector and (forward) the batch-to-tile map.
+// control block (digit counts, tickets), the pair count (all four counter
+// words for a batch, whose counters live in the workspace; a forward
+// state's overflow and error words are sticky, cleared by
+// gsr_forward_check), the tile ranges, the scan's and the radix passes'
+// look-back words, the sorted-buffer selector and (forward) the
+// batch-to-tile map.
 // The global radix passes cover only the tile bits of the keys (bits 32
 // up); the depth bits are sorted per tile segment.
 constexpr int kDepthPasses = 4;
@@ -131,14 +134,14 @@ hipError_t upload_views(ViewD* dst, const ViewD* src, int n_views, WordUpload& u
   return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
 }
 
-hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, uint32_t* ranges, size_t X, size_t R,
-                           uint32_t P, uint32_t* sel, hipStream_t s, const WordUpload* up,
+hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, bool sticky_flags, uint32_t* ranges, size_t X,
+                           size_t R, uint32_t P, uint32_t* sel, hipStream_t s, const WordUpload* up,
                            uint32_t* batch_tile = nullptr, size_t n_batches = 0) {
   ClearSet cs{};
   cs.p[0] = reinterpret_cast<uint32_t*>(b.ctl);
   cs.n[0] = sizeof(SortCtl) / 4;
   cs.p[1] = counters;
-  cs.n[1] = 4;
+  cs.n[1] = sticky_flags ? 1 : 4;
   cs.p[2] = ranges;
   cs.n[2] = 2 * X;
   cs.p[3] = reinterpret_cast<uint32_t*>(b.scan_status);
@@ -393,7 +396,7 @@ gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camer
   }
   WordUpload up;
   HIP_TRY(upload_views(b.views, hv.data(), n_views, up, s));
-  HIP_TRY(clear_workspace(b, state->counters, state->ranges, X, R, P, state->sort_sel, s, &up,
+  HIP_TRY(clear_workspace(b, state->counters, true, state->ranges, X, R, P, state->sort_sel, s, &up,
                           state->batch_map + X + 1, state->batch_capacity));
   const ModelD md = make_model(*model);
   {
@@ -406,11 +409,17 @@ gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camer
     HIP_TRY(launch_scan(b.n_tiles, state->offsets, b.scan_status, &b.ctl->scan_ticket, R, state->counters, P, s));
   }
   if (n_pairs_host) {
-    uint32_t K = 0;
-    HIP_TRY(hipMemcpyAsync(&K, state->counters + kCntPairs, 4, hipMemcpyDeviceToHost, s));
+    // the pair count, and the sticky error word (this call's scan, or an
+    // earlier call on this state that nobody checked)
+    uint32_t cnt[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(cnt, state->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    *n_pairs_host = K;
-    if (K > P) return GSR_ENOSPACE;
+    *n_pairs_host = cnt[kCntPairs];
+    if (cnt[kCntError]) return GSR_EDEVICE;
+    if (cnt[kCntPairs] > P) {
+      HIP_TRY(launch_clear_u32(state->counters + kCntOverflow, 1, s));  // this call's overflow is reported now
+      return GSR_ENOSPACE;
+    }
   }
   {
     StageScope sc(timer, GSR_STAGE_DUPLICATE, s);
@@ -533,6 +542,8 @@ gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host,
   const hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipMemcpyAsync(cnt, state->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  // the overflow and error words are reported once: cleared for the calls to come
+  HIP_TRY(launch_clear_u32(state->counters + kCntOverflow, 2, s));
   if (n_pairs_host) *n_pairs_host = cnt[kCntPairs];
   if (cnt[kCntError]) return GSR_EDEVICE;
   if (cnt[kCntOverflow]) return GSR_ENOSPACE;
@@ -681,7 +692,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   WordUpload up;
   HIP_TRY(upload_views(b.views, bp.views.data(), n_views, up, s));
   HIP_TRY(hipMemcpyAsync(b.req_rec, bp.req_rec.data(), 4 * (n_req + 1), hipMemcpyHostToDevice, s));
-  HIP_TRY(clear_workspace(b, b.counters, b.ranges, bp.X, R, P, b.sel, s, &up));
+  HIP_TRY(clear_workspace(b, b.counters, false, b.ranges, bp.X, R, P, b.sel, s, &up));
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
     for (int m = 0; m < n_models; ++m) {
@@ -732,6 +743,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
     HIP_TRY(launch_blend_fwd_tile(b.views, n_views, (uint32_t)bp.X, b.records, R, b.vals, b.sel, P, b.ranges,
                                   nullptr, 0, req_status, nullptr, b.ctl->tile_class, b.class_list, s));
   }
+  HIP_TRY(launch_batch_error(b.counters, n_req, req_status, s));
   return GSR_OK;
 }
 

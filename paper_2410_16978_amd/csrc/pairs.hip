@@ -113,7 +113,7 @@ k_scan(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out, 
       if (bid == nb - 1) {
         const uint64_t K = excl + total;
         counters[kCntPairs] = K > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)K;
-        counters[kCntOverflow] = K > pair_capacity ? 1u : 0u;
+        if (K > pair_capacity) atomicOr(&counters[kCntOverflow], 1u);  // sticky until the caller checks
       }
     }
   }
@@ -326,6 +326,20 @@ __global__ void k_batch_status(const uint32_t* __restrict__ req_rec, int n_req,
   }
   counters[kCntPairs] = k_fit;
   counters[kCntOverflow] = 0;
+}
+
+// After a batch: a device-side error anywhere in the call (the sort's or the
+// scan's bounded waits, inconsistent offsets) marks every request
+// GSR_EDEVICE (-4), so no image of a faulty sort is reported as good.
+__global__ void k_batch_error(const uint32_t* __restrict__ counters, int n_req, int32_t* __restrict__ req_status) {
+  if (counters[kCntError] == 0u) return;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_req; q += gridDim.x * blockDim.x) req_status[q] = -4;
+}
+
+hipError_t launch_batch_error(const uint32_t* counters, int n_req, int32_t* req_status, hipStream_t s) {
+  if (n_req <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_error, dim3(1), dim3(256), 0, s, counters, n_req, req_status);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_status(const uint32_t* req_rec, int n_req, const uint32_t* offsets,

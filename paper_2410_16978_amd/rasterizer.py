@@ -288,6 +288,7 @@ class ForwardState:
     height: int
     n: int
     n_pairs: int = None
+    generation: int = 0  # forwards run on this state (a backward checks its forward is the latest)
 
     @property
     def final_T(self):
@@ -389,6 +390,7 @@ def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, 
             continue
         _check(rc, "gsr_rasterize_forward")
         st.n_pairs = int(npairs.value) if sync else None
+        st.generation += 1
         if debug:
             return rgb, alpha, st, dbg
         return rgb, alpha, st
@@ -419,6 +421,7 @@ def rasterize_forward_noalloc(model, cams, views, state, out, n_pairs=False, str
                                              C.byref(npairs) if n_pairs else None, _stream(stream))
     _check(rc, "gsr_rasterize_forward_noalloc")
     state.n_pairs = int(npairs.value) if n_pairs else None
+    state.generation += 1
     return rgb, alpha, state
 
 

@@ -164,3 +164,22 @@ def test_autograd_function_chain_rule(orc):
     assert_grad_close(params["opacity_logit"].grad.cpu().numpy(), ref["opacity"] * o * (1 - o),
                       sens["opacity"] * o * (1 - o), "logit", ex, g32["opacity"] * o * (1 - o))
     assert_grad_close(params["sh"].grad.cpu().numpy(), ref["sh"], sens["sh"], "sh", ex, g32["sh"])
+
+
+def test_backward_of_an_overwritten_forward_raises():
+    """Two forwards on one RenderContext share its buffers: the first graph's
+    backward must refuse (its records and checkpoints are the second's)."""
+    import torch
+    from paper_2410_16978_amd import autograd as ag
+    sc, cams, vss, Gr, Ga = _case(seed=15, D=1)
+    params = {k: torch.tensor(sc[k], device="cuda", requires_grad=True)
+              for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")}
+    layer = torch.tensor(sc["layer"], device="cuda")
+    rctx = ag.RenderContext()
+    rgb1, _ = ag.render_params(params, layer, 1, cams, vss, rctx)
+    rgb2, _ = ag.render_params(params, layer, 1, cams, vss, rctx)
+    with pytest.raises(RuntimeError, match="overwritten"):
+        rgb1.sum().backward()
+    rgb2.sum().backward()  # the latest forward's backward is fine
+    torch.cuda.synchronize()
+    assert torch.isfinite(params["mean"].grad).all()

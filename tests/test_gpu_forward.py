@@ -171,6 +171,37 @@ def test_capacity_regrow_and_overflow_flag(orc):
     assert e.value.status == rz.GSR_ENOSPACE
 
 
+def test_overflow_and_error_words_are_sticky_until_checked():
+    """An overflow in one non-synchronising call is still reported after a
+    later call that fits (the flags are not reset per call); the check clears
+    them.  An error word set on the state (here from the host, standing in
+    for a kernel's bounded wait giving up) makes the next synchronising
+    forward fail with GSR_EDEVICE, and the check reports and clears it."""
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    w = scenes.plain_forward_4k()
+    model = rz.to_device(w.scene)
+    small = rz.make_state(4096, 1, 128, 128, 100, "cuda")
+    rz.rasterize_forward(model, w.cams, w.views, state=small, sync=False)  # overflows
+    empty = [scenes.view_state(0)]  # every layer hidden: no pairs
+    rz.rasterize_forward(model, w.cams, empty, state=small, sync=False)
+    torch.cuda.synchronize()
+    with pytest.raises(rz.GsrError) as e:
+        rz.forward_check(small)
+    assert e.value.status == rz.GSR_ENOSPACE
+    assert rz.forward_check(small) == 0  # reported once
+    st = rz.make_state(4096, 1, 128, 128, 100_000, "cuda")
+    st.counters[2] = 16
+    with pytest.raises(rz.GsrError) as e:
+        rz.rasterize_forward(model, w.cams, w.views, state=st)
+    assert e.value.status == rz.GSR_EDEVICE
+    with pytest.raises(rz.GsrError) as e:
+        rz.forward_check(st)
+    assert e.value.status == rz.GSR_EDEVICE
+    rgb, alpha, st = rz.rasterize_forward(model, w.cams, w.views, state=st)
+    assert rz.forward_check(st) == st.n_pairs > 0
+
+
 def test_invalid_arguments_rejected():
     from paper_2410_16978_amd import rasterizer as rz
     w = scenes.plain_forward_4k()
