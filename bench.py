@@ -130,20 +130,44 @@ def bench_stereo(rz, scenes, torch, frames, warmup):
     _, _, st1 = rz.rasterize_forward(model, cams[:1], [full])
     _, _, st1b = rz.rasterize_forward(model, cams[1:], [full])
     n = int(model["layer"].shape[0])
-    st2 = rz.make_state(n, 2, W, H, int(st2.n_pairs * 1.02) + 4096)
+    cap2 = int(st2.n_pairs * 1.02) + 4096
+    st2 = rz.make_state(n, 2, W, H, cap2)
+    st2s = rz.make_state(n, 2, W, H, cap2, shared=True)
     st1 = rz.make_state(n, 1, W, H, int(max(st1.n_pairs, st1b.n_pairs) * 1.02) + 4096)
     out2 = (torch.empty((2, 3, H, W), device="cuda"), torch.empty((2, H, W), device="cuda"))
+    out2s = (torch.empty((2, 3, H, W), device="cuda"), torch.empty((2, H, W), device="cuda"))
     outs = [(torch.empty((1, 3, H, W), device="cuda"), torch.empty((1, H, W), device="cuda")) for _ in range(2)]
+    centre = scenes.centre_camera(cams[0], cams[1])
 
     def batched(vs):
         rz.rasterize_forward(model, cams, [vs, vs], state=st2, sync=False, out=out2)
+
+    def shared(vs):
+        vs_s = scenes.with_sort_cam(vs, centre)
+        rz.rasterize_forward(model, cams, [vs_s, vs_s], state=st2s, sync=False, out=out2s)
 
     def plain(vs):
         for e in range(2):
             rz.rasterize_forward(model, cams[e:e + 1], [vs], state=st1, sync=False, out=outs[e])
 
+    # one frame both ways: the shared order's image error against per-eye sorting
+    batched(vstates[0])
+    shared(vstates[0])
+    torch.cuda.synchronize()
+    diff = float((out2s[0] - out2[0]).abs().max().item())
+    stages = {}
+    for name, fn in (("batched", batched), ("shared_order", shared)):
+        tm = rz.Timer()
+        st = st2 if name == "batched" else st2s
+        for i in range(3):
+            rz.rasterize_forward(model, cams, [vstates[i]] * 2 if name == "batched" else
+                                 [scenes.with_sort_cam(vstates[i], centre)] * 2, state=st, sync=False,
+                                 out=out2 if name == "batched" else out2s, timer=tm)
+        stages[name] = {k: round(v[0] / 3, 4) for k, v in tm.read().items() if v[1]}
+        tm.close()
+
     res = {}
-    for name, fn in (("batched", batched), ("plain", plain)):
+    for name, fn in (("batched", batched), ("shared_order", shared), ("plain", plain)):
         for i in range(warmup):
             fn(vstates[i])
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
@@ -158,9 +182,13 @@ def bench_stereo(rz, scenes, torch, frames, warmup):
         res[name] = {"mpix_s": round(2 * W * H / (mean * 1e-3) / 1e6, 1), "ms_per_frame": round(mean, 4),
                      "p50_ms": round(percentile(ms, 50), 4), "p99_ms": round(percentile(ms, 99), 4)}
     rz.forward_check(st2)
+    rz.forward_check(st2s)
     rz.forward_check(st1)
     return {"workload": wl.name, "frames": frames, "pairs": st2.capacity, **res,
-            "speedup_vs_plain": round(res["plain"]["ms_per_frame"] / res["batched"]["ms_per_frame"], 3)}
+            "speedup_vs_plain": round(res["plain"]["ms_per_frame"] / res["batched"]["ms_per_frame"], 3),
+            "shared_order_speedup_vs_plain": round(res["plain"]["ms_per_frame"] / res["shared_order"]["ms_per_frame"],
+                                                   3),
+            "shared_order_image_max_abs_vs_per_eye": diff, "stage_ms_per_frame": stages}
 
 
 def bench_serving(rz, scenes, torch, seconds, rate):

@@ -93,6 +93,20 @@ typedef struct {
   int32_t n_clip;                      /* 0 .. GSR_MAX_CLIP */
   gsr_clip_plane clip[GSR_MAX_CLIP];
   float bg[3];                         /* background colour composited behind the splats */
+  /* Depth order of the pairs within each tile.  0: each view's own
+   * camera-space depth (exact per view).  1: one order for all views of the
+   * call (gsr_rasterize_forward: decided by views[0]; gsr_render_batch: by
+   * the request's vs): the Gaussians are sorted once by their depth in
+   * sort_cam (only its R and t are read; for stereo, the camera at the eye
+   * centre), each view's pairs are emitted in that order and only grouped
+   * by tile (Sec. 3.3: one sort shared by both eyes instead of one per
+   * eye).  With parallel eyes and sort_cam their centre the depths agree
+   * with each eye's own and the images are those of per-eye sorting; with
+   * converging eyes pairs of nearly equal depth may be blended in the
+   * other order.  The depth key is the bit pattern of the float depth as an
+   * unsigned integer (ties: ascending Gaussian index). */
+  int32_t sort_shared;
+  gsr_camera sort_cam;
 } gsr_view_state;
 
 /* Gaussian arrays (device, structure of arrays, see above; host struct). */
@@ -206,9 +220,11 @@ gsr_status gsr_timer_read(gsr_timer* t, float* ms /* [GSR_N_STAGES] */, uint32_t
 
 /* Bytes of scratch workspace a forward or backward of n_views views of a
  * model with n Gaussians at width x height needs, for a pair capacity of
- * pair_capacity.  Returns 0 on bad arguments. */
+ * pair_capacity; shared_order != 0 adds the buffers of a forward with a
+ * shared depth order (gsr_view_state.sort_shared: about 24 B per Gaussian
+ * and 24 B per record more).  Returns 0 on bad arguments. */
 size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t height,
-                          uint32_t pair_capacity);
+                          uint32_t pair_capacity, int32_t shared_order);
 
 /* The activated scale float[3][n] and opacity float[n] of a model exactly as
  * the kernels compute them: for model->raw = 1, exp of the log-scales and
@@ -232,7 +248,10 @@ gsr_status gsr_activate(const gsr_model* model, float* scale_out, float* opacity
  * incomplete - check with gsr_forward_check after synchronising.
  * ws: scratch of at least gsr_workspace_size(...) bytes, 256-byte aligned.
  * timer: optional (NULL), see gsr_timer.  GSR_EINVAL when the total tile
- * count X is 2^24 - 1 or more (the batch map holds tiles in 24 bits). */
+ * count X is 2^24 - 1 or more (the batch map holds tiles in 24 bits).
+ * With views[0].sort_shared the views share one depth order (see
+ * gsr_view_state); the workspace must then be sized with shared_order set,
+ * and the state can not be used for a backward. */
 gsr_status gsr_rasterize_forward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,
                                  const gsr_view_state* views, gsr_fwd_state* state,
                                  void* ws, size_t ws_bytes, float* rgb, float* alpha,
@@ -283,7 +302,9 @@ gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host,
  *   2 |dL/dmean| + 0.1 |dL/dsh| + 0.1 |dL/dlog scale| (Sec. 3.2.2).
  * ws: scratch of at least gsr_workspace_size(...) bytes.
  * The backward uses no atomics: per-pair partial gradients are summed in a
- * fixed order, so repeated calls give bitwise identical results. */
+ * fixed order, so repeated calls give bitwise identical results.
+ * GSR_EINVAL for views with a shared depth order (a rendering
+ * approximation; training differentiates each view's own order). */
 typedef struct {
   float *g_mean, *g_scale, *g_quat, *g_opacity, *g_sh;
 } gsr_grads;

@@ -63,7 +63,7 @@ def lib():
         for name, mtype, rtype in (("oracle_render_f32", Model32, C.c_float), ("oracle_render_f64", Model64, C.c_double)):
             f = getattr(_lib, name)
             f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), C.c_int, C.c_int,
-                          C.POINTER(Outputs), C.c_int]
+                          C.POINTER(Outputs), C.c_int, C.POINTER(Camera)]
             f.restype = C.c_int
         for name, mtype, in_t, out_t in (("oracle_backward_f32", Model32, C.c_float, C.c_float),
                                          ("oracle_backward_f64", Model64, C.c_double, C.c_double),
@@ -125,8 +125,12 @@ class _ModelArrays:
                         _ptr(self.layer, C.c_uint8))
 
 
-def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pairs=False, n_threads=0):
+def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pairs=False, n_threads=0,
+           sort_cams=None):
     """Render views; `scenes` is one scene for every view or a list, one per view.
+    sort_cams (optional, one camera per view): the depth order of each view's
+    pairs is the depth in that camera (the eyes of a stereo frame given the
+    same centre camera share one order); default each view's own.
 
     Returns a dict of numpy arrays: rgb [V][3][H][W] (list if resolutions
     differ), alpha, final_T, last, n_contrib, margin, rec [R][10], rect, n_tiles,
@@ -151,6 +155,7 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
     marr = (M * max(V, 1))(*mstructs)
     carr = (Camera * max(V, 1))(*[camera_struct(c) for c in cams])
     varr = (View * max(V, 1))(*[view_struct(v) for v in views])
+    sarr = None if sort_cams is None else (Camera * max(V, 1))(*[camera_struct(c) for c in sort_cams])
     n_pix = sum(c["width"] * c["height"] for c in cams)
     n_rec = sum(int(s["mean"].shape[1]) for s in scenes)
     tiles = sum(((c["width"] + tile - 1) // tile) * ((c["height"] + tile - 1) // tile) for c in cams)
@@ -182,7 +187,7 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
         out.pair_cap = 0
         probe = Outputs()
         probe.pair_cap = 0
-        rc = fn(V, marr, carr, varr, tile, int(brute_force), C.byref(probe), n_threads)
+        rc = fn(V, marr, carr, varr, tile, int(brute_force), C.byref(probe), n_threads, sarr)
         if rc != 0:
             raise RuntimeError(f"oracle render failed: {rc}")
         K = int(probe.counts[0])
@@ -193,7 +198,7 @@ def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pa
         out.keys = _ptr(res["keys"], C.c_uint64)
         out.vals = _ptr(res["vals"], C.c_uint32)
         out.pair_cap = K
-    rc = fn(V, marr, carr, varr, tile, int(brute_force), C.byref(out), n_threads)
+    rc = fn(V, marr, carr, varr, tile, int(brute_force), C.byref(out), n_threads, sarr)
     if rc != 0:
         raise RuntimeError(f"oracle render failed: {rc}")
     K, E, A, T = (int(x) for x in out.counts)

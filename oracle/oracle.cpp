@@ -286,13 +286,20 @@ template <typename T> struct Scene {
   std::vector<oc_view> views;
   std::vector<ViewInfo<T>> info;
   std::vector<Proj<T>> proj;  // all records
+  // per record: the depth key the pairs are sorted by within a tile, the
+  // bits of the camera-space depth as an unsigned integer; the view's own
+  // depth, or that of the view's sort camera (one order shared by the eyes
+  // of a stereo frame, Sec. 3.3)
+  std::vector<uint32_t> sort_key;
   uint64_t total_tiles = 0, total_recs = 0, total_pix = 0;
   int tile = 16;
 };
 
+template <typename T> uint32_t depth_bits(T d);
+
 template <typename T>
 void build_scene(Scene<T>& sc, int n_views, const Model<T>* models, const oc_camera* cams,
-                 const oc_view* views, int tile) {
+                 const oc_view* views, int tile, const oc_camera* sort_cams = nullptr) {
   SH<T> sh;
   sc.n_views = n_views;
   sc.tile = tile;
@@ -312,9 +319,23 @@ void build_scene(Scene<T>& sc, int n_views, const Model<T>* models, const oc_cam
     sc.total_pix += (uint64_t)cams[v].width * cams[v].height;
   }
   sc.proj.resize(sc.total_recs);
-  for (int v = 0; v < n_views; ++v)
-    for (int i = 0; i < sc.models[v].n; ++i)
-      sc.proj[sc.info[v].rec_off + i] = project_one(sc.models[v], i, sc.cams[v], sc.views[v], tile, sh);
+  sc.sort_key.resize(sc.total_recs);
+  for (int v = 0; v < n_views; ++v) {
+    const Model<T>& m = sc.models[v];
+    for (int i = 0; i < m.n; ++i) {
+      const uint64_t r = sc.info[v].rec_off + i;
+      sc.proj[r] = project_one(m, i, sc.cams[v], sc.views[v], tile, sh);
+      if (sort_cams) {
+        // depth of the centre in the sort camera, in the order of the
+        // view's own depth
+        const Cam<T> S(sort_cams[v]);
+        const T mx = m.mean[i], my = m.mean[m.n + i], mz = m.mean[2 * m.n + i];
+        sc.sort_key[r] = depth_bits(((S.R[6] * mx + S.R[7] * my) + S.R[8] * mz) + S.t[2]);
+      } else {
+        sc.sort_key[r] = sc.proj[r].valid ? depth_bits(sc.proj[r].tz) : 0u;
+      }
+    }
+  }
 }
 
 template <typename T> uint32_t depth_bits(T d) {
@@ -432,7 +453,7 @@ template <typename T> Sorted<T> sort_pairs(const Scene<T>& sc) {
   s.sorted = s.emit;
   std::stable_sort(s.sorted.begin(), s.sorted.end(), [&](const Pair& x, const Pair& y) {
     if (x.tile != y.tile) return x.tile < y.tile;
-    return sc.proj[x.rec].tz < sc.proj[y.rec].tz;
+    return sc.sort_key[x.rec] < sc.sort_key[y.rec];
   });
   s.start.assign(sc.total_tiles, 0);
   s.end.assign(sc.total_tiles, 0);
@@ -459,7 +480,7 @@ template <typename T> struct ListSource {
         for (int i = 0; i < sc.models[v].n; ++i)
           if (sc.proj[vi.rec_off + i].valid) brute[v].push_back((uint32_t)(vi.rec_off + i));
         std::stable_sort(brute[v].begin(), brute[v].end(), [&](uint32_t x, uint32_t y) {
-          return sc.proj[x].tz < sc.proj[y].tz;
+          return sc.sort_key[x] < sc.sort_key[y];
         });
       }
     } else {
@@ -484,7 +505,7 @@ template <typename T> struct ListSource {
 
 template <typename T>
 int render(int n_views, const Model<T>* models, const oc_camera* cams, const oc_view* views,
-           int tile, int brute_force, oc_outputs* out, int n_threads) {
+           int tile, int brute_force, oc_outputs* out, int n_threads, const oc_camera* sort_cams) {
   if (n_views < 0 || !out || (tile != 8 && tile != 16 && tile != 32)) return -1;
   for (int v = 0; v < n_views; ++v) {
     if (models[v].n < 0 || models[v].D < 0 || models[v].D > 3) return -1;
@@ -497,7 +518,7 @@ int render(int n_views, const Model<T>* models, const oc_camera* cams, const oc_
   (void)n_threads;
 #endif
   Scene<T> sc;
-  build_scene(sc, n_views, models, cams, views, tile);
+  build_scene(sc, n_views, models, cams, views, tile, sort_cams);
   Sorted<T> so = sort_pairs(sc);
   const uint64_t K = so.sorted.size();
   out->counts[0] = K;
@@ -524,9 +545,9 @@ int render(int n_views, const Model<T>* models, const oc_camera* cams, const oc_
     for (uint64_t k = 0; k < K; ++k) {
       const Pair& e = so.emit[k];
       const Pair& s = so.sorted[k];
-      if (out->keys_emit) out->keys_emit[k] = (e.tile << 32) | depth_bits(sc.proj[e.rec].tz);
+      if (out->keys_emit) out->keys_emit[k] = (e.tile << 32) | sc.sort_key[e.rec];
       if (out->vals_emit) out->vals_emit[k] = e.rec;
-      if (out->keys) out->keys[k] = (s.tile << 32) | depth_bits(sc.proj[s.rec].tz);
+      if (out->keys) out->keys[k] = (s.tile << 32) | sc.sort_key[s.rec];
       if (out->vals) out->vals[k] = s.rec;
     }
   }
@@ -959,17 +980,19 @@ template <typename T, typename MS> Model<T> to_model(const MS& s) {
 extern "C" {
 
 int oracle_render_f32(int n_views, const oc_model32* models, const oc_camera* cams,
-                      const oc_view* views, int tile, int brute_force, oc_outputs* out, int n_threads) {
+                      const oc_view* views, int tile, int brute_force, oc_outputs* out, int n_threads,
+                      const oc_camera* sort_cams) {
   std::vector<Model<float>> ms;
   for (int v = 0; v < n_views; ++v) ms.push_back(to_model<float>(models[v]));
-  return render<float>(n_views, ms.data(), cams, views, tile, brute_force, out, n_threads);
+  return render<float>(n_views, ms.data(), cams, views, tile, brute_force, out, n_threads, sort_cams);
 }
 
 int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* cams,
-                      const oc_view* views, int tile, int brute_force, oc_outputs* out, int n_threads) {
+                      const oc_view* views, int tile, int brute_force, oc_outputs* out, int n_threads,
+                      const oc_camera* sort_cams) {
   std::vector<Model<double>> ms;
   for (int v = 0; v < n_views; ++v) ms.push_back(to_model<double>(models[v]));
-  return render<double>(n_views, ms.data(), cams, views, tile, brute_force, out, n_threads);
+  return render<double>(n_views, ms.data(), cams, views, tile, brute_force, out, n_threads, sort_cams);
 }
 
 int oracle_backward_f32(int n_views, const oc_model32* model, const oc_camera* cams, const oc_view* views,

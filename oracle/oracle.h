@@ -95,14 +95,18 @@ typedef struct {
 /* Render n_views views; view v renders models[v] with cams[v] and views[v].
  * tile: tile edge in pixels (8, 16 or 32).  brute_force != 0 ignores the
  * tiles and blends, per pixel, every surviving Gaussian sorted by
- * (depth, index).  Returns 0, or -1 on bad arguments, -2 if pair_cap is too
- * small for the requested pair arrays (counts[0] then holds K). */
+ * (depth key, index).  The depth key of a Gaussian is the bit pattern, as
+ * an unsigned integer, of its camera-space depth: in the view's camera, or,
+ * when sort_cams is non-NULL, in sort_cams[v] (only R and t are used; the
+ * eyes of a stereo frame given the same centre camera share one depth
+ * order, Sec. 3.3).  Returns 0, or -1 on bad arguments, -2 if pair_cap is
+ * too small for the requested pair arrays (counts[0] then holds K). */
 int oracle_render_f32(int n_views, const oc_model32* models, const oc_camera* cams,
                       const oc_view* views, int tile, int brute_force, oc_outputs* out,
-                      int n_threads);
+                      int n_threads, const oc_camera* sort_cams);
 int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* cams,
                       const oc_view* views, int tile, int brute_force, oc_outputs* out,
-                      int n_threads);
+                      int n_threads, const oc_camera* sort_cams);
 
 /* Gradients of L = sum(dL_drgb * rgb) + sum(dL_dalpha * alpha) over n_views
  * views of ONE model, with respect to the activated parameters.  Gaussians

@@ -16,6 +16,17 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    if ((expr) != hipSuccess) return GSR_EHIP; \
+  } while (0)
+
+#define HIP_TRY_E(expr)                          \
+  do {                                           \
+    const hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return e_;             \
+  } while (0)
+
 // Lays buffers out in a byte arena; with base == nullptr it only measures.
 struct Carver {
   char* base;
@@ -67,10 +78,29 @@ struct PipeBufs {
   uint32_t* last = nullptr;
   uint32_t* counters = nullptr;
   uint32_t* sel = nullptr;
+  // a shared depth order (Gaussians sorted before they are paired): their
+  // keys and record ids (double-buffered), the sort's control block and
+  // look-back words, words [count, selector after the depth passes,
+  // selector after the unit passes], and the emission sequence
+  uint64_t* gk_a = nullptr;
+  uint64_t* gk_b = nullptr;
+  uint32_t* gv_a = nullptr;
+  uint32_t* gv_b = nullptr;
+  SortCtl* gctl = nullptr;
+  uint32_t* gstatus = nullptr;
+  uint32_t* gwords = nullptr;
+  uint32_t* seq_rec = nullptr;
+  uint32_t* n_tiles_seq = nullptr;
+  uint4* tile_box_seq = nullptr;
 };
 
+// Passes of the Gaussian sort of a shared depth order: 4 over the depth
+// bits, then 1 or 2 over the sort unit.
+constexpr int kOrderDepthPasses = 4;
+int order_unit_passes(uint32_t n_units) { return n_units <= 1 ? 0 : (n_units <= 256 ? 1 : 2); }
+
 size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t n_req, bool batch,
-             size_t X, size_t Q, bool backward) {
+             size_t X, size_t Q, bool backward, size_t R_sort = 0) {
   b.views = c.take<ViewD>(std::max<size_t>(n_views, 1));
   b.req_rec = c.take<uint32_t>(n_req + 1);
   b.n_tiles = c.take<uint32_t>(std::max<size_t>(R, 1));
@@ -99,6 +129,18 @@ size_t carve(Carver& c, PipeBufs& b, size_t n_views, size_t R, size_t P, size_t 
     b.last = c.take<uint32_t>(std::max<size_t>(Q, 1));
     b.counters = c.take<uint32_t>(4);
     b.sel = c.take<uint32_t>(1);
+  }
+  if (R_sort) {
+    b.gk_a = c.take<uint64_t>(R_sort);
+    b.gk_b = c.take<uint64_t>(R_sort);
+    b.gv_a = c.take<uint32_t>(R_sort);
+    b.gv_b = c.take<uint32_t>(R_sort);
+    b.gctl = c.take<SortCtl>(1);
+    b.gstatus = c.take<uint32_t>(sort_status_words((uint32_t)R_sort));
+    b.gwords = c.take<uint32_t>(4);
+    b.seq_rec = c.take<uint32_t>(std::max<size_t>(R, 1));
+    b.n_tiles_seq = c.take<uint32_t>(std::max<size_t>(R, 1));
+    b.tile_box_seq = c.take<uint4>(std::max<size_t>(R, 1));
   }
   return c.off + kAlign;
 }
@@ -136,7 +178,7 @@ hipError_t upload_views(ViewD* dst, const ViewD* src, int n_views, WordUpload& u
 
 hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, bool sticky_flags, uint32_t* ranges, size_t X,
                            size_t R, uint32_t P, uint32_t* sel, hipStream_t s, const WordUpload* up,
-                           uint32_t* batch_tile = nullptr, size_t n_batches = 0) {
+                           uint32_t* batch_tile = nullptr, size_t n_batches = 0, uint32_t n_sort = 0) {
   ClearSet cs{};
   cs.p[0] = reinterpret_cast<uint32_t*>(b.ctl);
   cs.n[0] = sizeof(SortCtl) / 4;
@@ -160,11 +202,55 @@ hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, bool sticky_fl
   cs.n[5] = 1;
   cs.n_ranges = 6;
   if (batch_tile && n_batches) {
-    cs.p[6] = batch_tile;
-    cs.n[6] = n_batches;
-    cs.n_ranges = 7;
+    cs.p[cs.n_ranges] = batch_tile;
+    cs.n[cs.n_ranges++] = n_batches;
+  }
+  if (b.gctl) {  // the Gaussian sort's control block, look-back words and selectors
+    cs.p[cs.n_ranges] = reinterpret_cast<uint32_t*>(b.gctl);
+    cs.n[cs.n_ranges++] = sizeof(SortCtl) / 4;
+    cs.p[cs.n_ranges] = b.gstatus;
+    cs.n[cs.n_ranges++] = sort_status_words(n_sort);
+    cs.p[cs.n_ranges] = b.gwords;
+    cs.n[cs.n_ranges++] = 4;
   }
   return launch_clear_multi(cs, s, up);
+}
+
+// The sort fields of view d from its view state: a shared order puts the
+// sort camera's depth row in the view (a unit) or points it at its lead.
+void set_sort_fields(ViewD& d, const gsr_view_state& vs, uint32_t mode, uint32_t unit, uint32_t off, uint32_t lead) {
+  d.sort_mode = mode;
+  d.sort_unit = unit;
+  d.sort_off = off;
+  d.sort_lead = lead;
+  if (mode == kSortCamera) {
+    d.sort_r[0] = vs.sort_cam.R[6];
+    d.sort_r[1] = vs.sort_cam.R[7];
+    d.sort_r[2] = vs.sort_cam.R[8];
+    d.sort_t = vs.sort_cam.t[2];
+  }
+}
+
+// The order stages of a call whose Gaussians are depth-sorted before they
+// are paired, up to the pair count: the Gaussian sort (records written by
+// the projection into gk_a / gv_a), then the emission sequence and its
+// tile-count scan into `offsets` (total into counters).
+hipError_t order_before_pairs(const PipeBufs& b, ViewD* views_dev, int n_views, uint32_t R, uint32_t n_sort,
+                              uint32_t n_units, uint32_t* offsets, uint32_t* counters, uint32_t P, hipStream_t s) {
+  uint32_t* sel = &b.gwords[1];
+  HIP_TRY_E(launch_sort(b.gk_a, b.gk_b, b.gv_a, b.gv_b, b.gwords, n_sort, 0, kOrderDepthPasses, b.gctl->hist,
+                        b.gstatus, b.gctl->pass_ctr, &b.gwords[1], counters + kCntError, s));
+  const int up = order_unit_passes(n_units);
+  if (up > 0) {
+    HIP_TRY_E(launch_sort(b.gk_a, b.gk_b, b.gv_a, b.gv_b, b.gwords, n_sort, kOrderDepthPasses, kOrderDepthPasses + up,
+                          b.gctl->hist, b.gstatus, b.gctl->pass_ctr, &b.gwords[2], counters + kCntError, s,
+                          &b.gwords[1]));
+    sel = &b.gwords[2];
+  }
+  HIP_TRY_E(launch_seq_build(views_dev, n_views, R, b.gk_a, b.gk_b, b.gv_a, b.gv_b, sel, n_sort, b.n_tiles,
+                             b.tile_box, b.seq_rec, b.n_tiles_seq, b.tile_box_seq, counters, s));
+  HIP_TRY_E(launch_scan(b.n_tiles_seq, offsets, b.scan_status, &b.ctl->scan_ticket, R, counters, P, s));
+  return hipSuccess;
 }
 
 bool model_ok(const gsr_model* m) {
@@ -179,7 +265,9 @@ bool camera_ok(const gsr_camera& c) {
          c.fy > 0.f;
 }
 
-bool view_ok(const gsr_view_state& v) { return v.n_clip >= 0 && v.n_clip <= GSR_MAX_CLIP; }
+bool view_ok(const gsr_view_state& v) {
+  return v.n_clip >= 0 && v.n_clip <= GSR_MAX_CLIP && (v.sort_shared == 0 || v.sort_shared == 1);
+}
 
 uint32_t tiles_of(const gsr_camera& c) {
   return div_up((uint32_t)c.width, (uint32_t)kTile) * div_up((uint32_t)c.height, (uint32_t)kTile);
@@ -227,10 +315,7 @@ std::vector<JobD> make_jobs(const ModelD& m, const std::vector<int>& view_ids) {
   return jobs;
 }
 
-#define HIP_TRY(expr)                      \
-  do {                                     \
-    if ((expr) != hipSuccess) return GSR_EHIP; \
-  } while (0)
+
 
 }  // namespace
 
@@ -346,12 +431,14 @@ uint32_t gsr_batch_capacity(uint32_t pair_capacity, uint32_t total_tiles) {
   return pair_capacity / (uint32_t)kBatch + total_tiles + 1;
 }
 
-size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t height, uint32_t pair_capacity) {
+size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t height, uint32_t pair_capacity,
+                          int32_t shared_order) {
   if (n < 0 || n_views <= 0 || width <= 0 || height <= 0 || pair_capacity >= (1u << 30)) return 0;
   Carver c(nullptr);
   PipeBufs b;
   const size_t X = (size_t)n_views * (size_t)((width + kTile - 1) / kTile) * (size_t)((height + kTile - 1) / kTile);
-  return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, X, 0, true);
+  return carve(c, b, (size_t)n_views, (size_t)n * n_views, pair_capacity, 0, false, X, 0, true,
+               shared_order ? (size_t)std::max(n, 1) : 0);
 }
 
 }  // extern "C"
@@ -376,9 +463,13 @@ gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camer
   const uint64_t X = (uint64_t)tiles_per_view * n_views;
   if (X >= kBatchTileMask || state->batch_capacity < gsr_batch_capacity(P, (uint32_t)X)) return GSR_EINVAL;
   const size_t plane = (size_t)W * H;
+  // one depth order for all views: the Gaussians are sorted by their depth in
+  // views[0].sort_cam before they are paired
+  const bool shared = views[0].sort_shared != 0;
+  const uint32_t n_sort = shared ? std::max(n, 1u) : 0u;
   Carver c(ws);
   PipeBufs b;
-  if (carve(c, b, n_views, R, P, 0, false, X, 0, backward_layout) > ws_bytes)
+  if (carve(c, b, n_views, R, P, 0, false, X, 0, backward_layout, n_sort) > ws_bytes)
     return GSR_ENOSPACE;
 
   std::vector<ViewD> hv(n_views);
@@ -391,22 +482,28 @@ gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camer
     d.alpha = alpha + plane * v;
     d.pix = state->pixel_state + 4 * plane * v;
     d.last = state->last + plane * v;
+    if (shared) set_sort_fields(d, views[0], v == 0 ? kSortCamera : kSortFollow, 0, 0, 0);
     hv[v] = d;
     ids[v] = v;
   }
   WordUpload up;
   HIP_TRY(upload_views(b.views, hv.data(), n_views, up, s));
   HIP_TRY(clear_workspace(b, state->counters, true, state->ranges, X, R, P, state->sort_sel, s, &up,
-                          state->batch_map + X + 1, state->batch_capacity));
+                          state->batch_map + X + 1, state->batch_capacity, n_sort));
+  if (shared) HIP_TRY(launch_set_u32(&b.gwords[0], n_sort, s));
   const ModelD md = make_model(*model);
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
     for (const JobD& j : make_jobs(md, ids))
-      HIP_TRY(launch_project(j, b.views, state->records, b.n_tiles, b.tile_box, s));
+      HIP_TRY(launch_project(j, b.views, state->records, b.n_tiles, b.tile_box, shared ? b.gk_a : nullptr,
+                             shared ? b.gv_a : nullptr, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_SCAN, s);
-    HIP_TRY(launch_scan(b.n_tiles, state->offsets, b.scan_status, &b.ctl->scan_ticket, R, state->counters, P, s));
+    if (shared)
+      HIP_TRY(order_before_pairs(b, b.views, n_views, R, n_sort, 1, state->offsets, state->counters, P, s));
+    else
+      HIP_TRY(launch_scan(b.n_tiles, state->offsets, b.scan_status, &b.ctl->scan_ticket, R, state->counters, P, s));
   }
   if (n_pairs_host) {
     // the pair count, and the sticky error word (this call's scan, or an
@@ -423,8 +520,12 @@ gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camer
   }
   {
     StageScope sc(timer, GSR_STAGE_DUPLICATE, s);
-    HIP_TRY(launch_duplicate(b.n_tiles, state->offsets, b.tile_box, R, state->counters, P, b.keys_a,
-                             state->pair_vals, b.rec_of, s));
+    if (shared)
+      HIP_TRY(launch_duplicate(b.n_tiles_seq, state->offsets, b.tile_box_seq, R, state->counters, P, b.keys_a,
+                               state->pair_vals, b.rec_of, s, b.seq_rec));
+    else
+      HIP_TRY(launch_duplicate(b.n_tiles, state->offsets, b.tile_box, R, state->counters, P, b.keys_a,
+                               state->pair_vals, b.rec_of, s));
   }
   if (debug && (debug->keys_emit || debug->vals_emit)) {
     if (debug->keys_emit) HIP_TRY(hipMemcpyAsync(debug->keys_emit, b.keys_a, 8ull * P, hipMemcpyDeviceToDevice, s));
@@ -450,10 +551,15 @@ gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camer
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
-    HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->sort_sel,
-                                 state->ranges, (uint32_t)X, b.rec_of, state->counters, P, state->pair_emit,
-                                 debug ? debug->keys_sorted : nullptr, b.ctl->tile_class, b.class_list,
-                                 &b.ctl->seg_ticket, state->counters + kCntError, s));
+    if (shared)  // the pairs of every tile are in depth order already
+      HIP_TRY(launch_finalize_pairs(state->pair_vals, state->pair_vals + P, b.keys_a, b.keys_b, state->sort_sel,
+                                    b.rec_of, state->counters, P, state->pair_emit,
+                                    debug ? debug->keys_sorted : nullptr, s));
+    else
+      HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, state->pair_vals, state->pair_vals + P, state->sort_sel,
+                                   state->ranges, (uint32_t)X, b.rec_of, state->counters, P, state->pair_emit,
+                                   debug ? debug->keys_sorted : nullptr, b.ctl->tile_class, b.class_list,
+                                   &b.ctl->seg_ticket, state->counters + kCntError, s));
   }
   uint32_t* batch_tile = state->batch_map + X + 1;
   {
@@ -527,7 +633,7 @@ gsr_status gsr_rasterize_forward_noalloc(const gsr_model* model, int32_t n_views
   Carver c(nullptr);
   PipeBufs b;
   const size_t need = carve(c, b, (size_t)n_views, (size_t)model->n * (size_t)n_views, state->pair_capacity, 0,
-                            false, X, 0, false);
+                            false, X, 0, false, views[0].sort_shared ? (size_t)std::max(model->n, 1) : 0);
   if (need > kNoallocScratchBytes) return GSR_ENOSPACE;
   void* ws = nullptr;
   const gsr_status st = scratch_of_current_device(&ws);
@@ -556,7 +662,7 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
                                   const gsr_grads* grads, float* max_contrib, float* activity, gsr_timer* timer,
                                   void* stream) {
   if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !grads) return GSR_EINVAL;
-  if (n_views > kMaxJobViews) return GSR_EINVAL;
+  if (n_views > kMaxJobViews || views[0].sort_shared) return GSR_EINVAL;
   if (model->n > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_sh))
     return GSR_EINVAL;
   if (!state_ok(state)) return GSR_EINVAL;
@@ -628,6 +734,11 @@ struct BatchPlan {
   std::vector<ViewD> views;
   std::vector<uint32_t> req_rec;
   uint64_t R = 0, X = 0, Q = 0;
+  // with any request sharing one depth order between its eyes, every view
+  // takes the order-first path: R_sort records in n_units sort units
+  bool ordered = false;
+  uint64_t R_sort = 0;
+  uint32_t n_units = 0;
 };
 
 bool plan_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs, int32_t n_req, BatchPlan& bp) {
@@ -655,6 +766,27 @@ bool plan_batch(const gsr_model* models, int32_t n_models, const gsr_request* re
     }
   }
   bp.req_rec[n_req] = (uint32_t)bp.R;
+  for (int q = 0; q < n_req; ++q) bp.ordered = bp.ordered || reqs[q].vs.sort_shared != 0;
+  if (bp.ordered) {
+    // each view is a sort unit by its own depth, except the eyes of a
+    // request that shares one order: the first eye sorts by the request's
+    // sort camera, the second follows it
+    size_t v = 0;
+    for (int q = 0; q < n_req; ++q) {
+      const gsr_request& r = reqs[q];
+      const bool sh = r.vs.sort_shared != 0;
+      for (int e = 0; e < r.n_views; ++e, ++v) {
+        ViewD& d = bp.views[v];
+        if (sh && e > 0) {
+          set_sort_fields(d, r.vs, kSortFollow, 0, 0, (uint32_t)(v - e));
+        } else {
+          set_sort_fields(d, r.vs, sh ? kSortCamera : kSortOwn, bp.n_units++, (uint32_t)bp.R_sort, 0);
+          bp.R_sort += (uint64_t)models[r.model].n;
+        }
+      }
+    }
+    if (bp.n_units > 65536) return false;  // two unit passes at most
+  }
   return bp.R < (1ull << 31) && bp.X < (1ull << 31);
 }
 
@@ -666,7 +798,8 @@ size_t gsr_batch_workspace_size(const gsr_model* models, int32_t n_models, const
   if (!plan_batch(models, n_models, reqs, n_req, bp) || pair_capacity >= (1u << 30)) return 0;
   Carver c(nullptr);
   PipeBufs b;
-  return carve(c, b, bp.views.size(), bp.R, pair_capacity, n_req, true, bp.X, bp.Q, false);
+  return carve(c, b, bp.views.size(), bp.R, pair_capacity, n_req, true, bp.X, bp.Q, false,
+               bp.ordered ? std::max<uint64_t>(bp.R_sort, 1) : 0);
 }
 
 gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr_request* reqs, int32_t n_req,
@@ -679,9 +812,10 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   const uint32_t P = pair_capacity;
   const uint32_t R = (uint32_t)bp.R;
   const int n_views = (int)bp.views.size();
+  const uint32_t n_sort = bp.ordered ? (uint32_t)std::max<uint64_t>(bp.R_sort, 1) : 0u;
   Carver c(ws);
   PipeBufs b;
-  if (carve(c, b, n_views, R, P, n_req, true, bp.X, bp.Q, false) > ws_bytes) return GSR_ENOSPACE;
+  if (carve(c, b, n_views, R, P, n_req, true, bp.X, bp.Q, false, n_sort) > ws_bytes) return GSR_ENOSPACE;
   // per-view transmittance / last index scratch
   size_t q_off = 0;
   for (ViewD& d : bp.views) {
@@ -692,7 +826,8 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   WordUpload up;
   HIP_TRY(upload_views(b.views, bp.views.data(), n_views, up, s));
   HIP_TRY(hipMemcpyAsync(b.req_rec, bp.req_rec.data(), 4 * (n_req + 1), hipMemcpyHostToDevice, s));
-  HIP_TRY(clear_workspace(b, b.counters, false, b.ranges, bp.X, R, P, b.sel, s, &up));
+  HIP_TRY(clear_workspace(b, b.counters, false, b.ranges, bp.X, R, P, b.sel, s, &up, nullptr, 0, n_sort));
+  if (bp.ordered) HIP_TRY(launch_set_u32(&b.gwords[0], n_sort, s));
   {
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
     for (int m = 0; m < n_models; ++m) {
@@ -702,17 +837,27 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
       if (ids.empty()) continue;
       const ModelD md = make_model(models[m]);
       for (const JobD& j : make_jobs(md, ids))
-        HIP_TRY(launch_project(j, b.views, b.records, b.n_tiles, b.tile_box, s));
+        HIP_TRY(launch_project(j, b.views, b.records, b.n_tiles, b.tile_box, bp.ordered ? b.gk_a : nullptr,
+                               bp.ordered ? b.gv_a : nullptr, s));
     }
   }
   {
     StageScope sc(timer, GSR_STAGE_SCAN, s);
-    HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.scan_status, &b.ctl->scan_ticket, R, b.counters, P, s));
+    if (bp.ordered)
+      HIP_TRY(order_before_pairs(b, b.views, n_views, R, n_sort, bp.n_units, b.offsets, b.counters, P, s));
+    else
+      HIP_TRY(launch_scan(b.n_tiles, b.offsets, b.scan_status, &b.ctl->scan_ticket, R, b.counters, P, s));
+    // (a request's records keep their positions in the emission sequence,
+    // so its pairs end at offsets[req_rec[q + 1]] in either order)
     HIP_TRY(launch_batch_status(b.req_rec, n_req, b.offsets, P, b.counters, req_status, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_DUPLICATE, s);
-    HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, b.counters, P, b.keys_a, b.vals, b.rec_of, s));
+    if (bp.ordered)
+      HIP_TRY(launch_duplicate(b.n_tiles_seq, b.offsets, b.tile_box_seq, R, b.counters, P, b.keys_a, b.vals,
+                               b.rec_of, s, b.seq_rec));
+    else
+      HIP_TRY(launch_duplicate(b.n_tiles, b.offsets, b.tile_box, R, b.counters, P, b.keys_a, b.vals, b.rec_of, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
@@ -734,9 +879,13 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   {
     StageScope sc(timer, GSR_STAGE_SORT, s);
-    HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, b.vals, b.vals + P, b.sel, b.ranges, (uint32_t)bp.X, b.rec_of,
-                                 b.counters, P, nullptr, nullptr, b.ctl->tile_class, b.class_list,
-                                 &b.ctl->seg_ticket, b.counters + kCntError, s));
+    if (bp.ordered)  // the pairs of every tile are in depth order already
+      HIP_TRY(launch_finalize_pairs(b.vals, b.vals + P, b.keys_a, b.keys_b, b.sel, b.rec_of, b.counters, P, nullptr,
+                                    nullptr, s));
+    else
+      HIP_TRY(launch_sort_segments(b.keys_a, b.keys_b, b.vals, b.vals + P, b.sel, b.ranges, (uint32_t)bp.X,
+                                   b.rec_of, b.counters, P, nullptr, nullptr, b.ctl->tile_class, b.class_list,
+                                   &b.ctl->seg_ticket, b.counters + kCntError, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_BLEND, s);

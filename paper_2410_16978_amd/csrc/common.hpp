@@ -63,7 +63,20 @@ struct ViewD {
   float* alpha;        // [H][W]
   float* pix;          // [H][W][4]: final transmittance, colour before the background
   uint32_t* last;      // [H][W]
+  // Depth order of a call that sorts Gaussians before pairing them (one
+  // order shared by the eyes of a stereo frame, Sec. 3.3): kSortNone in the
+  // per-tile path; a sort unit's records take slots [sort_off, sort_off + n)
+  // of the Gaussian sort, keyed by (sort_unit, depth) with the depth its own
+  // (kSortOwn) or the sort camera's, sort_r . mean + sort_t (kSortCamera); a
+  // follower (kSortFollow) takes the order of view sort_lead.
+  uint32_t sort_mode;
+  uint32_t sort_unit;
+  uint32_t sort_off;
+  uint32_t sort_lead;
+  float sort_r[3];
+  float sort_t;
 };
+constexpr uint32_t kSortNone = 0, kSortOwn = 1, kSortCamera = 2, kSortFollow = 3;
 
 struct ModelD {
   int32_t n, D;
@@ -129,9 +142,10 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
 // Launchers (host side, defined in the .hip files).  All enqueue on `s`.
 namespace gsr {
 
+constexpr int kClearRanges = 12;
 struct ClearSet {
-  uint32_t* p[8];
-  size_t n[8];
+  uint32_t* p[kClearRanges];
+  size_t n[kClearRanges];
   int n_ranges;
 };
 // Small host data (view descriptions) carried in the kernel arguments of
@@ -146,17 +160,26 @@ hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s, const WordUploa
 hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out, hipStream_t s);
 hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
-                          uint4* tile_box, hipStream_t s);
+                          uint4* tile_box, uint64_t* sort_keys, uint32_t* sort_vals, hipStream_t s);
 uint32_t scan_tiles(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint32_t* ticket, uint32_t n,
                        uint32_t* counters, uint32_t pair_capacity, hipStream_t s);
 hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
-                            uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s);
+                            uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s,
+                            const uint32_t* rec_map = nullptr);
+hipError_t launch_set_u32(uint32_t* p, uint32_t value, hipStream_t s);
+hipError_t launch_seq_build(const ViewD* views_dev, int n_views, uint32_t n_rec, const uint64_t* sk_a,
+                            const uint64_t* sk_b, const uint32_t* sv_a, const uint32_t* sv_b, const uint32_t* sel,
+                            uint32_t n_sort, const uint32_t* n_tiles, const uint4* tile_box, uint32_t* seq_rec,
+                            uint32_t* n_tiles_seq, uint4* tile_box_seq, uint32_t* counters, hipStream_t s);
+hipError_t launch_finalize_pairs(uint32_t* vals_a, uint32_t* vals_b, const uint64_t* keys_a, const uint64_t* keys_b,
+                                 const uint32_t* sel, const uint32_t* rec_of, const uint32_t* counters,
+                                 uint32_t pair_capacity, uint32_t* emit, uint64_t* keys_out, hipStream_t s);
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                        const uint32_t* counters, uint32_t pair_capacity, int pass_begin, int pass_end,
                        uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, uint32_t* sel_out,
-                       uint32_t* error_flag, hipStream_t s);
+                       uint32_t* error_flag, hipStream_t s, const uint32_t* sel_in = nullptr);
 size_t sort_status_stride(uint32_t pair_capacity);
 constexpr uint32_t kXcds = 8;  // accelerator dies per MI355X, each with its own L2
 constexpr uint32_t kT12MaxPairs = 1u << 24;  // the one-pass tile grouping keeps per-block tile counts: 4 B per pair slot

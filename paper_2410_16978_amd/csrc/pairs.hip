@@ -165,12 +165,13 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint
 // lane.  Pairs at or beyond min(capacity, counters[pairs]) are dropped (the
 // overflow flag or the batch status already records it).  The sort carries
 // each pair's emission index as its value; rec_of[e] keeps the record of
-// emission index e.
+// emission index e (rec_map[j] when the records were given in another
+// order, the j-th of the arrays being record rec_map[j]).
 __global__ void __launch_bounds__(256)
 k_duplicate(const uint32_t* __restrict__ n_tiles, const uint32_t* __restrict__ offsets,
             const uint4* __restrict__ tile_box, uint32_t n_rec, const uint32_t* __restrict__ counters,
             uint32_t pair_capacity, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-            uint32_t* __restrict__ rec_of) {
+            uint32_t* __restrict__ rec_of, const uint32_t* __restrict__ rec_map) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const uint32_t lim = min(pair_capacity, counters[kCntPairs]);
@@ -213,17 +214,135 @@ k_duplicate(const uint32_t* __restrict__ n_tiles, const uint32_t* __restrict__ o
       const uint32_t tile = bx + dy * bw + (j - dy * w);
       keys[e] = ((uint64_t)tile << 32) | bz;
       vals[e] = e;
-      rec_of[e] = r0 + (uint32_t)lo;
+      rec_of[e] = rec_map ? rec_map[r0 + (uint32_t)lo] : r0 + (uint32_t)lo;
     }
   }
 }
 
 hipError_t launch_duplicate(const uint32_t* n_tiles, const uint32_t* offsets, const uint4* tile_box,
                             uint32_t n_rec, const uint32_t* counters, uint32_t pair_capacity,
-                            uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s) {
+                            uint64_t* keys, uint32_t* vals, uint32_t* rec_of, hipStream_t s,
+                            const uint32_t* rec_map) {
   if (n_rec == 0) return hipSuccess;
   hipLaunchKernelGGL(k_duplicate, dim3(div_up(n_rec, 256u)), dim3(256), 0, s, n_tiles, offsets, tile_box,
-                     n_rec, counters, pair_capacity, keys, vals, rec_of);
+                     n_rec, counters, pair_capacity, keys, vals, rec_of, rec_map);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- depth order first
+// Calls whose Gaussians are depth-sorted before they are paired (one order
+// for the eyes of a stereo frame, Sec. 3.3) emit each view's records in the
+// sorted order; a stable grouping of the pairs by tile then leaves every
+// tile's pairs in depth order, with no per-tile sort.
+
+__global__ void k_set_u32(uint32_t* p, uint32_t value) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = value;
+}
+
+hipError_t launch_set_u32(uint32_t* p, uint32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, p, value);
+  return hipGetLastError();
+}
+
+// View whose records include record r (views are in record order).
+__device__ __forceinline__ int view_of_record(const ViewD* __restrict__ views, int n_views, uint32_t r) {
+  int lo = 0, hi = n_views - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (views[mid].rec_off <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Position s of the emission sequence (view by view, each view's records in
+// its unit's depth order, a follower in its lead's): the record, its tile
+// count, and its tile box whose depth word is the sort key (the pair keys'
+// low word).  A culled record (no tiles) keeps a zero box.
+__global__ void __launch_bounds__(256)
+k_seq_build(const ViewD* __restrict__ views, int n_views, uint32_t n_rec, const uint64_t* __restrict__ sk_a,
+            const uint64_t* __restrict__ sk_b, const uint32_t* __restrict__ sv_a, const uint32_t* __restrict__ sv_b,
+            const uint32_t* __restrict__ sel, uint32_t n_sort, const uint32_t* __restrict__ n_tiles,
+            const uint4* __restrict__ tile_box, uint32_t* __restrict__ seq_rec, uint32_t* __restrict__ n_tiles_seq,
+            uint4* __restrict__ tile_box_seq, uint32_t* __restrict__ counters) {
+  const bool side = *sel != 0;
+  const uint64_t* keys = side ? sk_b : sk_a;
+  const uint32_t* vals = side ? sv_b : sv_a;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_rec; s += gridDim.x * blockDim.x) {
+    const int v = view_of_record(views, n_views, s);
+    const ViewD& V = views[v];
+    const uint32_t lead = V.sort_mode == kSortFollow ? V.sort_lead : (uint32_t)v;
+    const uint32_t v_end = v + 1 < n_views ? views[v + 1].rec_off : n_rec;
+    uint32_t rec = s, nt = 0, key = 0;
+    bool ok = lead < (uint32_t)n_views;
+    if (ok) {
+      const ViewD& L = views[lead];
+      const uint32_t slot = L.sort_off + (s - V.rec_off);
+      ok = slot < n_sort;
+      if (ok) {
+        const uint32_t lead_rec = vals[slot];
+        const uint32_t gi = lead_rec - L.rec_off;  // the Gaussian (wraps when out of range)
+        key = (uint32_t)keys[slot];
+        ok = lead_rec >= L.rec_off && V.rec_off + gi < v_end;
+        if (ok) rec = V.rec_off + gi;
+      }
+    }
+    if (!ok) atomicOr(&counters[kCntError], 64u);  // an inconsistent order: the pairs of s are dropped
+    if (ok) nt = n_tiles[rec];
+    uint4 tb = make_uint4(0u, 0u, 0u, 0u);
+    if (nt) {
+      tb = tile_box[rec];
+      tb.z = key;
+    }
+    seq_rec[s] = rec;
+    n_tiles_seq[s] = nt;
+    tile_box_seq[s] = tb;
+  }
+}
+
+hipError_t launch_seq_build(const ViewD* views_dev, int n_views, uint32_t n_rec, const uint64_t* sk_a,
+                            const uint64_t* sk_b, const uint32_t* sv_a, const uint32_t* sv_b, const uint32_t* sel,
+                            uint32_t n_sort, const uint32_t* n_tiles, const uint4* tile_box, uint32_t* seq_rec,
+                            uint32_t* n_tiles_seq, uint4* tile_box_seq, uint32_t* counters, hipStream_t s) {
+  if (n_rec == 0) return hipSuccess;
+  uint32_t grid = div_up(n_rec, 256u);
+  if (grid > 16384) grid = 16384;
+  hipLaunchKernelGGL(k_seq_build, dim3(grid), dim3(256), 0, s, views_dev, n_views, n_rec, sk_a, sk_b, sv_a, sv_b,
+                     sel, n_sort, n_tiles, tile_box, seq_rec, n_tiles_seq, tile_box_seq, counters);
+  return hipGetLastError();
+}
+
+// After the tile grouping of depth-ordered pairs: each sorted pair's value
+// (its emission index) becomes its record id; the emission index goes to
+// emit and the key to keys_out (both nullable).
+__global__ void __launch_bounds__(256)
+k_finalize_pairs(uint32_t* __restrict__ vals_a, uint32_t* __restrict__ vals_b, const uint64_t* __restrict__ keys_a,
+                 const uint64_t* __restrict__ keys_b, const uint32_t* __restrict__ sel,
+                 const uint32_t* __restrict__ rec_of, uint32_t* __restrict__ counters, uint32_t pair_capacity,
+                 uint32_t* __restrict__ emit, uint64_t* __restrict__ keys_out) {
+  const uint32_t K = min(counters[kCntPairs], pair_capacity);
+  const bool side = *sel != 0;
+  uint32_t* vals = side ? vals_b : vals_a;
+  const uint64_t* keys = side ? keys_b : keys_a;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+    uint32_t e = vals[k];
+    if (e >= K) {
+      atomicOr(&counters[kCntError], 64u);
+      e = 0;
+    }
+    vals[k] = rec_of[e];
+    if (emit) emit[k] = e;
+    if (keys_out) keys_out[k] = keys[k];
+  }
+}
+
+hipError_t launch_finalize_pairs(uint32_t* vals_a, uint32_t* vals_b, const uint64_t* keys_a, const uint64_t* keys_b,
+                                 const uint32_t* sel, const uint32_t* rec_of, const uint32_t* counters,
+                                 uint32_t pair_capacity, uint32_t* emit, uint64_t* keys_out, hipStream_t s) {
+  if (pair_capacity == 0) return hipSuccess;
+  uint32_t grid = div_up(pair_capacity, 256u);
+  if (grid > 16384) grid = 16384;
+  hipLaunchKernelGGL(k_finalize_pairs, dim3(grid), dim3(256), 0, s, vals_a, vals_b, keys_a, keys_b, sel, rec_of,
+                     const_cast<uint32_t*>(counters), pair_capacity, emit, keys_out);
   return hipGetLastError();
 }
 

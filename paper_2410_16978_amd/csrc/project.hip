@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_clear_multi(ClearSet cs, WordUpload up)
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
+  for (int r = 0; r < kClearRanges; ++r) {
     if (r >= cs.n_ranges) break;
     for (; i < cs.n[r]; i += stride) cs.p[r][i] = 0u;
     i -= cs.n[r];  // continue the grid-stride walk into the next range
@@ -103,7 +103,8 @@ hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out
 template <int D>
 __global__ void __launch_bounds__(256)
 k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records,
-          uint32_t* __restrict__ n_tiles_out, uint4* __restrict__ tile_box) {
+          uint32_t* __restrict__ n_tiles_out, uint4* __restrict__ tile_box, uint64_t* __restrict__ sort_keys,
+          uint32_t* __restrict__ sort_vals) {
   constexpr int NC = (D + 1) * (D + 1);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const ModelD& m = job.m;
@@ -121,6 +122,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
     const ViewD& V = views[job.view[jv]];
     const uint32_t r = V.rec_off + (uint32_t)i;
     uint32_t nt = 0;
+    uint32_t own_key = 0xFFFFFFFFu;  // depth bits of a kept record (culled ones sort last)
     do {
       // layer activation mask
       if (layer >= 32u || !((V.layer_mask >> layer) & 1u)) break;
@@ -246,7 +248,18 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const uint32_t base_tile = V.tile_off + (uint32_t)y0 * (uint32_t)V.tiles_x + (uint32_t)x0;
       tile_box[r] = make_uint4(base_tile, (uint32_t)(x1 - x0) | ((uint32_t)(y1 - y0) << 16),
                                __float_as_uint(tz), (uint32_t)V.tiles_x);
+      own_key = __float_as_uint(tz);
     } while (false);
+    if (sort_keys && (V.sort_mode == kSortOwn || V.sort_mode == kSortCamera)) {
+      // the Gaussian's key in its sort unit: its own depth, or (every
+      // Gaussian, kept in this view or not: a follower view may keep it) its
+      // depth in the sort camera, in the order of the view's own depth
+      const uint32_t key = V.sort_mode == kSortOwn
+                               ? own_key
+                               : __float_as_uint(((V.sort_r[0] * mx + V.sort_r[1] * my) + V.sort_r[2] * mz) + V.sort_t);
+      sort_keys[V.sort_off + (uint32_t)i] = ((uint64_t)V.sort_unit << 32) | key;
+      sort_vals[V.sort_off + (uint32_t)i] = r;
+    }
     n_tiles_out[r] = nt;
     if (nt == 0) {
       // culled: the record's tile count slot says so (the rest is never read)
@@ -256,14 +269,18 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
 }
 
 hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
-                          uint4* tile_box, hipStream_t s) {
+                          uint4* tile_box, uint64_t* sort_keys, uint32_t* sort_vals, hipStream_t s) {
   if (job.m.n <= 0 || job.n_views <= 0) return hipSuccess;
   const dim3 grid(div_up((uint32_t)job.m.n, 256u)), block(256);
   switch (job.m.D) {
-    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
-    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                               sort_keys, sort_vals); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                               sort_keys, sort_vals); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                               sort_keys, sort_vals); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                                sort_keys, sort_vals); break;
   }
   return hipGetLastError();
 }

@@ -121,7 +121,7 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
             uint32_t* __restrict__ vals1, const uint32_t* __restrict__ counters, uint32_t cap,
             const uint32_t* __restrict__ hist, int pass_begin, int pass_end, uint32_t* __restrict__ sel_out,
             uint32_t* __restrict__ status, uint32_t nb_max, uint32_t* __restrict__ pass_ctr,
-            uint32_t* __restrict__ err, int pass) {
+            uint32_t* __restrict__ err, int pass, const uint32_t* __restrict__ sel_in) {
   __shared__ uint32_t s_bid;
   __shared__ uint32_t wave_cnt[kSortWaves][256];
   __shared__ uint32_t s_start[256];
@@ -165,14 +165,16 @@ k_sort_pass(uint64_t* __restrict__ keys0, uint64_t* __restrict__ keys1, uint32_t
     moved_all += mv;
     if (p < pass) moved_before += mv;
   }
-  if (pass == pass_end - 1 && blockIdx.x == 0 && t == 0) *sel_out = moved_all & 1u;
+  // the keys start in buffer 0, or where an earlier launch left them
+  const uint32_t start = sel_in ? (*sel_in & 1u) : 0u;
+  if (pass == pass_end - 1 && blockIdx.x == 0 && t == 0) *sel_out = (start + moved_all) & 1u;
   if ((triv >> pass) & 1u) return;
   for (int i = t; i < kSortWaves * 256; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
   __syncthreads();
   const uint32_t bid = s_bid;
   const uint32_t base = bid * (uint32_t)kSortTile;
   if (base >= K) return;
-  const uint32_t src = moved_before & 1u;
+  const uint32_t src = (start + moved_before) & 1u;
   const uint64_t* kin = src ? keys1 : keys0;
   const uint32_t* vin = src ? vals1 : vals0;
   uint64_t* kout = src ? keys0 : keys1;
@@ -595,11 +597,14 @@ size_t sort_status_words(uint32_t pair_capacity) {
 // pass_ctr [kMaxSortPasses] and the passes' look-back words in status are
 // zero; the digit counts go to hist.
 // *sel_out receives the buffer holding the result (0: a, 1: b); with no
-// pass it is left as it is.
+// pass it is left as it is.  sel_in (nullable, a word other than sel_out)
+// says which buffer holds the keys on entry (an earlier launch's passes);
+// the digit counts are read from keys_a, which then holds a permutation of
+// the keys too.
 hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uint32_t* vals_b,
                        const uint32_t* counters, uint32_t pair_capacity, int pass_begin, int pass_end,
                        uint32_t* hist, uint32_t* status, uint32_t* pass_ctr, uint32_t* sel_out,
-                       uint32_t* error_flag, hipStream_t s) {
+                       uint32_t* error_flag, hipStream_t s, const uint32_t* sel_in) {
   if (pass_begin < 0 || pass_end > kMaxSortPasses || pass_begin > pass_end) return hipErrorInvalidValue;
   if (pass_end - pass_begin > kHistMaxPasses) return hipErrorInvalidValue;
   const uint32_t nb_max = div_up(pair_capacity > 0 ? pair_capacity : 1u, (uint32_t)kSortTile);
@@ -615,7 +620,7 @@ hipError_t launch_sort(uint64_t* keys_a, uint64_t* keys_b, uint32_t* vals_a, uin
   for (int p = pass_begin; p < pass_end; ++p)
     hipLaunchKernelGGL(k_sort_pass, dim3(nb_max), dim3(kSortThreads), 0, s, keys_a, keys_b, vals_a, vals_b,
                        counters, pair_capacity, hist, pass_begin, pass_end, sel_out, status, nb_max, pass_ctr,
-                       error_flag, p);
+                       error_flag, p, sel_in);
   return hipGetLastError();
 }
 

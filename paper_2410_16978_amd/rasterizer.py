@@ -53,7 +53,7 @@ class ClipPlane(C.Structure):
 
 class ViewState(C.Structure):
     _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", ClipPlane * MAX_CLIP),
-                ("bg", C.c_float * 3)]
+                ("bg", C.c_float * 3), ("sort_shared", C.c_int32), ("sort_cam", Camera)]
 
 
 class Model(C.Structure):
@@ -99,7 +99,7 @@ def lib():
     L.gsr_batch_capacity.restype = C.c_uint32
     L.gsr_batch_capacity.argtypes = [C.c_uint32, C.c_uint32]
     L.gsr_workspace_size.restype = C.c_size_t
-    L.gsr_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32]
+    L.gsr_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_int32]
     L.gsr_rasterize_forward.restype = C.c_int
     L.gsr_rasterize_forward.argtypes = [C.POINTER(Model), C.c_int32, C.POINTER(Camera), C.POINTER(ViewState),
                                         C.POINTER(FwdState), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
@@ -186,7 +186,15 @@ def view_struct(vs):
     bg = vs.get("bg", (0.0, 0.0, 0.0))
     for j in range(3):
         v.bg[j] = float(bg[j])
+    if vs.get("sort_cam") is not None:  # one depth order, in this camera, for all views of the call
+        v.sort_shared = 1
+        v.sort_cam = camera_struct(vs["sort_cam"])
     return v
+
+
+def shared_order(views):
+    """Whether a call with these view states uses one shared depth order."""
+    return len(views) > 0 and views[0].get("sort_cam") is not None
 
 
 _MODEL_KEYS = ("mean", "scale", "quat", "opacity", "sh", "layer")
@@ -289,6 +297,7 @@ class ForwardState:
     n: int
     n_pairs: int = None
     generation: int = 0  # forwards run on this state (a backward checks its forward is the latest)
+    shared: bool = False  # workspace sized for a shared depth order
 
     @property
     def final_T(self):
@@ -301,24 +310,26 @@ class ForwardState:
                         self.batch_map.data_ptr(), self.counters.data_ptr(), self.capacity, self.batch_capacity)
 
 
-def workspace_size(n, n_views, width, height, pair_capacity):
-    return int(lib().gsr_workspace_size(int(n), int(n_views), int(width), int(height), int(pair_capacity)))
+def workspace_size(n, n_views, width, height, pair_capacity, shared=False):
+    return int(lib().gsr_workspace_size(int(n), int(n_views), int(width), int(height), int(pair_capacity),
+                                        1 if shared else 0))
 
 
 def _tiles(w, h):
     return ((w + TILE - 1) // TILE) * ((h + TILE - 1) // TILE)
 
 
-def make_state(n, n_views, width, height, capacity, device="cuda", old=None):
-    """Allocate (or reuse, when the shapes match) a forward state."""
+def make_state(n, n_views, width, height, capacity, device="cuda", old=None, shared=False):
+    """Allocate (or reuse, when the shapes match) a forward state; shared:
+    its workspace also holds the buffers of a shared depth order."""
     capacity = int(max(capacity, 1))
     R = n * n_views
     X = _tiles(width, height) * n_views
     Q = n_views * width * height
     if old is not None and old.n == n and old.n_views == n_views and old.width == width and old.height == height \
-            and old.capacity >= capacity:
+            and old.capacity >= capacity and (old.shared or not shared):
         return old
-    ws = workspace_size(n, n_views, width, height, capacity)
+    ws = workspace_size(n, n_views, width, height, capacity, shared)
     if ws == 0:
         raise GsrError(GSR_EINVAL, "workspace_size")
     B = int(lib().gsr_batch_capacity(capacity, X))
@@ -336,7 +347,7 @@ def make_state(n, n_views, width, height, capacity, device="cuda", old=None):
         batch_map=torch.empty(X + 1 + B, dtype=torch.int32, **kw),
         counters=torch.zeros(4, dtype=torch.int32, **kw),
         capacity=capacity, batch_capacity=B, workspace=torch.empty(ws, dtype=torch.uint8, **kw),
-        n_views=n_views, width=width, height=height, n=n)
+        n_views=n_views, width=width, height=height, n=n, shared=bool(shared))
 
 
 def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, debug=False, stream=None,
@@ -360,7 +371,8 @@ def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, 
     varr = (ViewState * V)(*[view_struct(v) for v in views])
     if capacity is None:
         capacity = state.capacity if state is not None else max(1024, 4 * n * V)
-    st = make_state(n, V, W, H, capacity, dev, state)
+    shared = shared_order(views)
+    st = make_state(n, V, W, H, capacity, dev, state, shared)
     if out is None:
         rgb = torch.empty((V, 3, H, W), dtype=torch.float32, device=dev)
         alpha = torch.empty((V, H, W), dtype=torch.float32, device=dev)
@@ -386,7 +398,7 @@ def rasterize_forward(model, cams, views, state=None, capacity=None, sync=True, 
                                      C.byref(npairs) if sync else None,
                                      C.byref(dbg_struct) if dbg_struct is not None else None, _timer(timer), s)
         if rc == GSR_ENOSPACE and sync:
-            st = make_state(n, V, W, H, int(npairs.value * 1.125) + 1024, dev, None)
+            st = make_state(n, V, W, H, int(npairs.value * 1.125) + 1024, dev, None, shared)
             continue
         _check(rc, "gsr_rasterize_forward")
         st.n_pairs = int(npairs.value) if sync else None

@@ -253,6 +253,35 @@ def stereo_cameras(direction, width, height, ipd=0.064, distance=3.0, fov_y_deg=
             orbit_camera(direction, width, height, distance, fov_y_deg, offset_x=+ipd / 2)]
 
 
+def stereo_rig(direction, width, height, ipd=0.064, distance=3.0, fov_y_deg=60.0, toe_in_deg=0.0):
+    """Left eye, right eye and the camera at their centre (the head camera,
+    which also gives a shared depth order).  toe_in_deg = 0: parallel eyes
+    (as stereo_cameras); > 0: each eye turned inwards by that angle about
+    the head's y axis (converging eyes)."""
+    d = np.asarray(direction, dtype=np.float64)
+    d /= np.linalg.norm(d)
+    head = distance * d
+    Rh = look_at_rotation(head)
+    eyes = []
+    for sign in (-1.0, 1.0):
+        c = head + sign * (ipd / 2) * Rh[0]
+        a = math.radians(-sign * toe_in_deg)  # the left eye turns right, the right eye left
+        Ry = np.array([[math.cos(a), 0.0, math.sin(a)], [0.0, 1.0, 0.0], [-math.sin(a), 0.0, math.cos(a)]])
+        R = Ry @ Rh
+        eyes.append(make_camera(R, -R @ c, width, height, fov_y_deg=fov_y_deg))
+    centre = make_camera(Rh, -Rh @ head, width, height, fov_y_deg=fov_y_deg)
+    return eyes[0], eyes[1], centre
+
+
+def centre_camera(left, right):
+    """The camera half way between two parallel eyes (their rotation, the
+    midpoint of their centres): the camera of a shared stereo depth order."""
+    R = np.asarray(left["R"], np.float64)
+    c = 0.5 * (camera_center(left) + camera_center(right))
+    return make_camera(R, -R @ c, left["width"], left["height"], fx=left["fx"], fy=left["fy"], cx=left["cx"],
+                       cy=left["cy"], znear=left["znear"], guard=left["guard"])
+
+
 def random_direction(rng):
     d = rng.standard_normal(3)
     return d / np.linalg.norm(d)
@@ -266,15 +295,27 @@ def camera_center(cam):
 # --------------------------------------------------------------------------
 # view state: layer-activation mask, clip planes, background
 # --------------------------------------------------------------------------
-def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0)):
+def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0), sort_cam=None):
+    """sort_cam (optional): one depth order for all views of the call, the
+    depth in this camera (the eye centre of a stereo frame)."""
     clips = list(clips)
     assert len(clips) <= MAX_CLIP
-    return {
+    vs = {
         "layer_mask": int(layer_mask) & 0xFFFFFFFF,
         "clips": [(np.asarray(n, np.float32).reshape(3), float(np.float32(d)), int(bits) & 0xFFFFFFFF)
                   for (n, d, bits) in clips],
         "bg": np.asarray(bg, np.float32).reshape(3),
     }
+    if sort_cam is not None:
+        vs["sort_cam"] = sort_cam
+    return vs
+
+
+def with_sort_cam(vs, sort_cam):
+    """A copy of view state vs with a shared depth order in sort_cam."""
+    out = dict(vs)
+    out["sort_cam"] = sort_cam
+    return out
 
 
 def random_view_state(rng, n_layers, n_clip_range=(1, 3), bg=(0.0, 0.0, 0.0)):

@@ -404,3 +404,60 @@ def test_double_and_float_agree(orc, layered):
     b = orc.render(to64(sc), [cam], [vs], dtype=np.float64)
     ok = a["margin"] >= 1
     np.testing.assert_allclose(a["rgb"][:, :, ok[0]], b["rgb"][:, :, ok[0]], atol=2e-5)
+
+
+# ---------------------------------------------------------------- shared depth order (stereo)
+def _stereo_case(toe_in_deg, seed=2, W=96, H=80):
+    sc = small_layered_scene(seed=seed, n_per_layer=250, log_scale_mu=-3.4)
+    left, right, centre = scenes.stereo_rig([0.2, 0.3, -1.0], W, H, ipd=0.3, distance=1.6, toe_in_deg=toe_in_deg)
+    vs = scenes.view_state(0b111, bg=(0.1, 0.2, 0.3))
+    return sc, [left, right], [vs, vs], centre
+
+
+def test_sort_camera_equal_to_the_view_is_the_default(orc):
+    """Sorting each view by the depth in its own camera is the default order."""
+    sc, cams, vss, _ = _stereo_case(4.0)
+    a = orc.render(sc, cams, vss, pairs=True)
+    b = orc.render(sc, cams, vss, pairs=True, sort_cams=cams)
+    for k in ("rgb", "alpha", "keys", "vals", "ranges", "last"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_shared_order_sorts_every_tile_by_the_centre_depth(orc):
+    """Converging eyes sorted by the centre camera's depth: every tile holds
+    the same pairs as with per-eye sorting, ordered by (centre depth bits,
+    Gaussian index); the brute-force blend in the same order agrees bit for
+    bit; the images differ from per-eye sorting, but only slightly (pairs of
+    nearly equal depth swap)."""
+    sc, cams, vss, centre = _stereo_case(6.0)
+    n = sc["mean"].shape[1]
+    own = orc.render(sc, cams, vss, pairs=True)
+    sh = orc.render(sc, cams, vss, pairs=True, sort_cams=[centre, centre])
+    bf = orc.render(sc, cams, vss, brute_force=True, sort_cams=[centre, centre])
+    # centre depth of every Gaussian, float32 in the oracle's operation order
+    R = centre["R"].astype(np.float32).reshape(9)
+    m = sc["mean"].astype(np.float32)
+    zc = ((R[6] * m[0] + R[7] * m[1]) + R[8] * m[2]) + np.float32(centre["t"][2])
+    kc = zc.astype(np.float32).view(np.uint32)
+    np.testing.assert_array_equal(sh["ranges"], own["ranges"])
+    for t0, t1 in sh["ranges"]:
+        v_sh, v_own = sh["vals"][t0:t1], own["vals"][t0:t1]
+        assert sorted(v_sh.tolist()) == sorted(v_own.tolist())
+        g = v_sh % n
+        order = np.lexsort((g, kc[g]))
+        np.testing.assert_array_equal(order, np.arange(len(g)))
+        np.testing.assert_array_equal(sh["keys"][t0:t1] & 0xFFFFFFFF, kc[g])
+    np.testing.assert_array_equal(bf["rgb"], sh["rgb"])
+    d = np.abs(sh["rgb"] - own["rgb"])
+    assert 0 < d.max() and d.mean() < 1e-3
+    assert not np.array_equal(sh["keys"], own["keys"])
+
+
+def test_parallel_eyes_share_the_per_eye_order(orc):
+    """Parallel eyes: the centre camera's depth rows equal the eyes', so
+    the shared order is each eye's own and the images are identical."""
+    sc, cams, vss, centre = _stereo_case(0.0)
+    own = orc.render(sc, cams, vss, pairs=True)
+    sh = orc.render(sc, cams, vss, pairs=True, sort_cams=[centre, centre])
+    for k in ("rgb", "alpha", "keys", "vals", "last"):
+        np.testing.assert_array_equal(sh[k], own[k], err_msg=k)
