@@ -790,7 +790,9 @@ int backward(int n_views, const Model<TF>& m, const oc_camera* cams, const oc_vi
   for (int v = 0; v < n_views; ++v) {
     const int W = sc.cams[v].W, H = sc.cams[v].H;
     const uint64_t po = sc.info[v].pix_off;
-#pragma omp parallel for schedule(dynamic, 8)
+    // rows go to threads round-robin (a fixed assignment for a given thread
+    // count), so every per-record sum is taken in the same order on every run
+#pragma omp parallel for schedule(static, 1)
     for (int y = 0; y < H; ++y) {
       int tid = 0;
 #ifdef _OPENMP
