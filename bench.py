@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "render Mpix/s + p50/p99 frame latency; fwd+bwd iters/s; vs plain, 1 GPU"
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (packed) peak, published
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
-STAGES = ("project", "scan", "duplicate", "sort", "ranges", "blend", "blend_bwd", "project_bwd")
+STAGES = ("project", "scan", "duplicate", "sort", "ranges", "blend", "blend_bwd", "project_bwd", "bwd_order")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_training_step_200k.json")
 
 
@@ -89,6 +89,18 @@ def algorithmic_work(orc_fwd, scene, n_pix):
         "project_bwd": {"bytes": nv * (36 + 48 + 12 * nc + 40 + 4 * (10 + 3 * nc)) + 4 * n * (11 + 3 * nc)},
         "pixels": n_pix,
     }
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_cpu_baseline(workload, threads, min_seconds, max_steps=200):
@@ -189,6 +201,41 @@ def bench_stereo(rz, scenes, torch, frames, warmup):
             "shared_order_speedup_vs_plain": round(res["plain"]["ms_per_frame"] / res["shared_order"]["ms_per_frame"],
                                                    3),
             "shared_order_image_max_abs_vs_per_eye": diff, "stage_ms_per_frame": stages}
+
+
+def bench_plain_forward(rz, scenes, torch, frames=1000, warmup=50):
+    """Plain forward render: 4096 Gaussians (uniform in [-1, 1]^3, SH0), one
+    128x128 view, one launch chain per frame; per-frame latency from HIP
+    events over `frames` frames (p50 / p99), Mpix/s, and the launch chain
+    broken down by stage (library-recorded events)."""
+    wl = scenes.plain_forward_4k()
+    model = rz.to_device(wl.scene)
+    cams, views = wl.cams, wl.views
+    W, H = cams[0]["width"], cams[0]["height"]
+    _, _, st = rz.rasterize_forward(model, cams, views)
+    st = rz.make_state(wl.scene["mean"].shape[1], 1, W, H, int(st.n_pairs * 1.05) + 1024)
+    out = (torch.empty((1, 3, H, W), device="cuda"), torch.empty((1, H, W), device="cuda"))
+    for _ in range(warmup):
+        rz.rasterize_forward(model, cams, views, state=st, sync=False, out=out)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(frames):
+        rz.rasterize_forward(model, cams, views, state=st, sync=False, out=out)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(frames)]
+    mean = ev[0].elapsed_time(ev[-1]) / frames
+    tm = rz.Timer()
+    for _ in range(100):
+        rz.rasterize_forward(model, cams, views, state=st, sync=False, out=out, timer=tm)
+    stages = {k: round(v[0] / 100 * 1e3, 2) for k, v in tm.read().items() if v[1]}
+    tm.close()
+    rz.forward_check(st)
+    return {"workload": wl.name, "frames": frames, "mpix_s": round(W * H / (mean * 1e-3) / 1e6, 2),
+            "ms_per_frame": round(mean, 4), "p50_ms": round(percentile(ms, 50), 4),
+            "p99_ms": round(percentile(ms, 99), 4), "pairs": st.n_pairs if st.n_pairs else None,
+            "stage_us_per_frame": stages}
 
 
 def bench_serving(rz, scenes, torch, seconds, rate):
@@ -321,10 +368,13 @@ def main():
                     help="skip the layered-stereo and serving measurements (profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving trace")
     ap.add_argument("--workload", default="training_step_200k",
-                    choices=["training_step_200k", "layered_training_4m"],
+                    choices=["training_step_200k", "layered_training_4m", "layered_stereo_1m"],
                     help="training_step_200k (default): the 200k/800x800 step; layered_training_4m: 4M Gaussians, "
-                         "8 views of 1024^2 per step, pruning every 100 steps")
+                         "8 views of 1024^2 per step, pruning every 100 steps; layered_stereo_1m: only the layered "
+                         "stereo frames (1M Gaussians, 2 x 1832x1920; profiling runs)")
     ap.add_argument("--train-steps", type=int, default=200, help="steps of the layered_training_4m workload")
+    ap.add_argument("--extra-train-steps", type=int, default=50,
+                    help="steps of the layered_training_4m entry of the default run (0: left out)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -354,6 +404,9 @@ def main():
         return
     if args.workload == "layered_training_4m":
         print(json.dumps(bench_layered_training(args, torch, rz, ag, scenes)), flush=True)
+        return
+    if args.workload == "layered_stereo_1m":
+        print(json.dumps(bench_stereo(rz, scenes, torch, frames=args.steps, warmup=args.warmup)), flush=True)
         return
     wl = scenes.training_step_200k(seed=0)
     sc = wl.scene
@@ -501,20 +554,33 @@ def main():
 
     # ---------------- layered stereo render and serving, each vs the plain path
     if not args.no_extra:
+        result["plain_forward_4k_128px"] = bench_plain_forward(rz, scenes, torch)
         result["stereo_render"] = bench_stereo(rz, scenes, torch, frames=max(10, min(args.steps, 50)),
                                                warmup=max(2, min(args.warmup, 5)))
         result["serving"] = bench_serving(rz, scenes, torch, args.serve_seconds, 200.0)
+        if args.extra_train_steps > 0:
+            sub = argparse.Namespace(warmup=3, train_steps=args.extra_train_steps)
+            lt = bench_layered_training(sub, torch, rz, ag, scenes)
+            result["layered_training_4m"] = {k: lt[k] for k in (
+                "value", "unit", "steps", "ms_per_step", "plain_ms_per_step", "speedup_vs_plain", "prunes",
+                "pruned", "pruned_fraction_of_trainable", "gaussians_after")}
+            result["layered_training_4m"]["workload"] = lt["config"]["workload"]
 
     # ---------------- CPU oracle on one step of the same workload
     threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
     orc_fwd = None
     if not args.no_cpu_baseline:
         orc_fwd, n_cpu, t_f, t_b = run_cpu_baseline(wl, threads, args.cpu_seconds)
+        _, n1, t1f, t1b = run_cpu_baseline(wl, 1, 0.0, max_steps=1)
         result["cpu_baseline"] = {"value": round(n_cpu / (t_f + t_b), 4), "unit": "iters/s", "cores": threads,
                                   "kind": "oracle",
                                   "sample": "%d full steps (forward + backward) of the same 200k/800x800 "
                                             "workload in %.1f s; forward %.2f s, backward %.2f s per step"
-                                            % (n_cpu, t_f + t_b, t_f / n_cpu, t_b / n_cpu)}
+                                            % (n_cpu, t_f + t_b, t_f / n_cpu, t_b / n_cpu),
+                                  "single_thread": {"value": round(n1 / (t1f + t1b), 4), "cores": 1,
+                                                    "sample": "1 full step: forward %.2f s, backward %.2f s"
+                                                              % (t1f, t1b)},
+                                  "cpu_model": cpu_model()}
     else:
         import oracle
         orc_fwd = oracle.render(wl.scene, wl.cams, wl.views, n_threads=threads)

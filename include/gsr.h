@@ -210,8 +210,9 @@ enum {
   GSR_STAGE_SORT,
   GSR_STAGE_RANGES,
   GSR_STAGE_BLEND,
-  GSR_STAGE_BLEND_BWD,
+  GSR_STAGE_BLEND_BWD,     /* the backward blend kernel alone */
   GSR_STAGE_PROJECT_BWD,
+  GSR_STAGE_BWD_ORDER,     /* the backward's ordering of batches, heaviest first */
   GSR_N_STAGES
 };
 gsr_status gsr_timer_create(gsr_timer** out);

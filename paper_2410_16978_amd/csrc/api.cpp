@@ -706,10 +706,13 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
     cs.n_ranges = 3;
     HIP_TRY(launch_clear_multi(cs, s, up.n ? &up : nullptr));
   }
+  const uint32_t* batch_tile = state->batch_map + X + 1;
+  {
+    StageScope sc(timer, GSR_STAGE_BWD_ORDER, s);
+    HIP_TRY(launch_batch_order(batch_tile, n_batches, b.order_cnt, b.order_list, s));
+  }
   {
     StageScope sc(timer, GSR_STAGE_BLEND_BWD, s);
-    const uint32_t* batch_tile = state->batch_map + X + 1;
-    HIP_TRY(launch_batch_order(batch_tile, n_batches, b.order_cnt, b.order_list, s));
     HIP_TRY(launch_blend_bwd(b.views, n_views, state->records, R, state->pair_vals, state->sort_sel, P,
                              state->ranges, reinterpret_cast<const float4*>(state->checkpoints), batch_tile,
                              n_batches, b.order_cnt, b.order_list, dL_drgb, dL_dalpha, state->pair_emit, b.g_pair,

@@ -239,7 +239,7 @@ def activate(model, stream=None):
 
 
 # ---------------------------------------------------------------- timer
-STAGES = ("project", "scan", "duplicate", "sort", "ranges", "blend", "blend_bwd", "project_bwd")
+STAGES = ("project", "scan", "duplicate", "sort", "ranges", "blend", "blend_bwd", "project_bwd", "bwd_order")
 
 
 class Timer:
