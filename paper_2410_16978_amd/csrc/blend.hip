@@ -27,6 +27,7 @@
 // in a fixed order through LDS, and written as the pair's partial gradient:
 // no atomics, bitwise reproducible.
 #include "common.hpp"
+#include "cull.hpp"
 
 namespace gsr {
 
@@ -43,7 +44,7 @@ struct BatchLds {
   float4 a[kBatch];    // u, v, conic a, 2 b
   float4 b[kBatch];    // conic c, opacity, r, g
   float c[kBatch];     // b
-  float4 ell[kBatch];  // q cut-off with margin, -b/c, -b/a (the conic's minimum over a rectangle)
+  float cut[kBatch];   // q cut-off with margin
 };
 
 __device__ __forceinline__ int find_view(const ViewD* __restrict__ views, int n_views, uint32_t tile) {
@@ -93,10 +94,8 @@ __device__ __forceinline__ Staged fetch(const float* __restrict__ records, uint3
 // and this computation, so skipping a pair for pixel centres where its q
 // exceeds the cut-off never changes a result.  The cut-off is negative
 // (nothing reachable) when 255 o < 1.
-__device__ __forceinline__ float4 reach_conic(const Staged& st) {
-  const float o = st.b.y;
-  const float qo = fminf(kQMax, 2.f * __logf(255.f * o)) * 1.01f + 0.05f;
-  return make_float4(qo, -st.a.w / st.b.x, -st.a.w / st.a.z, 0.f);
+__device__ __forceinline__ float reach_cutoff(const Staged& st) {
+  return fminf(kQMax, 2.f * __logf(255.f * st.b.y)) * 1.01f + 0.05f;
 }
 
 __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int tid) {
@@ -104,30 +103,8 @@ __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int 
     L.a[tid] = make_float4(st.a.x, st.a.y, st.a.z, 2.f * st.a.w);
     L.b[tid] = st.b;
     L.c[tid] = st.c;
-    L.ell[tid] = reach_conic(st);
+    L.cut[tid] = reach_cutoff(st);
   }
-}
-
-// q = a dx^2 + 2 b dx dy + c dy^2 at an offset, lowered by a bound on its
-// rounding (a few ulps of the summed term magnitudes).
-__device__ __forceinline__ float conic_low(float a, float b, float c, float dx, float dy) {
-  const float t1 = a * dx * dx, t2 = c * dy * dy, t3 = 2.f * b * dx * dy;
-  return (t1 + t2 + t3) - 4e-6f * (t1 + t2 + fabsf(t3));
-}
-
-// Whether the pair's ellipse {q <= cut-off} meets the rectangle of pixel
-// centres [x0, x1] x [y0, y1]: q is convex, so if the centre lies outside
-// the rectangle its minimum there is on an edge, where it is the clamped
-// one-dimensional minimum.  Anything not finite keeps the pair.
-__device__ __forceinline__ bool conic_meets(const float4 A, float c, const float4 E, float x0, float x1, float y0,
-                                            float y1) {
-  const float mx = A.x, my = A.y, a = A.z, b = A.w;
-  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
-  float m = conic_low(a, b, c, x0 - mx, fminf(fmaxf(E.y * (x0 - mx), y0 - my), y1 - my));
-  m = fminf(m, conic_low(a, b, c, x1 - mx, fminf(fmaxf(E.y * (x1 - mx), y0 - my), y1 - my)));
-  m = fminf(m, conic_low(a, b, c, fminf(fmaxf(E.z * (y0 - my), x0 - mx), x1 - mx), y0 - my));
-  m = fminf(m, conic_low(a, b, c, fminf(fmaxf(E.z * (y1 - my), x0 - mx), x1 - mx), y1 - my));
-  return !(m > E.x);
 }
 
 // Lane permutation within rows / quads (DPP); lanes a row mask leaves out
@@ -142,25 +119,36 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// The wave's list of the batch's pairs (ascending, j < n) that can reach a
-// pixel centre of its rectangle [qx0, qx1] x [qy0, qy1] (the ellipse of the
-// cut-off meets the rectangle); each lane tests one pair per round, a
-// ballot compacts the hits.  Returns the (wave-uniform) count.  Pairs not in
-// the list cannot reach alpha >= 1/255 on any of the wave's pixels, so
-// skipping them changes nothing.
-__device__ __forceinline__ int wave_list(const BatchLds& L, uint8_t* list, int n, float qx0, float qx1, float qy0,
-                                         float qy1) {
+// Block memberships of a batch: thread t of a 1024-thread block takes pair
+// t mod 256 and the tile's block row t / 256 and writes the 4 bits of the
+// row's 4 x 4 blocks the pair's ellipse reaches (band_blocks) to
+// nib[row][pair].  A tile is 4 x 4 such blocks; bit 4 row + column of a
+// pair's 16-bit block mask is block (column, row).
+static_assert(kBatch * 4 == 1024, "one block row per thread");
+
+__device__ __forceinline__ void block_nibbles(const BatchLds& L, uint8_t (*nib)[kBatch], int n, float tx0,
+                                              float ty0) {
+  const int j = threadIdx.x & (kBatch - 1), r = threadIdx.x >> 8;
+  uint32_t bits = 0u;
+  if (j < n) {
+    const float4 A = L.a[j];
+    bits = band_blocks(A.x, A.y, A.z, 0.5f * A.w, L.b[j].x, L.cut[j], tx0, ty0 + 4.f * (float)r);
+  }
+  nib[r][j] = (uint8_t)bits;
+}
+
+// The wave's list of the batch's pairs (ascending, j < n) whose ellipse
+// reaches its block (bit `col` of the block row's nibbles); each lane tests
+// one pair per round, a ballot compacts the hits.  Returns the
+// (wave-uniform) count.  Pairs not in the list cannot reach alpha >= 1/255 on
+// any of the wave's pixels, so skipping them changes nothing.
+__device__ __forceinline__ int wave_list(const uint8_t* nib_row, int col, uint8_t* list, int n) {
   const int lane = threadIdx.x & 63;
   int cnt = 0;
 #pragma unroll
   for (int r = 0; r < kBatch / 64; ++r) {
     const int j = r * 64 + lane;
-    bool hit = false;
-    if (j < n) {
-      const float4 E = L.ell[j];
-      const float4 A = L.a[j];
-      hit = E.x > 0.05f && conic_meets(make_float4(A.x, A.y, A.z, 0.5f * A.w), L.b[j].x, E, qx0, qx1, qy0, qy1);
-    }
+    const bool hit = j < n && ((nib_row[j] >> col) & 1u);
     const uint64_t m = __ballot(hit);
     if (hit) list[cnt + __popcll(m & lanes_below())] = (uint8_t)j;
     cnt += __popcll(m);
@@ -256,6 +244,7 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
              const uint32_t* __restrict__ class_count, const uint32_t* __restrict__ class_list) {
   __shared__ BatchLds L;
   __shared__ uint8_t lists[16][kBatch];
+  __shared__ uint8_t nib[4][kBatch];
   // block b takes the b-th tile of the largest-first order (if given): the
   // class counts are read at once, the first wave finds b's class by a scan
   __shared__ uint32_t s_tile;
@@ -282,14 +271,16 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   const uint32_t upto_slot = (2u << slot) - 1u;  // stop bits of the slots up to this one
   const uint32_t local = tile - V.tile_off;
   const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
-  const int sx0 = tx * kTile + (wave & 3) * kQuadPix, sy0 = ty * kTile + (wave >> 2) * kQuadPix;
   const int lx = (wave & 3) * kQuadPix + (p & 3), ly = (wave >> 2) * kQuadPix + (p >> 2);  // in the tile
   const int px = tx * kTile + lx, py = ty * kTile + ly;
   const int bidx = ((ly >> 3) * 2 + (lx >> 3)) * 64 + (ly & 7) * 8 + (lx & 7);  // backward's thread of this pixel
   const bool inside = px < V.W && py < V.H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const float qx0 = (float)sx0 + 0.5f, qx1 = qx0 + 3.f, qy0 = (float)sy0 + 0.5f, qy1 = qy0 + 3.f;
   const uint32_t* vals = pair_vals + (*sel ? cap : 0u);
+  // a training forward leaves each sorted pair's block mask for the backward
+  // in the other half of pair_vals (free once the sort is done)
+  uint16_t* blk_out = ckpt ? reinterpret_cast<uint16_t*>(const_cast<uint32_t*>(pair_vals) + (*sel ? 0u : cap))
+                           : nullptr;
   const uint32_t t_end = min(ranges[2 * tile + 1], cap);
   const uint32_t t_start = min(ranges[2 * tile], t_end);
   const uint32_t b0 = first_batch(tile, t_start);
@@ -316,10 +307,14 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       const uint32_t k = start + kBatch + (uint32_t)tid;
       rid = tid < kBatch && k < t_end ? vals[k] : 0u;
     }
+    block_nibbles(L, nib, n, (float)(tx * kTile) + 0.5f, (float)(ty * kTile) + 0.5f);
+    __syncthreads();
+    if (blk_out && tid < n)
+      blk_out[start + tid] = (uint16_t)(nib[0][tid] | (nib[1][tid] << 4) | (nib[2][tid] << 8) | (nib[3][tid] << 12));
     const float T0 = T;
     float D0 = 0.f, D1 = 0.f, D2 = 0.f;
     uint32_t lst = 0;
-    const int cnt = __ballot(!done) ? wave_list(L, list, n, qx0, qx1, qy0, qy1) : 0;
+    const int cnt = __ballot(!done) ? wave_list(nib[wave >> 2], wave & 3, list, n) : 0;
     int stepped = cnt;
     for (int t0 = 0; t0 < cnt; t0 += 4) {
       const int te = t0 + slot;
@@ -538,7 +533,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   __shared__ BatchLds L;
   constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
   __shared__ float part[4][kGradSlots][kSub];
-  __shared__ uint8_t lists[4][kBatch];
+  __shared__ uint16_t s_blk[kBatch];  // block masks the forward left
   // block b takes the b-th batch of the heaviest-first order: the first wave
   // scans the class counts and finds b's class
   __shared__ uint32_t s_bi;
@@ -581,7 +576,8 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   const size_t plane = (size_t)V.W * V.H;
   const size_t pix = inside ? (size_t)py * V.W + px : 0;
   const size_t vpix = (size_t)vi * plane;  // views of one call share a resolution
-  uint32_t plast = 0;
+  // lim: this pixel's pairs j < lim lie in front of its last blended pair
+  int lim = 0;
   // With S the colour behind the current pair and T the transmittance behind
   // it, dL/dalpha = Tb (G . c) - P / (1 - alpha) where P = sum_ch G_ch S_ch -
   // GA Tfin.  The kernel carries Q = P / T instead: then dL/dalpha =
@@ -595,8 +591,9 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   double T = 1.0;
   float Tfin = 1.f, Q = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GA = 0.f;
   if (inside) {
-    plast = V.last[pix];
+    const uint32_t plast = V.last[pix];
     if (plast > start) {
+      lim = (int)min(plast - start, (uint32_t)n);
       const float4 ps = reinterpret_cast<const float4*>(V.pix)[pix];
       Tfin = ps.x;
       // batch of the pixel's last blended pair (>= c)
@@ -613,8 +610,6 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       }
       if (dL_dalpha) GA = dL_dalpha[vpix + pix];
       Q = __fdiv_rn(fmaf(G2, sb.w, fmaf(G1, sb.z, fmaf(G0, sb.y, -GA * Tfin))), (float)T);
-    } else {
-      plast = 0;
     }
   }
   // thread t stages pair t and later combines its sums (sub-batch t / kSub
@@ -622,24 +617,22 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   // index stay in its registers
   const Staged mine = fetch(records, n_rec, vals, start + tid, tid < n);
   put(L, mine, tid < n, tid);
+  {
+    const uint16_t* blk = reinterpret_cast<const uint16_t*>(pair_vals + (*sel ? 0u : cap));
+    s_blk[tid] = tid < n ? blk[start + tid] : (uint16_t)0;
+  }
   uint32_t my_emit = tid < n ? pair_emit[start + tid] : 0u;
   if (my_emit >= cap) my_emit = 0;  // never write out of range (an inconsistent sort shows up as wrong gradients)
   for (int i = tid; i < 4 * kGradSlots * kSub; i += 256) (&part[0][0][0])[i] = 0.f;
-  const float qx0 = (float)(tx * kTile + (wave & 1) * 8) + 0.5f, qx1 = qx0 + 7.f;
-  const float qy0 = (float)(ty * kTile + (wave >> 1) * 8) + 0.5f, qy1 = qy0 + 7.f;
+  // the wave's 8 x 8 quadrant: 2 x 2 of the tile's 4 x 4 blocks
+  const uint32_t qmask = 0x33u << (2 * (wave & 1) + 8 * (wave >> 1));
+  // the wave's reach: no pair at or behind its pixels' last blended pair counts
+  int n_wave = lim;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) n_wave = max(n_wave, __shfl_xor(n_wave, off, 64));
+  n_wave = __builtin_amdgcn_readfirstlane(n_wave);
   __syncthreads();
 
-  // the wave's pairs: those reaching its quadrant, in front of its pixels'
-  // last blended pair
-  uint8_t* list = lists[wave];
-  int cnt = 0;
-  {
-    uint32_t wl = plast;  // wave maximum of plast
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) wl = max(wl, (uint32_t)__shfl_xor((int)wl, off, 64));
-    const int n_wave = wl > start ? (int)min(wl - start, (uint32_t)n) : 0;
-    if (n_wave > 0) cnt = wave_list(L, list, n_wave, qx0, qx1, qy0, qy1);
-  }
   // back to front in sub-batches of kSub pairs; after each, the four wave
   // partials of its pairs are summed in a fixed order and written out
   const int n_sub = (n + kSub - 1) / kSub;
@@ -649,36 +642,41 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   const int row = lane >> 4;
   const int q_lane = (lane & 2) ? 8 : 2 * (((lane >> 2) & 1) * 2 + ((lane >> 3) & 1)) + (row & 1);
   const bool writer = !(lane & 1) && (!(lane & 2) || ((lane & 12) == 0 && !(row & 1)));
+  const bool front = row >= 2;
   float* part_lane = &part[wave][q_lane][0];
+  struct PairLds {
+    float4 A, B;
+    float c;
+  };
+  auto load = [&](int j) -> PairLds { return PairLds{L.a[j], L.b[j], L.c[j]}; };
   // one pair for this pixel: updates T and Q (back to front) and returns the
   // nine per-pixel terms; inactive pairs give zeros
-  auto eval = [&](int j, bool valid, float (&v)[9], float& w) -> bool {
-    const uint32_t kk = start + (uint32_t)j;
+  auto eval = [&](const PairLds& P, int j, bool valid, float (&v)[9], float& w) -> bool {
     // branch-free: every lane evaluates the pair, selects keep what counts
-    const float4 A = L.a[j], B = L.b[j];
-    const float cbl = L.c[j];
+    const float4 A = P.A, B = P.B;
     const float dx = A.x - fx, dy = A.y - fy;
     const float power = pair_power(A, B, dx, dy);
     const float G = pair_gauss(power);
     const float oG = B.y * G;
     const float alpha = fminf(kAlphaMax, oG);
-    const bool contrib = valid && kk < plast && power <= 0.f && alpha >= kAlphaMin;
+    const bool contrib = valid && j < lim && power <= 0.f && alpha >= kAlphaMin;
     const bool has_grad = contrib && !(oG > kAlphaMax);  // alpha not clamped: it has a gradient
+    // ae is alpha where the pair blends and 0 elsewhere: with it the colour
+    // weight, the Q step and the transmittance need no further selects
+    const float ae = contrib ? alpha : 0.f;
     // transmittance in front of this pair: T / (1 - alpha), alpha <= 0.99,
     // the reciprocal refined by one Newton step (a few units of 2^-53)
-    const double om = 1.0 - (double)alpha;
+    const double om = 1.0 - (double)ae;
     double inv1m = __builtin_amdgcn_rcp(om);
     inv1m = fma(inv1m, fma(-om, inv1m, 1.0), inv1m);
     const double Tbd = T * inv1m;
     const float Tb = (float)Tbd;
-    const float wv = alpha * Tb;
-    const float gcol = fmaf(G2, cbl, fmaf(G1, B.w, G0 * B.z));  // G . c
+    const float gcol = fmaf(G2, P.c, fmaf(G1, B.w, G0 * B.z));  // G . c
     const float dq = gcol - Q;
-    const float dalpha = Tb * dq;
-    w = contrib ? wv : 0.f;
-    Q = fmaf(contrib ? alpha : 0.f, dq, Q);
+    w = ae * Tb;
+    Q = fmaf(ae, dq, Q);
     T = contrib ? Tbd : T;
-    const float h = has_grad ? dalpha * oG : 0.f;
+    const float h = (Tb * dq) * (has_grad ? oG : 0.f);  // dL/dalpha o G
     const float hx = h * dx, hy = h * dy;
     v[0] = hx;
     v[1] = hy;
@@ -691,62 +689,72 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
     v[8] = G2 * w;
     return contrib;
   };
-  int t = cnt - 1;
+  // highest pair of a wave-uniform bit set, removed from it
+  auto pop = [](uint64_t& m) -> int {
+    const int b = 63 - (int)__builtin_clzll(m);
+    m &= ~(1ull << b);
+    return b;
+  };
   for (int sb = n_sub - 1; sb >= 0; --sb) {
-    const int j0 = sb * kSub, j1 = min(n, j0 + kSub);
+    const int j0 = sb * kSub;
+    // the wave's pairs of this sub-batch: lane l tests pair j0 + l, a ballot
+    // gives the set of those that can reach alpha >= 1/255 at a pixel centre
+    // of its quadrant in front of its pixels' last blended pair
+    const int jl = j0 + lane;
+    uint64_t m = ballot(jl < n_wave && (s_blk[jl] & qmask) != 0u);
     // two pairs per step (the second, in front, may be absent)
-    while (t >= 0) {
-      const int ja = list[t];
-      if (ja < j0) break;
-      const int jn = t > 0 ? (int)list[t - 1] : -1;
-      const bool hb = jn >= j0;
-      const int jb = hb ? jn : ja;
-      t -= hb ? 2 : 1;
+    while (m != 0ull) {
+      const int ja = pop(m);
+      const bool hb = m != 0ull;
+      const int jb = hb ? pop(m) : ja;
+      const PairLds pa = load(j0 + ja), pb = load(j0 + jb);
       float va[9], vb[9], wa, wb;
-      const bool ca = eval(ja, true, va, wa);
-      const bool cb = eval(jb, hb, vb, wb);
-      if (ballot(ca || cb) == 0ull) continue;
-      // reduce-scatter: halves (back | front pair), then row pairs, then
-      // within rows by mirror exchanges that keep one operand per lane half
-      float X[9];
+      const bool ca = eval(pa, j0 + ja, true, va, wa);
+      const bool cb = eval(pb, j0 + jb, hb, vb, wb);
+      if (ballot(ca || cb) != 0ull) {
+        // reduce-scatter: halves (back | front pair), then row pairs, then
+        // within rows by mirror exchanges that keep one operand per lane half
+        float X[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) X[q] = swap32_add(va[q], vb[q]);
-      const float Y0 = swap16_add(X[0], X[1]), Y1 = swap16_add(X[2], X[3]);
-      const float Y2 = swap16_add(X[4], X[5]), Y3 = swap16_add(X[6], X[7]);
-      const float Y4 = swap16_add(X[8], X[8]);
-      const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
-      const float Z0 = (b3 ? Y1 : Y0) + dpp<0x140, 0xF>(b3 ? Y0 : Y1);  // row_mirror
-      const float Z1 = (b3 ? Y3 : Y2) + dpp<0x140, 0xF>(b3 ? Y2 : Y3);
-      const float Z2 = Y4 + dpp<0x140, 0xF>(Y4);
-      const float W0 = (b2 ? Z1 : Z0) + dpp<0x141, 0xF>(b2 ? Z0 : Z1);  // row_half_mirror
-      const float W1 = Z2 + dpp<0x141, 0xF>(Z2);
-      float R = (b1 ? W1 : W0) + dpp<0x4E, 0xF>(b1 ? W0 : W1);  // quad_perm [2,3,0,1]
-      R += qperm<0xB1>(R);                                        // quad_perm [1,0,3,2]
-      const float mxa = want_max ? wave_max63(wa) : 0.f;
-      const float mxb = want_max ? wave_max63(wb) : 0.f;
-      const bool front = row >= 2;
-      if (writer && (!front || hb)) part_lane[(front ? jb : ja) - j0] = R;
-      if (lane == 63) {
-        part[wave][9][ja - j0] = mxa;
-        if (hb) part[wave][9][jb - j0] = mxb;
+        for (int q = 0; q < 9; ++q) X[q] = swap32_add(va[q], vb[q]);
+        const float Y0 = swap16_add(X[0], X[1]), Y1 = swap16_add(X[2], X[3]);
+        const float Y2 = swap16_add(X[4], X[5]), Y3 = swap16_add(X[6], X[7]);
+        const float Y4 = swap16_add(X[8], X[8]);
+        const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+        const float Z0 = (b3 ? Y1 : Y0) + dpp<0x140, 0xF>(b3 ? Y0 : Y1);  // row_mirror
+        const float Z1 = (b3 ? Y3 : Y2) + dpp<0x140, 0xF>(b3 ? Y2 : Y3);
+        const float Z2 = Y4 + dpp<0x140, 0xF>(Y4);
+        const float W0 = (b2 ? Z1 : Z0) + dpp<0x141, 0xF>(b2 ? Z0 : Z1);  // row_half_mirror
+        const float W1 = Z2 + dpp<0x141, 0xF>(Z2);
+        float R = (b1 ? W1 : W0) + dpp<0x4E, 0xF>(b1 ? W0 : W1);  // quad_perm [2,3,0,1]
+        R += qperm<0xB1>(R);                                        // quad_perm [1,0,3,2]
+        if (writer && (!front || hb)) part_lane[front ? jb : ja] = R;
+        if (want_max) {
+          const float mxa = wave_max63(wa);
+          const float mxb = wave_max63(wb);
+          if (lane == 63) {
+            part[wave][9][ja] = mxa;
+            if (hb) part[wave][9][jb] = mxb;
+          }
+        }
       }
     }
     __syncthreads();
-    if (tid >= j0 && tid < j1) {
+    if (tid >= j0 && tid < j0 + kSub && tid < n) {
       const int js = tid - j0;
-      float m[9], o[12];
+      float m9[9], o[12];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) m[q] = ((part[0][q][js] + part[1][q][js]) + part[2][q][js]) + part[3][q][js];
+      for (int q = 0; q < 9; ++q) m9[q] = ((part[0][q][js] + part[1][q][js]) + part[2][q][js]) + part[3][q][js];
       const float4 A = mine.a, B = mine.b;  // the conic unscaled
-      o[0] = -fmaf(A.z, m[0], A.w * m[1]);
-      o[1] = -fmaf(A.w, m[0], B.x * m[1]);
-      o[2] = -0.5f * m[2];
-      o[3] = -m[3];
-      o[4] = -0.5f * m[4];
-      o[5] = B.y > 0.f ? m[5] / B.y : 0.f;
-      o[6] = m[6];
-      o[7] = m[7];
-      o[8] = m[8];
+      o[0] = -fmaf(A.z, m9[0], A.w * m9[1]);
+      o[1] = -fmaf(A.w, m9[0], B.x * m9[1]);
+      o[2] = -0.5f * m9[2];
+      o[3] = -m9[3];
+      o[4] = -0.5f * m9[4];
+      o[5] = B.y > 0.f ? m9[5] / B.y : 0.f;
+      o[6] = m9[6];
+      o[7] = m9[7];
+      o[8] = m9[8];
       o[9] = fmaxf(fmaxf(part[0][9][js], part[1][9][js]), fmaxf(part[2][9][js], part[3][9][js]));
       o[10] = 0.f;
       o[11] = 0.f;
