@@ -135,7 +135,12 @@ typedef struct {
  *   offsets     uint32[R+1]   first pair (emission order) of each record;
  *                             offsets[R] = pair count
  *   pair_vals   uint32[2][P]  sorted record ids; which half holds the result
- *                             is recorded on the device in *sort_sel
+ *                             is recorded on the device in *sort_sel.  A
+ *                             forward with checkpoints leaves in the other
+ *                             half, as uint16[P], each sorted pair's mask of
+ *                             the 4 x 4-pixel blocks of its tile that its
+ *                             ellipse reaches (bit 4 row + column), for the
+ *                             backward
  *   sort_sel    uint32[1]
  *   pair_emit   uint32[P]     emission index of each sorted pair
  *   ranges      uint32[X][2]  [start, end) of each tile's pairs

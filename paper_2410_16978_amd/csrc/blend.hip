@@ -532,7 +532,10 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
             float* __restrict__ g_pair, uint8_t* __restrict__ alive, int want_max) {
   __shared__ BatchLds L;
   constexpr int kSub = 64;  // pairs whose wave partials are held in LDS at a time
-  __shared__ float part[4][kGradSlots][kSub];
+  // one float of padding per row: the nine lanes that store a pair's sums
+  // write rows q_lane = 0..8 at one column, which then fall in different banks
+  constexpr int kSubPad = kSub + 1;
+  __shared__ float part[4][kGradSlots][kSubPad];
   __shared__ uint16_t s_blk[kBatch];  // block masks the forward left
   // block b takes the b-th batch of the heaviest-first order: the first wave
   // scans the class counts and finds b's class
@@ -623,7 +626,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
   }
   uint32_t my_emit = tid < n ? pair_emit[start + tid] : 0u;
   if (my_emit >= cap) my_emit = 0;  // never write out of range (an inconsistent sort shows up as wrong gradients)
-  for (int i = tid; i < 4 * kGradSlots * kSub; i += 256) (&part[0][0][0])[i] = 0.f;
+  for (int i = tid; i < 4 * kGradSlots * kSubPad; i += 256) (&part[0][0][0])[i] = 0.f;
   // the wave's 8 x 8 quadrant: 2 x 2 of the tile's 4 x 4 blocks
   const uint32_t qmask = 0x33u << (2 * (wave & 1) + 8 * (wave >> 1));
   // the wave's reach: no pair at or behind its pixels' last blended pair counts
@@ -765,7 +768,7 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       alive[my_emit] = 1;
     }
     __syncthreads();
-    for (int i = tid; i < 4 * kGradSlots * kSub; i += 256) (&part[0][0][0])[i] = 0.f;
+    for (int i = tid; i < 4 * kGradSlots * kSubPad; i += 256) (&part[0][0][0])[i] = 0.f;
     __syncthreads();
   }
 }
