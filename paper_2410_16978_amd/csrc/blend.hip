@@ -159,11 +159,17 @@ __device__ __forceinline__ int wave_list(const uint8_t* nib_row, int col, uint8_
 
 // Base-2 exponent kPowScale q of one pair at a pixel offset (dx, dy) =
 // centre - pixel, q = a dx^2 + 2 b dx dy + c dy^2 from the staged conic;
-// G = 2^power.  This file is compiled without implicit FMA contraction, so
-// the forward and the backward evaluate this (and alpha) with the same
-// instructions and take the same skip decisions.  power <= 0 is q >= 0.
+// G = 2^power.  q is rounded exactly as its plain left-to-right evaluation
+// is - (a dx) dx + (c dy) dy first, then + (2b dx) dy, no fused operations -
+// which is also the reference's order: for a thin splat q is a small
+// difference of terms thousands of times larger, and any other order rounds
+// it differently by enough to move alpha across the 1/255 cut-off.  This file
+// is compiled without implicit FMA contraction, so the forward and the
+// backward evaluate this (and alpha) with the same instructions and take
+// the same skip decisions.  power <= 0 is q >= 0.
 __device__ __forceinline__ float pair_power(const float4 A, const float4 B, float dx, float dy) {
-  return kPowScale * fmaf(A.z * dx, dx, fmaf(B.x * dy, dy, A.w * (dx * dy)));
+  const float qa = (A.z * dx) * dx, qc = (B.x * dy) * dy, qb = (A.w * dx) * dy;
+  return kPowScale * ((qa + qc) + qb);
 }
 
 __device__ __forceinline__ float pair_gauss(float power) { return __builtin_amdgcn_exp2f(power); }

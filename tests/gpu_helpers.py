@@ -23,7 +23,7 @@ def oracle_rect_to_box(rect, depth, tile_off, tiles_x):
                      np.full_like(base, tiles_x)], 1).astype(np.uint32)
 
 
-def compare_forward(scene, cams, views, orc, check_pairs=True, label=""):
+def compare_forward(scene, cams, views, orc, check_pairs=True, label="", max_flagged=None):
     """Run both paths and assert the parity bar; returns a stats dict.  With
     a shared depth order (views[0]["sort_cam"]) the oracle sorts every view
     by the depth in that camera and the emission order differs by design
@@ -83,16 +83,18 @@ def compare_forward(scene, cams, views, orc, check_pairs=True, label=""):
         rg = st.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)[:len(ref["ranges"])]
         np.testing.assert_array_equal(rg, ref["ranges"], err_msg=f"{label} tile ranges")
     last = st.last.cpu().numpy().view(np.uint32).reshape(V, H, W)
-    stats = assert_images(rgb, alpha, ref, label, last=last)
+    stats = assert_images(rgb, alpha, ref, label, last=last, max_flagged=max_flagged)
     stats["K"] = K
     return stats
 
 
-def assert_images(rgb, alpha, ref, label="", last=None):
+def assert_images(rgb, alpha, ref, label="", last=None, max_flagged=None):
     """Images within IMAGE_TOL max-abs on every pixel whose oracle decision
     margin is >= 1 (no threshold within the rounding tolerance); at most
-    max(2, 1e-3 * pixels) pixels may be flagged.  `last` (optional) must equal
-    the oracle's last blended index on the unflagged pixels."""
+    max_flagged pixels may be flagged (default max(2, 1e-3 * pixels); the
+    full-size tests pass the count measured for their scene, the oracle's
+    margins being deterministic).  `last` (optional) must equal the oracle's
+    last blended index on the unflagged pixels."""
     flag = ref["margin"] < 1.0
     g_rgb = rgb.cpu().numpy() if hasattr(rgb, "cpu") else np.asarray(rgb)
     g_alpha = alpha.cpu().numpy() if hasattr(alpha, "cpu") else np.asarray(alpha)
@@ -105,7 +107,8 @@ def assert_images(rgb, alpha, ref, label="", last=None):
         mism_last = int(((last != ref["last"]) & ok).sum())
         assert mism_last == 0, f"{label} last index differs on {mism_last} pixels"
     n_flag = int(flag.sum())
-    assert n_flag <= max(2, 1e-3 * flag.size), f"{label} too many threshold-near pixels {n_flag}"
+    cap = max(2, 1e-3 * flag.size) if max_flagged is None else max_flagged
+    assert n_flag <= cap, f"{label} too many threshold-near pixels {n_flag} (cap {cap})"
     return {"max_err": max_err, "flagged": n_flag, "pixels": int(flag.size),
             "max_err_all": max(float(err_rgb.max()), float(err_a.max()))}
 
@@ -195,12 +198,13 @@ def assert_grad_close(got, ref, sens, name, exempt=None, ref32=None):
     return misses
 
 
-def checked_exempt(orc, scene, cams, views, rgb, alpha, last, final_T, label="", cap=0.01):
+def checked_exempt(orc, scene, cams, views, rgb, alpha, last, final_T, label="", cap=0.01, max_flagged=None):
     """Forward parity first (images and last index on the unflagged pixels,
     see assert_images), then the flip exemption, capped at max(2, cap * n)
     Gaussians."""
     ref_fwd = orc.render(scene, cams, views, pairs=True)
-    assert_images(rgb, alpha, ref_fwd, label, last=np.asarray(last).reshape(ref_fwd["last"].shape))
+    assert_images(rgb, alpha, ref_fwd, label, last=np.asarray(last).reshape(ref_fwd["last"].shape),
+                  max_flagged=max_flagged)
     n = scene["mean"].shape[1]
     ex = flip_exempt(ref_fwd, n, last, final_T)
     print(f"{label} exempt Gaussians: {int(ex.sum())} of {n}", flush=True)

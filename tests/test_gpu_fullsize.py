@@ -22,6 +22,12 @@ from tests.gpu_helpers import SENS_K, assert_grad_close, assert_images, checked_
 
 pytestmark = pytest.mark.gpu
 
+# threshold-near pixels (oracle decision margin < 1), measured on these
+# scenes (the oracle's margins are deterministic): the image bar holds on
+# every other pixel, and no more pixels than these may be flagged
+C2_FLAGGED = 183
+STEREO_1M_FLAGGED = 2033
+
 
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
@@ -38,7 +44,7 @@ def c2():
 
 
 def test_training_step_200k_forward(c2, orc):
-    st = compare_forward(c2.scene, c2.cams, c2.views, orc, label="200k")
+    st = compare_forward(c2.scene, c2.cams, c2.views, orc, label="200k", max_flagged=C2_FLAGGED)
     print("200k forward:", st, flush=True)
 
 
@@ -98,7 +104,7 @@ def c2_grads(c2, orc):
              "opacity_logit": o * (1 - o), "sh": 1.0}
     st = rctx.state
     ex = checked_exempt(orc, act, cams, vss, rgb.detach(), alpha.detach(), st.last.cpu().numpy().view(np.uint32),
-                        st.final_T.cpu().numpy(), "200k step")
+                        st.final_T.cpu().numpy(), "200k step", max_flagged=C2_FLAGGED)
     return {"Gr": Gr, "Ga": Ga, "got": got, "max_contrib": rctx.max_contrib.cpu().numpy(), "exempt": ex,
             "ref": {k: ref[SRC[k]] * chain[k] for k in KEYS},
             "sens": {k: sens[SRC[k]] * chain[k] for k in KEYS},
@@ -179,7 +185,7 @@ def test_training_step_200k_central_differences(c2, c2_grads, orc):
 
 def test_layered_stereo_1m(orc):
     w = scenes.layered_stereo()
-    st = compare_forward(w.scene, w.cams, w.views, orc, label="stereo 1M")
+    st = compare_forward(w.scene, w.cams, w.views, orc, label="stereo 1M", max_flagged=STEREO_1M_FLAGGED)
     print("stereo 1M:", st, flush=True)
 
 
