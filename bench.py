@@ -238,42 +238,76 @@ def bench_plain_forward(rz, scenes, torch, frames=1000, warmup=50):
             "stage_us_per_frame": stages}
 
 
-def bench_serving(rz, scenes, torch, seconds, rate):
+def bench_serving(rz, scenes, torch, seconds, rates=(200.0,), budgets=(16 << 30,), saturation=True):
     """Serving: resident models of 500k and 2M Gaussians (5 layers, SH3);
     open-loop Poisson requests (resolution 512^2, 1024^2 or stereo
     1832x1920, random layer mask and clip planes).  Continuous batching
     (arrival-order admission into batched launches on two streams) vs the
-    plain path (one request per launch, one stream) on the same trace, then
-    the same requests all at once (saturation throughput)."""
+    plain path (one request per launch, one stream) on the same trace, per
+    HBM budget and arrival rate; optionally the same requests all at once
+    (saturation throughput).  Each slot's workspace is allocated once at
+    the budget and frames are dropped on completion (no device allocation
+    while serving: each slot's images are carved from an arena allocated
+    once); the cyclic garbage collector is paused during the timed runs (as
+    a latency-critical server would run it); the device-busy fraction is the
+    union of the launches' device intervals over their span; the five
+    slowest requests are listed with their admission delay, batch size and
+    launch host time."""
+    import gc
     from paper_2410_16978_amd.serve import GpuExecutor, Scheduler, requests_from_trace
     models = [rz.to_device(m) for m in scenes.serving_models()]
-    trace = scenes.poisson_trace(rate, seconds, seed=0)
     ex0 = GpuExecutor(models, slots=2)
-    ex0.calibrate(requests_from_trace(trace))
+    for rate in rates:
+        ex0.calibrate(requests_from_trace(scenes.poisson_trace(rate, seconds, seed=0)))
     table = ex0.pair_table
-    budget = 16 << 30
-    res = {"models": [500_000, 2_000_000], "rate_hz": rate, "trace_s": seconds, "requests": len(trace)}
-    for mode in ("open_loop", "saturation"):
+    del ex0
+    res = {"models": [500_000, 2_000_000], "trace_s": seconds, "runs": []}
+    plans = [("open_loop", budget, rate) for budget in budgets for rate in rates]
+    if saturation:
+        plans.append(("saturation", budgets[-1], rates[0]))
+    for mode, budget, rate in plans:
+        trace = scenes.poisson_trace(rate, seconds, seed=0)
+        entry = {"mode": mode, "budget_gib": budget / (1 << 30), "rate_hz": rate, "requests": len(trace)}
+        max_pix = max(sum(c["width"] * c["height"] for c in t["cams"]) for t in trace)
         for name, batched in (("batched", True), ("plain", False)):
+            # a batch's workspace can exceed the sum of its requests' costs a
+            # little (per-call sort words): the slots get a quarter more
+            ex = GpuExecutor(models, slots=2 if batched else 1, pair_table=table, ws_bytes=budget * 5 // 4,
+                             keep_results=False, out_pixels=(16 if batched else 1) * max_pix)
+            warm = requests_from_trace(trace[:400])
+            if mode == "saturation":
+                for r in warm:
+                    r.arrival = 0.0
+            Scheduler(ex, budget, max_batch=16, batched=batched).run(warm)
+            torch.cuda.synchronize()
+            ex.busy_fraction()
             reqs = requests_from_trace(trace)
             if mode == "saturation":
                 for r in reqs:
                     r.arrival = 0.0
-            ex = GpuExecutor(models, slots=2 if batched else 1, pair_table=table)
-            # warm up on the whole trace: the slots' workspaces reach their final size outside the timing
-            Scheduler(ex, budget, max_batch=16, batched=batched).run(reqs)
-            reqs = requests_from_trace(trace)
-            if mode == "saturation":
-                for r in reqs:
-                    r.arrival = 0.0
-            torch.cuda.synchronize()
-            stats = Scheduler(ex, budget, max_batch=16, batched=batched).run(reqs)
-            torch.cuda.synchronize()
+            regrows0 = ex.regrows
+            gc.collect()
+            gc.disable()
+            try:
+                stats = Scheduler(ex, budget, max_batch=16, batched=batched).run(reqs)
+                torch.cuda.synchronize()
+            finally:
+                gc.enable()
             sm = stats.summary()
-            res.setdefault(mode, {})[name] = {k: sm[k] for k in ("p50_ms", "p99_ms", "frames_per_s", "mpix_per_s",
-                                                                  "launches", "reruns")}
+            out = {k: sm[k] for k in ("p50_ms", "p99_ms", "frames_per_s", "mpix_per_s", "launches", "reruns")}
+            out["device_busy"] = round(ex.busy_fraction(), 3)
+            out["workspace_regrows"] = ex.regrows - regrows0
+            slow = sorted((r for r in reqs if r.status == 0), key=lambda r: r.arrival - r.done)[:5]
+            out["slowest"] = [{"latency_ms": round((r.done - r.arrival) * 1e3, 2),
+                               "admit_delay_ms": round((r.admitted - r.arrival) * 1e3, 2), "batch": r.batch,
+                               "launch_host_ms": round(r.launch_ms, 2), "pixels": r.pixels} for r in slow]
             if any(r.status != 0 for r in reqs):
-                res.setdefault(mode, {})[name]["failed"] = sum(r.status != 0 for r in reqs)
+                out["failed"] = sum(r.status != 0 for r in reqs)
+            entry[name] = out
+            print(f"serving {mode} budget {budget >> 30} GiB rate {rate:g}/s {name}: p50 {out['p50_ms']} ms, "
+                  f"p99 {out['p99_ms']} ms, busy {out['device_busy']}", file=sys.stderr, flush=True)
+            del ex
+        res["runs"].append(entry)
     return res
 
 
@@ -368,10 +402,12 @@ def main():
                     help="skip the layered-stereo and serving measurements (profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving trace")
     ap.add_argument("--workload", default="training_step_200k",
-                    choices=["training_step_200k", "layered_training_4m", "layered_stereo_1m"],
+                    choices=["training_step_200k", "layered_training_4m", "layered_stereo_1m", "serving_c4"],
                     help="training_step_200k (default): the 200k/800x800 step; layered_training_4m: 4M Gaussians, "
                          "8 views of 1024^2 per step, pruning every 100 steps; layered_stereo_1m: only the layered "
-                         "stereo frames (1M Gaussians, 2 x 1832x1920; profiling runs)")
+                         "stereo frames (1M Gaussians, 2 x 1832x1920; profiling runs); serving_c4: the serving "
+                         "trace of --serve-seconds (30 by default here) at 200 and 800 requests/s under 2 GiB and "
+                         "16 GiB budgets")
     ap.add_argument("--train-steps", type=int, default=200, help="steps of the layered_training_4m workload")
     ap.add_argument("--extra-train-steps", type=int, default=50,
                     help="steps of the layered_training_4m entry of the default run (0: left out)")
@@ -407,6 +443,11 @@ def main():
         return
     if args.workload == "layered_stereo_1m":
         print(json.dumps(bench_stereo(rz, scenes, torch, frames=args.steps, warmup=args.warmup)), flush=True)
+        return
+    if args.workload == "serving_c4":
+        secs = args.serve_seconds if "--serve-seconds" in sys.argv else 30.0
+        print(json.dumps(bench_serving(rz, scenes, torch, secs, rates=(200.0, 800.0), budgets=(2 << 30, 16 << 30),
+                                       saturation=False)), flush=True)
         return
     wl = scenes.training_step_200k(seed=0)
     sc = wl.scene
@@ -557,7 +598,7 @@ def main():
         result["plain_forward_4k_128px"] = bench_plain_forward(rz, scenes, torch)
         result["stereo_render"] = bench_stereo(rz, scenes, torch, frames=max(10, min(args.steps, 50)),
                                                warmup=max(2, min(args.warmup, 5)))
-        result["serving"] = bench_serving(rz, scenes, torch, args.serve_seconds, 200.0)
+        result["serving"] = bench_serving(rz, scenes, torch, args.serve_seconds, rates=(200.0, 800.0))
         if args.extra_train_steps > 0:
             sub = argparse.Namespace(warmup=3, train_steps=args.extra_train_steps)
             lt = bench_layered_training(sub, torch, rz, ag, scenes)

@@ -162,7 +162,8 @@ int tile_pass_end(uint64_t total_tiles) {
 }
 
 // The views array goes to the device in the arguments of the clear launch
-// when it is small enough (one launch, no copy), else by a copy.
+// when it is small enough (one launch), else in upload launches of their own;
+// never by a copy from pageable host memory.
 hipError_t upload_views(ViewD* dst, const ViewD* src, int n_views, WordUpload& up, hipStream_t s) {
   const size_t bytes = sizeof(ViewD) * (size_t)n_views;
   up.dst = nullptr;
@@ -173,7 +174,7 @@ hipError_t upload_views(ViewD* dst, const ViewD* src, int n_views, WordUpload& u
     std::memcpy(up.w, src, bytes);
     return hipSuccess;
   }
-  return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  return launch_upload(reinterpret_cast<uint32_t*>(dst), src, bytes / 4, s);
 }
 
 hipError_t clear_workspace(const PipeBufs& b, uint32_t* counters, bool sticky_flags, uint32_t* ranges, size_t X,
@@ -828,7 +829,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
   }
   WordUpload up;
   HIP_TRY(upload_views(b.views, bp.views.data(), n_views, up, s));
-  HIP_TRY(hipMemcpyAsync(b.req_rec, bp.req_rec.data(), 4 * (n_req + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_upload(b.req_rec, bp.req_rec.data(), (size_t)n_req + 1, s));
   HIP_TRY(clear_workspace(b, b.counters, false, b.ranges, bp.X, R, P, b.sel, s, &up, nullptr, 0, n_sort));
   if (bp.ordered) HIP_TRY(launch_set_u32(&b.gwords[0], n_sort, s));
   {

@@ -157,6 +157,7 @@ struct WordUpload {
   uint32_t w[kUploadWords];
 };
 hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s, const WordUpload* up = nullptr);
+hipError_t launch_upload(uint32_t* dst, const void* src, size_t n_words, hipStream_t s);
 hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out, hipStream_t s);
 hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,

@@ -2,6 +2,9 @@
 // colour, tile box).  Compiled with -ffp-contract=off: every expression is
 // evaluated as written, each + - * / sqrt correctly rounded, so the records,
 // tile boxes and depth keys are reproducible bit for bit.
+#include <algorithm>
+#include <cstring>
+
 #include "common.hpp"
 
 #include <cstddef>
@@ -79,6 +82,25 @@ hipError_t launch_clear_multi(const ClearSet& cs, hipStream_t s, const WordUploa
   const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
   hipLaunchKernelGGL(k_clear_multi, dim3(grid), dim3(256), 0, s, cs, u);
   return hipGetLastError();
+}
+
+// Host words to the device carried in kernel arguments, kUploadWords at a
+// time (no copy from pageable host memory, which the runtime may stage
+// synchronously): stream-ordered like any launch.
+hipError_t launch_upload(uint32_t* dst, const void* src, size_t n_words, hipStream_t s) {
+  const uint32_t* w = static_cast<const uint32_t*>(src);
+  ClearSet none{};
+  none.n_ranges = 0;
+  for (size_t k = 0; k < n_words; k += kUploadWords) {
+    WordUpload u;
+    u.dst = dst + k;
+    u.n = (uint32_t)std::min<size_t>(kUploadWords, n_words - k);
+    std::memcpy(u.w, w + k, 4 * (size_t)u.n);
+    hipLaunchKernelGGL(k_clear_multi, dim3(1), dim3(256), 0, s, none, u);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 __global__ void __launch_bounds__(256) k_activate(ModelD m, float* __restrict__ scale_out,

@@ -37,6 +37,8 @@ class Request:
     admitted: float = math.nan
     done: float = math.nan
     status: int = 1          # 1 pending, 0 ok, <0 error
+    batch: int = 0           # requests in the launch that rendered it
+    launch_ms: float = math.nan  # host time of that launch call
 
     @property
     def pixels(self):
@@ -154,9 +156,10 @@ class Scheduler:
                 if not batch:
                     break
                 tnow = ex.now() - t0
-                for r in batch:
-                    r.admitted = tnow
                 h = ex.launch(batch)
+                t_l = (ex.now() - t0 - tnow) * 1e3
+                for r in batch:
+                    r.admitted, r.batch, r.launch_ms = tnow, len(batch), t_l
                 launches += 1
                 used += nbytes
                 max_used = max(max_used, used)
@@ -206,9 +209,23 @@ class SimExecutor:
 
 
 class GpuExecutor:
-    """Drives gsr_render_batch on `slots` streams over resident models."""
+    """Drives gsr_render_batch on `slots` streams over resident models.
 
-    def __init__(self, models, slots=2, pair_table=None, safety=1.3, device="cuda", timer=None):
+    ws_bytes: each slot's workspace is allocated once at that size (a
+    launch whose batch needs more regrows it; `regrows` counts those), so
+    that no device allocation happens while serving; a request's budget cost
+    is the workspace of a batch holding it alone (the library's own size
+    function) plus its images.  out_pixels: each slot carves its requests'
+    images from an arena of that many pixels allocated once (the images of a
+    launch stay valid until its slot's next launch; a batch that does not
+    fit gets fresh tensors).  keep_results=False drops a request's images
+    when its launch completes (a server hands them on).
+    Every launch records HIP events around itself on its stream, so that the
+    device-busy time (the union of the launches' intervals) can be measured
+    (busy_fraction)."""
+
+    def __init__(self, models, slots=2, pair_table=None, safety=1.3, device="cuda", timer=None, ws_bytes=None,
+                 keep_results=True, out_pixels=None):
         import torch
         from . import rasterizer as rz
         self.torch, self.rz = torch, rz
@@ -220,8 +237,18 @@ class GpuExecutor:
         self.safety = safety
         self.device = device
         self.ws = [None] * slots
+        if ws_bytes:
+            self.ws = [torch.empty(int(ws_bytes), dtype=torch.uint8, device=device) for _ in range(slots)]
         self.status = [None] * slots
+        self.arena = [None] * slots
+        if out_pixels:
+            self.arena = [torch.empty(4 * int(out_pixels), dtype=torch.float32, device=device) for _ in range(slots)]
+        self.mstructs = None
+        self._cost = {}
         self.timer = timer
+        self.keep_results = keep_results
+        self.regrows = 0
+        self.intervals = []  # (start event, end event) per launch
         self.n = [int(m["layer"].shape[0]) for m in models]
 
     def now(self):
@@ -242,11 +269,22 @@ class GpuExecutor:
         return est
 
     def cost(self, r):
-        # workspace of the request's share of a batch + its outputs
-        pix = r.pixels
-        tiles = sum(((c["width"] + 15) // 16) * ((c["height"] + 15) // 16) for c in r.cams)
-        recs = self.n[r.model] * len(r.cams)
-        return recs * (4 + 4 + 16 + 48) + self.pairs_estimate(r) * 24 + pix * (4 + 4 + 16) + tiles * 8 + 4096
+        # the workspace of a batch holding this request alone, plus its images
+        key = (r.model, tuple((c["width"], c["height"]) for c in r.cams), r.tries)
+        c = self._cost.get(key)
+        if c is None:
+            rz = self.rz
+            if self.mstructs is None:
+                self.mstructs = (rz.Model * len(self.models))(*[rz.model_struct(m) for m in self.models])
+            q = rz.Request()
+            q.model = int(r.model)
+            q.n_views = len(r.cams)
+            for e, cam in enumerate(r.cams):
+                q.cam[e] = rz.camera_struct(cam)
+            q.vs = rz.view_struct(r.view)
+            c = rz.batch_workspace_size(self.mstructs, (rz.Request * 1)(q), self.pairs_estimate(r)) + 16 * r.pixels
+            self._cost[key] = c
+        return c
 
     def calibrate(self, reqs):
         """Measure the pair count of one view per (model, resolution)."""
@@ -265,19 +303,59 @@ class GpuExecutor:
         s = self.streams[slot]
         cap = sum(self.pairs_estimate(r) for r in reqs)
         reqd = [{"model": r.model, "cams": r.cams, "view": r.view} for r in reqs]
+        outputs = None
+        arena = self.arena[slot]
+        if arena is not None and 4 * sum(r.pixels for r in reqs) <= arena.numel():
+            outputs, off = [], 0
+            for r in reqs:
+                rgbs, alphas = [], []
+                for c in r.cams:
+                    H, W = c["height"], c["width"]
+                    rgbs.append(arena[off:off + 3 * H * W].view(3, H, W))
+                    alphas.append(arena[off + 3 * H * W:off + 4 * H * W].view(H, W))
+                    off += 4 * H * W
+                outputs.append((rgbs, alphas))
         with torch.cuda.stream(s):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev0.record(s)
             outs, status, ws = rz.render_batch(self.models, reqd, cap, workspace=self.ws[slot],
-                                               status=self.status[slot], stream=s, timer=self.timer)
-            ev = torch.cuda.Event()
+                                               status=self.status[slot], outputs=outputs, stream=s,
+                                               timer=self.timer)
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
+        if self.ws[slot] is not None and ws is not self.ws[slot]:
+            self.regrows += 1
         self.ws[slot], self.status[slot] = ws, status
+        self.intervals.append((ev0, ev))
         return {"slot": slot, "event": ev, "outs": outs, "status": status, "n": len(reqs), "reqs": reqs}
 
     def poll(self, h):
         if not h["event"].query():
             return None
         st = h["status"][:h["n"]].cpu().tolist()
-        for r, o in zip(h["reqs"], h["outs"]):
-            r.result = o
+        if self.keep_results:
+            for r, o in zip(h["reqs"], h["outs"]):
+                r.result = o
+        h["outs"] = None
         self.free_streams.append(h["slot"])
         return st
+
+    def busy_fraction(self):
+        """Fraction of the span from the first launch's start to the last
+        launch's end during which at least one launch was on the device
+        (call after the work has completed); clears the interval log."""
+        if not self.intervals:
+            return 0.0
+        ref = self.intervals[0][0]
+        iv = sorted((ref.elapsed_time(a), ref.elapsed_time(b)) for a, b in self.intervals)
+        self.intervals = []
+        busy, cur_s, cur_e = 0.0, iv[0][0], iv[0][1]
+        for a, b in iv[1:]:
+            if a > cur_e:
+                busy += cur_e - cur_s
+                cur_s, cur_e = a, b
+            else:
+                cur_e = max(cur_e, b)
+        busy += cur_e - cur_s
+        span = max(b for _, b in iv) - iv[0][0]
+        return busy / span if span > 0 else 0.0
