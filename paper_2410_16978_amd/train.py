@@ -179,6 +179,15 @@ class LayeredTrainer:
         arrays["meta"] = np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8)
         np.savez(path, **arrays)
 
+    def export_ply(self, path):
+        """The model as one layered PLY (the layer of each Gaussian a vertex
+        property, Sec. 3.2; see ply.py)."""
+        from . import ply, scenes
+        p = {k: v.detach().cpu().numpy() for k, v in self.params.items()}
+        sc = scenes._finish(p["mean"], p["log_scale"], p["quat"], p["opacity_logit"], p["sh"],
+                            self.layer.cpu().numpy())
+        ply.write_ply(path, sc)
+
     def load(self, path):
         z = np.load(path, allow_pickle=False)
         for k in PARAM_KEYS:

@@ -81,3 +81,22 @@ def test_checkpoint_resume(tmp_path):
     # the backward has no atomics: resuming reproduces the run bit for bit
     for k in a.params:
         np.testing.assert_array_equal(a.params[k].detach().cpu().numpy(), b.params[k].detach().cpu().numpy())
+
+
+def test_export_ply_holds_the_trained_layered_model(tmp_path):
+    """The trainer's model exported as one layered PLY (Sec. 3.2) reads back
+    bit-exactly, layers included."""
+    import torch
+    from paper_2410_16978_amd import ply
+    from paper_2410_16978_amd.train import LayeredTrainer, PruneConfig
+    sc, cams, targets, _, _ = _setup(seed=2)
+    a = LayeredTrainer(sc, cams, targets, 0b10, views_per_step=2, prune=PruneConfig(interval=100), seed=3)
+    for _ in range(3):
+        a.step()
+    torch.cuda.synchronize()
+    path = tmp_path / "trained.ply"
+    a.export_ply(path)
+    back = ply.read_ply(path)
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "sh"):
+        np.testing.assert_array_equal(back[k], a.params[k].detach().cpu().numpy(), err_msg=k)
+    np.testing.assert_array_equal(back["layer"], a.layer.cpu().numpy())
