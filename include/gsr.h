@@ -107,6 +107,14 @@ typedef struct {
    * unsigned integer (ties: ascending Gaussian index). */
   int32_t sort_shared;
   gsr_camera sort_cam;
+  /* Per-layer opacity at render time (Sec. 1: layers shown with variable
+   * opacity; Sec. 5: fading between layers).  0: off.  1: a Gaussian of
+   * layer l is drawn with opacity o * layer_opacity[l] (its record holds
+   * that product, a product below 1/255 culls it like any too transparent
+   * Gaussian, and the backward's opacity gradient is with respect to o,
+   * i.e. layer_opacity[l] times that of the product).  Factors in [0, 1]. */
+  int32_t layer_fade;
+  float layer_opacity[32];
 } gsr_view_state;
 
 /* Gaussian arrays (device, structure of arrays, see above; host struct). */

@@ -28,7 +28,8 @@ class Clip(C.Structure):
 
 
 class View(C.Structure):
-    _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", Clip * 8), ("bg", C.c_float * 3)]
+    _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", Clip * 8), ("bg", C.c_float * 3),
+                ("layer_fade", C.c_int32), ("layer_opacity", C.c_float * 32)]
 
 
 def _model_struct(ptr_t):
@@ -107,6 +108,10 @@ def view_struct(vs):
         v.clip[k].layer_bits = bits & 0xFFFFFFFF
     for j in range(3):
         v.bg[j] = float(vs["bg"][j])
+    if vs.get("layer_opacity") is not None:
+        v.layer_fade = 1
+        for l, f in enumerate(vs["layer_opacity"]):
+            v.layer_opacity[l] = float(f)
     return v
 
 

@@ -144,6 +144,7 @@ template <typename T> struct Proj {
   T a, b, c, det;
   // record
   T u, v, ca, cb, cc, op, rgb[3];
+  T fade = T(1);  // the view's opacity factor of the Gaussian's layer
   uint32_t clamp = 0;
   int rect[4] = {0, 0, 0, 0};
   uint32_t ntiles = 0;
@@ -174,6 +175,12 @@ Proj<T> project_one(const Model<T>& m, int i, const Cam<T>& cam, const oc_view& 
   p.tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + cam.t[2];
   if (!(p.tz > cam.znear)) return p;
   p.op = m.opacity[i];
+  // The view's opacity factor of the layer scales the opacity it is drawn
+  // with; a product below the blend's skip threshold draws nothing.
+  if (vs.layer_fade) {
+    p.fade = T(vs.layer_opacity[layer]);
+    p.op = p.op * p.fade;
+  }
   if (p.op < Consts<T>::alpha_min()) return p;
   // Unit quaternion (w, x, y, z) and its rotation matrix.
   T qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
@@ -599,8 +606,8 @@ void backward_gaussian(const Model<T>& m, int i, const Cam<T>& cam, const Proj<T
                        const T* g2, T* gm, T* gs, T* gq, T* go, T* gsh) {
   const int n = m.n;
   const T* W = cam.R;
-  // --- opacity
-  *go += g2[5];
+  // --- opacity: the record's opacity is o times the layer's factor
+  *go += p.fade * g2[5];
   // --- colour: SH coefficients and the view direction
   T drgb[3];
   for (int ch = 0; ch < 3; ++ch) drgb[ch] = ((p.clamp >> ch) & 1u) ? T(0) : g2[6 + ch];
@@ -712,7 +719,7 @@ template <typename TG, typename TF> Proj<TG> convert(const Proj<TF>& p) {
   q.J00 = TG(p.J00); q.J02 = TG(p.J02); q.J11 = TG(p.J11); q.J12 = TG(p.J12);
   for (int k = 0; k < 6; ++k) q.Tm[k] = TG(p.Tm[k]);
   q.a = TG(p.a); q.b = TG(p.b); q.c = TG(p.c); q.det = TG(p.det);
-  q.u = TG(p.u); q.v = TG(p.v); q.ca = TG(p.ca); q.cb = TG(p.cb); q.cc = TG(p.cc); q.op = TG(p.op);
+  q.u = TG(p.u); q.v = TG(p.v); q.ca = TG(p.ca); q.cb = TG(p.cb); q.cc = TG(p.cc); q.op = TG(p.op); q.fade = TG(p.fade);
   for (int k = 0; k < 3; ++k) q.rgb[k] = TG(p.rgb[k]);
   q.clamp = p.clamp;
   for (int k = 0; k < 4; ++k) q.rect[k] = p.rect[k];

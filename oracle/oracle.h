@@ -50,6 +50,11 @@ typedef struct {
   int32_t n_clip;
   oc_clip clip[8];
   float bg[3];
+  /* per-layer opacity (layers shown at variable opacity, Sec. 1; fading
+   * between layers, Sec. 5): when layer_fade is non-zero a Gaussian of layer
+   * l is drawn with opacity o * layer_opacity[l]; zero leaves o alone */
+  int32_t layer_fade;
+  float layer_opacity[32];
 } oc_view;
 
 /* Gaussian arrays, structure of arrays.  mean[3][n], scale[3][n] (activated),

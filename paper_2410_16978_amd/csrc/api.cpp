@@ -291,6 +291,7 @@ ViewD make_view(const gsr_camera& c, const gsr_view_state& vs) {
     v.clip[k].bits = vs.clip[k].layer_bits;
   }
   for (int j = 0; j < 3; ++j) v.bg[j] = vs.bg[j];
+  for (int l = 0; l < 32; ++l) v.layer_op[l] = vs.layer_fade ? vs.layer_opacity[l] : 1.f;
   return v;
 }
 

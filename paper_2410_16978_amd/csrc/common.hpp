@@ -75,6 +75,7 @@ struct ViewD {
   uint32_t sort_lead;
   float sort_r[3];
   float sort_t;
+  float layer_op[32];  // opacity factor per layer (1 when the view has no fading)
 };
 constexpr uint32_t kSortNone = 0, kSortOwn = 1, kSortCamera = 2, kSortFollow = 3;
 

@@ -162,7 +162,8 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const float ty = ((W[3] * mx + W[4] * my) + W[5] * mz) + V.t[1];
       const float tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + V.t[2];
       if (!(tz > V.znear)) break;
-      if (op < kAlphaMin) break;
+      const float opv = op * V.layer_op[layer];  // the view's fading of the layer
+      if (opv < kAlphaMin) break;
       if (qn < 0.f) {
         float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
         qn = sqrt_rn(((qw * qw + qx * qx) + qy * qy) + qz * qz);
@@ -265,7 +266,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       }
       float4* rec = reinterpret_cast<float4*>(records + (size_t)r * kRecordFloats);
       rec[0] = make_float4(u, v, ca, cb);
-      rec[1] = make_float4(cc, op, rgb[0], rgb[1]);
+      rec[1] = make_float4(cc, opv, rgb[0], rgb[1]);
       rec[2] = make_float4(rgb[2], tz, __uint_as_float(clamp_bits), __uint_as_float(nt));
       const uint32_t base_tile = V.tile_off + (uint32_t)y0 * (uint32_t)V.tiles_x + (uint32_t)x0;
       tile_box[r] = make_uint4(base_tile, (uint32_t)(x1 - x0) | ((uint32_t)(y1 - y0) << 16),

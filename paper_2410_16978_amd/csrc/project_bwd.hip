@@ -121,7 +121,7 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
       const uint32_t clamp_bits = __float_as_uint(rec[10]);
       double g[9];
       record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
-      go += g[5];
+      go += g[5] * (double)V.layer_op[layer];  // the record holds o times the view's factor
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) g_col[(size_t)r * 3 + ch] = ((clamp_bits >> ch) & 1u) ? 0.f : (float)g[6 + ch];
       double W[9];

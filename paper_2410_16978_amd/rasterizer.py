@@ -53,7 +53,8 @@ class ClipPlane(C.Structure):
 
 class ViewState(C.Structure):
     _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", ClipPlane * MAX_CLIP),
-                ("bg", C.c_float * 3), ("sort_shared", C.c_int32), ("sort_cam", Camera)]
+                ("bg", C.c_float * 3), ("sort_shared", C.c_int32), ("sort_cam", Camera),
+                ("layer_fade", C.c_int32), ("layer_opacity", C.c_float * 32)]
 
 
 class Model(C.Structure):
@@ -189,6 +190,13 @@ def view_struct(vs):
     if vs.get("sort_cam") is not None:  # one depth order, in this camera, for all views of the call
         v.sort_shared = 1
         v.sort_cam = camera_struct(vs["sort_cam"])
+    fade = vs.get("layer_opacity")
+    if fade is not None:  # per-layer opacity factors of this view
+        if len(fade) > 32:
+            raise ValueError("at most 32 layer opacity factors")
+        v.layer_fade = 1
+        for l, f in enumerate(fade):
+            v.layer_opacity[l] = float(f)
     return v
 
 

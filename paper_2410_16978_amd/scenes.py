@@ -295,9 +295,12 @@ def camera_center(cam):
 # --------------------------------------------------------------------------
 # view state: layer-activation mask, clip planes, background
 # --------------------------------------------------------------------------
-def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0), sort_cam=None):
+def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0), sort_cam=None, layer_opacity=None):
     """sort_cam (optional): one depth order for all views of the call, the
-    depth in this camera (the eye centre of a stereo frame)."""
+    depth in this camera (the eye centre of a stereo frame).
+    layer_opacity (optional): up to 32 factors in [0, 1], one per layer; a
+    Gaussian of layer l is drawn with its opacity times factor l (layers not
+    listed keep factor 0)."""
     clips = list(clips)
     assert len(clips) <= MAX_CLIP
     vs = {
@@ -308,6 +311,10 @@ def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0), sort_cam=Non
     }
     if sort_cam is not None:
         vs["sort_cam"] = sort_cam
+    if layer_opacity is not None:
+        f = np.asarray(layer_opacity, np.float32).reshape(-1)
+        assert f.size <= 32 and np.all((f >= 0) & (f <= 1))
+        vs["layer_opacity"] = np.concatenate([f, np.zeros(32 - f.size, np.float32)])
     return vs
 
 

@@ -183,3 +183,15 @@ def test_backward_of_an_overwritten_forward_raises():
     rgb2.sum().backward()  # the latest forward's backward is fine
     torch.cuda.synchronize()
     assert torch.isfinite(params["mean"].grad).all()
+
+
+def test_gradients_with_layer_fading(orc):
+    sc, cams, _, Gr, Ga = _case(seed=21, D=2, n_views=2)
+    vss = [scenes.view_state(0b111, clips=[([0.2, 0.1, 1.0], 0.3, 0b1)], bg=(0.2, 0.3, 0.1),
+                             layer_opacity=[0.4, 1.0, 0.7]),
+           scenes.view_state(0b111, bg=(0.2, 0.3, 0.1), layer_opacity=[1.0, 0.25, 0.9])]
+    got = _gpu_grads(sc, cams, vss, Gr, Ga)
+    ref, sens, g32, ex = _refs(orc, sc, cams, vss, Gr, Ga, got, label="fading")
+    for k in ("mean", "scale", "quat", "opacity", "sh", "activity"):
+        assert_grad_close(got[k], ref[k], sens[k], k, ex, g32[k])
+    np.testing.assert_allclose(got["max_contrib"][~ex], ref["max_contrib"][~ex], rtol=1e-4, atol=1e-7)

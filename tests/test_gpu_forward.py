@@ -218,3 +218,15 @@ def test_invalid_arguments_rejected():
     model2["sh_degree"] = 4
     with pytest.raises(ValueError):
         rz.rasterize_forward(model2, w.cams, w.views)
+
+
+def test_layer_fading(orc):
+    """Per-layer opacity factors (fading between layers), one of them small
+    enough to push part of its layer below the 1/255 cut."""
+    sc = small_layered_scene(seed=12, n_per_layer=500, n_layers=4)
+    cams = [scenes.orbit_camera([0.2, 0.4, -1.0], 90, 66), scenes.orbit_camera([-0.3, 0.1, -1.0], 90, 66)]
+    scenes.enforce_distinct_depths(sc, cams)
+    vss = [scenes.view_state(0b1111, clips=[([0.3, -0.2, 0.9], 0.05, 0b0100)], bg=(0.1, 0.2, 0.3),
+                             layer_opacity=[1.0, 0.3, 0.012, 0.75]),
+           scenes.view_state(0b1011, layer_opacity=[0.0, 0.5, 1.0, 1.0])]
+    print("fading:", compare_forward(sc, cams, vss, orc, label="fading"))

@@ -384,3 +384,56 @@ def test_condition_bounds_the_entries_and_their_float32_rounding(orc):
         assert np.all(c >= 16 * np.abs(ex[k]) * (1 - 1e-12)), k
         assert np.all(np.abs(fv[k] - ex[k]) <= 2.0 ** -24 * c), k
         assert np.any(c > 0), k
+
+
+# ---------------------------------------------------------------- per-layer opacity (fading)
+FADE = [0.45, 0.8]
+
+
+def test_layer_fade_gradient_is_the_premultiplied_scenes(orc):
+    """Drawing with opacity o f is drawing the scene whose opacity is o' = o f:
+    every gradient but the opacity's is that scene's, and dL/do = f dL/do'."""
+    s64, cams, vss, Gr, Ga = _setup(seed=8, n_views=2)
+    vf = [scenes.view_state(0x3, bg=(0.2, 0.3, 0.1), layer_opacity=FADE)] * 2
+    pre = dict(s64)
+    # the factors as the view carries them (float32); o f is then exact in float64
+    f = np.asarray(FADE, np.float32).astype(np.float64)[s64["layer"].astype(np.int64)]
+    pre["opacity"] = s64["opacity"] * f
+    a = orc.backward(s64, cams, vf, Gr, Ga, dtype=np.float64)
+    b = orc.backward(pre, cams, vss, Gr, Ga, dtype=np.float64)
+    for k in ("mean", "scale", "quat", "sh", "max_contrib"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    np.testing.assert_allclose(a["opacity"], f * b["opacity"], rtol=1e-12, atol=1e-300)
+    assert np.any(a["opacity"] != 0)
+
+
+def test_layer_fade_opacity_gradient_matches_central_differences(orc):
+    s64, cams, vss, Gr, Ga = _setup(seed=9, n_views=1)
+    vf = [scenes.view_state(0x3, bg=(0.2, 0.3, 0.1), layer_opacity=FADE)]
+    s64["opacity"] = s64["opacity"].astype(np.float64)
+    g = orc.backward(s64, cams, vf, Gr, Ga, dtype=np.float64)
+    active = np.nonzero(g["max_contrib"] > 0.05)[0]
+    rng = np.random.default_rng(4)
+    checked = 0
+    for i in rng.permutation(active):
+        arr = s64["opacity"]
+        th = float(arr[i])
+        h = 1e-5
+
+        def f(val):
+            arr[i] = val
+            out = _loss(orc, s64, cams, vf, Gr, Ga)
+            arr[i] = th
+            return out
+
+        fd = (f(th + h) - f(th - h)) / (2 * h)
+        fd2 = (f(th + h / 2) - f(th - h / 2)) / h
+        if abs(fd - fd2) > 1e-2 * max(abs(fd), 1e-6):
+            continue  # crosses a threshold: take another
+        assert abs(g["opacity"][i] - fd) <= 1e-3 * max(abs(fd), 1e-4), (i, g["opacity"][i], fd)
+        checked += 1
+        if checked == 8:
+            break
+    assert checked == 8
+    # both layers were sampled
+    assert len(set(s64["layer"][active].tolist())) == 2

@@ -461,3 +461,61 @@ def test_parallel_eyes_share_the_per_eye_order(orc):
     sh = orc.render(sc, cams, vss, pairs=True, sort_cams=[centre, centre])
     for k in ("rgb", "alpha", "keys", "vals", "last"):
         np.testing.assert_array_equal(sh[k], own[k], err_msg=k)
+
+
+# ---------------------------------------------------------------- per-layer opacity (fading)
+def _premultiplied(sc, factors):
+    """The scene with each Gaussian's opacity multiplied by its layer's factor
+    (in float32 for a float32 scene, one rounding like the render's)."""
+    out = dict(sc)
+    f = np.asarray(factors, np.float32)[sc["layer"].astype(np.int64)]
+    out["opacity"] = (sc["opacity"] * f.astype(sc["opacity"].dtype)).astype(sc["opacity"].dtype)
+    return out
+
+
+def test_layer_fade_of_ones_is_no_fading(orc, layered):
+    sc, cam, vs = layered
+    a = orc.render(sc, [cam], [vs], pairs=True)
+    b = orc.render(sc, [cam], [scenes.view_state(vs["layer_mask"], vs["clips"], vs["bg"], layer_opacity=[1.0] * 32)],
+                   pairs=True)
+    for k in ("rgb", "alpha", "final_T", "rec", "keys", "vals"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_layer_fade_equals_premultiplied_opacity(orc, layered, dtype):
+    """Fading layer l by f draws the scene whose layer-l opacities are o f."""
+    sc, cam, vs = layered
+    fac = [0.35, 1.0, 0.6]
+    s = to64(sc) if dtype == np.float64 else sc
+    vf = scenes.view_state(vs["layer_mask"], vs["clips"], vs["bg"], layer_opacity=fac)
+    a = orc.render(s, [cam], [vf], dtype=dtype, pairs=True)
+    b = orc.render(_premultiplied(s, fac), [cam], [vs], dtype=dtype, pairs=True)
+    for k in ("rgb", "alpha", "final_T", "rec", "keys", "vals"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    # and the fading changed the image
+    assert np.abs(a["rgb"] - orc.render(s, [cam], [vs], dtype=dtype)["rgb"]).max() > 1e-3
+
+
+def test_layer_fade_to_zero_hides_the_layer(orc, layered):
+    """A factor of 0 takes every opacity below the 1/255 cut: the layer is
+    gone, exactly as if its mask bit were clear."""
+    sc, cam, vs = layered
+    vf = scenes.view_state(0b111, vs["clips"], vs["bg"], layer_opacity=[1.0, 0.0, 1.0])
+    a = orc.render(sc, [cam], [vf])
+    b = orc.render(sc, [cam], [scenes.view_state(0b101, vs["clips"], vs["bg"])])
+    np.testing.assert_array_equal(a["rgb"], b["rgb"])
+    np.testing.assert_array_equal(a["alpha"], b["alpha"])
+
+
+def test_layer_fade_monotone_in_the_factor(orc):
+    """One splat over a black background: its peak alpha is o f, clamped at
+    0.99, and zero below the 1/255 cut."""
+    sc = make_scene([[0.0, 0.0, 3.0]], [[0.05, 0.05, 0.05]], opacity=[0.8], rgb=[[1.0, 1.0, 1.0]])
+    cam = axis_camera(33, 33, f=80.0, cx=16.5, cy=16.5)
+    for f in (1.0, 0.5, 0.1, 0.004):
+        r = orc.render(to64(sc), [cam], [scenes.view_state(layer_opacity=[f])], dtype=np.float64)
+        peak = r["alpha"][0].max()
+        of = float(np.float32(0.8)) * float(np.float32(f))  # the float32 inputs, multiplied in float64
+        want = of if of >= 1 / 255 else 0.0
+        assert abs(peak - want) < 1e-9 * max(want, 1.0), (f, peak)
