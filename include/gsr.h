@@ -361,6 +361,26 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
                             int32_t n_req, uint32_t pair_capacity, void* ws, size_t ws_bytes,
                             int32_t* req_status, gsr_timer* timer, void* stream);
 
+/* Inactive-pruning activity from one optimiser step (Sec. 3.2.2 tracks the
+ * optimisation of each Gaussian's position, colour and scale and removes
+ * Gaussians whose activity over a pruning window stays at or below a
+ * threshold).  For every Gaussian whose layer bit is set in
+ * trainable_layers,
+ *   activity[i] += 2 |d mean_i| + 0.1 |d sh_i| + 0.1 |d log_scale_i|,
+ * d = after - before of the step and |.| the Euclidean norm over the
+ * Gaussian's 3, 3 (D+1)^2 and 3 values (float32, one thread per Gaussian;
+ * other Gaussians untouched).
+ *   mean_before/after       float[3][n]
+ *   log_scale_before/after  float[3][n]
+ *   sh_before/after         float[(D+1)^2][3][n], D = sh_degree <= 3
+ *   layer uint8[n]; activity float[n], accumulated
+ * Device arrays the caller owns; asynchronous on stream; GSR_EINVAL on a
+ * NULL array (n > 0) or a bad size or degree. */
+gsr_status gsr_update_activity(int32_t n, int32_t sh_degree, uint32_t trainable_layers, const float* mean_before,
+                               const float* mean_after, const float* log_scale_before, const float* log_scale_after,
+                               const float* sh_before, const float* sh_after, const uint8_t* layer, float* activity,
+                               void* stream);
+
 /* L1 loss of alpha-channel training (Sec. 3.2.1) and its gradient.  Per
  * view v the target colour is the target's premultiplied colour composited
  * over the view's background bg_v: target = target_rgb + (1 - target_alpha)

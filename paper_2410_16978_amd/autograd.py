@@ -17,8 +17,12 @@ class RenderContext:
     """Reusable buffers of one rendering configuration (pair capacity,
     workspace, per-Gaussian accumulators for pruning)."""
 
-    def __init__(self, trainable_layers=0xFFFFFFFF, track_activity=False, sync=True, timer=None):
+    def __init__(self, trainable_layers=0xFFFFFFFF, track_activity=False, sync=True, timer=None,
+                 grad_activity=True):
         self.state = None
+        # track_activity: the backward updates max_contrib and, with
+        # grad_activity, adds the gradient-norm activity into `activity`
+        self.grad_activity = grad_activity
         self.timer = timer
         self.trainable_layers = int(trainable_layers)
         self.track_activity = track_activity
@@ -57,7 +61,7 @@ class _RasterizeFn(torch.autograd.Function):
             n = ctx.model["mean"].shape[1]
             if rctx.max_contrib is None or rctx.max_contrib.numel() != n:
                 rctx.reset_accumulators(n, ctx.model["mean"].device)
-            mc, act = rctx.max_contrib, rctx.activity
+            mc, act = rctx.max_contrib, (rctx.activity if rctx.grad_activity else None)
         g = rz.rasterize_backward(ctx.model, ctx.cams, ctx.views, ctx.state,
                                   g_rgb.contiguous() if g_rgb is not None else None,
                                   g_alpha.contiguous() if g_alpha is not None else None,

@@ -25,6 +25,7 @@ SOURCES = {
     "blend.hip": ["-ffp-contract=off"],
     "project_bwd.hip": [],
     "loss.hip": [],
+    "train.hip": [],
     "api.cpp": ["-x", "hip"],
 }
 

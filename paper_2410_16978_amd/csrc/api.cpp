@@ -443,6 +443,21 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
                shared_order ? (size_t)std::max(n, 1) : 0);
 }
 
+gsr_status gsr_update_activity(int32_t n, int32_t sh_degree, uint32_t trainable_layers, const float* mean_before,
+                               const float* mean_after, const float* log_scale_before, const float* log_scale_after,
+                               const float* sh_before, const float* sh_after, const uint8_t* layer, float* activity,
+                               void* stream) {
+  if (n < 0 || sh_degree < 0 || sh_degree > 3) return GSR_EINVAL;
+  if (n == 0) return GSR_OK;
+  if (!mean_before || !mean_after || !log_scale_before || !log_scale_after || !sh_before || !sh_after || !layer ||
+      !activity)
+    return GSR_EINVAL;
+  HIP_TRY(launch_update_activity(n, sh_degree, trainable_layers, mean_before, mean_after, log_scale_before,
+                                 log_scale_after, sh_before, sh_after, layer, activity,
+                                 static_cast<hipStream_t>(stream)));
+  return GSR_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -211,6 +211,9 @@ uint32_t l1_loss_blocks(int n_views, int hw);
 hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
                           const float* t_alpha, const float* bg_host, float* partials, float* loss,
                           const float* g_loss, float* dL_drgb, float* dL_dalpha, hipStream_t s);
+hipError_t launch_update_activity(int n, int sh_degree, uint32_t trainable, const float* mean0, const float* mean1,
+                                  const float* ls0, const float* ls1, const float* sh0, const float* sh1,
+                                  const uint8_t* layer, float* activity, hipStream_t s);
 hipError_t launch_batch_order(const uint32_t* batch_tile, uint32_t n_batches, uint32_t* order_cnt,
                               uint32_t* order_list, hipStream_t s);
 hipError_t launch_blend_bwd(const ViewD* views_dev, int n_views, const float* records, uint32_t n_rec,

@@ -126,6 +126,8 @@ def lib():
     L.gsr_l1_alpha_loss.restype = C.c_int
     L.gsr_l1_alpha_loss.argtypes = [C.c_int32, C.c_int32, C.c_int32] + [C.c_void_p] * 4 + [
         C.POINTER(C.c_float), C.c_void_p, C.c_size_t] + [C.c_void_p] * 4 + [C.c_void_p]
+    L.gsr_update_activity.restype = C.c_int
+    L.gsr_update_activity.argtypes = [C.c_int32, C.c_int32, C.c_uint32] + [C.c_void_p] * 8 + [C.c_void_p]
     L.gsr_activate.restype = C.c_int
     L.gsr_activate.argtypes = [C.POINTER(Model), C.c_void_p, C.c_void_p, C.c_void_p]
     L.gsr_timer_create.restype = C.c_int
@@ -573,3 +575,24 @@ def l1_alpha_loss(rgb, alpha, target_rgb, target_alpha, bgs, loss=True, grads=Fa
     _check(rc, "gsr_l1_alpha_loss")
     return out, g_rgb, g_a
 
+
+
+def update_activity(before, after, layer, sh_degree, trainable, activity, stream=None):
+    """activity[i] += 2|d mean| + 0.1|d sh| + 0.1|d log_scale| for the
+    Gaussians of trainable layers (gsr_update_activity); before / after map
+    "mean" [3,n], "log_scale" [3,n] and "sh" [(D+1)^2,3,n] to contiguous
+    float32 device tensors, layer uint8 [n], activity float32 [n]."""
+    n = int(layer.shape[0])
+    nc = (int(sh_degree) + 1) ** 2
+    shapes = {"mean": (3, n), "log_scale": (3, n), "sh": (nc, 3, n)}
+    for d in (before, after):
+        for k, shp in shapes.items():
+            t = d[k]
+            if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"update_activity: {k} must be contiguous float32 {shp}")
+    if tuple(activity.shape) != (n,) or activity.dtype != torch.float32 or layer.dtype != torch.uint8:
+        raise ValueError("update_activity: activity float32 [n] and layer uint8 [n] expected")
+    rc = lib().gsr_update_activity(n, int(sh_degree), int(trainable) & 0xFFFFFFFF, _ptr(before["mean"]),
+                                   _ptr(after["mean"]), _ptr(before["log_scale"]), _ptr(after["log_scale"]),
+                                   _ptr(before["sh"]), _ptr(after["sh"]), _ptr(layer), _ptr(activity), _stream(stream))
+    _check(rc, "gsr_update_activity")

@@ -7,12 +7,24 @@ them untouched.  Every step renders a batch of views with a random
 background colour and compares RGB and alpha with the target (alpha-channel
 training, Sec. 3.2.1).
 
-Inactive pruning (Sec. 3.2.2): each step adds, per Gaussian,
-2 |dL/dmean| + 0.1 |dL/dSH| + 0.1 |dL/dlog scale| (fused into the backward
-kernel); every dR = 100 steps the average over the window is compared with
-a threshold T (T0 = 0.015), trainable Gaussians at or below it are removed,
-and T decays by 0.975.  Which norm the paper means is a reading (the
-gradient's L2 norm); the magnitudes behind T0 are tied to the paper's data.
+Inactive pruning (Sec. 3.2.2): the paper tracks how the optimisation moves
+each Gaussian's position, colour and scale, compares that activity with a
+threshold T (T0 = 0.015) at every densification interval (dR = 100 steps),
+removes the trainable Gaussians at or below it and decays T by 0.975.  What
+is measured is a reading; two are built:
+
+* "update" (default): after each optimiser step, 2 |d mean| + 0.1 |d SH| +
+  0.1 |d log scale| of the change the step made (gsr_update_activity),
+  summed over the window and compared with T.  Adam's steps are about the
+  learning rate in size whatever the gradient's scale, so a Gaussian the
+  optimiser moves in most steps collects far more than T0 over a window and
+  one it never moves collects exactly 0; the threshold then does not depend
+  on the loss's scale.
+* "gradient": the same weights on the L2 norms of the per-step gradients
+  (fused into the backward kernel), averaged over the window.  Its scale is
+  the loss's: at the 4M-Gaussian workload every trainable Gaussian's average
+  is below T0.
+
 Optionally, Gaussians whose largest alpha * T over the window stayed below
 1/255 (they never visibly contributed) are removed as well; both criteria are
 counted separately.
@@ -27,6 +39,7 @@ import numpy as np
 import torch
 
 from . import autograd as ag
+from . import rasterizer as rz
 
 PARAM_KEYS = ("mean", "log_scale", "quat", "opacity_logit", "sh")
 
@@ -39,6 +52,7 @@ class PruneConfig:
     use_max_contrib: bool = True
     min_contrib: float = 1.0 / 255.0
     use_activity: bool = True  # False: count the activity rule's decisions but prune by max_contrib only
+    measure: str = "update"    # "update": optimiser-step norms, window sum; "gradient": gradient norms, window mean
 
 
 class PruneState:
@@ -60,9 +74,14 @@ class PruneState:
     def decide(self, activity_sum, max_contrib, layer, trainable_layers):
         """Keep mask after a window; activity_sum is the window's sum.
         Returns keep (bool tensor) and per-criterion counts; decays T."""
-        avg = activity_sum / max(self.steps_in_window, 1)
+        if self.cfg.measure == "update":
+            score = activity_sum
+        elif self.cfg.measure == "gradient":
+            score = activity_sum / max(self.steps_in_window, 1)
+        else:
+            raise ValueError(f"unknown activity measure {self.cfg.measure!r}")
         trainable = ((int(trainable_layers) >> layer.to(torch.int64)) & 1).bool()
-        inactive = trainable & (avg <= self.T)
+        inactive = trainable & (score <= self.T)
         invisible = trainable & (max_contrib < self.cfg.min_contrib) if self.cfg.use_max_contrib else \
             torch.zeros_like(inactive)
         keep = ~((inactive if self.cfg.use_activity else torch.zeros_like(inactive)) | invisible)
@@ -91,7 +110,9 @@ class LayeredTrainer:
         self.lrs = lrs or {"mean": 1.6e-4, "log_scale": 5e-3, "quat": 1e-3, "opacity_logit": 5e-2, "sh": 2.5e-3}
         self.opt = self._make_opt()
         self.prune = PruneState(prune or PruneConfig())
-        self.rctx = ag.RenderContext(trainable_layers=self.trainable, track_activity=True, sync=sync)
+        self.rctx = ag.RenderContext(trainable_layers=self.trainable, track_activity=True, sync=sync,
+                                     grad_activity=self.prune.cfg.measure == "gradient")
+        self._before = None  # parameters before the optimiser step ("update" measure)
         self.rng = np.random.default_rng(seed)
         self.it = 0
         self.history = []
@@ -118,13 +139,27 @@ class LayeredTrainer:
         loss = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, [bg] * len(cams))
         self.opt.zero_grad(set_to_none=True)
         loss.backward()
-        self.opt.step()
+        if self.prune.cfg.measure == "update":
+            self._step_with_update_activity()
+        else:
+            self.opt.step()
         self.it += 1
         self.prune.steps_in_window += 1
         out = {"it": self.it, "loss": loss}
         if self.prune.due():
             out["prune"] = self.prune_now()
         return out
+
+    def _step_with_update_activity(self):
+        """The optimiser step, then the activity of the change it made."""
+        keys = ("mean", "log_scale", "sh")
+        if self._before is None or self._before["mean"].shape != self.params["mean"].shape:
+            self._before = {k: torch.empty_like(self.params[k]) for k in keys}
+        for k in keys:
+            self._before[k].copy_(self.params[k].detach())
+        self.opt.step()
+        rz.update_activity(self._before, {k: self.params[k].detach() for k in keys}, self.layer, self.sh_degree,
+                           self.trainable, self.rctx.activity)
 
     def prune_now(self):
         n = self.n

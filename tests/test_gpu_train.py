@@ -100,3 +100,31 @@ def test_export_ply_holds_the_trained_layered_model(tmp_path):
     for k in ("mean", "log_scale", "quat", "opacity_logit", "sh"):
         np.testing.assert_array_equal(back[k], a.params[k].detach().cpu().numpy(), err_msg=k)
     np.testing.assert_array_equal(back["layer"], a.layer.cpu().numpy())
+
+
+@pytest.mark.parametrize("n,D", [(10007, 3), (300, 0), (1, 1)])
+def test_update_activity_matches_oracle(n, D):
+    """gsr_update_activity against the oracle's definition, ragged n, frozen
+    layers untouched."""
+    import torch
+    from oracle import training
+    from paper_2410_16978_amd import rasterizer as rz
+    rng = np.random.default_rng(n + D)
+    nc = (D + 1) ** 2
+    b = {"mean": rng.standard_normal((3, n)), "log_scale": rng.normal(-4, 1, (3, n)),
+         "sh": rng.standard_normal((nc, 3, n))}
+    a = {k: v + rng.normal(0, 1e-3, v.shape) * (rng.random(n) < 0.8) for k, v in b.items()}
+    b = {k: v.astype(np.float32) for k, v in b.items()}
+    a = {k: v.astype(np.float32) for k, v in a.items()}
+    layer = rng.integers(0, 4, n).astype(np.uint8)
+    act0 = rng.random(n).astype(np.float32)
+    act = torch.tensor(act0, device="cuda")
+    rz.update_activity({k: torch.tensor(v, device="cuda") for k, v in b.items()},
+                       {k: torch.tensor(v, device="cuda") for k, v in a.items()},
+                       torch.tensor(layer, device="cuda"), D, 0b1011, act)
+    torch.cuda.synchronize()
+    got = act.cpu().numpy()
+    want = training.update_activity(b, a, layer, 0b1011, act0)
+    frozen = layer == 2
+    np.testing.assert_array_equal(got[frozen], act0[frozen])
+    np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-7)

@@ -38,7 +38,8 @@ def test_threshold_schedule_closed_form():
 
 
 def test_window_average_and_comparison():
-    ps = PruneState(PruneConfig(interval=100, threshold=0.015, use_max_contrib=False))
+    """The gradient measure: the window's average against T."""
+    ps = PruneState(PruneConfig(interval=100, threshold=0.015, use_max_contrib=False, measure="gradient"))
     ps.steps_in_window = 100
     # sums over a 100-step window: averages 0.0149, 0.015 (equal: pruned), 0.0151
     act = torch.tensor([1.49, 1.5, 1.51], dtype=torch.float64)
@@ -65,3 +66,21 @@ def test_max_contrib_criterion_counted_separately():
     keep, counts = ps.decide(act, mc, torch.zeros(3, dtype=torch.uint8), 1)
     assert keep.tolist() == [True, False, False]
     assert counts["max_contrib"] == 2 and counts["activity"] == 1 and counts["both"] == 1
+
+
+def test_update_measure_compares_the_window_sum():
+    """The update measure: the window's accumulated activity against T."""
+    ps = PruneState(PruneConfig(interval=100, threshold=0.015, use_max_contrib=False))
+    assert ps.cfg.measure == "update"
+    ps.steps_in_window = 100
+    act = torch.tensor([0.0149, 0.015, 0.0151, 0.0], dtype=torch.float64)
+    keep, counts = ps.decide(act, torch.ones(4), torch.zeros(4, dtype=torch.uint8), 0xFFFFFFFF)
+    assert keep.tolist() == [False, False, True, False]
+    assert counts["activity"] == 3
+    assert ps.T == pytest.approx(0.015 * 0.975)
+
+
+def test_unknown_measure_rejected():
+    ps = PruneState(PruneConfig(measure="hessian"))
+    with pytest.raises(ValueError):
+        ps.decide(torch.ones(2), torch.ones(2), torch.zeros(2, dtype=torch.uint8), 1)
