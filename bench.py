@@ -330,10 +330,11 @@ def bench_layered_training(args, torch, rz, ag, scenes):
         t_rgb[i:i + 8], t_alpha[i:i + 8] = r, a
     del tgt
     trainable = wl.extra["trainable_layers"]
-    # inactive pruning as the paper runs it: the activity of the optimiser's updates over each 100-step
-    # window against T (T0 = 0.015, decay 0.975), plus the max-contribution criterion
+    # inactive pruning: the window's average activity against T (T0 = 0.015, decay 0.975) under the chosen
+    # reading of the norms, plus the max-contribution criterion
     tr = LayeredTrainer(wl.scene, pool, (t_rgb, t_alpha), trainable_layers=trainable, views_per_step=8,
-                        prune=PruneConfig(interval=100), seed=0)
+                        prune=PruneConfig(interval=100, measure=args.activity_measure,
+                                          threshold=args.prune_threshold), seed=0)
     n0 = tr.n
     n_trainable0 = int(((trainable >> tr.layer.to(torch.int64)) & 1).sum())
     for _ in range(args.warmup):  # sizes the pair buffers (synchronising forwards)
@@ -375,14 +376,16 @@ def bench_layered_training(args, torch, rz, ag, scenes):
     dt_plain = (time.perf_counter() - tp) / plain_steps
     pr = {"activity": [p["activity"] for p in prunes], "max_contrib": [p["max_contrib"] for p in prunes],
           "both": [p["both"] for p in prunes], "pruned": sum(p["pruned"] for p in prunes),
-          "thresholds": [round(p["threshold"], 6) for p in prunes]}
+          "thresholds": [round(p["threshold"], 6) for p in prunes],
+          "avg_activity_p10_p50_p90_p99_max": [[float("%.4g" % x) for x in p.get("avg_quantiles", [])]
+                                               for p in prunes]}
     return {"metric": "layered training iters/s (8 views of 1024^2 per step), 1 GPU", "value": round(steps / dt, 3),
             "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
             "ms_per_step": round(dt / steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": wl.name, "gaussians": n0, "layers": 8, "sh_degree": 3, "views_per_step": 8,
                        "width": W, "height": H, "trainable_layers": trainable, "prune_interval": 100,
-                       "activity_measure": "optimiser update norms, window sum vs T",
+                       "activity_measure": args.activity_measure, "prune_threshold_T0": args.prune_threshold,
                        "step": "forward + L1(rgb, alpha) + backward + Adam, random background"},
             "plain_ms_per_step": round(dt_plain * 1e3, 3),
             "speedup_vs_plain": round(dt_plain / (dt / steps), 3),
@@ -411,7 +414,12 @@ def main():
                          "trace of --serve-seconds (30 by default here) at 200 and 800 requests/s under 2 GiB and "
                          "16 GiB budgets")
     ap.add_argument("--train-steps", type=int, default=200, help="steps of the layered_training_4m workload")
-    ap.add_argument("--extra-train-steps", type=int, default=50,
+    ap.add_argument("--activity-measure", default="update", choices=["update", "gradient"],
+                    help="reading of the inactive-pruning norms (layered_training_4m)")
+    ap.add_argument("--prune-threshold", type=float, default=1.5e-4,
+                    help="inactive-pruning T0 of the layered_training_4m workload (the paper's 0.015 was tuned on its "
+                         "data; under the update reading every trainable Gaussian of this scene averages below it)")
+    ap.add_argument("--extra-train-steps", type=int, default=100,
                     help="steps of the layered_training_4m entry of the default run (0: left out)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales the HBM byte counters)")

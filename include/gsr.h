@@ -314,6 +314,12 @@ gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host,
  *   an accumulation window).
  * activity float[n] (optional): accumulated (+=) with
  *   2 |dL/dmean| + 0.1 |dL/dsh| + 0.1 |dL/dlog scale| (Sec. 3.2.2).
+ * grads->densify_grad, grads->densify_count float[n] (optional, NULL:
+ *   not tracked): accumulated (+=) with the statistic of adaptive density
+ *   control - per trainable Gaussian and view in which it covers at least
+ *   one tile, the length of the gradient with respect to its projected
+ *   centre in normalised device coordinates, |(dL/du W/2, dL/dv H/2)| (u, v
+ *   in pixels), and 1 for the view.
  * ws: scratch of at least gsr_workspace_size(...) bytes.
  * The backward uses no atomics: per-pair partial gradients are summed in a
  * fixed order, so repeated calls give bitwise identical results.
@@ -321,6 +327,7 @@ gsr_status gsr_forward_check(const gsr_fwd_state* state, uint32_t* n_pairs_host,
  * approximation; training differentiates each view's own order). */
 typedef struct {
   float *g_mean, *g_scale, *g_quat, *g_opacity, *g_sh;
+  float *densify_grad, *densify_count;  /* optional accumulators, see above */
 } gsr_grads;
 
 gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const gsr_camera* cams,

@@ -72,7 +72,8 @@ def lib():
             f = getattr(_lib, name)
             Pi, Po = C.POINTER(in_t), C.POINTER(out_t)
             f.argtypes = [C.c_int, C.POINTER(mtype), C.POINTER(Camera), C.POINTER(View), Pi, Pi, C.c_uint32,
-                          Po, Po, Po, Po, Po, Po, Po] + ([Po, C.c_int] if name.endswith("exact") else []) + [C.c_int]
+                          Po, Po, Po, Po, Po, Po, Po] + ([Po, C.c_int] if name.endswith("exact") else []) + [
+                              C.c_int, Po, Po]
             f.restype = C.c_int
         _lib.oracle_sh_basis_f64.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib.oracle_sh_basis_f32.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -265,7 +266,7 @@ def backward(scene, cams, views, dL_drgb, dL_dalpha, trainable=0xFFFFFFFF, dtype
     nc = (int(scene["sh_degree"]) + 1) ** 2
     g = {"mean": np.zeros((3, n), out_dt), "scale": np.zeros((3, n), out_dt), "quat": np.zeros((4, n), out_dt),
          "opacity": np.zeros(n, out_dt), "sh": np.zeros((nc, 3, n), out_dt), "max_contrib": np.zeros(n, out_dt),
-         "activity": np.zeros(n, out_dt)}
+         "activity": np.zeros(n, out_dt), "densify_grad": np.zeros(n, out_dt), "densify_count": np.zeros(n, out_dt)}
     drgb = np.ascontiguousarray(dL_drgb, in_dt).reshape(-1)
     dal = np.ascontiguousarray(dL_dalpha, in_dt).reshape(-1)
     ci = C.c_float if in_dt == np.float32 else C.c_double
@@ -276,7 +277,8 @@ def backward(scene, cams, views, dL_drgb, dL_dalpha, trainable=0xFFFFFFFF, dtype
     extra = (_ptr(packed, C.c_double), int(fwd_values)) if exact else ()
     rc = fn(V, C.byref(ma.struct), carr, varr, _ptr(drgb, ci), _ptr(dal, ci), trainable & 0xFFFFFFFF,
             _ptr(g["mean"], co), _ptr(g["scale"], co), _ptr(g["quat"], co), _ptr(g["opacity"], co),
-            _ptr(g["sh"], co), _ptr(g["max_contrib"], co), _ptr(g["activity"], co), *extra, n_threads)
+            _ptr(g["sh"], co), _ptr(g["max_contrib"], co), _ptr(g["activity"], co), *extra, n_threads,
+            _ptr(g["densify_grad"], co), _ptr(g["densify_count"], co))
     if rc != 0:
         raise RuntimeError(f"oracle backward failed: {rc}")
     if packed is not None:

@@ -771,7 +771,7 @@ template <typename TF, typename TG>
 int backward(int n_views, const Model<TF>& m, const oc_camera* cams, const oc_view* views, const TF* dL_drgb,
              const TF* dL_dalpha, uint32_t trainable, TG* g_mean, TG* g_scale, TG* g_quat, TG* g_opacity,
              TG* g_sh, TG* max_contrib, TG* activity, int n_threads, bool fwd_values = false,
-             TG* cond = nullptr) {
+             TG* cond = nullptr, TG* dens_grad = nullptr, TG* dens_cnt = nullptr) {
   if (n_views < 0 || m.n < 0 || m.D < 0 || m.D > 3) return -1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -925,11 +925,21 @@ int backward(int n_views, const Model<TF>& m, const oc_camera* cams, const oc_vi
     std::fill(gq.begin(), gq.end(), TG(0));
     std::fill(gsh.begin(), gsh.end(), TG(0));
     TG mcv = TG(0);
+    TG dgs = TG(0), dgc = TG(0);
     const bool train = m.layer[i] < 32 && ((trainable >> m.layer[i]) & 1u);
     for (int v = 0; v < n_views; ++v) {
       const uint64_t r = sc.info[v].rec_off + i;
       if (!sc.proj[r].valid) continue;
       mcv = std::max(mcv, mcr[r]);
+      if (train && sc.proj[r].ntiles > 0) {
+        // densification statistic: the length of the loss gradient with
+        // respect to the projected centre in normalised device coordinates
+        // (x_ndc spans [-1, 1] over the width: du / dx_ndc = W / 2)
+        const TG gx = g2[r].g[0] * (TG(sc.cams[v].W) / TG(2));
+        const TG gy = g2[r].g[1] * (TG(sc.cams[v].H) / TG(2));
+        dgs += std::sqrt(gx * gx + gy * gy);
+        dgc += TG(1);
+      }
       const Proj<TG> pg = train ? chain_proj(v, sc.proj[r]) : Proj<TG>();
       if (train)
         backward_gaussian(mg.m, i, cams_g[v], pg, sh, g2[r].g, gm.data(), gs.data(), gq.data(), &go, gsh.data());
@@ -962,6 +972,8 @@ int backward(int n_views, const Model<TF>& m, const oc_camera* cams, const oc_vi
       for (int k = 0; k < per; ++k) cond[(size_t)k * N + i] = csum[k];
     }
     if (max_contrib) max_contrib[i] = mcv;
+    if (dens_grad) dens_grad[i] = dgs;
+    if (dens_cnt) dens_cnt[i] = dgc;
     if (activity) {
       TG pm = TG(0), pc = TG(0), ps = TG(0);
       for (int j = 0; j < 3; ++j) pm += gm[j] * gm[j];
@@ -1007,27 +1019,30 @@ int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* ca
 int oracle_backward_f32(int n_views, const oc_model32* model, const oc_camera* cams, const oc_view* views,
                         const float* dL_drgb, const float* dL_dalpha, uint32_t trainable, float* g_mean,
                         float* g_scale, float* g_quat, float* g_opacity, float* g_sh, float* max_contrib,
-                        float* activity, int n_threads) {
+                        float* activity, int n_threads, float* dens_grad, float* dens_cnt) {
   return backward<float, float>(n_views, to_model<float>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
-                                g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads);
+                                g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads, false,
+                                nullptr, dens_grad, dens_cnt);
 }
 
 int oracle_backward_f64(int n_views, const oc_model64* model, const oc_camera* cams, const oc_view* views,
                         const double* dL_drgb, const double* dL_dalpha, uint32_t trainable, double* g_mean,
                         double* g_scale, double* g_quat, double* g_opacity, double* g_sh,
-                        double* max_contrib, double* activity, int n_threads) {
+                        double* max_contrib, double* activity, int n_threads, double* dens_grad,
+                        double* dens_cnt) {
   return backward<double, double>(n_views, to_model<double>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
-                                  g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads);
+                                  g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads, false,
+                                  nullptr, dens_grad, dens_cnt);
 }
 
 int oracle_backward_exact(int n_views, const oc_model32* model, const oc_camera* cams, const oc_view* views,
                           const float* dL_drgb, const float* dL_dalpha, uint32_t trainable, double* g_mean,
                           double* g_scale, double* g_quat, double* g_opacity, double* g_sh,
                           double* max_contrib, double* activity, double* cond, int fwd_values,
-                          int n_threads) {
+                          int n_threads, double* dens_grad, double* dens_cnt) {
   return backward<float, double>(n_views, to_model<float>(*model), cams, views, dL_drgb, dL_dalpha, trainable,
                                  g_mean, g_scale, g_quat, g_opacity, g_sh, max_contrib, activity, n_threads,
-                                 fwd_values != 0, cond);
+                                 fwd_values != 0, cond, dens_grad, dens_cnt);
 }
 
 void oracle_sh_basis_f64(const double* dir, double* out16) {

@@ -137,22 +137,29 @@ int oracle_render_f64(int n_views, const oc_model64* models, const oc_camera* ca
  * the slot's per-pixel terms (dL/dalpha taken as the sum of the magnitudes
  * of its operands), each weighted by its pixel's number of blended pairs
  * + 16: the scale of the error that float32 per-pixel arithmetic (whose
- * transmittance carries one rounding per pair) leaves on the entry. */
+ * transmittance carries one rounding per pair) leaves on the entry.
+ * dens_grad[n], dens_cnt[n] (optional): the statistic of adaptive density
+ * control - over the views in which the Gaussian is visible (covers at
+ * least one tile), the sum of the lengths of the gradient with respect to
+ * its projected centre in normalised device coordinates ((dL/du W/2,
+ * dL/dv H/2), pixels u, v) and the number of those views; zero for frozen
+ * layers. */
 int oracle_backward_f32(int n_views, const oc_model32* model, const oc_camera* cams,
                         const oc_view* views, const float* dL_drgb, const float* dL_dalpha,
                         uint32_t trainable_layers, float* g_mean, float* g_scale, float* g_quat,
                         float* g_opacity, float* g_sh, float* max_contrib, float* activity,
-                        int n_threads);
+                        int n_threads, float* dens_grad, float* dens_cnt);
 int oracle_backward_f64(int n_views, const oc_model64* model, const oc_camera* cams,
                         const oc_view* views, const double* dL_drgb, const double* dL_dalpha,
                         uint32_t trainable_layers, double* g_mean, double* g_scale, double* g_quat,
                         double* g_opacity, double* g_sh, double* max_contrib, double* activity,
-                        int n_threads);
+                        int n_threads, double* dens_grad, double* dens_cnt);
 int oracle_backward_exact(int n_views, const oc_model32* model, const oc_camera* cams,
                           const oc_view* views, const float* dL_drgb, const float* dL_dalpha,
                           uint32_t trainable_layers, double* g_mean, double* g_scale, double* g_quat,
                           double* g_opacity, double* g_sh, double* max_contrib, double* activity,
-                          double* cond, int fwd_values, int n_threads);
+                          double* cond, int fwd_values, int n_threads, double* dens_grad,
+                          double* dens_cnt);
 
 /* Real spherical-harmonic basis values Y_k(dir) for k < 16 (degree <= 3),
  * float and double, for the orthonormality check. */

@@ -29,6 +29,7 @@ class RenderContext:
         self.sync = sync
         self.max_contrib = None
         self.activity = None
+        self.densify_stats = None  # (grad_sum, count) [n] accumulators of density control, or None
 
     def reset_accumulators(self, n, device):
         self.max_contrib = torch.zeros(n, dtype=torch.float32, device=device)
@@ -65,7 +66,8 @@ class _RasterizeFn(torch.autograd.Function):
         g = rz.rasterize_backward(ctx.model, ctx.cams, ctx.views, ctx.state,
                                   g_rgb.contiguous() if g_rgb is not None else None,
                                   g_alpha.contiguous() if g_alpha is not None else None,
-                                  trainable=rctx.trainable_layers, max_contrib=mc, activity=act, timer=rctx.timer)
+                                  trainable=rctx.trainable_layers, max_contrib=mc, activity=act, timer=rctx.timer,
+                                  densify=rctx.densify_stats)
         return g["mean"], g["scale"], g["quat"], g["opacity"], g["sh"], None, None, None, None, None, None
 
 

@@ -742,7 +742,8 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
       HIP_TRY(launch_project_bwd(j, b.views, state->records, state->offsets, b.g_pair,
                                  reinterpret_cast<const uint8_t*>(b.alive), P,
                                  state->counters, trainable_layers, grads->g_mean, grads->g_scale, grads->g_quat,
-                                 grads->g_opacity, grads->g_sh, b.g_col, max_contrib, activity, s));
+                                 grads->g_opacity, grads->g_sh, b.g_col, max_contrib, activity,
+                                 grads->densify_grad, grads->densify_count, s));
   }
   return GSR_OK;
 }

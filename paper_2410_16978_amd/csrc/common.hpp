@@ -227,7 +227,7 @@ hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const flo
                               uint32_t pair_capacity,
                               const uint32_t* counters, uint32_t trainable, float* g_mean, float* g_scale,
                               float* g_quat, float* g_opacity, float* g_sh, float* g_col, float* max_contrib,
-                              float* activity, hipStream_t s);
+                              float* activity, float* dens_grad, float* dens_cnt, hipStream_t s);
 hipError_t launch_batch_error(const uint32_t* counters, int n_req, int32_t* req_status, hipStream_t s);
 hipError_t launch_batch_status(const uint32_t* req_rec, int n_req, const uint32_t* offsets,
                                uint32_t pair_capacity, uint32_t* counters, int32_t* req_status,

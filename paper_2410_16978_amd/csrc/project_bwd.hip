@@ -67,7 +67,7 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
                    const uint8_t* __restrict__ alive, uint32_t cap, const uint32_t* __restrict__ counters,
                    uint32_t trainable, float* __restrict__ g_mean, float* __restrict__ g_scale,
                    float* __restrict__ g_quat, float* __restrict__ g_opacity, float* __restrict__ g_col,
-                   float* __restrict__ max_contrib) {
+                   float* __restrict__ max_contrib, float* __restrict__ dens_grad, float* __restrict__ dens_cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const ModelD& m = job.m;
   if (i >= m.n) return;
@@ -77,6 +77,7 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
   const uint32_t K = min(counters[kCntPairs], cap);
   float wmax = 0.f;
   double gm[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0}, go = 0.0;
+  double dgs = 0.0, dgc = 0.0;
   if (!train && max_contrib) {
     double g[9];
     for (int jv = 0; jv < job.n_views; ++jv) {
@@ -122,6 +123,13 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
       double g[9];
       record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
       go += g[5] * (double)V.layer_op[layer];  // the record holds o times the view's factor
+      {
+        // density-control statistic: gradient of the projected centre in
+        // normalised device coordinates (du / dx_ndc = W / 2)
+        const double gx = g[0] * (0.5 * (double)V.W), gy = g[1] * (0.5 * (double)V.H);
+        dgs += sqrt(gx * gx + gy * gy);
+        dgc += 1.0;
+      }
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) g_col[(size_t)r * 3 + ch] = ((clamp_bits >> ch) & 1u) ? 0.f : (float)g[6 + ch];
       double W[9];
@@ -269,6 +277,10 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
   for (int k = 0; k < 4; ++k) g_quat[(size_t)k * n + i] = (float)gq[k];
   g_opacity[i] = (float)go;
   if (max_contrib) max_contrib[i] = fmaxf(max_contrib[i], wmax);
+  if (train && dens_grad) {
+    dens_grad[i] += (float)dgs;
+    dens_cnt[i] += (float)dgc;
+  }
 }
 
 // Colour: SH coefficients and, through the view direction, the mean; then
@@ -366,11 +378,12 @@ hipError_t launch_project_bwd(const JobD& job, const ViewD* views_dev, const flo
                               uint32_t pair_capacity,
                               const uint32_t* counters, uint32_t trainable, float* g_mean, float* g_scale,
                               float* g_quat, float* g_opacity, float* g_sh, float* g_col, float* max_contrib,
-                              float* activity, hipStream_t s) {
+                              float* activity, float* dens_grad, float* dens_cnt, hipStream_t s) {
   if (job.m.n <= 0) return hipSuccess;
   const dim3 grid(div_up((uint32_t)job.m.n, 256u)), block(256);
   hipLaunchKernelGGL(k_project_bwd_geom, grid, block, 0, s, job, views_dev, records, offsets, g_pair, alive,
-                     pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_col, max_contrib);
+                     pair_capacity, counters, trainable, g_mean, g_scale, g_quat, g_opacity, g_col, max_contrib,
+                     dens_grad, dens_cnt);
   switch (job.m.D) {
     case 0: hipLaunchKernelGGL(k_project_bwd_sh<0>, grid, block, 0, s, job, views_dev, records, trainable, g_col,
                                g_mean, g_scale, g_sh, activity); break;

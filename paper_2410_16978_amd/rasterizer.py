@@ -78,7 +78,8 @@ class Debug(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [("g_mean", C.c_void_p), ("g_scale", C.c_void_p), ("g_quat", C.c_void_p),
-                ("g_opacity", C.c_void_p), ("g_sh", C.c_void_p)]
+                ("g_opacity", C.c_void_p), ("g_sh", C.c_void_p), ("densify_grad", C.c_void_p),
+                ("densify_count", C.c_void_p)]
 
 
 class Request(C.Structure):
@@ -460,8 +461,10 @@ def forward_check(state, stream=None):
 
 # ---------------------------------------------------------------- backward
 def rasterize_backward(model, cams, views, state, dL_drgb=None, dL_dalpha=None, trainable=0xFFFFFFFF,
-                       max_contrib=None, activity=None, grads=None, stream=None, timer=None):
-    """Gradients w.r.t. the activated parameters (dict of tensors like model)."""
+                       max_contrib=None, activity=None, grads=None, stream=None, timer=None, densify=None):
+    """Gradients w.r.t. the activated parameters (dict of tensors like model).
+    densify (optional): (grad_sum, count) float32 [n] tensors accumulated
+    with the density-control statistic (see gsr_grads in gsr.h)."""
     L = lib()
     V = len(cams)
     n = int(model["layer"].shape[0])
@@ -478,6 +481,11 @@ def rasterize_backward(model, cams, views, state, dL_drgb=None, dL_dalpha=None, 
                  "opacity": torch.empty((n,), dtype=torch.float32, device=dev),
                  "sh": torch.empty((nc, 3, n), dtype=torch.float32, device=dev)}
     g = Grads(*[grads[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "sh")])
+    if densify is not None:
+        for t in densify:
+            if tuple(t.shape) != (n,) or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("densify accumulators must be contiguous float32 [n]")
+        g.densify_grad, g.densify_count = densify[0].data_ptr(), densify[1].data_ptr()
     for t in (dL_drgb, dL_dalpha):
         if t is not None and (not t.is_contiguous() or t.dtype != torch.float32):
             raise ValueError("upstream gradients must be contiguous float32")

@@ -150,8 +150,11 @@ def grad_refs(orc, scene, cams, views, Gr, Ga, trainable=0xFFFFFFFF):
         2.0 * np.linalg.norm(sens["mean"].reshape(-1, n), axis=0)
         + 0.1 * np.linalg.norm(sens["sh"].reshape(-1, n), axis=0)
         + 0.1 * np.linalg.norm((sens["scale"] * s).reshape(-1, n), axis=0))
-    ref = {k: ex[k] for k in keys + ("activity", "max_contrib")}
-    return ref, sens, {k: g32[k].astype(np.float64) for k in keys + ("activity",)}
+    # density-control statistic: a sum of norms of the centre's 2D gradient;
+    # its sensitivity from the float32 forward values
+    sens["densify_grad"] = np.abs(ex["densify_grad"] - fv["densify_grad"])
+    ref = {k: ex[k] for k in keys + ("activity", "max_contrib", "densify_grad", "densify_count")}
+    return ref, sens, {k: g32[k].astype(np.float64) for k in keys + ("activity", "densify_grad")}
 
 
 def assert_grad_close(got, ref, sens, name, exempt=None, ref32=None):

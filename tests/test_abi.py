@@ -61,7 +61,7 @@ int main(void) {
   P(gsr_camera); O(gsr_camera, fx); O(gsr_camera, width); O(gsr_camera, guard);
   P(gsr_clip_plane); P(gsr_view_state); O(gsr_view_state, clip); O(gsr_view_state, bg);
   O(gsr_view_state, sort_shared); O(gsr_view_state, sort_cam); O(gsr_view_state, layer_fade);
-  O(gsr_view_state, layer_opacity);
+  O(gsr_view_state, layer_opacity); O(gsr_grads, densify_grad); O(gsr_grads, densify_count);
   P(gsr_model); O(gsr_model, mean); O(gsr_model, layer);
   P(gsr_fwd_state); O(gsr_fwd_state, pixel_state); O(gsr_fwd_state, pair_capacity);
   O(gsr_fwd_state, batch_capacity);

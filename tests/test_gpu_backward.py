@@ -195,3 +195,32 @@ def test_gradients_with_layer_fading(orc):
     for k in ("mean", "scale", "quat", "opacity", "sh", "activity"):
         assert_grad_close(got[k], ref[k], sens[k], k, ex, g32[k])
     np.testing.assert_allclose(got["max_contrib"][~ex], ref["max_contrib"][~ex], rtol=1e-4, atol=1e-7)
+
+
+def test_density_control_statistic_matches_oracle(orc):
+    """The backward's density-control accumulators (gsr_grads.densify_*):
+    counts exact (visibility is decided by the bit-exact records), sums of
+    the centre's NDC gradient lengths under the gradient bar; accumulation
+    over two calls doubles them; frozen layers untouched."""
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    sc, cams, vss, Gr, Ga = _case(seed=23, D=1, n_views=2)
+    model = rz.to_device(sc)
+    rgb, alpha, st = rz.rasterize_forward(model, cams, vss)
+    n = sc["mean"].shape[1]
+    dg = torch.zeros(n, device="cuda")
+    dc = torch.zeros(n, device="cuda")
+    for _ in range(2):
+        rz.rasterize_backward(model, cams, vss, st, torch.as_tensor(Gr).cuda(), torch.as_tensor(Ga).cuda(),
+                              trainable=0b110, densify=(dg, dc))
+    torch.cuda.synchronize()
+    got_g, got_c = dg.cpu().numpy() / 2, dc.cpu().numpy() / 2
+    ref, sens, g32 = grad_refs(orc, sc, cams, vss, Gr, Ga, trainable=0b110)
+    frozen = sc["layer"] == 0
+    assert np.all(dg.cpu().numpy()[frozen] == 0) and np.all(dc.cpu().numpy()[frozen] == 0)
+    np.testing.assert_array_equal(got_c, ref["densify_count"])
+    assert got_c.max() == 2 and (got_c > 0).sum() > 100
+    last = st.last.cpu().numpy().view(np.uint32)
+    ex = checked_exempt(orc, sc, cams, vss, rgb.cpu().numpy(), alpha.cpu().numpy(), last, st.final_T.cpu().numpy(),
+                        "densify")
+    assert_grad_close(got_g, ref["densify_grad"], sens["densify_grad"], "densify_grad", ex, g32["densify_grad"])

@@ -128,3 +128,40 @@ def test_update_activity_matches_oracle(n, D):
     frozen = layer == 2
     np.testing.assert_array_equal(got[frozen], act0[frozen])
     np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-7)
+
+
+def test_density_control_in_layered_training():
+    """Clone / split decided as the oracle's plan decides from the trainer's
+    accumulated statistic; frozen Gaussians untouched and first; children in
+    their parent's layer; training continues on the grown model; the
+    opacity reset caps only the trainable layer."""
+    import torch
+    from oracle import training
+    from paper_2410_16978_amd.train import DensifyConfig, LayeredTrainer, PruneConfig
+    sc, cams, targets, n_s, _ = _setup(seed=4)
+    cfg = DensifyConfig(start=10 ** 6, grad_threshold=1e-6)  # densify_now called by hand
+    tr = LayeredTrainer(sc, cams, targets, trainable_layers=0b10, views_per_step=2,
+                        prune=PruneConfig(interval=10 ** 6), densify=cfg, extent=5.0, seed=2)
+    for _ in range(4):
+        tr.step()
+    torch.cuda.synchronize()
+    frozen0 = {k: v.detach().clone()[..., :n_s] for k, v in tr.params.items()}
+    plan = training.densify_plan(tr.dens[0].cpu().numpy(), tr.dens[1].cpu().numpy(),
+                                 np.exp(tr.params["log_scale"].detach().cpu().numpy().astype(np.float64)),
+                                 tr.layer.cpu().numpy(), 0b10, cfg.grad_threshold, cfg.percent_dense, 5.0, 2)
+    n0 = tr.n
+    c = tr.densify_now()
+    assert c["cloned"] == plan.count("clone") and c["split"] == plan.count("split")
+    assert c["cloned"] + c["split"] > 0
+    assert c["before"] == n0 and c["after"] == n0 + c["cloned"] + c["split"] * (cfg.n_split - 1) - c["pruned"]
+    assert tr.n == c["after"] and tr.dens[0].numel() == tr.n and float(tr.dens[1].sum()) == 0
+    for k in frozen0:
+        assert torch.equal(tr.params[k].detach()[..., :n_s], frozen0[k]), k
+    assert int((tr.layer == 0).sum()) == n_s and int((tr.layer[n_s:] == 1).sum()) == tr.n - n_s
+    losses = [float(tr.step()["loss"]) for _ in range(4)]
+    assert np.all(np.isfinite(losses))
+    torch.cuda.synchronize()
+    tr.reset_opacity()
+    op = torch.sigmoid(tr.params["opacity_logit"].detach())
+    assert float(op[n_s:].max()) <= 0.01 * (1 + 1e-6)
+    assert torch.equal(tr.params["opacity_logit"].detach()[:n_s], frozen0["opacity_logit"])

@@ -437,3 +437,39 @@ def test_layer_fade_opacity_gradient_matches_central_differences(orc):
     assert checked == 8
     # both layers were sampled
     assert len(set(s64["layer"][active].tolist())) == 2
+
+
+# ---------------------------------------------------------------- density-control statistic
+def test_densify_statistic_is_the_ndc_gradient_of_the_centre(orc):
+    """One Gaussian, two views: the principal point (cx, cy) moves the
+    projected centre (u, v) one for one and nothing else that the image
+    depends on near the axis, so central differences over cx and cy give
+    dL/du and dL/dv per view; the statistic is the sum over the views of
+    |(dL/du W/2, dL/dv H/2)| and the count is 2."""
+    sc = make_scene([[0.05, -0.03, 0.0]], [[0.08, 0.05, 0.03]], quats=[[0.9, 0.2, -0.3, 0.1]], opacity=[0.7],
+                    rgb=[[0.8, 0.3, 0.2]], layer=[1], dtype=np.float64)
+    W, H = 40, 32
+    cams = [scenes.orbit_camera([0.2, 0.1, -1.0], W, H), scenes.orbit_camera([-0.3, 0.2, -1.0], W, H)]
+    vss = [scenes.view_state(bg=(0.1, 0.2, 0.3))] * 2
+    rng = np.random.default_rng(2)
+    Gr = rng.standard_normal((2, 3, H, W))
+    Ga = rng.standard_normal((2, H, W))
+    g = orc.backward(sc, cams, vss, Gr, Ga, trainable=0b10, dtype=np.float64)
+    want = 0.0
+    for v in range(2):
+        d = []
+        for key in ("cx", "cy"):
+            h = 2.0 ** -12  # cameras hold float32: a step that is exact there
+
+            def f(delta):
+                cs = [dict(c) for c in cams]
+                cs[v][key] = cams[v][key] + delta
+                return _loss(orc, sc, cs, vss, Gr, Ga)
+
+            d.append((f(h) - f(-h)) / (2 * h))
+        want += np.hypot(d[0] * W / 2, d[1] * H / 2)
+    assert g["densify_count"][0] == 2
+    assert abs(g["densify_grad"][0] - want) <= 1e-6 * want, (g["densify_grad"][0], want)
+    # frozen: nothing accumulated
+    g0 = orc.backward(sc, cams, vss, Gr, Ga, trainable=0b01, dtype=np.float64)
+    assert g0["densify_grad"][0] == 0 and g0["densify_count"][0] == 0
