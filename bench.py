@@ -125,6 +125,45 @@ def run_cpu_baseline(workload, threads, min_seconds, max_steps=200):
     return first, steps, t_f, t_b
 
 
+def bench_compressed(rz, torch, scene, cams, vstates, st, out, frames, warmup):
+    """The same batched stereo frames from compressed attributes (Sec. 4.3):
+    16-bit parameters with packed SH triplets, and with a 16k-entry K-means
+    SH codebook; frame time, projection time and device bytes per Gaussian
+    against the float model (the codebook is built on the host first; its
+    time is reported, not timed with the frames)."""
+    from paper_2410_16978_amd import compress
+    res = {"float32_bytes_per_gaussian": 4 * (3 + 3 + 4 + 1 + 3 * (int(scene["sh_degree"]) + 1) ** 2) + 1}
+    for name, mode in (("half_packed", "packed"), ("half_codebook", "codebook")):
+        t0 = time.perf_counter()
+        comp = compress.compress(scene, mode, codebook_size=16384, iters=4, sample=65536)
+        enc = time.perf_counter() - t0
+        model = rz.to_device_compressed(comp)
+        tm = rz.Timer()
+        for i in range(3):
+            rz.rasterize_forward(model, cams, [vstates[i]] * 2, state=st, sync=False, out=out, timer=tm)
+        stage = {k: round(v[0] / 3, 4) for k, v in tm.read().items() if v[1]}
+        tm.close()
+        for i in range(warmup):
+            rz.rasterize_forward(model, cams, [vstates[i]] * 2, state=st, sync=False, out=out)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(frames):
+            rz.rasterize_forward(model, cams, [vstates[warmup + i]] * 2, state=st, sync=False, out=out)
+        ev[1].record()
+        torch.cuda.synchronize()
+        rz.forward_check(st)
+        mean = ev[0].elapsed_time(ev[1]) / frames
+        W, H = cams[0]["width"], cams[0]["height"]
+        res[name] = {"mpix_s": round(2 * W * H / (mean * 1e-3) / 1e6, 1), "ms_per_frame": round(mean, 4),
+                     "project_ms": stage.get("project"), "bytes_per_gaussian": round(compress.nbytes_per_gaussian(comp), 2),
+                     "encode_s": round(enc, 2)}
+        if mode == "codebook":
+            res[name]["codebook_bytes"] = int(comp["codebook"].nbytes)
+        del model
+    return res
+
+
 def bench_stereo(rz, scenes, torch, frames, warmup):
     """Layered stereo frames: 1M Gaussians in 5 CT-like shells, SH3, two eyes
     of 1832x1920, a random 5-bit layer mask and 1-3 clip planes per frame.
@@ -196,7 +235,8 @@ def bench_stereo(rz, scenes, torch, frames, warmup):
     rz.forward_check(st2)
     rz.forward_check(st2s)
     rz.forward_check(st1)
-    return {"workload": wl.name, "frames": frames, "pairs": st2.capacity, **res,
+    comp_res = bench_compressed(rz, torch, wl.scene, cams, vstates, st2, out2, frames, warmup)
+    return {"workload": wl.name, "frames": frames, "pairs": st2.capacity, **res, "compressed": comp_res,
             "speedup_vs_plain": round(res["plain"]["ms_per_frame"] / res["batched"]["ms_per_frame"], 3),
             "shared_order_speedup_vs_plain": round(res["plain"]["ms_per_frame"] / res["shared_order"]["ms_per_frame"],
                                                    3),

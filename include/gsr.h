@@ -117,6 +117,39 @@ typedef struct {
   float layer_opacity[32];
 } gsr_view_state;
 
+/* Compressed attributes for rendering (device arrays, structure of arrays;
+ * host struct).  Sec. 4.3 renders with 16-bit floats for the point-cloud
+ * parameters and either quantised spherical-harmonic coefficient triplets
+ * or, "clustered", one shared set of SH coefficients per Gaussian out of a
+ * K-means codebook built across all layers (Sec. 3.3).  M = (D+1)^2 - 1
+ * higher coefficients per channel, D = sh_degree.  Half values are IEEE
+ * binary16 bit patterns, decoded exactly (subnormals included). */
+enum { GSR_FORMAT_F32 = 0, GSR_FORMAT_HALF_PACKED = 1, GSR_FORMAT_HALF_CODEBOOK = 2 };
+typedef struct {
+  const uint16_t* mean;     /* half[3][n] */
+  const uint16_t* scale;    /* half[3][n], activated scales */
+  const uint16_t* quat;     /* half[4][n], (w, x, y, z) */
+  const uint16_t* opacity;  /* half[n], activated opacity */
+  const uint16_t* sh_dc;    /* half[3][n]: the degree-0 coefficient of r, g, b */
+  /* GSR_FORMAT_HALF_PACKED: coefficient k = 1 .. M of Gaussian i is the word
+   * sh_packed[(k-1) n + i], unsigned codes q of r in bits 0-10, g in bits
+   * 11-21 and b in bits 22-31; the value of channel ch is the float32
+   * sh_lo[ch] + q * sh_step[ch] (the product rounded, then the sum). */
+  const uint32_t* sh_packed;
+  float sh_lo[3], sh_step[3];
+  /* GSR_FORMAT_HALF_CODEBOOK: coefficient k = 1 .. M, channel ch of
+   * Gaussian i is the half codebook[sh_index[i] S + (k - 1) 3 + ch], with
+   * the entry stride S = 3M rounded up to a multiple of 8 halves (16-byte
+   * entries: S = 0, 16, 24, 48 for D = 0 .. 3; the padding is not read);
+   * the array is 16-byte aligned.  An index at or above codebook_size is an
+   * error (the forward reads entry 0 instead and reports GSR_EDEVICE through
+   * gsr_forward_check, or for every request of a gsr_render_batch call). */
+  const uint16_t* sh_index; /* uint16[n] */
+  const uint16_t* codebook; /* half[codebook_size][S] */
+  int32_t codebook_size;    /* 1 .. 65536 */
+  int32_t reserved;         /* must be 0 */
+} gsr_compressed;
+
 /* Gaussian arrays (device, structure of arrays, see above; host struct). */
 typedef struct {
   int32_t n;           /* number of Gaussians, >= 0 */
@@ -128,7 +161,11 @@ typedef struct {
                           the kernels apply exp and the logistic function themselves and
                           the backward's g_scale / g_opacity are with respect to these raw
                           values. */
-  int32_t reserved;    /* must be 0 */
+  int32_t format;      /* GSR_FORMAT_F32 (0): the float arrays above.  Otherwise the
+                          attributes are read from *compressed (mean ... sh are not read,
+                          raw must be 0); forward and batch rendering only (the backward
+                          returns GSR_EINVAL).  layer is read in every format. */
+  const gsr_compressed* compressed;  /* host pointer, read during the call; NULL for F32 */
 } gsr_model;
 
 /* Buffers that carry a forward pass to its backward (device, caller-owned;
@@ -244,7 +281,7 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
  * the kernels compute them: for model->raw = 1, exp of the log-scales and
  * the logistic function of the logits (Sec. 3.2 parameters); for raw = 0 a
  * copy.  Outputs are device arrays the caller owns.  Returns GSR_EINVAL on
- * bad arguments; asynchronous on stream. */
+ * bad arguments or a compressed model; asynchronous on stream. */
 gsr_status gsr_activate(const gsr_model* model, float* scale_out, float* opacity_out, void* stream);
 
 /* Forward render of n_views views of one model, all at the same resolution

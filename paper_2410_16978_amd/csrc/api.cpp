@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -256,9 +257,21 @@ hipError_t order_before_pairs(const PipeBufs& b, ViewD* views_dev, int n_views, 
 
 bool model_ok(const gsr_model* m) {
   if (!m || m->n < 0 || m->sh_degree < 0 || m->sh_degree > 3) return false;
-  if ((m->raw != 0 && m->raw != 1) || m->reserved != 0) return false;
-  if (m->n > 0 && (!m->mean || !m->scale || !m->quat || !m->opacity || !m->sh || !m->layer)) return false;
-  return true;
+  if (m->raw != 0 && m->raw != 1) return false;
+  if (m->format == GSR_FORMAT_F32)
+    return m->n == 0 || (m->mean && m->scale && m->quat && m->opacity && m->sh && m->layer);
+  if (m->format != GSR_FORMAT_HALF_PACKED && m->format != GSR_FORMAT_HALF_CODEBOOK) return false;
+  const gsr_compressed* c = m->compressed;
+  if (m->raw != 0 || !c || c->reserved != 0) return false;
+  if (m->n == 0) return true;
+  if (!m->layer || !c->mean || !c->scale || !c->quat || !c->opacity || !c->sh_dc) return false;
+  if (m->sh_degree == 0) return true;  // no higher coefficients to read
+  if (m->format == GSR_FORMAT_HALF_PACKED) {
+    for (int ch = 0; ch < 3; ++ch)
+      if (!std::isfinite(c->sh_lo[ch]) || !std::isfinite(c->sh_step[ch])) return false;
+    return c->sh_packed != nullptr;
+  }
+  return c->sh_index && c->codebook && c->codebook_size >= 1 && c->codebook_size <= 65536;
 }
 
 bool camera_ok(const gsr_camera& c) {
@@ -297,9 +310,18 @@ ViewD make_view(const gsr_camera& c, const gsr_view_state& vs) {
 
 ModelD make_model(const gsr_model& m) {
   ModelD d;
+  std::memset(&d, 0, sizeof(d));
   d.n = m.n; d.D = m.sh_degree;
   d.mean = m.mean; d.scale = m.scale; d.quat = m.quat; d.opacity = m.opacity; d.sh = m.sh; d.layer = m.layer;
   d.raw = m.raw;
+  d.fmt = m.format;
+  if (m.format != GSR_FORMAT_F32 && m.compressed) {
+    const gsr_compressed& c = *m.compressed;
+    d.h_mean = c.mean; d.h_scale = c.scale; d.h_quat = c.quat; d.h_opacity = c.opacity; d.h_dc = c.sh_dc;
+    d.sh_packed = c.sh_packed; d.sh_index = c.sh_index; d.codebook = c.codebook;
+    for (int ch = 0; ch < 3; ++ch) { d.sh_lo[ch] = c.sh_lo[ch]; d.sh_step[ch] = c.sh_step[ch]; }
+    d.codebook_size = (uint32_t)c.codebook_size;
+  }
   return d;
 }
 
@@ -513,7 +535,7 @@ gsr_status forward_impl(const gsr_model* model, int32_t n_views, const gsr_camer
     StageScope sc(timer, GSR_STAGE_PROJECT, s);
     for (const JobD& j : make_jobs(md, ids))
       HIP_TRY(launch_project(j, b.views, state->records, b.n_tiles, b.tile_box, shared ? b.gk_a : nullptr,
-                             shared ? b.gv_a : nullptr, s));
+                             shared ? b.gv_a : nullptr, state->counters, s));
   }
   {
     StageScope sc(timer, GSR_STAGE_SCAN, s);
@@ -679,7 +701,7 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
                                   const gsr_grads* grads, float* max_contrib, float* activity, gsr_timer* timer,
                                   void* stream) {
   if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !grads) return GSR_EINVAL;
-  if (n_views > kMaxJobViews || views[0].sort_shared) return GSR_EINVAL;
+  if (n_views > kMaxJobViews || views[0].sort_shared || model->format != GSR_FORMAT_F32) return GSR_EINVAL;
   if (model->n > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_sh))
     return GSR_EINVAL;
   if (!state_ok(state)) return GSR_EINVAL;
@@ -859,7 +881,7 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
       const ModelD md = make_model(models[m]);
       for (const JobD& j : make_jobs(md, ids))
         HIP_TRY(launch_project(j, b.views, b.records, b.n_tiles, b.tile_box, bp.ordered ? b.gk_a : nullptr,
-                               bp.ordered ? b.gv_a : nullptr, s));
+                               bp.ordered ? b.gv_a : nullptr, b.counters, s));
     }
   }
   {
@@ -918,7 +940,8 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
 }
 
 gsr_status gsr_activate(const gsr_model* model, float* scale_out, float* opacity_out, void* stream) {
-  if (!model_ok(model) || (model->n > 0 && (!scale_out || !opacity_out))) return GSR_EINVAL;
+  if (!model_ok(model) || model->format != GSR_FORMAT_F32 || (model->n > 0 && (!scale_out || !opacity_out)))
+    return GSR_EINVAL;
   HIP_TRY(launch_activate(make_model(*model), scale_out, opacity_out, static_cast<hipStream_t>(stream)));
   return GSR_OK;
 }

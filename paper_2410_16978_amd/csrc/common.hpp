@@ -79,11 +79,19 @@ struct ViewD {
 };
 constexpr uint32_t kSortNone = 0, kSortOwn = 1, kSortCamera = 2, kSortFollow = 3;
 
+constexpr int kFmtF32 = 0, kFmtHalfPacked = 1, kFmtHalfCodebook = 2;
 struct ModelD {
   int32_t n, D;
   const float *mean, *scale, *quat, *opacity, *sh;
   const uint8_t* layer;
   int32_t raw;  // scale / opacity hold log-scales / logits
+  int32_t fmt;  // kFmt*: where the attributes live
+  // compressed attributes (half bit patterns), see gsr_compressed
+  const uint16_t *h_mean, *h_scale, *h_quat, *h_opacity, *h_dc;
+  const uint32_t* sh_packed;
+  const uint16_t *sh_index, *codebook;
+  float sh_lo[3], sh_step[3];
+  uint32_t codebook_size;
 };
 
 // Parameter activations of raw models: scale = exp(log-scale), opacity =
@@ -162,7 +170,8 @@ hipError_t launch_upload(uint32_t* dst, const void* src, size_t n_words, hipStre
 hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out, hipStream_t s);
 hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
-                          uint4* tile_box, uint64_t* sort_keys, uint32_t* sort_vals, hipStream_t s);
+                          uint4* tile_box, uint64_t* sort_keys, uint32_t* sort_vals, uint32_t* counters,
+                          hipStream_t s);
 uint32_t scan_tiles(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint64_t* status, uint32_t* ticket, uint32_t n,
                        uint32_t* counters, uint32_t pair_capacity, hipStream_t s);

@@ -119,22 +119,90 @@ hipError_t launch_activate(const ModelD& m, float* scale_out, float* opacity_out
   return hipGetLastError();
 }
 
+// IEEE binary16 bit pattern to float (v_cvt_f32_f16: exact, every half is
+// a float; half denormals are kept in the default floating-point mode).
+__device__ __forceinline__ float half_bits(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+// Halves per codebook entry: 3 M rounded up to 16 bytes.
+template <int D> constexpr int codebook_stride() { return ((3 * ((D + 1) * (D + 1) - 1)) + 7) & ~7; }
+
+// Attribute loads per storage format: float arrays (activations applied for
+// raw models) or half bit patterns of activated values.
+template <int F>
+__device__ __forceinline__ float ld_attr(const float* f, const uint16_t* h, size_t idx) {
+  if constexpr (F == kFmtF32) return f[idx];
+  else return half_bits(h[idx]);
+}
+template <int F> __device__ __forceinline__ float ld_scale(const ModelD& m, size_t idx) {
+  if constexpr (F == kFmtF32) return act_scale(m.scale[idx], m.raw);
+  else return half_bits(m.h_scale[idx]);
+}
+
+// The (D+1)^2 x 3 SH coefficients of Gaussian i, coefficient-major ([k][ch]).
+template <int D, int F>
+__device__ __forceinline__ void load_sh(const ModelD& m, int i, float* sh, uint32_t* counters) {
+  constexpr int NC = (D + 1) * (D + 1);
+  const size_t n = (size_t)m.n;
+  if constexpr (F == kFmtF32) {
+#pragma unroll
+    for (int k = 0; k < NC * 3; ++k) sh[k] = m.sh[(size_t)k * n + i];
+  } else {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) sh[ch] = half_bits(m.h_dc[(size_t)ch * n + i]);
+    if constexpr (F == kFmtHalfPacked) {
+#pragma unroll
+      for (int k = 1; k < NC; ++k) {
+        const uint32_t w = m.sh_packed[(size_t)(k - 1) * n + i];
+        sh[k * 3 + 0] = m.sh_lo[0] + (float)(w & 0x7FFu) * m.sh_step[0];
+        sh[k * 3 + 1] = m.sh_lo[1] + (float)((w >> 11) & 0x7FFu) * m.sh_step[1];
+        sh[k * 3 + 2] = m.sh_lo[2] + (float)(w >> 22) * m.sh_step[2];
+      }
+    } else {
+      uint32_t idx = m.sh_index[i];
+      if (idx >= m.codebook_size) {
+        atomicOr(&counters[kCntError], 128u);  // index outside the codebook: entry 0 is read
+        idx = 0u;
+      }
+      constexpr int S = codebook_stride<D>();
+      // the entry in 16-byte loads (8 halves each)
+      const uint4* row = reinterpret_cast<const uint4*>(m.codebook + (size_t)idx * S);
+#pragma unroll
+      for (int q = 0; q < S / 8; ++q) {
+        const uint4 w = row[q];
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+          const int k = 3 + 8 * q + h;  // position in sh[]: coefficient-major after the 3 DC values
+          if (k < NC * 3) sh[k] = half_bits((ws[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
+        }
+      }
+    }
+  }
+}
+
 // One thread per Gaussian; the Gaussian's attributes are read once and
 // projected for every view of the job (stereo eyes, training views).  SH
-// coefficients are read only if some view keeps the Gaussian.
-template <int D>
+// coefficients are read only if some view keeps the Gaussian.  F selects
+// the storage format of the attributes (float, or half with packed or
+// codebook SH).
+template <int D, int F>
 __global__ void __launch_bounds__(256)
 k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records,
           uint32_t* __restrict__ n_tiles_out, uint4* __restrict__ tile_box, uint64_t* __restrict__ sort_keys,
-          uint32_t* __restrict__ sort_vals) {
+          uint32_t* __restrict__ sort_vals, uint32_t* __restrict__ counters) {
   constexpr int NC = (D + 1) * (D + 1);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const ModelD& m = job.m;
   if (i >= m.n) return;
   const int n = m.n;
   const uint32_t layer = m.layer[i];
-  const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
-  const float op = act_opacity(m.opacity[i], m.raw);
+  const float mx = ld_attr<F>(m.mean, m.h_mean, i), my = ld_attr<F>(m.mean, m.h_mean, (size_t)n + i),
+              mz = ld_attr<F>(m.mean, m.h_mean, 2 * (size_t)n + i);
+  float op;
+  if constexpr (F == kFmtF32) op = act_opacity(m.opacity[i], m.raw);
+  else op = half_bits(m.h_opacity[i]);
   float sh[NC * 3];
   bool sh_loaded = false;
   float Rq[9];
@@ -165,7 +233,8 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const float opv = op * V.layer_op[layer];  // the view's fading of the layer
       if (opv < kAlphaMin) break;
       if (qn < 0.f) {
-        float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
+        float qw = ld_attr<F>(m.quat, m.h_quat, i), qx = ld_attr<F>(m.quat, m.h_quat, (size_t)n + i),
+              qy = ld_attr<F>(m.quat, m.h_quat, 2 * (size_t)n + i), qz = ld_attr<F>(m.quat, m.h_quat, 3 * (size_t)n + i);
         qn = sqrt_rn(((qw * qw + qx * qx) + qy * qy) + qz * qz);
         if (!(qn > 0.f)) { qn = 0.f; break; }
         qw = __fdiv_rn(qw, qn); qx = __fdiv_rn(qx, qn); qy = __fdiv_rn(qy, qn); qz = __fdiv_rn(qz, qn);
@@ -181,8 +250,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       }
       if (!(qn > 0.f)) break;
       // Sigma = M M^T, M = Rq diag(s)
-      const float s0 = act_scale(m.scale[i], m.raw), s1 = act_scale(m.scale[n + i], m.raw),
-                  s2 = act_scale(m.scale[2 * n + i], m.raw);
+      const float s0 = ld_scale<F>(m, i), s1 = ld_scale<F>(m, (size_t)n + i), s2 = ld_scale<F>(m, 2 * (size_t)n + i);
       float M[9];
 #pragma unroll
       for (int rr = 0; rr < 3; ++rr) {
@@ -249,8 +317,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       float Y[16];
       sh_basis<D>(dirx, diry, dirz, Y);
       if (!sh_loaded) {
-#pragma unroll
-        for (int k = 0; k < NC * 3; ++k) sh[k] = m.sh[(size_t)k * n + i];
+        load_sh<D, F>(m, i, sh, counters);
         sh_loaded = true;
       }
       float rgb[3];
@@ -291,19 +358,40 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
   }
 }
 
-hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
-                          uint4* tile_box, uint64_t* sort_keys, uint32_t* sort_vals, hipStream_t s) {
-  if (job.m.n <= 0 || job.n_views <= 0) return hipSuccess;
+namespace {
+template <int F>
+void launch_project_fmt(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
+                        uint4* tile_box, uint64_t* sort_keys, uint32_t* sort_vals, uint32_t* counters,
+                        hipStream_t s) {
   const dim3 grid(div_up((uint32_t)job.m.n, 256u)), block(256);
   switch (job.m.D) {
-    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
-                               sort_keys, sort_vals); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
-                               sort_keys, sort_vals); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
-                               sort_keys, sort_vals); break;
-    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
-                                sort_keys, sort_vals); break;
+    case 0: hipLaunchKernelGGL((k_project<0, F>), grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                               sort_keys, sort_vals, counters); break;
+    case 1: hipLaunchKernelGGL((k_project<1, F>), grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                               sort_keys, sort_vals, counters); break;
+    case 2: hipLaunchKernelGGL((k_project<2, F>), grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                               sort_keys, sort_vals, counters); break;
+    default: hipLaunchKernelGGL((k_project<3, F>), grid, block, 0, s, job, views_dev, records, n_tiles, tile_box,
+                                sort_keys, sort_vals, counters); break;
+  }
+}
+}  // namespace
+
+hipError_t launch_project(const JobD& job, const ViewD* views_dev, float* records, uint32_t* n_tiles,
+                          uint4* tile_box, uint64_t* sort_keys, uint32_t* sort_vals, uint32_t* counters,
+                          hipStream_t s) {
+  if (job.m.n <= 0 || job.n_views <= 0) return hipSuccess;
+  switch (job.m.fmt) {
+    case kFmtHalfPacked:
+      launch_project_fmt<kFmtHalfPacked>(job, views_dev, records, n_tiles, tile_box, sort_keys, sort_vals, counters, s);
+      break;
+    case kFmtHalfCodebook:
+      launch_project_fmt<kFmtHalfCodebook>(job, views_dev, records, n_tiles, tile_box, sort_keys, sort_vals, counters,
+                                           s);
+      break;
+    default:
+      launch_project_fmt<kFmtF32>(job, views_dev, records, n_tiles, tile_box, sort_keys, sort_vals, counters, s);
+      break;
   }
   return hipGetLastError();
 }

@@ -57,10 +57,20 @@ class ViewState(C.Structure):
                 ("layer_fade", C.c_int32), ("layer_opacity", C.c_float * 32)]
 
 
+class Compressed(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p), ("opacity", C.c_void_p),
+                ("sh_dc", C.c_void_p), ("sh_packed", C.c_void_p), ("sh_lo", C.c_float * 3),
+                ("sh_step", C.c_float * 3), ("sh_index", C.c_void_p), ("codebook", C.c_void_p),
+                ("codebook_size", C.c_int32), ("reserved", C.c_int32)]
+
+
 class Model(C.Structure):
     _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("mean", C.c_void_p), ("scale", C.c_void_p),
                 ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p), ("layer", C.c_void_p),
-                ("raw", C.c_int32), ("reserved", C.c_int32)]
+                ("raw", C.c_int32), ("format", C.c_int32), ("compressed", C.c_void_p)]
+
+
+FORMATS = {"f32": 0, "half_packed": 1, "half_codebook": 2}
 
 
 class FwdState(C.Structure):
@@ -221,7 +231,66 @@ def to_device(scene, device="cuda"):
     return out
 
 
+def to_device_compressed(comp, device="cuda"):
+    """Compressed attribute arrays (compress.compress) -> a model dict for
+    the forward and batch calls (half bit patterns held as int16 tensors,
+    packed words as int32)."""
+    def dev(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a).view(dt)).to(device).contiguous()
+
+    out = {"sh_degree": int(comp["sh_degree"]), "format": comp["format"],
+           "layer": torch.as_tensor(np.ascontiguousarray(comp["layer"], np.uint8)).to(device)}
+    for k in ("mean", "scale", "quat", "opacity", "sh_dc"):
+        out[k] = dev(comp[k], np.int16)
+    cs = Compressed(*[out[k].data_ptr() for k in ("mean", "scale", "quat", "opacity", "sh_dc")])
+    if comp["format"] == "half_packed":
+        out["sh_packed"] = dev(comp["sh_packed"], np.int32)
+        cs.sh_packed = out["sh_packed"].data_ptr() if out["sh_packed"].numel() else None
+        for ch in range(3):
+            cs.sh_lo[ch] = float(comp["sh_lo"][ch])
+            cs.sh_step[ch] = float(comp["sh_step"][ch])
+    elif comp["format"] == "half_codebook":
+        out["sh_index"] = dev(comp["sh_index"], np.int16)
+        out["codebook"] = dev(comp["codebook"], np.int16)
+        cs.sh_index = out["sh_index"].data_ptr()
+        cs.codebook = out["codebook"].data_ptr()
+        cs.codebook_size = int(comp["codebook_size"])
+    else:
+        raise ValueError(f"unknown format {comp['format']!r}")
+    out["_cstruct"] = cs  # host struct the model struct points to (lives with the dict)
+    return out
+
+
+def _compressed_model_struct(model):
+    n = int(model["layer"].shape[0])
+    D = int(model["sh_degree"])
+    M = (D + 1) ** 2 - 1
+    shapes = {"mean": (3, n), "scale": (3, n), "quat": (4, n), "opacity": (n,), "sh_dc": (3, n)}
+    if model["format"] == "half_packed":
+        shapes["sh_packed"] = (M, n)
+    else:
+        shapes["sh_index"] = (n,)
+    for k, shp in shapes.items():
+        t = model[k]
+        if not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp or t.element_size() != (
+                4 if k == "sh_packed" else 2):
+            raise ValueError(f"compressed model[{k!r}]: contiguous CUDA {shp} of 16-bit (32-bit packed) words")
+    if model["format"] == "half_codebook":
+        cb = model["codebook"]
+        S = (3 * M + 7) // 8 * 8
+        if cb.dim() != 2 or cb.shape[1] != S or cb.element_size() != 2 or not cb.is_contiguous() or \
+                cb.data_ptr() % 16:
+            raise ValueError(f"compressed model['codebook']: contiguous 16-byte aligned [K, {S}] half bits")
+    lay = model["layer"]
+    if not lay.is_cuda or lay.dtype != torch.uint8 or tuple(lay.shape) != (n,):
+        raise ValueError("model['layer'] must be a CUDA uint8 tensor [n]")
+    return Model(n, D, None, None, None, None, None, lay.data_ptr(), 0, FORMATS[model["format"]],
+                 C.addressof(model["_cstruct"]))
+
+
 def model_struct(model):
+    if model.get("format", "f32") != "f32":
+        return _compressed_model_struct(model)
     n = int(model["layer"].shape[0])
     D = int(model["sh_degree"])
     nc = (D + 1) ** 2
@@ -234,7 +303,7 @@ def model_struct(model):
         want = torch.uint8 if k == "layer" else torch.float32
         if t.dtype != want:
             raise ValueError(f"model[{k!r}] must be {want}")
-    return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS], 1 if model.get("raw", False) else 0, 0)
+    return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS], 1 if model.get("raw", False) else 0, 0, None)
 
 
 def activate(model, stream=None):

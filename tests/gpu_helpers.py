@@ -7,9 +7,11 @@ IMAGE_TOL = 1e-4  # max-abs on images, FP32
 GRAD_RTOL = 1e-3  # relative error of gradients
 
 
-def gpu_forward(scene, cams, views, debug=True, capacity=None):
+def gpu_forward(scene, cams, views, debug=True, capacity=None, model=None):
+    """model (optional): a device model to render instead of scene's."""
     from paper_2410_16978_amd import rasterizer as rz
-    model = rz.to_device(scene)
+    if model is None:
+        model = rz.to_device(scene)
     res = rz.rasterize_forward(model, cams, views, debug=debug, capacity=capacity)
     torch.cuda.synchronize()
     return model, res
@@ -23,13 +25,15 @@ def oracle_rect_to_box(rect, depth, tile_off, tiles_x):
                      np.full_like(base, tiles_x)], 1).astype(np.uint32)
 
 
-def compare_forward(scene, cams, views, orc, check_pairs=True, label="", max_flagged=None):
+def compare_forward(scene, cams, views, orc, check_pairs=True, label="", max_flagged=None, device_model=None):
     """Run both paths and assert the parity bar; returns a stats dict.  With
     a shared depth order (views[0]["sort_cam"]) the oracle sorts every view
     by the depth in that camera and the emission order differs by design
     (the GPU emits each view's pairs in the sorted Gaussian order), so the
-    emitted keys are compared as multisets."""
-    model, (rgb, alpha, st, dbg) = gpu_forward(scene, cams, views)
+    emitted keys are compared as multisets.  device_model (optional): the
+    device model the GPU renders (a compressed one, whose decoded scene is
+    `scene`)."""
+    model, (rgb, alpha, st, dbg) = gpu_forward(scene, cams, views, model=device_model)
     sort_cam = views[0].get("sort_cam")
     ref = orc.render(scene, cams, views, pairs=check_pairs, n_threads=0,
                      sort_cams=None if sort_cam is None else [sort_cam] * len(cams))

@@ -62,7 +62,9 @@ int main(void) {
   P(gsr_clip_plane); P(gsr_view_state); O(gsr_view_state, clip); O(gsr_view_state, bg);
   O(gsr_view_state, sort_shared); O(gsr_view_state, sort_cam); O(gsr_view_state, layer_fade);
   O(gsr_view_state, layer_opacity); O(gsr_grads, densify_grad); O(gsr_grads, densify_count);
-  P(gsr_model); O(gsr_model, mean); O(gsr_model, layer);
+  P(gsr_model); O(gsr_model, mean); O(gsr_model, layer); O(gsr_model, format); O(gsr_model, compressed);
+  P(gsr_compressed); O(gsr_compressed, sh_packed); O(gsr_compressed, sh_lo); O(gsr_compressed, sh_index);
+  O(gsr_compressed, codebook_size);
   P(gsr_fwd_state); O(gsr_fwd_state, pixel_state); O(gsr_fwd_state, pair_capacity);
   O(gsr_fwd_state, batch_capacity);
   P(gsr_debug); P(gsr_grads);
@@ -81,7 +83,7 @@ def test_binding_struct_layout_matches_header(tmp_path):
     got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().splitlines())
     py = {"gsr_camera": rz.Camera, "gsr_clip_plane": rz.ClipPlane, "gsr_view_state": rz.ViewState,
           "gsr_model": rz.Model, "gsr_fwd_state": rz.FwdState, "gsr_debug": rz.Debug, "gsr_grads": rz.Grads,
-          "gsr_request": rz.Request}
+          "gsr_request": rz.Request, "gsr_compressed": rz.Compressed}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
