@@ -115,6 +115,14 @@ typedef struct {
    * i.e. layer_opacity[l] times that of the product).  Factors in [0, 1]. */
   int32_t layer_fade;
   float layer_opacity[32];
+  /* Mip-Splatting's 2D filter (the anti-aliasing Sec. 4.4 reports trying;
+   * forward only).  0: off, the screen-space covariance is dilated by 0.3 px^2.
+   * 1: it is dilated by mip_2d_var px^2 instead (> 0) and the opacity is
+   * multiplied by sqrt(max(det S, 0) / det(S + mip_2d_var I)), S the
+   * undilated screen-space covariance (float32: det S = s00 s11 - s01 s01,
+   * the quotient, its correctly rounded square root). */
+  int32_t mip_2d;
+  float mip_2d_var;
 } gsr_view_state;
 
 /* Compressed attributes for rendering (device arrays, structure of arrays;
@@ -166,6 +174,12 @@ typedef struct {
                           raw must be 0); forward and batch rendering only (the backward
                           returns GSR_EINVAL).  layer is read in every format. */
   const gsr_compressed* compressed;  /* host pointer, read during the call; NULL for F32 */
+  /* Mip-Splatting's 3D filter (optional, forward only; NULL: none): device
+   * float[n] variances f^2.  Gaussian i is drawn with scales
+   * sqrt(s_k^2 + f^2) and opacity o * sqrt((s_0^2 s_1^2) s_2^2 / ((p_0 p_1) p_2)),
+   * p_k = s_k^2 + f^2 (float32, in that order, square roots correctly
+   * rounded): the Gaussian convolved with an isotropic one of variance f^2. */
+  const float* filter_3d;
 } gsr_model;
 
 /* Buffers that carry a forward pass to its backward (device, caller-owned;

@@ -29,13 +29,15 @@ class Clip(C.Structure):
 
 class View(C.Structure):
     _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", Clip * 8), ("bg", C.c_float * 3),
-                ("layer_fade", C.c_int32), ("layer_opacity", C.c_float * 32)]
+                ("layer_fade", C.c_int32), ("layer_opacity", C.c_float * 32), ("mip_2d", C.c_int32),
+                ("mip_2d_var", C.c_float)]
 
 
 def _model_struct(ptr_t):
     class M(C.Structure):
         _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("mean", ptr_t), ("scale", ptr_t),
-                    ("quat", ptr_t), ("opacity", ptr_t), ("sh", ptr_t), ("layer", C.POINTER(C.c_uint8))]
+                    ("quat", ptr_t), ("opacity", ptr_t), ("sh", ptr_t), ("layer", C.POINTER(C.c_uint8)),
+                    ("filter_3d", ptr_t)]
     return M
 
 
@@ -113,6 +115,9 @@ def view_struct(vs):
         v.layer_fade = 1
         for l, f in enumerate(vs["layer_opacity"]):
             v.layer_opacity[l] = float(f)
+    if vs.get("mip_2d_var") is not None:
+        v.mip_2d = 1
+        v.mip_2d_var = float(vs["mip_2d_var"])
     return v
 
 
@@ -125,10 +130,14 @@ class _ModelArrays:
         self.arrs = {k: np.ascontiguousarray(scene[k], dtype=self.dtype)
                      for k in ("mean", "scale", "quat", "opacity", "sh")}
         self.layer = np.ascontiguousarray(scene["layer"], dtype=np.uint8)
+        self.filter_3d = None
+        if scene.get("filter_3d") is not None:
+            self.filter_3d = np.ascontiguousarray(scene["filter_3d"], dtype=self.dtype)
         M = Model32 if self.dtype == np.float32 else Model64
         self.struct = M(int(self.layer.shape[0]), int(scene["sh_degree"]),
                         *[_ptr(self.arrs[k], ct) for k in ("mean", "scale", "quat", "opacity", "sh")],
-                        _ptr(self.layer, C.c_uint8))
+                        _ptr(self.layer, C.c_uint8),
+                        None if self.filter_3d is None else _ptr(self.filter_3d, ct))
 
 
 def render(scenes, cams, views, tile=16, brute_force=False, dtype=np.float32, pairs=False, n_threads=0,

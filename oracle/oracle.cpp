@@ -45,6 +45,7 @@ template <typename T> struct Model {
   int n, D;
   const T *mean, *scale, *quat, *opacity, *sh;
   const uint8_t* layer;
+  const T* filter3d = nullptr;  // Mip-Splatting 3D filter variances, or null
 };
 
 template <typename T> struct Consts {
@@ -199,7 +200,18 @@ Proj<T> project_one(const Model<T>& m, int i, const Cam<T>& cam, const oc_view& 
   Rq[7] = T(2) * (qy * qz + qw * qx);
   Rq[8] = T(1) - T(2) * (qx * qx + qy * qy);
   // Sigma = M M^T with M = Rq diag(s).
-  const T s0 = m.scale[i], s1 = m.scale[n + i], s2 = m.scale[2 * n + i];
+  T s0 = m.scale[i], s1 = m.scale[n + i], s2 = m.scale[2 * n + i];
+  if (m.filter3d) {
+    // Mip-Splatting's 3D filter: convolving with an isotropic Gaussian of
+    // variance f2 adds f2 to every principal variance (R diag(s^2) R^T +
+    // f2 I = R diag(s^2 + f2) R^T); the peak scales by the ratio of the
+    // square roots of the determinants, which preserves the integral.
+    const T f2 = m.filter3d[i];
+    const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
+    const T p0 = q0 + f2, p1 = q1 + f2, p2 = q2 + f2;
+    s0 = std::sqrt(p0); s1 = std::sqrt(p1); s2 = std::sqrt(p2);
+    p.op = p.op * std::sqrt(((q0 * q1) * q2) / ((p0 * p1) * p2));
+  }
   for (int r = 0; r < 3; ++r) {
     p.M[3 * r + 0] = Rq[3 * r + 0] * s0;
     p.M[3 * r + 1] = Rq[3 * r + 1] * s1;
@@ -238,11 +250,19 @@ Proj<T> project_one(const Model<T>& m, int i, const Cam<T>& cam, const oc_view& 
   const T s00 = (U[0] * Tm[0] + U[1] * Tm[1]) + U[2] * Tm[2];
   const T s01 = (U[0] * Tm[3] + U[1] * Tm[4]) + U[2] * Tm[5];
   const T s11 = (U[3] * Tm[3] + U[4] * Tm[4]) + U[5] * Tm[5];
-  p.a = s00 + Consts<T>::kappa();
+  // Screen-space low-pass: the fixed dilation, or Mip-Splatting's 2D filter
+  // (its variance instead, and the peak scaled so the integral is kept).
+  const T dil = vs.mip_2d ? T(vs.mip_2d_var) : Consts<T>::kappa();
+  p.a = s00 + dil;
   p.b = s01;
-  p.c = s11 + Consts<T>::kappa();
+  p.c = s11 + dil;
   p.det = p.a * p.c - p.b * p.b;
   if (!(p.det > T(0))) return p;
+  if (vs.mip_2d) {
+    const T det0 = s00 * s11 - s01 * s01;
+    p.op = p.op * std::sqrt(std::max(det0, T(0)) / p.det);
+  }
+  if (p.op < Consts<T>::alpha_min()) return p;
   p.ca = p.c / p.det;
   p.cb = -p.b / p.det;
   p.cc = p.a / p.det;
@@ -773,6 +793,9 @@ int backward(int n_views, const Model<TF>& m, const oc_camera* cams, const oc_vi
              TG* g_sh, TG* max_contrib, TG* activity, int n_threads, bool fwd_values = false,
              TG* cond = nullptr, TG* dens_grad = nullptr, TG* dens_cnt = nullptr) {
   if (n_views < 0 || m.n < 0 || m.D < 0 || m.D > 3) return -1;
+  if (m.filter3d) return -1;  // the Mip filters are forward-only
+  for (int v = 0; v < n_views; ++v)
+    if (views[v].mip_2d) return -1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
@@ -993,6 +1016,7 @@ template <typename T, typename MS> Model<T> to_model(const MS& s) {
   m.n = s.n; m.D = s.sh_degree;
   m.mean = s.mean; m.scale = s.scale; m.quat = s.quat; m.opacity = s.opacity; m.sh = s.sh;
   m.layer = s.layer;
+  m.filter3d = s.filter_3d;
   return m;
 }
 

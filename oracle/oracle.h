@@ -55,6 +55,14 @@ typedef struct {
    * l is drawn with opacity o * layer_opacity[l]; zero leaves o alone */
   int32_t layer_fade;
   float layer_opacity[32];
+  /* Mip-Splatting's 2D filter (forward only): when mip_2d is non-zero the
+   * screen-space covariance S is dilated by mip_2d_var instead of 0.3 and the
+   * opacity multiplied by sqrt(max(det S, 0) / det(S + mip_2d_var I)).  A
+   * model's filter_3d (variances f^2) widens each scale to sqrt(s^2 + f^2)
+   * and multiplies the opacity by sqrt(prod s^2 / prod (s^2 + f^2)).  The
+   * backward rejects both. */
+  int32_t mip_2d;
+  float mip_2d_var;
 } oc_view;
 
 /* Gaussian arrays, structure of arrays.  mean[3][n], scale[3][n] (activated),
@@ -63,12 +71,14 @@ typedef struct {
   int32_t n, sh_degree;
   const float *mean, *scale, *quat, *opacity, *sh;
   const uint8_t* layer;
+  const float* filter_3d;  /* optional Mip-Splatting 3D filter variances [n], or NULL */
 } oc_model32;
 
 typedef struct {
   int32_t n, sh_degree;
   const double *mean, *scale, *quat, *opacity, *sh;
   const uint8_t* layer;
+  const double* filter_3d;
 } oc_model64;
 
 /* Outputs of a render; every pointer may be NULL.  Views are concatenated in

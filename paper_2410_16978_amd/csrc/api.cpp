@@ -280,6 +280,7 @@ bool camera_ok(const gsr_camera& c) {
 }
 
 bool view_ok(const gsr_view_state& v) {
+  if (v.mip_2d != 0 && (v.mip_2d != 1 || !(v.mip_2d_var > 0.f) || !std::isfinite(v.mip_2d_var))) return false;
   return v.n_clip >= 0 && v.n_clip <= GSR_MAX_CLIP && (v.sort_shared == 0 || v.sort_shared == 1);
 }
 
@@ -305,6 +306,8 @@ ViewD make_view(const gsr_camera& c, const gsr_view_state& vs) {
   }
   for (int j = 0; j < 3; ++j) v.bg[j] = vs.bg[j];
   for (int l = 0; l < 32; ++l) v.layer_op[l] = vs.layer_fade ? vs.layer_opacity[l] : 1.f;
+  v.mip_2d = vs.mip_2d ? 1u : 0u;
+  v.mip_var = vs.mip_2d_var;
   return v;
 }
 
@@ -315,6 +318,7 @@ ModelD make_model(const gsr_model& m) {
   d.mean = m.mean; d.scale = m.scale; d.quat = m.quat; d.opacity = m.opacity; d.sh = m.sh; d.layer = m.layer;
   d.raw = m.raw;
   d.fmt = m.format;
+  d.filter_3d = m.filter_3d;
   if (m.format != GSR_FORMAT_F32 && m.compressed) {
     const gsr_compressed& c = *m.compressed;
     d.h_mean = c.mean; d.h_scale = c.scale; d.h_quat = c.quat; d.h_opacity = c.opacity; d.h_dc = c.sh_dc;
@@ -701,7 +705,10 @@ gsr_status gsr_rasterize_backward(const gsr_model* model, int32_t n_views, const
                                   const gsr_grads* grads, float* max_contrib, float* activity, gsr_timer* timer,
                                   void* stream) {
   if (!single_view_args_ok(model, n_views, cams, views) || !state || !ws || !grads) return GSR_EINVAL;
-  if (n_views > kMaxJobViews || views[0].sort_shared || model->format != GSR_FORMAT_F32) return GSR_EINVAL;
+  if (n_views > kMaxJobViews || views[0].sort_shared || model->format != GSR_FORMAT_F32 || model->filter_3d)
+    return GSR_EINVAL;
+  for (int v = 0; v < n_views; ++v)
+    if (views[v].mip_2d) return GSR_EINVAL;  // the Mip filters are rendered, not differentiated
   if (model->n > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_sh))
     return GSR_EINVAL;
   if (!state_ok(state)) return GSR_EINVAL;

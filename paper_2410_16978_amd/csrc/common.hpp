@@ -76,6 +76,8 @@ struct ViewD {
   float sort_r[3];
   float sort_t;
   float layer_op[32];  // opacity factor per layer (1 when the view has no fading)
+  uint32_t mip_2d;     // Mip-Splatting 2D filter: dilation mip_var, opacity compensated
+  float mip_var;
 };
 constexpr uint32_t kSortNone = 0, kSortOwn = 1, kSortCamera = 2, kSortFollow = 3;
 
@@ -92,6 +94,7 @@ struct ModelD {
   const uint16_t *sh_index, *codebook;
   float sh_lo[3], sh_step[3];
   uint32_t codebook_size;
+  const float* filter_3d;  // Mip-Splatting 3D filter variances, or null
 };
 
 // Parameter activations of raw models: scale = exp(log-scale), opacity =

@@ -250,7 +250,16 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       }
       if (!(qn > 0.f)) break;
       // Sigma = M M^T, M = Rq diag(s)
-      const float s0 = ld_scale<F>(m, i), s1 = ld_scale<F>(m, (size_t)n + i), s2 = ld_scale<F>(m, 2 * (size_t)n + i);
+      float s0 = ld_scale<F>(m, i), s1 = ld_scale<F>(m, (size_t)n + i), s2 = ld_scale<F>(m, 2 * (size_t)n + i);
+      float opf = opv;  // opacity after the Mip filters
+      if (m.filter_3d) {
+        // 3D filter: the Gaussian convolved with an isotropic one of variance f2
+        const float f2 = m.filter_3d[i];
+        const float q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
+        const float p0 = q0 + f2, p1 = q1 + f2, p2 = q2 + f2;
+        s0 = sqrt_rn(p0); s1 = sqrt_rn(p1); s2 = sqrt_rn(p2);
+        opf = opf * sqrt_rn(__fdiv_rn((q0 * q1) * q2, (p0 * p1) * p2));
+      }
       float M[9];
 #pragma unroll
       for (int rr = 0; rr < 3; ++rr) {
@@ -290,9 +299,16 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const float s00 = (U[0] * Tm[0] + U[1] * Tm[1]) + U[2] * Tm[2];
       const float s01 = (U[0] * Tm[3] + U[1] * Tm[4]) + U[2] * Tm[5];
       const float s11 = (U[3] * Tm[3] + U[4] * Tm[4]) + U[5] * Tm[5];
-      const float a = s00 + kKappa, b = s01, c = s11 + kKappa;
+      const float dil = V.mip_2d ? V.mip_var : kKappa;
+      const float a = s00 + dil, b = s01, c = s11 + dil;
       const float det = a * c - b * b;
       if (!(det > 0.f)) break;
+      if (V.mip_2d) {
+        // 2D Mip filter: the dilation's opacity compensation
+        const float det0 = s00 * s11 - s01 * s01;
+        opf = opf * sqrt_rn(__fdiv_rn(fmaxf(det0, 0.f), det));
+      }
+      if (opf < kAlphaMin) break;
       const float ca = __fdiv_rn(c, det), cb = __fdiv_rn(-b, det), cc = __fdiv_rn(a, det);
       const float u = __fdiv_rn(V.fx * tx, tz) + V.cx;
       const float v = __fdiv_rn(V.fy * ty, tz) + V.cy;
@@ -333,7 +349,7 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       }
       float4* rec = reinterpret_cast<float4*>(records + (size_t)r * kRecordFloats);
       rec[0] = make_float4(u, v, ca, cb);
-      rec[1] = make_float4(cc, opv, rgb[0], rgb[1]);
+      rec[1] = make_float4(cc, opf, rgb[0], rgb[1]);
       rec[2] = make_float4(rgb[2], tz, __uint_as_float(clamp_bits), __uint_as_float(nt));
       const uint32_t base_tile = V.tile_off + (uint32_t)y0 * (uint32_t)V.tiles_x + (uint32_t)x0;
       tile_box[r] = make_uint4(base_tile, (uint32_t)(x1 - x0) | ((uint32_t)(y1 - y0) << 16),

@@ -54,7 +54,8 @@ class ClipPlane(C.Structure):
 class ViewState(C.Structure):
     _fields_ = [("layer_mask", C.c_uint32), ("n_clip", C.c_int32), ("clip", ClipPlane * MAX_CLIP),
                 ("bg", C.c_float * 3), ("sort_shared", C.c_int32), ("sort_cam", Camera),
-                ("layer_fade", C.c_int32), ("layer_opacity", C.c_float * 32)]
+                ("layer_fade", C.c_int32), ("layer_opacity", C.c_float * 32), ("mip_2d", C.c_int32),
+                ("mip_2d_var", C.c_float)]
 
 
 class Compressed(C.Structure):
@@ -67,7 +68,7 @@ class Compressed(C.Structure):
 class Model(C.Structure):
     _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("mean", C.c_void_p), ("scale", C.c_void_p),
                 ("quat", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p), ("layer", C.c_void_p),
-                ("raw", C.c_int32), ("format", C.c_int32), ("compressed", C.c_void_p)]
+                ("raw", C.c_int32), ("format", C.c_int32), ("compressed", C.c_void_p), ("filter_3d", C.c_void_p)]
 
 
 FORMATS = {"f32": 0, "half_packed": 1, "half_codebook": 2}
@@ -210,6 +211,9 @@ def view_struct(vs):
         v.layer_fade = 1
         for l, f in enumerate(fade):
             v.layer_opacity[l] = float(f)
+    if vs.get("mip_2d_var") is not None:  # Mip-Splatting 2D filter of this variance
+        v.mip_2d = 1
+        v.mip_2d_var = float(vs["mip_2d_var"])
     return v
 
 
@@ -228,6 +232,8 @@ def to_device(scene, device="cuda"):
         a = scene[k]
         dtype = torch.uint8 if k == "layer" else torch.float32
         out[k] = torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).contiguous()
+    if scene.get("filter_3d") is not None:  # Mip-Splatting 3D filter variances
+        out["filter_3d"] = torch.as_tensor(np.ascontiguousarray(scene["filter_3d"], np.float32)).to(device)
     return out
 
 
@@ -258,7 +264,19 @@ def to_device_compressed(comp, device="cuda"):
     else:
         raise ValueError(f"unknown format {comp['format']!r}")
     out["_cstruct"] = cs  # host struct the model struct points to (lives with the dict)
+    if comp.get("filter_3d") is not None:
+        out["filter_3d"] = torch.as_tensor(np.ascontiguousarray(comp["filter_3d"], np.float32)).to(device)
     return out
+
+
+def _filter_3d_ptr(model, n):
+    """Device pointer of the optional Mip-Splatting 3D filter variances."""
+    f = model.get("filter_3d")
+    if f is None:
+        return None
+    if not f.is_cuda or f.dtype != torch.float32 or tuple(f.shape) != (n,) or not f.is_contiguous():
+        raise ValueError("model['filter_3d'] must be a contiguous CUDA float32 tensor [n]")
+    return f.data_ptr()
 
 
 def _compressed_model_struct(model):
@@ -285,7 +303,7 @@ def _compressed_model_struct(model):
     if not lay.is_cuda or lay.dtype != torch.uint8 or tuple(lay.shape) != (n,):
         raise ValueError("model['layer'] must be a CUDA uint8 tensor [n]")
     return Model(n, D, None, None, None, None, None, lay.data_ptr(), 0, FORMATS[model["format"]],
-                 C.addressof(model["_cstruct"]))
+                 C.addressof(model["_cstruct"]), _filter_3d_ptr(model, n))
 
 
 def model_struct(model):
@@ -303,7 +321,8 @@ def model_struct(model):
         want = torch.uint8 if k == "layer" else torch.float32
         if t.dtype != want:
             raise ValueError(f"model[{k!r}] must be {want}")
-    return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS], 1 if model.get("raw", False) else 0, 0, None)
+    return Model(n, D, *[model[k].data_ptr() for k in _MODEL_KEYS], 1 if model.get("raw", False) else 0, 0, None,
+                 _filter_3d_ptr(model, n))
 
 
 def activate(model, stream=None):

@@ -295,12 +295,15 @@ def camera_center(cam):
 # --------------------------------------------------------------------------
 # view state: layer-activation mask, clip planes, background
 # --------------------------------------------------------------------------
-def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0), sort_cam=None, layer_opacity=None):
+def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0), sort_cam=None, layer_opacity=None,
+               mip_2d_var=None):
     """sort_cam (optional): one depth order for all views of the call, the
     depth in this camera (the eye centre of a stereo frame).
     layer_opacity (optional): up to 32 factors in [0, 1], one per layer; a
     Gaussian of layer l is drawn with its opacity times factor l (layers not
-    listed keep factor 0)."""
+    listed keep factor 0).
+    mip_2d_var (optional): render with Mip-Splatting's 2D filter of this
+    variance (px^2) instead of the fixed 0.3 px^2 dilation."""
     clips = list(clips)
     assert len(clips) <= MAX_CLIP
     vs = {
@@ -315,6 +318,9 @@ def view_state(layer_mask=0xFFFFFFFF, clips=(), bg=(0.0, 0.0, 0.0), sort_cam=Non
         f = np.asarray(layer_opacity, np.float32).reshape(-1)
         assert f.size <= 32 and np.all((f >= 0) & (f <= 1))
         vs["layer_opacity"] = np.concatenate([f, np.zeros(32 - f.size, np.float32)])
+    if mip_2d_var is not None:
+        assert mip_2d_var > 0
+        vs["mip_2d_var"] = float(np.float32(mip_2d_var))
     return vs
 
 

@@ -62,7 +62,8 @@ int main(void) {
   P(gsr_clip_plane); P(gsr_view_state); O(gsr_view_state, clip); O(gsr_view_state, bg);
   O(gsr_view_state, sort_shared); O(gsr_view_state, sort_cam); O(gsr_view_state, layer_fade);
   O(gsr_view_state, layer_opacity); O(gsr_grads, densify_grad); O(gsr_grads, densify_count);
-  P(gsr_model); O(gsr_model, mean); O(gsr_model, layer); O(gsr_model, format); O(gsr_model, compressed);
+  P(gsr_model); O(gsr_model, mean); O(gsr_model, layer); O(gsr_model, format); O(gsr_model, compressed); O(gsr_model, filter_3d);
+  O(gsr_view_state, mip_2d); O(gsr_view_state, mip_2d_var);
   P(gsr_compressed); O(gsr_compressed, sh_packed); O(gsr_compressed, sh_lo); O(gsr_compressed, sh_index);
   O(gsr_compressed, codebook_size);
   P(gsr_fwd_state); O(gsr_fwd_state, pixel_state); O(gsr_fwd_state, pair_capacity);

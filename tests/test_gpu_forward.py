@@ -230,3 +230,36 @@ def test_layer_fading(orc):
                              layer_opacity=[1.0, 0.3, 0.012, 0.75]),
            scenes.view_state(0b1011, layer_opacity=[0.0, 0.5, 1.0, 1.0])]
     print("fading:", compare_forward(sc, cams, vss, orc, label="fading"))
+
+
+def test_mip_filters(orc):
+    """Mip-Splatting's 2D filter (per view) and 3D filter (per Gaussian
+    variances from the cameras): records bit-exact, images within the bar;
+    also from compressed attributes."""
+    from paper_2410_16978_amd import compress, mip
+    from paper_2410_16978_amd import rasterizer as rz
+    from oracle import compressed as oc
+    sc = small_layered_scene(seed=14, n_per_layer=400)
+    cams = scenes.stereo_cameras([0.2, 0.4, -1.0], 96, 72)
+    scenes.enforce_distinct_depths(sc, cams)
+    sc["filter_3d"] = mip.filter_3d_variance(sc["mean"], cams) * 50.0  # widened to matter at this size
+    vs = scenes.view_state(0b111, bg=(0.1, 0.2, 0.3), mip_2d_var=0.1)
+    print("mip:", compare_forward(sc, cams, [vs, vs], orc, label="mip"))
+    comp = compress.compress(sc, "packed")
+    comp["filter_3d"] = sc["filter_3d"]
+    dec = oc.decode(comp)
+    dec["filter_3d"] = sc["filter_3d"]
+    print("mip packed:", compare_forward(dec, cams, [vs, vs], orc, label="mip packed",
+                                         device_model=rz.to_device_compressed(comp)))
+
+
+def test_mip_filters_are_forward_only():
+    import torch
+    from paper_2410_16978_amd import rasterizer as rz
+    sc = small_layered_scene(seed=15, n_per_layer=50)
+    cam = scenes.orbit_camera([0.2, 0.4, -1.0], 32, 32)
+    model = rz.to_device(sc)
+    vs = scenes.view_state(mip_2d_var=0.1)
+    rgb, alpha, st = rz.rasterize_forward(model, [cam], [vs])
+    with pytest.raises(rz.GsrError):
+        rz.rasterize_backward(model, [cam], [vs], st, torch.zeros_like(rgb), torch.zeros_like(alpha))
