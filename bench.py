@@ -650,7 +650,8 @@ def main():
                                                warmup=max(2, min(args.warmup, 5)))
         result["serving"] = bench_serving(rz, scenes, torch, args.serve_seconds, rates=(200.0, 800.0))
         if args.extra_train_steps > 0:
-            sub = argparse.Namespace(warmup=3, train_steps=args.extra_train_steps)
+            sub = argparse.Namespace(warmup=3, train_steps=args.extra_train_steps, activity_measure=args.activity_measure,
+                                     prune_threshold=args.prune_threshold)
             lt = bench_layered_training(sub, torch, rz, ag, scenes)
             result["layered_training_4m"] = {k: lt[k] for k in (
                 "value", "unit", "steps", "ms_per_step", "plain_ms_per_step", "speedup_vs_plain", "prunes",
