@@ -224,3 +224,34 @@ def test_density_control_statistic_matches_oracle(orc):
     ex = checked_exempt(orc, sc, cams, vss, rgb.cpu().numpy(), alpha.cpu().numpy(), last, st.final_T.cpu().numpy(),
                         "densify")
     assert_grad_close(got_g, ref["densify_grad"], sens["densify_grad"], "densify_grad", ex, g32["densify_grad"])
+
+
+def test_gradients_of_large_splats_with_long_pair_lists(orc):
+    """Splats covering dozens of tiles (up to 72 pairs per record, each
+    record's pair partials summed over a long list): gradients match and stay
+    bitwise reproducible."""
+    sc = scenes.shell_scene(120, 3, 2, seed=33, log_scale_mu=-2.3, log_scale_sigma=0.5, opacity="normal")
+    cams = [scenes.orbit_camera([0.3, 0.2, -1.0], 256, 192), scenes.orbit_camera([-0.4, 0.3, -1.0], 256, 192)]
+    scenes.enforce_distinct_depths(sc, cams)
+    vss = [scenes.view_state(0b111, bg=(0.2, 0.3, 0.1))] * 2
+    rng = np.random.default_rng(33)
+    Gr = rng.standard_normal((2, 3, 192, 256)).astype(np.float32)
+    Ga = rng.standard_normal((2, 192, 256)).astype(np.float32)
+    nt = orc.render(sc, cams, vss)["n_tiles"]
+    assert (nt >= 18).sum() > 50 and nt.max() > 64  # many split records, some past a full wave
+    got = _gpu_grads(sc, cams, vss, Gr, Ga)
+    again = _gpu_grads(sc, cams, vss, Gr, Ga)
+    for k in ("mean", "scale", "quat", "opacity", "sh", "max_contrib"):
+        np.testing.assert_array_equal(got[k], again[k])
+    ref, sens, g32 = grad_refs(orc, sc, cams, vss, Gr, Ga)
+    # a large splat's 1/255 boundary crosses many pixels, so more records than
+    # in the other scenes have a decision within rounding of its threshold in
+    # the oracle itself (8 of 360): the exemption's cap is 3 % here.  Other
+    # seeds of this recipe: 31 leaves one SH entry at 1.08 x the plain bar
+    # (inside the sensitivity bar; the float32 oracle has none there), 32 has
+    # one pixel decided the other way whose tile list exempts 155 Gaussians
+    ex = checked_exempt(orc, sc, cams, vss, got["rgb"], got["alpha"], got["last"], got["final_T"], "large splats",
+                        cap=0.03)
+    for k in ("mean", "scale", "quat", "opacity", "sh", "activity"):
+        assert_grad_close(got[k], ref[k], sens[k], k, ex, g32[k])
+    np.testing.assert_allclose(got["max_contrib"][~ex], ref["max_contrib"][~ex], rtol=1e-4, atol=1e-7)
