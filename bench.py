@@ -358,7 +358,7 @@ def bench_layered_training(args, torch, rz, ag, scenes):
     (Sec. 3.2.2) - iters/s and the pruned fraction per criterion; and the
     plain path (8 sequential single-view launches per step) for the same
     steps."""
-    from paper_2410_16978_amd.train import LayeredTrainer, PruneConfig
+    from paper_2410_16978_amd.train import FusedAdam, LayeredTrainer, PruneConfig
     wl = scenes.layered_training_4m()
     pool = wl.extra["pool"]
     tgt = rz.to_device(wl.extra["target_scene"])
@@ -397,7 +397,7 @@ def bench_layered_training(args, torch, rz, ag, scenes):
     # plain: the same training, one view per launch (8 launches per step)
     plain_steps = max(5, min(steps // 10, 20))
     params = {k: v.detach().clone().requires_grad_(True) for k, v in tr.params.items()}
-    opt = torch.optim.Adam([params[k] for k in params], lr=1e-4, eps=1e-15)
+    opt = FusedAdam(params, tr.lrs)
     ctxs = [ag.RenderContext(trainable_layers=trainable) for _ in range(8)]
     rng = np.random.default_rng(1)
     for it in range(plain_steps + 2):
@@ -406,12 +406,13 @@ def bench_layered_training(args, torch, rz, ag, scenes):
             tp = time.perf_counter()
         idx = rng.choice(len(pool), 8, replace=False)
         bg = tuple(float(x) for x in rng.uniform(0, 1, 3))
-        opt.zero_grad(set_to_none=True)
+        for p in params.values():
+            p.grad = None
         for v, i in enumerate(idx):
             rgb, alpha = ag.render_params(params, tr.layer, tr.sh_degree, [pool[i]], [scenes.view_state(bg=bg)],
                                           ctxs[v])
             (ag.l1_alpha_loss(rgb, alpha, t_rgb[i:i + 1], t_alpha[i:i + 1], [bg]) / 8.0).backward()
-        opt.step()
+        opt.step(params, tr.layer, tr.sh_degree, trainable)
     torch.cuda.synchronize()
     dt_plain = (time.perf_counter() - tp) / plain_steps
     pr = {"activity": [p["activity"] for p in prunes], "max_contrib": [p["max_contrib"] for p in prunes],

@@ -419,6 +419,30 @@ gsr_status gsr_render_batch(const gsr_model* models, int32_t n_models, const gsr
                             int32_t n_req, uint32_t pair_capacity, void* ws, size_t ws_bytes,
                             int32_t* req_status, gsr_timer* timer, void* stream);
 
+/* One Adam step on the parameters of the Gaussians of the trainable layers
+ * (Sec. 3.2: earlier layers are frozen while a layer trains; their
+ * gradients are zero, so Adam leaves them unchanged: they are skipped and
+ * none of their values is read or written).  groups[5] are, in order, the
+ * mean [3][n], log-scale [3][n], quaternion [4][n], opacity logit [n] and
+ * SH [(D+1)^2][3][n] planes, each with its gradient, first and second
+ * moments (same layout) and learning rate.  Per value, t = step >= 1:
+ *   m <- m + (1 - beta1) (g - m);  v <- beta2 v + (1 - beta2) g^2;
+ *   p <- p - lr / (1 - beta1^t) * m / (sqrt(v) / sqrt(1 - beta2^t) + eps)
+ * in float32.  activity (optional, float[n]): accumulated with the step's
+ * update-norm activity, as gsr_update_activity defines it from the values
+ * before and after.  Device arrays; asynchronous on stream; GSR_EINVAL on a
+ * NULL array, a bad size, degree, step or hyper-parameter. */
+typedef struct {
+  float* param;
+  const float* grad;
+  float* exp_avg;
+  float* exp_avg_sq;
+  float lr;
+} gsr_adam_group;
+gsr_status gsr_adam_step(int32_t n, int32_t sh_degree, uint32_t trainable_layers, const uint8_t* layer,
+                         const gsr_adam_group* groups, float beta1, float beta2, float eps, int32_t step,
+                         float* activity, void* stream);
+
 /* Inactive-pruning activity from one optimiser step (Sec. 3.2.2 tracks the
  * optimisation of each Gaussian's position, colour and scale and removes
  * Gaussians whose activity over a pruning window stays at or below a

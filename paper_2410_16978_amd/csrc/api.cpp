@@ -469,6 +469,31 @@ size_t gsr_workspace_size(int32_t n, int32_t n_views, int32_t width, int32_t hei
                shared_order ? (size_t)std::max(n, 1) : 0);
 }
 
+gsr_status gsr_adam_step(int32_t n, int32_t sh_degree, uint32_t trainable_layers, const uint8_t* layer,
+                         const gsr_adam_group* groups, float beta1, float beta2, float eps, int32_t step,
+                         float* activity, void* stream) {
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !groups || step < 1) return GSR_EINVAL;
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f)) return GSR_EINVAL;
+  if (n == 0) return GSR_OK;
+  if (!layer) return GSR_EINVAL;
+  const int planes[kAdamGroups] = {3, 3, 4, 1, 3 * (sh_degree + 1) * (sh_degree + 1)};
+  AdamArgs a;
+  const double bc1 = 1.0 - std::pow((double)beta1, (double)step);
+  const double bc2 = 1.0 - std::pow((double)beta2, (double)step);
+  for (int gi = 0; gi < kAdamGroups; ++gi) {
+    const gsr_adam_group& g = groups[gi];
+    if (!g.param || !g.grad || !g.exp_avg || !g.exp_avg_sq || !(g.lr >= 0.f)) return GSR_EINVAL;
+    a.g[gi] = AdamGroupD{g.param, g.exp_avg, g.exp_avg_sq, g.grad, planes[gi], (float)((double)g.lr / bc1)};
+  }
+  a.one_minus_b1 = 1.f - beta1;
+  a.b2 = beta2;
+  a.one_minus_b2 = 1.f - beta2;
+  a.bc2_sqrt = (float)std::sqrt(bc2);
+  a.eps = eps;
+  HIP_TRY(launch_adam(n, a, layer, trainable_layers, activity, static_cast<hipStream_t>(stream)));
+  return GSR_OK;
+}
+
 gsr_status gsr_update_activity(int32_t n, int32_t sh_degree, uint32_t trainable_layers, const float* mean_before,
                                const float* mean_after, const float* log_scale_before, const float* log_scale_after,
                                const float* sh_before, const float* sh_after, const uint8_t* layer, float* activity,

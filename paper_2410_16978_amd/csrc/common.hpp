@@ -223,6 +223,21 @@ uint32_t l1_loss_blocks(int n_views, int hw);
 hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* alpha, const float* t_rgb,
                           const float* t_alpha, const float* bg_host, float* partials, float* loss,
                           const float* g_loss, float* dL_drgb, float* dL_dalpha, hipStream_t s);
+// Adam over the parameter groups of a model: mean, log-scale, quaternion,
+// opacity logit, SH (in that order), each planes x n floats.
+constexpr int kAdamGroups = 5;
+struct AdamGroupD {
+  float *p, *m, *v;
+  const float* grad;
+  int32_t planes;
+  float step_size;  // lr / (1 - beta1^t)
+};
+struct AdamArgs {
+  AdamGroupD g[kAdamGroups];
+  float one_minus_b1, b2, one_minus_b2, bc2_sqrt, eps;
+};
+hipError_t launch_adam(int n, const AdamArgs& a, const uint8_t* layer, uint32_t trainable, float* activity,
+                       hipStream_t s);
 hipError_t launch_update_activity(int n, int sh_degree, uint32_t trainable, const float* mean0, const float* mean1,
                                   const float* ls0, const float* ls1, const float* sh0, const float* sh1,
                                   const uint8_t* layer, float* activity, hipStream_t s);

@@ -93,6 +93,11 @@ class Grads(C.Structure):
                 ("densify_count", C.c_void_p)]
 
 
+class AdamGroup(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("exp_avg", C.c_void_p), ("exp_avg_sq", C.c_void_p),
+                ("lr", C.c_float)]
+
+
 class Request(C.Structure):
     _fields_ = [("model", C.c_int32), ("n_views", C.c_int32), ("cam", Camera * 2), ("vs", ViewState),
                 ("rgb", C.c_void_p * 2), ("alpha", C.c_void_p * 2)]
@@ -138,6 +143,9 @@ def lib():
     L.gsr_l1_alpha_loss.restype = C.c_int
     L.gsr_l1_alpha_loss.argtypes = [C.c_int32, C.c_int32, C.c_int32] + [C.c_void_p] * 4 + [
         C.POINTER(C.c_float), C.c_void_p, C.c_size_t] + [C.c_void_p] * 4 + [C.c_void_p]
+    L.gsr_adam_step.restype = C.c_int
+    L.gsr_adam_step.argtypes = [C.c_int32, C.c_int32, C.c_uint32, C.c_void_p, C.POINTER(AdamGroup), C.c_float,
+                                C.c_float, C.c_float, C.c_int32, C.c_void_p, C.c_void_p]
     L.gsr_update_activity.restype = C.c_int
     L.gsr_update_activity.argtypes = [C.c_int32, C.c_int32, C.c_uint32] + [C.c_void_p] * 8 + [C.c_void_p]
     L.gsr_activate.restype = C.c_int
@@ -692,3 +700,31 @@ def update_activity(before, after, layer, sh_degree, trainable, activity, stream
                                    _ptr(after["mean"]), _ptr(before["log_scale"]), _ptr(after["log_scale"]),
                                    _ptr(before["sh"]), _ptr(after["sh"]), _ptr(layer), _ptr(activity), _stream(stream))
     _check(rc, "gsr_update_activity")
+
+
+ADAM_KEYS = ("mean", "log_scale", "quat", "opacity_logit", "sh")
+
+
+def adam_step(params, grads, exp_avg, exp_avg_sq, lrs, layer, sh_degree, trainable, step, betas=(0.9, 0.999),
+              eps=1e-15, activity=None, stream=None):
+    """gsr_adam_step: one Adam step, in place, on the Gaussians of the
+    trainable layers; dicts keyed by ADAM_KEYS of contiguous float32 device
+    tensors ([3,n], [3,n], [4,n], [n], [(D+1)^2,3,n]); activity (optional
+    [n]) accumulates the step's update-norm activity."""
+    n = int(layer.shape[0])
+    nc = (int(sh_degree) + 1) ** 2
+    shapes = {"mean": (3, n), "log_scale": (3, n), "quat": (4, n), "opacity_logit": (n,), "sh": (nc, 3, n)}
+    groups = (AdamGroup * 5)()
+    for gi, k in enumerate(ADAM_KEYS):
+        for t in (params[k], grads[k], exp_avg[k], exp_avg_sq[k]):
+            if tuple(t.shape) != shapes[k] or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"adam_step: {k} tensors must be contiguous CUDA float32 {shapes[k]}")
+        groups[gi] = AdamGroup(params[k].data_ptr(), grads[k].data_ptr(), exp_avg[k].data_ptr(),
+                               exp_avg_sq[k].data_ptr(), float(lrs[k]))
+    if layer.dtype != torch.uint8:
+        raise ValueError("adam_step: layer must be uint8")
+    if activity is not None and (tuple(activity.shape) != (n,) or activity.dtype != torch.float32):
+        raise ValueError("adam_step: activity must be float32 [n]")
+    rc = lib().gsr_adam_step(n, int(sh_degree), int(trainable) & 0xFFFFFFFF, _ptr(layer), groups, float(betas[0]),
+                             float(betas[1]), float(eps), int(step), _ptr(activity), _stream(stream))
+    _check(rc, "gsr_adam_step")

@@ -46,7 +46,6 @@ moments.
 from __future__ import annotations
 
 import dataclasses
-import io
 import json
 
 import numpy as np
@@ -181,6 +180,48 @@ def camera_extent(cams):
     return float(1.1 * d) if d > 0 else 1.0
 
 
+class FusedAdam:
+    """Adam (gsr_adam_step) over the parameter groups of a layered model:
+    one kernel launch per step that skips the frozen layers' Gaussians and,
+    given an activity buffer, adds the update-norm activity of the step.
+    Moments are tensors shaped like the parameters; `t` counts the steps."""
+
+    def __init__(self, params, lrs, betas=(0.9, 0.999), eps=1e-15):
+        self.lrs = dict(lrs)
+        self.betas = tuple(betas)
+        self.eps = float(eps)
+        self.t = 0
+        self.m = {k: torch.zeros_like(params[k].detach()) for k in PARAM_KEYS}
+        self.v = {k: torch.zeros_like(params[k].detach()) for k in PARAM_KEYS}
+
+    def step(self, params, layer, sh_degree, trainable, activity=None):
+        self.t += 1
+        grads = {k: params[k].grad if params[k].grad is not None else torch.zeros_like(params[k].detach())
+                 for k in PARAM_KEYS}
+        rz.adam_step({k: params[k].detach() for k in PARAM_KEYS}, {k: g.contiguous() for k, g in grads.items()},
+                     self.m, self.v, self.lrs, layer, sh_degree, trainable, self.t, self.betas, self.eps,
+                     activity=activity)
+
+    def remap(self, idx, m_new):
+        """Keep the moments of Gaussians idx, then m_new zero columns."""
+        for st in (self.m, self.v):
+            for k in PARAM_KEYS:
+                t = st[k].index_select(-1, idx)
+                if m_new:
+                    t = torch.cat([t, torch.zeros(t.shape[:-1] + (m_new,), dtype=t.dtype, device=t.device)], dim=-1)
+                st[k] = t.contiguous()
+
+    def arrays(self):
+        out = {f"adam_m_{k}": v.cpu().numpy() for k, v in self.m.items()}
+        out.update({f"adam_v_{k}": v.cpu().numpy() for k, v in self.v.items()})
+        return out
+
+    def load_arrays(self, z, t, device):
+        self.t = int(t)
+        self.m = {k: torch.tensor(z[f"adam_m_{k}"], device=device) for k in PARAM_KEYS}
+        self.v = {k: torch.tensor(z[f"adam_v_{k}"], device=device) for k in PARAM_KEYS}
+
+
 class LayeredTrainer:
     """Adam on the trainable layers of a layered Gaussian scene."""
 
@@ -200,7 +241,6 @@ class LayeredTrainer:
         self.prune = PruneState(prune or PruneConfig())
         self.rctx = ag.RenderContext(trainable_layers=self.trainable, track_activity=True, sync=sync,
                                      grad_activity=self.prune.cfg.measure == "gradient")
-        self._before = None  # parameters before the optimiser step ("update" measure)
         self.densify = densify                        # DensifyConfig or None
         self.extent = camera_extent(cams) if extent is None else float(extent)
         self.dens = None                              # (grad_sum, count) accumulators
@@ -210,12 +250,8 @@ class LayeredTrainer:
         self.it = 0
         self.history = []
 
-    def _make_opt(self, state=None):
-        opt = torch.optim.Adam([{"params": [self.params[k]], "lr": self.lrs[k], "name": k} for k in PARAM_KEYS],
-                               eps=1e-15)
-        if state is not None:
-            opt.load_state_dict(state)
-        return opt
+    def _make_opt(self):
+        return FusedAdam(self.params, self.lrs)
 
     @property
     def n(self):
@@ -230,12 +266,11 @@ class LayeredTrainer:
         t_alpha = self.targets[1][idx].contiguous()
         rgb, alpha = ag.render_params(self.params, self.layer, self.sh_degree, cams, views, self.rctx)
         loss = ag.l1_alpha_loss(rgb, alpha, t_rgb, t_alpha, [bg] * len(cams))
-        self.opt.zero_grad(set_to_none=True)
+        for k in PARAM_KEYS:
+            self.params[k].grad = None
         loss.backward()
-        if self.prune.cfg.measure == "update":
-            self._step_with_update_activity()
-        else:
-            self.opt.step()
+        act = self.rctx.activity if self.prune.cfg.measure == "update" else None
+        self.opt.step(self.params, self.layer, self.sh_degree, self.trainable, activity=act)
         self.it += 1
         self.prune.steps_in_window += 1
         out = {"it": self.it, "loss": loss}
@@ -302,21 +337,8 @@ class LayeredTrainer:
         with torch.no_grad():
             lo = self.params["opacity_logit"]
             lo.copy_(torch.where(live, torch.clamp(lo, max=cap), lo))
-        st = self.opt.state.get(self.params["opacity_logit"])
-        if st:
-            for m in ("exp_avg", "exp_avg_sq"):
-                st[m][live] = 0.0
-
-    def _step_with_update_activity(self):
-        """The optimiser step, then the activity of the change it made."""
-        keys = ("mean", "log_scale", "sh")
-        if self._before is None or self._before["mean"].shape != self.params["mean"].shape:
-            self._before = {k: torch.empty_like(self.params[k]) for k in keys}
-        for k in keys:
-            self._before[k].copy_(self.params[k].detach())
-        self.opt.step()
-        rz.update_activity(self._before, {k: self.params[k].detach() for k in keys}, self.layer, self.sh_degree,
-                           self.trainable, self.rctx.activity)
+        for st in (self.opt.m, self.opt.v):
+            st["opacity_logit"][live] = 0.0
 
     def prune_now(self):
         n = self.n
@@ -341,7 +363,6 @@ class LayeredTrainer:
         """Keep the Gaussians idx (in that order), then append `extra`
         (parameters of new Gaussians, zero Adam moments).  Per-Gaussian
         accumulators follow (new Gaussians start at zero)."""
-        old_state = self.opt.state_dict()
         m_new = 0 if extra is None else int(extra_layer.numel())
         new_params = {}
         for k in PARAM_KEYS:
@@ -349,21 +370,11 @@ class LayeredTrainer:
             if m_new:
                 t = torch.cat([t, extra[k].to(t.dtype)], dim=-1)
             new_params[k] = t.contiguous().requires_grad_(True)
-        for gi, k in enumerate(PARAM_KEYS):
-            st = old_state["state"].get(gi)
-            if st is not None:
-                for m in ("exp_avg", "exp_avg_sq"):
-                    t = st[m].index_select(-1, idx)
-                    if m_new:
-                        t = torch.cat([t, torch.zeros(t.shape[:-1] + (m_new,), dtype=t.dtype, device=t.device)],
-                                      dim=-1)
-                    st[m] = t.contiguous()
+        self.opt.remap(idx, m_new)
         self.params = new_params
         lay = self.layer.index_select(0, idx)
         self.layer = (torch.cat([lay, extra_layer]) if m_new else lay).contiguous()
-        self.opt = self._make_opt(old_state)
         self.rctx.state = None
-        self._before = None
 
         def remap(t):
             u = t.index_select(0, idx)
@@ -379,7 +390,7 @@ class LayeredTrainer:
     # ---------------------------------------------------------- checkpoint
     def state_dict(self):
         return {"params": {k: v.detach().cpu().numpy() for k, v in self.params.items()},
-                "layer": self.layer.cpu().numpy(), "opt": self.opt.state_dict(),
+                "layer": self.layer.cpu().numpy(), "opt": self.opt.arrays(), "opt_t": self.opt.t,
                 "prune": {"T": self.prune.T, "steps_in_window": self.prune.steps_in_window,
                           "n_prunes": self.prune.n_prunes},
                 "activity": None if self.rctx.activity is None else self.rctx.activity.cpu().numpy(),
@@ -388,9 +399,8 @@ class LayeredTrainer:
 
     def save(self, path):
         sd = self.state_dict()
-        buf = io.BytesIO()
-        torch.save(sd["opt"], buf)
         arrays = {f"param_{k}": v for k, v in sd["params"].items()}
+        arrays.update(sd["opt"])
         arrays["layer"] = sd["layer"]
         if sd["activity"] is not None:
             arrays["activity"] = sd["activity"]
@@ -398,8 +408,8 @@ class LayeredTrainer:
         if self.dens is not None:
             arrays["densify_grad"] = self.dens[0].cpu().numpy()
             arrays["densify_count"] = self.dens[1].cpu().numpy()
-        arrays["opt"] = np.frombuffer(buf.getvalue(), dtype=np.uint8)
-        meta = {"prune": sd["prune"], "rng": sd["rng"], "it": sd["it"], "trainable": self.trainable}
+        meta = {"prune": sd["prune"], "rng": sd["rng"], "it": sd["it"], "trainable": self.trainable,
+                "adam_t": sd["opt_t"]}
         arrays["meta"] = np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8)
         np.savez(path, **arrays)
 
@@ -417,9 +427,9 @@ class LayeredTrainer:
         for k in PARAM_KEYS:
             self.params[k] = torch.tensor(z[f"param_{k}"], device=self.device, requires_grad=True)
         self.layer = torch.tensor(z["layer"], device=self.device)
-        opt_state = torch.load(io.BytesIO(z["opt"].tobytes()), weights_only=True, map_location=self.device)
-        self.opt = self._make_opt(opt_state)
         meta = json.loads(z["meta"].tobytes().decode())
+        self.opt = self._make_opt()
+        self.opt.load_arrays(z, meta["adam_t"], self.device)
         self.prune.T = meta["prune"]["T"]
         self.prune.steps_in_window = meta["prune"]["steps_in_window"]
         self.prune.n_prunes = meta["prune"]["n_prunes"]
@@ -438,4 +448,3 @@ class LayeredTrainer:
                 self.rctx.densify_stats = self.dens
             else:
                 self._reset_densify_stats()
-        self._before = None

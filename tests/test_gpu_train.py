@@ -165,3 +165,47 @@ def test_density_control_in_layered_training():
     op = torch.sigmoid(tr.params["opacity_logit"].detach())
     assert float(op[n_s:].max()) <= 0.01 * (1 + 1e-6)
     assert torch.equal(tr.params["opacity_logit"].detach()[:n_s], frozen0["opacity_logit"])
+
+
+def test_fused_adam_matches_torch_adam():
+    """gsr_adam_step against torch.optim.Adam over three steps: trainable
+    layers' values within float rounding, frozen layers' values, gradients and
+    moments untouched; the activity is the update-norm activity of each step's
+    change (oracle definition)."""
+    import torch
+    from oracle import training
+    from paper_2410_16978_amd import rasterizer as rz
+    rng = np.random.default_rng(7)
+    n, D = 5003, 2
+    shapes = {"mean": (3, n), "log_scale": (3, n), "quat": (4, n), "opacity_logit": (n,), "sh": ((D + 1) ** 2, 3, n)}
+    lrs = {"mean": 1.6e-4, "log_scale": 5e-3, "quat": 1e-3, "opacity_logit": 5e-2, "sh": 2.5e-3}
+    layer = rng.integers(0, 3, n).astype(np.uint8)
+    live = layer != 1  # trainable layers 0 and 2
+    p0 = {k: rng.standard_normal(s).astype(np.float32) for k, s in shapes.items()}
+    ref = {k: torch.tensor(v, device="cuda", requires_grad=True) for k, v in p0.items()}
+    topt = torch.optim.Adam([{"params": [ref[k]], "lr": lrs[k]} for k in rz.ADAM_KEYS], eps=1e-15)
+    got = {k: torch.tensor(v, device="cuda") for k, v in p0.items()}
+    m = {k: torch.zeros_like(v) for k, v in got.items()}
+    v2 = {k: torch.zeros_like(v) for k, v in got.items()}
+    act = torch.zeros(n, device="cuda")
+    act_want = np.zeros(n)
+    lay = torch.tensor(layer, device="cuda")
+    for t in range(1, 4):
+        g = {k: rng.standard_normal(s).astype(np.float32) * (live if k != "sh" else live[None, None]) for k, s in
+             shapes.items()}
+        before = {k: got[k].cpu().numpy() for k in ("mean", "log_scale", "sh")}
+        for k in rz.ADAM_KEYS:
+            ref[k].grad = torch.tensor(g[k], device="cuda")
+        topt.step()
+        rz.adam_step(got, {k: torch.tensor(g[k], device="cuda") for k in rz.ADAM_KEYS}, m, v2, lrs, lay, D, 0b101, t,
+                     activity=act)
+        torch.cuda.synchronize()
+        after = {k: got[k].cpu().numpy() for k in ("mean", "log_scale", "sh")}
+        act_want = training.update_activity(before, after, layer, 0b101, act_want)
+        for k in rz.ADAM_KEYS:
+            a, b = got[k].cpu().numpy(), ref[k].detach().cpu().numpy()
+            np.testing.assert_array_equal(a[..., ~live], p0[k][..., ~live], err_msg=f"{k} frozen")
+            np.testing.assert_allclose(a[..., live], b[..., live], rtol=2e-6, atol=1e-6 * lrs[k], err_msg=k)
+            assert np.all(m[k].cpu().numpy()[..., ~live] == 0) and np.all(v2[k].cpu().numpy()[..., ~live] == 0)
+    np.testing.assert_allclose(act.cpu().numpy(), act_want, rtol=1e-5, atol=1e-9)
+    assert np.all(act.cpu().numpy()[~live] == 0)
