@@ -93,3 +93,50 @@ def test_batch_workspace_and_argument_checks(setup):
     bad["model"] = 5
     with pytest.raises(rz.GsrError):
         rz.render_batch(models, [bad], 1000)
+
+
+def test_mixed_features_alone_equals_in_mix_and_oracle(orc):
+    """One batch mixing a float model, a packed and a codebook-compressed one
+    (with 3D filter variances), requests with per-layer fading, the 2D Mip
+    filter, a shared stereo depth order and plain ones: every request's image
+    is bit-identical alone and in the mix, and matches the oracle's render of
+    its (decoded) scene."""
+    import torch
+    from oracle import compressed as oc
+    from paper_2410_16978_amd import compress, mip
+    from paper_2410_16978_amd import rasterizer as rz
+    a = scenes.shell_scene(500, 4, 3, seed=21, log_scale_mu=-3.3, log_scale_sigma=0.4, palette=True)
+    b = scenes.shell_scene(400, 4, 2, seed=22, log_scale_mu=-3.1, log_scale_sigma=0.4, palette=True)
+    cp = compress.compress(a, "packed")
+    cc = compress.compress(b, "codebook", codebook_size=128, iters=2)
+    rng = np.random.default_rng(9)
+    eyes = scenes.stereo_cameras([0.2, 0.3, -1.0], 64, 56)
+    cc["filter_3d"] = mip.filter_3d_variance(oc.decode(cc)["mean"], eyes) * 30.0
+    scn = [a, oc.decode(cp), oc.decode(cc)]
+    scn[2]["filter_3d"] = cc["filter_3d"]
+    models = [rz.to_device(a), rz.to_device_compressed(cp), rz.to_device_compressed(cc)]
+    reqs = [
+        {"model": 0, "cams": [scenes.orbit_camera([0.3, 0.1, -1.0], 72, 48)],
+         "view": scenes.view_state(0b1111, layer_opacity=[1.0, 0.4, 0.05, 0.8], bg=(0.1, 0.2, 0.3))},
+        {"model": 1, "cams": eyes, "view": scenes.with_sort_cam(scenes.view_state(0b0111), scenes.centre_camera(*eyes))},
+        {"model": 2, "cams": [scenes.orbit_camera([-0.2, 0.4, -1.0], 80, 64)],
+         "view": scenes.view_state(mip_2d_var=0.1, clips=[([0.2, 0.1, 1.0], 0.1, 0b11)])},
+        {"model": 1, "cams": [scenes.orbit_camera(scenes.random_direction(rng), 48, 48)],
+         "view": scenes.random_view_state(rng, 4)},
+        {"model": 2, "cams": eyes, "view": scenes.view_state(0b1011, layer_opacity=[0.5] * 4, mip_2d_var=0.2)},
+    ]
+    mixed, st = _render(rz, models, reqs)
+    assert np.all(st == 0)
+    for q, rq in enumerate(reqs):
+        alone, st1 = _render(rz, models, [rq])
+        assert st1[0] == 0
+        sort_cam = rq["view"].get("sort_cam")
+        ref = orc.render(scn[rq["model"]], rq["cams"], [rq["view"]] * len(rq["cams"]),
+                         sort_cams=None if sort_cam is None else [sort_cam] * len(rq["cams"]))
+        for e in range(len(rq["cams"])):
+            np.testing.assert_array_equal(mixed[q][0][e], alone[0][0][e])
+            np.testing.assert_array_equal(mixed[q][1][e], alone[0][1][e])
+            flag = ref["margin"][e] < 1.0
+            assert flag.sum() <= max(2, 1e-3 * flag.size), f"request {q} eye {e}: {int(flag.sum())} flagged pixels"
+            err = np.abs(mixed[q][0][e] - ref["rgb"][e]).max(axis=0)
+            assert err[~flag].max() <= 1e-4, f"request {q} eye {e}: {err[~flag].max()}"

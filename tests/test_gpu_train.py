@@ -209,3 +209,34 @@ def test_fused_adam_matches_torch_adam():
             assert np.all(m[k].cpu().numpy()[..., ~live] == 0) and np.all(v2[k].cpu().numpy()[..., ~live] == 0)
     np.testing.assert_allclose(act.cpu().numpy(), act_want, rtol=1e-5, atol=1e-9)
     assert np.all(act.cpu().numpy()[~live] == 0)
+
+
+def test_checkpoint_resume_across_density_control(tmp_path):
+    """A run with density control (clone / split with random children) and
+    inactive pruning, saved before a densification and resumed from the
+    file, reproduces the run bit for bit."""
+    import torch
+    from paper_2410_16978_amd.train import DensifyConfig, LayeredTrainer, PruneConfig
+    sc, cams, targets, _, _ = _setup(seed=6)
+    cfg = dict(start=4, interval=4, until=100, grad_threshold=1e-6, opacity_reset_interval=6)
+
+    def make(seed):
+        return LayeredTrainer(sc, cams, targets, 0b10, views_per_step=2, prune=PruneConfig(interval=5, threshold=1e-12),
+                              densify=DensifyConfig(**cfg), extent=5.0, seed=seed)
+
+    a = make(5)
+    for _ in range(3):
+        a.step()
+    path = str(tmp_path / "ck.npz")
+    a.save(path)
+    events = [a.step() for _ in range(7)]
+    assert any("densify" in e for e in events) and any("prune" in e for e in events)
+    b = make(99)
+    b.load(path)
+    for _ in range(7):
+        b.step()
+    torch.cuda.synchronize()
+    assert a.n == b.n and a.it == b.it
+    for k in a.params:
+        np.testing.assert_array_equal(a.params[k].detach().cpu().numpy(), b.params[k].detach().cpu().numpy())
+    np.testing.assert_array_equal(a.layer.cpu().numpy(), b.layer.cpu().numpy())

@@ -96,3 +96,23 @@ def test_noalloc_refuses_sizes_beyond_its_scratch():
     with pytest.raises(rz.GsrError) as e:
         rz.rasterize_forward_noalloc(model, cams, vss, st, out)
     assert e.value.status == rz.GSR_ENOSPACE
+
+
+def test_noalloc_renders_a_compressed_model(orc):
+    """The entry point that allocates nothing renders compressed attributes
+    as the workspace forward does (bit-identical images)."""
+    import torch
+    from paper_2410_16978_amd import compress
+    from paper_2410_16978_amd import rasterizer as rz
+    sc = scenes.shell_scene(300, 3, 3, seed=44, log_scale_mu=-3.2, log_scale_sigma=0.4, palette=True)
+    model = rz.to_device_compressed(compress.compress(sc, "codebook", codebook_size=64, iters=2))
+    cam = scenes.orbit_camera([0.2, 0.3, -1.0], 96, 64)
+    vs = scenes.view_state(layer_opacity=[1.0, 0.6, 0.3])
+    rgb, alpha, st = rz.rasterize_forward(model, [cam], [vs])
+    torch.cuda.synchronize()
+    st2 = rz.make_state(300 * 3, 1, 96, 64, int(st.n_pairs * 1.1) + 256)
+    out = (torch.empty((1, 3, 64, 96), device="cuda"), torch.empty((1, 64, 96), device="cuda"))
+    rz.rasterize_forward_noalloc(model, [cam], [vs], st2, out)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out[0].cpu().numpy(), rgb.cpu().numpy())
+    np.testing.assert_array_equal(out[1].cpu().numpy(), alpha.cpu().numpy())
