@@ -46,8 +46,10 @@ def percentile(xs, q):
 
 
 def kernel_source_hash():
+    """Hash of the sources the blend kernels are built from (the stored
+    traffic figure is the backward blend's)."""
     h = hashlib.sha256()
-    for f in ("blend.hip", "sort.hip", "project.hip", "project_bwd.hip", "pairs.hip", "common.hpp"):
+    for f in ("blend.hip", "cull.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2410_16978_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -263,3 +263,15 @@ def test_mip_filters_are_forward_only():
     rgb, alpha, st = rz.rasterize_forward(model, [cam], [vs])
     with pytest.raises(rz.GsrError):
         rz.rasterize_backward(model, [cam], [vs], st, torch.zeros_like(rgb), torch.zeros_like(alpha))
+
+
+def test_dense_tiles(orc):
+    """Tiles of more than 1024 pairs (up to about 2900 here, a dozen batches
+    of 256) on two views: the same bar as every other tile."""
+    sc = scenes.shell_scene(1000, 3, 1, seed=41, log_scale_mu=-2.8, log_scale_sigma=0.4, opacity="normal")
+    cams = [scenes.orbit_camera([0.2, 0.3, -1.0], 48, 40), scenes.orbit_camera([-0.1, 0.35, -1.0], 48, 40)]
+    scenes.enforce_distinct_depths(sc, cams)
+    ref = orc.render(sc, cams[:1], [scenes.view_state()], pairs=True)
+    counts = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    assert (counts >= 1024).sum() >= 2
+    print("dense:", compare_forward(sc, cams, [scenes.view_state(bg=(0.2, 0.1, 0.3))] * 2, orc, label="dense"))
