@@ -182,11 +182,29 @@ __device__ __forceinline__ void load_sh(const ModelD& m, int i, float* sh, uint3
   }
 }
 
+// The tests a view makes before it needs more than the Gaussian's layer,
+// centre and opacity: layer mask, clip planes, near plane, faded opacity.
+__device__ __forceinline__ bool view_may_keep(const ViewD& V, uint32_t layer, float mx, float my, float mz,
+                                              float op) {
+  if (layer >= 32u || !((V.layer_mask >> layer) & 1u)) return false;
+  for (int k = 0; k < V.n_clip; ++k) {
+    const ClipD& c = V.clip[k];
+    if (!((c.bits >> layer) & 1u)) continue;
+    const float sd = ((c.n[0] * mx + c.n[1] * my) + c.n[2] * mz) + c.d;
+    if (sd < 0.f) return false;
+  }
+  const float* W = V.R;
+  const float tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + V.t[2];
+  if (!(tz > V.znear)) return false;
+  return op * V.layer_op[layer] >= kAlphaMin;
+}
+
 // One thread per Gaussian; the Gaussian's attributes are read once and
-// projected for every view of the job (stereo eyes, training views).  SH
-// coefficients are read only if some view keeps the Gaussian.  F selects
-// the storage format of the attributes (float, or half with packed or
-// codebook SH).
+// projected for every view of the job (stereo eyes, training views).  The
+// rest of its attributes (rotation, scale, 3D filter, SH) are read only if
+// some view may keep it, and then all at once: one memory round trip after
+// the first instead of one per attribute group.  F selects the storage
+// format of the attributes (float, or half with packed or codebook SH).
 template <int D, int F>
 __global__ void __launch_bounds__(256)
 k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records,
@@ -203,8 +221,22 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
   float op;
   if constexpr (F == kFmtF32) op = act_opacity(m.opacity[i], m.raw);
   else op = half_bits(m.h_opacity[i]);
+  bool maybe = false;
+  for (int jv = 0; jv < job.n_views && !maybe; ++jv)
+    maybe = view_may_keep(views[job.view[jv]], layer, mx, my, mz, op);
   float sh[NC * 3];
-  bool sh_loaded = false;
+  float qw = 0.f, qx = 0.f, qy = 0.f, qz = 0.f, sc0 = 0.f, sc1 = 0.f, sc2 = 0.f, f2 = 0.f;
+  if (maybe) {
+    qw = ld_attr<F>(m.quat, m.h_quat, i);
+    qx = ld_attr<F>(m.quat, m.h_quat, (size_t)n + i);
+    qy = ld_attr<F>(m.quat, m.h_quat, 2 * (size_t)n + i);
+    qz = ld_attr<F>(m.quat, m.h_quat, 3 * (size_t)n + i);
+    sc0 = ld_scale<F>(m, i);
+    sc1 = ld_scale<F>(m, (size_t)n + i);
+    sc2 = ld_scale<F>(m, 2 * (size_t)n + i);
+    if (m.filter_3d) f2 = m.filter_3d[i];
+    load_sh<D, F>(m, i, sh, counters);
+  }
   float Rq[9];
   float qn = -1.f;  // < 0: rotation not computed yet
 
@@ -233,8 +265,6 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const float opv = op * V.layer_op[layer];  // the view's fading of the layer
       if (opv < kAlphaMin) break;
       if (qn < 0.f) {
-        float qw = ld_attr<F>(m.quat, m.h_quat, i), qx = ld_attr<F>(m.quat, m.h_quat, (size_t)n + i),
-              qy = ld_attr<F>(m.quat, m.h_quat, 2 * (size_t)n + i), qz = ld_attr<F>(m.quat, m.h_quat, 3 * (size_t)n + i);
         qn = sqrt_rn(((qw * qw + qx * qx) + qy * qy) + qz * qz);
         if (!(qn > 0.f)) { qn = 0.f; break; }
         qw = __fdiv_rn(qw, qn); qx = __fdiv_rn(qx, qn); qy = __fdiv_rn(qy, qn); qz = __fdiv_rn(qz, qn);
@@ -250,11 +280,10 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       }
       if (!(qn > 0.f)) break;
       // Sigma = M M^T, M = Rq diag(s)
-      float s0 = ld_scale<F>(m, i), s1 = ld_scale<F>(m, (size_t)n + i), s2 = ld_scale<F>(m, 2 * (size_t)n + i);
+      float s0 = sc0, s1 = sc1, s2 = sc2;
       float opf = opv;  // opacity after the Mip filters
       if (m.filter_3d) {
         // 3D filter: the Gaussian convolved with an isotropic one of variance f2
-        const float f2 = m.filter_3d[i];
         const float q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
         const float p0 = q0 + f2, p1 = q1 + f2, p2 = q2 + f2;
         s0 = sqrt_rn(p0); s1 = sqrt_rn(p1); s2 = sqrt_rn(p2);
@@ -332,10 +361,6 @@ k_project(JobD job, const ViewD* __restrict__ views, float* __restrict__ records
       const float dirx = __fdiv_rn(ddx, dl), diry = __fdiv_rn(ddy, dl), dirz = __fdiv_rn(ddz, dl);
       float Y[16];
       sh_basis<D>(dirx, diry, dirz, Y);
-      if (!sh_loaded) {
-        load_sh<D, F>(m, i, sh, counters);
-        sh_loaded = true;
-      }
       float rgb[3];
       uint32_t clamp_bits = 0;
 #pragma unroll
