@@ -25,14 +25,18 @@ __device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restri
                                             uint32_t zero, uint32_t K, double* g, float& wmax) {
   for (int c = 0; c < 9; ++c) g[c] = 0.0;
   const uint32_t e0 = offsets[r], e1 = min(offsets[r + 1], K);
-  // four pairs per step: their flags, then their loads, in flight at once
+  if (e0 >= e1) return;
+  // four pairs per step: their loads in flight at once, and with them the
+  // flags of the next step's four (one load round trip per step)
+  bool live[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) live[u] = alive[min(e0 + (uint32_t)u, e1 - 1u)] != 0;
   for (uint32_t e = e0; e < e1; e += 4) {
     uint32_t idx[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint32_t q = e + (uint32_t)u;
-      const bool live = alive[min(q, e1 - 1u)] != 0;
-      idx[u] = q < e1 && live ? q : zero;
+      idx[u] = q < e1 && live[u] ? q : zero;
     }
     float4 x[12];
 #pragma unroll
@@ -42,6 +46,14 @@ __device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restri
       x[3 * u + 1] = src[1];
       x[3 * u + 2] = src[2];
     }
+    uint8_t nf[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) nf[u] = alive[min(e + 4u + (uint32_t)u, e1 - 1u)];
+    // keeps those flag loads here, issued before the wait for the partials
+    // (left alone, the compiler moves them down to their use)
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < 4; ++u) live[u] = nf[u] != 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const float4 x0 = x[3 * u], x1 = x[3 * u + 1], x2 = x[3 * u + 2];
