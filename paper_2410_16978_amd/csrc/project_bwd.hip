@@ -20,11 +20,10 @@ namespace gsr {
 // written); their loads are redirected to the zero entry at index `zero`, so
 // the loads stay branch-free and adding its +0 leaves every sum bit for bit
 // unchanged (a sum that starts at +0 never holds -0).
-__device__ __forceinline__ void record_grad(uint32_t r, const uint32_t* __restrict__ offsets,
-                                            const float* __restrict__ g_pair, const uint8_t* __restrict__ alive,
-                                            uint32_t zero, uint32_t K, double* g, float& wmax) {
+__device__ __forceinline__ void record_grad(uint32_t e0, uint32_t e1, const float* __restrict__ g_pair,
+                                            const uint8_t* __restrict__ alive, uint32_t zero, double* g,
+                                            float& wmax) {
   for (int c = 0; c < 9; ++c) g[c] = 0.0;
-  const uint32_t e0 = offsets[r], e1 = min(offsets[r + 1], K);
   if (e0 >= e1) return;
   // four pairs per step: their loads in flight at once, and with them the
   // flags of the next step's four (one load round trip per step)
@@ -94,7 +93,11 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
     double g[9];
     for (int jv = 0; jv < job.n_views; ++jv) {
       const uint32_t r = views[job.view[jv]].rec_off + (uint32_t)i;
-      if (__float_as_uint(records[(size_t)r * kRecordFloats + 11]) != 0u) record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
+      const uint32_t kept = __float_as_uint(records[(size_t)r * kRecordFloats + 11]);
+      uint32_t e0 = offsets[r], e1 = offsets[r + 1];
+      asm volatile("" : "+v"(e0), "+v"(e1));  // both loads issued before the test, not sunk below it
+      e1 = min(e1, K);
+      if (kept != 0u) record_grad(e0, e1, g_pair, alive, cap, g, wmax);
     }
   }
   if (train) {
@@ -130,10 +133,14 @@ k_project_bwd_geom(JobD job, const ViewD* __restrict__ views, const float* __res
       const ViewD& V = views[job.view[jv]];
       const uint32_t r = V.rec_off + (uint32_t)i;
       const float* rec = records + (size_t)r * kRecordFloats;
-      if (__float_as_uint(rec[11]) == 0u) continue;  // culled in this view
-      const uint32_t clamp_bits = __float_as_uint(rec[10]);
+      // the record's flags and pair range, read together
+      const uint32_t kept = __float_as_uint(rec[11]), clamp_bits = __float_as_uint(rec[10]);
+      uint32_t e0 = offsets[r], e1 = offsets[r + 1];
+      asm volatile("" : "+v"(e0), "+v"(e1));  // both loads issued before the test, not sunk below it
+      e1 = min(e1, K);
+      if (kept == 0u) continue;  // culled in this view
       double g[9];
-      record_grad(r, offsets, g_pair, alive, cap, K, g, wmax);
+      record_grad(e0, e1, g_pair, alive, cap, g, wmax);
       go += g[5] * (double)V.layer_op[layer];  // the record holds o times the view's factor
       {
         // density-control statistic: gradient of the projected centre in
