@@ -297,11 +297,23 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   uint32_t last = 0;
   bool done = !inside;
   uint32_t n_ck = 0;  // batches processed (checkpoints written)
+  // per batch parity, byte w: whether wave w still has a live pixel
+  __shared__ __align__(16) uint32_t s_live[2][4];
   // record id of this thread's pair of the next batch, loaded a batch ahead
   // (one of the two dependent loads of the staging off the serial path)
   uint32_t rid = tid < kBatch && t_start + (uint32_t)tid < t_end ? vals[t_start + tid] : 0u;
   for (uint32_t start = t_start, c = 0; start < t_end; start += kBatch, ++c) {
-    if (!__syncthreads_or(!done)) break;  // also orders the previous batch's LDS reads before the refill
+    // the block leaves once every pixel has stopped: each wave posts its
+    // flag, one barrier (which also orders the previous batch's LDS reads
+    // before the refill), every wave reads the sixteen posts (the other
+    // parity's posts are rewritten only after the next batch's barriers)
+    {
+      const bool any_live = __ballot(!done) != 0ull;
+      if (lane == 0) reinterpret_cast<uint8_t*>(s_live[c & 1])[wave] = any_live ? 1 : 0;
+      __syncthreads();
+      const uint4 posts = *reinterpret_cast<const uint4*>(s_live[c & 1]);
+      if ((posts.x | posts.y | posts.z | posts.w) == 0u) break;
+    }
     if (ckpt && tid == 0 && c > 0) {
       if (b0 + c - 1 < batch_cap) batch_tile[b0 + c - 1] = batch_word(tile, s_est);
       s_est = 0;
