@@ -761,6 +761,8 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       }
     }
     __syncthreads();
+    // each column is combined by one thread, which also zeroes it for the
+    // next sub-batch (columns of no pair were never written and stay zero)
     if (tid >= j0 && tid < j0 + kSub && tid < n) {
       const int js = tid - j0;
       float m9[9], o[12];
@@ -777,6 +779,10 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       o[7] = m9[7];
       o[8] = m9[8];
       o[9] = fmaxf(fmaxf(part[0][9][js], part[1][9][js]), fmaxf(part[2][9][js], part[3][9][js]));
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int q = 0; q < kGradSlots; ++q) part[w][q][js] = 0.f;
       o[10] = 0.f;
       o[11] = 0.f;
       float4* dst = reinterpret_cast<float4*>(g_pair + (size_t)my_emit * 12);
@@ -785,8 +791,6 @@ k_blend_bwd(const ViewD* __restrict__ views, int n_views, const float* __restric
       dst[2] = make_float4(o[8], o[9], o[10], o[11]);
       alive[my_emit] = 1;
     }
-    __syncthreads();
-    for (int i = tid; i < 4 * kGradSlots * kSubPad; i += 256) (&part[0][0][0])[i] = 0.f;
     __syncthreads();
   }
 }
