@@ -44,7 +44,6 @@ struct BatchLds {
   float4 a[kBatch];    // u, v, conic a, 2 b
   float4 b[kBatch];    // conic c, opacity, r, g
   float c[kBatch];     // b
-  float cut[kBatch];   // q cut-off with margin
 };
 
 __device__ __forceinline__ int find_view(const ViewD* __restrict__ views, int n_views, uint32_t tile) {
@@ -94,8 +93,8 @@ __device__ __forceinline__ Staged fetch(const float* __restrict__ records, uint3
 // and this computation, so skipping a pair for pixel centres where its q
 // exceeds the cut-off never changes a result.  The cut-off is negative
 // (nothing reachable) when 255 o < 1.
-__device__ __forceinline__ float reach_cutoff(const Staged& st) {
-  return fminf(kQMax, 2.f * __logf(255.f * st.b.y)) * 1.01f + 0.05f;
+__device__ __forceinline__ float reach_cutoff(float opacity) {
+  return fminf(kQMax, 2.f * __logf(255.f * opacity)) * 1.01f + 0.05f;
 }
 
 __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int tid) {
@@ -103,8 +102,58 @@ __device__ __forceinline__ void put(BatchLds& L, const Staged& st, bool ok, int 
     L.a[tid] = make_float4(st.a.x, st.a.y, st.a.z, 2.f * st.a.w);
     L.b[tid] = st.b;
     L.c[tid] = st.c;
-    L.cut[tid] = reach_cutoff(st);
   }
+}
+
+// A batch's records as they lie in memory (floats 0-3, 4-7 and 8 of each):
+// the forward loads them from global memory straight into LDS, the next
+// batch's while the current one is blended.
+struct BatchRaw {
+  float4 a[kBatch];  // u, v, conic a, b
+  float4 b[kBatch];  // conic c, opacity, r, g
+  float c[kBatch];   // b
+};
+
+// s_waitcnt operands: vmcnt(0), and lgkmcnt(0), each leaving the other
+// counters alone
+constexpr int kWaitVm0 = 0x0F70;
+constexpr int kWaitLgkm0 = 0xC07F;
+
+// A barrier for LDS traffic only: the wave's LDS accesses complete, then the
+// block meets (the signal fences keep the compiler from moving memory
+// accesses across it).  Loads into LDS in flight keep running, where
+// __syncthreads would wait for them.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// LDS address of p as a plain number: a load into LDS aimed at it carries no
+// alias information, so the compiler puts no wait for it before the reads
+// that follow (it would otherwise wait before every read of the same LDS
+// array, the batch in use among them).  The kernel waits for these loads
+// itself, before the barrier that precedes the first read of their data.
+__device__ __forceinline__ lds_void* lds_target(void* p) {
+  return (lds_void*)(size_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(size_t)(lds_void*)p);
+}
+
+// Starts the loads of one wave's 64 records of a batch into its LDS slots
+// 64 w .. 64 w + 63 (w = the wave; lane l's record lands in slot 64 w + l):
+// the data skips registers and has landed once the wave's vector-memory
+// count has drained.  Every lane loads (a lane without a pair loads record
+// 0), so the slots are always written whole.
+__device__ __forceinline__ void stage_async(BatchRaw& D, const float* __restrict__ records, uint32_t n_rec,
+                                            uint32_t r, bool ok) {
+  if (!ok || r >= n_rec) r = 0;
+  const float* g = records + (size_t)r * kRecordFloats;
+  const int w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;
+  __builtin_amdgcn_global_load_lds(g, lds_target(&D.a[w0]), 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(g + 4, lds_target(&D.b[w0]), 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(g + 8, lds_target(&D.c[w0]), 4, 0, 0);
 }
 
 // Lane permutation within rows / quads (DPP); lanes a row mask leaves out
@@ -126,13 +175,13 @@ __device__ __forceinline__ uint64_t lanes_below() {
 // pair's 16-bit block mask is block (column, row).
 static_assert(kBatch * 4 == 1024, "one block row per thread");
 
-__device__ __forceinline__ void block_nibbles(const BatchLds& L, uint8_t (*nib)[kBatch], int n, float tx0,
+__device__ __forceinline__ void block_nibbles(const BatchRaw& L, uint8_t (*nib)[kBatch], int n, float tx0,
                                               float ty0) {
   const int j = threadIdx.x & (kBatch - 1), r = threadIdx.x >> 8;
   uint32_t bits = 0u;
   if (j < n) {
-    const float4 A = L.a[j];
-    bits = band_blocks(A.x, A.y, A.z, 0.5f * A.w, L.b[j].x, L.cut[j], tx0, ty0 + 4.f * (float)r);
+    const float4 A = L.a[j], B = L.b[j];
+    bits = band_blocks(A.x, A.y, A.z, A.w, B.x, reach_cutoff(B.y), tx0, ty0 + 4.f * (float)r);
   }
   nib[r][j] = (uint8_t)bits;
 }
@@ -242,13 +291,15 @@ __device__ __forceinline__ uint32_t quad_max_u32(uint32_t v) {
   return v;
 }
 
-__global__ void __launch_bounds__(1024)
+// At most 80 SGPRs: two 1024-thread blocks per compute unit need it (with
+// 81 the kernel measured 35 % slower, one block per compute unit at a time).
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_num_sgpr(80)))
 k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles, const float* __restrict__ records,
              uint32_t n_rec, const uint32_t* __restrict__ pair_vals, const uint32_t* __restrict__ sel, uint32_t cap,
              const uint32_t* __restrict__ ranges, uint32_t* __restrict__ batch_tile, uint32_t batch_cap,
              const int32_t* __restrict__ req_status, float4* __restrict__ ckpt,
              const uint32_t* __restrict__ class_count, const uint32_t* __restrict__ class_list) {
-  __shared__ BatchLds L;
+  __shared__ BatchRaw R[2];  // batch c's records in R[c & 1]
   __shared__ uint8_t lists[16][kBatch];
   __shared__ uint8_t nib[4][kBatch];
   // block b takes the b-th tile of the largest-first order (if given): the
@@ -299,14 +350,24 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
   uint32_t n_ck = 0;  // batches processed (checkpoints written)
   // per batch parity, byte w: whether wave w still has a live pixel
   __shared__ __align__(16) uint32_t s_live[2][4];
-  // record id of this thread's pair of the next batch, loaded a batch ahead
-  // (one of the two dependent loads of the staging off the serial path)
-  uint32_t rid = tid < kBatch && t_start + (uint32_t)tid < t_end ? vals[t_start + tid] : 0u;
+  // Staging: waves 0-3 load the records of batch c + 1 straight into LDS
+  // while batch c is blended, and the record ids of batch c + 2 into
+  // registers; batch 0's loads start here.
+  const bool stager = tid < kBatch;
+  uint32_t rid = stager && t_start + (uint32_t)tid < t_end ? vals[t_start + tid] : 0u;
+  if (stager && t_start < t_end) stage_async(R[0], records, n_rec, rid, t_start + (uint32_t)tid < t_end);
+  {
+    const uint32_t k = t_start + kBatch + (uint32_t)tid;
+    rid = stager && k < t_end ? vals[k] : 0u;
+  }
   for (uint32_t start = t_start, c = 0; start < t_end; start += kBatch, ++c) {
+    // this batch's records have landed (each wave waits for its own loads);
     // the block leaves once every pixel has stopped: each wave posts its
-    // flag, one barrier (which also orders the previous batch's LDS reads
-    // before the refill), every wave reads the sixteen posts (the other
-    // parity's posts are rewritten only after the next batch's barriers)
+    // flag, one barrier (which also shows the records to every wave and
+    // orders the previous batch's reads of the other buffer before its
+    // refill), every wave reads the sixteen posts (the other parity's posts
+    // are rewritten only after the next batch's barriers)
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     {
       const bool any_live = __ballot(!done) != 0ull;
       if (lane == 0) reinterpret_cast<uint8_t*>(s_live[c & 1])[wave] = any_live ? 1 : 0;
@@ -319,14 +380,15 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       s_est = 0;
     }
     const int n = (int)min((uint32_t)kBatch, t_end - start);
-    if (tid < kBatch) put(L, fetch_record(records, n_rec, rid, tid < n), tid < n, tid);
-    __syncthreads();
+    const BatchRaw& L = R[c & 1];
     {
-      const uint32_t k = start + kBatch + (uint32_t)tid;
-      rid = tid < kBatch && k < t_end ? vals[k] : 0u;
+      const uint32_t nstart = start + kBatch;
+      if (stager && nstart < t_end) stage_async(R[(c + 1) & 1], records, n_rec, rid, nstart + (uint32_t)tid < t_end);
+      const uint32_t k = nstart + kBatch + (uint32_t)tid;
+      rid = stager && k < t_end ? vals[k] : 0u;
     }
     block_nibbles(L, nib, n, (float)(tx * kTile) + 0.5f, (float)(ty * kTile) + 0.5f);
-    __syncthreads();
+    lds_barrier();
     if (blk_out && tid < n)
       blk_out[start + tid] = (uint16_t)(nib[0][tid] | (nib[1][tid] << 4) | (nib[2][tid] << 8) | (nib[3][tid] << 12));
     const float T0 = T;
@@ -338,8 +400,9 @@ k_blend_tile(const ViewD* __restrict__ views, int n_views, uint32_t total_tiles,
       const int te = t0 + slot;
       const bool has = te < cnt;
       const int j = has ? (int)list[te] : 0;
-      const float4 A = L.a[j], B = L.b[j];
+      const float4 R4 = L.a[j], B = L.b[j];
       const float cb = L.c[j];
+      const float4 A = make_float4(R4.x, R4.y, R4.z, 2.f * R4.w);  // b doubled (exact)
       const float power = pair_power(A, B, A.x - fx, A.y - fy);
       const float alpha = pair_alpha(B, power);
       const bool cand = has && !done && power <= 0.f && alpha >= kAlphaMin;
