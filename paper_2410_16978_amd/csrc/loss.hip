@@ -115,19 +115,37 @@ k_l1_loss4(int n_views, int hw, const float4* __restrict__ rgb, const float4* __
   }
 }
 
-// One block: the partial sums in a fixed order.
-__global__ void __launch_bounds__(256)
+// One block of 1024 threads: the partial sums in a fixed order (one pair of
+// partials per thread - there are at most kLossBlocks - then wave sums, then
+// the sixteen wave sums in order): one load round trip and one barrier.
+static_assert(kLossBlocks <= 1024, "one pair of partials per thread");
+__global__ void __launch_bounds__(1024)
 k_l1_loss_final(uint32_t n_part, uint32_t total, const float* __restrict__ partials, float* __restrict__ loss) {
-  __shared__ float lds[8];
+  __shared__ float lds[2][16];
   float c = 0.f, a = 0.f;
   for (uint32_t b = threadIdx.x; b < n_part; b += blockDim.x) {
     c += partials[2 * b];
     a += partials[2 * b + 1];
   }
-  const float tc = l1_block_sum(c, lds);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c += __shfl_xor(c, off, 64);
+    a += __shfl_xor(a, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    lds[0][wave] = c;
+    lds[1][wave] = a;
+  }
   __syncthreads();
-  const float ta = l1_block_sum(a, lds);
-  if (threadIdx.x == 0) loss[0] = tc / (float)(3 * (size_t)total) + ta / (float)total;
+  if (threadIdx.x == 0) {
+    float tc = 0.f, ta = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      tc += lds[0][w];
+      ta += lds[1][w];
+    }
+    loss[0] = tc / (float)(3 * (size_t)total) + ta / (float)total;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -174,13 +192,13 @@ hipError_t launch_l1_loss(int n_views, int hw, const float* rgb, const float* al
                        reinterpret_cast<const float4*>(t_rgb), reinterpret_cast<const float4*>(t_alpha), bg, partials,
                        g_loss, grads ? reinterpret_cast<float4*>(dL_drgb) : nullptr,
                        grads ? reinterpret_cast<float4*>(dL_dalpha) : nullptr);
-    hipLaunchKernelGGL(k_l1_loss_final, dim3(1), dim3(256), 0, s, blocks4, (uint32_t)n_views * (uint32_t)hw,
+    hipLaunchKernelGGL(k_l1_loss_final, dim3(1), dim3(1024), 0, s, blocks4, (uint32_t)n_views * (uint32_t)hw,
                        partials, loss);
   } else if (loss) {  // with the gradient in the same pass when both are asked for
     const uint32_t n_part = min(blocks, kLossBlocks);
     hipLaunchKernelGGL(k_l1_loss, dim3(n_part), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
                        partials, g_loss, grads ? dL_drgb : nullptr, grads ? dL_dalpha : nullptr);
-    hipLaunchKernelGGL(k_l1_loss_final, dim3(1), dim3(256), 0, s, n_part, (uint32_t)n_views * (uint32_t)hw,
+    hipLaunchKernelGGL(k_l1_loss_final, dim3(1), dim3(1024), 0, s, n_part, (uint32_t)n_views * (uint32_t)hw,
                        partials, loss);
   } else if (grads)
     hipLaunchKernelGGL(k_l1_loss_grad, dim3(blocks), dim3(256), 0, s, n_views, hw, rgb, alpha, t_rgb, t_alpha, bg,
