@@ -275,3 +275,28 @@ def test_dense_tiles(orc):
     counts = ref["ranges"][:, 1] - ref["ranges"][:, 0]
     assert (counts >= 1024).sum() >= 2
     print("dense:", compare_forward(sc, cams, [scenes.view_state(bg=(0.2, 0.1, 0.3))] * 2, orc, label="dense"))
+
+
+def test_batch_boundaries_and_early_stop(orc):
+    """One 16 x 16 tile holding exactly N pairs for N around the 256-pair
+    batches (255 to 769).  Faint splats keep pixels live through the last,
+    partial batch (each batch's records load during the one before);
+    opaque, wide splats stop every pixel in the first batch while the second
+    batch's records are already loading, so the block leaves at the next
+    batch's test.  Records, pairs and images against the oracle."""
+    cam = axis_camera(16, 16, f=20.0, cx=8.0, cy=8.0)
+    vs = scenes.view_state()
+    for n in (255, 256, 257, 511, 512, 513, 769):
+        for label, op_lo, op_hi, log_s in (("faint", 0.005, 0.02, -3.5), ("opaque", 0.95, 0.99, -0.5)):
+            rng = np.random.default_rng(n)
+            z = rng.uniform(2.0, 4.0, n)
+            xy = rng.uniform(-0.1, 0.1, (n, 2)) * z[:, None]
+            sc = make_scene(np.column_stack([xy, z]), np.exp(rng.normal(log_s, 0.2, (n, 3))),
+                            quats=rng.standard_normal((n, 4)), opacity=rng.uniform(op_lo, op_hi, n),
+                            rgb=rng.uniform(0, 1, (n, 3)))
+            scenes.enforce_distinct_depths(sc, [cam])
+            if label == "opaque":
+                ref = orc.render(sc, [cam], [vs], pairs=True)
+                assert int(ref["last"].max()) <= 256  # every pixel stops in the first batch
+            st = compare_forward(sc, [cam], [vs], orc, label=f"{label} {n}")
+            assert st["K"] == n
