@@ -275,3 +275,28 @@ def test_gradients_through_dense_tiles(orc):
     for k in ("mean", "scale", "quat", "opacity", "sh", "activity"):
         assert_grad_close(got[k], ref[k], sens[k], k, ex, g32[k])
     np.testing.assert_allclose(got["max_contrib"][~ex], ref["max_contrib"][~ex], rtol=1e-4, atol=1e-7)
+
+
+def test_gradients_at_batch_boundaries(orc):
+    """One 16 x 16 tile of exactly N pairs around the 256-pair batches:
+    faint splats (every batch has live pixels, the last one partial) and
+    opaque wide ones (every pixel stops in the first batch, the later
+    batches have no work).  Gradients within the bar."""
+    from tests.helpers import axis_camera, make_scene
+    cam = axis_camera(16, 16, f=20.0, cx=8.0, cy=8.0)
+    vss = [scenes.view_state(bg=(0.2, 0.1, 0.3))]
+    for n in (256, 257, 513):
+        for label, op_lo, op_hi, log_s in (("faint", 0.005, 0.02, -3.5), ("opaque", 0.95, 0.99, -0.5)):
+            rng = np.random.default_rng(100 + n)
+            z = rng.uniform(2.0, 4.0, n)
+            xy = rng.uniform(-0.1, 0.1, (n, 2)) * z[:, None]
+            sc = make_scene(np.column_stack([xy, z]), np.exp(rng.normal(log_s, 0.2, (n, 3))),
+                            quats=rng.standard_normal((n, 4)), opacity=rng.uniform(op_lo, op_hi, n),
+                            rgb=rng.uniform(0, 1, (n, 3)))
+            scenes.enforce_distinct_depths(sc, [cam])
+            Gr = rng.standard_normal((1, 3, 16, 16)).astype(np.float32)
+            Ga = rng.standard_normal((1, 16, 16)).astype(np.float32)
+            got = _gpu_grads(sc, [cam], vss, Gr, Ga)
+            ref, sens, g32, ex = _refs(orc, sc, [cam], vss, Gr, Ga, got, label=f"{label} {n}")
+            for k in ("mean", "scale", "quat", "opacity", "sh", "activity"):
+                assert_grad_close(got[k], ref[k], sens[k], k, ex, g32[k])
